@@ -1,0 +1,196 @@
+"""Python front end of the FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg use it; the renderer never imports it.  See ``oracle.c`` for
+the definition it computes and the passages of NavGSim (arXiv 2603.15186) it
+follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "oracle.c")
+
+MODE_ALL_LEAVES = 0
+MODE_THRESHOLD = 1
+
+# Relative margins within which a compositing decision may go either way:
+# q vs 9, alpha vs 1/255f, transmittance vs 1e-4f.  They bound the error of a
+# single-precision evaluation of the same quantities (derivation in the
+# design notes); decisions inside them are forked.
+DEFAULT_EPS = (1e-4, 1e-4, 5e-4)
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-fPIC", "-shared", SRC_PATH, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("position", ctypes.c_float * 3), ("R", ctypes.c_float * 9),
+                ("znear", ctypes.c_float), ("bg", ctypes.c_float * 3)]
+
+
+def _cam(c) -> _Camera:
+    k = _Camera()
+    k.width, k.height = int(c.width), int(c.height)
+    k.fx, k.fy, k.cx, k.cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+    for i in range(3):
+        k.position[i] = float(np.float32(c.position[i]))
+        k.bg[i] = float(c.bg[i])
+    R = np.asarray(c.R, np.float32).ravel()
+    for i in range(9):
+        k.R[i] = float(R[i])
+    k.znear = float(c.znear)
+    return k
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.or_cut.restype = ctypes.c_int64
+        L.or_cut.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.POINTER(_Camera),
+                             ctypes.c_int32, ctypes.c_float, P, ctypes.c_int64]
+        L.or_project.restype = None
+        L.or_project.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32,
+                                 ctypes.POINTER(_Camera), P]
+        L.or_render_pixels.restype = ctypes.c_int32
+        L.or_render_pixels.argtypes = [ctypes.c_int64, P, ctypes.POINTER(_Camera), ctypes.c_int64,
+                                       P, P, P, ctypes.c_int32, P, P, P, P]
+        L.or_sh_basis.restype = None
+        L.or_sh_basis.argtypes = [P, P]
+        L.or_proj_stride.restype = ctypes.c_int32
+        L.or_num_threads.restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# Column layout of ``project``'s output.
+PROJ_FIELDS = ("valid", "u", "v", "A", "B", "C", "S00", "S01", "S11", "r", "g", "b",
+               "z", "zkey", "opacity", "tx", "ty")
+PF = {k: i for i, k in enumerate(PROJ_FIELDS)}
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def sh_basis(d) -> np.ndarray:
+    """Real SH Y_lm(d), index l*l + l + m, l <= 3, for a unit direction."""
+    d = _c(d, np.float64)
+    out = np.zeros(16)
+    lib().or_sh_basis(_p(d), _p(out))
+    return out
+
+
+def cut(scene, cam, mode=MODE_THRESHOLD, tau=1.0) -> np.ndarray:
+    """Ascending node ids of the level-of-detail cut."""
+    L = lib()
+    n = scene.n
+    k = _cam(cam)
+    if scene.parent is None:
+        return np.arange(n, dtype=np.int32)
+    bound = _c(scene.bound, np.float32); par = _c(scene.parent, np.int32)
+    fc = _c(scene.first_child, np.int32); cc = _c(scene.child_count, np.int32)
+    cap = 1 << 16
+    while True:
+        out = np.empty(cap, np.int32)
+        cnt = L.or_cut(n, _p(bound), _p(par), _p(fc), _p(cc), ctypes.byref(k), int(mode),
+                       float(tau), _p(out), cap)
+        if cnt <= cap:
+            return out[:cnt].copy()
+        cap = int(cnt)
+
+
+def project(scene, ids, cam) -> np.ndarray:
+    """FP64 projection of the Gaussians ``ids``: (m, len(PROJ_FIELDS))."""
+    L = lib()
+    ids = _c(ids, np.int32)
+    m = ids.size
+    stride = int(L.or_proj_stride())
+    out = np.zeros((m, stride))
+    means = _c(scene.means, np.float32); scales = _c(scene.scales, np.float32)
+    quats = _c(scene.quats, np.float32); op = _c(scene.opacity, np.float32)
+    sh = _c(scene.sh, np.float32)
+    L.or_project(m, _p(ids), _p(means), _p(scales), _p(quats), _p(op), _p(sh),
+                 int(scene.sh_degree), ctypes.byref(_cam(cam)), _p(out))
+    return out
+
+
+class PixelResult:
+    """Oracle output for a set of pixels.
+
+    branches[i, b] = (R, G, B, depth, alpha) of branch b (b < nbranch[i]);
+    branch 0 follows every FP64 decision.
+    """
+
+    def __init__(self, px, py, branches, nbranch, nalg, flags):
+        self.px, self.py = px, py
+        self.branches, self.nbranch, self.nalg, self.flags = branches, nbranch, nalg, flags
+
+    @property
+    def primary(self):
+        return self.branches[:, 0, :]
+
+
+def render_pixels(proj, cam, px, py, eps=DEFAULT_EPS, cap=8) -> PixelResult:
+    L = lib()
+    proj = _c(proj, np.float64)
+    px = _c(px, np.int32); py = _c(py, np.int32)
+    n = px.size
+    out = np.zeros((n, cap, 5))
+    nb = np.zeros(n, np.int32); nalg = np.zeros(n, np.int64); fl = np.zeros(n, np.int32)
+    e = _c(eps, np.float64)
+    rc = L.or_render_pixels(proj.shape[0], _p(proj), ctypes.byref(_cam(cam)), n, _p(px), _p(py),
+                            _p(e), int(cap), _p(out), _p(nb), _p(nalg), _p(fl))
+    if rc != 0:
+        raise MemoryError("oracle render_pixels failed")
+    return PixelResult(px, py, out, nb, nalg, fl)
+
+
+def render(scene, cam, mode=MODE_THRESHOLD, tau=1.0, eps=DEFAULT_EPS, cap=8, ids=None):
+    """Full-image oracle render.  Returns (PixelResult over all pixels in
+    row-major order, cut ids, projection)."""
+    if ids is None:
+        ids = cut(scene, cam, mode, tau)
+    proj = project(scene, ids, cam)
+    yy, xx = np.mgrid[0:cam.height, 0:cam.width]
+    res = render_pixels(proj, cam, xx.ravel(), yy.ravel(), eps, cap)
+    return res, ids, proj
+
+
+def image(res: PixelResult, cam):
+    """(rgb[3,H,W], depth[H,W], alpha[H,W]) of branch 0 of a full render."""
+    p = res.primary
+    H, W = cam.height, cam.width
+    return (p[:, :3].T.reshape(3, H, W).copy(), p[:, 3].reshape(H, W).copy(),
+            p[:, 4].reshape(H, W).copy())
