@@ -1,0 +1,206 @@
+/*
+ * hgs.h -- C ABI of the MI355X (gfx950) forward renderer for hierarchical
+ * 3D Gaussian Splatting scenes.
+ *
+ * The operation (NavGSim, arXiv 2603.15186):
+ *   - Sec. III-B: a scene is a tree of anisotropic 3D Gaussians; leaves hold
+ *     the fine detail, internal nodes aggregate it; level-of-detail rendering
+ *     selects Gaussians from different levels of the tree.
+ *   - Eq. (1) and the Supplementary Material: each Gaussian's density is
+ *     exp(-1/2 (x - mu)^T Sigma^-1 (x - mu)) with Sigma = R S S^T R^T.
+ *   - Sec. III-A: a view is rendered from the camera intrinsics and
+ *     extrinsics alone.
+ * A render is: a level-of-detail cut through the hierarchy, EWA projection
+ * of the cut's Gaussians to 2D conics with spherical-harmonic colour, tile
+ * binning with a (tile, depth) radix sort, and front-to-back alpha
+ * compositing per 16x16 tile (alpha capped at 0.99, skipped below 1/255,
+ * stop before transmittance drops below 1e-4, 3-sigma support).
+ *
+ * Conventions: world z is up.  Camera frame: x right, y down, z forward.
+ * Pixel (i, j) has its centre at (i + 0.5, j + 0.5).  Outputs are planar
+ * FP32: rgb[3][H][W], depth[H][W] (sum of w_i z_i, not normalised),
+ * alpha[H][W] (1 - final transmittance).
+ *
+ * Errors: every entry point returns an hgs_status; nothing throws or aborts
+ * across the ABI.  hgs_last_error() describes the last failure of a context.
+ * A context is not thread-safe: use one per host thread.
+ */
+#ifndef HGS_H
+#define HGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hgs_status;
+#define HGS_OK 0
+#define HGS_E_INVALID (-1)        /* bad argument (null, NaN, out of range) */
+#define HGS_E_STATE (-2)          /* call out of order (e.g. render before load) */
+#define HGS_E_OOM (-3)            /* device or host allocation failed */
+#define HGS_E_HIP (-4)            /* a HIP runtime call failed */
+#define HGS_E_CAPACITY (-5)       /* a work buffer overflowed and regrowth is off */
+#define HGS_E_BAD_HIERARCHY (-6)  /* hierarchy arrays are inconsistent */
+#define HGS_E_UNSUPPORTED (-7)    /* valid request this build does not support */
+
+/* LOD modes (hgs_set_lod). */
+#define HGS_LOD_ALL_LEAVES 0      /* every leaf, no culling */
+#define HGS_LOD_THRESHOLD 1       /* projected-size threshold cut */
+#define HGS_LOD_LEARNED 2         /* MLP-refined cut, threshold rule as fallback */
+
+/* Options (hgs_set_option). */
+#define HGS_OPT_SYNC_CHECK 1      /* 1 (default): hgs_render waits for the GPU and
+                                     checks capacities; 0: fully asynchronous,
+                                     call hgs_check() after synchronising */
+#define HGS_OPT_AUTO_REGROW 2     /* 1 (default): regrow and re-render on overflow */
+#define HGS_OPT_COUNT_NALG 3      /* 1: count evaluated (pixel, Gaussian) pairs */
+#define HGS_OPT_BATCH_DEPTH 4     /* Gaussians staged in LDS per batch: 64..256 */
+#define HGS_OPT_USE_GRAPH 5       /* 1: capture the render in a hipGraph and replay */
+#define HGS_OPT_PERSISTENT 6      /* 1: composite with a persistent tile queue */
+#define HGS_OPT_EXACT_TILES 7     /* 1 (default): bin only tiles the ellipse reaches */
+#define HGS_OPT_INITIAL_CAPACITY 8 /* >0: restart work buffers at this many entries
+                                      (exercises overflow and regrowth); 0: automatic */
+#define HGS_OPT_STAGE_TIMING 9    /* 1: time the stages of every render with HIP events
+                                     on its stream; setting it clears the sums */
+
+typedef struct hgs_ctx hgs_ctx;
+
+/* Gaussians, host arrays borrowed for the duration of the call (copied).
+ * means[n*3] metres; scales[n*3] metres, > 0; quats[n*4] (w,x,y,z), nonzero,
+ * normalised by the renderer; opacity[n] in (0, 1]; sh[n*K*3] with
+ * K = (sh_degree+1)^2, index (g*K + k)*3 + channel, k = l*l + l + m
+ * (real harmonics with the Condon-Shortley phase); colour is
+ * clamp(sum_k sh_k Y_k(d) + 0.5, 0, 1) with d the unit world-space direction
+ * from the camera centre to the mean. */
+typedef struct {
+    int64_t n;
+    int32_t sh_degree;            /* 0..3 */
+    int32_t reserved;
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* opacity;
+    const float* sh;
+} hgs_gaussians;
+
+/* Hierarchy over the same n Gaussians: node k is Gaussian k.  Level-major
+ * ids, roots first, children of a node contiguous and one level down:
+ * nodes [level_offset[L], level_offset[L+1]) form level L; parent[k] = -1
+ * for roots; child_count[k] = 0 for leaves (first_child ignored then).
+ * bound[k*4] = (cx, cy, cz, r): a sphere enclosing the 3-sigma spheres of
+ * every leaf below k.  Host arrays, borrowed for the call (copied). */
+typedef struct {
+    int64_t n_nodes;
+    const int32_t* parent;
+    const int32_t* first_child;
+    const int32_t* child_count;
+    const float* bound;
+    int32_t n_levels;
+    int32_t reserved;
+    const int64_t* level_offset;  /* n_levels + 1 entries */
+} hgs_hierarchy;
+
+/* Pinhole camera.  R maps world to camera coordinates (rows: right, down,
+ * forward); position is the camera centre in world coordinates. */
+typedef struct {
+    int32_t width, height;        /* 1..8192 */
+    float fx, fy, cx, cy;         /* pixels */
+    float position[3];
+    float R[9];                   /* row-major */
+    float znear;                  /* metres, > 0 (0.2 by convention) */
+    float bg[3];                  /* background colour */
+} hgs_camera;
+
+/* Caller-owned device buffers of one view, written on the render stream. */
+typedef struct {
+    float* rgb;                   /* [3][H][W] */
+    float* depth;                 /* [H][W]; may be NULL */
+    float* alpha;                 /* [H][W]; may be NULL */
+} hgs_output;
+
+/* Counters of the last render (all views), and GPU stage times summed over
+ * the renders timed since HGS_OPT_STAGE_TIMING was last set:
+ * ms_cut (LOD cut), ms_project (projection), ms_sort (depth sort, pair
+ * emission, tile sort, tile ranges), ms_composite (the compositing kernel),
+ * ms_total (whole render). */
+typedef struct {
+    int64_t cut_size;             /* Gaussians selected by the cut */
+    int64_t visible;              /* of those, binned to at least one tile */
+    int64_t pairs;                /* (tile, Gaussian) pairs sorted */
+    int64_t n_alg;                /* evaluated pairs with q <= 9 (if counted) */
+    int64_t tiles;                /* tiles composited */
+    int64_t regrows;              /* buffer regrowths during the last render */
+    int64_t timed_renders;        /* renders summed in the ms_* fields */
+    double ms_cut, ms_project, ms_sort, ms_composite, ms_total;
+} hgs_stats;
+
+/* Create a context on HIP device `device`.  *out is set on success. */
+hgs_status hgs_create(int32_t device, hgs_ctx** out);
+
+/* Free the context and all device memory it owns.  NULL is ignored. */
+void hgs_destroy(hgs_ctx* ctx);
+
+/* Description of the context's last failure ("" if none); owned by the
+ * context, valid until its next call.  Safe with ctx == NULL. */
+const char* hgs_last_error(const hgs_ctx* ctx);
+
+/* Check a scene on the host only (never touches a device).  Writes a
+ * NUL-terminated reason into msg (if msg_len > 0) on failure.
+ * Returns HGS_E_INVALID or HGS_E_BAD_HIERARCHY on failure. */
+hgs_status hgs_validate_scene(const hgs_gaussians* g, const hgs_hierarchy* h,
+                              char* msg, int64_t msg_len);
+
+/* Validate and upload a scene (h == NULL: flat scene).  On failure the
+ * previously loaded scene stays in place. */
+hgs_status hgs_load_scene(hgs_ctx* ctx, const hgs_gaussians* g, const hgs_hierarchy* h);
+
+/* Set the n >= 1 views of the next renders (copied). */
+hgs_status hgs_set_cameras(hgs_ctx* ctx, int32_t n, const hgs_camera* cams);
+
+/* Level-of-detail mode and threshold tau (pixels, > 0): an internal node is
+ * refined while its projected size 2 f r / |c - o| (f = max(fx, fy)) exceeds
+ * tau, evaluated exactly in FP64 as (2 f r)^2 > tau^2 |c - o|^2.  Flat scenes
+ * ignore the mode.  LEARNED needs hgs_load_lod_mlp first (else HGS_E_STATE). */
+hgs_status hgs_set_lod(hgs_ctx* ctx, int32_t mode, float tau_px);
+
+/* Set an HGS_OPT_* option. */
+hgs_status hgs_set_option(hgs_ctx* ctx, int32_t option, int64_t value);
+
+/* Render every view set by hgs_set_cameras into outs[0..n) on `stream`
+ * (a hipStream_t; NULL = default stream).  With HGS_OPT_SYNC_CHECK on, the
+ * call returns after the GPU finished and buffers were checked; otherwise
+ * it only enqueues. */
+hgs_status hgs_render(hgs_ctx* ctx, void* stream, const hgs_output* outs);
+
+/* After an asynchronous render and a stream synchronisation: HGS_OK, or
+ * HGS_E_CAPACITY if a work buffer overflowed (outputs are then invalid;
+ * capacities have been grown for the next render). */
+hgs_status hgs_check(hgs_ctx* ctx);
+
+/* Ascending node ids of view `view`'s cut from the last render.  Writes
+ * min(count, cap) ids to host_ids and the full count to *count. */
+hgs_status hgs_get_cut(hgs_ctx* ctx, int32_t view, int32_t* host_ids, int64_t cap,
+                       int64_t* count);
+
+/* Stage-wise intermediates of view `view` from the last render, in cut
+ * order: per Gaussian 12 floats (u, v, conic A, B, C, r, g, b, depth,
+ * opacity, tile count, valid).  Conic recomputed from the stored factors. */
+hgs_status hgs_get_projected(hgs_ctx* ctx, int32_t view, float* host_out, int64_t cap,
+                             int64_t* count);
+
+/* Counters of the last render (synchronises with it). */
+hgs_status hgs_get_stats(hgs_ctx* ctx, hgs_stats* out);
+
+/* Sort n (key, value) pairs on the device by the low `key_bits` bits of the
+ * key, stably (LSD radix, 8-bit digits).  keys/vals are device pointers and
+ * are sorted in place; the context's scratch memory is used.  For testing
+ * the sort on its own. */
+hgs_status hgs_sort_pairs(hgs_ctx* ctx, void* stream, uint32_t* keys, uint32_t* vals,
+                          int64_t n, int32_t key_bits);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGS_H */

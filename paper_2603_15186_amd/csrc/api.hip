@@ -1,0 +1,881 @@
+// Host side of the C ABI: context, validation, scene upload, cameras,
+// capacity management and the render sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "lod_mlp.h"
+
+using namespace hgs;
+
+namespace {
+
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct hgs_ctx {
+    int device = 0;
+    std::string err;
+    // scene
+    bool loaded = false;
+    bool hier = false;
+    int64_t n = 0;
+    int sh_degree = 0;
+    int n_levels = 0;
+    std::vector<int64_t> level_offset;
+    int64_t n_leaves = 0;
+    DevMem geo, sh, bound, child, leaf_ids, parent, nodefeat;
+    // views
+    std::vector<hgs_camera> cams;
+    ViewDev* views_host = nullptr;    // pinned mirror
+    DevMem views;
+    DevMem tile_view;
+    uint32_t total_tiles = 0;
+    hipEvent_t views_copied = nullptr;
+    bool views_dirty = true;
+    // lod
+    int lod_mode = HGS_LOD_THRESHOLD;
+    float tau = 1.0f;
+    bool mlp_loaded = false;
+    DevMem mlp_w, mlp_dev;
+    LodMlpDev mlp_host{};
+    // options
+    bool sync_check = true, auto_regrow = true, use_graph = false;
+    RenderOpts ropts;
+    // work buffers
+    uint32_t frontier_cap = 0, cut_cap = 0, pair_cap = 0;
+    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, rect, offsets;
+    DevMem pkey[2], pval[2], ranges, scan_tmp, hist, counters;
+    Counters* ctr_host = nullptr;     // pinned
+    bool last_valid = false;
+    int64_t regrows = 0;
+    uint32_t forced_cap = 0;          // test hook: start from this capacity
+    // stage timing: 6 events per render (start, cut, project, binning, composite start, end)
+    bool stage_timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double acc_ms[5] = {0, 0, 0, 0, 0};
+    int64_t acc_n = 0;
+    // sort scratch for hgs_sort_pairs
+    DevMem sort_k, sort_v, sort_n;
+};
+
+namespace {
+
+hgs_status fail(hgs_ctx* c, hgs_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIP_TRY(c, call)                                                                          \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return fail((c), HGS_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+void release(DevMem& m) {
+    if (m.p) (void)hipFree(m.p);
+    m.p = nullptr;
+    m.bytes = 0;
+}
+
+hgs_status ensure(hgs_ctx* c, DevMem& m, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (m.bytes >= bytes) return HGS_OK;
+    release(m);
+    hipError_t e = hipMalloc(&m.p, bytes);
+    if (e != hipSuccess) {
+        m.p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, HGS_E_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    m.bytes = bytes;
+    return HGS_OK;
+}
+
+template <typename T>
+T* P(const DevMem& m) { return static_cast<T*>(m.p); }
+
+bool finite(float x) { return std::isfinite(x); }
+
+hgs_status validate(const hgs_gaussians* g, const hgs_hierarchy* h, std::string* why) {
+    auto bad = [&](hgs_status s, const std::string& m) {
+        *why = m;
+        return s;
+    };
+    if (!g) return bad(HGS_E_INVALID, "gaussians is NULL");
+    if (g->n <= 0) return bad(HGS_E_INVALID, "n must be positive");
+    if (g->n > (int64_t)0x7fffffff) return bad(HGS_E_UNSUPPORTED, "n exceeds 2^31-1");
+    if (g->sh_degree < 0 || g->sh_degree > 3) return bad(HGS_E_INVALID, "sh_degree must be 0..3");
+    if (!g->means || !g->scales || !g->quats || !g->opacity || !g->sh)
+        return bad(HGS_E_INVALID, "a Gaussian array is NULL");
+    const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
+    for (int64_t i = 0; i < g->n; ++i) {
+        for (int j = 0; j < 3; ++j) {
+            if (!finite(g->means[3 * i + j])) return bad(HGS_E_INVALID, "mean of Gaussian " + std::to_string(i) + " is not finite");
+            const float s = g->scales[3 * i + j];
+            if (!(s > 0.f) || !finite(s)) return bad(HGS_E_INVALID, "scale of Gaussian " + std::to_string(i) + " is not a positive number");
+        }
+        float qq = 0.f;
+        for (int j = 0; j < 4; ++j) {
+            const float q = g->quats[4 * i + j];
+            if (!finite(q)) return bad(HGS_E_INVALID, "quaternion of Gaussian " + std::to_string(i) + " is not finite");
+            qq += q * q;
+        }
+        if (!(qq > 0.f)) return bad(HGS_E_INVALID, "quaternion of Gaussian " + std::to_string(i) + " is zero");
+        const float o = g->opacity[i];
+        if (!(o > 0.f && o <= 1.f)) return bad(HGS_E_INVALID, "opacity of Gaussian " + std::to_string(i) + " is outside (0, 1]");
+        for (int k = 0; k < 3 * K; ++k)
+            if (!finite(g->sh[(int64_t)3 * K * i + k])) return bad(HGS_E_INVALID, "SH of Gaussian " + std::to_string(i) + " is not finite");
+    }
+    if (!h) return HGS_OK;
+    if (h->n_nodes != g->n) return bad(HGS_E_BAD_HIERARCHY, "n_nodes differs from the Gaussian count");
+    if (!h->parent || !h->first_child || !h->child_count || !h->bound || !h->level_offset)
+        return bad(HGS_E_BAD_HIERARCHY, "a hierarchy array is NULL");
+    if (h->n_levels < 1 || h->n_levels > 64) return bad(HGS_E_BAD_HIERARCHY, "n_levels must be 1..64");
+    const int64_t n = h->n_nodes;
+    if (h->level_offset[0] != 0 || h->level_offset[h->n_levels] != n)
+        return bad(HGS_E_BAD_HIERARCHY, "level_offset must start at 0 and end at n_nodes");
+    for (int L = 0; L < h->n_levels; ++L)
+        if (h->level_offset[L + 1] <= h->level_offset[L]) return bad(HGS_E_BAD_HIERARCHY, "empty or decreasing level");
+    for (int64_t k = 0; k < h->level_offset[1]; ++k)
+        if (h->parent[k] != -1) return bad(HGS_E_BAD_HIERARCHY, "level 0 must hold only roots (parent -1)");
+    int L = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        while (k >= h->level_offset[L + 1]) ++L;
+        const float* b = h->bound + 4 * k;
+        if (!finite(b[0]) || !finite(b[1]) || !finite(b[2]) || !(b[3] >= 0.f) || !finite(b[3]))
+            return bad(HGS_E_INVALID, "bound of node " + std::to_string(k) + " is invalid");
+        if (L > 0) {
+            const int32_t p = h->parent[k];
+            if (p < h->level_offset[L - 1] || p >= h->level_offset[L])
+                return bad(HGS_E_BAD_HIERARCHY, "parent of node " + std::to_string(k) + " is not on the level above");
+            const int32_t f = h->first_child[p], c = h->child_count[p];
+            if (k < f || k >= (int64_t)f + c)
+                return bad(HGS_E_BAD_HIERARCHY, "node " + std::to_string(k) + " is outside its parent's child range");
+        }
+        const int32_t c = h->child_count[k];
+        if (c < 0) return bad(HGS_E_BAD_HIERARCHY, "negative child_count at node " + std::to_string(k));
+        if (c > 0) {
+            if (L + 1 >= h->n_levels) return bad(HGS_E_BAD_HIERARCHY, "node on the last level has children");
+            const int64_t f = h->first_child[k];
+            if (f < h->level_offset[L + 1] || f + c > h->level_offset[L + 2])
+                return bad(HGS_E_BAD_HIERARCHY, "children of node " + std::to_string(k) + " are not on the next level");
+            if (k > h->level_offset[L] && h->child_count[k - 1] > 0 &&
+                f != (int64_t)h->first_child[k - 1] + h->child_count[k - 1])
+                return bad(HGS_E_BAD_HIERARCHY, "children are not contiguous in parent order at node " + std::to_string(k));
+            for (int32_t j = 0; j < c; ++j)
+                if (h->parent[f + j] != k) return bad(HGS_E_BAD_HIERARCHY, "child/parent links disagree at node " + std::to_string(k));
+        }
+    }
+    return HGS_OK;
+}
+
+int bits_for(uint32_t n) {
+    int b = 1;
+    while (b < 32 && (1ull << b) < n) ++b;
+    return b;
+}
+
+__global__ void k_reset(Counters* c) {
+    if (threadIdx.x == 0) {
+        Counters z = {};
+        *c = z;
+    }
+}
+
+hgs_status alloc_work(hgs_ctx* c) {
+    hgs_status s;
+    const size_t F = c->frontier_cap, M = c->cut_cap, Pc = c->pair_cap;
+    for (int i = 0; i < 2; ++i)
+        if ((s = ensure(c, c->frontier[i], F * sizeof(uint2)))) return s;
+    if ((s = ensure(c, c->cut, M * sizeof(uint2)))) return s;
+    if ((s = ensure(c, c->proj, M * sizeof(Proj)))) return s;
+    for (int i = 0; i < 2; ++i) {
+        if ((s = ensure(c, c->dkey[i], M * 4))) return s;
+        if ((s = ensure(c, c->dval[i], M * 4))) return s;
+        if ((s = ensure(c, c->pkey[i], Pc * 4))) return s;
+        if ((s = ensure(c, c->pval[i], Pc * 4))) return s;
+    }
+    if ((s = ensure(c, c->ntiles, M * 4))) return s;
+    if ((s = ensure(c, c->rect, M * sizeof(ushort4)))) return s;
+    if ((s = ensure(c, c->offsets, M * 4))) return s;
+    if ((s = ensure(c, c->scan_tmp, (kScanBlocks + 1) * sizeof(uint2)))) return s;
+    if ((s = ensure(c, c->hist, (256 * kSortBlocks + 256) * 4))) return s;
+    return HGS_OK;
+}
+
+uint32_t clamp_cap(uint64_t x) {
+    const uint64_t lim = 0xF0000000ull;
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(x, 1024), lim);
+}
+
+void initial_caps(hgs_ctx* c) {
+    if (c->forced_cap) {
+        c->cut_cap = c->frontier_cap = c->forced_cap;
+        c->pair_cap = c->forced_cap;
+        return;
+    }
+    const uint64_t V = c->cams.size();
+    const uint64_t per_view = c->hier ? (uint64_t)c->n_leaves : (uint64_t)c->n;
+    const uint64_t budget = 48ull << 20;     // entries
+    uint64_t m = std::min<uint64_t>(V * per_view, budget);
+    if (!c->hier || c->lod_mode == HGS_LOD_ALL_LEAVES) m = std::min<uint64_t>(V * per_view, 1ull << 31);
+    c->cut_cap = std::max(c->cut_cap, clamp_cap(m));
+    c->frontier_cap = std::max(c->frontier_cap, clamp_cap(std::min<uint64_t>(m, budget)));
+    c->pair_cap = std::max(c->pair_cap, clamp_cap(std::min<uint64_t>(8 * (uint64_t)c->cut_cap, 256ull << 20)));
+}
+
+hgs_status upload_views(hgs_ctx* c, hipStream_t s, const hgs_output* outs) {
+    const int V = (int)c->cams.size();
+    bool changed = c->views_dirty;
+    for (int v = 0; v < V; ++v) {
+        ViewDev& d = c->views_host[v];
+        if (d.rgb != outs[v].rgb || d.depth != outs[v].depth || d.alpha != outs[v].alpha) changed = true;
+    }
+    if (!changed) return HGS_OK;
+    HIP_TRY(c, hipEventSynchronize(c->views_copied));   // previous copy done with the mirror
+    for (int v = 0; v < V; ++v) {
+        ViewDev& d = c->views_host[v];
+        d.rgb = outs[v].rgb;
+        d.depth = outs[v].depth;
+        d.alpha = outs[v].alpha;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->views.p, c->views_host, sizeof(ViewDev) * V, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipEventRecord(c->views_copied, s));
+    c->views_dirty = false;
+    return HGS_OK;
+}
+
+hgs_status harvest_events(hgs_ctx* c) {
+    for (size_t b = 0; b + 6 <= c->ev_used; b += 6) {
+        HIP_TRY(c, hipEventSynchronize(c->ev_pool[b + 5]));
+        float t[5];
+        HIP_TRY(c, hipEventElapsedTime(&t[0], c->ev_pool[b], c->ev_pool[b + 1]));
+        HIP_TRY(c, hipEventElapsedTime(&t[1], c->ev_pool[b + 1], c->ev_pool[b + 2]));
+        HIP_TRY(c, hipEventElapsedTime(&t[2], c->ev_pool[b + 2], c->ev_pool[b + 4]));
+        HIP_TRY(c, hipEventElapsedTime(&t[3], c->ev_pool[b + 4], c->ev_pool[b + 5]));
+        HIP_TRY(c, hipEventElapsedTime(&t[4], c->ev_pool[b], c->ev_pool[b + 5]));
+        for (int i = 0; i < 5; ++i) c->acc_ms[i] += t[i];
+        ++c->acc_n;
+    }
+    c->ev_used = 0;
+    return HGS_OK;
+}
+
+// Event slot k of the current render, creating pool entries on demand.
+hipEvent_t stage_event(hgs_ctx* c, int k) {
+    const size_t i = c->ev_used + k;
+    while (c->ev_pool.size() <= i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[i];
+}
+
+void mark(hgs_ctx* c, int k, hipStream_t s) {
+    if (!c->stage_timing) return;
+    hipEvent_t e = stage_event(c, k);
+    if (e) (void)hipEventRecord(e, s);
+}
+
+void enqueue_render(hgs_ctx* c, hipStream_t s) {
+    Counters* ctr = P<Counters>(c->counters);
+    if (c->stage_timing && c->ev_used >= 6 * 512) (void)harvest_events(c);
+    mark(c, 0, s);
+    k_reset<<<1, 64, 0, s>>>(ctr);
+    CutArgs ca{};
+    ca.bound = P<float4>(c->bound);
+    ca.child = P<int2>(c->child);
+    ca.leaf_ids = P<int32_t>(c->leaf_ids);
+    ca.n_leaves = c->n_leaves;
+    ca.n_nodes = c->n;
+    ca.level_offset_host = c->level_offset.data();
+    ca.n_levels = c->n_levels;
+    ca.mode = c->lod_mode;
+    ca.flat = !c->hier;
+    ca.views = P<ViewDev>(c->views);
+    ca.n_views = (int)c->cams.size();
+    ca.frontier[0] = P<uint2>(c->frontier[0]);
+    ca.frontier[1] = P<uint2>(c->frontier[1]);
+    ca.frontier_cap = c->frontier_cap;
+    ca.cut = P<uint2>(c->cut);
+    ca.cut_cap = c->cut_cap;
+    ca.scan_tmp = P<uint2>(c->scan_tmp);
+    ca.ctr = ctr;
+    ca.mlp = (c->lod_mode == HGS_LOD_LEARNED && c->mlp_loaded) ? c->mlp_dev.p : nullptr;
+    launch_cut(ca, s);
+    mark(c, 1, s);
+
+    ProjectArgs pa{};
+    pa.cut = ca.cut;
+    pa.cut_cap = c->cut_cap;
+    pa.geo = P<float4>(c->geo);
+    pa.sh = P<float>(c->sh);
+    pa.n = c->n;
+    pa.sh_degree = c->sh_degree;
+    pa.views = ca.views;
+    pa.proj = P<Proj>(c->proj);
+    pa.depth_key = P<uint32_t>(c->dkey[0]);
+    pa.depth_val = P<uint32_t>(c->dval[0]);
+    pa.ntiles = P<uint32_t>(c->ntiles);
+    pa.rect = P<ushort4>(c->rect);
+    pa.exact_tiles = c->ropts.exact_tiles;
+    pa.ctr = ctr;
+    launch_project(pa, s);
+    mark(c, 2, s);
+
+    SortArgs sa{};
+    sa.keys[0] = P<uint32_t>(c->dkey[0]);
+    sa.keys[1] = P<uint32_t>(c->dkey[1]);
+    sa.vals[0] = P<uint32_t>(c->dval[0]);
+    sa.vals[1] = P<uint32_t>(c->dval[1]);
+    sa.count = &ctr->cut;
+    sa.cap = c->cut_cap;
+    sa.key_bits = 32;
+    sa.hist = P<uint32_t>(c->hist);
+    const int dr = launch_sort(sa, s);
+
+    EmitArgs ea{};
+    ea.order = sa.vals[dr];
+    ea.ntiles = pa.ntiles;
+    ea.rect = pa.rect;
+    ea.proj = pa.proj;
+    ea.cut = ca.cut;
+    ea.views = ca.views;
+    ea.cut_cap = c->cut_cap;
+    ea.offsets = P<uint32_t>(c->offsets);
+    ea.keys = P<uint32_t>(c->pkey[0]);
+    ea.vals = P<uint32_t>(c->pval[0]);
+    ea.pair_cap = c->pair_cap;
+    ea.exact_tiles = c->ropts.exact_tiles;
+    ea.scan_tmp = ca.scan_tmp;
+    ea.ctr = ctr;
+    launch_emit(ea, s);
+
+    SortArgs pb{};
+    pb.keys[0] = P<uint32_t>(c->pkey[0]);
+    pb.keys[1] = P<uint32_t>(c->pkey[1]);
+    pb.vals[0] = P<uint32_t>(c->pval[0]);
+    pb.vals[1] = P<uint32_t>(c->pval[1]);
+    pb.count = &ctr->pairs;
+    pb.cap = c->pair_cap;
+    pb.key_bits = bits_for(c->total_tiles);
+    pb.hist = sa.hist;
+    const int pr = launch_sort(pb, s);
+
+    CompositeArgs xa{};
+    xa.keys = pb.keys[pr];
+    xa.vals = pb.vals[pr];
+    xa.pair_cap = c->pair_cap;
+    xa.cut_cap = c->cut_cap;
+    xa.ranges = P<uint2>(c->ranges);
+    xa.total_tiles = c->total_tiles;
+    xa.proj = pa.proj;
+    xa.views = ca.views;
+    xa.tile_view = P<uint32_t>(c->tile_view);
+    xa.n_views = ca.n_views;
+    xa.opts = c->ropts;
+    xa.ctr = ctr;
+    launch_ranges(xa, s);
+    mark(c, 4, s);
+    launch_composite(xa, s);
+    mark(c, 5, s);
+    if (c->stage_timing) c->ev_used += 6;
+}
+
+hgs_status grow_from(hgs_ctx* c, const Counters& k) {
+    auto grow = [](uint32_t cap, uint32_t need) {
+        uint64_t g = std::max<uint64_t>((uint64_t)need + need / 4, 2ull * cap);
+        return clamp_cap(g);
+    };
+    if (k.overflow & kOvFrontier) c->frontier_cap = grow(c->frontier_cap, k.need_frontier);
+    if (k.overflow & kOvCut) c->cut_cap = grow(c->cut_cap, k.need_cut);
+    if (k.overflow & kOvPairs) c->pair_cap = grow(c->pair_cap, k.need_pairs);
+    // a cut overflow leaves the pair count unknown; keep pairs proportional
+    if (k.overflow & kOvCut) c->pair_cap = std::max(c->pair_cap, clamp_cap(std::min<uint64_t>(8ull * c->cut_cap, 0xF0000000ull)));
+    ++c->regrows;
+    return alloc_work(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+hgs_status hgs_create(int32_t device, hgs_ctx** out) {
+    if (!out) return HGS_E_INVALID;
+    *out = nullptr;
+    int nd = 0;
+    if (hipGetDeviceCount(&nd) != hipSuccess || nd <= 0) {
+        (void)hipGetLastError();
+        return HGS_E_HIP;
+    }
+    if (device < 0 || device >= nd) return HGS_E_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return HGS_E_HIP;
+    hgs_ctx* c = new (std::nothrow) hgs_ctx();
+    if (!c) return HGS_E_OOM;
+    c->device = device;
+    if (ensure(c, c->counters, sizeof(Counters)) != HGS_OK ||
+        hipHostMalloc((void**)&c->ctr_host, sizeof(Counters), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->views_copied, hipEventDisableTiming) != hipSuccess) {
+        hgs_destroy(c);
+        return HGS_E_HIP;
+    }
+    std::memset(c->ctr_host, 0, sizeof(Counters));
+    *out = c;
+    return HGS_OK;
+}
+
+void hgs_destroy(hgs_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    DevMem* all[] = {&c->geo, &c->sh, &c->bound, &c->child, &c->leaf_ids, &c->parent, &c->nodefeat, &c->views,
+                     &c->tile_view, &c->mlp_w, &c->mlp_dev, &c->frontier[0], &c->frontier[1], &c->cut, &c->proj,
+                     &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->rect, &c->offsets,
+                     &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
+                     &c->counters, &c->sort_k, &c->sort_v, &c->sort_n};
+    for (DevMem* m : all) release(*m);
+    if (c->views_host) (void)hipHostFree(c->views_host);
+    if (c->ctr_host) (void)hipHostFree(c->ctr_host);
+    if (c->views_copied) (void)hipEventDestroy(c->views_copied);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char* hgs_last_error(const hgs_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+hgs_status hgs_validate_scene(const hgs_gaussians* g, const hgs_hierarchy* h, char* msg, int64_t msg_len) {
+    std::string why;
+    hgs_status s = validate(g, h, &why);
+    if (msg && msg_len > 0) {
+        const size_t n = std::min<size_t>(why.size(), (size_t)msg_len - 1);
+        std::memcpy(msg, why.data(), n);
+        msg[n] = 0;
+    }
+    return s;
+}
+
+hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarchy* h) {
+    if (!c) return HGS_E_INVALID;
+    std::string why;
+    hgs_status s = validate(g, h, &why);
+    if (s != HGS_OK) return fail(c, s, "%s", why.c_str());
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t n = g->n;
+    const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
+    // host-side re-layout: geo = 3 float4 per Gaussian, SH planar by (k, c)
+    std::vector<float4> geo((size_t)n * 3);
+    for (int64_t i = 0; i < n; ++i) {
+        geo[3 * i] = make_float4(g->means[3 * i], g->means[3 * i + 1], g->means[3 * i + 2], g->opacity[i]);
+        geo[3 * i + 1] = make_float4(g->quats[4 * i], g->quats[4 * i + 1], g->quats[4 * i + 2], g->quats[4 * i + 3]);
+        geo[3 * i + 2] = make_float4(g->scales[3 * i], g->scales[3 * i + 1], g->scales[3 * i + 2], 0.f);
+    }
+    std::vector<float> sh((size_t)n * K * 3);
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < K * 3; ++k) sh[(size_t)k * n + i] = g->sh[(size_t)i * K * 3 + k];
+    // new buffers first, so a failure leaves the old scene intact
+    DevMem ngeo, nsh, nbound, nchild, nleaf, nparent, nfeat;
+    auto cleanup = [&]() {
+        release(ngeo); release(nsh); release(nbound); release(nchild); release(nleaf); release(nparent); release(nfeat);
+    };
+    if ((s = ensure(c, ngeo, geo.size() * sizeof(float4))) || (s = ensure(c, nsh, sh.size() * sizeof(float)))) {
+        cleanup();
+        return s;
+    }
+    hipError_t e = hipMemcpy(ngeo.p, geo.data(), geo.size() * sizeof(float4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(nsh.p, sh.data(), sh.size() * sizeof(float), hipMemcpyHostToDevice);
+    std::vector<int64_t> lo;
+    int64_t n_leaves = n;
+    if (e == hipSuccess && h) {
+        std::vector<float4> bound((size_t)n);
+        std::vector<int2> child((size_t)n);
+        std::vector<int32_t> leaves;
+        std::vector<float4> feat((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            bound[i] = make_float4(h->bound[4 * i], h->bound[4 * i + 1], h->bound[4 * i + 2], h->bound[4 * i + 3]);
+            child[i] = make_int2(h->child_count[i] > 0 ? h->first_child[i] : 0, h->child_count[i]);
+            if (h->child_count[i] == 0) leaves.push_back((int32_t)i);
+        }
+        // learned-LOD node features: thinnest axis and children's colour variance
+        for (int64_t i = 0; i < n; ++i) {
+            const float* q = g->quats + 4 * i;
+            const double qn = std::sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3]);
+            const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+            const float* sc = g->scales + 3 * i;
+            const int a = (sc[0] <= sc[1] && sc[0] <= sc[2]) ? 0 : (sc[1] <= sc[2] ? 1 : 2);
+            double col[3];
+            if (a == 0) { col[0] = 1 - 2 * (y * y + z * z); col[1] = 2 * (x * y + w * z); col[2] = 2 * (x * z - w * y); }
+            else if (a == 1) { col[0] = 2 * (x * y - w * z); col[1] = 1 - 2 * (x * x + z * z); col[2] = 2 * (y * z + w * x); }
+            else { col[0] = 2 * (x * z + w * y); col[1] = 2 * (y * z - w * x); col[2] = 1 - 2 * (x * x + y * y); }
+            double var = 0.0;
+            const int32_t cc = h->child_count[i];
+            if (cc > 1) {
+                double m[3] = {0, 0, 0}, m2 = 0;
+                for (int32_t j = 0; j < cc; ++j) {
+                    const int64_t ch = h->first_child[i] + j;
+                    for (int k = 0; k < 3; ++k) {
+                        const double v = g->sh[(size_t)ch * K * 3 + k];
+                        m[k] += v;
+                        m2 += v * v;
+                    }
+                }
+                var = m2 / cc - (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / ((double)cc * cc);
+                var *= 0.28209479177387814 * 0.28209479177387814;
+            }
+            feat[i] = make_float4((float)col[0], (float)col[1], (float)col[2], (float)std::max(var, 0.0));
+        }
+        if ((s = ensure(c, nbound, bound.size() * sizeof(float4))) || (s = ensure(c, nchild, child.size() * sizeof(int2))) ||
+            (s = ensure(c, nleaf, leaves.size() * sizeof(int32_t))) || (s = ensure(c, nparent, (size_t)n * 4)) ||
+            (s = ensure(c, nfeat, feat.size() * sizeof(float4)))) {
+            cleanup();
+            return s;
+        }
+        e = hipMemcpy(nbound.p, bound.data(), bound.size() * sizeof(float4), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(nchild.p, child.data(), child.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(nleaf.p, leaves.data(), leaves.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(nparent.p, h->parent, (size_t)n * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(nfeat.p, feat.data(), feat.size() * sizeof(float4), hipMemcpyHostToDevice);
+        lo.assign(h->level_offset, h->level_offset + h->n_levels + 1);
+        n_leaves = (int64_t)leaves.size();
+    }
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(c, HGS_E_HIP, "scene upload failed: %s", hipGetErrorString(e));
+    }
+    release(c->geo); release(c->sh); release(c->bound); release(c->child); release(c->leaf_ids);
+    release(c->parent); release(c->nodefeat);
+    c->geo = ngeo; c->sh = nsh; c->bound = nbound; c->child = nchild; c->leaf_ids = nleaf;
+    c->parent = nparent; c->nodefeat = nfeat;
+    c->hier = h != nullptr;
+    c->n = n;
+    c->sh_degree = g->sh_degree;
+    c->level_offset = lo;
+    c->n_levels = h ? h->n_levels : 0;
+    c->n_leaves = n_leaves;
+    c->loaded = true;
+    c->mlp_loaded = false;
+    c->last_valid = false;
+    if (!c->cams.empty()) {
+        initial_caps(c);
+        if ((s = alloc_work(c))) return s;
+    }
+    return HGS_OK;
+}
+
+hgs_status hgs_set_cameras(hgs_ctx* c, int32_t n, const hgs_camera* cams) {
+    if (!c) return HGS_E_INVALID;
+    if (n < 1 || n > kMaxViews || !cams) return fail(c, HGS_E_INVALID, "need 1..%d cameras", kMaxViews);
+    for (int v = 0; v < n; ++v) {
+        const hgs_camera& k = cams[v];
+        if (k.width < 1 || k.height < 1 || k.width > 8192 || k.height > 8192)
+            return fail(c, HGS_E_INVALID, "camera %d: size must be 1..8192", v);
+        if (!(k.fx > 0.f) || !(k.fy > 0.f) || !finite(k.cx) || !finite(k.cy) || !(k.znear > 0.f) || !finite(k.znear))
+            return fail(c, HGS_E_INVALID, "camera %d: focal lengths and znear must be positive", v);
+        for (int i = 0; i < 9; ++i)
+            if (!finite(k.R[i])) return fail(c, HGS_E_INVALID, "camera %d: rotation not finite", v);
+        for (int i = 0; i < 3; ++i)
+            if (!finite(k.position[i]) || !finite(k.bg[i])) return fail(c, HGS_E_INVALID, "camera %d: position/bg not finite", v);
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    // tile layout: views in order, row-major tiles within a view
+    uint64_t tiles = 0;
+    std::vector<uint32_t> tile_base(n);
+    for (int v = 0; v < n; ++v) {
+        tile_base[v] = (uint32_t)tiles;
+        tiles += (uint64_t)((cams[v].width + kTile - 1) / kTile) * ((cams[v].height + kTile - 1) / kTile);
+    }
+    if (tiles >= (1ull << 31)) return fail(c, HGS_E_UNSUPPORTED, "too many tiles");
+    hgs_status s;
+    if ((s = ensure(c, c->views, sizeof(ViewDev) * n)) || (s = ensure(c, c->tile_view, tiles * 4)) ||
+        (s = ensure(c, c->ranges, tiles * sizeof(uint2))))
+        return s;
+    if ((int)c->cams.size() < n || !c->views_host) {
+        if (c->views_host) {
+            HIP_TRY(c, hipEventSynchronize(c->views_copied));
+            (void)hipHostFree(c->views_host);
+        }
+        c->views_host = nullptr;
+        HIP_TRY(c, hipHostMalloc((void**)&c->views_host, sizeof(ViewDev) * n, hipHostMallocDefault));
+    } else {
+        HIP_TRY(c, hipEventSynchronize(c->views_copied));
+    }
+    std::vector<uint32_t> tv(tiles);
+    for (int v = 0; v < n; ++v) {
+        const hgs_camera& k = cams[v];
+        ViewDev d{};
+        for (int i = 0; i < 3; ++i) d.o[i] = (double)k.position[i];
+        for (int i = 0; i < 9; ++i) d.R[i] = (double)k.R[i];
+        d.fx = k.fx; d.fy = k.fy; d.cx = k.cx; d.cy = k.cy;
+        d.W = (double)k.width; d.H = (double)k.height; d.znear = k.znear;
+        d.f2 = 2.0 * std::max(d.fx, d.fy);
+        d.tau2 = (double)c->tau * (double)c->tau;
+        {
+            // same arithmetic order as the device node test (no contraction:
+            // these are single products and sums)
+            volatile double a = d.fx * d.fx, b = d.cx * d.cx;
+            d.nl = a + b;
+            const double cxw = d.cx - d.W;
+            volatile double b2 = cxw * cxw;
+            d.nr = a + b2;
+            volatile double e = d.fy * d.fy, f = d.cy * d.cy;
+            d.nt = e + f;
+            const double cyh = d.cy - d.H;
+            volatile double f2 = cyh * cyh;
+            d.nb = e + f2;
+        }
+        d.limx = 1.3 * (0.5 * k.width / d.fx);
+        d.limy = 1.3 * (0.5 * k.height / d.fy);
+        for (int i = 0; i < 3; ++i) d.bg[i] = k.bg[i];
+        d.width = k.width; d.height = k.height;
+        d.tiles_x = (k.width + kTile - 1) / kTile;
+        d.tiles_y = (k.height + kTile - 1) / kTile;
+        d.tile_base = tile_base[v];
+        d.rgb = d.depth = d.alpha = nullptr;
+        c->views_host[v] = d;
+        const uint32_t nt = (uint32_t)(d.tiles_x * d.tiles_y);
+        for (uint32_t t = 0; t < nt; ++t) tv[tile_base[v] + t] = (uint32_t)v;
+    }
+    HIP_TRY(c, hipMemcpy(c->tile_view.p, tv.data(), tiles * 4, hipMemcpyHostToDevice));
+    c->cams.assign(cams, cams + n);
+    c->total_tiles = (uint32_t)tiles;
+    c->views_dirty = true;
+    c->last_valid = false;
+    if (c->loaded) {
+        initial_caps(c);
+        if ((s = alloc_work(c))) return s;
+    }
+    return HGS_OK;
+}
+
+hgs_status hgs_set_lod(hgs_ctx* c, int32_t mode, float tau) {
+    if (!c) return HGS_E_INVALID;
+    if (mode < HGS_LOD_ALL_LEAVES || mode > HGS_LOD_LEARNED) return fail(c, HGS_E_INVALID, "unknown LOD mode %d", mode);
+    if (!(tau > 0.f) || !finite(tau)) return fail(c, HGS_E_INVALID, "tau must be a positive number");
+    if (mode == HGS_LOD_LEARNED && !c->mlp_loaded) return fail(c, HGS_E_STATE, "learned LOD needs hgs_load_lod_mlp first");
+    c->lod_mode = mode;
+    c->tau = tau;
+    if (c->views_host) HIP_TRY(c, hipEventSynchronize(c->views_copied));
+    for (size_t v = 0; c->views_host && v < c->cams.size(); ++v) c->views_host[v].tau2 = (double)tau * (double)tau;
+    c->views_dirty = true;
+    return HGS_OK;
+}
+
+hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
+    if (!c) return HGS_E_INVALID;
+    switch (opt) {
+        case HGS_OPT_SYNC_CHECK: c->sync_check = val != 0; return HGS_OK;
+        case HGS_OPT_AUTO_REGROW: c->auto_regrow = val != 0; return HGS_OK;
+        case HGS_OPT_COUNT_NALG: c->ropts.count_nalg = val != 0; return HGS_OK;
+        case HGS_OPT_BATCH_DEPTH:
+            if (val != 64 && val != 128 && val != 256 && val != 512) return fail(c, HGS_E_INVALID, "batch depth must be 64, 128, 256 or 512");
+            c->ropts.batch = (int)val;
+            return HGS_OK;
+        case HGS_OPT_USE_GRAPH: c->use_graph = val != 0; return HGS_OK;
+        case HGS_OPT_PERSISTENT: c->ropts.persistent = val != 0; return HGS_OK;
+        case HGS_OPT_EXACT_TILES: c->ropts.exact_tiles = val != 0; return HGS_OK;
+        case HGS_OPT_STAGE_TIMING: {
+            hgs_status s = harvest_events(c);
+            if (s) return s;
+            c->stage_timing = val != 0;
+            for (double& a : c->acc_ms) a = 0;
+            c->acc_n = 0;
+            return HGS_OK;
+        }
+        case HGS_OPT_INITIAL_CAPACITY: {
+            if (val < 0 || val > 0x7fffffff) return fail(c, HGS_E_INVALID, "capacity out of range");
+            c->forced_cap = (uint32_t)val;
+            if (c->forced_cap) {
+                // shrink: drop the work buffers so they are re-made at this size
+                DevMem* w[] = {&c->frontier[0], &c->frontier[1], &c->cut, &c->proj, &c->dkey[0], &c->dkey[1],
+                               &c->dval[0], &c->dval[1], &c->ntiles, &c->rect, &c->offsets, &c->pkey[0],
+                               &c->pkey[1], &c->pval[0], &c->pval[1]};
+                HIP_TRY(c, hipDeviceSynchronize());
+                for (DevMem* m : w) release(*m);
+                c->frontier_cap = c->cut_cap = c->pair_cap = 0;
+                if (c->loaded && !c->cams.empty()) {
+                    initial_caps(c);
+                    hgs_status s = alloc_work(c);
+                    if (s) return s;
+                }
+            }
+            return HGS_OK;
+        }
+        default: return fail(c, HGS_E_INVALID, "unknown option %d", opt);
+    }
+}
+
+hgs_status hgs_render(hgs_ctx* c, void* stream, const hgs_output* outs) {
+    if (!c) return HGS_E_INVALID;
+    if (!c->loaded) return fail(c, HGS_E_STATE, "no scene loaded");
+    if (c->cams.empty()) return fail(c, HGS_E_STATE, "no cameras set");
+    if (!outs) return fail(c, HGS_E_INVALID, "outs is NULL");
+    for (size_t v = 0; v < c->cams.size(); ++v)
+        if (!outs[v].rgb) return fail(c, HGS_E_INVALID, "view %zu: rgb output is NULL", v);
+    if (c->lod_mode == HGS_LOD_LEARNED && !c->mlp_loaded) return fail(c, HGS_E_STATE, "learned LOD without a network");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    hgs_status st;
+    if ((st = upload_views(c, s, outs))) return st;
+    c->regrows = 0;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        enqueue_render(c, s);
+        HIP_TRY(c, hipGetLastError());
+        c->last_valid = true;
+        if (!c->sync_check) return HGS_OK;
+        HIP_TRY(c, hipMemcpyAsync(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        const Counters k = *c->ctr_host;
+        if (!k.overflow) return HGS_OK;
+        c->last_valid = false;
+        if (!c->auto_regrow) {
+            grow_from(c, k);
+            return fail(c, HGS_E_CAPACITY, "work buffers overflowed (bits %u); capacities grown", k.overflow);
+        }
+        if ((st = grow_from(c, k))) return st;
+    }
+    return fail(c, HGS_E_CAPACITY, "work buffers kept overflowing");
+}
+
+hgs_status hgs_check(hgs_ctx* c) {
+    if (!c) return HGS_E_INVALID;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost));
+    const Counters k = *c->ctr_host;
+    if (k.overflow) {
+        c->last_valid = false;
+        hgs_status s = grow_from(c, k);
+        if (s) return s;
+        return fail(c, HGS_E_CAPACITY, "work buffers overflowed (bits %u); capacities grown", k.overflow);
+    }
+    return HGS_OK;
+}
+
+hgs_status hgs_get_cut(hgs_ctx* c, int32_t view, int32_t* ids, int64_t cap, int64_t* count) {
+    if (!c || !count) return HGS_E_INVALID;
+    if (!c->last_valid) return fail(c, HGS_E_STATE, "no valid render");
+    if (view < 0 || view >= (int)c->cams.size()) return fail(c, HGS_E_INVALID, "view out of range");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost));
+    const uint32_t m = std::min(c->ctr_host->cut, c->cut_cap);
+    std::vector<uint2> e(m);
+    if (m) HIP_TRY(c, hipMemcpy(e.data(), c->cut.p, (size_t)m * sizeof(uint2), hipMemcpyDeviceToHost));
+    int64_t k = 0;
+    for (uint32_t i = 0; i < m; ++i)
+        if ((int32_t)e[i].y == view) {
+            if (ids && k < cap) ids[k] = (int32_t)e[i].x;
+            ++k;
+        }
+    *count = k;
+    return HGS_OK;
+}
+
+hgs_status hgs_get_projected(hgs_ctx* c, int32_t view, float* out, int64_t cap, int64_t* count) {
+    if (!c || !count) return HGS_E_INVALID;
+    if (!c->last_valid) return fail(c, HGS_E_STATE, "no valid render");
+    if (view < 0 || view >= (int)c->cams.size()) return fail(c, HGS_E_INVALID, "view out of range");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost));
+    const uint32_t m = std::min(c->ctr_host->cut, c->cut_cap);
+    std::vector<uint2> e(m);
+    std::vector<Proj> p(m);
+    std::vector<uint32_t> nt(m);
+    if (m) {
+        HIP_TRY(c, hipMemcpy(e.data(), c->cut.p, (size_t)m * sizeof(uint2), hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(p.data(), c->proj.p, (size_t)m * sizeof(Proj), hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(nt.data(), c->ntiles.p, (size_t)m * 4, hipMemcpyDeviceToHost));
+    }
+    int64_t k = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        if ((int32_t)e[i].y != view) continue;
+        if (out && k < cap) {
+            float* o = out + 12 * k;
+            const Proj& q = p[i];
+            const double A = (double)q.p * q.p, B = (double)q.p * q.r, C = (double)q.r * q.r + (double)q.s * q.s;
+            o[0] = (float)q.u; o[1] = (float)q.v; o[2] = (float)A; o[3] = (float)B; o[4] = (float)C;
+            o[5] = q.c0; o[6] = q.c1; o[7] = q.c2; o[8] = q.z; o[9] = q.opacity;
+            o[10] = (float)nt[i];
+            o[11] = q.p > 0.f ? 1.f : 0.f;
+        }
+        ++k;
+    }
+    *count = k;
+    return HGS_OK;
+}
+
+hgs_status hgs_get_stats(hgs_ctx* c, hgs_stats* out) {
+    if (!c || !out) return HGS_E_INVALID;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost));
+    const Counters& k = *c->ctr_host;
+    std::memset(out, 0, sizeof(*out));
+    out->cut_size = std::min(k.cut, c->cut_cap);
+    out->visible = k.visible;
+    out->pairs = std::min(k.pairs, c->pair_cap);
+    out->n_alg = (int64_t)k.nalg;
+    out->tiles = c->total_tiles;
+    out->regrows = c->regrows;
+    hgs_status s = harvest_events(c);
+    if (s) return s;
+    out->timed_renders = c->acc_n;
+    out->ms_cut = c->acc_ms[0];
+    out->ms_project = c->acc_ms[1];
+    out->ms_sort = c->acc_ms[2];
+    out->ms_composite = c->acc_ms[3];
+    out->ms_total = c->acc_ms[4];
+    return HGS_OK;
+}
+
+hgs_status hgs_sort_pairs(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* vals, int64_t n, int32_t key_bits) {
+    if (!c || (!keys && n > 0) || (!vals && n > 0)) return HGS_E_INVALID;
+    if (n < 0 || n >= (int64_t)0xF0000000ll) return fail(c, HGS_E_INVALID, "n out of range");
+    if (key_bits < 1 || key_bits > 32) return fail(c, HGS_E_INVALID, "key_bits must be 1..32");
+    if (n == 0) return HGS_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    hgs_status st;
+    if ((st = ensure(c, c->sort_k, (size_t)n * 4)) || (st = ensure(c, c->sort_v, (size_t)n * 4)) ||
+        (st = ensure(c, c->sort_n, 4)) || (st = ensure(c, c->hist, (256 * kSortBlocks + 256) * 4)))
+        return st;
+    const uint32_t nn = (uint32_t)n;
+    HIP_TRY(c, hipMemcpyAsync(c->sort_n.p, &nn, 4, hipMemcpyHostToDevice, s));
+    SortArgs a{};
+    a.keys[0] = keys;
+    a.keys[1] = P<uint32_t>(c->sort_k);
+    a.vals[0] = vals;
+    a.vals[1] = P<uint32_t>(c->sort_v);
+    a.count = P<uint32_t>(c->sort_n);
+    a.cap = nn;
+    a.key_bits = key_bits;
+    a.hist = P<uint32_t>(c->hist);
+    const int r = launch_sort(a, s);
+    if (r == 1) {
+        HIP_TRY(c, hipMemcpyAsync(keys, a.keys[1], (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(vals, a.vals[1], (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return HGS_OK;
+}
+
+}  // extern "C"

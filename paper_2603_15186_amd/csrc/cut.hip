@@ -1,0 +1,247 @@
+// Level-of-detail cut on the GPU.
+//
+// Top-down, level-synchronous traversal of the hierarchy for all views at
+// once (NavGSim Sec. III-B: LOD rendering selects Gaussians from different
+// levels of the tree).  The frontier holds (node, view) entries of one level
+// in (view, node) order.  Per level:
+//   count : each block evaluates its contiguous chunk and reduces
+//           (emitted, children) counts;
+//   scan  : one block scans the per-block counts, advances the cut size and
+//           sets the next frontier size (capacity checks here);
+//   emit  : each block re-evaluates its chunk (deterministic), scans within
+//           the block and writes emitted ids and child ids in order.
+// Ids come out ascending per view because ids are level-major and children
+// of a node are contiguous and ordered like their parents.
+//
+// The node test is exact: FP64 with +, -, * only, in a fixed order, with FMA
+// contraction disabled, so every IEEE FP64 implementation selects the same
+// node set.
+#include "device_util.h"
+#include "internal.h"
+#include "lod_mlp.h"
+
+namespace hgs {
+
+namespace {
+
+constexpr int kNT = 256;
+
+enum : uint32_t { kDrop = 0, kEmit = 1, kExpand = 2 };
+
+// Decide a node for a view: dropped (sphere outside the frustum), emitted,
+// or expanded into its children.
+__device__ __noinline__ uint32_t node_decision(const ViewDev& V, int k, float4 b, int nchild, int mode,
+                                               const void* mlp, int level) {
+#pragma clang fp contract(off)
+    const double dx = (double)b.x - V.o[0];
+    const double dy = (double)b.y - V.o[1];
+    const double dz = (double)b.z - V.o[2];
+    const double r = (double)b.w;
+    const double px = (V.R[0] * dx + V.R[1] * dy) + V.R[2] * dz;
+    const double py = (V.R[3] * dx + V.R[4] * dy) + V.R[5] * dz;
+    const double pz = (V.R[6] * dx + V.R[7] * dy) + V.R[8] * dz;
+    if (pz + r < V.znear) return kDrop;
+    const double rr = r * r;
+    const double eL = V.fx * px + V.cx * pz;
+    if (eL < 0.0 && eL * eL > rr * V.nl) return kDrop;
+    const double eR = V.fx * px + (V.cx - V.W) * pz;
+    if (eR > 0.0 && eR * eR > rr * V.nr) return kDrop;
+    const double eT = V.fy * py + V.cy * pz;
+    if (eT < 0.0 && eT * eT > rr * V.nt) return kDrop;
+    const double eB = V.fy * py + (V.cy - V.H) * pz;
+    if (eB > 0.0 && eB * eB > rr * V.nb) return kDrop;
+    if (nchild == 0) return kEmit;
+    const double a = V.f2 * r;
+    const double lhs = a * a;
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    const double rhs = V.tau2 * d2;
+    const bool expand = lhs > rhs;
+    if (!expand) return kEmit;
+    if (mode == HGS_LOD_LEARNED && mlp != nullptr) {
+        // learned refinement: may keep a node the threshold would expand
+        const double dist = sqrt(d2);
+        if (!lod_mlp_expand(mlp, V, k, b, dist, pz, level)) return kEmit;
+    }
+    return kExpand;
+}
+
+struct LevelCtx {
+    const float4* bound;
+    const int2* child;
+    const ViewDev* views;
+    const uint2* in;
+    uint32_t* in_count;
+    uint2* out;
+    uint32_t out_cap;
+    uint2* cut;
+    uint32_t cut_cap;
+    uint2* tmp;               // [G] block counts, then offsets; [G] = level base
+    Counters* ctr;
+    int mode;
+    const void* mlp;
+    int level;
+    int out_slot;             // index of the next frontier's counter
+};
+
+__device__ __forceinline__ void chunk_of(uint32_t n, int G, int b, uint32_t* lo, uint32_t* hi) {
+    uint32_t chunk = ceil_div(n, (uint32_t)G);
+    if (chunk < (uint32_t)kNT) chunk = kNT;
+    chunk = ceil_div(chunk, (uint32_t)kNT) * kNT;
+    uint64_t s = (uint64_t)b * chunk, e = s + chunk;
+    *lo = (uint32_t)(s < n ? s : n);
+    *hi = (uint32_t)(e < n ? e : n);
+}
+
+__device__ __forceinline__ uint2 eval_entry(const LevelCtx& c, uint2 e) {
+    const float4 b = c.bound[e.x];
+    const int2 ch = c.child[e.x];
+    const uint32_t d = node_decision(c.views[e.y], (int)e.x, b, ch.y, c.mode, c.mlp, c.level);
+    return make_uint2(d == kEmit ? 1u : 0u, d == kExpand ? (uint32_t)ch.y : 0u);
+}
+
+__global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap) {
+    __shared__ uint2 sh[kNT / kWave + 1];
+    uint32_t n = *c.in_count;
+    n = n < in_cap ? n : in_cap;
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
+    uint2 acc = make_uint2(0, 0);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kNT) {
+        const uint2 r = eval_entry(c, c.in[i]);
+        acc.x += r.x;
+        acc.y += r.y;
+    }
+    uint2 tot;
+    block_excl_scan2<kNT>(acc, sh, &tot);
+    if (threadIdx.x == 0) c.tmp[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G) {
+    __shared__ uint2 sh[1024 / kWave + 1];
+    const int t = threadIdx.x;
+    const uint2 x = t < G ? c.tmp[t] : make_uint2(0, 0);
+    uint2 tot;
+    const uint2 ex = block_excl_scan2<1024>(x, sh, &tot);
+    if (t < G) c.tmp[t] = ex;
+    if (t == 0) {
+        Counters* k = c.ctr;
+        const uint32_t base = k->cut;
+        c.tmp[G] = make_uint2(base, 0);
+        const uint64_t want_cut = (uint64_t)base + tot.x;
+        if (want_cut > c.cut_cap) {
+            k->overflow |= kOvCut;
+            if (want_cut > k->need_cut) k->need_cut = (uint32_t)(want_cut < 0xffffffffull ? want_cut : 0xffffffffull);
+        }
+        k->cut = (uint32_t)(want_cut < c.cut_cap ? want_cut : c.cut_cap);
+        if (tot.y > c.out_cap) {
+            k->overflow |= kOvFrontier;
+            if (tot.y > k->need_frontier) k->need_frontier = tot.y;
+        }
+        k->frontier[c.out_slot] = tot.y < c.out_cap ? tot.y : c.out_cap;
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap) {
+    __shared__ uint2 sh[kNT / kWave + 1];
+    uint32_t n = *c.in_count;
+    n = n < in_cap ? n : in_cap;
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
+    if (lo >= hi) return;
+    uint2 off = c.tmp[blockIdx.x];
+    const uint32_t base = c.tmp[gridDim.x].x;
+    for (uint32_t s = lo; s < hi; s += kNT) {
+        const uint32_t i = s + threadIdx.x;
+        uint2 r = make_uint2(0, 0);
+        uint2 e = make_uint2(0, 0);
+        if (i < hi) {
+            e = c.in[i];
+            r = eval_entry(c, e);
+        }
+        uint2 tot;
+        const uint2 ex = block_excl_scan2<kNT>(r, sh, &tot);
+        if (r.x) {
+            const uint64_t pos = (uint64_t)base + off.x + ex.x;
+            if (pos < c.cut_cap) c.cut[pos] = e;
+        }
+        if (r.y) {
+            const int first = c.child[e.x].x;
+            for (uint32_t j = 0; j < r.y; ++j) {
+                const uint64_t pos = (uint64_t)off.y + ex.y + j;
+                if (pos < c.out_cap) c.out[pos] = make_uint2((uint32_t)(first + (int)j), e.y);
+            }
+        }
+        off.x += tot.x;
+        off.y += tot.y;
+    }
+}
+
+// Frontier of every view's roots (nodes [0, n_roots)), view-major.
+__global__ void k_init_roots(uint2* out, uint32_t n_roots, uint32_t n_views, uint32_t cap, Counters* ctr, int slot) {
+    const uint32_t total = n_roots * n_views;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x)
+        if (i < cap) out[i] = make_uint2(i % n_roots, i / n_roots);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (total > cap) {
+            ctr->overflow |= kOvFrontier;
+            if (total > ctr->need_frontier) ctr->need_frontier = total;
+        }
+        ctr->frontier[slot] = total < cap ? total : cap;
+    }
+}
+
+// Every listed id (or 0..n-1 when ids is null) for every view, view-major.
+__global__ void k_emit_all(uint2* cut, const int32_t* ids, uint32_t n, uint32_t n_views, uint32_t cap, Counters* ctr) {
+    const uint64_t total = (uint64_t)n * n_views;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total && i < cap;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = (uint32_t)(i % n);
+        cut[i] = make_uint2(ids ? (uint32_t)ids[k] : k, (uint32_t)(i / n));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (total > cap) {
+            ctr->overflow |= kOvCut;
+            ctr->need_cut = (uint32_t)(total < 0xffffffffull ? total : 0xffffffffull);
+        }
+        ctr->cut = (uint32_t)(total < cap ? total : cap);
+    }
+}
+
+}  // namespace
+
+void launch_cut(const CutArgs& a, hipStream_t s) {
+    const int G = kScanBlocks;
+    if (a.flat || a.mode == HGS_LOD_ALL_LEAVES) {
+        const uint32_t n = a.flat ? (uint32_t)a.n_nodes : (uint32_t)a.n_leaves;
+        const int32_t* ids = a.flat ? nullptr : a.leaf_ids;
+        k_emit_all<<<2048, 256, 0, s>>>(a.cut, ids, n, (uint32_t)a.n_views, a.cut_cap, a.ctr);
+        return;
+    }
+    const uint32_t n_roots = (uint32_t)a.level_offset_host[1];
+    k_init_roots<<<64, 256, 0, s>>>(a.frontier[0], n_roots, (uint32_t)a.n_views, a.frontier_cap, a.ctr, 0);
+    int cur = 0;
+    for (int L = 0; L < a.n_levels; ++L) {
+        LevelCtx c;
+        c.bound = a.bound;
+        c.child = a.child;
+        c.views = a.views;
+        c.in = a.frontier[cur];
+        c.in_count = &a.ctr->frontier[cur];
+        c.out = a.frontier[cur ^ 1];
+        c.out_cap = a.frontier_cap;
+        c.cut = a.cut;
+        c.cut_cap = a.cut_cap;
+        c.tmp = a.scan_tmp;
+        c.ctr = a.ctr;
+        c.mode = a.mode;
+        c.mlp = a.mlp;
+        c.level = L;
+        c.out_slot = cur ^ 1;
+        k_level_count<<<G, kNT, 0, s>>>(c, a.frontier_cap);
+        k_level_scan<<<1, 1024, 0, s>>>(c, G);
+        k_level_emit<<<G, kNT, 0, s>>>(c, a.frontier_cap);
+        cur ^= 1;
+    }
+}
+
+}  // namespace hgs

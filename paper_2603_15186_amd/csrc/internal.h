@@ -1,0 +1,176 @@
+// Internal declarations shared by the renderer's translation units: device
+// data layouts, per-view parameters, counters and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hgs.h"
+
+namespace hgs {
+
+constexpr int kTile = 16;                 // tile edge in pixels
+constexpr int kTilePx = kTile * kTile;    // pixels per tile
+constexpr int kMaxViews = 4096;
+
+// Overflow bits in Counters::overflow.
+constexpr uint32_t kOvFrontier = 1u;
+constexpr uint32_t kOvCut = 2u;
+constexpr uint32_t kOvPairs = 4u;
+
+// Per-view parameters, resident in device memory.  FP64 copies of the
+// extrinsics and intrinsics feed the cut and the projection; the compositor
+// reads the image layout and output pointers.
+struct ViewDev {
+    double o[3];
+    double R[9];
+    double fx, fy, cx, cy, W, H, znear;
+    double f2, tau2;                 // cut: 2 max(fx, fy) and tau^2
+    double nl, nr, nt, nb;           // squared lengths of the side-plane normals
+    double limx, limy;               // Jacobian clamp on x/z and y/z
+    float bg[3];
+    int32_t width, height, tiles_x, tiles_y;
+    uint32_t tile_base;              // first global tile id of this view
+    float* rgb;
+    float* depth;
+    float* alpha;
+};
+
+// Projected Gaussian, one per cut entry (48 bytes).  The conic is kept as
+// the factors of q = (p dx + r dy)^2 + (s dy)^2, which evaluates a sum of
+// squares instead of a cancelling quadratic form.
+struct alignas(16) Proj {
+    double u, v;                     // 2D mean, pixels
+    float p, r, s;                   // conic factors
+    float opacity;
+    float c0, c1, c2;                // clamped RGB
+    float z;                         // camera-space depth
+};
+
+// Device counters of one render.
+struct Counters {
+    uint32_t frontier[2];            // frontier sizes (ping, pong)
+    uint32_t cut;                    // cut entries written so far
+    uint32_t pairs;                  // total (tile, Gaussian) pairs
+    uint32_t overflow;               // kOv* bits
+    uint32_t need_frontier;          // largest frontier requested
+    uint32_t need_cut;               // cut entries requested
+    uint32_t need_pairs;             // pairs requested
+    uint32_t visible;                // cut entries with at least one tile
+    uint32_t tile_queue;             // persistent compositor work counter
+    unsigned long long nalg;         // evaluated (pixel, Gaussian) pairs
+};
+
+// Options of the compositor and binning.
+struct RenderOpts {
+    int batch = 256;
+    bool count_nalg = false;
+    bool persistent = false;
+    bool exact_tiles = true;
+};
+
+// ---------------------------------------------------------------- launchers
+
+// Scan scratch needs (uint2 / uint32 elements).
+constexpr int kScanBlocks = 1024;
+constexpr int kSortBlocks = 1024;
+
+// Threshold / all-leaves / flat cut for all views.  Writes (node, view)
+// entries to `cut` and the count to ctr->cut.
+struct CutArgs {
+    const float4* bound;
+    const int2* child;               // (first_child, child_count)
+    const int32_t* leaf_ids;         // ascending leaf ids (all-leaves mode)
+    int64_t n_leaves;
+    int64_t n_nodes;
+    const int64_t* level_offset_host;
+    int n_levels;
+    int mode;                        // HGS_LOD_*
+    bool flat;
+    const ViewDev* views;
+    int n_views;
+    uint2* frontier[2];
+    uint32_t frontier_cap;
+    uint2* cut;
+    uint32_t cut_cap;
+    uint2* scan_tmp;                 // kScanBlocks + 1 entries
+    Counters* ctr;
+    // learned refinement (nullptr = off)
+    const void* mlp;
+};
+void launch_cut(const CutArgs& a, hipStream_t s);
+
+struct ProjectArgs {
+    const uint2* cut;
+    uint32_t cut_cap;
+    const float4* geo;               // [n*3]
+    const float* sh;                 // planar [(k*3+c)*n + g]
+    int64_t n;
+    int sh_degree;
+    const ViewDev* views;
+    Proj* proj;
+    uint32_t* depth_key;
+    uint32_t* depth_val;
+    uint32_t* ntiles;
+    ushort4* rect;
+    bool exact_tiles;
+    Counters* ctr;
+};
+void launch_project(const ProjectArgs& a, hipStream_t s);
+
+// Pair emission in depth order: offsets = exclusive scan of ntiles over the
+// depth-sorted entries.
+struct EmitArgs {
+    const uint32_t* order;           // depth-sorted entry indices
+    const uint32_t* ntiles;
+    const ushort4* rect;
+    const Proj* proj;
+    const uint2* cut;
+    const ViewDev* views;
+    uint32_t cut_cap;
+    uint32_t* offsets;               // scratch [cut_cap]
+    uint32_t* keys;
+    uint32_t* vals;
+    uint32_t pair_cap;
+    bool exact_tiles;
+    uint2* scan_tmp;
+    Counters* ctr;
+};
+void launch_emit(const EmitArgs& a, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs by the low key_bits bits.
+// count: device pointer to n (clamped to cap).  Ping-pong buffers; returns
+// the index (0 or 1) of the buffer pair that holds the result.
+struct SortArgs {
+    uint32_t* keys[2];
+    uint32_t* vals[2];
+    const uint32_t* count;
+    uint32_t cap;
+    int key_bits;
+    uint32_t* hist;                  // 256 * kSortBlocks + 256
+};
+int launch_sort(const SortArgs& a, hipStream_t s);
+
+struct CompositeArgs {
+    const uint32_t* keys;            // sorted tile ids
+    const uint32_t* vals;            // entry indices
+    uint32_t pair_cap;
+    uint32_t cut_cap;
+    uint2* ranges;                   // [total_tiles]
+    uint32_t total_tiles;
+    const Proj* proj;
+    const ViewDev* views;
+    const uint32_t* tile_view;       // [total_tiles] view of each global tile
+    int n_views;
+    RenderOpts opts;
+    Counters* ctr;
+};
+void launch_ranges(const CompositeArgs& a, hipStream_t s);
+void launch_composite(const CompositeArgs& a, hipStream_t s);
+
+void launch_reset_counters(Counters* c, hipStream_t s);
+
+}  // namespace hgs

@@ -1,0 +1,381 @@
+// EWA projection of the cut's Gaussians with spherical-harmonic colour, and
+// pair emission in depth order.
+//
+// Per cut entry (node, view): Sigma = R S S^T R^T (Supplementary Material of
+// NavGSim), camera-space mean t = W (mu - o), first-order perspective
+// Jacobian J at the mean (x/z and y/z clamped to 1.3x the half field of
+// view), Sigma' = J W Sigma W^T J^T + 0.3 I, 2D mean (fx tx/tz + cx,
+// fy ty/tz + cy), colour clamp(sum_k f_k Y_k(d) + 0.5, 0, 1).
+//
+// The geometry runs in FP64 (the pass is bound by HBM traffic; FP64 keeps
+// the conic of edge-on sheets accurate).  Sigma' is formed as T T^T with
+// T = J W R S (2x3), which is symmetric positive semidefinite by
+// construction.  The depth key is the single-precision value of the FP64
+// camera depth, whose three-term sum is evaluated in a fixed order with
+// contraction disabled, so the depth order is an exact, reproducible result.
+#include "device_util.h"
+#include "internal.h"
+
+namespace hgs {
+
+namespace {
+
+constexpr int kNT = 256;
+// Binning covers q <= 9 (1 + kBinSlack): a superset of every pixel the
+// compositor can take, whatever the rounding of its single-precision q.
+constexpr double kBinSlack = 1e-3;
+
+// Real spherical-harmonic basis (Condon-Shortley phase) up to degree 3 as
+// Cartesian polynomials of the unit direction; index l*l + l + m.
+// Constants: sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) times the polynomial's
+// normalising factor, e.g. 0.5 sqrt(1/pi), sqrt(3/(4 pi)), 0.5 sqrt(15/pi),
+// 0.25 sqrt(5/pi), 0.25 sqrt(15/pi), 0.25 sqrt(35/(2 pi)), 0.5 sqrt(105/pi),
+// 0.25 sqrt(21/(2 pi)), 0.25 sqrt(7/pi), 0.25 sqrt(105/pi).
+__device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t n, int64_t g, int deg, float x,
+                                          float y, float z, float rgb[3]) {
+    constexpr float k00 = 0.28209479177387814f;
+    constexpr float k1 = 0.48860251190291992f;
+    constexpr float k2a = 1.0925484305920792f, k2b = 0.31539156525252005f, k2c = 0.54627421529603959f;
+    constexpr float k3a = 0.59004358992664352f, k3b = 2.8906114426405538f, k3c = 0.45704579946446572f,
+                    k3d = 0.3731763325901154f, k3e = 1.4453057213202769f;
+    float Y[16];
+    Y[0] = k00;
+    int K = 1;
+    if (deg >= 1) {
+        Y[1] = -k1 * y;
+        Y[2] = k1 * z;
+        Y[3] = -k1 * x;
+        K = 4;
+    }
+    if (deg >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = k2a * x * y;
+        Y[5] = -k2a * y * z;
+        Y[6] = k2b * (3.f * zz - 1.f);
+        Y[7] = -k2a * x * z;
+        Y[8] = k2c * (xx - yy);
+        K = 9;
+        if (deg >= 3) {
+            Y[9] = -k3a * y * (3.f * xx - yy);
+            Y[10] = k3b * x * y * z;
+            Y[11] = -k3c * y * (5.f * zz - 1.f);
+            Y[12] = k3d * z * (5.f * zz - 3.f);
+            Y[13] = -k3c * x * (5.f * zz - 1.f);
+            Y[14] = k3e * z * (xx - yy);
+            Y[15] = -k3a * x * (xx - 3.f * yy);
+            K = 16;
+        }
+    }
+    float acc[3] = {0.5f, 0.5f, 0.5f};
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = fmaf(sh[(int64_t)(k * 3 + c) * n + g], Y[k], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rgb[c] = fminf(fmaxf(acc[c], 0.f), 1.f);
+}
+
+// Does the ellipse q(d) <= qmax (q = A dx^2 + 2 B dx dy + C dy^2, d relative
+// to the mean) reach the rectangle [x0, x1] x [y0, y1]?  Exact minimum of the
+// quadratic over the rectangle: inside, or on one of the four edges.
+__device__ __forceinline__ bool ellipse_hits_rect(double A, double B, double C, double x0, double x1, double y0,
+                                                  double y1, double qmax) {
+    if (x0 <= 0.0 && 0.0 <= x1 && y0 <= 0.0 && 0.0 <= y1) return true;
+    double best = 1e300;
+    const double xs[2] = {x0, x1}, ys[2] = {y0, y1};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double X = xs[i];
+        double y = -B * X / C;
+        y = y < y0 ? y0 : (y > y1 ? y1 : y);
+        const double q = A * X * X + 2.0 * B * X * y + C * y * y;
+        best = q < best ? q : best;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double Y = ys[i];
+        double x = -B * Y / A;
+        x = x < x0 ? x0 : (x > x1 ? x1 : x);
+        const double q = A * x * x + 2.0 * B * x * Y + C * Y * Y;
+        best = q < best ? q : best;
+    }
+    return best <= qmax;
+}
+
+// Conic of a projected entry, rebuilt from its stored single-precision
+// factors (the same inputs in the counting and the emitting pass).
+__device__ __forceinline__ void conic_of(const Proj& p, double* A, double* B, double* C) {
+    const double pp = p.p, rr = p.r, ss = p.s;
+    *A = pp * pp;
+    *B = pp * rr;
+    *C = rr * rr + ss * ss;
+}
+
+// Number of tiles of rect `rc` that the ellipse reaches (all of them when
+// exact is false).
+__device__ __forceinline__ uint32_t count_tiles(const Proj& p, ushort4 rc, int W, int H, bool exact) {
+    const uint32_t all = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
+    if (!exact || all <= 1) return all;
+    double A, B, C;
+    conic_of(p, &A, &B, &C);
+    const double qmax = 9.0 * (1.0 + kBinSlack);
+    uint32_t n = 0;
+    for (int ty = rc.y; ty <= rc.w; ++ty) {
+        const double y0 = ty * kTile + 0.5 - p.v;
+        const double y1 = fmin((double)(ty * kTile + kTile - 1), (double)(H - 1)) + 0.5 - p.v;
+        for (int tx = rc.x; tx <= rc.z; ++tx) {
+            const double x0 = tx * kTile + 0.5 - p.u;
+            const double x1 = fmin((double)(tx * kTile + kTile - 1), (double)(W - 1)) + 0.5 - p.u;
+            n += ellipse_hits_rect(A, B, C, x0, x1, y0, y1, qmax) ? 1u : 0u;
+        }
+    }
+    return n;
+}
+
+__global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
+    const uint32_t m = min(a.ctr->cut, a.cut_cap);
+    uint32_t vis = 0;
+    for (uint32_t i = blockIdx.x * kNT + threadIdx.x; i < m; i += gridDim.x * kNT) {
+        const uint2 e = a.cut[i];
+        const ViewDev& V = a.views[e.y];
+        const int64_t g = e.x;
+        const float4 g0 = a.geo[3 * g], g1 = a.geo[3 * g + 1], g2 = a.geo[3 * g + 2];
+        double dx, dy, dz, tx, ty, tz;
+        {
+#pragma clang fp contract(off)
+            dx = (double)g0.x - V.o[0];
+            dy = (double)g0.y - V.o[1];
+            dz = (double)g0.z - V.o[2];
+            tx = (V.R[0] * dx + V.R[1] * dy) + V.R[2] * dz;
+            ty = (V.R[3] * dx + V.R[4] * dy) + V.R[5] * dz;
+            tz = (V.R[6] * dx + V.R[7] * dy) + V.R[8] * dz;
+        }
+        Proj p = {};
+        uint32_t ntiles = 0;
+        ushort4 rc = make_ushort4(1, 1, 0, 0);
+        const float zf = (float)tz;
+        if (tz > V.znear) {
+            // rotation of the normalised quaternion (w, x, y, z)
+            double qw = g1.x, qx = g1.y, qy = g1.z, qz = g1.w;
+            const double qi = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+            qw *= qi; qx *= qi; qy *= qi; qz *= qi;
+            const double Rq[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
+                                  2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
+                                  2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
+            const double iz = 1.0 / tz;
+            double xr = tx * iz, yr = ty * iz;
+            xr = fmin(fmax(xr, -V.limx), V.limx);
+            yr = fmin(fmax(yr, -V.limy), V.limy);
+            // M = J W (2x3)
+            double M0[3], M1[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                M0[j] = V.fx * iz * (V.R[j] - xr * V.R[6 + j]);
+                M1[j] = V.fy * iz * (V.R[3 + j] - yr * V.R[6 + j]);
+            }
+            // T = M R diag(s)
+            const double sc[3] = {g2.x, g2.y, g2.z};
+            double T0[3], T1[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                T0[k] = (M0[0] * Rq[k] + M0[1] * Rq[3 + k] + M0[2] * Rq[6 + k]) * sc[k];
+                T1[k] = (M1[0] * Rq[k] + M1[1] * Rq[3 + k] + M1[2] * Rq[6 + k]) * sc[k];
+            }
+            const double s00 = T0[0] * T0[0] + T0[1] * T0[1] + T0[2] * T0[2] + 0.3;
+            const double s01 = T0[0] * T1[0] + T0[1] * T1[1] + T0[2] * T1[2];
+            const double s11 = T1[0] * T1[0] + T1[1] * T1[1] + T1[2] * T1[2] + 0.3;
+            const double det = s00 * s11 - s01 * s01;
+            if (det > 0.0) {
+                const double u = V.fx * tx * iz + V.cx;
+                const double v = V.fy * ty * iz + V.cy;
+                // q = (p dx + r dy)^2 + (s dy)^2 with p^2 = s11/det,
+                // p r = -s01/det, r^2 + s^2 = s00/det
+                const double is11 = 1.0 / s11;
+                p.u = u;
+                p.v = v;
+                p.p = (float)sqrt(s11 / det);
+                p.r = (float)(-s01 / sqrt(det * s11));
+                p.s = (float)sqrt(is11);
+                p.opacity = g0.w;
+                p.z = zf;
+                // pixel-centre bounding box of q <= 9 (1 + slack)
+                const double qm = 9.0 * (1.0 + kBinSlack);
+                const double ex = sqrt(qm * s00) + 1e-6, ey = sqrt(qm * s11) + 1e-6;
+                const double px0 = ceil(u - ex - 0.5), px1 = floor(u + ex - 0.5);
+                const double py0 = ceil(v - ey - 0.5), py1 = floor(v + ey - 0.5);
+                const double cx0 = fmax(px0, 0.0), cx1 = fmin(px1, (double)(V.width - 1));
+                const double cy0 = fmax(py0, 0.0), cy1 = fmin(py1, (double)(V.height - 1));
+                if (cx0 <= cx1 && cy0 <= cy1) {
+                    rc = make_ushort4((unsigned short)((int)cx0 / kTile), (unsigned short)((int)cy0 / kTile),
+                                      (unsigned short)((int)cx1 / kTile), (unsigned short)((int)cy1 / kTile));
+                    ntiles = count_tiles(p, rc, V.width, V.height, a.exact_tiles);
+                }
+                if (ntiles > 0) {
+                    const double id = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+                    float rgb[3];
+                    sh_colour(a.sh, a.n, g, a.sh_degree, (float)(dx * id), (float)(dy * id), (float)(dz * id), rgb);
+                    p.c0 = rgb[0];
+                    p.c1 = rgb[1];
+                    p.c2 = rgb[2];
+                }
+            }
+        }
+        a.proj[i] = p;
+        a.rect[i] = rc;
+        a.ntiles[i] = ntiles;
+        // positive depths order as their bit patterns; unbinned entries last
+        a.depth_key[i] = ntiles > 0 ? __float_as_uint(zf) : 0xffffffffu;
+        a.depth_val[i] = i;
+        vis += ntiles > 0 ? 1u : 0u;
+    }
+    vis = wave_sum(vis);
+    if (lane_id() == 0 && vis) atomicAdd(&a.ctr->visible, vis);
+}
+
+// ---------------------------------------------------------------- emission
+
+struct ScanCtx {
+    const uint32_t* order;
+    const uint32_t* ntiles;
+    const uint32_t* count;
+    uint32_t cap;
+    uint32_t* offsets;
+    uint2* tmp;
+    Counters* ctr;
+    uint32_t pair_cap;
+};
+
+__device__ __forceinline__ void chunk_of(uint32_t n, int G, int b, uint32_t* lo, uint32_t* hi) {
+    uint32_t chunk = ceil_div(n, (uint32_t)G);
+    if (chunk < (uint32_t)kNT) chunk = kNT;
+    chunk = ceil_div(chunk, (uint32_t)kNT) * kNT;
+    uint64_t s = (uint64_t)b * chunk, e = s + chunk;
+    *lo = (uint32_t)(s < n ? s : n);
+    *hi = (uint32_t)(e < n ? e : n);
+}
+
+__global__ __launch_bounds__(kNT) void k_scan_reduce(ScanCtx c) {
+    __shared__ uint32_t sh[kNT / kWave + 1];
+    const uint32_t n = min(*c.count, c.cap);
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
+    uint32_t acc = 0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kNT) {
+        const uint32_t e = c.order[i];
+        acc += e < n ? c.ntiles[e] : 0u;
+    }
+    uint32_t tot;
+    block_excl_scan<kNT>(acc, sh, &tot);
+    if (threadIdx.x == 0) c.tmp[blockIdx.x] = make_uint2(tot, 0);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(ScanCtx c, int G) {
+    __shared__ uint32_t sh[1024 / kWave + 1];
+    const int t = threadIdx.x;
+    // 64-bit running total: detect pair counts beyond 2^32 as overflow
+    const uint32_t x = t < G ? c.tmp[t].x : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<1024>(x, sh, &tot);
+    if (t < G) c.tmp[t].x = ex;
+    if (t == 0) {
+        Counters* k = c.ctr;
+        if (tot > c.pair_cap) {
+            k->overflow |= kOvPairs;
+            if (tot > k->need_pairs) k->need_pairs = tot;
+        }
+        k->pairs = tot < c.pair_cap ? tot : c.pair_cap;
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_scan_write(ScanCtx c) {
+    __shared__ uint32_t sh[kNT / kWave + 1];
+    const uint32_t n = min(*c.count, c.cap);
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
+    if (lo >= hi) return;
+    uint32_t off = c.tmp[blockIdx.x].x;
+    for (uint32_t s = lo; s < hi; s += kNT) {
+        const uint32_t i = s + threadIdx.x;
+        uint32_t x = 0;
+        if (i < hi) {
+            const uint32_t e = c.order[i];
+            x = e < n ? c.ntiles[e] : 0u;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<kNT>(x, sh, &tot);
+        if (i < hi) c.offsets[i] = off + ex;
+        off += tot;
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_emit(EmitArgs a) {
+    const uint32_t m = min(a.ctr->cut, a.cut_cap);
+    const uint32_t cap = a.pair_cap;
+    for (uint32_t i = blockIdx.x * kNT + threadIdx.x; i < m; i += gridDim.x * kNT) {
+        const uint32_t e = a.order[i];
+        if (e >= m) continue;
+        const uint32_t nt = a.ntiles[e];
+        if (nt == 0) continue;
+        uint32_t pos = a.offsets[i];
+        const ushort4 rc = a.rect[e];
+        const ViewDev& V = a.views[a.cut[e].y];
+        const uint32_t tb = V.tile_base;
+        const int tw = V.tiles_x;
+        const uint32_t all = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
+        if (!a.exact_tiles || all <= 1) {
+            for (int ty = rc.y; ty <= rc.w; ++ty)
+                for (int tx = rc.x; tx <= rc.z; ++tx) {
+                    if (pos < cap) {
+                        a.keys[pos] = tb + (uint32_t)(ty * tw + tx);
+                        a.vals[pos] = e;
+                    }
+                    ++pos;
+                }
+            continue;
+        }
+        const Proj p = a.proj[e];
+        double A, B, C;
+        conic_of(p, &A, &B, &C);
+        const double qmax = 9.0 * (1.0 + kBinSlack);
+        for (int ty = rc.y; ty <= rc.w; ++ty) {
+            const double y0 = ty * kTile + 0.5 - p.v;
+            const double y1 = fmin((double)(ty * kTile + kTile - 1), (double)(V.height - 1)) + 0.5 - p.v;
+            for (int tx = rc.x; tx <= rc.z; ++tx) {
+                const double x0 = tx * kTile + 0.5 - p.u;
+                const double x1 = fmin((double)(tx * kTile + kTile - 1), (double)(V.width - 1)) + 0.5 - p.u;
+                if (ellipse_hits_rect(A, B, C, x0, x1, y0, y1, qmax)) {
+                    if (pos < cap) {
+                        a.keys[pos] = tb + (uint32_t)(ty * tw + tx);
+                        a.vals[pos] = e;
+                    }
+                    ++pos;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+void launch_project(const ProjectArgs& a, hipStream_t s) {
+    k_project<<<4096, kNT, 0, s>>>(a);
+}
+
+void launch_emit(const EmitArgs& a, hipStream_t s) {
+    const int G = kScanBlocks;
+    ScanCtx c;
+    c.order = a.order;
+    c.ntiles = a.ntiles;
+    c.count = &a.ctr->cut;
+    c.cap = a.cut_cap;
+    c.offsets = a.offsets;
+    c.tmp = a.scan_tmp;
+    c.ctr = a.ctr;
+    c.pair_cap = a.pair_cap;
+    k_scan_reduce<<<G, kNT, 0, s>>>(c);
+    k_scan_blocks<<<1, 1024, 0, s>>>(c, G);
+    k_scan_write<<<G, kNT, 0, s>>>(c);
+    k_emit<<<4096, kNT, 0, s>>>(a);
+}
+
+}  // namespace hgs

@@ -1,0 +1,269 @@
+"""GPU parity of the HIP renderer against the FP64 oracle, through the C ABI.
+
+Sizes: the 20k-Gaussian random box at 256x256 (16 x 16 tiles) in full; the
+floor-plan scene at reduced leaf counts in full frames with a ragged tile
+edge; the 2M-leaf floor plan at 1280x720 on sampled pixels and bit-exact
+cuts.  The radix sort is checked bit-exactly against numpy's stable sort.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_15186_amd.synth import workloads as W, yaw_camera
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _hgs():
+    from paper_2603_15186_amd import hgs
+    return hgs
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = _hgs().Renderer(0)
+    yield r
+    r.close()
+
+
+def _render(r, scene, cams, mode=1, tau=1.0, **opts):
+    hgs = _hgs()
+    r.load_scene(scene)
+    r.set_cameras(cams)
+    if scene.parent is not None:
+        r.set_lod(mode, tau)
+    for k, v in opts.items():
+        r.set_option(getattr(hgs, "HGS_OPT_" + k.upper()), v)
+    outs = r.render()
+    torch.cuda.synchronize()
+    return [(a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()) for a, b, c in outs]
+
+
+def _check_full(img, scene, cam, mode=O.MODE_THRESHOLD, tau=1.0, ids=None, max_skip=0.002):
+    res, _, _ = O.render(scene, cam, mode, tau, ids=ids)
+    px, py = res.px, res.py
+    g = parity.gpu_pixels(*img, px, py)
+    ok, best, skipped = parity.branch_errors(g, res)
+    msg = parity.summary(ok, best, skipped)
+    print(msg, flush=True)
+    assert ok.all(), msg
+    assert skipped.mean() <= max_skip, msg
+    return res
+
+
+# ------------------------------------------------------------------ sort
+
+@pytest.mark.parametrize("n,bits", [(1, 8), (1000, 8), (300001, 12), (300001, 19), (2_000_003, 32), (5_000_000, 12)])
+def test_radix_sort_bit_exact(R, n, bits):
+    rng = np.random.default_rng(n + bits)
+    keys = rng.integers(0, 1 << bits, size=n, dtype=np.uint64).astype(np.uint32)
+    if n > 10:
+        keys[: n // 10] = keys[0]            # many equal keys: stability matters
+    vals = np.arange(n, dtype=np.uint32)
+    kd = torch.from_numpy(keys.view(np.int32)).cuda()
+    vd = torch.from_numpy(vals.view(np.int32)).cuda()
+    R.sort_pairs(kd, vd, bits)
+    torch.cuda.synchronize()
+    order = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(kd.cpu().numpy().view(np.uint32), keys[order])
+    np.testing.assert_array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
+
+
+# ------------------------------------------------------------------ flat scene
+
+@pytest.fixture(scope="module")
+def box():
+    return W.box20k()
+
+
+def test_box20k_full_frame_parity(R, box):
+    scene, cams = box
+    img = _render(R, scene, cams, count_nalg=1)[0]
+    res = _check_full(img, scene, cams[0])
+    st = R.stats()
+    assert st["cut_size"] == scene.n
+    # the GPU evaluates the same pixel/Gaussian pairs up to forks
+    assert abs(st["n_alg"] - res.nalg.sum()) <= 0.001 * res.nalg.sum()
+
+
+def test_box20k_centre_camera_parity(R, box):
+    scene, _ = box
+    cam = W.box_camera(center_view=True)
+    img = _render(R, scene, [cam])[0]
+    _check_full(img, scene, cam)
+
+
+def test_projection_stage_parity(R, box):
+    scene, cams = box
+    _render(R, scene, cams)
+    g = R.get_projected(0)
+    ids = np.arange(scene.n)
+    pr = O.project(scene, ids, cams[0])
+    valid = g[:, 11] > 0
+    assert np.array_equal(valid, pr[:, 0] > 0)
+    pv = pr[valid]
+    gv = g[valid]
+    # the 2D mean is read back rounded to single precision
+    for k, f in ((0, "u"), (1, "v")):
+        assert np.all(np.abs(gv[:, k] - pv[:, O.PF[f]]) <= 1e-4 + 1.2e-7 * np.abs(pv[:, O.PF[f]])), f
+    # conic from single-precision factors: relative to its scale sqrt(A C)
+    scale = np.sqrt(pv[:, O.PF["A"]] * pv[:, O.PF["C"]])
+    for k, f in ((2, "A"), (3, "B"), (4, "C")):
+        err = np.abs(gv[:, k] - pv[:, O.PF[f]]) / scale
+        assert err.max() <= 1e-5, (f, err.max())
+    np.testing.assert_array_equal(gv[:, 8], pv[:, O.PF["zkey"]].astype(np.float32))
+    vis = gv[:, 10] > 0
+    for k, f in ((5, "r"), (6, "g"), (7, "b")):
+        np.testing.assert_allclose(gv[vis, k], pv[vis, O.PF[f]], atol=2e-6)
+
+
+def test_invariance_across_launch_choices(R, box):
+    """Bitwise identical output for every batch depth, with and without exact
+    tile binning, persistent compositing, and across repeated renders."""
+    scene, cams = box
+    ref = _render(R, scene, cams, batch_depth=256, exact_tiles=1, persistent=0)[0]
+    again = _render(R, scene, cams)[0]
+    for a, b in zip(ref, again):
+        assert np.array_equal(a, b)
+    for opts in ({"batch_depth": 64}, {"batch_depth": 128}, {"batch_depth": 512}, {"exact_tiles": 0},
+                 {"persistent": 1}):
+        img = _render(R, scene, cams, **opts)[0]
+        for a, b in zip(ref, img):
+            assert np.array_equal(a, b), opts
+    _render(R, scene, cams, batch_depth=256, exact_tiles=1, persistent=0)
+
+
+def test_background_when_nothing_visible(R, box):
+    scene, _ = box
+    cam = yaw_camera(100, 37, 90.0, (2.0, -1.0, 1.5), -math.pi / 2, bg=(0.25, 0.5, 0.75))
+    rgb, dep, alp = _render(R, scene, [cam])[0]
+    np.testing.assert_array_equal(rgb[0], np.float32(0.25))
+    np.testing.assert_array_equal(rgb[2], np.float32(0.75))
+    assert not alp.any() and not dep.any()
+
+
+def test_capacity_regrow_gives_identical_image(R, box):
+    scene, cams = box
+    hgs = _hgs()
+    ref = _render(R, scene, cams)[0]
+    R.set_option(hgs.HGS_OPT_INITIAL_CAPACITY, 1024)
+    img = _render(R, scene, cams)[0]
+    assert R.stats()["regrows"] >= 1
+    R.set_option(hgs.HGS_OPT_INITIAL_CAPACITY, 0)
+    for a, b in zip(ref, img):
+        assert np.array_equal(a, b)
+
+
+def test_capacity_error_without_regrow(R, box):
+    scene, cams = box
+    hgs = _hgs()
+    R.load_scene(scene)
+    R.set_cameras(cams)
+    R.set_option(hgs.HGS_OPT_INITIAL_CAPACITY, 1024)
+    R.set_option(hgs.HGS_OPT_AUTO_REGROW, 0)
+    with pytest.raises(hgs.HgsError) as ei:
+        R.render()
+    assert ei.value.status == hgs.HGS_E_CAPACITY
+    R.set_option(hgs.HGS_OPT_AUTO_REGROW, 1)
+    R.set_option(hgs.HGS_OPT_INITIAL_CAPACITY, 0)
+    R.render()
+
+
+# ------------------------------------------------------------------ hierarchy
+
+@pytest.fixture(scope="module")
+def plan_small():
+    return W.plan2m(scale=0.02, n_poses=12)
+
+
+def _small_cam(c, W_=200, H_=117):
+    """A smaller camera with the pose of c (ragged tiles: 200 = 12.5 x 16)."""
+    return yaw_camera(W_, H_, 900.0 * W_ / 1280.0, c.position, math.atan2(c.R[2][1], c.R[2][0]))
+
+
+@pytest.mark.parametrize("tau", [0.5, 1.0, 2.0, 4.0, 16.0])
+def test_cut_bit_exact_small_plan(R, plan_small, tau):
+    scene, cams = plan_small
+    R.load_scene(scene)
+    R.set_cameras(cams[:4])
+    R.set_lod(1, tau)
+    R.render()
+    for v in range(4):
+        got = R.get_cut(v)
+        want = O.cut(scene, cams[v], O.MODE_THRESHOLD, tau)
+        assert np.array_equal(got, want), (v, tau, got.size, want.size)
+
+
+@pytest.mark.parametrize("tau", [1.0, 8.0])
+def test_plan_full_frame_parity(R, plan_small, tau):
+    scene, cams = plan_small
+    cam = _small_cam(cams[3])
+    img = _render(R, scene, [cam], tau=tau)[0]
+    _check_full(img, scene, cam, tau=tau)
+
+
+def test_all_leaves_mode_parity(R, plan_small):
+    scene, cams = plan_small
+    cam = _small_cam(cams[5], 96, 80)
+    img = _render(R, scene, [cam], mode=0)[0]
+    assert np.array_equal(R.get_cut(0), scene.leaf_ids())
+    _check_full(img, scene, cam, mode=O.MODE_ALL_LEAVES)
+
+
+def test_batched_views_equal_single_views(R, plan_small):
+    scene, cams = plan_small
+    views = [_small_cam(cams[1], 320, 240), _small_cam(cams[4], 128, 72), cams[7], _small_cam(cams[9], 33, 17)]
+    batch = _render(R, scene, views)
+    for v, cam in enumerate(views):
+        single = _render(R, scene, [cam])[0]
+        for a, b in zip(batch[v], single):
+            assert np.array_equal(a, b), v
+
+
+# ---------------------------------------------------------- full-size scene
+
+@pytest.fixture(scope="module")
+def plan_full():
+    return W.plan2m(n_poses=200)
+
+
+def test_plan2m_cut_bit_exact(R, plan_full):
+    scene, cams = plan_full
+    R.load_scene(scene)
+    sel = [0, 57, 123, 199]
+    R.set_cameras([cams[i] for i in sel])
+    for tau in (1.0, 2.0, 4.0):
+        R.set_lod(1, tau)
+        R.render()
+        for v, i in enumerate(sel):
+            got = R.get_cut(v)
+            want = O.cut(scene, cams[i], O.MODE_THRESHOLD, tau)
+            assert np.array_equal(got, want), (i, tau, got.size, want.size)
+
+
+def test_plan2m_sampled_pixel_parity(R, plan_full):
+    """1280x720 frames of the 2M-leaf scene at tau = 1 in the bench's launch
+    configuration; 3,000 sampled pixels per frame plus two full rows."""
+    scene, cams = plan_full
+    rng = np.random.default_rng(7)
+    for i in (10, 150):
+        cam = cams[i]
+        img = _render(R, scene, [cam])[0]
+        ids = R.get_cut(0)
+        px = np.concatenate([rng.integers(0, 1280, 3000), np.arange(1280), np.arange(1280)])
+        py = np.concatenate([rng.integers(0, 720, 3000), np.full(1280, 360), np.full(1280, 719)])
+        proj = O.project(scene, ids, cam)
+        res = O.render_pixels(proj, cam, px, py)
+        g = parity.gpu_pixels(*img, px, py)
+        ok, best, skipped = parity.branch_errors(g, res)
+        msg = parity.summary(ok, best, skipped)
+        print(i, msg, flush=True)
+        assert ok.all(), msg
+        assert skipped.mean() <= 0.002, msg
