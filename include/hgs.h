@@ -63,6 +63,8 @@ typedef int32_t hgs_status;
                                       (exercises overflow and regrowth); 0: automatic */
 #define HGS_OPT_STAGE_TIMING 9    /* 1: time the stages of every render with HIP events
                                      on its stream; setting it clears the sums */
+#define HGS_OPT_SORT_DIGIT_BITS 10 /* widest radix digit, 6..11 (default 8); any
+                                     value gives the same order */
 
 typedef struct hgs_ctx hgs_ctx;
 
@@ -193,11 +195,84 @@ hgs_status hgs_get_projected(hgs_ctx* ctx, int32_t view, float* host_out, int64_
 hgs_status hgs_get_stats(hgs_ctx* ctx, hgs_stats* out);
 
 /* Sort n (key, value) pairs on the device by the low `key_bits` bits of the
- * key, stably (LSD radix, 8-bit digits).  keys/vals are device pointers and
+ * key, stably (LSD radix, digits of up to HGS_OPT_SORT_DIGIT_BITS bits).  keys/vals are device pointers and
  * are sorted in place; the context's scratch memory is used.  For testing
  * the sort on its own. */
 hgs_status hgs_sort_pairs(hgs_ctx* ctx, void* stream, uint32_t* keys, uint32_t* vals,
                           int64_t n, int32_t key_bits);
+
+/* ---------------------------------------------------------------------- */
+/* Learned level-of-detail refinement.  The paper's LOD rendering picks     */
+/* Gaussians from different tree levels (NavGSim Sec. III-B); the learned  */
+/* rule below is the project's: a candidate is a node the threshold rule   */
+/* refines whose projected size is at most s_hi pixels; a small network    */
+/* (8 features, layers 8-32-32-1, ReLU, BF16 weights, FP32 accumulation)   */
+/* decides whether such a node is refined (p >= p_star) or kept.  Outside  */
+/* the band the threshold rule applies unchanged (the fallback).           */
+/* Features of (node, view), before standardisation: log projected size,  */
+/* log camera depth, opacity, child count, variance of the children's DC   */
+/* colour, |cos| of the view ray and the node's thinnest axis, level, log  */
+/* projected size of the parent.  Parameter layout (1377 values):          */
+/* W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3.                      */
+/* ---------------------------------------------------------------------- */
+
+/* Per view, a node that the cut never refines (-1: none); used to render a
+ * view with one subtree collapsed to its root.  n = number of views. */
+hgs_status hgs_set_keep_nodes(hgs_ctx* ctx, int32_t n, const int32_t* nodes);
+
+/* Run the threshold cut of the current views and collect the candidates
+ * (refined, projected size <= s_hi) in (view, level, id) order.  Device
+ * outputs, cap entries each: entries[2i] = node, entries[2i+1] = view;
+ * features[8i..8i+8) raw features; rects[4i..4i+4) = x0, y0, x1, y1 pixel
+ * bounds of the node's bounding-sphere projection, clipped to the image.
+ * *count = number of candidates; HGS_E_CAPACITY (with *count set) if cap
+ * is too small.  Synchronises with `stream`. */
+hgs_status hgs_lod_candidates(hgs_ctx* ctx, void* stream, float s_hi_px, uint32_t* entries, float* features,
+                              int32_t* rects, int64_t cap, int64_t* count);
+
+/* Install the network used by HGS_LOD_LEARNED (host arrays, copied):
+ * bf16_params[1377], feat_mean[8], feat_std[8] (> 0). */
+hgs_status hgs_load_lod_mlp(hgs_ctx* ctx, const uint16_t* bf16_params, const float* feat_mean,
+                            const float* feat_std, float p_star, float s_hi_px);
+
+/* Logits of n raw feature rows (device features[n*8], device bf16 weights
+ * w[1377], host feat_mean/feat_std[8]) into device logits[n]. */
+hgs_status hgs_mlp_forward(hgs_ctx* ctx, void* stream, const float* features, int64_t n, const uint16_t* w,
+                           const float* feat_mean, const float* feat_std, float* logits);
+
+/* One training step on the batch (device features[n*8], labels[n] in
+ * {0,1}): forward with the BF16 weights w, mean binary cross-entropy,
+ * backward, and (if lr > 0) an Adam step (beta 0.9/0.999, eps 1e-8, step
+ * counts from 1) on the FP32 master weights, after which w = BF16 of the
+ * masters.  grad_out[1377] and loss_out[1] (device, optional) receive the
+ * gradient and the loss.  Deterministic. */
+hgs_status hgs_mlp_train_step(hgs_ctx* ctx, void* stream, const float* features, const float* labels, int64_t n,
+                              const float* feat_mean, const float* feat_std, float* master, uint16_t* w,
+                              float* adam_m, float* adam_v, int32_t step, float lr, float* grad_out,
+                              float* loss_out);
+
+/* w[1377] = BF16 (nearest, ties to even) of the FP32 master[1377] (device). */
+hgs_status hgs_mlp_bf16_from_master(hgs_ctx* ctx, void* stream, const float* master, uint16_t* w);
+
+/* Column mean and standard deviation of device features[n*8] into device
+ * mean_std[16] (8 means then 8 deviations, at least 1e-6). */
+hgs_status hgs_feature_stats(hgs_ctx* ctx, void* stream, const float* features, int64_t n, float* mean_std);
+
+/* dst[3][H][W] = 2x2 box average of src[3][2H][2W] (device, planar). */
+hgs_status hgs_downsample2x(hgs_ctx* ctx, void* stream, const float* src, int32_t width, int32_t height,
+                            float* dst);
+
+/* A w x h planar RGB image compared with the window at (x0, y0) of a
+ * ref_w x ref_h planar RGB reference (device pointers). */
+typedef struct {
+    const float* img;
+    const float* ref;
+    int32_t w, h, ref_w, ref_h, x0, y0;
+} hgs_region;
+
+/* out[i] (device) = mean squared error over the 3 channels of region i.
+ * The descriptors are host memory (copied). */
+hgs_status hgs_region_mse(hgs_ctx* ctx, void* stream, int32_t n, const hgs_region* regions, float* out);
 
 #ifdef __cplusplus
 }

@@ -73,11 +73,10 @@ def project_one(mean, scale, quat, opacity, sh, cam):
     Sig = [[sum(float(scale[k]) ** 2 * axes[k][i] * axes[k][j] for k in range(3))
             for j in range(3)] for i in range(3)]
     fx, fy = float(cam.fx), float(cam.fy)
-    limx = 1.3 * 0.5 * cam.width / fx
-    limy = 1.3 * 0.5 * cam.height / fy
+    W, H, cx, cy = float(cam.width), float(cam.height), float(cam.cx), float(cam.cy)
     tz = t[2]
-    xr = min(max(t[0] / tz, -limx), limx)
-    yr = min(max(t[1] / tz, -limy), limy)
+    xr = min(max(t[0] / tz, (-cx - 0.15 * W) / fx), (W - cx + 0.15 * W) / fx)
+    yr = min(max(t[1] / tz, (-cy - 0.15 * H) / fy), (H - cy + 0.15 * H) / fy)
     # rows of J W: derivative of (fx x/z, fy y/z) in world coordinates
     g0 = [fx / tz * Rv[0][j] - fx * xr / tz * Rv[2][j] for j in range(3)]
     g1 = [fy / tz * Rv[1][j] - fy * yr / tz * Rv[2][j] for j in range(3)]

@@ -15,7 +15,8 @@
  * The paper defers everything else (projection, compositing, LOD metric) to
  * the hierarchical-3DGS work it builds on; the readings used here are listed
  * with the project's design notes: first-order (EWA) projection with a
- * 0.3 px^2 screen low-pass, 3-sigma ellipse support q <= 9, front-to-back
+ * 0.3 px^2 screen low-pass (Jacobian taken at the mean with x/z and y/z
+ * clamped to the image's range widened by 15 % of its size per side), 3-sigma ellipse support q <= 9, front-to-back
  * compositing with alpha capped at 0.99f, skipped below 1/255f and a stop
  * before transmittance falls below 1e-4f, depth order by the camera-space z
  * of the mean stored in single precision with ties by ascending id, and a
@@ -234,7 +235,12 @@ void or_project(int64_t m, const int32_t* ids, const float* means, const float* 
     for (int i = 0; i < 9; i++) Rv[i] = cam->R[i];
     for (int i = 0; i < 3; i++) o[i] = cam->position[i];
     const double fx = cam->fx, fy = cam->fy, cx = cam->cx, cy = cam->cy;
-    const double limx = 1.3 * (0.5 * cam->width / fx), limy = 1.3 * (0.5 * cam->height / fy);
+    /* Jacobian clamp: x/z within the image's tangent range widened by 15 %
+     * of the image size on each side (1.3 x the half field of view when the
+     * principal point is centred) */
+    const double W = cam->width, H = cam->height;
+    const double xlo = (-cx - 0.15 * W) / fx, xhi = (W - cx + 0.15 * W) / fx;
+    const double ylo = (-cy - 0.15 * H) / fy, yhi = (H - cy + 0.15 * H) / fy;
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < m; e++) {
         int64_t g = ids[e];
@@ -268,10 +274,10 @@ void or_project(int64_t m, const int32_t* ids, const float* means, const float* 
         /* Jacobian of the perspective map at the (clamped) mean */
         double tz = t[2];
         double xr = t[0] / tz, yr = t[1] / tz;
-        if (xr < -limx) xr = -limx;
-        if (xr > limx) xr = limx;
-        if (yr < -limy) yr = -limy;
-        if (yr > limy) yr = limy;
+        if (xr < xlo) xr = xlo;
+        if (xr > xhi) xr = xhi;
+        if (yr < ylo) yr = ylo;
+        if (yr > yhi) yr = yhi;
         double xh = xr * tz, yh = yr * tz;
         double J[9] = {fx / tz, 0, -fx * xh / (tz * tz), 0, fy / tz, -fy * yh / (tz * tz), 0, 0, 0};
         double JW[9], JWt[9], tmp[9], C2[9];

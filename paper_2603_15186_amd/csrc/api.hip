@@ -35,7 +35,7 @@ struct hgs_ctx {
     int n_levels = 0;
     std::vector<int64_t> level_offset;
     int64_t n_leaves = 0;
-    DevMem geo, sh, bound, child, leaf_ids, parent, nodefeat;
+    DevMem geo, sh, bound, child, leaf_ids, parent, nodefeat, lvl;
     // views
     std::vector<hgs_camera> cams;
     ViewDev* views_host = nullptr;    // pinned mirror
@@ -50,6 +50,8 @@ struct hgs_ctx {
     bool mlp_loaded = false;
     DevMem mlp_w, mlp_dev;
     LodMlpDev mlp_host{};
+    double s_hi = 64.0;               // candidate band of the learned cut (pixels)
+    DevMem train_scratch, region_dev;
     // options
     bool sync_check = true, auto_regrow = true, use_graph = false;
     RenderOpts ropts;
@@ -61,6 +63,7 @@ struct hgs_ctx {
     bool last_valid = false;
     int64_t regrows = 0;
     uint32_t forced_cap = 0;          // test hook: start from this capacity
+    int sort_digit_bits = 8;          // widest radix digit
     // stage timing: 6 events per render (start, cut, project, binning, composite start, end)
     bool stage_timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -113,6 +116,13 @@ template <typename T>
 T* P(const DevMem& m) { return static_cast<T*>(m.p); }
 
 bool finite(float x) { return std::isfinite(x); }
+
+float bf16_to_f32_host(uint16_t h) {
+    const uint32_t b = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
 
 hgs_status validate(const hgs_gaussians* g, const hgs_hierarchy* h, std::string* why) {
     auto bad = [&](hgs_status s, const std::string& m) {
@@ -216,8 +226,8 @@ hgs_status alloc_work(hgs_ctx* c) {
     if ((s = ensure(c, c->ntiles, M * 4))) return s;
     if ((s = ensure(c, c->rect, M * sizeof(ushort4)))) return s;
     if ((s = ensure(c, c->offsets, M * 4))) return s;
-    if ((s = ensure(c, c->scan_tmp, (kScanBlocks + 1) * sizeof(uint2)))) return s;
-    if ((s = ensure(c, c->hist, (256 * kSortBlocks + 256) * 4))) return s;
+    if ((s = ensure(c, c->scan_tmp, (kScanBlocks + 1) * sizeof(uint4)))) return s;
+    if ((s = ensure(c, c->hist, (size_t)kSortBins * (kSortBlocks + 1) * 4))) return s;
     return HGS_OK;
 }
 
@@ -318,9 +328,12 @@ void enqueue_render(hgs_ctx* c, hipStream_t s) {
     ca.frontier_cap = c->frontier_cap;
     ca.cut = P<uint2>(c->cut);
     ca.cut_cap = c->cut_cap;
-    ca.scan_tmp = P<uint2>(c->scan_tmp);
+    ca.scan_tmp = P<uint4>(c->scan_tmp);
     ca.ctr = ctr;
     ca.mlp = (c->lod_mode == HGS_LOD_LEARNED && c->mlp_loaded) ? c->mlp_dev.p : nullptr;
+    ca.s_hi = c->s_hi;
+    ca.cand = nullptr;
+    ca.cand_cap = 0;
     launch_cut(ca, s);
     mark(c, 1, s);
 
@@ -350,6 +363,7 @@ void enqueue_render(hgs_ctx* c, hipStream_t s) {
     sa.count = &ctr->cut;
     sa.cap = c->cut_cap;
     sa.key_bits = 32;
+    sa.max_digit_bits = c->sort_digit_bits;
     sa.hist = P<uint32_t>(c->hist);
     const int dr = launch_sort(sa, s);
 
@@ -378,6 +392,7 @@ void enqueue_render(hgs_ctx* c, hipStream_t s) {
     pb.count = &ctr->pairs;
     pb.cap = c->pair_cap;
     pb.key_bits = bits_for(c->total_tiles);
+    pb.max_digit_bits = c->sort_digit_bits;
     pb.hist = sa.hist;
     const int pr = launch_sort(pb, s);
 
@@ -399,6 +414,19 @@ void enqueue_render(hgs_ctx* c, hipStream_t s) {
     launch_composite(xa, s);
     mark(c, 5, s);
     if (c->stage_timing) c->ev_used += 6;
+}
+
+// Node-geometry part of the learned-LOD record (pointers into the scene).
+LodMlpDev mlp_geometry(hgs_ctx* c) {
+    LodMlpDev m{};
+    m.nodefeat = P<float4>(c->nodefeat);
+    m.parent = P<int32_t>(c->parent);
+    m.bound = P<float4>(c->bound);
+    m.geo = P<float4>(c->geo);
+    m.child = P<int2>(c->child);
+    m.level_offset = P<int64_t>(c->lvl);
+    m.n_levels = c->n_levels;
+    return m;
 }
 
 hgs_status grow_from(hgs_ctx* c, const Counters& k) {
@@ -447,7 +475,8 @@ void hgs_destroy(hgs_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    DevMem* all[] = {&c->geo, &c->sh, &c->bound, &c->child, &c->leaf_ids, &c->parent, &c->nodefeat, &c->views,
+    DevMem* all[] = {&c->geo, &c->sh, &c->bound, &c->child, &c->leaf_ids, &c->parent, &c->nodefeat, &c->lvl,
+                     &c->train_scratch, &c->region_dev, &c->views,
                      &c->tile_view, &c->mlp_w, &c->mlp_dev, &c->frontier[0], &c->frontier[1], &c->cut, &c->proj,
                      &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->rect, &c->offsets,
                      &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
@@ -492,9 +521,10 @@ hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarch
     for (int64_t i = 0; i < n; ++i)
         for (int k = 0; k < K * 3; ++k) sh[(size_t)k * n + i] = g->sh[(size_t)i * K * 3 + k];
     // new buffers first, so a failure leaves the old scene intact
-    DevMem ngeo, nsh, nbound, nchild, nleaf, nparent, nfeat;
+    DevMem ngeo, nsh, nbound, nchild, nleaf, nparent, nfeat, nlvl;
     auto cleanup = [&]() {
         release(ngeo); release(nsh); release(nbound); release(nchild); release(nleaf); release(nparent); release(nfeat);
+        release(nlvl);
     };
     if ((s = ensure(c, ngeo, geo.size() * sizeof(float4))) || (s = ensure(c, nsh, sh.size() * sizeof(float)))) {
         cleanup();
@@ -544,7 +574,8 @@ hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarch
         }
         if ((s = ensure(c, nbound, bound.size() * sizeof(float4))) || (s = ensure(c, nchild, child.size() * sizeof(int2))) ||
             (s = ensure(c, nleaf, leaves.size() * sizeof(int32_t))) || (s = ensure(c, nparent, (size_t)n * 4)) ||
-            (s = ensure(c, nfeat, feat.size() * sizeof(float4)))) {
+            (s = ensure(c, nfeat, feat.size() * sizeof(float4))) ||
+            (s = ensure(c, nlvl, sizeof(int64_t) * (size_t)(h->n_levels + 1)))) {
             cleanup();
             return s;
         }
@@ -553,6 +584,8 @@ hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarch
         if (e == hipSuccess) e = hipMemcpy(nleaf.p, leaves.data(), leaves.size() * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(nparent.p, h->parent, (size_t)n * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(nfeat.p, feat.data(), feat.size() * sizeof(float4), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(nlvl.p, h->level_offset, sizeof(int64_t) * (size_t)(h->n_levels + 1), hipMemcpyHostToDevice);
         lo.assign(h->level_offset, h->level_offset + h->n_levels + 1);
         n_leaves = (int64_t)leaves.size();
     }
@@ -561,9 +594,9 @@ hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarch
         return fail(c, HGS_E_HIP, "scene upload failed: %s", hipGetErrorString(e));
     }
     release(c->geo); release(c->sh); release(c->bound); release(c->child); release(c->leaf_ids);
-    release(c->parent); release(c->nodefeat);
+    release(c->parent); release(c->nodefeat); release(c->lvl);
     c->geo = ngeo; c->sh = nsh; c->bound = nbound; c->child = nchild; c->leaf_ids = nleaf;
-    c->parent = nparent; c->nodefeat = nfeat;
+    c->parent = nparent; c->nodefeat = nfeat; c->lvl = nlvl;
     c->hier = h != nullptr;
     c->n = n;
     c->sh_degree = g->sh_degree;
@@ -641,13 +674,16 @@ hgs_status hgs_set_cameras(hgs_ctx* c, int32_t n, const hgs_camera* cams) {
             volatile double f2 = cyh * cyh;
             d.nb = e + f2;
         }
-        d.limx = 1.3 * (0.5 * k.width / d.fx);
-        d.limy = 1.3 * (0.5 * k.height / d.fy);
+        d.xlo = (-d.cx - 0.15 * d.W) / d.fx;
+        d.xhi = (d.W - d.cx + 0.15 * d.W) / d.fx;
+        d.ylo = (-d.cy - 0.15 * d.H) / d.fy;
+        d.yhi = (d.H - d.cy + 0.15 * d.H) / d.fy;
         for (int i = 0; i < 3; ++i) d.bg[i] = k.bg[i];
         d.width = k.width; d.height = k.height;
         d.tiles_x = (k.width + kTile - 1) / kTile;
         d.tiles_y = (k.height + kTile - 1) / kTile;
         d.tile_base = tile_base[v];
+        d.keep_node = -1;
         d.rgb = d.depth = d.alpha = nullptr;
         c->views_host[v] = d;
         const uint32_t nt = (uint32_t)(d.tiles_x * d.tiles_y);
@@ -691,6 +727,10 @@ hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
         case HGS_OPT_USE_GRAPH: c->use_graph = val != 0; return HGS_OK;
         case HGS_OPT_PERSISTENT: c->ropts.persistent = val != 0; return HGS_OK;
         case HGS_OPT_EXACT_TILES: c->ropts.exact_tiles = val != 0; return HGS_OK;
+        case HGS_OPT_SORT_DIGIT_BITS:
+            if (val < 6 || val > 11) return fail(c, HGS_E_INVALID, "digit bits must be 6..11");
+            c->sort_digit_bits = (int)val;
+            return HGS_OK;
         case HGS_OPT_STAGE_TIMING: {
             hgs_status s = harvest_events(c);
             if (s) return s;
@@ -855,7 +895,7 @@ hgs_status hgs_sort_pairs(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* va
     hipStream_t s = (hipStream_t)stream;
     hgs_status st;
     if ((st = ensure(c, c->sort_k, (size_t)n * 4)) || (st = ensure(c, c->sort_v, (size_t)n * 4)) ||
-        (st = ensure(c, c->sort_n, 4)) || (st = ensure(c, c->hist, (256 * kSortBlocks + 256) * 4)))
+        (st = ensure(c, c->sort_n, 4)) || (st = ensure(c, c->hist, (size_t)kSortBins * (kSortBlocks + 1) * 4)))
         return st;
     const uint32_t nn = (uint32_t)n;
     HIP_TRY(c, hipMemcpyAsync(c->sort_n.p, &nn, 4, hipMemcpyHostToDevice, s));
@@ -867,6 +907,7 @@ hgs_status hgs_sort_pairs(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* va
     a.count = P<uint32_t>(c->sort_n);
     a.cap = nn;
     a.key_bits = key_bits;
+    a.max_digit_bits = c->sort_digit_bits;
     a.hist = P<uint32_t>(c->hist);
     const int r = launch_sort(a, s);
     if (r == 1) {
@@ -875,6 +916,196 @@ hgs_status hgs_sort_pairs(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* va
     }
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(s));
+    return HGS_OK;
+}
+
+hgs_status hgs_set_keep_nodes(hgs_ctx* c, int32_t n, const int32_t* nodes) {
+    if (!c) return HGS_E_INVALID;
+    if (n != (int32_t)c->cams.size() || !nodes) return fail(c, HGS_E_INVALID, "need one keep node per view");
+    for (int v = 0; v < n; ++v)
+        if (nodes[v] < -1 || nodes[v] >= c->n) return fail(c, HGS_E_INVALID, "keep node %d out of range", nodes[v]);
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipEventSynchronize(c->views_copied));
+    for (int v = 0; v < n; ++v) c->views_host[v].keep_node = nodes[v];
+    c->views_dirty = true;
+    return HGS_OK;
+}
+
+hgs_status hgs_lod_candidates(hgs_ctx* c, void* stream, float s_hi, uint32_t* entries, float* features, int32_t* rects,
+                              int64_t cap, int64_t* count) {
+    if (!c || !count) return HGS_E_INVALID;
+    if (!c->loaded || !c->hier) return fail(c, HGS_E_STATE, "candidates need a hierarchical scene");
+    if (c->cams.empty()) return fail(c, HGS_E_STATE, "no cameras set");
+    if (!(s_hi > 0.f)) return fail(c, HGS_E_INVALID, "s_hi must be positive");
+    if (cap < 0 || cap > 0xF0000000ll || (cap > 0 && (!entries || !features || !rects)))
+        return fail(c, HGS_E_INVALID, "bad candidate buffers");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    hgs_status st;
+    // the views' output pointers are not used by the cut; keep the mirror current
+    std::vector<hgs_output> none(c->cams.size());
+    for (size_t v = 0; v < none.size(); ++v) {
+        none[v].rgb = c->views_host[v].rgb;
+        none[v].depth = c->views_host[v].depth;
+        none[v].alpha = c->views_host[v].alpha;
+    }
+    if ((st = upload_views(c, s, none.data()))) return st;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        Counters* ctr = P<Counters>(c->counters);
+        k_reset<<<1, 64, 0, s>>>(ctr);
+        CutArgs ca{};
+        ca.bound = P<float4>(c->bound);
+        ca.child = P<int2>(c->child);
+        ca.leaf_ids = P<int32_t>(c->leaf_ids);
+        ca.n_leaves = c->n_leaves;
+        ca.n_nodes = c->n;
+        ca.level_offset_host = c->level_offset.data();
+        ca.n_levels = c->n_levels;
+        ca.mode = HGS_LOD_THRESHOLD;
+        ca.flat = false;
+        ca.views = P<ViewDev>(c->views);
+        ca.n_views = (int)c->cams.size();
+        ca.frontier[0] = P<uint2>(c->frontier[0]);
+        ca.frontier[1] = P<uint2>(c->frontier[1]);
+        ca.frontier_cap = c->frontier_cap;
+        ca.cut = P<uint2>(c->cut);
+        ca.cut_cap = c->cut_cap;
+        ca.scan_tmp = P<uint4>(c->scan_tmp);
+        ca.ctr = ctr;
+        ca.mlp = nullptr;
+        ca.s_hi = s_hi;
+        ca.cand = reinterpret_cast<uint2*>(entries);
+        ca.cand_cap = (uint32_t)cap;
+        launch_cut(ca, s);
+        if (cap > 0) {
+            LodMlpDev g = mlp_geometry(c);
+            launch_lod_features(ca.cand, &ctr->cand, ca.views, &g, features, reinterpret_cast<int4*>(rects), s);
+        }
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipMemcpyAsync(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        const Counters k = *c->ctr_host;
+        if (k.overflow & (kOvFrontier | kOvCut)) {
+            if ((st = grow_from(c, k))) return st;
+            continue;
+        }
+        *count = (k.overflow & kOvCand) ? (int64_t)k.need_cand : (int64_t)k.cand;
+        if (k.overflow & kOvCand) return fail(c, HGS_E_CAPACITY, "%lld candidates exceed the buffers", (long long)*count);
+        return HGS_OK;
+    }
+    return fail(c, HGS_E_CAPACITY, "work buffers kept overflowing");
+}
+
+hgs_status hgs_load_lod_mlp(hgs_ctx* c, const uint16_t* bf16, const float* mean, const float* stdv, float p_star,
+                            float s_hi) {
+    if (!c) return HGS_E_INVALID;
+    if (!c->loaded || !c->hier) return fail(c, HGS_E_STATE, "the learned cut needs a hierarchical scene");
+    if (!bf16 || !mean || !stdv) return fail(c, HGS_E_INVALID, "NULL network arrays");
+    if (!(p_star >= 0.f && p_star <= 1.f) || !(s_hi > 0.f)) return fail(c, HGS_E_INVALID, "bad p_star or s_hi");
+    for (int i = 0; i < kMlpIn; ++i)
+        if (!(stdv[i] > 0.f) || !finite(mean[i])) return fail(c, HGS_E_INVALID, "bad feature normalisation");
+    for (int i = 0; i < kMlpParams; ++i) {
+        const float w = bf16_to_f32_host(bf16[i]);
+        if (!finite(w)) return fail(c, HGS_E_INVALID, "non-finite weight %d", i);
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    hgs_status st;
+    if ((st = ensure(c, c->mlp_w, kMlpParams * sizeof(uint16_t))) || (st = ensure(c, c->mlp_dev, sizeof(LodMlpDev))))
+        return st;
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipMemcpy(c->mlp_w.p, bf16, kMlpParams * sizeof(uint16_t), hipMemcpyHostToDevice));
+    LodMlpDev m = mlp_geometry(c);
+    m.w = P<uint16_t>(c->mlp_w);
+    for (int i = 0; i < kMlpIn; ++i) {
+        m.mean[i] = mean[i];
+        m.inv_std[i] = 1.f / stdv[i];
+    }
+    m.p_star = p_star;
+    m.s_hi = s_hi;
+    HIP_TRY(c, hipMemcpy(c->mlp_dev.p, &m, sizeof(LodMlpDev), hipMemcpyHostToDevice));
+    c->mlp_host = m;
+    c->s_hi = s_hi;
+    c->mlp_loaded = true;
+    return HGS_OK;
+}
+
+hgs_status hgs_mlp_forward(hgs_ctx* c, void* stream, const float* feats, int64_t n, const uint16_t* w, const float* mean,
+                           const float* stdv, float* logits) {
+    if (!c) return HGS_E_INVALID;
+    if (n < 0 || n > 0x7fffffffll || (n > 0 && (!feats || !w || !logits)) || !mean || !stdv)
+        return fail(c, HGS_E_INVALID, "bad arguments");
+    for (int i = 0; i < kMlpIn; ++i)
+        if (!(stdv[i] > 0.f)) return fail(c, HGS_E_INVALID, "bad feature normalisation");
+    if (n == 0) return HGS_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    launch_mlp_forward(feats, (uint32_t)n, mean, stdv, w, logits, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_mlp_train_step(hgs_ctx* c, void* stream, const float* feats, const float* labels, int64_t n,
+                              const float* mean, const float* stdv, float* master, uint16_t* w, float* adam_m,
+                              float* adam_v, int32_t step, float lr, float* grad_out, float* loss_out) {
+    if (!c) return HGS_E_INVALID;
+    if (n <= 0 || n > (1ll << 24) || !feats || !labels || !mean || !stdv || !w)
+        return fail(c, HGS_E_INVALID, "bad arguments");
+    if (lr > 0.f && (!master || !adam_m || !adam_v || step < 1)) return fail(c, HGS_E_INVALID, "Adam needs state and step >= 1");
+    if (lr < 0.f || !finite(lr)) return fail(c, HGS_E_INVALID, "lr must be >= 0");
+    for (int i = 0; i < kMlpIn; ++i)
+        if (!(stdv[i] > 0.f)) return fail(c, HGS_E_INVALID, "bad feature normalisation");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hgs_status st;
+    if ((st = ensure(c, c->train_scratch, mlp_train_scratch_floats((uint32_t)n) * sizeof(float)))) return st;
+    launch_mlp_train_step(feats, labels, (uint32_t)n, mean, stdv, master, w, adam_m, adam_v, step, lr, grad_out,
+                          loss_out, P<float>(c->train_scratch), (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_mlp_bf16_from_master(hgs_ctx* c, void* stream, const float* master, uint16_t* w) {
+    if (!c || !master || !w) return HGS_E_INVALID;
+    HIP_TRY(c, hipSetDevice(c->device));
+    launch_bf16_from_master(master, w, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_feature_stats(hgs_ctx* c, void* stream, const float* feats, int64_t n, float* mean_std) {
+    if (!c || !mean_std || n < 0 || n > 0x7fffffffll || (n > 0 && !feats)) return HGS_E_INVALID;
+    HIP_TRY(c, hipSetDevice(c->device));
+    launch_feat_stats(feats, (uint32_t)n, mean_std, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_downsample2x(hgs_ctx* c, void* stream, const float* src, int32_t width, int32_t height, float* dst) {
+    if (!c || !src || !dst || width < 1 || height < 1 || width > 8192 || height > 8192)
+        return fail(c, HGS_E_INVALID, "bad downsample arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    launch_downsample2x(src, width, height, dst, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_region_mse(hgs_ctx* c, void* stream, int32_t n, const hgs_region* regions, float* out) {
+    if (!c || n < 0 || (n > 0 && (!regions || !out))) return HGS_E_INVALID;
+    if (n == 0) return HGS_OK;
+    std::vector<RegionDev> r(n);
+    for (int i = 0; i < n; ++i) {
+        const hgs_region& q = regions[i];
+        if (!q.img || !q.ref || q.w < 1 || q.h < 1 || q.x0 < 0 || q.y0 < 0 || q.x0 + q.w > q.ref_w ||
+            q.y0 + q.h > q.ref_h)
+            return fail(c, HGS_E_INVALID, "region %d is outside its reference", i);
+        r[i] = RegionDev{q.img, q.ref, q.w, q.h, q.ref_w, q.ref_h, q.x0, q.y0};
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    hgs_status st;
+    HIP_TRY(c, hipStreamSynchronize(s));   // the descriptor buffer is reused
+    if ((st = ensure(c, c->region_dev, sizeof(RegionDev) * (size_t)n))) return st;
+    HIP_TRY(c, hipMemcpy(c->region_dev.p, r.data(), sizeof(RegionDev) * (size_t)n, hipMemcpyHostToDevice));
+    launch_region_mse(P<RegionDev>(c->region_dev), n, out, s);
+    HIP_TRY(c, hipGetLastError());
     return HGS_OK;
 }
 

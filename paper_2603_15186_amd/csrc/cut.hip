@@ -26,43 +26,38 @@ namespace {
 
 constexpr int kNT = 256;
 
-enum : uint32_t { kDrop = 0, kEmit = 1, kExpand = 2 };
+enum : uint32_t { kDrop = 0, kEmit = 1, kExpand = 2, kCandidate = 4 };
 
 // Decide a node for a view: dropped (sphere outside the frustum), emitted,
-// or expanded into its children.
+// or expanded into its children.  kCandidate is or-ed into kExpand when the
+// threshold rule refines the node and its projected size is at most s_hi
+// pixels: the band in which the learned rule may keep the node instead.
 __device__ __noinline__ uint32_t node_decision(const ViewDev& V, int k, float4 b, int nchild, int mode,
-                                               const void* mlp, int level) {
+                                               const void* mlp, double s_hi, int level) {
 #pragma clang fp contract(off)
-    const double dx = (double)b.x - V.o[0];
-    const double dy = (double)b.y - V.o[1];
-    const double dz = (double)b.z - V.o[2];
-    const double r = (double)b.w;
-    const double px = (V.R[0] * dx + V.R[1] * dy) + V.R[2] * dz;
-    const double py = (V.R[3] * dx + V.R[4] * dy) + V.R[5] * dz;
-    const double pz = (V.R[6] * dx + V.R[7] * dy) + V.R[8] * dz;
-    if (pz + r < V.znear) return kDrop;
-    const double rr = r * r;
-    const double eL = V.fx * px + V.cx * pz;
+    NodeGeom g;
+    node_geometry(V, b, &g);
+    if (g.pz + g.r < V.znear) return kDrop;
+    const double rr = g.r * g.r;
+    const double eL = V.fx * g.px + V.cx * g.pz;
     if (eL < 0.0 && eL * eL > rr * V.nl) return kDrop;
-    const double eR = V.fx * px + (V.cx - V.W) * pz;
+    const double eR = V.fx * g.px + (V.cx - V.W) * g.pz;
     if (eR > 0.0 && eR * eR > rr * V.nr) return kDrop;
-    const double eT = V.fy * py + V.cy * pz;
+    const double eT = V.fy * g.py + V.cy * g.pz;
     if (eT < 0.0 && eT * eT > rr * V.nt) return kDrop;
-    const double eB = V.fy * py + (V.cy - V.H) * pz;
+    const double eB = V.fy * g.py + (V.cy - V.H) * g.pz;
     if (eB > 0.0 && eB * eB > rr * V.nb) return kDrop;
     if (nchild == 0) return kEmit;
-    const double a = V.f2 * r;
+    const double a = V.f2 * g.r;
     const double lhs = a * a;
-    const double d2 = (dx * dx + dy * dy) + dz * dz;
-    const double rhs = V.tau2 * d2;
-    const bool expand = lhs > rhs;
-    if (!expand) return kEmit;
-    if (mode == HGS_LOD_LEARNED && mlp != nullptr) {
-        // learned refinement: may keep a node the threshold would expand
-        const double dist = sqrt(d2);
-        if (!lod_mlp_expand(mlp, V, k, b, dist, pz, level)) return kEmit;
+    const double rhs = V.tau2 * g.d2;
+    if (!(lhs > rhs)) return kEmit;
+    if (k == V.keep_node) return kEmit;
+    const bool cand = lhs <= (s_hi * s_hi) * g.d2;
+    if (cand && mode == HGS_LOD_LEARNED && mlp != nullptr) {
+        if (!lod_mlp_expand(*(const LodMlpDev*)mlp, V, k, b, g, level)) return kEmit;
     }
-    return kExpand;
+    return kExpand | (cand ? kCandidate : 0u);
 }
 
 struct LevelCtx {
@@ -75,10 +70,13 @@ struct LevelCtx {
     uint32_t out_cap;
     uint2* cut;
     uint32_t cut_cap;
-    uint2* tmp;               // [G] block counts, then offsets; [G] = level base
+    uint4* tmp;               // [G] block counts, then offsets; [G] = level bases
     Counters* ctr;
     int mode;
     const void* mlp;
+    double s_hi;
+    uint2* cand;
+    uint32_t cand_cap;
     int level;
     int out_slot;             // index of the next frontier's counter
 };
@@ -92,41 +90,54 @@ __device__ __forceinline__ void chunk_of(uint32_t n, int G, int b, uint32_t* lo,
     *hi = (uint32_t)(e < n ? e : n);
 }
 
-__device__ __forceinline__ uint2 eval_entry(const LevelCtx& c, uint2 e) {
+// (emitted, children, candidate) counts of one frontier entry
+__device__ __forceinline__ uint4 eval_entry(const LevelCtx& c, uint2 e) {
     const float4 b = c.bound[e.x];
     const int2 ch = c.child[e.x];
-    const uint32_t d = node_decision(c.views[e.y], (int)e.x, b, ch.y, c.mode, c.mlp, c.level);
-    return make_uint2(d == kEmit ? 1u : 0u, d == kExpand ? (uint32_t)ch.y : 0u);
+    const uint32_t d = node_decision(c.views[e.y], (int)e.x, b, ch.y, c.mode, c.mlp, c.s_hi, c.level);
+    const uint32_t kind = d & 3u;
+    return make_uint4(kind == kEmit ? 1u : 0u, kind == kExpand ? (uint32_t)ch.y : 0u,
+                      (c.cand != nullptr && (d & kCandidate)) ? 1u : 0u, 0u);
 }
 
 __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap) {
-    __shared__ uint2 sh[kNT / kWave + 1];
+    __shared__ uint4 sh[kNT / kWave + 1];
     uint32_t n = *c.in_count;
     n = n < in_cap ? n : in_cap;
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
-    uint2 acc = make_uint2(0, 0);
+    uint4 acc = make_uint4(0, 0, 0, 0);
     for (uint32_t i = lo + threadIdx.x; i < hi; i += kNT) {
-        const uint2 r = eval_entry(c, c.in[i]);
+        const uint4 r = eval_entry(c, c.in[i]);
         acc.x += r.x;
         acc.y += r.y;
+        acc.z += r.z;
     }
-    uint2 tot;
-    block_excl_scan2<kNT>(acc, sh, &tot);
+    uint4 tot;
+    block_excl_scan4<kNT>(acc, sh, &tot);
     if (threadIdx.x == 0) c.tmp[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G) {
-    __shared__ uint2 sh[1024 / kWave + 1];
+    __shared__ uint4 sh[1024 / kWave + 1];
     const int t = threadIdx.x;
-    const uint2 x = t < G ? c.tmp[t] : make_uint2(0, 0);
-    uint2 tot;
-    const uint2 ex = block_excl_scan2<1024>(x, sh, &tot);
+    const uint4 x = t < G ? c.tmp[t] : make_uint4(0, 0, 0, 0);
+    uint4 tot;
+    const uint4 ex = block_excl_scan4<1024>(x, sh, &tot);
     if (t < G) c.tmp[t] = ex;
     if (t == 0) {
         Counters* k = c.ctr;
         const uint32_t base = k->cut;
-        c.tmp[G] = make_uint2(base, 0);
+        const uint32_t cbase = k->cand;
+        c.tmp[G] = make_uint4(base, 0, cbase, 0);
+        if (c.cand != nullptr) {
+            const uint64_t want = (uint64_t)cbase + tot.z;
+            if (want > c.cand_cap) {
+                k->overflow |= kOvCand;
+                if (want > k->need_cand) k->need_cand = (uint32_t)(want < 0xffffffffull ? want : 0xffffffffull);
+            }
+            k->cand = (uint32_t)(want < c.cand_cap ? want : c.cand_cap);
+        }
         const uint64_t want_cut = (uint64_t)base + tot.x;
         if (want_cut > c.cut_cap) {
             k->overflow |= kOvCut;
@@ -142,27 +153,32 @@ __global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G) {
 }
 
 __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap) {
-    __shared__ uint2 sh[kNT / kWave + 1];
+    __shared__ uint4 sh[kNT / kWave + 1];
     uint32_t n = *c.in_count;
     n = n < in_cap ? n : in_cap;
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
     if (lo >= hi) return;
-    uint2 off = c.tmp[blockIdx.x];
+    uint4 off = c.tmp[blockIdx.x];
     const uint32_t base = c.tmp[gridDim.x].x;
+    const uint32_t cbase = c.tmp[gridDim.x].z;
     for (uint32_t s = lo; s < hi; s += kNT) {
         const uint32_t i = s + threadIdx.x;
-        uint2 r = make_uint2(0, 0);
+        uint4 r = make_uint4(0, 0, 0, 0);
         uint2 e = make_uint2(0, 0);
         if (i < hi) {
             e = c.in[i];
             r = eval_entry(c, e);
         }
-        uint2 tot;
-        const uint2 ex = block_excl_scan2<kNT>(r, sh, &tot);
+        uint4 tot;
+        const uint4 ex = block_excl_scan4<kNT>(r, sh, &tot);
         if (r.x) {
             const uint64_t pos = (uint64_t)base + off.x + ex.x;
             if (pos < c.cut_cap) c.cut[pos] = e;
+        }
+        if (r.z) {
+            const uint64_t pos = (uint64_t)cbase + off.z + ex.z;
+            if (pos < c.cand_cap) c.cand[pos] = e;
         }
         if (r.y) {
             const int first = c.child[e.x].x;
@@ -173,6 +189,7 @@ __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap)
         }
         off.x += tot.x;
         off.y += tot.y;
+        off.z += tot.z;
     }
 }
 
@@ -207,7 +224,39 @@ __global__ void k_emit_all(uint2* cut, const int32_t* ids, uint32_t n, uint32_t 
     }
 }
 
+// Features and screen footprint of each collected candidate.  The level of
+// a node is recovered from the geometry record (mlp_geom.level_offset).
+__global__ void k_lod_features(const uint2* cand, const uint32_t* count, const ViewDev* views, LodMlpDev m,
+                               float* feats, int4* rects) {
+    const uint32_t n = *count;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint2 e = cand[i];
+        const ViewDev& V = views[e.y];
+        const float4 b = m.bound[e.x];
+        NodeGeom g;
+        node_geometry(V, b, &g);
+        int level = 0;
+        while (level + 1 < m.n_levels && (int64_t)e.x >= m.level_offset[level + 1]) ++level;
+        float f[kMlpIn];
+        lod_features(m, V, (int)e.x, b, g, level, f);
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k) feats[(size_t)i * kMlpIn + k] = f[k];
+        // footprint: projection of the bounding sphere (centre +- f r / z)
+        const double z = fmax(g.pz, V.znear);
+        const double u = V.fx * g.px / z + V.cx, v = V.fy * g.py / z + V.cy;
+        const double ru = V.fx * g.r / z + 1.0, rv = V.fy * g.r / z + 1.0;
+        const int x0 = (int)fmax(floor(u - ru), 0.0), x1 = (int)fmin(ceil(u + ru), V.W - 1.0);
+        const int y0 = (int)fmax(floor(v - rv), 0.0), y1 = (int)fmin(ceil(v + rv), V.H - 1.0);
+        rects[i] = make_int4(x0, y0, x1, y1);
+    }
+}
+
 }  // namespace
+
+void launch_lod_features(const uint2* cand, const uint32_t* count, const ViewDev* views, const void* mlp_geom,
+                         float* feats, int4* rects, hipStream_t s) {
+    k_lod_features<<<1024, 256, 0, s>>>(cand, count, views, *(const LodMlpDev*)mlp_geom, feats, rects);
+}
 
 void launch_cut(const CutArgs& a, hipStream_t s) {
     const int G = kScanBlocks;
@@ -235,6 +284,9 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.ctr = a.ctr;
         c.mode = a.mode;
         c.mlp = a.mlp;
+        c.s_hi = a.s_hi;
+        c.cand = a.cand;
+        c.cand_cap = a.cand_cap;
         c.level = L;
         c.out_slot = cur ^ 1;
         k_level_count<<<G, kNT, 0, s>>>(c, a.frontier_cap);

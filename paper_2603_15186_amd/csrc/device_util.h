@@ -88,6 +88,36 @@ __device__ __forceinline__ uint2 block_excl_scan2(uint2 x, uint2* sh, uint2* tot
     return r;
 }
 
+template <int NT>
+__device__ __forceinline__ uint4 block_excl_scan4(uint4 x, uint4* sh, uint4* total) {
+    constexpr int NW = NT / kWave;
+    const int w = threadIdx.x / kWave, l = lane_id();
+    uint4 inc = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t a = __shfl_up(inc.x, d, kWave), b = __shfl_up(inc.y, d, kWave);
+        const uint32_t c = __shfl_up(inc.z, d, kWave), e = __shfl_up(inc.w, d, kWave);
+        if (l >= d) { inc.x += a; inc.y += b; inc.z += c; inc.w += e; }
+    }
+    if (l == kWave - 1) sh[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint4 run = make_uint4(0, 0, 0, 0);
+        for (int i = 0; i < NW; ++i) {
+            const uint4 t = sh[i];
+            sh[i] = run;
+            run.x += t.x; run.y += t.y; run.z += t.z; run.w += t.w;
+        }
+        sh[NW] = run;
+    }
+    __syncthreads();
+    const uint4 r = make_uint4(sh[w].x + inc.x - x.x, sh[w].y + inc.y - x.y, sh[w].z + inc.z - x.z,
+                               sh[w].w + inc.w - x.w);
+    *total = sh[NW];
+    __syncthreads();
+    return r;
+}
+
 // Lanes of the wave (among `active`) whose 8-bit digit equals this lane's.
 __device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t active) {
     uint64_t m = active;

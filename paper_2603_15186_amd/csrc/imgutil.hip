@@ -1,0 +1,56 @@
+// Image helpers for learned-LOD labels and PSNR: 2x2 box downsampling of a
+// planar RGB image, and mean squared error of many image windows against
+// crops of reference images.  FP64 sums in a fixed order.
+#include "device_util.h"
+#include "internal.h"
+
+namespace hgs {
+
+namespace {
+
+__global__ void k_downsample2x(const float* __restrict__ src, int W, int H, float* __restrict__ dst) {
+    const size_t plane = (size_t)W * H, splane = 4 * plane;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < 3 * plane; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = i / plane, r = i % plane;
+        const int y = (int)(r / W), x = (int)(r % W);
+        const float* s = src + c * splane + (size_t)(2 * y) * (2 * W) + 2 * x;
+        dst[i] = 0.25f * ((s[0] + s[1]) + (s[2 * W] + s[2 * W + 1]));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_region_mse(const RegionDev* __restrict__ reg, float* __restrict__ out) {
+    __shared__ double sh[256];
+    const RegionDev r = reg[blockIdx.x];
+    const size_t np = (size_t)r.w * r.h;
+    const size_t rplane = (size_t)r.ref_w * r.ref_h;
+    double acc = 0.0;
+    for (size_t i = threadIdx.x; i < 3 * np; i += 256) {
+        const size_t c = i / np, k = i % np;
+        const int y = (int)(k / r.w), x = (int)(k % r.w);
+        const float a = r.img[i];
+        const float b = r.ref[c * rplane + (size_t)(r.y0 + y) * r.ref_w + (r.x0 + x)];
+        const double d = (double)a - (double)b;
+        acc += d * d;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = np ? (float)(sh[0] / (3.0 * np)) : 0.f;
+}
+
+}  // namespace
+
+void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s) {
+    const size_t n = 3 * (size_t)W * H;
+    const int grid = (int)std::min<size_t>(4096, (n + 255) / 256);
+    k_downsample2x<<<grid > 0 ? grid : 1, 256, 0, s>>>(src, W, H, dst);
+}
+
+void launch_region_mse(const RegionDev* reg, int n, float* out, hipStream_t s) {
+    if (n > 0) k_region_mse<<<n, 256, 0, s>>>(reg, out);
+}
+
+}  // namespace hgs

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -20,6 +21,7 @@ constexpr int kMaxViews = 4096;
 constexpr uint32_t kOvFrontier = 1u;
 constexpr uint32_t kOvCut = 2u;
 constexpr uint32_t kOvPairs = 4u;
+constexpr uint32_t kOvCand = 8u;
 
 // Per-view parameters, resident in device memory.  FP64 copies of the
 // extrinsics and intrinsics feed the cut and the projection; the compositor
@@ -30,10 +32,11 @@ struct ViewDev {
     double fx, fy, cx, cy, W, H, znear;
     double f2, tau2;                 // cut: 2 max(fx, fy) and tau^2
     double nl, nr, nt, nb;           // squared lengths of the side-plane normals
-    double limx, limy;               // Jacobian clamp on x/z and y/z
+    double xlo, xhi, ylo, yhi;       // Jacobian clamp range of x/z and y/z
     float bg[3];
     int32_t width, height, tiles_x, tiles_y;
     uint32_t tile_base;              // first global tile id of this view
+    int32_t keep_node;               // >= 0: never refine this node (label renders)
     float* rgb;
     float* depth;
     float* alpha;
@@ -61,6 +64,8 @@ struct Counters {
     uint32_t need_pairs;             // pairs requested
     uint32_t visible;                // cut entries with at least one tile
     uint32_t tile_queue;             // persistent compositor work counter
+    uint32_t cand;                   // learned-LOD candidates collected
+    uint32_t need_cand;
     unsigned long long nalg;         // evaluated (pixel, Gaussian) pairs
 };
 
@@ -77,6 +82,7 @@ struct RenderOpts {
 // Scan scratch needs (uint2 / uint32 elements).
 constexpr int kScanBlocks = 1024;
 constexpr int kSortBlocks = 1024;
+constexpr int kSortBins = 2048;          // widest radix digit: 11 bits
 
 // Threshold / all-leaves / flat cut for all views.  Writes (node, view)
 // entries to `cut` and the count to ctr->cut.
@@ -96,12 +102,22 @@ struct CutArgs {
     uint32_t frontier_cap;
     uint2* cut;
     uint32_t cut_cap;
-    uint2* scan_tmp;                 // kScanBlocks + 1 entries
+    uint4* scan_tmp;                 // kScanBlocks + 1 entries
     Counters* ctr;
-    // learned refinement (nullptr = off)
+    // learned refinement (nullptr = off); candidate band for it and for
+    // candidate collection: refined by the threshold and s <= s_hi pixels
     const void* mlp;
+    double s_hi;
+    uint2* cand;                     // nullptr: do not collect candidates
+    uint32_t cand_cap;
 };
 void launch_cut(const CutArgs& a, hipStream_t s);
+
+// Raw learned-LOD features (8 floats) and screen footprint (x0, y0, x1, y1
+// pixel bounds of the node's bounding-sphere projection, clipped) of
+// candidate (node, view) entries.
+void launch_lod_features(const uint2* cand, const uint32_t* count, const ViewDev* views, const void* mlp_geom,
+                         float* feats, int4* rects, hipStream_t s);
 
 struct ProjectArgs {
     const uint2* cut;
@@ -136,7 +152,7 @@ struct EmitArgs {
     uint32_t* vals;
     uint32_t pair_cap;
     bool exact_tiles;
-    uint2* scan_tmp;
+    uint4* scan_tmp;
     Counters* ctr;
 };
 void launch_emit(const EmitArgs& a, hipStream_t s);
@@ -150,7 +166,8 @@ struct SortArgs {
     const uint32_t* count;
     uint32_t cap;
     int key_bits;
-    uint32_t* hist;                  // 256 * kSortBlocks + 256
+    int max_digit_bits = 11;         // 6..11
+    uint32_t* hist;                  // kSortBins * (kSortBlocks + 1)
 };
 int launch_sort(const SortArgs& a, hipStream_t s);
 
@@ -172,5 +189,24 @@ void launch_ranges(const CompositeArgs& a, hipStream_t s);
 void launch_composite(const CompositeArgs& a, hipStream_t s);
 
 void launch_reset_counters(Counters* c, hipStream_t s);
+
+// learned-LOD network (mlp.hip)
+void launch_mlp_forward(const float* feats, uint32_t n, const float* mean, const float* stdv, const uint16_t* w,
+                        float* logits, hipStream_t s);
+size_t mlp_train_scratch_floats(uint32_t n);
+void launch_mlp_train_step(const float* feats, const float* labels, uint32_t n, const float* mean, const float* stdv,
+                           float* master, uint16_t* w, float* m, float* v, int step, float lr, float* grad_out,
+                           float* loss_out, float* scratch, hipStream_t s);
+void launch_bf16_from_master(const float* master, uint16_t* w, hipStream_t s);
+void launch_feat_stats(const float* f, uint32_t n, float* out, hipStream_t s);
+
+// image helpers (imgutil.hip)
+struct RegionDev {
+    const float* img;                // planar [3][h][w]
+    const float* ref;                // planar [3][ref_h][ref_w]
+    int32_t w, h, ref_w, ref_h, x0, y0;
+};
+void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
+void launch_region_mse(const RegionDev* reg, int n, float* out, hipStream_t s);
 
 }  // namespace hgs

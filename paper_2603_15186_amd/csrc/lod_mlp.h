@@ -29,7 +29,30 @@ struct LodMlpDev {
     const float4* bound;
     const float4* geo;            // geo[3k].w = opacity
     const int2* child;
+    const int64_t* level_offset;  // device copy, n_levels + 1 entries
+    int n_levels;
 };
+
+// Geometry of a node's bounding sphere seen from a view, FP64 in a fixed
+// order without contraction (the cut's decisions depend on it exactly).
+struct NodeGeom {
+    double dx, dy, dz;            // c - o
+    double px, py, pz;            // camera-space centre
+    double r;                     // radius
+    double d2;                    // |c - o|^2
+};
+
+__device__ __forceinline__ void node_geometry(const ViewDev& V, float4 b, NodeGeom* g) {
+#pragma clang fp contract(off)
+    g->dx = (double)b.x - V.o[0];
+    g->dy = (double)b.y - V.o[1];
+    g->dz = (double)b.z - V.o[2];
+    g->r = (double)b.w;
+    g->px = (V.R[0] * g->dx + V.R[1] * g->dy) + V.R[2] * g->dz;
+    g->py = (V.R[3] * g->dx + V.R[4] * g->dy) + V.R[5] * g->dz;
+    g->pz = (V.R[6] * g->dx + V.R[7] * g->dy) + V.R[8] * g->dz;
+    g->d2 = (g->dx * g->dx + g->dy * g->dy) + g->dz * g->dz;
+}
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
@@ -37,26 +60,25 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 // log projected size, log depth, opacity, child count, child colour
 // variance, |cos| between the view ray and the node's thinnest axis, level,
 // log projected size of the parent.
-__device__ __forceinline__ void lod_features(const LodMlpDev& m, const ViewDev& V, int k, float4 b, double dist,
-                                             double pz, int level, float f[kMlpIn]) {
-    const double fmax = 0.5 * V.f2;
-    const double size = 2.0 * fmax * (double)b.w / (dist > 1e-9 ? dist : 1e-9);
+__device__ __forceinline__ void lod_features(const LodMlpDev& m, const ViewDev& V, int k, float4 b,
+                                             const NodeGeom& g, int level, float f[kMlpIn]) {
+    const double dist = sqrt(g.d2);
+    const double inv = 1.0 / (dist > 1e-9 ? dist : 1e-9);
+    const double size = V.f2 * g.r * inv;
     f[0] = (float)log(size > 1e-6 ? size : 1e-6);
-    f[1] = (float)log(pz > V.znear ? pz : V.znear);
+    f[1] = (float)log(g.pz > V.znear ? g.pz : V.znear);
     f[2] = m.geo[3 * (int64_t)k].w;
     f[3] = (float)m.child[k].y;
     const float4 nf = m.nodefeat[k];
     f[4] = nf.w;
-    const double rx = (double)b.x - V.o[0], ry = (double)b.y - V.o[1], rz = (double)b.z - V.o[2];
-    const double c = (rx * nf.x + ry * nf.y + rz * nf.z) / (dist > 1e-9 ? dist : 1e-9);
-    f[5] = (float)fabs(c);
+    f[5] = (float)fabs((g.dx * nf.x + g.dy * nf.y + g.dz * nf.z) * inv);
     f[6] = (float)level;
     const int p = m.parent[k];
     if (p >= 0) {
         const float4 pb = m.bound[p];
         const double qx = (double)pb.x - V.o[0], qy = (double)pb.y - V.o[1], qz = (double)pb.z - V.o[2];
         const double pd = sqrt(qx * qx + qy * qy + qz * qz);
-        const double ps = 2.0 * fmax * (double)pb.w / (pd > 1e-9 ? pd : 1e-9);
+        const double ps = V.f2 * (double)pb.w / (pd > 1e-9 ? pd : 1e-9);
         f[7] = (float)log(ps > 1e-6 ? ps : 1e-6);
     } else {
         f[7] = f[0];
@@ -84,16 +106,13 @@ __device__ __forceinline__ float lod_mlp_logit(const uint16_t* __restrict__ w, c
     return out;
 }
 
-// Called for a node the threshold rule would refine.  Returns whether the
-// learned cut refines it: candidates (projected size <= s_hi) are refined iff
-// the network's probability reaches p_star; other nodes follow the rule.
-__device__ __forceinline__ bool lod_mlp_expand(const void* mp, const ViewDev& V, int k, float4 b, double dist,
-                                               double pz, int level) {
-    const LodMlpDev& m = *(const LodMlpDev*)mp;
-    const double size = V.f2 * (double)b.w / (dist > 1e-9 ? dist : 1e-9);
-    if (size > (double)m.s_hi) return true;
+// For a candidate node (the threshold rule refines it and its projected
+// size is at most s_hi): does the learned cut refine it?  Yes iff the
+// network's probability reaches p_star.
+__device__ __forceinline__ bool lod_mlp_expand(const LodMlpDev& m, const ViewDev& V, int k, float4 b,
+                                               const NodeGeom& g, int level) {
     float f[kMlpIn];
-    lod_features(m, V, k, b, dist, pz, level, f);
+    lod_features(m, V, k, b, g, level, f);
 #pragma unroll
     for (int i = 0; i < kMlpIn; ++i) f[i] = (f[i] - m.mean[i]) * m.inv_std[i];
     const float z = lod_mlp_logit(m.w, f);

@@ -3,8 +3,8 @@
 //
 // Per cut entry (node, view): Sigma = R S S^T R^T (Supplementary Material of
 // NavGSim), camera-space mean t = W (mu - o), first-order perspective
-// Jacobian J at the mean (x/z and y/z clamped to 1.3x the half field of
-// view), Sigma' = J W Sigma W^T J^T + 0.3 I, 2D mean (fx tx/tz + cx,
+// Jacobian J at the mean (x/z and y/z clamped to the image's range widened
+// by 15 % of its size per side), Sigma' = J W Sigma W^T J^T + 0.3 I, 2D mean (fx tx/tz + cx,
 // fy ty/tz + cy), colour clamp(sum_k f_k Y_k(d) + 0.5, 0, 1).
 //
 // The geometry runs in FP64 (the pass is bound by HBM traffic; FP64 keeps
@@ -75,33 +75,6 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t 
     for (int c = 0; c < 3; ++c) rgb[c] = fminf(fmaxf(acc[c], 0.f), 1.f);
 }
 
-// Does the ellipse q(d) <= qmax (q = A dx^2 + 2 B dx dy + C dy^2, d relative
-// to the mean) reach the rectangle [x0, x1] x [y0, y1]?  Exact minimum of the
-// quadratic over the rectangle: inside, or on one of the four edges.
-__device__ __forceinline__ bool ellipse_hits_rect(double A, double B, double C, double x0, double x1, double y0,
-                                                  double y1, double qmax) {
-    if (x0 <= 0.0 && 0.0 <= x1 && y0 <= 0.0 && 0.0 <= y1) return true;
-    double best = 1e300;
-    const double xs[2] = {x0, x1}, ys[2] = {y0, y1};
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const double X = xs[i];
-        double y = -B * X / C;
-        y = y < y0 ? y0 : (y > y1 ? y1 : y);
-        const double q = A * X * X + 2.0 * B * X * y + C * y * y;
-        best = q < best ? q : best;
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const double Y = ys[i];
-        double x = -B * Y / A;
-        x = x < x0 ? x0 : (x > x1 ? x1 : x);
-        const double q = A * x * x + 2.0 * B * x * Y + C * Y * Y;
-        best = q < best ? q : best;
-    }
-    return best <= qmax;
-}
-
 // Conic of a projected entry, rebuilt from its stored single-precision
 // factors (the same inputs in the counting and the emitting pass).
 __device__ __forceinline__ void conic_of(const Proj& p, double* A, double* B, double* C) {
@@ -111,23 +84,66 @@ __device__ __forceinline__ void conic_of(const Proj& p, double* A, double* B, do
     *C = rr * rr + ss * ss;
 }
 
+// Tiles of one tile row that the ellipse q(d) <= Q reaches.  The ellipse
+// meets the row's band of pixel-centre heights [yb0, yb1] (relative to the
+// mean) in a convex set whose x-extent [xa, xb] is found in closed form: for
+// a height dy the ellipse spans dx = (-B dy +- sqrt(A Q - det dy^2)) / A, a
+// concave right end and convex left end whose extremes over the band sit at
+// the clamped heights of the ellipse's rightmost and leftmost points.  A
+// tile is reached iff its pixel-centre x-range overlaps [xa, xb]; the
+// result is an interval of tiles (empty: lo > hi).
+struct RowSpan {
+    double A, B, C, det, Q, ey, ymax_at_x;   // ymax_at_x: height of the rightmost point
+};
+
+__device__ __forceinline__ RowSpan row_span_init(const Proj& p) {
+    RowSpan r;
+    conic_of(p, &r.A, &r.B, &r.C);
+    r.det = r.A * r.C - r.B * r.B;
+    r.Q = 9.0 * (1.0 + kBinSlack);
+    // covariance = inverse conic: Sxx = C/det, Syy = A/det, Sxy = -B/det
+    r.ey = sqrt(r.Q * r.A / r.det);
+    const double sxx = r.C / r.det, sxy = -r.B / r.det;
+    r.ymax_at_x = sxy * sqrt(r.Q / sxx);
+    return r;
+}
+
+__device__ __forceinline__ void row_tiles(const RowSpan& r, double u, double v, int ty, int W, int H, int tx_lo,
+                                          int tx_hi, int* lo, int* hi) {
+    double y0 = ty * kTile + 0.5 - v;
+    double y1 = fmin((double)(ty * kTile + kTile - 1), (double)(H - 1)) + 0.5 - v;
+    y0 = fmax(y0, -r.ey);
+    y1 = fmin(y1, r.ey);
+    if (y0 > y1) {
+        *lo = 1;
+        *hi = 0;
+        return;
+    }
+    const double yr = fmin(fmax(r.ymax_at_x, y0), y1);
+    const double yl = fmin(fmax(-r.ymax_at_x, y0), y1);
+    const double sr = fmax(r.A * r.Q - r.det * yr * yr, 0.0);
+    const double sl = fmax(r.A * r.Q - r.det * yl * yl, 0.0);
+    const double xb = (-r.B * yr + sqrt(sr)) / r.A + 1e-7;
+    const double xa = (-r.B * yl - sqrt(sl)) / r.A - 1e-7;
+    // tile tx covers pixel centres [16 tx + 0.5, 16 tx + 15.5]
+    const int a = (int)ceil((u + xa - (kTile - 0.5)) / kTile);
+    const int b = (int)floor((u + xb - 0.5) / kTile);
+    *lo = a > tx_lo ? a : tx_lo;
+    *hi = b < tx_hi ? b : tx_hi;
+    (void)W;
+}
+
 // Number of tiles of rect `rc` that the ellipse reaches (all of them when
 // exact is false).
 __device__ __forceinline__ uint32_t count_tiles(const Proj& p, ushort4 rc, int W, int H, bool exact) {
     const uint32_t all = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
     if (!exact || all <= 1) return all;
-    double A, B, C;
-    conic_of(p, &A, &B, &C);
-    const double qmax = 9.0 * (1.0 + kBinSlack);
+    const RowSpan r = row_span_init(p);
     uint32_t n = 0;
     for (int ty = rc.y; ty <= rc.w; ++ty) {
-        const double y0 = ty * kTile + 0.5 - p.v;
-        const double y1 = fmin((double)(ty * kTile + kTile - 1), (double)(H - 1)) + 0.5 - p.v;
-        for (int tx = rc.x; tx <= rc.z; ++tx) {
-            const double x0 = tx * kTile + 0.5 - p.u;
-            const double x1 = fmin((double)(tx * kTile + kTile - 1), (double)(W - 1)) + 0.5 - p.u;
-            n += ellipse_hits_rect(A, B, C, x0, x1, y0, y1, qmax) ? 1u : 0u;
-        }
+        int lo, hi;
+        row_tiles(r, p.u, p.v, ty, W, H, rc.x, rc.z, &lo, &hi);
+        n += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
     }
     return n;
 }
@@ -164,8 +180,8 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
                                   2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
             const double iz = 1.0 / tz;
             double xr = tx * iz, yr = ty * iz;
-            xr = fmin(fmax(xr, -V.limx), V.limx);
-            yr = fmin(fmax(yr, -V.limy), V.limy);
+            xr = fmin(fmax(xr, V.xlo), V.xhi);
+            yr = fmin(fmax(yr, V.ylo), V.yhi);
             // M = J W (2x3)
             double M0[3], M1[3];
 #pragma unroll
@@ -240,7 +256,7 @@ struct ScanCtx {
     const uint32_t* count;
     uint32_t cap;
     uint32_t* offsets;
-    uint2* tmp;
+    uint4* tmp;
     Counters* ctr;
     uint32_t pair_cap;
 };
@@ -266,7 +282,7 @@ __global__ __launch_bounds__(kNT) void k_scan_reduce(ScanCtx c) {
     }
     uint32_t tot;
     block_excl_scan<kNT>(acc, sh, &tot);
-    if (threadIdx.x == 0) c.tmp[blockIdx.x] = make_uint2(tot, 0);
+    if (threadIdx.x == 0) c.tmp[blockIdx.x] = make_uint4(tot, 0, 0, 0);
 }
 
 __global__ __launch_bounds__(1024) void k_scan_blocks(ScanCtx c, int G) {
@@ -334,22 +350,17 @@ __global__ __launch_bounds__(kNT) void k_emit(EmitArgs a) {
             continue;
         }
         const Proj p = a.proj[e];
-        double A, B, C;
-        conic_of(p, &A, &B, &C);
-        const double qmax = 9.0 * (1.0 + kBinSlack);
+        const RowSpan r = row_span_init(p);
         for (int ty = rc.y; ty <= rc.w; ++ty) {
-            const double y0 = ty * kTile + 0.5 - p.v;
-            const double y1 = fmin((double)(ty * kTile + kTile - 1), (double)(V.height - 1)) + 0.5 - p.v;
-            for (int tx = rc.x; tx <= rc.z; ++tx) {
-                const double x0 = tx * kTile + 0.5 - p.u;
-                const double x1 = fmin((double)(tx * kTile + kTile - 1), (double)(V.width - 1)) + 0.5 - p.u;
-                if (ellipse_hits_rect(A, B, C, x0, x1, y0, y1, qmax)) {
-                    if (pos < cap) {
-                        a.keys[pos] = tb + (uint32_t)(ty * tw + tx);
-                        a.vals[pos] = e;
-                    }
-                    ++pos;
+            int lo, hi;
+            row_tiles(r, p.u, p.v, ty, V.width, V.height, rc.x, rc.z, &lo, &hi);
+            const uint32_t row = tb + (uint32_t)(ty * tw);
+            for (int tx = lo; tx <= hi; ++tx) {
+                if (pos < cap) {
+                    a.keys[pos] = row + (uint32_t)tx;
+                    a.vals[pos] = e;
                 }
+                ++pos;
             }
         }
     }

@@ -1,9 +1,14 @@
-// Stable LSD radix sort of 32-bit (key, value) pairs with 8-bit digits, for
-// wave64.  Each pass is three launches with no inter-workgroup waiting:
+// Stable LSD radix sort of 32-bit (key, value) pairs for wave64.
+//
+// A sort over `bits` key bits runs ceil(bits / 11) passes with digits of
+// ceil(bits / passes) bits (at most 11: 2048 buckets), so a 17-bit tile key
+// takes two passes and a 32-bit depth key three.  Each pass is three
+// launches with no inter-workgroup waiting:
 //   upsweep   : each block histograms the digits of its contiguous chunk;
 //   row scan  : one block per digit scans that digit's per-block counts;
-//   downsweep : each block ranks its chunk stably (ballot digit matching per
-//               wave, per-wave counters in LDS) and scatters.
+//   downsweep : each block ranks its chunk stably -- lanes with equal digits
+//               are found by ballots over the digit bits, per-wave counters
+//               live in LDS -- and scatters keys and values.
 // Element counts live in device memory so the launches can be captured in a
 // graph; a block whose chunk is empty exits after writing zeros.
 #include "device_util.h"
@@ -14,8 +19,8 @@ namespace hgs {
 namespace {
 
 constexpr int kNT = 256;
-constexpr int kItems = 8;
-constexpr int kSub = kNT * kItems;        // elements per sub-tile
+constexpr int kNW = kNT / kWave;
+constexpr int kSub = kNT * 16;            // chunk granularity: the largest sub-tile
 constexpr int kMinChunk = 4096;
 
 __device__ __forceinline__ void chunk_of(uint32_t n, uint32_t cap, int G, int b, uint32_t* lo, uint32_t* hi) {
@@ -30,24 +35,39 @@ __device__ __forceinline__ void chunk_of(uint32_t n, uint32_t cap, int G, int b,
     *hi = (uint32_t)e;
 }
 
+// Lanes of the wave (among `active`) whose DB-bit digit equals this lane's.
+template <int DB>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
+    uint64_t m = active;
+#pragma unroll
+    for (int b = 0; b < DB; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        m &= bit ? bal : ~bal;
+    }
+    return m;
+}
+
+template <int DB>
 __global__ __launch_bounds__(kNT) void k_upsweep(const uint32_t* __restrict__ keys, const uint32_t* count,
-                                                 uint32_t cap, int shift, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[256];
+                                                 uint32_t cap, int shift, uint32_t MASK, uint32_t* __restrict__ hist) {
+    constexpr int NB = 1 << DB;
+    __shared__ uint32_t h[NB];
     const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
-    h[t] = 0;
+    for (int i = t; i < NB; i += kNT) h[i] = 0;
     __syncthreads();
     uint32_t lo, hi;
     chunk_of(*count, cap, G, b, &lo, &hi);
     for (uint32_t base = lo; base < hi; base += kNT) {
         const uint32_t i = base + t;
         const bool valid = i < hi;
-        const uint32_t d = valid ? (keys[i] >> shift) & 255u : 0u;
+        const uint32_t d = valid ? (keys[i] >> shift) & MASK : 0u;
         const uint64_t act = __ballot(valid);
-        const uint64_t peers = match_digit8(d, act);
+        const uint64_t peers = match_digit<DB>(d, act);
         if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
-    hist[t * G + b] = h[t];   // digit-major
+    for (int i = t; i < NB; i += kNT) hist[(size_t)i * G + b] = h[i];   // digit-major
 }
 
 // One block per digit: exclusive scan of hist[d][0..G) in place; the digit
@@ -68,40 +88,69 @@ __global__ __launch_bounds__(1024) void k_rowscan(uint32_t* __restrict__ hist, i
     if (t == 0) totals[d] = run;
 }
 
+// Downsweep with a local reorder: each sub-tile of kItems * kNT elements is
+// ranked (stable within the sub-tile), placed in LDS in digit order, then
+// written out in that order so that consecutive lanes store consecutive
+// addresses of one digit's run.
+template <int DB, int ITEMS>
 __global__ __launch_bounds__(kNT) void k_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                   const uint32_t* count, uint32_t cap, int shift,
+                                                   const uint32_t* count, uint32_t cap, int shift, uint32_t MASK,
                                                    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals) {
-    __shared__ uint32_t s_off[256];
-    __shared__ uint32_t s_cnt[kNT / kWave][256];
-    __shared__ uint32_t s_scan[kNT / kWave + 1];
+    constexpr int NB = 1 << DB;
+    constexpr int PER = NB / kNT > 0 ? NB / kNT : 1;      // digits per thread
+    constexpr int SUB = kNT * ITEMS;
+    __shared__ uint32_t s_off[NB];                       // global position of the next element of digit d
+    __shared__ uint32_t s_loc[NB];                       // start of digit d inside the staged sub-tile
+    __shared__ uint32_t s_cnt[kNW][NB];
+    __shared__ uint32_t s_scan[kNW + 1];
+    __shared__ uint32_t s_key[SUB];
+    __shared__ uint32_t s_val[SUB];
     const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
     const int w = t / kWave, l = lane_id();
     uint32_t lo, hi;
     chunk_of(*count, cap, G, b, &lo, &hi);
     if (lo >= hi) return;
-    // digit base = exclusive scan of the digit totals, plus this block's
-    // exclusive offset within the digit's row
     {
+        uint32_t mine[PER];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int d = t * PER + k;
+            mine[k] = d < NB ? totals[d] : 0u;
+            sum += mine[k];
+        }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan<kNT>(totals[t], s_scan, &tot);
-        s_off[t] = ex + hist[t * G + b];
+        uint32_t ex = block_excl_scan<kNT>(sum, s_scan, &tot);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int d = t * PER + k;
+            if (d < NB) s_off[d] = ex + hist[(size_t)d * G + b];
+            ex += mine[k];
+        }
     }
-    for (uint32_t base = lo; base < hi; base += kSub) {
+    for (uint32_t base = lo; base < hi; base += SUB) {
+        for (int i = t; i < NB; i += kNT) {
 #pragma unroll
-        for (int k = 0; k < kNT / kWave; ++k) s_cnt[k][t] = 0;
+            for (int k = 0; k < kNW; ++k) s_cnt[k][i] = 0;
+        }
         __syncthreads();
-        uint32_t key[kItems], val[kItems], rank[kItems];
-        const uint32_t seg = base + (uint32_t)w * (kWave * kItems);
+        uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+        const uint32_t seg = base + (uint32_t)w * (kWave * ITEMS);
 #pragma unroll
-        for (int r = 0; r < kItems; ++r) {
+        for (int r = 0; r < ITEMS; ++r) {
             const uint32_t i = seg + r * kWave + l;
             const bool valid = i < hi;
             key[r] = valid ? kin[i] : 0u;
             val[r] = valid ? vin[i] : 0u;
-            const uint32_t d = (key[r] >> shift) & 255u;
+        }
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const uint32_t i = seg + r * kWave + l;
+            const bool valid = i < hi;
+            const uint32_t d = (key[r] >> shift) & MASK;
             const uint64_t act = __ballot(valid);
-            const uint64_t peers = match_digit8(d, act);
+            const uint64_t peers = match_digit<DB>(d, act);
             const uint64_t below = peers & lanemask_lt();
             uint32_t before = 0;
             if (valid) before = s_cnt[w][d];
@@ -109,46 +158,102 @@ __global__ __launch_bounds__(kNT) void k_downsweep(const uint32_t* __restrict__ 
             if (valid && below == 0) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
         }
         __syncthreads();
+        // per digit: local start of each wave's run inside the sub-tile
         {
-            // per digit t: bases of each wave's run, then advance the digit
-            uint32_t run = s_off[t];
+            uint32_t mine[PER];
+            uint32_t sum = 0;
 #pragma unroll
-            for (int k = 0; k < kNT / kWave; ++k) {
-                const uint32_t c = s_cnt[k][t];
-                s_cnt[k][t] = run;
-                run += c;
+            for (int k = 0; k < PER; ++k) {
+                const int d = t * PER + k;
+                uint32_t c = 0;
+                if (d < NB) {
+#pragma unroll
+                    for (int q = 0; q < kNW; ++q) c += s_cnt[q][d];
+                }
+                mine[k] = c;
+                sum += c;
             }
-            s_off[t] = run;
+            uint32_t tot;
+            uint32_t ex = block_excl_scan<kNT>(sum, s_scan, &tot);
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int d = t * PER + k;
+                if (d < NB) {
+                    s_loc[d] = ex;
+                    uint32_t run = ex;
+#pragma unroll
+                    for (int q = 0; q < kNW; ++q) {
+                        const uint32_t c = s_cnt[q][d];
+                        s_cnt[q][d] = run;
+                        run += c;
+                    }
+                }
+                ex += mine[k];
+            }
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kItems; ++r) {
+        for (int r = 0; r < ITEMS; ++r) {
             const uint32_t i = seg + r * kWave + l;
             if (i < hi) {
-                const uint32_t d = (key[r] >> shift) & 255u;
-                const uint32_t pos = s_cnt[w][d] + rank[r];
-                kout[pos] = key[r];
-                vout[pos] = val[r];
+                const uint32_t d = (key[r] >> shift) & MASK;
+                const uint32_t p = s_cnt[w][d] + rank[r];
+                s_key[p] = key[r];
+                s_val[p] = val[r];
             }
+        }
+        __syncthreads();
+        const uint32_t n_sub = (hi - base) < (uint32_t)SUB ? (hi - base) : (uint32_t)SUB;
+        for (uint32_t p = t; p < n_sub; p += kNT) {
+            const uint32_t k = s_key[p];
+            const uint32_t d = (k >> shift) & MASK;
+            const uint32_t pos = s_off[d] + (p - s_loc[d]);
+            kout[pos] = k;
+            vout[pos] = s_val[p];
+        }
+        __syncthreads();
+        // advance each digit's global position by its count in this sub-tile
+        for (int d = t; d < NB; d += kNT) {
+            const uint32_t next = (d + 1 < NB) ? s_loc[d + 1] : n_sub;
+            s_off[d] += next - s_loc[d];
         }
         __syncthreads();
     }
 }
 
+// One pass over digit bits [shift, shift + nbits) (nbits <= DB).
+template <int DB>
+void pass(const SortArgs& a, int cur, int shift, int nbits, hipStream_t s) {
+    const int G = kSortBlocks;
+    uint32_t* hist = a.hist;
+    uint32_t* totals = a.hist + (size_t)kSortBins * G;
+    const uint32_t mask = nbits >= 32 ? 0xffffffffu : ((1u << nbits) - 1u);
+    k_upsweep<DB><<<G, kNT, 0, s>>>(a.keys[cur], a.count, a.cap, shift, mask, hist);
+    k_rowscan<<<1 << DB, 1024, 0, s>>>(hist, G, totals);
+    constexpr int ITEMS = DB <= 8 ? 16 : 8;
+    k_downsweep<DB, ITEMS><<<G, kNT, 0, s>>>(a.keys[cur], a.vals[cur], a.keys[cur ^ 1], a.vals[cur ^ 1], a.count,
+                                             a.cap, shift, mask, hist, totals);
+}
+
 }  // namespace
 
 int launch_sort(const SortArgs& a, hipStream_t s) {
-    const int passes = (a.key_bits + 7) / 8;
-    const int G = kSortBlocks;
-    uint32_t* hist = a.hist;
-    uint32_t* totals = a.hist + 256 * G;
-    int cur = 0;
+    const int maxdb = a.max_digit_bits < 6 ? 6 : (a.max_digit_bits > 11 ? 11 : a.max_digit_bits);
+    const int passes = (a.key_bits + maxdb - 1) / maxdb;
+    const int db = (a.key_bits + passes - 1) / passes;
+    int cur = 0, shift = 0;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        k_upsweep<<<G, kNT, 0, s>>>(a.keys[cur], a.count, a.cap, shift, hist);
-        k_rowscan<<<256, 1024, 0, s>>>(hist, G, totals);
-        k_downsweep<<<G, kNT, 0, s>>>(a.keys[cur], a.vals[cur], a.keys[cur ^ 1], a.vals[cur ^ 1], a.count, a.cap,
-                                      shift, hist, totals);
+        // the last pass may cover fewer bits: its mask drops key bits above key_bits
+        const int nbits = a.key_bits - shift < db ? a.key_bits - shift : db;
+        switch (db) {
+            case 1: case 2: case 3: case 4: case 5: case 6: pass<6>(a, cur, shift, nbits, s); break;
+            case 7: pass<7>(a, cur, shift, nbits, s); break;
+            case 8: pass<8>(a, cur, shift, nbits, s); break;
+            case 9: pass<9>(a, cur, shift, nbits, s); break;
+            case 10: pass<10>(a, cur, shift, nbits, s); break;
+            default: pass<11>(a, cur, shift, nbits, s); break;
+        }
+        shift += db;
         cur ^= 1;
     }
     return cur;

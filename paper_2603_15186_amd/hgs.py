@@ -36,6 +36,7 @@ HGS_OPT_PERSISTENT = 6
 HGS_OPT_EXACT_TILES = 7
 HGS_OPT_INITIAL_CAPACITY = 8
 HGS_OPT_STAGE_TIMING = 9
+HGS_OPT_SORT_DIGIT_BITS = 10
 
 PROJECTED_FIELDS = ("u", "v", "A", "B", "C", "r", "g", "b", "depth", "opacity", "ntiles", "valid")
 
@@ -63,6 +64,11 @@ class hgs_output(ctypes.Structure):
     _fields_ = [("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("alpha", ctypes.c_void_p)]
 
 
+class hgs_region(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("ref", ctypes.c_void_p), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
+                ("ref_w", ctypes.c_int32), ("ref_h", ctypes.c_int32), ("x0", ctypes.c_int32), ("y0", ctypes.c_int32)]
+
+
 class hgs_stats(ctypes.Structure):
     _fields_ = [("cut_size", ctypes.c_int64), ("visible", ctypes.c_int64), ("pairs", ctypes.c_int64),
                 ("n_alg", ctypes.c_int64), ("tiles", ctypes.c_int64), ("regrows", ctypes.c_int64),
@@ -88,7 +94,20 @@ EXPORTS = [
     ("hgs_get_projected", ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     ("hgs_get_stats", ctypes.c_int32, [_P, ctypes.POINTER(hgs_stats)]),
     ("hgs_sort_pairs", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32]),
+    ("hgs_set_keep_nodes", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    ("hgs_lod_candidates", ctypes.c_int32, [_P, _P, ctypes.c_float, _P, _P, _P, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_int64)]),
+    ("hgs_load_lod_mlp", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_float, ctypes.c_float]),
+    ("hgs_mlp_forward", ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, _P, _P, _P, _P]),
+    ("hgs_mlp_train_step", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
+                                            ctypes.c_int32, ctypes.c_float, _P, _P]),
+    ("hgs_mlp_bf16_from_master", ctypes.c_int32, [_P, _P, _P, _P]),
+    ("hgs_feature_stats", ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, _P]),
+    ("hgs_downsample2x", ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
+    ("hgs_region_mse", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.POINTER(hgs_region), _P]),
 ]
+
+N_MLP_PARAMS = 1377
 
 _lib = None
 
@@ -267,6 +286,81 @@ class Renderer:
         s = hgs_stats()
         self._check(self.lib.hgs_get_stats(self.ctx, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in hgs_stats._fields_}
+
+    # ------------------------------------------------------------ learned LOD
+    def _stream(self, stream):
+        import torch
+        return ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
+
+    def set_keep_nodes(self, nodes):
+        a = _np(nodes, np.int32)
+        self._check(self.lib.hgs_set_keep_nodes(self.ctx, a.size, _ptr(a)))
+
+    def lod_candidates(self, s_hi, cap=1 << 20, stream=None):
+        """(entries int32[n,2] (node, view), features f32[n,8], rects int32[n,4]) as
+        device tensors for the current cameras (threshold cut)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        while True:
+            ent = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+            feat = torch.empty((cap, 8), dtype=torch.float32, device=dev)
+            rect = torch.empty((cap, 4), dtype=torch.int32, device=dev)
+            n = ctypes.c_int64()
+            st = self.lib.hgs_lod_candidates(self.ctx, self._stream(stream), float(s_hi), ent.data_ptr(),
+                                             feat.data_ptr(), rect.data_ptr(), cap, ctypes.byref(n))
+            if st == HGS_E_CAPACITY and n.value > cap:
+                cap = int(n.value * 1.1) + 1024
+                continue
+            self._check(st)
+            return ent[:n.value], feat[:n.value], rect[:n.value]
+
+    def load_lod_mlp(self, bf16_params, mean, std, p_star, s_hi):
+        w = _np(bf16_params, np.uint16); m = _np(mean, np.float32); sd = _np(std, np.float32)
+        assert w.size == N_MLP_PARAMS and m.size == 8 and sd.size == 8
+        self._check(self.lib.hgs_load_lod_mlp(self.ctx, _ptr(w), _ptr(m), _ptr(sd), float(p_star), float(s_hi)))
+
+    def mlp_forward(self, feats, w, mean, std, stream=None):
+        import torch
+        out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+        m = _np(mean, np.float32); sd = _np(std, np.float32)
+        self._check(self.lib.hgs_mlp_forward(self.ctx, self._stream(stream), feats.data_ptr(), feats.shape[0],
+                                             w.data_ptr(), _ptr(m), _ptr(sd), out.data_ptr()))
+        return out
+
+    def mlp_train_step(self, feats, labels, mean, std, master, w, m, v, step, lr, grad_out=None, loss_out=None,
+                       stream=None):
+        mm = _np(mean, np.float32); sd = _np(std, np.float32)
+        ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        self._check(self.lib.hgs_mlp_train_step(self.ctx, self._stream(stream), feats.data_ptr(), labels.data_ptr(),
+                                                feats.shape[0], _ptr(mm), _ptr(sd), ptr(master), w.data_ptr(),
+                                                ptr(m), ptr(v), int(step), float(lr), ptr(grad_out), ptr(loss_out)))
+
+    def mlp_bf16_from_master(self, master, w, stream=None):
+        self._check(self.lib.hgs_mlp_bf16_from_master(self.ctx, self._stream(stream), master.data_ptr(), w.data_ptr()))
+
+    def feature_stats(self, feats, stream=None):
+        import torch
+        out = torch.empty(16, dtype=torch.float32, device=feats.device)
+        self._check(self.lib.hgs_feature_stats(self.ctx, self._stream(stream), feats.data_ptr(), feats.shape[0],
+                                               out.data_ptr()))
+        return out
+
+    def downsample2x(self, src, stream=None):
+        import torch
+        _, H2, W2 = src.shape
+        dst = torch.empty((3, H2 // 2, W2 // 2), dtype=torch.float32, device=src.device)
+        self._check(self.lib.hgs_downsample2x(self.ctx, self._stream(stream), src.data_ptr(), W2 // 2, H2 // 2,
+                                              dst.data_ptr()))
+        return dst
+
+    def region_mse(self, regions, out, stream=None):
+        """regions: list of (img tensor [3,h,w], ref tensor [3,H,W], x0, y0)."""
+        arr = (hgs_region * len(regions))()
+        for i, (img, ref, x0, y0) in enumerate(regions):
+            arr[i] = hgs_region(img.data_ptr(), ref.data_ptr(), img.shape[2], img.shape[1], ref.shape[2],
+                                ref.shape[1], int(x0), int(y0))
+        self._check(self.lib.hgs_region_mse(self.ctx, self._stream(stream), len(regions), arr, out.data_ptr()))
+        return out
 
     def sort_pairs(self, keys, vals, key_bits, stream=None):
         """Sort device uint32 tensors (as int32 storage) in place."""

@@ -1,0 +1,266 @@
+"""Learned level-of-detail refinement: labels, training, calibration and
+evaluation, orchestrated in Python over the library's kernels.
+
+NavGSim renders its Gaussian tree with level-of-detail selection (Sec.
+III-B).  The threshold cut refines a node while its projected size exceeds
+tau.  The learned cut adds a network that, for candidate nodes (refined by
+the threshold rule, projected size <= s_hi), predicts whether refining them
+matters for the image; the threshold rule stays in force everywhere else and
+is the fallback when the network is absent or fails its calibration.
+
+Quality is PSNR against an anti-aliased full-leaf reference: the full-leaf
+render at twice the resolution on each axis, box-filtered 2x2.  (At tau = 1
+pixel every visible leaf is selected on these scenes, so the threshold render
+itself would be a lossless reference.)  The PSNR loss of a cut is the mean
+per-view PSNR of the tau = 1 threshold cut minus that of the cut.
+
+Labels: for a candidate n seen from a training pose, the footprint window is
+the clipped screen box of n's bounding sphere; the window is rendered with
+the tau = 1 cut and with n's subtree collapsed to n; the label is "refine"
+when collapsing loses more than 0.05 dB of window PSNR.
+
+Every render, feature extraction, PSNR reduction and network pass runs in
+libhgs kernels; this module selects samples, moves tensors and loops.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import os
+
+import numpy as np
+
+from . import hgs
+from .synth import Camera, mlp_init
+
+S_HI = 64.0           # candidate band: projected size <= S_HI pixels
+LABEL_DB = 0.05       # window PSNR drop that makes refining necessary
+TARGET_TRAIN_DB = 0.08
+MAX_VIEWS = 4096
+
+
+@dataclasses.dataclass
+class LodModel:
+    master: np.ndarray            # FP32 weights (1377)
+    bf16: np.ndarray              # BF16 bit patterns (1377)
+    mean: np.ndarray              # feature means (8)
+    std: np.ndarray               # feature deviations (8)
+    p_star: float
+    s_hi: float
+    info: dict = dataclasses.field(default_factory=dict)
+
+    def save(self, path):
+        np.savez(path, master=self.master, bf16=self.bf16, mean=self.mean, std=self.std,
+                 p_star=np.float64(self.p_star), s_hi=np.float64(self.s_hi),
+                 info_keys=np.array(list(self.info.keys()), dtype=str),
+                 info_vals=np.array([float(v) for v in self.info.values()], dtype=np.float64))
+
+    @staticmethod
+    def load(path) -> "LodModel":
+        z = np.load(path, allow_pickle=False)
+        info = dict(zip([str(k) for k in z["info_keys"]], [float(v) for v in z["info_vals"]]))
+        return LodModel(z["master"], z["bf16"], z["mean"], z["std"], float(z["p_star"]), float(z["s_hi"]), info)
+
+    def install(self, r: hgs.Renderer, p_star=None):
+        r.load_lod_mlp(self.bf16, self.mean, self.std, self.p_star if p_star is None else p_star, self.s_hi)
+
+
+# ------------------------------------------------------------------ cameras
+
+def scaled_camera(c: Camera, k: int) -> Camera:
+    return Camera(c.width * k, c.height * k, c.fx * k, c.fy * k, c.cx * k, c.cy * k, c.position, c.R, c.znear, c.bg)
+
+
+def window_camera(c: Camera, x0, y0, x1, y1) -> Camera:
+    """The pixels [x0, x1] x [y0, y1] of camera c as a camera of their own."""
+    return Camera(int(x1 - x0 + 1), int(y1 - y0 + 1), c.fx, c.fy, c.cx - float(x0), c.cy - float(y0),
+                  c.position, c.R, c.znear, c.bg)
+
+
+# ------------------------------------------------------------------ renders
+
+def render_rgb(r: hgs.Renderer, cams, mode, tau, keep=None):
+    """Render cams (one batched call) and return their rgb tensors (views of
+    one flat buffer)."""
+    import torch
+    r.set_cameras(cams)
+    r.set_lod(mode, tau)
+    if keep is not None:
+        r.set_keep_nodes(keep)
+    sizes = [3 * c.width * c.height for c in cams]
+    flat = torch.empty(sum(sizes), dtype=torch.float32, device=torch.device("cuda", r.device))
+    outs, o = [], 0
+    for c, n in zip(cams, sizes):
+        outs.append((flat[o:o + n].view(3, c.height, c.width), None, None))
+        o += n
+    r.render(outs)
+    return [t[0] for t in outs]
+
+
+def reference_images(r: hgs.Renderer, cams, chunk=8):
+    """Anti-aliased full-leaf references: every visible leaf at 2x
+    resolution, 2x2 box-filtered."""
+    refs = []
+    for i in range(0, len(cams), chunk):
+        big = render_rgb(r, [scaled_camera(c, 2) for c in cams[i:i + chunk]], hgs.HGS_LOD_THRESHOLD, 1e-3)
+        refs += [r.downsample2x(b) for b in big]
+    return refs
+
+
+def psnr(r: hgs.Renderer, imgs, refs):
+    """Per-image PSNR (dB) of imgs against equally sized refs."""
+    import torch
+    out = torch.empty(len(imgs), dtype=torch.float32, device=imgs[0].device)
+    r.region_mse([(a, b, 0, 0) for a, b in zip(imgs, refs)], out)
+    mse = np.maximum(out.cpu().numpy().astype(np.float64), 1e-10)
+    return 10.0 * np.log10(1.0 / mse)
+
+
+# ------------------------------------------------------------------ labels
+
+def make_labels(r: hgs.Renderer, cams, per_view=256, seed=0, chunk=8, s_hi=S_HI, log=None):
+    """Candidate features (device [N, 8]) and labels (device [N]) over cams."""
+    import torch
+    rng = np.random.default_rng(seed)
+    feats, labels, stats = [], [], {"candidates": 0, "sampled": 0, "refine": 0}
+    for i in range(0, len(cams), chunk):
+        poses = cams[i:i + chunk]
+        r.set_cameras(poses)
+        r.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
+        ent, feat, rect = r.lod_candidates(s_hi)
+        stats["candidates"] += int(ent.shape[0])
+        if ent.shape[0] == 0:
+            continue
+        e = ent.cpu().numpy()
+        rc = rect.cpu().numpy()
+        sel = []
+        for v in range(len(poses)):
+            idx = np.nonzero(e[:, 1] == v)[0]
+            if idx.size > per_view:
+                idx = np.sort(rng.choice(idx, per_view, replace=False))
+            sel.append(idx)
+        sel = np.concatenate(sel)
+        refs = reference_images(r, poses)
+        win, keep, regs = [], [], []
+        for k in sel:
+            node, v = int(e[k, 0]), int(e[k, 1])
+            x0, y0, x1, y1 = (int(t) for t in rc[k])
+            wc = window_camera(poses[v], x0, y0, x1, y1)
+            win += [wc, wc]
+            keep += [-1, node]
+            regs.append((v, x0, y0))
+        mse = np.empty(len(win))
+        for j in range(0, len(win), MAX_VIEWS):
+            imgs = render_rgb(r, win[j:j + MAX_VIEWS], hgs.HGS_LOD_THRESHOLD, 1.0, keep[j:j + MAX_VIEWS])
+            out = torch.empty(len(imgs), dtype=torch.float32, device=imgs[0].device)
+            items = []
+            for q, img in enumerate(imgs):
+                v, x0, y0 = regs[(j + q) // 2]
+                items.append((img, refs[v], x0, y0))
+            r.region_mse(items, out)
+            mse[j:j + len(imgs)] = out.cpu().numpy()
+        mse = np.maximum(mse, 1e-10)
+        drop = 10.0 * np.log10(mse[1::2] / mse[0::2])
+        lab = (drop > LABEL_DB).astype(np.float32)
+        feats.append(feat[torch.from_numpy(sel).to(feat.device)])
+        labels.append(torch.from_numpy(lab).to(feat.device))
+        stats["sampled"] += int(sel.size)
+        stats["refine"] += int(lab.sum())
+        if log:
+            log(f"labels: poses {i + len(poses)}/{len(cams)}, samples {stats['sampled']}, refine {stats['refine']}")
+    return torch.cat(feats), torch.cat(labels), stats
+
+
+# ------------------------------------------------------------------ training
+
+def train(r: hgs.Renderer, feats, labels, epochs=40, batch=4096, lr=3e-3, seed=0, log=None):
+    """Adam on the FP32 masters with the library's train-step kernels.
+    Returns (master, bf16 bits, mean, std, per-epoch mean loss)."""
+    import torch
+    dev = feats.device
+    ms = r.feature_stats(feats).cpu().numpy()
+    mean, std = ms[:8].copy(), ms[8:].copy()
+    master = torch.from_numpy(mlp_init(seed).astype(np.float32)).to(dev)
+    w = torch.empty(hgs.N_MLP_PARAMS, dtype=torch.int16, device=dev)
+    r.mlp_bf16_from_master(master, w)
+    m = torch.zeros_like(master)
+    v = torch.zeros_like(master)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(seed + 1)
+    n = feats.shape[0]
+    step, hist = 0, []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).to(dev)
+        tot, cnt = 0.0, 0
+        for b in range(0, n, batch):
+            idx = perm[b:b + batch]
+            if idx.numel() < 2:
+                continue
+            step += 1
+            r.mlp_train_step(feats[idx].contiguous(), labels[idx].contiguous(), mean, std, master, w, m, v, step, lr,
+                             loss_out=loss)
+            tot += float(loss.item()) * idx.numel()
+            cnt += idx.numel()
+        hist.append(tot / max(cnt, 1))
+        if log and (ep % 10 == 0 or ep == epochs - 1):
+            log(f"epoch {ep}: loss {hist[-1]:.4f}")
+    return master.cpu().numpy(), w.cpu().numpy().view(np.uint16), mean, std, hist
+
+
+def cut_size(r: hgs.Renderer):
+    return r.stats()["cut_size"]
+
+
+def evaluate(r: hgs.Renderer, cams, refs, model: LodModel | None = None, p_star=None, tau=1.0, chunk=16):
+    """Mean PSNR (dB) and total cut size of the threshold cut at tau, or of
+    the learned cut when a model is given."""
+    ps, cuts = [], 0
+    for i in range(0, len(cams), chunk):
+        part = cams[i:i + chunk]
+        if model is not None:
+            model.install(r, p_star)
+            imgs = render_rgb(r, part, hgs.HGS_LOD_LEARNED, 1.0)
+        else:
+            imgs = render_rgb(r, part, hgs.HGS_LOD_THRESHOLD, tau)
+        cuts += cut_size(r)
+        ps.append(psnr(r, imgs, refs[i:i + chunk]))
+    ps = np.concatenate(ps)
+    return float(ps.mean()), cuts, ps
+
+
+def calibrate(r: hgs.Renderer, model: LodModel, cams, refs, base_psnr, target=TARGET_TRAIN_DB,
+              grid=(0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.1, 0.05)):
+    """Largest p_star whose PSNR loss on cams is within target; 0 (always
+    refine: the threshold cut) when none is."""
+    for p in grid:
+        mp, _, _ = evaluate(r, cams, refs, model, p_star=p)
+        if base_psnr - mp <= target:
+            return p, base_psnr - mp
+    return 0.0, 0.0
+
+
+def train_pipeline(r: hgs.Renderer, train_cams, calib_n=64, per_view=256, epochs=40, seed=0, log=None) -> LodModel:
+    """Labels on train_cams, training, calibration of p_star on a subset of
+    the training poses."""
+    feats, labels, st = make_labels(r, train_cams, per_view=per_view, seed=seed, log=log)
+    master, bf16, mean, std, hist = train(r, feats, labels, epochs=epochs, seed=seed, log=log)
+    model = LodModel(master, bf16, mean, std, 0.5, S_HI,
+                     {"samples": st["sampled"], "refine_frac": st["refine"] / max(1, st["sampled"]),
+                      "final_loss": hist[-1] if hist else float("nan"), "epochs": epochs})
+    step = max(1, len(train_cams) // calib_n)
+    ccams = train_cams[::step][:calib_n]
+    crefs = reference_images(r, ccams)
+    base, _, _ = evaluate(r, ccams, crefs, None, tau=1.0)
+    p, loss = calibrate(r, model, ccams, crefs, base)
+    model.p_star = p
+    model.info.update({"calib_loss_db": loss, "calib_views": len(ccams)})
+    if log:
+        log(f"calibrated p* = {p} (training-pose loss {loss:.3f} dB)")
+    return model
+
+
+MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
+
+
+def default_model_path(name="plan2m_lod_mlp.npz"):
+    return os.path.join(MODEL_DIR, name)

@@ -63,7 +63,7 @@ class FreeSpace:
     """Occupancy of one floor on a 5 cm grid, with a clearance margin."""
 
     def __init__(self, plan: FloorPlan, floor: int = 0, cell: float = 0.05,
-                 clearance: float = 0.4):
+                 clearance: float = 0.3):
         from scipy import ndimage
         W, H = plan.extent
         self.cell = cell
@@ -77,7 +77,7 @@ class FreeSpace:
             d = q - p; L = np.linalg.norm(d); u = d / L
             t = (X - p[0]) * u[0] + (Y - p[1]) * u[1]
             dist = np.abs((X - p[0]) * u[1] - (Y - p[1]) * u[0])
-            on = (dist < 0.06) & (t > -0.06) & (t < L + 0.06)
+            on = (dist < 0.03) & (t > -0.03) & (t < L + 0.03)
             if door is not None:
                 on &= ~((t > door) & (t < door + 0.9))
             occ |= on

@@ -217,20 +217,39 @@ def _make_plan(rng, extent, n_floors, ceiling, n_clutter):
             walls.append((p, q, None))
         obst = []
         per_floor = n_clutter // n_floors
-        for i in range(per_floor):
+        doors = []
+        for (p, q, t) in walls:
+            if t is None:
+                continue
+            L = math.hypot(q[0] - p[0], q[1] - p[1])
+            ux, uy = (q[0] - p[0]) / L, (q[1] - p[1]) / L
+            doors.append((p[0] + ux * (t + 0.45), p[1] + uy * (t + 0.45)))
+        # furniture-like clutter: along a random wall of a random room, kept
+        # away from doorways so that the rooms stay connected
+        placed = 0
+        while placed < per_floor:
             rx0, ry0, rx1, ry1 = rooms[rng.integers(len(rooms))]
-            if i % 2 == 0:
+            side = rng.integers(4)
+            box = placed % 2 == 0
+            if box:
                 ex, ey = rng.uniform(0.3, 1.5, size=2)
                 yaw = rng.uniform(0, math.pi)
                 rad = 0.5 * math.hypot(ex, ey)
-                cx = rng.uniform(rx0 + 0.3 + rad, max(rx0 + 0.31 + rad, rx1 - 0.3 - rad))
-                cy = rng.uniform(ry0 + 0.3 + rad, max(ry0 + 0.31 + rad, ry1 - 0.3 - rad))
-                obst.append(("box", cx, cy, ex, ey, yaw))
             else:
-                r = rng.uniform(0.1, 0.5)
-                cx = rng.uniform(rx0 + 0.3 + r, max(rx0 + 0.31 + r, rx1 - 0.3 - r))
-                cy = rng.uniform(ry0 + 0.3 + r, max(ry0 + 0.31 + r, ry1 - 0.3 - r))
-                obst.append(("cyl", cx, cy, r))
+                rad = rng.uniform(0.1, 0.5)
+            off = 0.05 + rad + rng.uniform(0.0, 0.6)
+            if side == 0:
+                cx, cy = rng.uniform(rx0 + rad, rx1 - rad), ry0 + off
+            elif side == 1:
+                cx, cy = rng.uniform(rx0 + rad, rx1 - rad), ry1 - off
+            elif side == 2:
+                cx, cy = rx0 + off, rng.uniform(ry0 + rad, ry1 - rad)
+            else:
+                cx, cy = rx1 - off, rng.uniform(ry0 + rad, ry1 - rad)
+            if any(math.hypot(cx - dx, cy - dy) < rad + 1.0 for dx, dy in doors):
+                continue
+            obst.append(("box", cx, cy, ex, ey, yaw) if box else ("cyl", cx, cy, rad))
+            placed += 1
         rooms_all.append(rooms)
         walls_all.append(walls)
         obst_all.append(obst)

@@ -6,7 +6,10 @@
   plan8m    : 8M-leaf 40x30 m plan; 256 random views, 128@320x240,
               96@640x480, 32@1280x720 (f = 900 W/1280), height 0.3..1.5 m.
   plan2m-lod: the plan2m scene with 2,000 training and 500 held-out
-              1280x720 poses (held-out poses >= 0.5 m from training ones).
+              1280x720 poses at 1.2 m with uniform yaw; a held-out position
+              is at least 0.15 m from every training position (the plan's
+              navigable area, about 70 m^2, cannot keep 2,000 poses 0.5 m
+              apart from 500 others).
   building30m: two 20x15 m floors, 30M leaves; 64 1920x1080 views (f=1300).
 
 Scenes can be scaled down with ``scale`` (leaf count multiplier) for tests.
@@ -50,7 +53,7 @@ def _load(path) -> Scene:
 def floorplan_scene(n_leaves, extent, n_floors, seed, sh_degree=3, n_clutter=300,
                     use_cache=True):
     """Hierarchical floor-plan scene and its plan (cached by parameters)."""
-    key = f"plan_{n_leaves}_{extent[0]}x{extent[1]}_{n_floors}_{seed}_{sh_degree}_{n_clutter}_v1"
+    key = f"plan_{n_leaves}_{extent[0]}x{extent[1]}_{n_floors}_{seed}_{sh_degree}_{n_clutter}_v2"
     path = os.path.join(cache_dir(), hashlib.sha1(key.encode()).hexdigest()[:16] + ".npz")
     leaves = None
     if use_cache and os.path.exists(path):
@@ -101,7 +104,7 @@ def plan2m_lod(scale=1.0, n_train=2000, n_eval=500, use_cache=True):
     scene, plan = floorplan_scene(n, (20.0, 15.0), 1, seed=1, use_cache=use_cache)
     fs = FreeSpace(plan, 0)
     tp, ty = random_poses(fs, n_train, 103, height=(1.2, 1.2))
-    ep, ey = random_poses(fs, n_eval, 104, height=(1.2, 1.2), avoid=tp, min_sep=0.5)
+    ep, ey = random_poses(fs, n_eval, 104, height=(1.2, 1.2), avoid=tp, min_sep=0.15)
     return scene, _cams(tp, ty, 1280, 720, 900.0), _cams(ep, ey, 1280, 720, 900.0)
 
 

@@ -1,0 +1,226 @@
+"""GPU checks of the learned level-of-detail part through the C ABI: the
+network kernels against the FP64 oracle, candidate extraction and features,
+collapsed-subtree renders, the learned cut's fallback, image helpers, and an
+end-to-end training run on a reduced floor plan."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from oracle import oracle as O
+from paper_2603_15186_amd.synth import mlp_init, workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_15186_amd import hgs
+    r = hgs.Renderer(0)
+    yield r
+    r.close()
+
+
+def _bf16_dev(p):
+    bits = M.bf16_bits(np.asarray(p, np.float32))
+    return torch.from_numpy(bits.view(np.int16).copy()).cuda(), M.bf16_value(bits)
+
+
+def _feats(seed, n):
+    rng = np.random.default_rng(seed)
+    F = rng.normal(size=(n, 8)) * rng.uniform(0.5, 3, 8) + rng.normal(size=8)
+    y = (rng.uniform(size=n) < 0.35).astype(np.float32)
+    return F.astype(np.float32), y
+
+
+def test_forward_matches_oracle(R):
+    F, _ = _feats(0, 3000)
+    mean, std = F.mean(0), F.std(0)
+    w, wv = _bf16_dev(mlp_init(1))
+    z = R.mlp_forward(torch.from_numpy(F).cuda(), w, mean, std).cpu().numpy()
+    X = M.standardise(F, mean.astype(np.float32), std.astype(np.float32))
+    zo, _ = M.forward(wv, X)
+    assert np.abs(z - zo).max() <= 1e-4 * np.abs(zo).max() + 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 1000, 4096, 9000])
+def test_gradient_and_loss_match_oracle(R, n):
+    F, y = _feats(n, n)
+    mean, std = F.mean(0), F.std(0) + 0.1
+    p = mlp_init(2)
+    w, wv = _bf16_dev(p)
+    g = torch.zeros(1377, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    R.mlp_train_step(torch.from_numpy(F).cuda(), torch.from_numpy(y).cuda(), mean, std, None, w, None, None, 0, 0.0,
+                     grad_out=g, loss_out=loss)
+    X = M.standardise(F, mean.astype(np.float32), std.astype(np.float32))
+    go = M.grad(wv, X, y)
+    gg = g.cpu().numpy()
+    assert np.abs(gg - go).max() <= 1e-4 * np.abs(go).max() + 1e-7
+    assert float(loss.item()) == pytest.approx(M.loss(wv, X, y), rel=1e-5)
+
+
+def test_adam_steps_match_oracle_and_are_deterministic(R):
+    F, y = _feats(7, 2048)
+    mean, std = F.mean(0), F.std(0)
+    X = M.standardise(F, mean.astype(np.float32), std.astype(np.float32))
+    Fd, yd = torch.from_numpy(F).cuda(), torch.from_numpy(y).cuda()
+    runs = []
+    for _ in range(2):
+        master = torch.from_numpy(mlp_init(4)).cuda()
+        w = torch.empty(1377, dtype=torch.int16, device="cuda")
+        R.mlp_bf16_from_master(master, w)
+        m = torch.zeros_like(master); v = torch.zeros_like(master)
+        po, mo, vo = mlp_init(4).astype(np.float64), np.zeros(1377), np.zeros(1377)
+        for t in range(1, 4):
+            wo = M.bf16_value(M.bf16_bits(po.astype(np.float32)))
+            go = M.grad(wo, X, y)
+            po, mo, vo = M.adam(po, mo, vo, go, t, 1e-2)
+            R.mlp_train_step(Fd, yd, mean, std, master, w, m, v, t, 1e-2)
+            np.testing.assert_allclose(master.cpu().numpy(), po, rtol=0, atol=1e-5)
+        np.testing.assert_array_equal(w.cpu().numpy().view(np.uint16), M.bf16_bits(master.cpu().numpy()))
+        runs.append(master.cpu().numpy())
+    np.testing.assert_array_equal(runs[0], runs[1])
+
+
+def test_feature_stats_and_image_helpers(R):
+    F, _ = _feats(9, 5000)
+    ms = R.feature_stats(torch.from_numpy(F).cuda()).cpu().numpy()
+    np.testing.assert_allclose(ms[:8], F.astype(np.float64).mean(0), rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(ms[8:], F.astype(np.float64).std(0), rtol=1e-5)
+    rng = np.random.default_rng(1)
+    big = rng.uniform(size=(3, 30, 46)).astype(np.float32)
+    small = R.downsample2x(torch.from_numpy(big).cuda()).cpu().numpy()
+    np.testing.assert_allclose(small, big.reshape(3, 15, 2, 23, 2).mean(axis=(2, 4)), atol=1e-7)
+    ref = torch.from_numpy(big).cuda()
+    img = torch.from_numpy(rng.uniform(size=(3, 7, 9)).astype(np.float32)).cuda()
+    out = torch.zeros(2, dtype=torch.float32, device="cuda")
+    R.region_mse([(img, ref, 5, 11), (ref, ref, 0, 0)], out)
+    want = ((img.cpu().numpy().astype(np.float64) - big[:, 11:18, 5:14]) ** 2).mean()
+    assert out[0].item() == pytest.approx(want, rel=1e-6)
+    assert out[1].item() == 0.0
+
+
+# ------------------------------------------------------------ candidates
+
+@pytest.fixture(scope="module")
+def plan():
+    scene, cams = W.plan2m(scale=0.05, n_poses=12)
+    return scene, cams
+
+
+def _sizes(scene, cam):
+    """(2 f r)^2 and d^2 per node in FP64 with separate products and sums,
+    as the cut evaluates them."""
+    c = scene.bound[:, :3].astype(np.float64) - cam.position.astype(np.float64)
+    r = scene.bound[:, 3].astype(np.float64)
+    a = (2.0 * max(cam.fx, cam.fy)) * r
+    d2 = (c[:, 0] * c[:, 0] + c[:, 1] * c[:, 1]) + c[:, 2] * c[:, 2]
+    return a * a, d2
+
+
+def test_candidates_are_the_refined_nodes_in_the_band(R, plan):
+    scene, cams = plan
+    from paper_2603_15186_amd import hgs
+    R.load_scene(scene)
+    R.set_cameras(cams[:4])
+    R.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
+    s_hi = 64.0
+    ent, feat, rect = R.lod_candidates(s_hi)
+    e = ent.cpu().numpy()
+    for v in range(4):
+        cut = O.cut(scene, cams[v], O.MODE_THRESHOLD, 1.0)
+        refined = set()
+        for k in cut:
+            a = int(scene.parent[k])
+            while a >= 0:
+                refined.add(a)
+                a = int(scene.parent[a])
+        lhs, d2 = _sizes(scene, cams[v])
+        want = sorted(k for k in refined if lhs[k] <= (s_hi * s_hi) * d2[k])
+        got = e[e[:, 1] == v, 0]
+        assert sorted(got.tolist()) == want
+        assert np.all(np.diff(np.searchsorted(scene.level_offset, got, side="right")) >= 0)
+    f = feat.cpu().numpy()
+    assert np.isfinite(f).all()
+    assert np.all(f[:, 0] <= math.log(s_hi) + 1e-5)          # log size within the band
+    assert np.all((f[:, 5] >= 0) & (f[:, 5] <= 1 + 1e-6))    # |cos|
+    rc = rect.cpu().numpy()
+    assert np.all(rc[:, 0] <= rc[:, 2]) and np.all(rc[:, 1] <= rc[:, 3])
+
+
+def test_keep_node_collapses_one_subtree(R, plan):
+    scene, cams = plan
+    from paper_2603_15186_amd import hgs
+    R.load_scene(scene)
+    R.set_cameras([cams[2]])
+    R.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
+    ent, _, _ = R.lod_candidates(64.0)
+    node = int(ent.cpu().numpy()[len(ent) // 2, 0])
+    R.set_keep_nodes([node])
+    R.render()
+    got = set(R.get_cut(0).tolist())
+    base = O.cut(scene, cams[2], O.MODE_THRESHOLD, 1.0)
+
+    def under(k):
+        while k >= 0:
+            if k == node:
+                return True
+            k = int(scene.parent[k])
+        return False
+
+    want = {int(k) for k in base if not under(int(k))} | {node}
+    assert got == want
+
+
+def test_learned_cut_fallback_and_band(R, plan):
+    """p* = 0 refines every candidate: the threshold cut, bit for bit; with
+    p* = 1 the learned cut is a coarsening of the threshold cut that only
+    keeps candidates."""
+    scene, cams = plan
+    from paper_2603_15186_amd import hgs
+    R.load_scene(scene)
+    with pytest.raises(hgs.HgsError) as ei:
+        R.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
+    assert ei.value.status == hgs.HGS_E_STATE
+    w = M.bf16_bits(mlp_init(5))
+    R.set_cameras(cams[:3])
+    R.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
+    ent, _, _ = R.lod_candidates(64.0)
+    cand = {(int(a), int(b)) for a, b in ent.cpu().numpy()}
+    for p_star in (0.0, 1.0):
+        R.load_lod_mlp(w, np.zeros(8), np.ones(8), p_star, 64.0)
+        R.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
+        R.render()
+        for v in range(3):
+            got = R.get_cut(v)
+            thr = O.cut(scene, cams[v], O.MODE_THRESHOLD, 1.0)
+            if p_star == 0.0:
+                assert np.array_equal(got, thr)
+            else:
+                s = set(got.tolist())
+                for k in thr:
+                    anc = [int(k)]
+                    while scene.parent[anc[-1]] >= 0:
+                        anc.append(int(scene.parent[anc[-1]]))
+                    hit = [a for a in anc if a in s]
+                    assert len(hit) == 1
+                    assert hit[0] == k or (hit[0], v) in cand
+                assert len(got) <= len(thr)
+
+
+def test_training_pipeline_end_to_end(R, plan):
+    """Labels from collapsed-window renders, training with the library's
+    kernels, calibration: the training loss falls and the calibrated cut
+    stays within the training-pose budget."""
+    scene, cams = plan
+    from paper_2603_15186_amd import lod
+    R.load_scene(scene)
+    model = lod.train_pipeline(R, cams[:10], calib_n=4, per_view=128, epochs=15, seed=0)
+    assert model.info["samples"] > 100
+    assert 0.0 <= model.p_star <= 0.9
+    assert model.info["calib_loss_db"] <= lod.TARGET_TRAIN_DB + 1e-9

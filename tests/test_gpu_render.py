@@ -60,20 +60,26 @@ def _check_full(img, scene, cam, mode=O.MODE_THRESHOLD, tau=1.0, ids=None, max_s
 
 # ------------------------------------------------------------------ sort
 
-@pytest.mark.parametrize("n,bits", [(1, 8), (1000, 8), (300001, 12), (300001, 19), (2_000_003, 32), (5_000_000, 12)])
-def test_radix_sort_bit_exact(R, n, bits):
+@pytest.mark.parametrize("n,bits,digit", [(1, 8, 11), (1000, 8, 8), (300001, 12, 11), (300001, 12, 6),
+                                          (300001, 19, 11), (300001, 19, 8), (2_000_003, 32, 11),
+                                          (2_000_003, 32, 8), (5_000_000, 17, 11), (5_000_000, 17, 9)])
+def test_radix_sort_bit_exact(R, n, bits, digit):
+    hgs = _hgs()
     rng = np.random.default_rng(n + bits)
-    keys = rng.integers(0, 1 << bits, size=n, dtype=np.uint64).astype(np.uint32)
+    keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)   # bits above key_bits ignored
     if n > 10:
         keys[: n // 10] = keys[0]            # many equal keys: stability matters
     vals = np.arange(n, dtype=np.uint32)
     kd = torch.from_numpy(keys.view(np.int32)).cuda()
     vd = torch.from_numpy(vals.view(np.int32)).cuda()
+    R.set_option(hgs.HGS_OPT_SORT_DIGIT_BITS, digit)
     R.sort_pairs(kd, vd, bits)
+    R.set_option(hgs.HGS_OPT_SORT_DIGIT_BITS, 8)
     torch.cuda.synchronize()
-    order = np.argsort(keys, kind="stable")
-    np.testing.assert_array_equal(kd.cpu().numpy().view(np.uint32), keys[order])
+    masked = keys & np.uint32((1 << bits) - 1) if bits < 32 else keys
+    order = np.argsort(masked, kind="stable")
     np.testing.assert_array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
+    np.testing.assert_array_equal(kd.cpu().numpy().view(np.uint32), keys[order])
 
 
 # ------------------------------------------------------------------ flat scene
@@ -133,11 +139,11 @@ def test_invariance_across_launch_choices(R, box):
     for a, b in zip(ref, again):
         assert np.array_equal(a, b)
     for opts in ({"batch_depth": 64}, {"batch_depth": 128}, {"batch_depth": 512}, {"exact_tiles": 0},
-                 {"persistent": 1}):
+                 {"persistent": 1}, {"sort_digit_bits": 11}, {"sort_digit_bits": 6}):
         img = _render(R, scene, cams, **opts)[0]
         for a, b in zip(ref, img):
             assert np.array_equal(a, b), opts
-    _render(R, scene, cams, batch_depth=256, exact_tiles=1, persistent=0)
+    _render(R, scene, cams, batch_depth=256, exact_tiles=1, persistent=0, sort_digit_bits=8)
 
 
 def test_background_when_nothing_visible(R, box):

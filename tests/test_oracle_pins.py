@@ -277,8 +277,10 @@ def test_oracle_matches_untiled_brute_force(seed):
     rng = np.random.default_rng(100 + seed)
     deg = seed % 4
     sc = _rand_scene(rng, 40, deg)
+    # seeds 4 and 5: off-centre principal point (window cameras)
+    cx, cy = (5.0, 15.0) if seed >= 4 else (None, None)
     cam = yaw_camera(24, 20, 22.0, (0.05, 0.0, 0.1), math.pi / 2 + 0.05 * seed,
-                     bg=(0.1, 0.0, 0.2) if seed % 2 else (0, 0, 0))
+                     bg=(0.1, 0.0, 0.2) if seed % 2 else (0, 0, 0), cx=cx, cy=cy)
     res, _ = _full(sc, cam)
     rgb, dep, alp = brute.render(sc, cam)
     k = 0
