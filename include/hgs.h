@@ -274,6 +274,35 @@ typedef struct {
  * The descriptors are host memory (copied). */
 hgs_status hgs_region_mse(hgs_ctx* ctx, void* stream, int32_t n, const hgs_region* regions, float* out);
 
+/* ---------------------------------------------------------------------- */
+/* Ground truth of synthetic scenes (evaluation, not the render path): the */
+/* exact surfaces the Gaussians approximate, ray cast with supersampling.  */
+/* They stand in for the posed photographs a reconstruction is judged      */
+/* against (NavGSim Table 2 reports PSNR against real images).             */
+/* ---------------------------------------------------------------------- */
+
+/* kind 0: rectangle o + u a + v b, u, v in [0, 1]; kind 1: cylinder side,
+ * axis through (o[0], o[1]), z from o[2] to o[2] + h, radius r; kind 2: disk
+ * centred at o with radius r, normal +z.  Colour = clamp(col * f(p), 0, 1)
+ * with pattern 0: f = 1; 1: 0.85 + 0.15 sign(sin(2 pi x / 0.4)); 2: 0.9 +
+ * 0.1 ((floor(x / 0.6) + floor(y / 0.6)) mod 2); 3: 0.55 if (z mod 3) < 0.12
+ * else 0.92 + 0.08 sin(2 pi (x + y) / 1.3). */
+typedef struct {
+    int32_t kind;
+    int32_t pattern;
+    float o[3], a[3], b[3];
+    float col[3];
+    float r, h;
+} hgs_surface;
+
+/* Copy n surfaces (host) into the context. */
+hgs_status hgs_set_surfaces(hgs_ctx* ctx, int32_t n, const hgs_surface* surfaces);
+
+/* Ray cast the surfaces seen by camera view `view` (of hgs_set_cameras)
+ * with ss x ss samples per pixel (1..4) into device rgb[3][H][W]; rays that
+ * hit nothing take the camera's background. */
+hgs_status hgs_render_surfaces(hgs_ctx* ctx, void* stream, int32_t view, int32_t ss, float* rgb);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,7 +51,8 @@ struct hgs_ctx {
     DevMem mlp_w, mlp_dev;
     LodMlpDev mlp_host{};
     double s_hi = 64.0;               // candidate band of the learned cut (pixels)
-    DevMem train_scratch, region_dev;
+    DevMem train_scratch, region_dev, surf;
+    int32_t n_surf = 0;
     // options
     bool sync_check = true, auto_regrow = true, use_graph = false;
     RenderOpts ropts;
@@ -231,8 +232,12 @@ hgs_status alloc_work(hgs_ctx* c) {
     return HGS_OK;
 }
 
-uint32_t clamp_cap(uint64_t x) {
-    const uint64_t lim = 0xF0000000ull;
+// Cut entries are addressed by 28-bit indices inside pair values; pairs by
+// 32-bit positions.
+constexpr uint64_t kEntryLimit = (uint64_t)kEntryMask + 1;
+constexpr uint64_t kPairLimit = 0xF0000000ull;
+
+uint32_t clamp_cap(uint64_t x, uint64_t lim = kEntryLimit) {
     return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(x, 1024), lim);
 }
 
@@ -248,8 +253,8 @@ void initial_caps(hgs_ctx* c) {
     uint64_t m = std::min<uint64_t>(V * per_view, budget);
     if (!c->hier || c->lod_mode == HGS_LOD_ALL_LEAVES) m = std::min<uint64_t>(V * per_view, 1ull << 31);
     c->cut_cap = std::max(c->cut_cap, clamp_cap(m));
-    c->frontier_cap = std::max(c->frontier_cap, clamp_cap(std::min<uint64_t>(m, budget)));
-    c->pair_cap = std::max(c->pair_cap, clamp_cap(std::min<uint64_t>(8 * (uint64_t)c->cut_cap, 256ull << 20)));
+    c->frontier_cap = std::max(c->frontier_cap, clamp_cap(std::min<uint64_t>(m, budget), kPairLimit));
+    c->pair_cap = std::max(c->pair_cap, clamp_cap(std::min<uint64_t>(8 * (uint64_t)c->cut_cap, 256ull << 20), kPairLimit));
 }
 
 hgs_status upload_views(hgs_ctx* c, hipStream_t s, const hgs_output* outs) {
@@ -430,15 +435,16 @@ LodMlpDev mlp_geometry(hgs_ctx* c) {
 }
 
 hgs_status grow_from(hgs_ctx* c, const Counters& k) {
-    auto grow = [](uint32_t cap, uint32_t need) {
+    auto grow = [](uint32_t cap, uint32_t need, uint64_t lim) {
         uint64_t g = std::max<uint64_t>((uint64_t)need + need / 4, 2ull * cap);
-        return clamp_cap(g);
+        return clamp_cap(g, lim);
     };
-    if (k.overflow & kOvFrontier) c->frontier_cap = grow(c->frontier_cap, k.need_frontier);
-    if (k.overflow & kOvCut) c->cut_cap = grow(c->cut_cap, k.need_cut);
-    if (k.overflow & kOvPairs) c->pair_cap = grow(c->pair_cap, k.need_pairs);
+    if (k.overflow & kOvFrontier) c->frontier_cap = grow(c->frontier_cap, k.need_frontier, kPairLimit);
+    if (k.overflow & kOvCut) c->cut_cap = grow(c->cut_cap, k.need_cut, kEntryLimit);
+    if (k.overflow & kOvPairs) c->pair_cap = grow(c->pair_cap, k.need_pairs, kPairLimit);
     // a cut overflow leaves the pair count unknown; keep pairs proportional
-    if (k.overflow & kOvCut) c->pair_cap = std::max(c->pair_cap, clamp_cap(std::min<uint64_t>(8ull * c->cut_cap, 0xF0000000ull)));
+    if (k.overflow & kOvCut)
+        c->pair_cap = std::max(c->pair_cap, clamp_cap(std::min<uint64_t>(8ull * c->cut_cap, kPairLimit), kPairLimit));
     ++c->regrows;
     return alloc_work(c);
 }
@@ -476,7 +482,7 @@ void hgs_destroy(hgs_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     DevMem* all[] = {&c->geo, &c->sh, &c->bound, &c->child, &c->leaf_ids, &c->parent, &c->nodefeat, &c->lvl,
-                     &c->train_scratch, &c->region_dev, &c->views,
+                     &c->train_scratch, &c->region_dev, &c->surf, &c->views,
                      &c->tile_view, &c->mlp_w, &c->mlp_dev, &c->frontier[0], &c->frontier[1], &c->cut, &c->proj,
                      &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->rect, &c->offsets,
                      &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
@@ -1105,6 +1111,35 @@ hgs_status hgs_region_mse(hgs_ctx* c, void* stream, int32_t n, const hgs_region*
     if ((st = ensure(c, c->region_dev, sizeof(RegionDev) * (size_t)n))) return st;
     HIP_TRY(c, hipMemcpy(c->region_dev.p, r.data(), sizeof(RegionDev) * (size_t)n, hipMemcpyHostToDevice));
     launch_region_mse(P<RegionDev>(c->region_dev), n, out, s);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_set_surfaces(hgs_ctx* c, int32_t n, const hgs_surface* surfaces) {
+    if (!c || n < 0 || (n > 0 && !surfaces)) return HGS_E_INVALID;
+    for (int i = 0; i < n; ++i) {
+        const hgs_surface& q = surfaces[i];
+        if (q.kind < 0 || q.kind > 2 || q.pattern < 0 || q.pattern > 3) return fail(c, HGS_E_INVALID, "surface %d: bad kind", i);
+        for (int k = 0; k < 3; ++k)
+            if (!finite(q.o[k]) || !finite(q.a[k]) || !finite(q.b[k]) || !finite(q.col[k]))
+                return fail(c, HGS_E_INVALID, "surface %d: not finite", i);
+    }
+    static_assert(sizeof(hgs_surface) == sizeof(SurfaceDev), "surface layout");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hgs_status st;
+    if ((st = ensure(c, c->surf, sizeof(SurfaceDev) * (size_t)(n > 0 ? n : 1)))) return st;
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (n) HIP_TRY(c, hipMemcpy(c->surf.p, surfaces, sizeof(SurfaceDev) * (size_t)n, hipMemcpyHostToDevice));
+    c->n_surf = n;
+    return HGS_OK;
+}
+
+hgs_status hgs_render_surfaces(hgs_ctx* c, void* stream, int32_t view, int32_t ss, float* rgb) {
+    if (!c || !rgb) return HGS_E_INVALID;
+    if (view < 0 || view >= (int32_t)c->cams.size()) return fail(c, HGS_E_INVALID, "view out of range");
+    if (ss < 1 || ss > 4) return fail(c, HGS_E_INVALID, "supersampling must be 1..4");
+    HIP_TRY(c, hipSetDevice(c->device));
+    launch_surfaces(P<SurfaceDev>(c->surf), c->n_surf, c->views_host[view], ss, rgb, (hipStream_t)stream);
     HIP_TRY(c, hipGetLastError());
     return HGS_OK;
 }

@@ -41,7 +41,7 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const Counters* ctr,
 
 template <int BATCH, bool COUNT>
 __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t tile, float4* s_a, float4* s_b,
-                                               float2* s_c, uint32_t* s_red) {
+                                               float2* s_c, uint32_t* s_m, uint32_t* s_red) {
     const uint32_t view = a.tile_view[tile];
     const ViewDev& V = a.views[view];
     const uint32_t local = tile - V.tile_base;
@@ -59,15 +59,20 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
     for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
         const uint32_t cnt = min((uint32_t)BATCH, rg.y - base);
         for (uint32_t j = threadIdx.x; j < cnt; j += kNT) {
-            const uint32_t e = a.vals[base + j];
+            const uint32_t val = a.vals[base + j];
+            const uint32_t e = val & kEntryMask;
             const Proj p = a.proj[e < a.cut_cap ? e : 0u];
             s_a[j] = make_float4((float)(p.u - dx0), (float)(p.v - dy0), p.p, p.r);
             s_b[j] = make_float4(p.s, p.opacity, p.z, p.c0);
             s_c[j] = make_float2(p.c1, p.c2);
+            s_m[j] = val >> kStripShift;
         }
         __syncthreads();
         if (!done) {
+            const uint32_t wbit = 1u << (threadIdx.x / kWave);
             for (uint32_t j = 0; j < cnt; ++j) {
+                // entries that reach no pixel centre of this wave's strip
+                if (!(__builtin_amdgcn_readfirstlane(s_m[j]) & wbit)) continue;
                 const float4 A = s_a[j];
                 const float ddx = fx - A.x, ddy = fy - A.y;
                 const float4 B = s_b[j];
@@ -123,8 +128,9 @@ __global__ __launch_bounds__(kNT) void k_composite(CompositeArgs a) {
     __shared__ float4 s_a[BATCH];
     __shared__ float4 s_b[BATCH];
     __shared__ float2 s_c[BATCH];
+    __shared__ uint32_t s_m[BATCH];
     __shared__ uint32_t s_red[kNT / kWave];
-    composite_tile<BATCH, COUNT>(a, blockIdx.x, s_a, s_b, s_c, s_red);
+    composite_tile<BATCH, COUNT>(a, blockIdx.x, s_a, s_b, s_c, s_m, s_red);
 }
 
 // Persistent variant: a fixed grid takes tiles from a global counter until
@@ -134,6 +140,7 @@ __global__ __launch_bounds__(kNT) void k_composite_persistent(CompositeArgs a) {
     __shared__ float4 s_a[BATCH];
     __shared__ float4 s_b[BATCH];
     __shared__ float2 s_c[BATCH];
+    __shared__ uint32_t s_m[BATCH];
     __shared__ uint32_t s_red[kNT / kWave];
     __shared__ uint32_t s_tile;
     for (;;) {
@@ -142,7 +149,7 @@ __global__ __launch_bounds__(kNT) void k_composite_persistent(CompositeArgs a) {
         const uint32_t tile = s_tile;
         __syncthreads();
         if (tile >= a.total_tiles) break;
-        composite_tile<BATCH, COUNT>(a, tile, s_a, s_b, s_c, s_red);
+        composite_tile<BATCH, COUNT>(a, tile, s_a, s_b, s_c, s_m, s_red);
     }
 }
 

@@ -241,12 +241,17 @@ __global__ void k_lod_features(const uint2* cand, const uint32_t* count, const V
         lod_features(m, V, (int)e.x, b, g, level, f);
 #pragma unroll
         for (int k = 0; k < kMlpIn; ++k) feats[(size_t)i * kMlpIn + k] = f[k];
-        // footprint: projection of the bounding sphere (centre +- f r / z)
-        const double z = fmax(g.pz, V.znear);
-        const double u = V.fx * g.px / z + V.cx, v = V.fy * g.py / z + V.cy;
-        const double ru = V.fx * g.r / z + 1.0, rv = V.fy * g.r / z + 1.0;
-        const int x0 = (int)fmax(floor(u - ru), 0.0), x1 = (int)fmin(ceil(u + ru), V.W - 1.0);
-        const int y0 = (int)fmax(floor(v - rv), 0.0), y1 = (int)fmin(ceil(v + rv), V.H - 1.0);
+        // footprint: projection of the bounding sphere (centre +- f r / z),
+        // the whole image when the sphere reaches the near plane; clamped to
+        // the image and never empty
+        int x0 = 0, y0 = 0, x1 = (int)V.W - 1, y1 = (int)V.H - 1;
+        if (g.pz - g.r > V.znear) {
+            const double u = V.fx * g.px / g.pz + V.cx, v = V.fy * g.py / g.pz + V.cy;
+            const double ru = V.fx * g.r / (g.pz - g.r) + 1.0, rv = V.fy * g.r / (g.pz - g.r) + 1.0;
+            const double lox = fmin(fmax(floor(u - ru), 0.0), V.W - 1.0), hix = fmin(fmax(ceil(u + ru), 0.0), V.W - 1.0);
+            const double loy = fmin(fmax(floor(v - rv), 0.0), V.H - 1.0), hiy = fmin(fmax(ceil(v + rv), 0.0), V.H - 1.0);
+            x0 = (int)lox; x1 = (int)hix; y0 = (int)loy; y1 = (int)hiy;
+        }
         rects[i] = make_int4(x0, y0, x1, y1);
     }
 }

@@ -16,6 +16,13 @@ namespace hgs {
 constexpr int kTile = 16;                 // tile edge in pixels
 constexpr int kTilePx = kTile * kTile;    // pixels per tile
 constexpr int kMaxViews = 4096;
+// Pair values carry the entry index in the low 28 bits and, in the top 4,
+// which 4-row strips of the tile (one per compositor wave) the ellipse
+// reaches at a pixel centre.
+constexpr int kStrips = 4;
+constexpr int kStripRows = kTile / kStrips;
+constexpr int kStripShift = 28;
+constexpr uint32_t kEntryMask = (1u << kStripShift) - 1u;
 
 // Overflow bits in Counters::overflow.
 constexpr uint32_t kOvFrontier = 1u;
@@ -207,6 +214,17 @@ struct RegionDev {
     int32_t w, h, ref_w, ref_h, x0, y0;
 };
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
+
+// ground-truth surfaces of synthetic scenes (surfaces.hip); layout of
+// hgs_surface
+struct SurfaceDev {
+    int32_t kind;                    // 0 rectangle, 1 cylinder side, 2 disk
+    int32_t pattern;                 // 0 none, 1 boards, 2 tiles, 3 wall stripes
+    float o[3], a[3], b[3];
+    float col[3];
+    float r, h;
+};
+void launch_surfaces(const SurfaceDev* surf, int ns, const ViewDev& V, int ss, float* out, hipStream_t s);
 void launch_region_mse(const RegionDev* reg, int n, float* out, hipStream_t s);
 
 }  // namespace hgs

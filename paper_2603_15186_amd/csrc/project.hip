@@ -108,26 +108,34 @@ __device__ __forceinline__ RowSpan row_span_init(const Proj& p) {
     return r;
 }
 
-__device__ __forceinline__ void row_tiles(const RowSpan& r, double u, double v, int ty, int W, int H, int tx_lo,
-                                          int tx_hi, int* lo, int* hi) {
-    double y0 = ty * kTile + 0.5 - v;
-    double y1 = fmin((double)(ty * kTile + kTile - 1), (double)(H - 1)) + 0.5 - v;
-    y0 = fmax(y0, -r.ey);
-    y1 = fmin(y1, r.ey);
-    if (y0 > y1) {
-        *lo = 1;
-        *hi = 0;
-        return;
-    }
+// x-extent [xa, xb] (absolute pixels) of the ellipse within the band of
+// pixel-centre heights [ya, yb] (absolute); false if they do not meet.
+__device__ __forceinline__ bool band_span(const RowSpan& r, double u, double v, double ya, double yb, double* xa,
+                                          double* xb) {
+    double y0 = fmax(ya - v, -r.ey);
+    double y1 = fmin(yb - v, r.ey);
+    if (y0 > y1) return false;
     const double yr = fmin(fmax(r.ymax_at_x, y0), y1);
     const double yl = fmin(fmax(-r.ymax_at_x, y0), y1);
     const double sr = fmax(r.A * r.Q - r.det * yr * yr, 0.0);
     const double sl = fmax(r.A * r.Q - r.det * yl * yl, 0.0);
-    const double xb = (-r.B * yr + sqrt(sr)) / r.A + 1e-7;
-    const double xa = (-r.B * yl - sqrt(sl)) / r.A - 1e-7;
+    *xb = u + (-r.B * yr + sqrt(sr)) / r.A + 1e-7;
+    *xa = u + (-r.B * yl - sqrt(sl)) / r.A - 1e-7;
+    return true;
+}
+
+__device__ __forceinline__ void row_tiles(const RowSpan& r, double u, double v, int ty, int W, int H, int tx_lo,
+                                          int tx_hi, int* lo, int* hi) {
+    double xa, xb;
+    const double ya = ty * kTile + 0.5, yb = fmin((double)(ty * kTile + kTile - 1), (double)(H - 1)) + 0.5;
+    if (!band_span(r, u, v, ya, yb, &xa, &xb)) {
+        *lo = 1;
+        *hi = 0;
+        return;
+    }
     // tile tx covers pixel centres [16 tx + 0.5, 16 tx + 15.5]
-    const int a = (int)ceil((u + xa - (kTile - 0.5)) / kTile);
-    const int b = (int)floor((u + xb - 0.5) / kTile);
+    const int a = (int)ceil((xa - (kTile - 0.5)) / kTile);
+    const int b = (int)floor((xb - 0.5) / kTile);
     *lo = a > tx_lo ? a : tx_lo;
     *hi = b < tx_hi ? b : tx_hi;
     (void)W;
@@ -337,28 +345,51 @@ __global__ __launch_bounds__(kNT) void k_emit(EmitArgs a) {
         const ViewDev& V = a.views[a.cut[e].y];
         const uint32_t tb = V.tile_base;
         const int tw = V.tiles_x;
-        const uint32_t all = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
-        if (!a.exact_tiles || all <= 1) {
+        if (!a.exact_tiles) {
             for (int ty = rc.y; ty <= rc.w; ++ty)
                 for (int tx = rc.x; tx <= rc.z; ++tx) {
                     if (pos < cap) {
                         a.keys[pos] = tb + (uint32_t)(ty * tw + tx);
-                        a.vals[pos] = e;
+                        a.vals[pos] = e | (0xFu << kStripShift);
                     }
                     ++pos;
                 }
             continue;
         }
+        // exact tiles, each tagged with the 4-row strips (one per wave of the
+        // compositor) that hold a pixel centre inside the ellipse
         const Proj p = a.proj[e];
         const RowSpan r = row_span_init(p);
+        const uint32_t all = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
         for (int ty = rc.y; ty <= rc.w; ++ty) {
             int lo, hi;
-            row_tiles(r, p.u, p.v, ty, V.width, V.height, rc.x, rc.z, &lo, &hi);
+            if (all <= 1) {
+                lo = rc.x;
+                hi = rc.z;
+            } else {
+                row_tiles(r, p.u, p.v, ty, V.width, V.height, rc.x, rc.z, &lo, &hi);
+            }
+            if (lo > hi) continue;
+            double sa[kStrips], sb[kStrips];
+            bool sv[kStrips];
+#pragma unroll
+            for (int q = 0; q < kStrips; ++q) {
+                const int y0 = ty * kTile + q * kStripRows;
+                sv[q] = y0 < V.height &&
+                        band_span(r, p.u, p.v, y0 + 0.5, fmin((double)(y0 + kStripRows - 1), (double)(V.height - 1)) + 0.5,
+                                  &sa[q], &sb[q]);
+            }
             const uint32_t row = tb + (uint32_t)(ty * tw);
             for (int tx = lo; tx <= hi; ++tx) {
+                const double x0c = tx * kTile + 0.5;
+                const double x1c = fmin((double)(tx * kTile + kTile - 1), (double)(V.width - 1)) + 0.5;
+                uint32_t mask = 0;
+#pragma unroll
+                for (int q = 0; q < kStrips; ++q)
+                    if (sv[q] && sb[q] >= x0c && sa[q] <= x1c) mask |= 1u << q;
                 if (pos < cap) {
                     a.keys[pos] = row + (uint32_t)tx;
-                    a.vals[pos] = e;
+                    a.vals[pos] = e | (mask << kStripShift);
                 }
                 ++pos;
             }

@@ -105,6 +105,8 @@ EXPORTS = [
     ("hgs_feature_stats", ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, _P]),
     ("hgs_downsample2x", ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
     ("hgs_region_mse", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.POINTER(hgs_region), _P]),
+    ("hgs_set_surfaces", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    ("hgs_render_surfaces", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
 ]
 
 N_MLP_PARAMS = 1377
@@ -360,6 +362,21 @@ class Renderer:
             arr[i] = hgs_region(img.data_ptr(), ref.data_ptr(), img.shape[2], img.shape[1], ref.shape[2],
                                 ref.shape[1], int(x0), int(y0))
         self._check(self.lib.hgs_region_mse(self.ctx, self._stream(stream), len(regions), arr, out.data_ptr()))
+        return out
+
+    # ------------------------------------------------------------ ground truth
+    def set_surfaces(self, surfaces):
+        """surfaces: numpy records of synth.SURFACE_DTYPE."""
+        a = np.ascontiguousarray(surfaces)
+        assert a.dtype.itemsize == 64
+        self._check(self.lib.hgs_set_surfaces(self.ctx, a.size, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def render_surfaces(self, view, ss=3, out=None, stream=None):
+        import torch
+        c = self.cams[view]
+        if out is None:
+            out = torch.empty((3, c.height, c.width), dtype=torch.float32, device=torch.device("cuda", self.device))
+        self._check(self.lib.hgs_render_surfaces(self.ctx, self._stream(stream), int(view), int(ss), out.data_ptr()))
         return out
 
     def sort_pairs(self, keys, vals, key_bits, stream=None):

@@ -8,11 +8,13 @@ the threshold rule, projected size <= s_hi), predicts whether refining them
 matters for the image; the threshold rule stays in force everywhere else and
 is the fallback when the network is absent or fails its calibration.
 
-Quality is PSNR against an anti-aliased full-leaf reference: the full-leaf
-render at twice the resolution on each axis, box-filtered 2x2.  (At tau = 1
-pixel every visible leaf is selected on these scenes, so the threshold render
-itself would be a lossless reference.)  The PSNR loss of a cut is the mean
-per-view PSNR of the tau = 1 threshold cut minus that of the cut.
+Quality is PSNR against ground-truth images of the scene: the exact
+surfaces the synthetic Gaussians were drawn from, ray cast with 3x3
+supersampling -- the stand-in for the posed photographs a reconstruction is
+judged against (Table 2 of the paper reports PSNR against real images).
+Without surfaces, an anti-aliased full-leaf render (twice the resolution,
+2x2 box filter) serves instead.  The PSNR loss of a cut is the mean per-view
+PSNR of the tau = 1 threshold cut minus that of the cut.
 
 Labels: for a candidate n seen from a training pose, the footprint window is
 the clipped screen box of n's bounding sphere; the window is rendered with
@@ -97,13 +99,20 @@ def render_rgb(r: hgs.Renderer, cams, mode, tau, keep=None):
     return [t[0] for t in outs]
 
 
-def reference_images(r: hgs.Renderer, cams, chunk=8):
-    """Anti-aliased full-leaf references: every visible leaf at 2x
-    resolution, 2x2 box-filtered."""
+def reference_images(r: hgs.Renderer, cams, chunk=8, surfaces=True):
+    """Ground-truth images of cams: the exact surfaces (installed with
+    Renderer.set_surfaces) ray cast with 3x3 samples per pixel; with
+    surfaces=False, anti-aliased full-leaf renders (every visible leaf at 2x
+    resolution, 2x2 box-filtered)."""
     refs = []
     for i in range(0, len(cams), chunk):
-        big = render_rgb(r, [scaled_camera(c, 2) for c in cams[i:i + chunk]], hgs.HGS_LOD_THRESHOLD, 1e-3)
-        refs += [r.downsample2x(b) for b in big]
+        part = cams[i:i + chunk]
+        if surfaces:
+            r.set_cameras(part)
+            refs += [r.render_surfaces(v, 3) for v in range(len(part))]
+        else:
+            big = render_rgb(r, [scaled_camera(c, 2) for c in part], hgs.HGS_LOD_THRESHOLD, 1e-3)
+            refs += [r.downsample2x(b) for b in big]
     return refs
 
 
@@ -239,12 +248,13 @@ def calibrate(r: hgs.Renderer, model: LodModel, cams, refs, base_psnr, target=TA
     return 0.0, 0.0
 
 
-def train_pipeline(r: hgs.Renderer, train_cams, calib_n=64, per_view=256, epochs=40, seed=0, log=None) -> LodModel:
+def train_pipeline(r: hgs.Renderer, train_cams, calib_n=64, per_view=256, epochs=40, seed=0, log=None,
+                   s_hi=S_HI) -> LodModel:
     """Labels on train_cams, training, calibration of p_star on a subset of
     the training poses."""
-    feats, labels, st = make_labels(r, train_cams, per_view=per_view, seed=seed, log=log)
+    feats, labels, st = make_labels(r, train_cams, per_view=per_view, seed=seed, log=log, s_hi=s_hi)
     master, bf16, mean, std, hist = train(r, feats, labels, epochs=epochs, seed=seed, log=log)
-    model = LodModel(master, bf16, mean, std, 0.5, S_HI,
+    model = LodModel(master, bf16, mean, std, 0.5, s_hi,
                      {"samples": st["sampled"], "refine_frac": st["refine"] / max(1, st["sampled"]),
                       "final_loss": hist[-1] if hist else float("nan"), "epochs": epochs})
     step = max(1, len(train_cams) // calib_n)

@@ -191,7 +191,7 @@ def _pastel(rng):
 
 @dataclasses.dataclass
 class FloorPlan:
-    """Geometry of a generated building (used for free-space queries)."""
+    """Geometry of a generated building (free-space queries, ground truth)."""
 
     extent: tuple
     n_floors: int
@@ -199,6 +199,28 @@ class FloorPlan:
     rooms: list          # per floor: list of (x0,y0,x1,y1)
     walls: list          # per floor: list of ((x0,y0),(x1,y1), door_t or None)
     obstacles: list      # per floor: list of ("box", cx, cy, ex, ey, yaw) / ("cyl", cx, cy, r)
+    surfaces: np.ndarray | None = None   # SURFACE_DTYPE records the leaves were drawn from
+
+
+# Record layout of one exact surface (matches the renderer's hgs_surface).
+SURFACE_DTYPE = np.dtype([("kind", "<i4"), ("pattern", "<i4"), ("o", "<f4", 3), ("a", "<f4", 3),
+                          ("b", "<f4", 3), ("col", "<f4", 3), ("r", "<f4"), ("h", "<f4")])
+
+
+def surfaces_array(S) -> np.ndarray:
+    """The generator's surfaces as SURFACE_DTYPE records."""
+    out = np.zeros(len(S.rects) + len(S.cyls) + len(S.disks), SURFACE_DTYPE)
+    i = 0
+    for (o, a, b, c, pat) in S.rects:
+        out[i] = (0, pat, o, a, b, np.clip(c, -10, 10), 0.0, 0.0)
+        i += 1
+    for (cxy, z0, r, h, c) in S.cyls:
+        out[i] = (1, 0, (cxy[0], cxy[1], z0), (0, 0, 0), (0, 0, 0), c, r, h)
+        i += 1
+    for (cc, r, c) in S.disks:
+        out[i] = (2, 0, cc, (0, 0, 0), (0, 0, 0), c, r, 0.0)
+        i += 1
+    return out
 
 
 def _make_plan(rng, extent, n_floors, ceiling, n_clutter):
@@ -333,6 +355,7 @@ def make_floorplan(n_leaves: int, extent=(20.0, 15.0), n_floors: int = 1,
     rng = np.random.default_rng(seed)
     plan = _make_plan(rng, extent, n_floors, ceiling, n_clutter)
     S = _plan_surfaces(rng, plan, None)
+    plan.surfaces = surfaces_array(S)
     areas = S.areas()
     share = areas / areas.sum() * n_leaves
     counts = np.floor(share).astype(np.int64)

@@ -58,9 +58,10 @@ def floorplan_scene(n_leaves, extent, n_floors, seed, sh_degree=3, n_clutter=300
     leaves = None
     if use_cache and os.path.exists(path):
         scene = _load(path)
-        from .scenes import _make_plan
-        rng = np.random.default_rng(seed)
+        from .scenes import _make_plan, _plan_surfaces, surfaces_array
+        rng = np.random.default_rng(seed)    # same draws as make_floorplan
         plan = _make_plan(rng, extent, n_floors, 3.0, n_clutter)
+        plan.surfaces = surfaces_array(_plan_surfaces(rng, plan, None))
         return scene, plan
     leaves, plan = make_floorplan(n_leaves, extent, n_floors, 3.0, n_clutter, sh_degree, seed)
     scene = build_hierarchy(leaves)
@@ -99,13 +100,14 @@ def plan8m(scale=1.0, n_views=(128, 96, 32), use_cache=True):
     return scene, plan8m_views(plan, n_views)
 
 
-def plan2m_lod(scale=1.0, n_train=2000, n_eval=500, use_cache=True):
+def plan2m_lod(scale=1.0, n_train=2000, n_eval=500, use_cache=True, with_plan=False):
     n = int(round(2_000_000 * scale))
     scene, plan = floorplan_scene(n, (20.0, 15.0), 1, seed=1, use_cache=use_cache)
     fs = FreeSpace(plan, 0)
     tp, ty = random_poses(fs, n_train, 103, height=(1.2, 1.2))
     ep, ey = random_poses(fs, n_eval, 104, height=(1.2, 1.2), avoid=tp, min_sep=0.15)
-    return scene, _cams(tp, ty, 1280, 720, 900.0), _cams(ep, ey, 1280, 720, 900.0)
+    out = (scene, _cams(tp, ty, 1280, 720, 900.0), _cams(ep, ey, 1280, 720, 900.0))
+    return out + (plan,) if with_plan else out
 
 
 def building30m(scale=1.0, n_views=64, use_cache=True):
