@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
-"""Throughput of the hierarchical-3DGS forward render on one MI355X.
+"""Throughput of the hierarchical-3DGS forward render on one MI355X:
+batched learned-LOD rendering against the plain threshold cut.
 
-Workload: the 2M-leaf floor-plan scene (20 x 15 m, SH degree 3, 8-level
-hierarchy) seen from robot poses of a 1.2 m-high trajectory at 1280x720
-(fx = 900), threshold LOD cut at tau = 1 px.  One step renders a batch of
-views through the whole path -- LOD cut, projection, depth sort, pair
-emission, tile sort, compositing -- in one call; inputs are resident in HBM.
+Workload (plan2m-lod): the 2M-leaf floor-plan scene (20 x 15 m, SH degree 3,
+8-level hierarchy) seen from 500 held-out robot poses at 1280x720 (fx = 900,
+1.2 m height, uniform yaw).  One step renders a batch of views (default 50)
+through the whole path -- learned LOD cut, projection, depth sort, pair
+emission, tile sort, compositing -- in one call; the batches cycle through
+the held-out poses, inputs resident in HBM.  The learned cut's network is
+the committed checkpoint trained on the scene's 2,000 training poses with
+the library's kernels (trained here if absent).
 
-Prints one JSON line: Mpixels/s of the batched path, the plain single-view
-rate on the same poses, the roofline of the dominant kernel (stage times
-from HIP events recorded on the render stream) and the FP64 CPU oracle's
-rate on a bounded sample of the same frames.
+Prints one JSON line: Mpixels/s of the batched learned path (value) and, on
+the same poses, the batched threshold cut at tau = 1, the batched threshold
+cut at the tau whose PSNR loss matches the learned cut's, the plain
+single-view tau = 1 path, the PSNR loss against ground-truth images of the
+synthetic surfaces, the roofline of the dominant kernel (stage times from HIP
+events recorded on the render stream) and the FP64 CPU oracle's rate on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -25,7 +32,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Mpixels/s at 720p: batched learned-LOD vs plain cut at ≤0.1 dB PSNR loss"
-HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 # FP32 flops of one evaluated (pixel, Gaussian) pair in the compositor:
 # dx, dy (2), t1 (3), t2 (1), q (3), exponent scale (1), exp (1), alpha (1),
@@ -38,22 +44,24 @@ def log(*a):
 
 
 def parse():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--views", type=int, default=32, help="views per step")
-    ap.add_argument("--tau", type=float, default=1.0)
-    ap.add_argument("--scale", type=float, default=1.0, help="leaf-count multiplier (1 = 2M leaves)")
+    ap.add_argument("--views", type=int, default=50, help="views per step")
+    ap.add_argument("--poses", type=int, default=500, help="held-out poses cycled through")
+    ap.add_argument("--single", type=int, default=100, help="poses timed on the single-view path")
+    ap.add_argument("--model", default=None, help="learned-cut checkpoint (.npz)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels instead of replaying a graph")
     return ap.parse_args()
 
 
 def cpu_baseline(scene, cam, tau, budget_s):
     """The FP64 oracle on one frame: full cut and projection, then
-    compositing of random pixels until about budget_s of work; the frame
-    time is extrapolated from the per-pixel time."""
+    compositing of random pixels for about budget_s; the frame time is
+    extrapolated from the per-pixel time."""
     import numpy as np
     from oracle import oracle as O
     t0 = time.perf_counter()
@@ -73,12 +81,12 @@ def cpu_baseline(scene, cam, tau, budget_s):
         n = min(n * 2, 1 << 16)
     t_frame = t_fixed + t_pix * npx / done
     return {"value": npx / t_frame / 1e6, "unit": "Mpixels/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"1 frame 1280x720 tau={tau}: full cut ({ids.size} Gaussians) + projection "
-                      f"({t_fixed:.2f} s), {done} random pixels composited ({t_pix:.2f} s), "
-                      f"frame time extrapolated to {t_frame:.1f} s"}
+            "sample": f"1 frame 1280x720 (threshold cut tau={tau}): full cut ({ids.size} Gaussians) + projection "
+                      f"({t_fixed:.2f} s), {done} random pixels composited ({t_pix:.2f} s), frame time "
+                      f"extrapolated to {t_frame:.1f} s"}
 
 
-def traffic_entry(kernel, launches_per_step):
+def traffic_entry(kernel):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
     taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -90,127 +98,175 @@ def traffic_entry(kernel, launches_per_step):
     if not e:
         return None
     src = os.path.join(ROOT, "paper_2603_15186_amd", "csrc", e["source"])
-    h = hashlib.sha1(open(src, "rb").read()).hexdigest()
-    if h != e.get("source_sha1"):
+    if hashlib.sha1(open(src, "rb").read()).hexdigest() != e.get("source_sha1"):
         return None
     return e["bytes_per_launch"]
+
+
+def timed_loop(r, hgs, torch, batches, outs, steps, warmup, stage_timing):
+    """Render `steps` batches (cycling) after `warmup` untimed ones; returns
+    (ms per step, stats with stage sums)."""
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        r.set_cameras(batches[i % len(batches)])
+        r.render(outs)
+    r.set_option(hgs.HGS_OPT_SYNC_CHECK, 0)
+    if stage_timing:
+        r.set_option(hgs.HGS_OPT_STAGE_TIMING, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        r.set_cameras(batches[i % len(batches)])
+        r.render(outs, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if r.check() != hgs.HGS_OK:
+        raise RuntimeError("work buffers overflowed inside the timed region")
+    st = r.stats()
+    if stage_timing:
+        r.set_option(hgs.HGS_OPT_STAGE_TIMING, 0)
+    r.set_option(hgs.HGS_OPT_SYNC_CHECK, 1)
+    return (t1 - t0) * 1e3 / steps, st
 
 
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
-              "this renderer shards by view across GPUs with no exchange, and only the single-GPU "
-              "share is built and measured.", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: the "
+              "renderer shards by view across GPUs with no exchange, and only the single-GPU share is built "
+              "and measured.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_2603_15186_amd import hgs
+    from paper_2603_15186_amd import hgs, lod
     from paper_2603_15186_amd.synth import workloads as W
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     t = time.perf_counter()
-    scene, traj = W.plan2m(scale=args.scale, n_poses=200)
+    scene, train_cams, eval_cams, plan = W.plan2m_lod(with_plan=True)
+    eval_cams = eval_cams[:args.poses]
     log(f"scene: {scene.n} nodes, {scene.n_levels} levels ({time.perf_counter() - t:.1f} s)")
-    step = max(1, len(traj) // args.views)
-    views = [traj[(i * step) % len(traj)] for i in range(args.views)]
-    px_per_step = sum(c.width * c.height for c in views)
+    B = args.views
+    batches = [eval_cams[i:i + B] for i in range(0, len(eval_cams) - B + 1, B)]
+    px_per_step = B * eval_cams[0].width * eval_cams[0].height
 
     r = hgs.Renderer(0)
     r.load_scene(scene)
-    r.set_cameras(views)
-    r.set_lod(hgs.HGS_LOD_THRESHOLD, args.tau)
+    r.set_surfaces(plan.surfaces)
+    path = args.model or lod.default_model_path()
+    if os.path.exists(path):
+        model = lod.LodModel.load(path)
+        origin = os.path.relpath(path, ROOT)
+    else:
+        log("no checkpoint: training the learned cut ...")
+        model = lod.train_pipeline(r, train_cams, calib_n=64, per_view=256, epochs=40, seed=0, log=log)
+        origin = "trained in this run"
+    log(f"learned cut: p*={model.p_star}, s_hi={model.s_hi} ({origin})")
+
+    # quality on all held-out poses (untimed): PSNR against ground truth
+    refs = lod.reference_images(r, eval_cams)
+    base_psnr, base_cut, _ = lod.evaluate(r, eval_cams, refs, None, tau=1.0)
+    learn_psnr, learn_cut, _ = lod.evaluate(r, eval_cams, refs, model)
+    loss = base_psnr - learn_psnr
+    tau_m, loss_m, cut_m = lod.tau_matched(r, eval_cams, refs, base_psnr, max(loss, 0.0))
+    log(f"PSNR tau=1 {base_psnr:.3f} dB, learned {learn_psnr:.3f} dB (loss {loss:.3f} dB), "
+        f"cut {learn_cut / base_cut:.3f} of tau=1; matched tau {tau_m:.2f} (loss {loss_m:.3f}, cut "
+        f"{(cut_m or base_cut) / base_cut:.3f})")
+    del refs
+    torch.cuda.empty_cache()
+
+    r.set_cameras(batches[0])
     outs = r.alloc_outputs()
-    stream = torch.cuda.current_stream()
-
-    # untimed: algorithmic counts of one step
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
+    # algorithmic counts of one learned step (untimed)
+    model.install(r)
+    r.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
     r.set_option(hgs.HGS_OPT_COUNT_NALG, 1)
-    r.render(outs)
-    st = r.stats()
-    r.set_option(hgs.HGS_OPT_COUNT_NALG, 0)
-    log(f"per step: cut {st['cut_size']}, visible {st['visible']}, pairs {st['pairs']}, n_alg {st['n_alg']}")
-
-    # warmup (capacities settle), then the timed steps, asynchronous
-    for _ in range(args.warmup):
+    n_alg = 0
+    for bt in batches:
+        r.set_cameras(bt)
         r.render(outs)
+        n_alg += r.stats()["n_alg"]
+    n_alg_step = n_alg / len(batches)
+    r.set_option(hgs.HGS_OPT_COUNT_NALG, 0)
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
+
+    # batched learned cut: the headline value (stage timing needs eager launches)
+    ms_learn, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+    ms_learn_eager, st = timed_loop(r, hgs, torch, batches, outs, args.steps, 1, True)
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
+    value = px_per_step / (ms_learn * 1e-3) / 1e6
+    log(f"batched learned: {ms_learn:.3f} ms/step ({ms_learn_eager:.3f} eager), {value:.1f} Mpix/s")
+    n = st["timed_renders"]
+    stage = {k: st["ms_" + k] / n for k in ("cut", "project", "sort", "composite")}
+
+    # batched threshold cuts
+    r.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
+    ms_t1, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
+    r.set_lod(hgs.HGS_LOD_THRESHOLD, tau_m)
+    ms_tm, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
+
+    # plain single-view path, tau = 1
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+    r.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
+    single = eval_cams[:args.single]
+    r.set_cameras([single[0]])
+    o1 = r.alloc_outputs()
+    stream = torch.cuda.current_stream()
+    r.render(o1)
     r.set_option(hgs.HGS_OPT_SYNC_CHECK, 0)
-    r.set_option(hgs.HGS_OPT_STAGE_TIMING, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r.render(outs, stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if r.check() != hgs.HGS_OK:
-        raise RuntimeError("work buffers overflowed inside the timed region")
-    times = r.stats()
-    r.set_option(hgs.HGS_OPT_STAGE_TIMING, 0)
-    r.set_option(hgs.HGS_OPT_SYNC_CHECK, 1)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = px_per_step / (ms_step * 1e-3) / 1e6
-    log(f"batched: {ms_step:.3f} ms/step, {value:.1f} Mpix/s")
-
-    # plain single-view path on the same poses
-    single_ms = 0.0
-    r.set_option(hgs.HGS_OPT_SYNC_CHECK, 0)
-    for c in views:
+    for c in single:
         r.set_cameras([c])
-        o = r.alloc_outputs()
-        r.render(o, stream)           # warm
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 3
-        e0.record(stream)
-        for _ in range(reps):
-            r.render(o, stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        if r.check() != hgs.HGS_OK:
-            raise RuntimeError("overflow in single-view timing")
-        single_ms += e0.elapsed_time(e1) / reps
+        r.render(o1, stream)
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t0) * 1e3 / len(single)
+    if r.check() != hgs.HGS_OK:
+        raise RuntimeError("overflow in single-view timing")
     r.set_option(hgs.HGS_OPT_SYNC_CHECK, 1)
-    single = px_per_step / (single_ms * 1e-3) / 1e6
-    log(f"single-view: {single_ms:.3f} ms for {len(views)} views, {single:.1f} Mpix/s")
+    px1 = single[0].width * single[0].height
+    mpix = lambda ms, px: px / (ms * 1e-3) / 1e6  # noqa: E731
 
-    n = times["timed_renders"]
-    stage = {k: times["ms_" + k] / n for k in ("cut", "project", "sort", "composite")}
     comp_ms = stage["composite"]
-    achieved = FLOPS_PER_PAIR * st["n_alg"] / (comp_ms * 1e-3) / 1e12
-    traffic = traffic_entry("composite", 1)
+    achieved = FLOPS_PER_PAIR * n_alg_step / (comp_ms * 1e-3) / 1e12
     roof = {"kernel": "k_composite", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
-            "ms_per_launch": comp_ms, "n_alg_per_launch": st["n_alg"], "flops_per_pair": FLOPS_PER_PAIR}
-    # HBM view of the binning stage (depth sort, emission, tile sort, ranges):
-    # minimum bytes = 16 B per cut entry per depth pass (4 passes) + 20 B per
-    # pair emitted (scan read 8 B/entry amortised) + 16 B per pair per tile
-    # pass + 8 B per pair for ranges.
-    tile_passes = (max(1, int(np.ceil(np.log2(max(2, sum((c.width + 15) // 16 * ((c.height + 15) // 16)
-                                                          for c in views)))))) + 7) // 8
-    sort_bytes = st["cut_size"] * (16 * 4 + 8) + st["pairs"] * (8 + 16 * tile_passes + 8)
+            "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic_entry("composite"),
+            "ms_per_launch": comp_ms, "n_alg_per_launch": n_alg_step, "flops_per_pair": FLOPS_PER_PAIR}
     extra = {
-        "plain_single_view_mpix_s": single,
-        "batched_over_single": value / single,
-        "stage_ms_per_step": stage,
-        "binning_gbs": sort_bytes / (stage["sort"] * 1e-3) / 1e9,
-        "cut_size_per_step": st["cut_size"], "pairs_per_step": st["pairs"], "n_alg_per_step": st["n_alg"],
+        "batched_threshold_tau1_mpix_s": mpix(ms_t1, px_per_step),
+        "batched_threshold_matched_mpix_s": mpix(ms_tm, px_per_step),
+        "matched_tau": tau_m, "matched_tau_loss_db": loss_m,
+        "plain_single_view_tau1_mpix_s": mpix(ms_single, px1),
+        "speedup_vs_plain_single_view": value / mpix(ms_single, px1),
+        "speedup_vs_batched_threshold_tau1": value / mpix(ms_t1, px_per_step),
+        "psnr_tau1_db": base_psnr, "psnr_learned_db": learn_psnr, "psnr_loss_db": loss,
+        "psnr_reference": "ray-cast ground truth of the synthetic surfaces, 3x3 supersampled",
+        "cut_learned_over_tau1": learn_cut / base_cut,
+        "learned_p_star": model.p_star, "learned_s_hi": model.s_hi, "learned_model": origin,
+        "stage_ms_per_step_eager": stage, "ms_per_step_eager": ms_learn_eager, "graph": not args.no_graph,
+        "n_alg_per_step": n_alg_step, "held_out_poses": len(eval_cams),
     }
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         from oracle import oracle as O
-        sizes = [O.cut(scene, c, O.MODE_THRESHOLD, args.tau).size for c in views]
-        med = views[int(np.argsort(sizes)[len(sizes) // 2])]
-        cpu = cpu_baseline(scene, med, args.tau, args.cpu_seconds)
+        sizes = [O.cut(scene, c, O.MODE_THRESHOLD, 1.0).size for c in batches[0]]
+        med = batches[0][int(np.argsort(sizes)[len(sizes) // 2])]
+        cpu = cpu_baseline(scene, med, 1.0, args.cpu_seconds)
     out = {
         "metric": METRIC, "value": value, "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": ms_learn, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "plan2m-720p-batched", "leaves": int(scene.child_count.size - np.count_nonzero(scene.child_count)),
-                   "nodes": scene.n, "views_per_step": len(views), "resolution": "1280x720", "fx": 900,
-                   "lod": f"threshold tau={args.tau}px", "parallelism": "single GPU"},
+        "config": {"workload": "plan2m-lod 1280x720 held-out poses, batched learned LOD cut",
+                   "leaves": int(np.count_nonzero(scene.child_count == 0)), "nodes": scene.n,
+                   "views_per_step": B, "resolution": "1280x720", "fx": 900,
+                   "lod": f"learned (p*={model.p_star}, s_hi={model.s_hi}px, threshold tau=1 fallback)",
+                   "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -56,7 +56,9 @@ typedef int32_t hgs_status;
 #define HGS_OPT_AUTO_REGROW 2     /* 1 (default): regrow and re-render on overflow */
 #define HGS_OPT_COUNT_NALG 3      /* 1: count evaluated (pixel, Gaussian) pairs */
 #define HGS_OPT_BATCH_DEPTH 4     /* Gaussians staged in LDS per batch: 64..256 */
-#define HGS_OPT_USE_GRAPH 5       /* 1: capture the render in a hipGraph and replay */
+#define HGS_OPT_USE_GRAPH 5       /* 1: capture the render in a hipGraph on first use and
+                                     replay it while cameras, LOD, options, scene and
+                                     buffers are unchanged (not with stage timing) */
 #define HGS_OPT_PERSISTENT 6      /* 1: composite with a persistent tile queue */
 #define HGS_OPT_EXACT_TILES 7     /* 1 (default): bin only tiles the ellipse reaches */
 #define HGS_OPT_INITIAL_CAPACITY 8 /* >0: restart work buffers at this many entries
@@ -134,6 +136,7 @@ typedef struct {
     int64_t tiles;                /* tiles composited */
     int64_t regrows;              /* buffer regrowths during the last render */
     int64_t timed_renders;        /* renders summed in the ms_* fields */
+    int64_t graph_launches;       /* renders replayed from a captured graph */
     double ms_cut, ms_project, ms_sort, ms_composite, ms_total;
 } hgs_stats;
 

@@ -65,6 +65,13 @@ struct hgs_ctx {
     int64_t regrows = 0;
     uint32_t forced_cap = 0;          // test hook: start from this capacity
     int sort_digit_bits = 8;          // widest radix digit
+    // captured render (HGS_OPT_USE_GRAPH): recorded on cap_stream, replayed
+    // on the caller's stream while nothing it depends on has changed
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_valid = false;
+    int64_t graph_launches = 0;
     // stage timing: 6 events per render (start, cut, project, binning, composite start, end)
     bool stage_timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -99,9 +106,18 @@ void release(DevMem& m) {
     m.bytes = 0;
 }
 
+void invalidate_graph(hgs_ctx* c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_valid = false;
+}
+
 hgs_status ensure(hgs_ctx* c, DevMem& m, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (m.bytes >= bytes) return HGS_OK;
+    invalidate_graph(c);     // a captured render holds the old address
     release(m);
     hipError_t e = hipMalloc(&m.p, bytes);
     if (e != hipSuccess) {
@@ -492,6 +508,8 @@ void hgs_destroy(hgs_ctx* c) {
     if (c->ctr_host) (void)hipHostFree(c->ctr_host);
     if (c->views_copied) (void)hipEventDestroy(c->views_copied);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    invalidate_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }
 
@@ -603,6 +621,7 @@ hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarch
     release(c->parent); release(c->nodefeat); release(c->lvl);
     c->geo = ngeo; c->sh = nsh; c->bound = nbound; c->child = nchild; c->leaf_ids = nleaf;
     c->parent = nparent; c->nodefeat = nfeat; c->lvl = nlvl;
+    invalidate_graph(c);
     c->hier = h != nullptr;
     c->n = n;
     c->sh_degree = g->sh_degree;
@@ -642,6 +661,12 @@ hgs_status hgs_set_cameras(hgs_ctx* c, int32_t n, const hgs_camera* cams) {
         tiles += (uint64_t)((cams[v].width + kTile - 1) / kTile) * ((cams[v].height + kTile - 1) / kTile);
     }
     if (tiles >= (1ull << 31)) return fail(c, HGS_E_UNSUPPORTED, "too many tiles");
+    // same view count and image sizes as before: the tile layout, its device
+    // table and a captured render stay valid (camera poses live in device
+    // memory uploaded before each render)
+    bool same_layout = (int)c->cams.size() == n;
+    for (int v = 0; same_layout && v < n; ++v)
+        same_layout = c->cams[v].width == cams[v].width && c->cams[v].height == cams[v].height;
     hgs_status s;
     if ((s = ensure(c, c->views, sizeof(ViewDev) * n)) || (s = ensure(c, c->tile_view, tiles * 4)) ||
         (s = ensure(c, c->ranges, tiles * sizeof(uint2))))
@@ -695,7 +720,10 @@ hgs_status hgs_set_cameras(hgs_ctx* c, int32_t n, const hgs_camera* cams) {
         const uint32_t nt = (uint32_t)(d.tiles_x * d.tiles_y);
         for (uint32_t t = 0; t < nt; ++t) tv[tile_base[v] + t] = (uint32_t)v;
     }
-    HIP_TRY(c, hipMemcpy(c->tile_view.p, tv.data(), tiles * 4, hipMemcpyHostToDevice));
+    if (!same_layout) {
+        HIP_TRY(c, hipMemcpy(c->tile_view.p, tv.data(), tiles * 4, hipMemcpyHostToDevice));
+        invalidate_graph(c);
+    }
     c->cams.assign(cams, cams + n);
     c->total_tiles = (uint32_t)tiles;
     c->views_dirty = true;
@@ -712,6 +740,7 @@ hgs_status hgs_set_lod(hgs_ctx* c, int32_t mode, float tau) {
     if (mode < HGS_LOD_ALL_LEAVES || mode > HGS_LOD_LEARNED) return fail(c, HGS_E_INVALID, "unknown LOD mode %d", mode);
     if (!(tau > 0.f) || !finite(tau)) return fail(c, HGS_E_INVALID, "tau must be a positive number");
     if (mode == HGS_LOD_LEARNED && !c->mlp_loaded) return fail(c, HGS_E_STATE, "learned LOD needs hgs_load_lod_mlp first");
+    invalidate_graph(c);
     c->lod_mode = mode;
     c->tau = tau;
     if (c->views_host) HIP_TRY(c, hipEventSynchronize(c->views_copied));
@@ -722,6 +751,7 @@ hgs_status hgs_set_lod(hgs_ctx* c, int32_t mode, float tau) {
 
 hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
     if (!c) return HGS_E_INVALID;
+    invalidate_graph(c);
     switch (opt) {
         case HGS_OPT_SYNC_CHECK: c->sync_check = val != 0; return HGS_OK;
         case HGS_OPT_AUTO_REGROW: c->auto_regrow = val != 0; return HGS_OK;
@@ -782,7 +812,24 @@ hgs_status hgs_render(hgs_ctx* c, void* stream, const hgs_output* outs) {
     if ((st = upload_views(c, s, outs))) return st;
     c->regrows = 0;
     for (int attempt = 0; attempt < 8; ++attempt) {
-        enqueue_render(c, s);
+        if (c->use_graph && !c->stage_timing) {
+            if (!c->graph_valid) {
+                invalidate_graph(c);
+                if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                enqueue_render(c, c->cap_stream);
+                hipGraph_t g = nullptr;
+                const hipError_t ce = hipStreamEndCapture(c->cap_stream, &g);
+                if (ce != hipSuccess) return fail(c, HGS_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+                c->graph = g;
+                HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+                c->graph_valid = true;
+            }
+            HIP_TRY(c, hipGraphLaunch(c->gexec, s));
+            ++c->graph_launches;
+        } else {
+            enqueue_render(c, s);
+        }
         HIP_TRY(c, hipGetLastError());
         c->last_valid = true;
         if (!c->sync_check) return HGS_OK;
@@ -884,6 +931,7 @@ hgs_status hgs_get_stats(hgs_ctx* c, hgs_stats* out) {
     hgs_status s = harvest_events(c);
     if (s) return s;
     out->timed_renders = c->acc_n;
+    out->graph_launches = c->graph_launches;
     out->ms_cut = c->acc_ms[0];
     out->ms_project = c->acc_ms[1];
     out->ms_sort = c->acc_ms[2];
@@ -1029,6 +1077,7 @@ hgs_status hgs_load_lod_mlp(hgs_ctx* c, const uint16_t* bf16, const float* mean,
     m.p_star = p_star;
     m.s_hi = s_hi;
     HIP_TRY(c, hipMemcpy(c->mlp_dev.p, &m, sizeof(LodMlpDev), hipMemcpyHostToDevice));
+    invalidate_graph(c);
     c->mlp_host = m;
     c->s_hi = s_hi;
     c->mlp_loaded = true;

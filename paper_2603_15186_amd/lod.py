@@ -184,7 +184,9 @@ def make_labels(r: hgs.Renderer, cams, per_view=256, seed=0, chunk=8, s_hi=S_HI,
 
 def train(r: hgs.Renderer, feats, labels, epochs=40, batch=4096, lr=3e-3, seed=0, log=None):
     """Adam on the FP32 masters with the library's train-step kernels.
-    Returns (master, bf16 bits, mean, std, per-epoch mean loss)."""
+    Batches are class-balanced (half "refine", half "keep", positives drawn
+    with replacement) because refinement labels are rare.  Returns (master,
+    bf16 bits, mean, std, per-epoch mean loss)."""
     import torch
     dev = feats.device
     ms = r.feature_stats(feats).cpu().numpy()
@@ -196,23 +198,29 @@ def train(r: hgs.Renderer, feats, labels, epochs=40, batch=4096, lr=3e-3, seed=0
     v = torch.zeros_like(master)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     rng = np.random.default_rng(seed + 1)
+    lab = labels.cpu().numpy()
+    pos = np.nonzero(lab > 0.5)[0]
+    neg = np.nonzero(lab <= 0.5)[0]
     n = feats.shape[0]
+    steps_per_epoch = max(1, n // batch)
     step, hist = 0, []
     for ep in range(epochs):
-        perm = torch.from_numpy(rng.permutation(n)).to(dev)
-        tot, cnt = 0.0, 0
-        for b in range(0, n, batch):
-            idx = perm[b:b + batch]
-            if idx.numel() < 2:
-                continue
+        tot = 0.0
+        for _ in range(steps_per_epoch):
+            if pos.size and neg.size:
+                half = batch // 2
+                idx = np.concatenate([rng.choice(pos, half, replace=True),
+                                      rng.choice(neg, batch - half, replace=neg.size < batch - half)])
+            else:
+                idx = rng.choice(n, min(batch, n), replace=False)
+            idx = torch.from_numpy(np.sort(idx)).to(dev)
             step += 1
             r.mlp_train_step(feats[idx].contiguous(), labels[idx].contiguous(), mean, std, master, w, m, v, step, lr,
                              loss_out=loss)
-            tot += float(loss.item()) * idx.numel()
-            cnt += idx.numel()
-        hist.append(tot / max(cnt, 1))
+            tot += float(loss.item())
+        hist.append(tot / steps_per_epoch)
         if log and (ep % 10 == 0 or ep == epochs - 1):
-            log(f"epoch {ep}: loss {hist[-1]:.4f}")
+            log(f"epoch {ep}: balanced loss {hist[-1]:.4f}")
     return master.cpu().numpy(), w.cpu().numpy().view(np.uint16), mean, std, hist
 
 
@@ -237,15 +245,20 @@ def evaluate(r: hgs.Renderer, cams, refs, model: LodModel | None = None, p_star=
     return float(ps.mean()), cuts, ps
 
 
-def calibrate(r: hgs.Renderer, model: LodModel, cams, refs, base_psnr, target=TARGET_TRAIN_DB,
-              grid=(0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.1, 0.05)):
-    """Largest p_star whose PSNR loss on cams is within target; 0 (always
-    refine: the threshold cut) when none is."""
+P_GRID = (0.95, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.1, 0.05, 0.02, 0.01)
+
+
+def calibrate(r: hgs.Renderer, model: LodModel, cams, refs, base_psnr, target=TARGET_TRAIN_DB, grid=P_GRID):
+    """Largest p_star (refine iff P(refine) >= p_star) whose PSNR loss on
+    cams is within target; 0 (always refine: the threshold cut) when none
+    is.  Returns (p_star, loss, table of (p, loss, cut size))."""
+    table = []
     for p in grid:
-        mp, _, _ = evaluate(r, cams, refs, model, p_star=p)
+        mp, cut, _ = evaluate(r, cams, refs, model, p_star=p)
+        table.append((p, base_psnr - mp, cut))
         if base_psnr - mp <= target:
-            return p, base_psnr - mp
-    return 0.0, 0.0
+            return p, base_psnr - mp, table
+    return 0.0, 0.0, table
 
 
 def train_pipeline(r: hgs.Renderer, train_cams, calib_n=64, per_view=256, epochs=40, seed=0, log=None,
@@ -261,10 +274,12 @@ def train_pipeline(r: hgs.Renderer, train_cams, calib_n=64, per_view=256, epochs
     ccams = train_cams[::step][:calib_n]
     crefs = reference_images(r, ccams)
     base, _, _ = evaluate(r, ccams, crefs, None, tau=1.0)
-    p, loss = calibrate(r, model, ccams, crefs, base)
+    p, loss, table = calibrate(r, model, ccams, crefs, base)
     model.p_star = p
     model.info.update({"calib_loss_db": loss, "calib_views": len(ccams)})
     if log:
+        for row in table:
+            log("  p* %.3f: loss %.3f dB, cut %d" % row)
         log(f"calibrated p* = {p} (training-pose loss {loss:.3f} dB)")
     return model
 
@@ -274,3 +289,52 @@ MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
 
 def default_model_path(name="plan2m_lod_mlp.npz"):
     return os.path.join(MODEL_DIR, name)
+
+
+def tau_matched(r: hgs.Renderer, cams, refs, base_psnr, loss_db, lo=1.0, hi=256.0, iters=10):
+    """Largest threshold tau whose PSNR loss on cams stays within loss_db
+    (bisection on log tau).  Returns (tau, loss, cut size)."""
+    best = (lo, 0.0, None)
+    a, b = math.log(lo), math.log(hi)
+    for _ in range(iters):
+        mid = math.exp(0.5 * (a + b))
+        mp, cut, _ = evaluate(r, cams, refs, None, tau=mid)
+        if base_psnr - mp <= loss_db:
+            best = (mid, base_psnr - mp, cut)
+            a = math.log(mid)
+        else:
+            b = math.log(mid)
+    return best
+
+
+def main(argv=None):
+    """Train the learned cut of the 2M-leaf floor plan on its 2,000 training
+    poses and save it: python -m paper_2603_15186_amd.lod --out PATH."""
+    import argparse
+    import time
+    from .synth import workloads as W
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--out", default=default_model_path())
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--per-view", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--calib", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+    t0 = time.time()
+    scene, train_cams, _, plan = W.plan2m_lod(with_plan=True)
+    r = hgs.Renderer(0)
+    r.load_scene(scene)
+    r.set_surfaces(plan.surfaces)
+    model = train_pipeline(r, train_cams[:args.train], calib_n=args.calib, per_view=args.per_view,
+                           epochs=args.epochs, seed=args.seed, log=lambda *a: print(*a, flush=True))
+    model.info["train_views"] = min(args.train, len(train_cams))
+    model.info["seconds"] = time.time() - t0
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    model.save(args.out)
+    print("saved", args.out, model.p_star, model.info, flush=True)
+    r.close()
+
+
+if __name__ == "__main__":
+    main()

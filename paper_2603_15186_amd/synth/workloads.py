@@ -78,12 +78,13 @@ def _cams(pos, yaw, W, H, f):
     return [yaw_camera(W, H, f, p, y) for p, y in zip(pos, yaw)]
 
 
-def plan2m(scale=1.0, n_poses=200, use_cache=True):
+def plan2m(scale=1.0, n_poses=200, use_cache=True, with_plan=False):
     n = int(round(2_000_000 * scale))
     scene, plan = floorplan_scene(n, (20.0, 15.0), 1, seed=1, use_cache=use_cache)
     fs = FreeSpace(plan, 0)
     pos, yaw = trajectory(fs, n_poses, seed=101, height=1.2)
-    return scene, _cams(pos, yaw, 1280, 720, 900.0)
+    out = (scene, _cams(pos, yaw, 1280, 720, 900.0))
+    return out + (plan,) if with_plan else out
 
 
 def plan8m_views(plan, n_views=(128, 96, 32), seed=102):

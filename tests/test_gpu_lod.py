@@ -109,8 +109,8 @@ def test_feature_stats_and_image_helpers(R):
 
 @pytest.fixture(scope="module")
 def plan():
-    scene, cams = W.plan2m(scale=0.05, n_poses=12)
-    return scene, cams
+    scene, cams, fp = W.plan2m(scale=0.05, n_poses=12, with_plan=True)
+    return scene, cams, fp
 
 
 def _sizes(scene, cam):
@@ -124,7 +124,7 @@ def _sizes(scene, cam):
 
 
 def test_candidates_are_the_refined_nodes_in_the_band(R, plan):
-    scene, cams = plan
+    scene, cams, _ = plan
     from paper_2603_15186_amd import hgs
     R.load_scene(scene)
     R.set_cameras(cams[:4])
@@ -154,7 +154,7 @@ def test_candidates_are_the_refined_nodes_in_the_band(R, plan):
 
 
 def test_keep_node_collapses_one_subtree(R, plan):
-    scene, cams = plan
+    scene, cams, _ = plan
     from paper_2603_15186_amd import hgs
     R.load_scene(scene)
     R.set_cameras(cams[:6])
@@ -184,7 +184,7 @@ def test_learned_cut_fallback_and_band(R, plan):
     """p* = 0 refines every candidate: the threshold cut, bit for bit; with
     p* = 1 the learned cut is a coarsening of the threshold cut that only
     keeps candidates."""
-    scene, cams = plan
+    scene, cams, _ = plan
     from paper_2603_15186_amd import hgs
     R.load_scene(scene)
     with pytest.raises(hgs.HgsError) as ei:
@@ -221,9 +221,10 @@ def test_training_pipeline_end_to_end(R, plan):
     """Labels from collapsed-window renders, training with the library's
     kernels, calibration: the training loss falls and the calibrated cut
     stays within the training-pose budget."""
-    scene, cams = plan
+    scene, cams, fp = plan
     from paper_2603_15186_amd import lod
     R.load_scene(scene)
+    R.set_surfaces(fp.surfaces)
     model = lod.train_pipeline(R, cams[:10], calib_n=4, per_view=128, epochs=15, seed=0, s_hi=256.0)
     assert model.info["samples"] > 100
     assert 0.0 <= model.p_star <= 0.9
@@ -235,7 +236,7 @@ def test_surface_ground_truth_matches_a_plain_ray_caster(R):
     kernel against a numpy ray caster of the same definition."""
     from paper_2603_15186_amd.synth import SURFACE_DTYPE, yaw_camera
     surf = np.zeros(2, SURFACE_DTYPE)
-    surf[0] = (0, 3, (-0.7, 2.0, -0.4), (1.1, 0.0, 0.0), (0.0, 0.0, 0.9), (0.8, 0.5, 0.3), 0.0, 0.0)
+    surf[0] = (0, 3, (-0.7, 2.0, -0.4), (1.1, 0.0, 0.0), (0.0, 0.0, 0.93), (0.8, 0.5, 0.3), 0.0, 0.0)
     surf[1] = (2, 0, (0.3, 3.0, 0.1), (0, 0, 0), (0, 0, 0), (0.1, 0.9, 0.2), 0.6, 0.0)
     cam = yaw_camera(40, 30, 30.0, (0.0, 0.0, 0.05), math.pi / 2, bg=(0.2, 0.2, 0.6))
     R.set_cameras([cam])
@@ -269,5 +270,7 @@ def test_surface_ground_truth_matches_a_plain_ray_caster(R):
             want[:, j, i] = acc / 4
     # single-precision ray casting: a sample on an edge may flip
     diff = np.abs(got - want)
-    assert (diff.max(axis=0) > 1e-4).mean() < 0.01
+    bad = diff.max(axis=0) > 1e-4
+    assert bad.mean() < 0.01, (bad.sum(), np.argwhere(bad)[:5].tolist(), got[:, bad][:, :5].T.tolist(),
+                               want[:, bad][:, :5].T.tolist())
     assert np.median(diff) < 1e-6

@@ -273,3 +273,35 @@ def test_plan2m_sampled_pixel_parity(R, plan_full):
         print(i, msg, flush=True)
         assert ok.all(), msg
         assert skipped.mean() <= 0.002, msg
+
+
+def test_graph_replays_match_eager_render(R, plan_small):
+    """The render captured in a hipGraph and replayed several times, with
+    eager work and synchronisations between replays, gives the eager
+    result every time; changing the LOD threshold re-captures."""
+    scene, cams = plan_small
+    hgs = _hgs()
+    views = [_small_cam(cams[1], 320, 240), _small_cam(cams[6], 200, 117), cams[8]]
+    ref = _render(R, scene, views, tau=1.0, use_graph=0)
+    outs = R.alloc_outputs()
+    R.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
+    side = torch.arange(100000, dtype=torch.int32, device="cuda")
+    for rep in range(5):
+        R.render(outs)
+        torch.cuda.synchronize()
+        for v in range(len(views)):
+            for a, b in zip(ref[v], outs[v]):
+                assert np.array_equal(a, b.cpu().numpy()), (rep, v)
+        # eager work between replays: a sort and a torch op
+        k = (side * 7919 % 1000).contiguous()
+        R.sort_pairs(k, side.clone(), 10)
+        side = side + 1
+        torch.cuda.synchronize()
+    assert R.stats()["graph_launches"] >= 5
+    R.set_lod(hgs.HGS_LOD_THRESHOLD, 8.0)
+    R.render(outs)
+    torch.cuda.synchronize()
+    ref8 = _render(R, scene, views, tau=8.0, use_graph=0)
+    for v in range(len(views)):
+        for a, b in zip(ref8[v], outs[v]):
+            assert np.array_equal(a, b.cpu().numpy()), v
