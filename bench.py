@@ -37,6 +37,7 @@ FP32_PEAK_TFLOPS = 157.3
 # dx, dy (2), t1 (3), t2 (1), q (3), exponent scale (1), exp (1), alpha (1),
 # cap (1), T' (2), weight (1), three colour and one depth FMA (8).
 FLOPS_PER_PAIR = 24
+TRAFFIC_FILE = "composite_traffic_plan2m_lod_50x720p.txt"
 
 
 def log(*a):
@@ -55,6 +56,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels instead of replaying a graph")
+    ap.add_argument("--workload", default="plan2m-lod", choices=["plan2m-lod", "plan8m"],
+                    help="plan2m-lod (the metric's workload) or plan8m (256 mixed-resolution views of the "
+                         "8M-leaf plan, threshold cuts; reported for reference)")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed batched learned path (for profilers): no quality evaluation, no "
                          "threshold or single-view comparison")
@@ -90,20 +94,25 @@ def cpu_baseline(scene, cam, tau, budget_s):
 
 
 def traffic_entry(kernel):
-    """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
+    e = {}
     with open(path) as f:
-        t = json.load(f)
-    e = t.get(kernel)
-    if not e:
+        for line in f:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            e[k.strip()] = v.strip()
+    if e.get("kernel") != kernel:
         return None
     src = os.path.join(ROOT, "paper_2603_15186_amd", "csrc", e["source"])
     if hashlib.sha1(open(src, "rb").read()).hexdigest() != e.get("source_sha1"):
         return None
-    return e["bytes_per_launch"]
+    return int(e["bytes_per_launch"])
 
 
 def timed_loop(r, hgs, torch, batches, outs, steps, warmup, stage_timing):
@@ -132,8 +141,47 @@ def timed_loop(r, hgs, torch, batches, outs, steps, warmup, stage_timing):
     return (t1 - t0) * 1e3 / steps, st
 
 
+def run_plan8m(args):
+    """256 views (128 @ 320x240, 96 @ 640x480, 32 @ 1280x720) of the
+    8M-leaf 40 x 30 m plan in one call, threshold cuts at tau 1, 2, 4."""
+    import torch
+    from paper_2603_15186_amd import hgs
+    from paper_2603_15186_amd.synth import workloads as W
+    t = time.perf_counter()
+    scene, views = W.plan8m()
+    log(f"plan8m: {scene.n} nodes, {len(views)} views ({time.perf_counter() - t:.1f} s)")
+    r = hgs.Renderer(0)
+    r.load_scene(scene)
+    r.set_cameras(views)
+    outs = r.alloc_outputs()
+    px = sum(c.width * c.height for c in views)
+    res = {}
+    for tau in (1.0, 2.0, 4.0):
+        r.set_lod(hgs.HGS_LOD_THRESHOLD, tau)
+        r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
+        ms, _ = timed_loop(r, hgs, torch, [views], outs, args.steps, args.warmup, False)
+        r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+        _, st = timed_loop(r, hgs, torch, [views], outs, 3, 1, True)
+        n = st["timed_renders"]
+        res[f"tau{tau:g}"] = {"ms_per_batch": ms, "mpix_s": px / (ms * 1e-3) / 1e6, "cut": st["cut_size"],
+                               "pairs": st["pairs"], "passes": st["passes"],
+                               "stage_ms": {k: st["ms_" + k] / n for k in ("cut", "project", "sort", "composite")}}
+        log(f"tau={tau}: {ms:.2f} ms per batch, {res[f'tau{tau:g}']['mpix_s']:.0f} Mpix/s")
+    out = {"metric": "Mpixels/s, 256 mixed-resolution views of the 8M-leaf plan in one call",
+           "value": res["tau1"]["mpix_s"], "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res["tau1"]["ms_per_batch"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "plan8m 256 views (128@320x240, 96@640x480, 32@1280x720), threshold tau=1",
+                      "nodes": scene.n, "pixels_per_batch": px, "parallelism": "single GPU"},
+           "extra": res}
+    print(json.dumps(out), flush=True)
+    r.close()
+
+
 def main():
     args = parse()
+    if args.workload == "plan8m":
+        return run_plan8m(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: the "
@@ -268,6 +316,7 @@ def main():
         "learned_p_star": model.p_star, "learned_s_hi": model.s_hi, "learned_model": origin,
         "stage_ms_per_step_eager": stage, "ms_per_step_eager": ms_learn_eager, "graph": not args.no_graph,
         "n_alg_per_step": n_alg_step, "held_out_poses": len(eval_cams),
+        "cut_entries_per_step": st["cut_size"], "visible_per_step": st["visible"], "pairs_per_step": st["pairs"],
     }
     cpu = None
     if not args.no_cpu_baseline:

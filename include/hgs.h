@@ -55,7 +55,7 @@ typedef int32_t hgs_status;
                                      call hgs_check() after synchronising */
 #define HGS_OPT_AUTO_REGROW 2     /* 1 (default): regrow and re-render on overflow */
 #define HGS_OPT_COUNT_NALG 3      /* 1: count evaluated (pixel, Gaussian) pairs */
-#define HGS_OPT_BATCH_DEPTH 4     /* Gaussians staged in LDS per batch: 64..256 */
+#define HGS_OPT_BATCH_DEPTH 4     /* Gaussians staged in LDS per batch: 64, 128 or 256 */
 #define HGS_OPT_USE_GRAPH 5       /* 1: capture the render in a hipGraph on first use and
                                      replay it while cameras, LOD, options, scene and
                                      buffers are unchanged (not with stage timing) */
@@ -67,6 +67,11 @@ typedef int32_t hgs_status;
                                      on its stream; setting it clears the sums */
 #define HGS_OPT_SORT_DIGIT_BITS 10 /* widest radix digit, 6..11 (default 8); any
                                      value gives the same order */
+#define HGS_OPT_PASS_VIEWS 11     /* >0: render at most this many views per pipeline
+                                     pass; 0 (default): one pass, split by the
+                                     renderer itself when a pass would outgrow
+                                     the 2^28-entry index space.  Images do not
+                                     depend on the passes. */
 
 typedef struct hgs_ctx hgs_ctx;
 
@@ -138,6 +143,7 @@ typedef struct {
     int64_t timed_renders;        /* renders summed in the ms_* fields */
     int64_t graph_launches;       /* renders replayed from a captured graph */
     double ms_cut, ms_project, ms_sort, ms_composite, ms_total;
+    int64_t passes;               /* pipeline passes of the last render */
 } hgs_stats;
 
 /* Create a context on HIP device `device`.  *out is set on success. */
@@ -184,7 +190,9 @@ hgs_status hgs_render(hgs_ctx* ctx, void* stream, const hgs_output* outs);
 hgs_status hgs_check(hgs_ctx* ctx);
 
 /* Ascending node ids of view `view`'s cut from the last render.  Writes
- * min(count, cap) ids to host_ids and the full count to *count. */
+ * min(count, cap) ids to host_ids and the full count to *count.  When the
+ * batch ran in several passes only views of the last pass are available
+ * (HGS_E_STATE otherwise); the same holds for hgs_get_projected. */
 hgs_status hgs_get_cut(hgs_ctx* ctx, int32_t view, int32_t* host_ids, int64_t cap,
                        int64_t* count);
 

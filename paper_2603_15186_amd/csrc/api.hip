@@ -44,6 +44,13 @@ struct hgs_ctx {
     uint32_t total_tiles = 0;
     hipEvent_t views_copied = nullptr;
     bool views_dirty = true;
+    // passes: a batch runs as consecutive groups of views, one pipeline pass
+    // per group, when a single pass would not fit the entry index space (or
+    // the caller caps the views per pass); every buffer is reused per pass
+    std::vector<uint32_t> tile_abs;   // tile offset of each view in the batch
+    std::vector<int> pass_v0;         // first view of each pass, then the view count
+    int pass_views = 0;               // HGS_OPT_PASS_VIEWS (0: no cap)
+    int want_passes = 1;
     // lod
     int lod_mode = HGS_LOD_THRESHOLD;
     float tau = 1.0f;
@@ -58,7 +65,7 @@ struct hgs_ctx {
     RenderOpts ropts;
     // work buffers
     uint32_t frontier_cap = 0, cut_cap = 0, pair_cap = 0;
-    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, rect, offsets;
+    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, rect, offsets, dec;
     DevMem pkey[2], pval[2], ranges, scan_tmp, hist, counters;
     Counters* ctr_host = nullptr;     // pinned
     bool last_valid = false;
@@ -232,6 +239,7 @@ hgs_status alloc_work(hgs_ctx* c) {
     const size_t F = c->frontier_cap, M = c->cut_cap, Pc = c->pair_cap;
     for (int i = 0; i < 2; ++i)
         if ((s = ensure(c, c->frontier[i], F * sizeof(uint2)))) return s;
+    if ((s = ensure(c, c->dec, F))) return s;
     if ((s = ensure(c, c->cut, M * sizeof(uint2)))) return s;
     if ((s = ensure(c, c->proj, M * sizeof(Proj)))) return s;
     for (int i = 0; i < 2; ++i) {
@@ -304,7 +312,6 @@ hgs_status harvest_events(hgs_ctx* c) {
         HIP_TRY(c, hipEventElapsedTime(&t[3], c->ev_pool[b + 4], c->ev_pool[b + 5]));
         HIP_TRY(c, hipEventElapsedTime(&t[4], c->ev_pool[b], c->ev_pool[b + 5]));
         for (int i = 0; i < 5; ++i) c->acc_ms[i] += t[i];
-        ++c->acc_n;
     }
     c->ev_used = 0;
     return HGS_OK;
@@ -327,8 +334,64 @@ void mark(hgs_ctx* c, int k, hipStream_t s) {
     if (e) (void)hipEventRecord(e, s);
 }
 
-void enqueue_render(hgs_ctx* c, hipStream_t s) {
-    Counters* ctr = P<Counters>(c->counters);
+int n_passes(const hgs_ctx* c) { return c->pass_v0.size() < 2 ? 1 : (int)c->pass_v0.size() - 1; }
+
+uint32_t pass_tile0(const hgs_ctx* c, int g) {
+    const int v = c->pass_v0[g];
+    return v < (int)c->cams.size() ? c->tile_abs[v] : c->total_tiles;
+}
+
+// Group the views into about `want` consecutive passes of similar pixel
+// count (at most pass_views views each) and make every view's tile base, and
+// the tile -> view table, relative to its pass.  upload_table: rewrite the
+// device table (the layout changed); otherwise only the host mirror moves.
+hgs_status plan_passes(hgs_ctx* c, int want, bool upload_table) {
+    const int V = (int)c->cams.size();
+    want = std::max(1, std::min(want, V));
+    uint64_t total = 0;
+    for (const hgs_camera& k : c->cams) total += (uint64_t)k.width * k.height;
+    std::vector<int> v0{0};
+    uint64_t acc = 0;
+    int in_pass = 0;
+    for (int v = 0; v < V; ++v) {
+        acc += (uint64_t)c->cams[v].width * c->cams[v].height;
+        ++in_pass;
+        const bool full = c->pass_views > 0 && in_pass >= c->pass_views;
+        if (v + 1 < V && (full || acc * (uint64_t)want >= total * (uint64_t)v0.size())) {
+            v0.push_back(v + 1);
+            in_pass = 0;
+        }
+    }
+    v0.push_back(V);
+    if (upload_table || v0 != c->pass_v0) {
+        upload_table = true;
+        invalidate_graph(c);
+    }
+    c->pass_v0 = v0;
+    c->want_passes = want;
+    HIP_TRY(c, hipEventSynchronize(c->views_copied));   // the mirror may still be in flight
+    std::vector<uint32_t> tv(upload_table ? c->total_tiles : 0);
+    for (size_t g = 0; g + 1 < v0.size(); ++g) {
+        const uint32_t t0 = c->tile_abs[v0[g]];
+        for (int v = v0[g]; v < v0[g + 1]; ++v) {
+            ViewDev& d = c->views_host[v];
+            d.tile_base = c->tile_abs[v] - t0;
+            if (!upload_table) continue;
+            const uint32_t nt = (uint32_t)(d.tiles_x * d.tiles_y);
+            for (uint32_t t = 0; t < nt; ++t) tv[c->tile_abs[v] + t] = (uint32_t)(v - v0[g]);
+        }
+    }
+    if (upload_table && c->total_tiles)
+        HIP_TRY(c, hipMemcpy(c->tile_view.p, tv.data(), (size_t)c->total_tiles * 4, hipMemcpyHostToDevice));
+    c->views_dirty = true;
+    return HGS_OK;
+}
+
+// One pipeline pass over the views of pass g (counters slot g).
+void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
+    Counters* ctr = P<Counters>(c->counters) + g;
+    const int v0 = c->pass_v0[g], v1 = c->pass_v0[g + 1];
+    const uint32_t t0 = pass_tile0(c, g), t1 = pass_tile0(c, g + 1);
     if (c->stage_timing && c->ev_used >= 6 * 512) (void)harvest_events(c);
     mark(c, 0, s);
     k_reset<<<1, 64, 0, s>>>(ctr);
@@ -342,14 +405,15 @@ void enqueue_render(hgs_ctx* c, hipStream_t s) {
     ca.n_levels = c->n_levels;
     ca.mode = c->lod_mode;
     ca.flat = !c->hier;
-    ca.views = P<ViewDev>(c->views);
-    ca.n_views = (int)c->cams.size();
+    ca.views = P<ViewDev>(c->views) + v0;
+    ca.n_views = v1 - v0;
     ca.frontier[0] = P<uint2>(c->frontier[0]);
     ca.frontier[1] = P<uint2>(c->frontier[1]);
     ca.frontier_cap = c->frontier_cap;
     ca.cut = P<uint2>(c->cut);
     ca.cut_cap = c->cut_cap;
     ca.scan_tmp = P<uint4>(c->scan_tmp);
+    ca.dec = P<uint8_t>(c->dec);
     ca.ctr = ctr;
     ca.mlp = (c->lod_mode == HGS_LOD_LEARNED && c->mlp_loaded) ? c->mlp_dev.p : nullptr;
     ca.s_hi = c->s_hi;
@@ -412,7 +476,7 @@ void enqueue_render(hgs_ctx* c, hipStream_t s) {
     pb.vals[1] = P<uint32_t>(c->pval[1]);
     pb.count = &ctr->pairs;
     pb.cap = c->pair_cap;
-    pb.key_bits = bits_for(c->total_tiles);
+    pb.key_bits = bits_for(t1 - t0);
     pb.max_digit_bits = c->sort_digit_bits;
     pb.hist = sa.hist;
     const int pr = launch_sort(pb, s);
@@ -423,10 +487,10 @@ void enqueue_render(hgs_ctx* c, hipStream_t s) {
     xa.pair_cap = c->pair_cap;
     xa.cut_cap = c->cut_cap;
     xa.ranges = P<uint2>(c->ranges);
-    xa.total_tiles = c->total_tiles;
+    xa.total_tiles = t1 - t0;
     xa.proj = pa.proj;
     xa.views = ca.views;
-    xa.tile_view = P<uint32_t>(c->tile_view);
+    xa.tile_view = P<uint32_t>(c->tile_view) + t0;
     xa.n_views = ca.n_views;
     xa.opts = c->ropts;
     xa.ctr = ctr;
@@ -435,6 +499,34 @@ void enqueue_render(hgs_ctx* c, hipStream_t s) {
     launch_composite(xa, s);
     mark(c, 5, s);
     if (c->stage_timing) c->ev_used += 6;
+}
+
+void enqueue_render(hgs_ctx* c, hipStream_t s) {
+    for (int g = 0; g < n_passes(c); ++g) enqueue_pass(c, s, g);
+    if (c->stage_timing) ++c->acc_n;
+}
+
+// Overflow bits of all passes and the largest need of any pass.
+Counters merge_passes(const hgs_ctx* c, uint64_t* need_cut_sum) {
+    Counters m{};
+    uint64_t sum = 0;
+    for (int g = 0; g < n_passes(c); ++g) {
+        const Counters& k = c->ctr_host[g];
+        m.overflow |= k.overflow;
+        m.need_frontier = std::max(m.need_frontier, k.need_frontier);
+        m.need_cut = std::max(m.need_cut, k.need_cut);
+        m.need_pairs = std::max(m.need_pairs, k.need_pairs);
+        m.need_cand = std::max(m.need_cand, k.need_cand);
+        sum += std::max(k.need_cut, k.cut);
+    }
+    if (need_cut_sum) *need_cut_sum = sum;
+    return m;
+}
+
+hgs_status read_counters(hgs_ctx* c, hipStream_t s) {
+    HIP_TRY(c, hipMemcpyAsync(c->ctr_host, c->counters.p, sizeof(Counters) * n_passes(c), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return HGS_OK;
 }
 
 // Node-geometry part of the learned-LOD record (pointers into the scene).
@@ -482,13 +574,13 @@ hgs_status hgs_create(int32_t device, hgs_ctx** out) {
     hgs_ctx* c = new (std::nothrow) hgs_ctx();
     if (!c) return HGS_E_OOM;
     c->device = device;
-    if (ensure(c, c->counters, sizeof(Counters)) != HGS_OK ||
-        hipHostMalloc((void**)&c->ctr_host, sizeof(Counters), hipHostMallocDefault) != hipSuccess ||
+    if (ensure(c, c->counters, sizeof(Counters) * kMaxViews) != HGS_OK ||
+        hipHostMalloc((void**)&c->ctr_host, sizeof(Counters) * kMaxViews, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->views_copied, hipEventDisableTiming) != hipSuccess) {
         hgs_destroy(c);
         return HGS_E_HIP;
     }
-    std::memset(c->ctr_host, 0, sizeof(Counters));
+    std::memset(c->ctr_host, 0, sizeof(Counters) * kMaxViews);
     *out = c;
     return HGS_OK;
 }
@@ -500,7 +592,7 @@ void hgs_destroy(hgs_ctx* c) {
     DevMem* all[] = {&c->geo, &c->sh, &c->bound, &c->child, &c->leaf_ids, &c->parent, &c->nodefeat, &c->lvl,
                      &c->train_scratch, &c->region_dev, &c->surf, &c->views,
                      &c->tile_view, &c->mlp_w, &c->mlp_dev, &c->frontier[0], &c->frontier[1], &c->cut, &c->proj,
-                     &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->rect, &c->offsets,
+                     &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->rect, &c->offsets, &c->dec,
                      &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
                      &c->counters, &c->sort_k, &c->sort_v, &c->sort_n};
     for (DevMem* m : all) release(*m);
@@ -681,7 +773,6 @@ hgs_status hgs_set_cameras(hgs_ctx* c, int32_t n, const hgs_camera* cams) {
     } else {
         HIP_TRY(c, hipEventSynchronize(c->views_copied));
     }
-    std::vector<uint32_t> tv(tiles);
     for (int v = 0; v < n; ++v) {
         const hgs_camera& k = cams[v];
         ViewDev d{};
@@ -717,15 +808,11 @@ hgs_status hgs_set_cameras(hgs_ctx* c, int32_t n, const hgs_camera* cams) {
         d.keep_node = -1;
         d.rgb = d.depth = d.alpha = nullptr;
         c->views_host[v] = d;
-        const uint32_t nt = (uint32_t)(d.tiles_x * d.tiles_y);
-        for (uint32_t t = 0; t < nt; ++t) tv[tile_base[v] + t] = (uint32_t)v;
-    }
-    if (!same_layout) {
-        HIP_TRY(c, hipMemcpy(c->tile_view.p, tv.data(), tiles * 4, hipMemcpyHostToDevice));
-        invalidate_graph(c);
     }
     c->cams.assign(cams, cams + n);
     c->total_tiles = (uint32_t)tiles;
+    c->tile_abs = tile_base;
+    if ((s = plan_passes(c, same_layout ? c->want_passes : 1, !same_layout))) return s;
     c->views_dirty = true;
     c->last_valid = false;
     if (c->loaded) {
@@ -757,12 +844,17 @@ hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
         case HGS_OPT_AUTO_REGROW: c->auto_regrow = val != 0; return HGS_OK;
         case HGS_OPT_COUNT_NALG: c->ropts.count_nalg = val != 0; return HGS_OK;
         case HGS_OPT_BATCH_DEPTH:
-            if (val != 64 && val != 128 && val != 256 && val != 512) return fail(c, HGS_E_INVALID, "batch depth must be 64, 128, 256 or 512");
+            if (val != 64 && val != 128 && val != 256) return fail(c, HGS_E_INVALID, "batch depth must be 64, 128 or 256");
             c->ropts.batch = (int)val;
             return HGS_OK;
         case HGS_OPT_USE_GRAPH: c->use_graph = val != 0; return HGS_OK;
         case HGS_OPT_PERSISTENT: c->ropts.persistent = val != 0; return HGS_OK;
         case HGS_OPT_EXACT_TILES: c->ropts.exact_tiles = val != 0; return HGS_OK;
+        case HGS_OPT_PASS_VIEWS:
+            if (val < 0 || val > kMaxViews) return fail(c, HGS_E_INVALID, "views per pass must be 0..%d", kMaxViews);
+            c->pass_views = (int)val;
+            if (!c->cams.empty()) return plan_passes(c, 1, true);
+            return HGS_OK;
         case HGS_OPT_SORT_DIGIT_BITS:
             if (val < 6 || val > 11) return fail(c, HGS_E_INVALID, "digit bits must be 6..11");
             c->sort_digit_bits = (int)val;
@@ -780,7 +872,7 @@ hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
             c->forced_cap = (uint32_t)val;
             if (c->forced_cap) {
                 // shrink: drop the work buffers so they are re-made at this size
-                DevMem* w[] = {&c->frontier[0], &c->frontier[1], &c->cut, &c->proj, &c->dkey[0], &c->dkey[1],
+                DevMem* w[] = {&c->frontier[0], &c->frontier[1], &c->dec, &c->cut, &c->proj, &c->dkey[0], &c->dkey[1],
                                &c->dval[0], &c->dval[1], &c->ntiles, &c->rect, &c->offsets, &c->pkey[0],
                                &c->pkey[1], &c->pval[0], &c->pval[1]};
                 HIP_TRY(c, hipDeviceSynchronize());
@@ -811,7 +903,7 @@ hgs_status hgs_render(hgs_ctx* c, void* stream, const hgs_output* outs) {
     hgs_status st;
     if ((st = upload_views(c, s, outs))) return st;
     c->regrows = 0;
-    for (int attempt = 0; attempt < 8; ++attempt) {
+    for (int attempt = 0; attempt < 16; ++attempt) {
         if (c->use_graph && !c->stage_timing) {
             if (!c->graph_valid) {
                 invalidate_graph(c);
@@ -833,25 +925,39 @@ hgs_status hgs_render(hgs_ctx* c, void* stream, const hgs_output* outs) {
         HIP_TRY(c, hipGetLastError());
         c->last_valid = true;
         if (!c->sync_check) return HGS_OK;
-        HIP_TRY(c, hipMemcpyAsync(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipStreamSynchronize(s));
-        const Counters k = *c->ctr_host;
+        if ((st = read_counters(c, s))) return st;
+        uint64_t need_sum = 0;
+        const Counters k = merge_passes(c, &need_sum);
         if (!k.overflow) return HGS_OK;
         c->last_valid = false;
         if (!c->auto_regrow) {
             grow_from(c, k);
             return fail(c, HGS_E_CAPACITY, "work buffers overflowed (bits %u); capacities grown", k.overflow);
         }
-        if ((st = grow_from(c, k))) return st;
+        const int np = n_passes(c);
+        const bool too_big = (uint64_t)k.need_cut >= kEntryLimit || (uint64_t)k.need_pairs > kPairLimit ||
+                             (uint64_t)k.need_frontier > kPairLimit;
+        if (too_big && np < (int)c->cams.size()) {
+            // a pass outgrew the index space: more, smaller passes
+            const uint64_t est = (3 * need_sum) / (2 * kEntryLimit) + 1;
+            if ((st = plan_passes(c, (int)std::max<uint64_t>(2 * np, est), false))) return st;
+            ++c->regrows;
+        } else if ((st = grow_from(c, k))) {
+            return st;
+        }
+        if ((st = upload_views(c, s, outs))) return st;
     }
-    return fail(c, HGS_E_CAPACITY, "work buffers kept overflowing");
+    const Counters k = merge_passes(c, nullptr);
+    return fail(c, HGS_E_CAPACITY, "work buffers kept overflowing (bits %u; need cut %u, pairs %u, frontier %u; "
+                "caps %u, %u, %u; %d passes)", k.overflow, k.need_cut, k.need_pairs, k.need_frontier, c->cut_cap,
+                c->pair_cap, c->frontier_cap, n_passes(c));
 }
 
 hgs_status hgs_check(hgs_ctx* c) {
     if (!c) return HGS_E_INVALID;
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost));
-    const Counters k = *c->ctr_host;
+    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters) * n_passes(c), hipMemcpyDeviceToHost));
+    const Counters k = merge_passes(c, nullptr);
     if (k.overflow) {
         c->last_valid = false;
         hgs_status s = grow_from(c, k);
@@ -867,13 +973,18 @@ hgs_status hgs_get_cut(hgs_ctx* c, int32_t view, int32_t* ids, int64_t cap, int6
     if (view < 0 || view >= (int)c->cams.size()) return fail(c, HGS_E_INVALID, "view out of range");
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipDeviceSynchronize());
-    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost));
-    const uint32_t m = std::min(c->ctr_host->cut, c->cut_cap);
+    const int last = n_passes(c) - 1, vb = c->pass_v0[last];
+    if (view < vb)
+        return fail(c, HGS_E_STATE, "view %d was rendered in an earlier pass of the batch; only the last pass "
+                    "(views %d..%d) keeps its intermediates", view, vb, (int)c->cams.size() - 1);
+    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters) * (last + 1), hipMemcpyDeviceToHost));
+    const uint32_t m = std::min(c->ctr_host[last].cut, c->cut_cap);
+    const uint32_t vrel = (uint32_t)(view - vb);
     std::vector<uint2> e(m);
     if (m) HIP_TRY(c, hipMemcpy(e.data(), c->cut.p, (size_t)m * sizeof(uint2), hipMemcpyDeviceToHost));
     int64_t k = 0;
     for (uint32_t i = 0; i < m; ++i)
-        if ((int32_t)e[i].y == view) {
+        if (e[i].y == vrel) {
             if (ids && k < cap) ids[k] = (int32_t)e[i].x;
             ++k;
         }
@@ -887,8 +998,13 @@ hgs_status hgs_get_projected(hgs_ctx* c, int32_t view, float* out, int64_t cap, 
     if (view < 0 || view >= (int)c->cams.size()) return fail(c, HGS_E_INVALID, "view out of range");
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipDeviceSynchronize());
-    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost));
-    const uint32_t m = std::min(c->ctr_host->cut, c->cut_cap);
+    const int last = n_passes(c) - 1, vb = c->pass_v0[last];
+    if (view < vb)
+        return fail(c, HGS_E_STATE, "view %d was rendered in an earlier pass of the batch; only the last pass "
+                    "(views %d..%d) keeps its intermediates", view, vb, (int)c->cams.size() - 1);
+    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters) * (last + 1), hipMemcpyDeviceToHost));
+    const uint32_t m = std::min(c->ctr_host[last].cut, c->cut_cap);
+    const uint32_t vrel = (uint32_t)(view - vb);
     std::vector<uint2> e(m);
     std::vector<Proj> p(m);
     std::vector<uint32_t> nt(m);
@@ -899,7 +1015,7 @@ hgs_status hgs_get_projected(hgs_ctx* c, int32_t view, float* out, int64_t cap, 
     }
     int64_t k = 0;
     for (uint32_t i = 0; i < m; ++i) {
-        if ((int32_t)e[i].y != view) continue;
+        if (e[i].y != vrel) continue;
         if (out && k < cap) {
             float* o = out + 12 * k;
             const Proj& q = p[i];
@@ -919,13 +1035,17 @@ hgs_status hgs_get_stats(hgs_ctx* c, hgs_stats* out) {
     if (!c || !out) return HGS_E_INVALID;
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipDeviceSynchronize());
-    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters), hipMemcpyDeviceToHost));
-    const Counters& k = *c->ctr_host;
+    const int np = n_passes(c);
+    HIP_TRY(c, hipMemcpy(c->ctr_host, c->counters.p, sizeof(Counters) * np, hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
-    out->cut_size = std::min(k.cut, c->cut_cap);
-    out->visible = k.visible;
-    out->pairs = std::min(k.pairs, c->pair_cap);
-    out->n_alg = (int64_t)k.nalg;
+    for (int g = 0; g < np; ++g) {
+        const Counters& k = c->ctr_host[g];
+        out->cut_size += std::min(k.cut, c->cut_cap);
+        out->visible += k.visible;
+        out->pairs += std::min(k.pairs, c->pair_cap);
+        out->n_alg += (int64_t)k.nalg;
+    }
+    out->passes = np;
     out->tiles = c->total_tiles;
     out->regrows = c->regrows;
     hgs_status s = harvest_events(c);
@@ -1025,6 +1145,7 @@ hgs_status hgs_lod_candidates(hgs_ctx* c, void* stream, float s_hi, uint32_t* en
         ca.cut = P<uint2>(c->cut);
         ca.cut_cap = c->cut_cap;
         ca.scan_tmp = P<uint4>(c->scan_tmp);
+        ca.dec = P<uint8_t>(c->dec);
         ca.ctr = ctr;
         ca.mlp = nullptr;
         ca.s_hi = s_hi;

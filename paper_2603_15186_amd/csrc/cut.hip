@@ -33,7 +33,7 @@ enum : uint32_t { kDrop = 0, kEmit = 1, kExpand = 2, kCandidate = 4 };
 // threshold rule refines the node and its projected size is at most s_hi
 // pixels: the band in which the learned rule may keep the node instead.
 __device__ __noinline__ uint32_t node_decision(const ViewDev& V, int k, float4 b, int nchild, int mode,
-                                               const void* mlp, double s_hi, int level) {
+                                               const void* mlp, const float* sw, double s_hi, int level) {
 #pragma clang fp contract(off)
     NodeGeom g;
     node_geometry(V, b, &g);
@@ -55,7 +55,7 @@ __device__ __noinline__ uint32_t node_decision(const ViewDev& V, int k, float4 b
     if (k == V.keep_node) return kEmit;
     const bool cand = lhs <= (s_hi * s_hi) * g.d2;
     if (cand && mode == HGS_LOD_LEARNED && mlp != nullptr) {
-        if (!lod_mlp_expand(*(const LodMlpDev*)mlp, V, k, b, g, level)) return kEmit;
+        if (!lod_mlp_expand(*(const LodMlpDev*)mlp, sw, V, k, b, g, level)) return kEmit;
     }
     return kExpand | (cand ? kCandidate : 0u);
 }
@@ -71,6 +71,7 @@ struct LevelCtx {
     uint2* cut;
     uint32_t cut_cap;
     uint4* tmp;               // [G] block counts, then offsets; [G] = level bases
+    uint8_t* dec;             // per frontier entry: decision of the count pass
     Counters* ctr;
     int mode;
     const void* mlp;
@@ -90,25 +91,44 @@ __device__ __forceinline__ void chunk_of(uint32_t n, int G, int b, uint32_t* lo,
     *hi = (uint32_t)(e < n ? e : n);
 }
 
-// (emitted, children, candidate) counts of one frontier entry
-__device__ __forceinline__ uint4 eval_entry(const LevelCtx& c, uint2 e) {
-    const float4 b = c.bound[e.x];
-    const int2 ch = c.child[e.x];
-    const uint32_t d = node_decision(c.views[e.y], (int)e.x, b, ch.y, c.mode, c.mlp, c.s_hi, c.level);
+// (emitted, children, candidate) counts of a decision
+__device__ __forceinline__ uint4 counts_of(const LevelCtx& c, uint32_t d, int nchild) {
     const uint32_t kind = d & 3u;
-    return make_uint4(kind == kEmit ? 1u : 0u, kind == kExpand ? (uint32_t)ch.y : 0u,
+    return make_uint4(kind == kEmit ? 1u : 0u, kind == kExpand ? (uint32_t)nchild : 0u,
                       (c.cand != nullptr && (d & kCandidate)) ? 1u : 0u, 0u);
 }
 
+// The network's weights widened to FP32 in LDS (learned mode only).
+__device__ __forceinline__ const float* stage_weights(const LevelCtx& c, float* s_w) {
+    if (c.mode != HGS_LOD_LEARNED || c.mlp == nullptr) return nullptr;
+    const uint16_t* w = ((const LodMlpDev*)c.mlp)->w;
+    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) s_w[i] = bf16_to_f32(w[i]);
+    __syncthreads();
+    return s_w;
+}
+
+// Count pass: decide every entry of the block's chunk once, remember the
+// decision for the emit pass, reduce the counts.
 __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap) {
     __shared__ uint4 sh[kNT / kWave + 1];
+    __shared__ float s_w[kMlpParams];
     uint32_t n = *c.in_count;
     n = n < in_cap ? n : in_cap;
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
+    if (lo >= hi) {
+        if (threadIdx.x == 0) c.tmp[blockIdx.x] = make_uint4(0, 0, 0, 0);
+        return;
+    }
+    const float* sw = stage_weights(c, s_w);
     uint4 acc = make_uint4(0, 0, 0, 0);
     for (uint32_t i = lo + threadIdx.x; i < hi; i += kNT) {
-        const uint4 r = eval_entry(c, c.in[i]);
+        const uint2 e = c.in[i];
+        const float4 b = c.bound[e.x];
+        const int2 ch = c.child[e.x];
+        const uint32_t d = node_decision(c.views[e.y], (int)e.x, b, ch.y, c.mode, c.mlp, sw, c.s_hi, c.level);
+        c.dec[i] = (uint8_t)d;
+        const uint4 r = counts_of(c, d, ch.y);
         acc.x += r.x;
         acc.y += r.y;
         acc.z += r.z;
@@ -168,7 +188,7 @@ __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap)
         uint2 e = make_uint2(0, 0);
         if (i < hi) {
             e = c.in[i];
-            r = eval_entry(c, e);
+            r = counts_of(c, c.dec[i], c.child[e.x].y);
         }
         uint4 tot;
         const uint4 ex = block_excl_scan4<kNT>(r, sh, &tot);
@@ -286,6 +306,7 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.cut = a.cut;
         c.cut_cap = a.cut_cap;
         c.tmp = a.scan_tmp;
+        c.dec = a.dec;
         c.ctr = a.ctr;
         c.mode = a.mode;
         c.mlp = a.mlp;

@@ -42,7 +42,7 @@ struct ViewDev {
     double xlo, xhi, ylo, yhi;       // Jacobian clamp range of x/z and y/z
     float bg[3];
     int32_t width, height, tiles_x, tiles_y;
-    uint32_t tile_base;              // first global tile id of this view
+    uint32_t tile_base;              // first tile id of this view within its pass
     int32_t keep_node;               // >= 0: never refine this node (label renders)
     float* rgb;
     float* depth;
@@ -110,6 +110,7 @@ struct CutArgs {
     uint2* cut;
     uint32_t cut_cap;
     uint4* scan_tmp;                 // kScanBlocks + 1 entries
+    uint8_t* dec;                    // frontier_cap bytes: per-entry decisions
     Counters* ctr;
     // learned refinement (nullptr = off); candidate band for it and for
     // candidate collection: refined by the threshold and s <= s_hi pixels

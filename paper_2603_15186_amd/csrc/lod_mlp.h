@@ -106,16 +106,38 @@ __device__ __forceinline__ float lod_mlp_logit(const uint16_t* __restrict__ w, c
     return out;
 }
 
+// Forward pass with the weights already widened to FP32 (e.g. staged in
+// LDS); same arithmetic as lod_mlp_logit.
+__device__ __forceinline__ float lod_mlp_logit_f32(const float* w, const float x[kMlpIn]) {
+    float h1[kMlpH];
+#pragma unroll
+    for (int j = 0; j < kMlpH; ++j) {
+        float acc = w[kOffB1 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i) acc = fmaf(w[kOffW1 + j * kMlpIn + i], x[i], acc);
+        h1[j] = acc > 0.f ? acc : 0.f;
+    }
+    float out = w[kOffB3];
+    for (int j = 0; j < kMlpH; ++j) {
+        float acc = w[kOffB2 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpH; ++i) acc = fmaf(w[kOffW2 + j * kMlpH + i], h1[i], acc);
+        acc = acc > 0.f ? acc : 0.f;
+        out = fmaf(w[kOffW3 + j], acc, out);
+    }
+    return out;
+}
+
 // For a candidate node (the threshold rule refines it and its projected
 // size is at most s_hi): does the learned cut refine it?  Yes iff the
-// network's probability reaches p_star.
-__device__ __forceinline__ bool lod_mlp_expand(const LodMlpDev& m, const ViewDev& V, int k, float4 b,
-                                               const NodeGeom& g, int level) {
+// network's probability reaches p_star.  sw: the weights as FP32 (LDS).
+__device__ __forceinline__ bool lod_mlp_expand(const LodMlpDev& m, const float* sw, const ViewDev& V, int k,
+                                               float4 b, const NodeGeom& g, int level) {
     float f[kMlpIn];
     lod_features(m, V, k, b, g, level, f);
 #pragma unroll
     for (int i = 0; i < kMlpIn; ++i) f[i] = (f[i] - m.mean[i]) * m.inv_std[i];
-    const float z = lod_mlp_logit(m.w, f);
+    const float z = lod_mlp_logit_f32(sw, f);
     const float p = 1.f / (1.f + __expf(-z));
     return p >= m.p_star;
 }

@@ -37,6 +37,7 @@ HGS_OPT_EXACT_TILES = 7
 HGS_OPT_INITIAL_CAPACITY = 8
 HGS_OPT_STAGE_TIMING = 9
 HGS_OPT_SORT_DIGIT_BITS = 10
+HGS_OPT_PASS_VIEWS = 11
 
 PROJECTED_FIELDS = ("u", "v", "A", "B", "C", "r", "g", "b", "depth", "opacity", "ntiles", "valid")
 
@@ -73,7 +74,7 @@ class hgs_stats(ctypes.Structure):
     _fields_ = [("cut_size", ctypes.c_int64), ("visible", ctypes.c_int64), ("pairs", ctypes.c_int64),
                 ("n_alg", ctypes.c_int64), ("tiles", ctypes.c_int64), ("regrows", ctypes.c_int64),
                 ("timed_renders", ctypes.c_int64), ("graph_launches", ctypes.c_int64), ("ms_cut", ctypes.c_double), ("ms_project", ctypes.c_double), ("ms_sort", ctypes.c_double),
-                ("ms_composite", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_composite", ctypes.c_double), ("ms_total", ctypes.c_double), ("passes", ctypes.c_int64)]
 
 
 # (name, restype, argtypes) of every exported entry point

@@ -27,6 +27,24 @@ def test_library_exports_every_declared_symbol():
     assert sorted(n for n, _, _ in hgs.EXPORTS) == names
 
 
+def test_binding_constants_match_header():
+    src = open(os.path.join(ROOT, "include", "hgs.h")).read()
+    found = re.findall(r"#define (HGS_[A-Z0-9_]+) +\(?(-?\d+)\)?", src)
+    assert len(found) >= 20
+    for name, val in found:
+        assert getattr(hgs, name) == int(val), name
+
+
+def test_stats_struct_matches_header_fields():
+    src = open(os.path.join(ROOT, "include", "hgs.h")).read()
+    body = src[src.index("typedef struct {\n    int64_t cut_size;"):src.index("} hgs_stats;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in re.findall(r"(?:int64_t|double) ([^;]+);", body):
+        names += [n.strip() for n in decl.split(",")]
+    assert [n for n, _ in hgs.hgs_stats._fields_] == names
+
+
 def test_binding_struct_sizes_match_header_layout():
     import ctypes
     assert ctypes.sizeof(hgs.hgs_gaussians) == 8 + 4 + 4 + 5 * 8

@@ -138,7 +138,7 @@ def test_invariance_across_launch_choices(R, box):
     again = _render(R, scene, cams)[0]
     for a, b in zip(ref, again):
         assert np.array_equal(a, b)
-    for opts in ({"batch_depth": 64}, {"batch_depth": 128}, {"batch_depth": 512}, {"exact_tiles": 0},
+    for opts in ({"batch_depth": 64}, {"batch_depth": 128}, {"batch_depth": 64, "persistent": 1}, {"exact_tiles": 0},
                  {"persistent": 1}, {"sort_digit_bits": 11}, {"sort_digit_bits": 6}):
         img = _render(R, scene, cams, **opts)[0]
         for a, b in zip(ref, img):
@@ -233,6 +233,41 @@ def test_batched_views_equal_single_views(R, plan_small):
             assert np.array_equal(a, b), v
 
 
+def test_multi_pass_batches_equal_one_pass(R, plan_small):
+    """A batch split into passes (at most 2 views, then 1 view per pass)
+    gives the one-pass images bitwise, also replayed from a captured graph;
+    the last pass keeps its cut, earlier passes' intermediates are gone."""
+    scene, cams = plan_small
+    hgs = _hgs()
+    views = [_small_cam(cams[1], 320, 240), _small_cam(cams[4], 128, 72), cams[7], _small_cam(cams[9], 33, 17),
+             _small_cam(cams[2], 200, 117)]
+    one = _render(R, scene, views, pass_views=0)
+    assert R.stats()["passes"] == 1
+    try:
+        for pv, n_pass in ((2, 3), (1, 5)):
+            got = _render(R, scene, views, pass_views=pv)
+            assert R.stats()["passes"] == n_pass
+            for v in range(len(views)):
+                for a, b in zip(one[v], got[v]):
+                    assert np.array_equal(a, b), (pv, v)
+        last = len(views) - 1
+        assert np.array_equal(R.get_cut(last), O.cut(scene, views[last], O.MODE_THRESHOLD, 1.0))
+        with pytest.raises(hgs.HgsError):
+            R.get_cut(0)
+        outs = R.alloc_outputs()
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
+        for rep in range(3):
+            R.render(outs)
+            torch.cuda.synchronize()
+            for v in range(len(views)):
+                for a, b in zip(one[v], outs[v]):
+                    assert np.array_equal(a, b.cpu().numpy()), (rep, v)
+        assert R.stats()["graph_launches"] >= 3
+    finally:
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+        R.set_option(hgs.HGS_OPT_PASS_VIEWS, 0)
+
+
 # ---------------------------------------------------------- full-size scene
 
 @pytest.fixture(scope="module")
@@ -305,3 +340,51 @@ def test_graph_replays_match_eager_render(R, plan_small):
     for v in range(len(views)):
         for a, b in zip(ref8[v], outs[v]):
             assert np.array_equal(a, b.cpu().numpy()), v
+
+
+# ------------------------------------------- 8M-leaf plan, 256 mixed views
+
+@pytest.fixture(scope="module")
+def plan8m():
+    return W.plan8m()
+
+
+@pytest.mark.timeout(600)
+def test_plan8m_mixed_resolution_batch(R, plan8m):
+    """The 256-view batch (128 @ 320x240, 96 @ 640x480, 32 @ 1280x720) of the
+    8M-leaf plan in one render call at tau = 1.  Its cut has more entries
+    than the 2^28-entry index space, so the renderer splits the batch into
+    passes by itself.  One view of each resolution equals its single-view
+    render bitwise; that render's cut is bit-exact and its sampled pixels
+    match the oracle."""
+    scene, views = plan8m
+    assert len(views) == 256
+    R.load_scene(scene)
+    R.set_cameras(views)
+    R.set_lod(1, 1.0)
+    outs = R.render()
+    torch.cuda.synchronize()
+    st = R.stats()
+    print("plan8m batch:", st, flush=True)
+    assert st["passes"] >= 2 and st["cut_size"] > (1 << 28)
+    picks = [5, 128 + 17, 224 + 9]
+    imgs = {v: tuple(t.cpu().numpy() for t in outs[v]) for v in picks}
+    del outs
+    rng = np.random.default_rng(3)
+    for v in picks:
+        cam = views[v]
+        R.set_cameras([cam])
+        single = R.render()[0]
+        torch.cuda.synchronize()
+        for a, b in zip(imgs[v], single):
+            assert np.array_equal(a, b.cpu().numpy()), v
+        want = O.cut(scene, cam, O.MODE_THRESHOLD, 1.0)
+        assert np.array_equal(R.get_cut(0), want), v
+        px = rng.integers(0, cam.width, 800)
+        py = rng.integers(0, cam.height, 800)
+        res = O.render_pixels(O.project(scene, want, cam), cam, px, py)
+        g = parity.gpu_pixels(*imgs[v], px, py)
+        ok, best, skipped = parity.branch_errors(g, res)
+        msg = parity.summary(ok, best, skipped)
+        print(v, cam.width, cam.height, msg, flush=True)
+        assert ok.all(), msg
