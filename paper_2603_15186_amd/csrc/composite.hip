@@ -1,17 +1,27 @@
 // Front-to-back alpha compositing per 16x16 tile.
 //
-// One 256-thread workgroup (four wave64s) per tile, one pixel per thread.
-// The tile's depth-sorted list is walked in batches: each batch is staged in
-// LDS as tile-relative single-precision records (the FP64 2D mean is made
-// tile-relative before rounding, so pixel offsets keep full precision), then
-// every thread walks the batch for its pixel.  Per entry:
-//   q = (p dx + r dy)^2 + (s dy)^2; skip unless q <= 9 (3-sigma support);
-//   alpha = min(0.99, o exp(-q/2)); skip if alpha < 1/255;
-//   T' = T (1 - alpha); stop before adding if T' < 1e-4;
-//   C += c alpha T, D += z alpha T, T = T'.
-// A workgroup leaves its list as soon as a barrier count shows every pixel
-// has stopped.  This is plain FP32 vector arithmetic, no matrix cores: the
-// work is a per-pixel recurrence, not a dense contraction.
+// One 256-thread workgroup (four wave64s) per tile, one pixel per thread;
+// each 16-lane quarter of a wave owns one 4x4 block of the tile.  The tile's
+// depth-sorted list is walked in batches of BATCH entries:
+//  1. staging: thread j turns entry j into a tile-relative FP32 record (the
+//     FP64 2D mean is made tile-relative before rounding) and marks the 4x4
+//     blocks holding a pixel centre that its 3-sigma ellipse may reach
+//     (exact row by row, with a relative slack of 1e-3 on the bound 9);
+//  2. compaction: for every block, the indices of its marked entries in
+//     depth order (ballots and prefix counts);
+//  3. compositing: the 16 lanes of a block walk that block's list; a wave
+//     runs to the longest of its four lists and shorter lists read a record
+//     that contributes nothing.  The body has no branches:
+//       q = t1^2 + t2^2 with t1 = p dx + r dy = p x + r y + c1 and
+//           t2 = s dy = s y + c2 around the tile origin;
+//       alpha = min(0.99, 2^(log2(o) - q log2(e)/2)) = min(0.99, o e^(-q/2)),
+//           replaced by 0 unless q <= 9, alpha >= 1/255 and the pixel is live;
+//       T' = T (1 - alpha); if T' < 1e-4 the pixel stops without adding,
+//       else C += c alpha T, D += z alpha T, T = T'.
+// A wave leaves its lists once a ballot shows all its pixels stopped, the
+// workgroup once a barrier count does.  This is plain FP32 vector arithmetic,
+// no matrix cores: the work is a per-pixel recurrence, not a dense
+// contraction.
 #include "device_util.h"
 #include "internal.h"
 
@@ -39,67 +49,148 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const Counters* ctr,
     }
 }
 
+constexpr int kBlocks = 16;                 // 4x4-pixel blocks per tile
+constexpr float kQMax = 9.f;
+constexpr float kQMask = 9.f * 1.001f;      // bound used to mark blocks
+
+// One staged Gaussian: t1 = p x + r y + c1, t2 = s y + c2 over tile-relative
+// pixel centres (x, y); lo = log2(opacity).
+struct alignas(16) StageA { float p, r, c1, s; };
+struct alignas(16) StageB { float c2, lo, z, col0; };
+struct alignas(16) StageC { float col1, col2; };
+
+// Blocks (bit 4 * band + column group) holding a pixel centre with
+// q <= kQMask, scanning pixel rows row_lo..row_hi.
+__device__ __forceinline__ uint32_t block_mask(float u, float v, float p, float r, float s, int row_lo,
+                                               int row_hi) {
+    const float R = sqrtf(kQMask) / s;
+    row_lo = max(row_lo, (int)ceilf(v - R - 0.5f));
+    row_hi = min(row_hi, (int)floorf(v + R - 0.5f));
+    const float ip = 1.f / p;
+    uint32_t m = 0;
+    for (int row = row_lo; row <= row_hi; ++row) {
+        const float dy = (float)row + 0.5f - v;
+        const float sd = s * dy;
+        const float h = sqrtf(fmaxf(fmaf(-sd, sd, kQMask), 0.f));
+        const float rd = r * dy;
+        const float xa = u - (rd + h) * ip, xb = u + (h - rd) * ip;
+        const int c0 = max(0, (int)ceilf(xa - 0.5f)), c1 = min(kTile - 1, (int)floorf(xb - 0.5f));
+        if (c0 <= c1) {
+            const uint32_t gl = (uint32_t)c0 >> 2, gh = (uint32_t)c1 >> 2;
+            m |= ((2u << gh) - (1u << gl)) << (4 * (row >> 2));
+        }
+    }
+    return m;
+}
+
 template <int BATCH, bool COUNT>
-__device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t tile, float4* s_a, float4* s_b,
-                                               float2* s_c, uint32_t* s_m, uint32_t* s_red) {
+__device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t tile, StageA* s_a, StageB* s_b,
+                                               StageC* s_c, uint16_t* s_idx, uint32_t* s_wc, uint32_t* s_n,
+                                               uint32_t* s_red) {
+    static_assert(BATCH <= kNT, "one entry per staging thread");
     const uint32_t view = a.tile_view[tile];
     const ViewDev& V = a.views[view];
     const uint32_t local = tile - V.tile_base;
     const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
     const int x0 = tx * kTile, y0 = ty * kTile;
-    const int lx = threadIdx.x % kTile, ly = threadIdx.x / kTile;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int g = lane >> 4, k = lane & 15;
+    const int gid = w * 4 + g;                          // this lane's 4x4 block
+    const int lx = g * 4 + (k & 3), ly = w * 4 + (k >> 2);
     const int px = x0 + lx, py = y0 + ly;
     const bool inside = px < V.width && py < V.height;
     const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
     const double dx0 = (double)x0, dy0 = (double)y0;
     const uint2 rg = a.ranges[tile];
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
-    bool done = !inside;
+    bool live = inside;
     uint32_t nalg = 0;
+    if (threadIdx.x == 0) {                             // record that adds nothing
+        s_a[BATCH] = StageA{0.f, 0.f, 0.f, 0.f};
+        s_b[BATCH] = StageB{0.f, -__builtin_inff(), 0.f, 0.f};
+        s_c[BATCH] = StageC{0.f, 0.f};
+    }
     for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
         const uint32_t cnt = min((uint32_t)BATCH, rg.y - base);
-        for (uint32_t j = threadIdx.x; j < cnt; j += kNT) {
+        // 1. staging
+        uint32_t m = 0;
+        const int j = threadIdx.x;
+        if (j < (int)cnt) {
             const uint32_t val = a.vals[base + j];
             const uint32_t e = val & kEntryMask;
-            const Proj p = a.proj[e < a.cut_cap ? e : 0u];
-            s_a[j] = make_float4((float)(p.u - dx0), (float)(p.v - dy0), p.p, p.r);
-            s_b[j] = make_float4(p.s, p.opacity, p.z, p.c0);
-            s_c[j] = make_float2(p.c1, p.c2);
-            s_m[j] = val >> kStripShift;
-        }
-        __syncthreads();
-        if (!done) {
-            const uint32_t wbit = 1u << (threadIdx.x / kWave);
-            for (uint32_t j = 0; j < cnt; ++j) {
-                // entries that reach no pixel centre of this wave's strip
-                if (!(__builtin_amdgcn_readfirstlane(s_m[j]) & wbit)) continue;
-                const float4 A = s_a[j];
-                const float ddx = fx - A.x, ddy = fy - A.y;
-                const float4 B = s_b[j];
-                const float t1 = fmaf(A.w, ddy, A.z * ddx);
-                const float t2 = B.x * ddy;
-                const float q = fmaf(t1, t1, t2 * t2);
-                if (q <= 9.f) {
-                    if (COUNT) ++nalg;
-                    const float al = fminf(0.99f, B.y * __builtin_amdgcn_exp2f(q * kNegHalfLog2e));
-                    if (al >= 1.f / 255.f) {
-                        const float Tn = T * (1.f - al);
-                        if (Tn < 1e-4f) {
-                            done = true;
-                            break;
-                        }
-                        const float w = al * T;
-                        const float2 Cc = s_c[j];
-                        C0 = fmaf(w, B.w, C0);
-                        C1 = fmaf(w, Cc.x, C1);
-                        C2 = fmaf(w, Cc.y, C2);
-                        D = fmaf(w, B.z, D);
-                        T = Tn;
-                    }
-                }
+            const Proj P = a.proj[e < a.cut_cap ? e : 0u];
+            const float u = (float)(P.u - dx0), v = (float)(P.v - dy0);
+            s_a[j] = StageA{P.p, P.r, -fmaf(P.p, u, P.r * v), P.s};
+            s_b[j] = StageB{-P.s * v, __log2f(P.opacity), P.z, P.c0};
+            s_c[j] = StageC{P.c1, P.c2};
+            // rows of the strips the binning marked
+            const uint32_t strips = val >> kStripShift;
+            if (strips) {
+                const int lo = 4 * (__builtin_ctz(strips)), hi = 4 * (31 - __builtin_clz(strips)) + 3;
+                m = block_mask(u, v, P.p, P.r, P.s, lo, hi);
             }
         }
-        if (__syncthreads_count(done ? 0 : 1) == 0) break;
+        // 2. per-block lists in depth order
+        uint32_t pre[kBlocks];
+#pragma unroll
+        for (int b = 0; b < kBlocks; ++b) {
+            const uint64_t bal = __ballot((m >> b) & 1u);
+            pre[b] = (uint32_t)__popcll(bal & lanemask_lt());
+            if (lane == 0) s_wc[w * kBlocks + b] = (uint32_t)__popcll(bal);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < kBlocks; ++b) {
+            if ((m >> b) & 1u) {
+                uint32_t off = pre[b];
+                for (int ww = 0; ww < w; ++ww) off += s_wc[ww * kBlocks + b];
+                s_idx[b * BATCH + off] = (uint16_t)(j * 16);     // byte offset of the record
+            }
+        }
+        if (threadIdx.x < kBlocks) {
+            uint32_t t = 0;
+            for (int ww = 0; ww < kNT / kWave; ++ww) t += s_wc[ww * kBlocks + threadIdx.x];
+            s_n[threadIdx.x] = t;
+        }
+        __syncthreads();
+        // 3. compositing
+        const uint32_t n_mine = s_n[gid];
+        const uint32_t n_wave = __builtin_amdgcn_readfirstlane(
+            max(max(s_n[w * 4], s_n[w * 4 + 1]), max(s_n[w * 4 + 2], s_n[w * 4 + 3])));
+        // four list entries per step (lists hold record byte offsets and are
+        // padded with the empty record)
+        const uint2* list4 = reinterpret_cast<const uint2*>(s_idx + gid * BATCH);
+        const uint32_t n_step = (n_wave + 3u) & ~3u;
+        for (uint32_t i = 0; i < n_step; i += 4) {
+            const uint2 q4 = list4[i >> 2];
+            const uint32_t id4[4] = {q4.x & 0xffffu, q4.x >> 16, q4.y & 0xffffu, q4.y >> 16};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool listed = i + u < n_mine;
+                const uint32_t off = listed ? id4[u] : (uint32_t)BATCH * 16u;
+                const StageA A = *reinterpret_cast<const StageA*>(reinterpret_cast<const char*>(s_a) + off);
+                const StageB B = *reinterpret_cast<const StageB*>(reinterpret_cast<const char*>(s_b) + off);
+                const StageC Cc = *reinterpret_cast<const StageC*>(reinterpret_cast<const char*>(s_c) + off);
+                const float t1 = fmaf(A.p, fx, fmaf(A.r, fy, A.c1));
+                const float t2 = fmaf(A.s, fy, B.c2);
+                const float q = fmaf(t1, t1, t2 * t2);
+                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, B.lo)));
+                const bool in = q <= kQMax;
+                if (COUNT) nalg += (live && in && listed) ? 1u : 0u;
+                const float al = (in && live && al0 >= 1.f / 255.f) ? al0 : 0.f;
+                const float Tn = T * (1.f - al);
+                const bool stop = Tn < 1e-4f;
+                const float wgt = stop ? 0.f : al * T;
+                C0 = fmaf(wgt, B.col0, C0);
+                C1 = fmaf(wgt, Cc.col1, C1);
+                C2 = fmaf(wgt, Cc.col2, C2);
+                D = fmaf(wgt, B.z, D);
+                T = stop ? T : Tn;
+                live = live && !stop;
+            }
+            if (__ballot(live) == 0) break;
+        }
+        if (__syncthreads_count(live ? 1 : 0) == 0) break;
     }
     if (inside) {
         const size_t plane = (size_t)V.width * V.height;
@@ -111,8 +202,8 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
         if (V.alpha) V.alpha[o] = 1.f - T;
     }
     if (COUNT) {
-        uint32_t s = wave_sum(nalg);
-        if (lane_id() == 0) s_red[threadIdx.x / kWave] = s;
+        uint32_t sum = wave_sum(nalg);
+        if (lane == 0) s_red[w] = sum;
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned long long t = 0;
@@ -123,33 +214,38 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
     }
 }
 
+// LDS of one workgroup.
+template <int BATCH>
+struct Shared {
+    StageA a[BATCH + 1];
+    StageB b[BATCH + 1];
+    StageC c[BATCH + 1];
+    alignas(16) uint16_t idx[kBlocks * BATCH];
+    uint32_t wc[(kNT / kWave) * kBlocks];
+    uint32_t n[kBlocks];
+    uint32_t red[kNT / kWave];
+    uint32_t tile;
+};
+
 template <int BATCH, bool COUNT>
 __global__ __launch_bounds__(kNT) void k_composite(CompositeArgs a) {
-    __shared__ float4 s_a[BATCH];
-    __shared__ float4 s_b[BATCH];
-    __shared__ float2 s_c[BATCH];
-    __shared__ uint32_t s_m[BATCH];
-    __shared__ uint32_t s_red[kNT / kWave];
-    composite_tile<BATCH, COUNT>(a, blockIdx.x, s_a, s_b, s_c, s_m, s_red);
+    __shared__ Shared<BATCH> sh;
+    composite_tile<BATCH, COUNT>(a, blockIdx.x, sh.a, sh.b, sh.c, sh.idx, sh.wc, sh.n, sh.red);
 }
 
 // Persistent variant: a fixed grid takes tiles from a global counter until
 // the counter passes the last tile (every workgroup reaches that exit).
 template <int BATCH, bool COUNT>
 __global__ __launch_bounds__(kNT) void k_composite_persistent(CompositeArgs a) {
-    __shared__ float4 s_a[BATCH];
-    __shared__ float4 s_b[BATCH];
-    __shared__ float2 s_c[BATCH];
-    __shared__ uint32_t s_m[BATCH];
-    __shared__ uint32_t s_red[kNT / kWave];
-    __shared__ uint32_t s_tile;
+    __shared__ Shared<BATCH> sh;
     for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(&a.ctr->tile_queue, 1u);
+        if (threadIdx.x == 0) sh.tile = atomicAdd(&a.ctr->tile_queue, 1u);
         __syncthreads();
-        const uint32_t tile = s_tile;
+        const uint32_t tile = sh.tile;
         __syncthreads();
         if (tile >= a.total_tiles) break;
-        composite_tile<BATCH, COUNT>(a, tile, s_a, s_b, s_c, s_m, s_red);
+        composite_tile<BATCH, COUNT>(a, tile, sh.a, sh.b, sh.c, sh.idx, sh.wc, sh.n, sh.red);
+        __syncthreads();
     }
 }
 
@@ -177,7 +273,6 @@ void launch_composite(const CompositeArgs& a, hipStream_t s) {
     switch (a.opts.batch) {
         case 64: launch_b<64>(a, s); break;
         case 128: launch_b<128>(a, s); break;
-        case 512: launch_b<512>(a, s); break;
         default: launch_b<256>(a, s); break;
     }
 }
