@@ -158,6 +158,7 @@ def run_plan8m(args):
     res = {}
     for tau in (1.0, 2.0, 4.0):
         r.set_lod(hgs.HGS_LOD_THRESHOLD, tau)
+        plan = r.autotune(reps=2)
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
         ms, _ = timed_loop(r, hgs, torch, [views], outs, args.steps, args.warmup, False)
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
@@ -165,6 +166,7 @@ def run_plan8m(args):
         n = st["timed_renders"]
         res[f"tau{tau:g}"] = {"ms_per_batch": ms, "mpix_s": px / (ms * 1e-3) / 1e6, "cut": st["cut_size"],
                                "pairs": st["pairs"], "passes": st["passes"],
+                               "plan": {k: plan[k] for k in ("batch_depth", "persistent", "sort_digit_bits")},
                                "stage_ms": {k: st["ms_" + k] / n for k in ("cut", "project", "sort", "composite")}}
         log(f"tau={tau}: {ms:.2f} ms per batch, {res[f'tau{tau:g}']['mpix_s']:.0f} Mpix/s")
     out = {"metric": "Mpixels/s, 256 mixed-resolution views of the 8M-leaf plan in one call",
@@ -247,6 +249,12 @@ def main():
         n_alg += r.stats()["n_alg"]
     n_alg_step = n_alg / len(batches)
     r.set_option(hgs.HGS_OPT_COUNT_NALG, 0)
+    # launch plan (batch depth, persistent compositing, radix digit width)
+    # picked by the library's autotuner on the first batch; images do not
+    # depend on it
+    r.set_cameras(batches[0])
+    plan = r.autotune(reps=3)
+    log(f"autotuned plan: {plan}")
     r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
 
     if args.quick:
@@ -333,6 +341,7 @@ def main():
                    "leaves": int(np.count_nonzero(scene.child_count == 0)), "nodes": scene.n,
                    "views_per_step": B, "resolution": "1280x720", "fx": 900,
                    "lod": f"learned (p*={model.p_star}, s_hi={model.s_hi}px, threshold tau=1 fallback)",
+                   "plan": {k: plan[k] for k in ("batch_depth", "persistent", "sort_digit_bits")},
                    "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -205,6 +205,27 @@ hgs_status hgs_get_projected(hgs_ctx* ctx, int32_t view, float* host_out, int64_
 /* Counters of the last render (synchronises with it). */
 hgs_status hgs_get_stats(hgs_ctx* ctx, hgs_stats* out);
 
+/* Launch plan chosen by hgs_autotune. */
+typedef struct {
+    int32_t batch_depth;          /* HGS_OPT_BATCH_DEPTH */
+    int32_t persistent;           /* HGS_OPT_PERSISTENT */
+    int32_t sort_digit_bits;      /* HGS_OPT_SORT_DIGIT_BITS */
+    int32_t from_cache;           /* 1: read from the plan cache, not timed */
+    double ms;                    /* render time of the plan (mean over reps) */
+    double ms_default;            /* render time of the default plan */
+} hgs_plan;
+
+/* Time the launch choices that do not change the image (compositor batch
+ * depth 64/128/256, persistent or one-workgroup-per-tile compositing, radix
+ * digit width 6..11) on the current scene, views and LOD, rendering every
+ * view reps >= 1 times per candidate into internal buffers on `stream`, and
+ * keep the fastest as the context's options (*out describes it; may be
+ * NULL).  Coordinate search: compositor choices first, then the digit
+ * width.  cache_path (NULL: none) names a text file of earlier plans keyed
+ * by scene size, view sizes and LOD; a matching line is applied without
+ * timing, a new plan is appended.  Synchronous; leaves stage timing off. */
+hgs_status hgs_autotune(hgs_ctx* ctx, void* stream, const char* cache_path, int32_t reps, hgs_plan* out);
+
 /* Sort n (key, value) pairs on the device by the low `key_bits` bits of the
  * key, stably (LSD radix, digits of up to HGS_OPT_SORT_DIGIT_BITS bits).  keys/vals are device pointers and
  * are sorted in place; the context's scratch memory is used.  For testing

@@ -65,7 +65,7 @@ struct hgs_ctx {
     RenderOpts ropts;
     // work buffers
     uint32_t frontier_cap = 0, cut_cap = 0, pair_cap = 0;
-    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, rect, offsets, dec;
+    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, bins, offsets, dec;
     DevMem pkey[2], pval[2], ranges, scan_tmp, hist, counters;
     Counters* ctr_host = nullptr;     // pinned
     bool last_valid = false;
@@ -249,7 +249,7 @@ hgs_status alloc_work(hgs_ctx* c) {
         if ((s = ensure(c, c->pval[i], Pc * 4))) return s;
     }
     if ((s = ensure(c, c->ntiles, M * 4))) return s;
-    if ((s = ensure(c, c->rect, M * sizeof(ushort4)))) return s;
+    if ((s = ensure(c, c->bins, M * sizeof(BinRec)))) return s;
     if ((s = ensure(c, c->offsets, M * 4))) return s;
     if ((s = ensure(c, c->scan_tmp, (kScanBlocks + 1) * sizeof(uint4)))) return s;
     if ((s = ensure(c, c->hist, (size_t)kSortBins * (kSortBlocks + 1) * 4))) return s;
@@ -434,7 +434,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pa.depth_key = P<uint32_t>(c->dkey[0]);
     pa.depth_val = P<uint32_t>(c->dval[0]);
     pa.ntiles = P<uint32_t>(c->ntiles);
-    pa.rect = P<ushort4>(c->rect);
+    pa.bins = P<BinRec>(c->bins);
     pa.exact_tiles = c->ropts.exact_tiles;
     pa.ctr = ctr;
     launch_project(pa, s);
@@ -455,10 +455,8 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     EmitArgs ea{};
     ea.order = sa.vals[dr];
     ea.ntiles = pa.ntiles;
-    ea.rect = pa.rect;
+    ea.bins = pa.bins;
     ea.proj = pa.proj;
-    ea.cut = ca.cut;
-    ea.views = ca.views;
     ea.cut_cap = c->cut_cap;
     ea.offsets = P<uint32_t>(c->offsets);
     ea.keys = P<uint32_t>(c->pkey[0]);
@@ -559,6 +557,63 @@ hgs_status grow_from(hgs_ctx* c, const Counters& k) {
 
 }  // namespace
 
+namespace {
+
+// Plan-cache key: scene size, view sizes and LOD (FNV-1a over the sizes).
+std::string plan_key(const hgs_ctx* c) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t x) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (x >> (8 * i)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    for (const hgs_camera& k : c->cams) mix(((uint64_t)k.width << 32) | (uint32_t)k.height);
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "n%lld_v%zu_%016llx_lod%d_tau%.6g", (long long)c->n, c->cams.size(),
+                  (unsigned long long)h, c->lod_mode, (double)c->tau);
+    return buf;
+}
+
+bool read_plan(const char* path, const std::string& key, hgs_plan* p) {
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[256];
+        hgs_plan q{};
+        if (std::sscanf(line, "%255s %d %d %d %lf %lf", k, &q.batch_depth, &q.persistent, &q.sort_digit_bits, &q.ms,
+                        &q.ms_default) == 6 && key == k) {
+            *p = q;          // the last matching line wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+// Mean render time of the current options over reps renders (after one
+// checked render that settles the buffer capacities).
+hgs_status time_plan(hgs_ctx* c, hipStream_t s, const hgs_output* outs, int reps, hipEvent_t e0, hipEvent_t e1,
+                     double* ms) {
+    hgs_status st = hgs_render(c, s, outs);
+    if (st) return st;
+    c->sync_check = false;
+    HIP_TRY(c, hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) enqueue_render(c, s);
+    HIP_TRY(c, hipEventRecord(e1, s));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    c->sync_check = true;
+    float t = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&t, e0, e1));
+    *ms = (double)t / reps;
+    return HGS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 hgs_status hgs_create(int32_t device, hgs_ctx** out) {
@@ -592,7 +647,7 @@ void hgs_destroy(hgs_ctx* c) {
     DevMem* all[] = {&c->geo, &c->sh, &c->bound, &c->child, &c->leaf_ids, &c->parent, &c->nodefeat, &c->lvl,
                      &c->train_scratch, &c->region_dev, &c->surf, &c->views,
                      &c->tile_view, &c->mlp_w, &c->mlp_dev, &c->frontier[0], &c->frontier[1], &c->cut, &c->proj,
-                     &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->rect, &c->offsets, &c->dec,
+                     &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->bins, &c->offsets, &c->dec,
                      &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
                      &c->counters, &c->sort_k, &c->sort_v, &c->sort_n};
     for (DevMem* m : all) release(*m);
@@ -873,7 +928,7 @@ hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
             if (c->forced_cap) {
                 // shrink: drop the work buffers so they are re-made at this size
                 DevMem* w[] = {&c->frontier[0], &c->frontier[1], &c->dec, &c->cut, &c->proj, &c->dkey[0], &c->dkey[1],
-                               &c->dval[0], &c->dval[1], &c->ntiles, &c->rect, &c->offsets, &c->pkey[0],
+                               &c->dval[0], &c->dval[1], &c->ntiles, &c->bins, &c->offsets, &c->pkey[0],
                                &c->pkey[1], &c->pval[0], &c->pval[1]};
                 HIP_TRY(c, hipDeviceSynchronize());
                 for (DevMem* m : w) release(*m);
@@ -1057,6 +1112,112 @@ hgs_status hgs_get_stats(hgs_ctx* c, hgs_stats* out) {
     out->ms_sort = c->acc_ms[2];
     out->ms_composite = c->acc_ms[3];
     out->ms_total = c->acc_ms[4];
+    return HGS_OK;
+}
+
+hgs_status hgs_autotune(hgs_ctx* c, void* stream, const char* cache_path, int32_t reps, hgs_plan* out) {
+    if (!c) return HGS_E_INVALID;
+    if (reps < 1 || reps > 1000) return fail(c, HGS_E_INVALID, "reps must be 1..1000");
+    if (!c->loaded || c->cams.empty()) return fail(c, HGS_E_STATE, "autotune needs a scene and cameras");
+    if (c->lod_mode == HGS_LOD_LEARNED && !c->mlp_loaded) return fail(c, HGS_E_STATE, "learned LOD without a network");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const std::string key = plan_key(c);
+    hgs_plan best{};
+    if (read_plan(cache_path, key, &best)) {
+        hgs_status st;
+        if ((st = hgs_set_option(c, HGS_OPT_BATCH_DEPTH, best.batch_depth)) ||
+            (st = hgs_set_option(c, HGS_OPT_PERSISTENT, best.persistent)) ||
+            (st = hgs_set_option(c, HGS_OPT_SORT_DIGIT_BITS, best.sort_digit_bits)))
+            return st;
+        best.from_cache = 1;
+        if (out) *out = best;
+        return HGS_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // internal outputs for every view
+    const int V = (int)c->cams.size();
+    size_t px = 0;
+    for (const hgs_camera& k : c->cams) px += (size_t)k.width * k.height;
+    DevMem buf;
+    hgs_status st = ensure(c, buf, px * 5 * sizeof(float));
+    if (st) return st;
+    std::vector<hgs_output> outs(V);
+    {
+        float* p = static_cast<float*>(buf.p);
+        for (int v = 0; v < V; ++v) {
+            const size_t n = (size_t)c->cams[v].width * c->cams[v].height;
+            outs[v].rgb = p;
+            outs[v].depth = p + 3 * n;
+            outs[v].alpha = p + 4 * n;
+            p += 5 * n;
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool graph = c->use_graph, timing = c->stage_timing, sync = c->sync_check;
+    auto restore = [&]() {
+        c->use_graph = graph;
+        c->sync_check = sync;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        release(buf);
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        restore();
+        return fail(c, HGS_E_HIP, "event creation failed");
+    }
+    if (timing && (st = hgs_set_option(c, HGS_OPT_STAGE_TIMING, 0))) {
+        restore();
+        return st;
+    }
+    c->use_graph = false;
+    c->sync_check = true;
+    invalidate_graph(c);
+    auto run = [&](int batch, int pers, int digits, double* ms) -> hgs_status {
+        c->ropts.batch = batch;
+        c->ropts.persistent = pers != 0;
+        c->sort_digit_bits = digits;
+        return time_plan(c, s, outs.data(), reps, e0, e1, ms);
+    };
+    double ms_default = 0.0;
+    if ((st = run(256, 0, 8, &ms_default))) {
+        restore();
+        return st;
+    }
+    best = hgs_plan{256, 0, 8, 0, ms_default, ms_default};
+    const int batches[3] = {64, 128, 256};
+    for (int b : batches)
+        for (int pers = 0; pers < 2; ++pers) {
+            if (b == 256 && pers == 0) continue;
+            double ms;
+            if ((st = run(b, pers, best.sort_digit_bits, &ms))) {
+                restore();
+                return st;
+            }
+            if (ms < best.ms) { best.batch_depth = b; best.persistent = pers; best.ms = ms; }
+        }
+    for (int d = 6; d <= 11; ++d) {
+        if (d == best.sort_digit_bits) continue;
+        double ms;
+        if ((st = run(best.batch_depth, best.persistent, d, &ms))) {
+            restore();
+            return st;
+        }
+        if (ms < best.ms) { best.sort_digit_bits = d; best.ms = ms; }
+    }
+    c->ropts.batch = best.batch_depth;
+    c->ropts.persistent = best.persistent != 0;
+    c->sort_digit_bits = best.sort_digit_bits;
+    c->last_valid = false;           // the last render went to internal buffers
+    restore();
+    invalidate_graph(c);
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f) return fail(c, HGS_E_INVALID, "cannot append to plan cache %s", cache_path);
+        std::fprintf(f, "%s %d %d %d %.6f %.6f\n", key.c_str(), best.batch_depth, best.persistent,
+                     best.sort_digit_bits, best.ms, best.ms_default);
+        std::fclose(f);
+    }
+    if (out) *out = best;
     return HGS_OK;
 }
 

@@ -38,14 +38,30 @@ __global__ void k_ranges_zero(uint2* ranges, uint32_t n) {
         ranges[i] = make_uint2(0, 0);
 }
 
+// [first, last + 1) of every tile's run in the tile-sorted keys, four keys
+// per thread and step (16-byte loads; key arrays start 256-byte aligned).
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const Counters* ctr, uint32_t cap, uint2* ranges,
                          uint32_t n_tiles) {
     const uint32_t P = min(ctr->pairs, cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
-        const uint32_t k = keys[i];
-        if (k >= n_tiles) continue;
-        if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
-        if (i + 1 == P || keys[i + 1] != k) ranges[k].y = i + 1;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; 4ull * q < P; q += gridDim.x * blockDim.x) {
+        const uint32_t i0 = 4 * q;
+        uint32_t k[6];
+        k[0] = i0 > 0 ? keys[i0 - 1] : 0xffffffffu;     // tile ids are below 2^31
+        if (i0 + 4 <= P) {
+            const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
+            k[1] = v.x; k[2] = v.y; k[3] = v.z; k[4] = v.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) k[1 + j] = i0 + j < P ? keys[i0 + j] : 0xffffffffu;
+        }
+        k[5] = i0 + 4 < P ? keys[i0 + 4] : 0xffffffffu;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t kk = k[1 + j];
+            if (kk >= n_tiles) continue;
+            if (k[j] != kk) ranges[kk].x = i0 + j;
+            if (k[j + 2] != kk) ranges[kk].y = i0 + j + 1;
+        }
     }
 }
 
@@ -117,18 +133,13 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
         const int j = threadIdx.x;
         if (j < (int)cnt) {
             const uint32_t val = a.vals[base + j];
-            const uint32_t e = val & kEntryMask;
+            const uint32_t e = val;
             const Proj P = a.proj[e < a.cut_cap ? e : 0u];
             const float u = (float)(P.u - dx0), v = (float)(P.v - dy0);
             s_a[j] = StageA{P.p, P.r, -fmaf(P.p, u, P.r * v), P.s};
             s_b[j] = StageB{-P.s * v, __log2f(P.opacity), P.z, P.c0};
             s_c[j] = StageC{P.c1, P.c2};
-            // rows of the strips the binning marked
-            const uint32_t strips = val >> kStripShift;
-            if (strips) {
-                const int lo = 4 * (__builtin_ctz(strips)), hi = 4 * (31 - __builtin_clz(strips)) + 3;
-                m = block_mask(u, v, P.p, P.r, P.s, lo, hi);
-            }
+            m = block_mask(u, v, P.p, P.r, P.s, 0, kTile - 1);
         }
         // 2. per-block lists in depth order
         uint32_t pre[kBlocks];

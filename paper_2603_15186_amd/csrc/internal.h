@@ -16,13 +16,13 @@ namespace hgs {
 constexpr int kTile = 16;                 // tile edge in pixels
 constexpr int kTilePx = kTile * kTile;    // pixels per tile
 constexpr int kMaxViews = 4096;
-// Pair values carry the entry index in the low 28 bits and, in the top 4,
-// which 4-row strips of the tile (one per compositor wave) the ellipse
-// reaches at a pixel centre.
-constexpr int kStrips = 4;
-constexpr int kStripRows = kTile / kStrips;
-constexpr int kStripShift = 28;
-constexpr uint32_t kEntryMask = (1u << kStripShift) - 1u;
+// Cut entries are addressed by 28-bit indices: the depth-sorted values
+// carry the entry index in the low 28 bits and min(tile count, 15) in the
+// top 4, so the pair-count scan reads tile counts in depth order without
+// gathering them (15: look the count up).
+constexpr int kNtShift = 28;
+constexpr uint32_t kEntryMask = (1u << kNtShift) - 1u;
+constexpr uint32_t kNtSat = 15u;
 
 // Overflow bits in Counters::overflow.
 constexpr uint32_t kOvFrontier = 1u;
@@ -58,6 +58,15 @@ struct alignas(16) Proj {
     float opacity;
     float c0, c1, c2;                // clamped RGB
     float z;                         // camera-space depth
+};
+
+// Where an entry bins: its tile rectangle and its view's tile layout
+// (16 bytes, so the depth-ordered emission gathers one record).
+struct alignas(16) BinRec {
+    ushort4 rc;                      // tile rectangle x0, y0, x1, y1 (inclusive)
+    uint32_t tile_base;              // first tile id of the view within its pass
+    uint16_t tiles_x;
+    uint16_t height;                 // image height in pixels
 };
 
 // Device counters of one render.
@@ -139,7 +148,7 @@ struct ProjectArgs {
     uint32_t* depth_key;
     uint32_t* depth_val;
     uint32_t* ntiles;
-    ushort4* rect;
+    BinRec* bins;
     bool exact_tiles;
     Counters* ctr;
 };
@@ -148,12 +157,10 @@ void launch_project(const ProjectArgs& a, hipStream_t s);
 // Pair emission in depth order: offsets = exclusive scan of ntiles over the
 // depth-sorted entries.
 struct EmitArgs {
-    const uint32_t* order;           // depth-sorted entry indices
+    const uint32_t* order;           // depth-sorted entries (index | min(tiles, 15) << 28)
     const uint32_t* ntiles;
-    const ushort4* rect;
+    const BinRec* bins;
     const Proj* proj;
-    const uint2* cut;
-    const ViewDev* views;
     uint32_t cut_cap;
     uint32_t* offsets;               // scratch [cut_cap]
     uint32_t* keys;

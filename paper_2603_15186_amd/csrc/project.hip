@@ -245,11 +245,16 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
             }
         }
         a.proj[i] = p;
-        a.rect[i] = rc;
+        BinRec br;
+        br.rc = rc;
+        br.tile_base = V.tile_base;
+        br.tiles_x = (uint16_t)V.tiles_x;
+        br.height = (uint16_t)V.height;
+        a.bins[i] = br;
         a.ntiles[i] = ntiles;
         // positive depths order as their bit patterns; unbinned entries last
         a.depth_key[i] = ntiles > 0 ? __float_as_uint(zf) : 0xffffffffu;
-        a.depth_val[i] = i;
+        a.depth_val[i] = i | (min(ntiles, kNtSat) << kNtShift);
         vis += ntiles > 0 ? 1u : 0u;
     }
     vis = wave_sum(vis);
@@ -269,6 +274,13 @@ struct ScanCtx {
     uint32_t pair_cap;
 };
 
+// Tile count of a depth-sorted value: carried in its top bits unless
+// saturated.
+__device__ __forceinline__ uint32_t tiles_of(const ScanCtx& c, uint32_t val, uint32_t n) {
+    const uint32_t nt = val >> kNtShift, e = val & kEntryMask;
+    return nt < kNtSat ? nt : (e < n ? c.ntiles[e] : 0u);
+}
+
 __device__ __forceinline__ void chunk_of(uint32_t n, int G, int b, uint32_t* lo, uint32_t* hi) {
     uint32_t chunk = ceil_div(n, (uint32_t)G);
     if (chunk < (uint32_t)kNT) chunk = kNT;
@@ -284,10 +296,7 @@ __global__ __launch_bounds__(kNT) void k_scan_reduce(ScanCtx c) {
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
     uint32_t acc = 0;
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += kNT) {
-        const uint32_t e = c.order[i];
-        acc += e < n ? c.ntiles[e] : 0u;
-    }
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kNT) acc += tiles_of(c, c.order[i], n);
     uint32_t tot;
     block_excl_scan<kNT>(acc, sh, &tot);
     if (threadIdx.x == 0) c.tmp[blockIdx.x] = make_uint4(tot, 0, 0, 0);
@@ -321,10 +330,7 @@ __global__ __launch_bounds__(kNT) void k_scan_write(ScanCtx c) {
     for (uint32_t s = lo; s < hi; s += kNT) {
         const uint32_t i = s + threadIdx.x;
         uint32_t x = 0;
-        if (i < hi) {
-            const uint32_t e = c.order[i];
-            x = e < n ? c.ntiles[e] : 0u;
-        }
+        if (i < hi) x = tiles_of(c, c.order[i], n);
         uint32_t tot;
         const uint32_t ex = block_excl_scan<kNT>(x, sh, &tot);
         if (i < hi) c.offsets[i] = off + ex;
@@ -332,68 +338,80 @@ __global__ __launch_bounds__(kNT) void k_scan_write(ScanCtx c) {
     }
 }
 
+// Pairs of one depth-ordered entry, handed to put(k, tile) in order.
+template <class F>
+__device__ __forceinline__ void entry_tiles(const EmitArgs& a, uint32_t e, uint32_t nt, const BinRec& br, F put) {
+    const ushort4 rc = br.rc;
+    const uint32_t tw = br.tiles_x;
+    const uint32_t all = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
+    uint32_t k = 0;
+    // the exact set is part of the rectangle: equal counts mean all of it
+    if (!a.exact_tiles || nt == all) {
+        for (int ty = rc.y; ty <= rc.w; ++ty)
+            for (int tx = rc.x; tx <= rc.z; ++tx) put(k++, br.tile_base + (uint32_t)ty * tw + (uint32_t)tx);
+        return;
+    }
+    const Proj p = a.proj[e];
+    const RowSpan r = row_span_init(p);
+    for (int ty = rc.y; ty <= rc.w; ++ty) {
+        int lo, hi;
+        row_tiles(r, p.u, p.v, ty, 0, br.height, rc.x, rc.z, &lo, &hi);
+        for (int tx = lo; tx <= hi; ++tx) put(k++, br.tile_base + (uint32_t)ty * tw + (uint32_t)tx);
+    }
+}
+
+// Each workgroup expands 256 consecutive depth-ordered entries into their
+// (tile, entry) pairs, which form one contiguous run of the pair arrays:
+// the run is assembled in LDS and written out coalesced; pairs past the
+// staging capacity are stored directly.
+constexpr uint32_t kEmitStage = 2048;
+
 __global__ __launch_bounds__(kNT) void k_emit(EmitArgs a) {
+    __shared__ uint32_t s_key[kEmitStage];
+    __shared__ uint32_t s_val[kEmitStage];
+    __shared__ uint32_t s_base, s_end;
     const uint32_t m = min(a.ctr->cut, a.cut_cap);
     const uint32_t cap = a.pair_cap;
-    for (uint32_t i = blockIdx.x * kNT + threadIdx.x; i < m; i += gridDim.x * kNT) {
-        const uint32_t e = a.order[i];
-        if (e >= m) continue;
-        const uint32_t nt = a.ntiles[e];
-        if (nt == 0) continue;
-        uint32_t pos = a.offsets[i];
-        const ushort4 rc = a.rect[e];
-        const ViewDev& V = a.views[a.cut[e].y];
-        const uint32_t tb = V.tile_base;
-        const int tw = V.tiles_x;
-        if (!a.exact_tiles) {
-            for (int ty = rc.y; ty <= rc.w; ++ty)
-                for (int tx = rc.x; tx <= rc.z; ++tx) {
-                    if (pos < cap) {
-                        a.keys[pos] = tb + (uint32_t)(ty * tw + tx);
-                        a.vals[pos] = e | (0xFu << kStripShift);
-                    }
-                    ++pos;
-                }
-            continue;
+    for (uint32_t first = blockIdx.x * kNT; first < m; first += gridDim.x * kNT) {
+        const uint32_t i = first + threadIdx.x;
+        uint32_t e = 0, nt = 0, pos = 0;
+        if (i < m) {
+            const uint32_t val = a.order[i];
+            e = val & kEntryMask;
+            nt = val >> kNtShift;
+            if (nt == kNtSat) nt = e < m ? a.ntiles[e] : 0u;
+            pos = a.offsets[i];
         }
-        // exact tiles, each tagged with the 4-row strips (one per wave of the
-        // compositor) that hold a pixel centre inside the ellipse
-        const Proj p = a.proj[e];
-        const RowSpan r = row_span_init(p);
-        const uint32_t all = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
-        for (int ty = rc.y; ty <= rc.w; ++ty) {
-            int lo, hi;
-            if (all <= 1) {
-                lo = rc.x;
-                hi = rc.z;
-            } else {
-                row_tiles(r, p.u, p.v, ty, V.width, V.height, rc.x, rc.z, &lo, &hi);
-            }
-            if (lo > hi) continue;
-            double sa[kStrips], sb[kStrips];
-            bool sv[kStrips];
-#pragma unroll
-            for (int q = 0; q < kStrips; ++q) {
-                const int y0 = ty * kTile + q * kStripRows;
-                sv[q] = y0 < V.height &&
-                        band_span(r, p.u, p.v, y0 + 0.5, fmin((double)(y0 + kStripRows - 1), (double)(V.height - 1)) + 0.5,
-                                  &sa[q], &sb[q]);
-            }
-            const uint32_t row = tb + (uint32_t)(ty * tw);
-            for (int tx = lo; tx <= hi; ++tx) {
-                const double x0c = tx * kTile + 0.5;
-                const double x1c = fmin((double)(tx * kTile + kTile - 1), (double)(V.width - 1)) + 0.5;
-                uint32_t mask = 0;
-#pragma unroll
-                for (int q = 0; q < kStrips; ++q)
-                    if (sv[q] && sb[q] >= x0c && sa[q] <= x1c) mask |= 1u << q;
-                if (pos < cap) {
-                    a.keys[pos] = row + (uint32_t)tx;
-                    a.vals[pos] = e | (mask << kStripShift);
+        if (threadIdx.x == 0) {
+            s_base = pos;
+            s_end = pos;
+        }
+        __syncthreads();
+        const uint32_t base = s_base;
+        if (nt) {
+            atomicMax(&s_end, pos + nt);
+            const BinRec br = a.bins[e];
+            const uint32_t lp = pos - base;
+            entry_tiles(a, e, nt, br, [&](uint32_t k, uint32_t tile) {
+                const uint32_t L = lp + k;
+                if (L < kEmitStage) {
+                    s_key[L] = tile;
+                    s_val[L] = e;
+                } else if (pos + k < cap) {
+                    a.keys[pos + k] = tile;
+                    a.vals[pos + k] = e;
                 }
-                ++pos;
+            });
+        }
+        __syncthreads();
+        const uint32_t len = min(s_end - base, kEmitStage);
+        for (uint32_t q = threadIdx.x; q < len; q += kNT) {
+            if (base + q < cap) {
+                a.keys[base + q] = s_key[q];
+                a.vals[base + q] = s_val[q];
             }
         }
+        __syncthreads();
     }
 }
 
@@ -417,7 +435,7 @@ void launch_emit(const EmitArgs& a, hipStream_t s) {
     k_scan_reduce<<<G, kNT, 0, s>>>(c);
     k_scan_blocks<<<1, 1024, 0, s>>>(c, G);
     k_scan_write<<<G, kNT, 0, s>>>(c);
-    k_emit<<<4096, kNT, 0, s>>>(a);
+    k_emit<<<2048, kNT, 0, s>>>(a);
 }
 
 }  // namespace hgs

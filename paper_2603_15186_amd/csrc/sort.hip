@@ -4,7 +4,8 @@
 // ceil(bits / passes) bits (at most 11: 2048 buckets), so a 17-bit tile key
 // takes two passes and a 32-bit depth key three.  Each pass is three
 // launches with no inter-workgroup waiting:
-//   upsweep   : each block histograms the digits of its contiguous chunk;
+//   upsweep   : each block histograms the digits of its contiguous chunk
+//               (LDS atomics into per-wave histograms);
 //   row scan  : one block per digit scans that digit's per-block counts;
 //   downsweep : each block ranks its chunk stably -- lanes with equal digits
 //               are found by ballots over the digit bits, per-wave counters
@@ -48,26 +49,39 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
     return m;
 }
 
+// Digit histogram of a block's chunk: per-wave LDS histograms take one
+// atomic add per key (counts do not depend on order), four keys per thread
+// and step with 16-byte loads (chunks start at multiples of kSub).
 template <int DB>
 __global__ __launch_bounds__(kNT) void k_upsweep(const uint32_t* __restrict__ keys, const uint32_t* count,
                                                  uint32_t cap, int shift, uint32_t MASK, uint32_t* __restrict__ hist) {
     constexpr int NB = 1 << DB;
-    __shared__ uint32_t h[NB];
+    __shared__ uint32_t h[kNW][NB];
     const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
-    for (int i = t; i < NB; i += kNT) h[i] = 0;
+    uint32_t* hw = h[t / kWave];
+    for (int i = t; i < NB; i += kNT) {
+#pragma unroll
+        for (int w = 0; w < kNW; ++w) h[w][i] = 0;
+    }
     __syncthreads();
     uint32_t lo, hi;
     chunk_of(*count, cap, G, b, &lo, &hi);
-    for (uint32_t base = lo; base < hi; base += kNT) {
-        const uint32_t i = base + t;
-        const bool valid = i < hi;
-        const uint32_t d = valid ? (keys[i] >> shift) & MASK : 0u;
-        const uint64_t act = __ballot(valid);
-        const uint64_t peers = match_digit<DB>(d, act);
-        if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    uint32_t base = lo;
+    for (; base + 4 * kNT <= hi; base += 4 * kNT) {
+        const uint4 k4 = *reinterpret_cast<const uint4*>(keys + base + 4 * t);
+        atomicAdd(&hw[(k4.x >> shift) & MASK], 1u);
+        atomicAdd(&hw[(k4.y >> shift) & MASK], 1u);
+        atomicAdd(&hw[(k4.z >> shift) & MASK], 1u);
+        atomicAdd(&hw[(k4.w >> shift) & MASK], 1u);
     }
+    for (uint32_t i = base + t; i < hi; i += kNT) atomicAdd(&hw[(keys[i] >> shift) & MASK], 1u);
     __syncthreads();
-    for (int i = t; i < NB; i += kNT) hist[(size_t)i * G + b] = h[i];   // digit-major
+    for (int i = t; i < NB; i += kNT) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kNW; ++w) c += h[w][i];
+        hist[(size_t)i * G + b] = c;   // digit-major
+    }
 }
 
 // One block per digit: exclusive scan of hist[d][0..G) in place; the digit

@@ -77,6 +77,11 @@ class hgs_stats(ctypes.Structure):
                 ("ms_composite", ctypes.c_double), ("ms_total", ctypes.c_double), ("passes", ctypes.c_int64)]
 
 
+class hgs_plan(ctypes.Structure):
+    _fields_ = [("batch_depth", ctypes.c_int32), ("persistent", ctypes.c_int32), ("sort_digit_bits", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
+
+
 # (name, restype, argtypes) of every exported entry point
 _P = ctypes.c_void_p
 EXPORTS = [
@@ -94,6 +99,7 @@ EXPORTS = [
     ("hgs_get_cut", ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     ("hgs_get_projected", ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     ("hgs_get_stats", ctypes.c_int32, [_P, ctypes.POINTER(hgs_stats)]),
+    ("hgs_autotune", ctypes.c_int32, [_P, _P, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(hgs_plan)]),
     ("hgs_sort_pairs", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32]),
     ("hgs_set_keep_nodes", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
     ("hgs_lod_candidates", ctypes.c_int32, [_P, _P, ctypes.c_float, _P, _P, _P, ctypes.c_int64,
@@ -289,6 +295,14 @@ class Renderer:
         s = hgs_stats()
         self._check(self.lib.hgs_get_stats(self.ctx, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in hgs_stats._fields_}
+
+    def autotune(self, cache_path=None, reps=3, stream=None) -> dict:
+        """Pick the fastest image-preserving launch plan for the current
+        scene, views and LOD (see hgs_autotune) and keep it."""
+        p = hgs_plan()
+        path = None if cache_path is None else os.fspath(cache_path).encode()
+        self._check(self.lib.hgs_autotune(self.ctx, self._stream(stream), path, int(reps), ctypes.byref(p)))
+        return {k: getattr(p, k) for k, _ in hgs_plan._fields_}
 
     # ------------------------------------------------------------ learned LOD
     def _stream(self, stream):

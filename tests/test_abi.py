@@ -1,5 +1,6 @@
 """The C ABI without a GPU: the library loads, exports every entry point the
 header declares, and rejects bad scenes on the host."""
+import ctypes
 import re
 import os
 
@@ -43,6 +44,15 @@ def test_stats_struct_matches_header_fields():
     for decl in re.findall(r"(?:int64_t|double) ([^;]+);", body):
         names += [n.strip() for n in decl.split(",")]
     assert [n for n, _ in hgs.hgs_stats._fields_] == names
+
+
+def test_plan_struct_matches_header_fields():
+    src = open(os.path.join(ROOT, "include", "hgs.h")).read()
+    body = src[src.index("typedef struct {\n    int32_t batch_depth;"):src.index("} hgs_plan;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = [n.strip() for n in re.findall(r"(?:int32_t|double) ([^;]+);", body)]
+    assert [n for n, _ in hgs.hgs_plan._fields_] == names
+    assert ctypes.sizeof(hgs.hgs_plan) == 4 * 4 + 2 * 8
 
 
 def test_binding_struct_sizes_match_header_layout():

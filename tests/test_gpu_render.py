@@ -268,6 +268,36 @@ def test_multi_pass_batches_equal_one_pass(R, plan_small):
         R.set_option(hgs.HGS_OPT_PASS_VIEWS, 0)
 
 
+def test_autotune_keeps_images_and_caches_the_plan(R, plan_small, tmp_path):
+    """The autotuner's plan renders the same images bitwise; a second call
+    with the same cache file applies the stored plan without timing."""
+    scene, cams = plan_small
+    hgs = _hgs()
+    views = [_small_cam(cams[1], 320, 240), cams[7], _small_cam(cams[9], 33, 17)]
+    ref = _render(R, scene, views, batch_depth=256, persistent=0, sort_digit_bits=8)
+    cache = tmp_path / "plans.txt"
+    try:
+        plan = R.autotune(cache, reps=2)
+        print("plan:", plan, flush=True)
+        assert plan["batch_depth"] in (64, 128, 256) and plan["persistent"] in (0, 1)
+        assert 6 <= plan["sort_digit_bits"] <= 11 and plan["from_cache"] == 0
+        assert 0 < plan["ms"] <= plan["ms_default"]
+        outs = R.render()
+        torch.cuda.synchronize()
+        for v in range(len(views)):
+            for a, b in zip(ref[v], outs[v]):
+                assert np.array_equal(a, b.cpu().numpy()), v
+        again = R.autotune(cache, reps=2)
+        assert again["from_cache"] == 1
+        assert (again["batch_depth"], again["persistent"], again["sort_digit_bits"]) == \
+            (plan["batch_depth"], plan["persistent"], plan["sort_digit_bits"])
+        assert len(cache.read_text().splitlines()) == 1
+    finally:
+        R.set_option(hgs.HGS_OPT_BATCH_DEPTH, 256)
+        R.set_option(hgs.HGS_OPT_PERSISTENT, 0)
+        R.set_option(hgs.HGS_OPT_SORT_DIGIT_BITS, 8)
+
+
 # ---------------------------------------------------------- full-size scene
 
 @pytest.fixture(scope="module")
