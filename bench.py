@@ -56,9 +56,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels instead of replaying a graph")
-    ap.add_argument("--workload", default="plan2m-lod", choices=["plan2m-lod", "plan8m"],
-                    help="plan2m-lod (the metric's workload) or plan8m (256 mixed-resolution views of the "
-                         "8M-leaf plan, threshold cuts; reported for reference)")
+    ap.add_argument("--workload", default="plan2m-lod", choices=["plan2m-lod", "plan8m", "building30m"],
+                    help="plan2m-lod (the metric's workload), plan8m (256 mixed-resolution views of the "
+                         "8M-leaf plan, threshold cuts) or building30m (64 1080p views of the 30M-leaf "
+                         "two-floor building, learned cut); the last two are reported for reference")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed batched learned path (for profilers): no quality evaluation, no "
                          "threshold or single-view comparison")
@@ -180,10 +181,79 @@ def run_plan8m(args):
     r.close()
 
 
+def run_building(args):
+    """64 views at 1920x1080 (f = 1300) along trajectories on both floors of
+    the 30M-leaf building, rendered in one call with the learned cut (the
+    2M-leaf plan's network; threshold fallback) and with the tau = 1 cut.
+    Frames/s, Mpixels/s, peak device memory in use, and PSNR of 8 sampled
+    views against the full-leaf render and the surfaces' ground truth."""
+    import numpy as np
+    import torch
+    from paper_2603_15186_amd import hgs, lod
+    from paper_2603_15186_amd.synth import workloads as W
+    t = time.perf_counter()
+    scene, views, plan = W.building30m(with_plan=True)
+    log(f"building30m: {scene.n} nodes, {len(views)} views ({time.perf_counter() - t:.1f} s)")
+    r = hgs.Renderer(0)
+    r.load_scene(scene)
+    r.set_surfaces(plan.surfaces)
+    model = lod.LodModel.load(args.model or lod.default_model_path())
+    model.install(r)
+    free0, total = torch.cuda.mem_get_info()
+    peak = total - free0
+    r.set_cameras(views)
+    outs = r.alloc_outputs()
+    px = sum(c.width * c.height for c in views)
+    res = {}
+    for name, mode in (("learned", hgs.HGS_LOD_LEARNED), ("tau1", hgs.HGS_LOD_THRESHOLD)):
+        r.set_lod(mode, 1.0)
+        plan_ = r.autotune(reps=2)
+        r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
+        ms, _ = timed_loop(r, hgs, torch, [views], outs, args.steps, args.warmup, False)
+        free, _ = torch.cuda.mem_get_info()
+        peak = max(peak, total - free)
+        r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+        _, st = timed_loop(r, hgs, torch, [views], outs, 2, 1, True)
+        n = st["timed_renders"]
+        res[name] = {"ms_per_batch": ms, "frames_s": len(views) / (ms * 1e-3), "mpix_s": px / (ms * 1e-3) / 1e6,
+                     "cut": st["cut_size"], "pairs": st["pairs"], "passes": st["passes"],
+                     "plan": {k: plan_[k] for k in ("batch_depth", "persistent", "sort_digit_bits")},
+                     "stage_ms": {k: st["ms_" + k] / n for k in ("cut", "project", "sort", "composite")}}
+        log(f"{name}: {ms:.2f} ms per batch, {res[name]['mpix_s']:.0f} Mpix/s, cut {st['cut_size']}")
+    del outs
+    torch.cuda.empty_cache()
+    # quality on 8 sampled views (untimed)
+    sample = views[::8]
+    full = lod.render_rgb(r, sample, hgs.HGS_LOD_ALL_LEAVES, 1.0)
+    gt = lod.reference_images(r, sample)
+    q = {}
+    for name, mode in (("learned", hgs.HGS_LOD_LEARNED), ("tau1", hgs.HGS_LOD_THRESHOLD)):
+        img = lod.render_rgb(r, sample, mode, 1.0)
+        q[name] = {"psnr_vs_full_leaf_db": float(np.mean(lod.psnr(r, img, full))),
+                   "psnr_vs_surfaces_db": float(np.mean(lod.psnr(r, img, gt)))}
+        free, _ = torch.cuda.mem_get_info()
+        peak = max(peak, total - free)
+    log(f"quality: {q}")
+    out = {"metric": "Mpixels/s, 64 views at 1920x1080 of the 30M-leaf building in one call (learned cut)",
+           "value": res["learned"]["mpix_s"], "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res["learned"]["ms_per_batch"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "building30m 64 views 1920x1080 fx=1300, learned cut (2M-leaf plan network, "
+                                  "threshold tau=1 fallback)", "nodes": scene.n, "pixels_per_batch": px,
+                      "parallelism": "single GPU"},
+           "extra": {"render": res, "quality_8_views": q, "peak_device_gb": peak / 1e9,
+                     "frames_s_learned": res["learned"]["frames_s"],
+                     "speedup_learned_vs_tau1": res["tau1"]["ms_per_batch"] / res["learned"]["ms_per_batch"]}}
+    print(json.dumps(out), flush=True)
+    r.close()
+
+
 def main():
     args = parse()
     if args.workload == "plan8m":
         return run_plan8m(args)
+    if args.workload == "building30m":
+        return run_building(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: the "
@@ -242,12 +312,15 @@ def main():
     model.install(r)
     r.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
     r.set_option(hgs.HGS_OPT_COUNT_NALG, 1)
-    n_alg = 0
+    n_alg = n_eval = 0
     for bt in batches:
         r.set_cameras(bt)
         r.render(outs)
-        n_alg += r.stats()["n_alg"]
+        st0 = r.stats()
+        n_alg += st0["n_alg"]
+        n_eval += st0["n_eval"]
     n_alg_step = n_alg / len(batches)
+    n_eval_step = n_eval / len(batches)
     r.set_option(hgs.HGS_OPT_COUNT_NALG, 0)
     # launch plan (batch depth, persistent compositing, radix digit width)
     # picked by the library's autotuner on the first batch; images do not
@@ -324,6 +397,7 @@ def main():
         "learned_p_star": model.p_star, "learned_s_hi": model.s_hi, "learned_model": origin,
         "stage_ms_per_step_eager": stage, "ms_per_step_eager": ms_learn_eager, "graph": not args.no_graph,
         "n_alg_per_step": n_alg_step, "held_out_poses": len(eval_cams),
+        "composite_slots_per_step": n_eval_step, "composite_lane_efficiency": n_alg_step / max(n_eval_step, 1),
         "cut_entries_per_step": st["cut_size"], "visible_per_step": st["visible"], "pairs_per_step": st["pairs"],
     }
     cpu = None

@@ -144,6 +144,8 @@ typedef struct {
     int64_t graph_launches;       /* renders replayed from a captured graph */
     double ms_cut, ms_project, ms_sort, ms_composite, ms_total;
     int64_t passes;               /* pipeline passes of the last render */
+    int64_t n_eval;               /* (pixel, list entry) slots the compositor walked,
+                                     including q > 9 and stopped pixels (if counted) */
 } hgs_stats;
 
 /* Create a context on HIP device `device`.  *out is set on success. */

@@ -182,7 +182,8 @@ hgs_status validate(const hgs_gaussians* g, const hgs_hierarchy* h, std::string*
     if (h->n_nodes != g->n) return bad(HGS_E_BAD_HIERARCHY, "n_nodes differs from the Gaussian count");
     if (!h->parent || !h->first_child || !h->child_count || !h->bound || !h->level_offset)
         return bad(HGS_E_BAD_HIERARCHY, "a hierarchy array is NULL");
-    if (h->n_levels < 1 || h->n_levels > 64) return bad(HGS_E_BAD_HIERARCHY, "n_levels must be 1..64");
+    if (h->n_levels < 1 || h->n_levels > kMaxLevels)
+        return bad(HGS_E_BAD_HIERARCHY, "n_levels must be 1.." + std::to_string(kMaxLevels));
     const int64_t n = h->n_nodes;
     if (h->level_offset[0] != 0 || h->level_offset[h->n_levels] != n)
         return bad(HGS_E_BAD_HIERARCHY, "level_offset must start at 0 and end at n_nodes");
@@ -1099,6 +1100,7 @@ hgs_status hgs_get_stats(hgs_ctx* c, hgs_stats* out) {
         out->visible += k.visible;
         out->pairs += std::min(k.pairs, c->pair_cap);
         out->n_alg += (int64_t)k.nalg;
+        out->n_eval += (int64_t)k.neval;
     }
     out->passes = np;
     out->tiles = c->total_tiles;

@@ -6,12 +6,13 @@
 //  1. staging: thread j turns entry j into a tile-relative FP32 record (the
 //     FP64 2D mean is made tile-relative before rounding) and marks the 4x4
 //     blocks holding a pixel centre that its 3-sigma ellipse may reach
-//     (exact row by row, with a relative slack of 1e-3 on the bound 9);
+//     (closed-form extent per band of four rows, with a relative slack of
+//     1e-3 on the bound 9);
 //  2. compaction: for every block, the indices of its marked entries in
 //     depth order (ballots and prefix counts);
 //  3. compositing: the 16 lanes of a block walk that block's list; a wave
-//     runs to the longest of its four lists and shorter lists read a record
-//     that contributes nothing.  The body has no branches:
+//     runs to the longest of its four lists and shorter lists are padded
+//     with a record that contributes nothing.  The body has no branches:
 //       q = t1^2 + t2^2 with t1 = p dx + r dy = p x + r y + c1 and
 //           t2 = s dy = s y + c2 around the tile origin;
 //       alpha = min(0.99, 2^(log2(o) - q log2(e)/2)) = min(0.99, o e^(-q/2)),
@@ -75,26 +76,30 @@ struct alignas(16) StageA { float p, r, c1, s; };
 struct alignas(16) StageB { float c2, lo, z, col0; };
 struct alignas(16) StageC { float col1, col2; };
 
-// Blocks (bit 4 * band + column group) holding a pixel centre with
-// q <= kQMask, scanning pixel rows row_lo..row_hi.
-__device__ __forceinline__ uint32_t block_mask(float u, float v, float p, float r, float s, int row_lo,
-                                               int row_hi) {
+// Blocks (bit 4 * band + column group) that may hold a pixel centre with
+// q <= kQMask.  Per band of four pixel rows, the ellipse's x-extent over the
+// band's continuous range of centre heights is found in closed form: for a
+// height dy the ellipse spans x = u + (-r dy +- sqrt(Q - (s dy)^2)) / p, and
+// the extreme ends over the band sit at its heights nearest to
+// dy* = -/+ r sqrt(Q) / (s sqrt(r^2 + s^2)) (the rightmost and leftmost
+// points).  The extent covers every row's span, so no block is missed.
+__device__ __forceinline__ uint32_t block_mask(float u, float v, float p, float r, float s) {
     const float R = sqrtf(kQMask) / s;
-    row_lo = max(row_lo, (int)ceilf(v - R - 0.5f));
-    row_hi = min(row_hi, (int)floorf(v + R - 0.5f));
+    const float ystar = -r * sqrtf(kQMask) / (s * sqrtf(fmaf(r, r, s * s)));
     const float ip = 1.f / p;
     uint32_t m = 0;
-    for (int row = row_lo; row <= row_hi; ++row) {
-        const float dy = (float)row + 0.5f - v;
-        const float sd = s * dy;
-        const float h = sqrtf(fmaxf(fmaf(-sd, sd, kQMask), 0.f));
-        const float rd = r * dy;
-        const float xa = u - (rd + h) * ip, xb = u + (h - rd) * ip;
-        const int c0 = max(0, (int)ceilf(xa - 0.5f)), c1 = min(kTile - 1, (int)floorf(xb - 0.5f));
-        if (c0 <= c1) {
-            const uint32_t gl = (uint32_t)c0 >> 2, gh = (uint32_t)c1 >> 2;
-            m |= ((2u << gh) - (1u << gl)) << (4 * (row >> 2));
-        }
+#pragma unroll
+    for (int band = 0; band < kTile / 4; ++band) {
+        const float y0 = fmaxf((float)(4 * band) + 0.5f - v, -R);
+        const float y1 = fminf((float)(4 * band) + 3.5f - v, R);
+        const float yr = fminf(fmaxf(ystar, y0), y1), yl = fminf(fmaxf(-ystar, y0), y1);
+        const float sr = s * yr, sl = s * yl;
+        const float xr = u + (sqrtf(fmaxf(fmaf(-sr, sr, kQMask), 0.f)) - r * yr) * ip;
+        const float xl = u - (sqrtf(fmaxf(fmaf(-sl, sl, kQMask), 0.f)) + r * yl) * ip;
+        // 1e-3 px absorbs the rounding of this single-precision evaluation
+        const int c0 = max(0, (int)ceilf(xl - 0.501f)), c1 = min(kTile - 1, (int)floorf(xr - 0.499f));
+        if (y0 <= y1 && c0 <= c1)
+            m |= ((2u << ((uint32_t)c1 >> 2)) - (1u << ((uint32_t)c0 >> 2))) << (4 * band);
     }
     return m;
 }
@@ -120,7 +125,7 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
     const uint2 rg = a.ranges[tile];
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
     bool live = inside;
-    uint32_t nalg = 0;
+    uint32_t nalg = 0, neval = 0;
     if (threadIdx.x == 0) {                             // record that adds nothing
         s_a[BATCH] = StageA{0.f, 0.f, 0.f, 0.f};
         s_b[BATCH] = StageB{0.f, -__builtin_inff(), 0.f, 0.f};
@@ -139,7 +144,7 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
             s_a[j] = StageA{P.p, P.r, -fmaf(P.p, u, P.r * v), P.s};
             s_b[j] = StageB{-P.s * v, __log2f(P.opacity), P.z, P.c0};
             s_c[j] = StageC{P.c1, P.c2};
-            m = block_mask(u, v, P.p, P.r, P.s, 0, kTile - 1);
+            m = block_mask(u, v, P.p, P.r, P.s);
         }
         // 2. per-block lists in depth order
         uint32_t pre[kBlocks];
@@ -164,21 +169,23 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
             s_n[threadIdx.x] = t;
         }
         __syncthreads();
-        // 3. compositing
+        // 3. compositing: pad this block's list with the empty record up to
+        // the wave's step count, so every step reads four offsets as they are
         const uint32_t n_mine = s_n[gid];
         const uint32_t n_wave = __builtin_amdgcn_readfirstlane(
             max(max(s_n[w * 4], s_n[w * 4 + 1]), max(s_n[w * 4 + 2], s_n[w * 4 + 3])));
-        // four list entries per step (lists hold record byte offsets and are
-        // padded with the empty record)
-        const uint2* list4 = reinterpret_cast<const uint2*>(s_idx + gid * BATCH);
         const uint32_t n_step = (n_wave + 3u) & ~3u;
+        uint16_t* list = s_idx + gid * BATCH;
+        for (uint32_t p = n_mine + (uint32_t)k; p < n_step; p += 16) list[p] = (uint16_t)(BATCH * 16);
+        __syncthreads();
+        const uint2* list4 = reinterpret_cast<const uint2*>(list);
         for (uint32_t i = 0; i < n_step; i += 4) {
             const uint2 q4 = list4[i >> 2];
             const uint32_t id4[4] = {q4.x & 0xffffu, q4.x >> 16, q4.y & 0xffffu, q4.y >> 16};
+            if (COUNT) neval += 4;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const bool listed = i + u < n_mine;
-                const uint32_t off = listed ? id4[u] : (uint32_t)BATCH * 16u;
+                const uint32_t off = id4[u];
                 const StageA A = *reinterpret_cast<const StageA*>(reinterpret_cast<const char*>(s_a) + off);
                 const StageB B = *reinterpret_cast<const StageB*>(reinterpret_cast<const char*>(s_b) + off);
                 const StageC Cc = *reinterpret_cast<const StageC*>(reinterpret_cast<const char*>(s_c) + off);
@@ -187,7 +194,7 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
                 const float q = fmaf(t1, t1, t2 * t2);
                 const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, B.lo)));
                 const bool in = q <= kQMax;
-                if (COUNT) nalg += (live && in && listed) ? 1u : 0u;
+                if (COUNT) nalg += (live && in && i + u < n_mine) ? 1u : 0u;
                 const float al = (in && live && al0 >= 1.f / 255.f) ? al0 : 0.f;
                 const float Tn = T * (1.f - al);
                 const bool stop = Tn < 1e-4f;
@@ -213,13 +220,20 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
         if (V.alpha) V.alpha[o] = 1.f - T;
     }
     if (COUNT) {
-        uint32_t sum = wave_sum(nalg);
-        if (lane == 0) s_red[w] = sum;
+        const uint32_t sum = wave_sum(nalg);
+        if (lane == 0) {
+            s_red[2 * w] = sum;
+            s_red[2 * w + 1] = neval * kWave;          // uniform per wave
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            unsigned long long t = 0;
-            for (int i = 0; i < kNT / kWave; ++i) t += s_red[i];
+            unsigned long long t = 0, ev = 0;
+            for (int i = 0; i < kNT / kWave; ++i) {
+                t += s_red[2 * i];
+                ev += s_red[2 * i + 1];
+            }
             if (t) atomicAdd(&a.ctr->nalg, t);
+            if (ev) atomicAdd(&a.ctr->neval, ev);
         }
         __syncthreads();
     }
@@ -234,7 +248,7 @@ struct Shared {
     alignas(16) uint16_t idx[kBlocks * BATCH];
     uint32_t wc[(kNT / kWave) * kBlocks];
     uint32_t n[kBlocks];
-    uint32_t red[kNT / kWave];
+    uint32_t red[2 * (kNT / kWave)];
     uint32_t tile;
 };
 

@@ -25,15 +25,16 @@ namespace hgs {
 namespace {
 
 constexpr int kNT = 256;
+constexpr int kNW = kNT / kWave;
 
 enum : uint32_t { kDrop = 0, kEmit = 1, kExpand = 2, kCandidate = 4 };
 
 // Decide a node for a view: dropped (sphere outside the frustum), emitted,
 // or expanded into its children.  kCandidate is or-ed into kExpand when the
 // threshold rule refines the node and its projected size is at most s_hi
-// pixels: the band in which the learned rule may keep the node instead.
-__device__ __noinline__ uint32_t node_decision(const ViewDev& V, int k, float4 b, int nchild, int mode,
-                                               const void* mlp, const float* sw, double s_hi, int level) {
+// pixels: the band in which the learned rule may keep the node instead (that
+// choice is made by k_level_mlp).
+__device__ __forceinline__ uint32_t node_decision(const ViewDev& V, int k, float4 b, int nchild, double s_hi) {
 #pragma clang fp contract(off)
     NodeGeom g;
     node_geometry(V, b, &g);
@@ -54,9 +55,6 @@ __device__ __noinline__ uint32_t node_decision(const ViewDev& V, int k, float4 b
     if (!(lhs > rhs)) return kEmit;
     if (k == V.keep_node) return kEmit;
     const bool cand = lhs <= (s_hi * s_hi) * g.d2;
-    if (cand && mode == HGS_LOD_LEARNED && mlp != nullptr) {
-        if (!lod_mlp_expand(*(const LodMlpDev*)mlp, sw, V, k, b, g, level)) return kEmit;
-    }
     return kExpand | (cand ? kCandidate : 0u);
 }
 
@@ -72,6 +70,7 @@ struct LevelCtx {
     uint32_t cut_cap;
     uint4* tmp;               // [G] block counts, then offsets; [G] = level bases
     uint8_t* dec;             // per frontier entry: decision of the count pass
+    bool defer;               // learned cut: candidates are decided by k_level_mlp
     Counters* ctr;
     int mode;
     const void* mlp;
@@ -108,10 +107,11 @@ __device__ __forceinline__ const float* stage_weights(const LevelCtx& c, float* 
 }
 
 // Count pass: decide every entry of the block's chunk once, remember the
-// decision for the emit pass, reduce the counts.
+// decision for the emit pass, reduce the counts.  In the learned cut a
+// candidate is counted as refined; k_level_mlp may then turn it into an
+// emitted node and correct the block's counts.
 __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap) {
     __shared__ uint4 sh[kNT / kWave + 1];
-    __shared__ float s_w[kMlpParams];
     uint32_t n = *c.in_count;
     n = n < in_cap ? n : in_cap;
     uint32_t lo, hi;
@@ -120,22 +120,107 @@ __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap
         if (threadIdx.x == 0) c.tmp[blockIdx.x] = make_uint4(0, 0, 0, 0);
         return;
     }
-    const float* sw = stage_weights(c, s_w);
     uint4 acc = make_uint4(0, 0, 0, 0);
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += kNT) {
-        const uint2 e = c.in[i];
-        const float4 b = c.bound[e.x];
-        const int2 ch = c.child[e.x];
-        const uint32_t d = node_decision(c.views[e.y], (int)e.x, b, ch.y, c.mode, c.mlp, sw, c.s_hi, c.level);
+    auto decide = [&](uint32_t i, bool valid, uint2 e, float4 b, int2 ch) {
+        if (!valid) return;
+        const uint32_t d = node_decision(c.views[e.y], (int)e.x, b, ch.y, c.s_hi);
         c.dec[i] = (uint8_t)d;
         const uint4 r = counts_of(c, d, ch.y);
         acc.x += r.x;
         acc.y += r.y;
         acc.z += r.z;
+    };
+    // two entries per lane and step: their gathers are in flight together
+    for (uint32_t s = lo; s < hi; s += 2 * kNT) {
+        const uint32_t i0 = s + threadIdx.x, i1 = i0 + kNT;
+        const bool v0 = i0 < hi, v1 = i1 < hi;
+        const uint2 e0 = v0 ? c.in[i0] : make_uint2(0, 0);
+        const uint2 e1 = v1 ? c.in[i1] : make_uint2(0, 0);
+        const float4 b0 = c.bound[e0.x], b1 = c.bound[e1.x];
+        const int2 ch0 = c.child[e0.x], ch1 = c.child[e1.x];
+        decide(i0, v0, e0, b0, ch0);
+        decide(i1, v1, e1, b1, ch1);
     }
     uint4 tot;
     block_excl_scan4<kNT>(acc, sh, &tot);
     if (threadIdx.x == 0) c.tmp[blockIdx.x] = tot;
+}
+
+// Learned-cut candidates of one level.  Block b takes the count pass's
+// chunk b, gathers its candidates (decision bit kCandidate) into an LDS
+// queue in order and evaluates them 256 at a time, one per lane.  The
+// network keeps a node (emits it) unless its probability reaches p*; the
+// block's counts lose each kept node's children and gain one emitted entry.
+__global__ __launch_bounds__(kNT) void k_level_mlp(LevelCtx c, uint32_t in_cap) {
+    __shared__ float s_w[kMlpParams];
+    __shared__ uint32_t s_q[2 * kNT];
+    __shared__ uint32_t s_wc[kNW + 1];
+    __shared__ uint32_t s_n;
+    __shared__ uint2 s_fix[kNW];
+    uint32_t n = *c.in_count;
+    n = n < in_cap ? n : in_cap;
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
+    if (lo >= hi) return;
+    const float* sw = stage_weights(c, s_w);
+    const LodMlpDev& m = *(const LodMlpDev*)c.mlp;
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) s_n = 0;
+    uint32_t kept_n = 0, lost = 0;
+    auto evaluate = [&](uint32_t cnt) {
+        if (threadIdx.x < cnt) {
+            const uint32_t i = s_q[threadIdx.x];
+            const uint2 e = c.in[i];
+            const ViewDev& V = c.views[e.y];
+            const float4 b = c.bound[e.x];
+            NodeGeom g;
+            node_geometry(V, b, &g);
+            if (!lod_mlp_expand(m, sw, V, (int)e.x, b, g, c.level)) {
+                c.dec[i] = (uint8_t)kEmit;
+                ++kept_n;
+                lost += (uint32_t)c.child[e.x].y;
+            }
+        }
+    };
+    for (uint32_t s = lo; s < hi; s += kNT) {
+        const uint32_t i = s + threadIdx.x;
+        const bool cand = i < hi && (c.dec[i] & kCandidate);
+        const uint64_t bal = __ballot(cand);
+        if (lane_id() == 0) s_wc[w] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t base = s_n;
+        for (int q = 0; q < w; ++q) base += s_wc[q];
+        if (cand) s_q[base + (uint32_t)__popcll(bal & lanemask_lt())] = i;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = s_n;
+            for (int q = 0; q < kNW; ++q) t += s_wc[q];
+            s_n = t;
+        }
+        __syncthreads();
+        const uint32_t qn = s_n;
+        if (qn >= (uint32_t)kNT) {
+            evaluate(kNT);
+            __syncthreads();
+            if (threadIdx.x < qn - kNT) s_q[threadIdx.x] = s_q[kNT + threadIdx.x];
+            if (threadIdx.x == 0) s_n = qn - kNT;
+            __syncthreads();
+        }
+    }
+    evaluate(s_n);
+    // this block's corrections (the count pass wrote tmp[b])
+    const uint32_t kx = wave_sum(kept_n), ky = wave_sum(lost);
+    if (lane_id() == 0) s_fix[w] = make_uint2(kx, ky);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint2 t = make_uint2(0, 0);
+        for (int q = 0; q < kNW; ++q) {
+            t.x += s_fix[q].x;
+            t.y += s_fix[q].y;
+        }
+        c.tmp[blockIdx.x].x += t.x;
+        c.tmp[blockIdx.x].y -= t.y;
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G) {
@@ -307,6 +392,7 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.cut_cap = a.cut_cap;
         c.tmp = a.scan_tmp;
         c.dec = a.dec;
+        c.defer = a.mode == HGS_LOD_LEARNED && a.mlp != nullptr;
         c.ctr = a.ctr;
         c.mode = a.mode;
         c.mlp = a.mlp;
@@ -316,6 +402,7 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.level = L;
         c.out_slot = cur ^ 1;
         k_level_count<<<G, kNT, 0, s>>>(c, a.frontier_cap);
+        if (c.defer) k_level_mlp<<<G, kNT, 0, s>>>(c, a.frontier_cap);
         k_level_scan<<<1, 1024, 0, s>>>(c, G);
         k_level_emit<<<G, kNT, 0, s>>>(c, a.frontier_cap);
         cur ^= 1;

@@ -24,6 +24,9 @@ constexpr int kNtShift = 28;
 constexpr uint32_t kEntryMask = (1u << kNtShift) - 1u;
 constexpr uint32_t kNtSat = 15u;
 
+// Hierarchy levels the scene validation allows.
+constexpr int kMaxLevels = 64;
+
 // Overflow bits in Counters::overflow.
 constexpr uint32_t kOvFrontier = 1u;
 constexpr uint32_t kOvCut = 2u;
@@ -82,7 +85,8 @@ struct Counters {
     uint32_t tile_queue;             // persistent compositor work counter
     uint32_t cand;                   // learned-LOD candidates collected
     uint32_t need_cand;
-    unsigned long long nalg;         // evaluated (pixel, Gaussian) pairs
+    unsigned long long nalg;         // evaluated (pixel, Gaussian) pairs with q <= 9
+    unsigned long long neval;        // (pixel, list entry) slots the compositor walked
 };
 
 // Options of the compositor and binning.

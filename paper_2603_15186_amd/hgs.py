@@ -74,7 +74,8 @@ class hgs_stats(ctypes.Structure):
     _fields_ = [("cut_size", ctypes.c_int64), ("visible", ctypes.c_int64), ("pairs", ctypes.c_int64),
                 ("n_alg", ctypes.c_int64), ("tiles", ctypes.c_int64), ("regrows", ctypes.c_int64),
                 ("timed_renders", ctypes.c_int64), ("graph_launches", ctypes.c_int64), ("ms_cut", ctypes.c_double), ("ms_project", ctypes.c_double), ("ms_sort", ctypes.c_double),
-                ("ms_composite", ctypes.c_double), ("ms_total", ctypes.c_double), ("passes", ctypes.c_int64)]
+                ("ms_composite", ctypes.c_double), ("ms_total", ctypes.c_double), ("passes", ctypes.c_int64),
+                ("n_eval", ctypes.c_int64)]
 
 
 class hgs_plan(ctypes.Structure):

@@ -111,7 +111,7 @@ def plan2m_lod(scale=1.0, n_train=2000, n_eval=500, use_cache=True, with_plan=Fa
     return out + (plan,) if with_plan else out
 
 
-def building30m(scale=1.0, n_views=64, use_cache=True):
+def building30m(scale=1.0, n_views=64, use_cache=True, with_plan=False):
     n = int(round(30_000_000 * scale))
     scene, plan = floorplan_scene(n, (20.0, 15.0), 2, seed=4, use_cache=use_cache)
     cams = []
@@ -120,4 +120,4 @@ def building30m(scale=1.0, n_views=64, use_cache=True):
         fs = FreeSpace(plan, f)
         pos, yaw = trajectory(fs, per, seed=105 + f, height=1.2)
         cams += _cams(pos, yaw, 1920, 1080, 1300.0)
-    return scene, cams
+    return (scene, cams, plan) if with_plan else (scene, cams)

@@ -274,3 +274,75 @@ def test_surface_ground_truth_matches_a_plain_ray_caster(R):
     assert bad.mean() < 0.01, (bad.sum(), np.argwhere(bad)[:5].tolist(), got[:, bad][:, :5].T.tolist(),
                                want[:, bad][:, :5].T.tolist())
     assert np.median(diff) < 1e-6
+
+
+# --------------------------------- the benchmark's step at full size
+
+@pytest.fixture(scope="module")
+def plan_lod():
+    scene, _, held = W.plan2m_lod()
+    return scene, held
+
+
+def test_bench_step_at_full_size(R, plan_lod):
+    """The benchmark's step at full size: 50 held-out 1280x720 views of the
+    2M-leaf plan in one call with the committed learned-cut network,
+    replayed from a captured graph.  For three views: every node of the
+    threshold cut has exactly one ancestor-or-self in the learned cut, which
+    is the node itself or a candidate of the band (refined by the threshold,
+    projected size <= s_hi); every learned-cut node outside the threshold cut
+    is such a candidate; 2,000 sampled pixels and one full row match the
+    oracle's render of the GPU's cut."""
+    from paper_2603_15186_amd import hgs, lod
+    from tests import parity
+    scene, held = plan_lod
+    model = lod.LodModel.load(lod.default_model_path())
+    R.load_scene(scene)
+    model.install(R)
+    views = held[:50]
+    R.set_cameras(views)
+    R.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
+    outs = R.alloc_outputs()
+    R.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
+    try:
+        for _ in range(3):
+            R.render(outs)
+        torch.cuda.synchronize()
+        st = R.stats()
+        assert st["graph_launches"] >= 2 and st["passes"] == 1
+        rng = np.random.default_rng(11)
+        for v in (0, 21, 49):
+            cam = views[v]
+            got = R.get_cut(v)
+            thr = O.cut(scene, cam, O.MODE_THRESHOLD, 1.0)
+            lhs, d2 = _sizes(scene, cam)
+            internal = scene.child_count > 0
+            band = internal & (lhs > d2) & (lhs <= (model.s_hi * model.s_hi) * d2)   # tau = 1
+            in_got = np.zeros(scene.n, bool)
+            in_got[got] = True
+            hits = np.zeros(thr.size, np.int64)
+            first = np.full(thr.size, -1, np.int64)
+            cur = thr.astype(np.int64)
+            while True:
+                alive = cur >= 0
+                if not alive.any():
+                    break
+                h = alive & in_got[np.where(alive, cur, 0)]
+                hits += h
+                first = np.where(h & (first < 0), cur, first)
+                cur = np.where(alive, scene.parent[np.where(alive, cur, 0)], -1)
+            assert np.all(hits == 1), v
+            assert np.all((first == thr) | band[first]), v
+            extra = np.setdiff1d(got, thr)
+            assert np.all(band[extra]), v
+            assert got.size <= thr.size
+            px = np.concatenate([rng.integers(0, cam.width, 2000), np.arange(cam.width)])
+            py = np.concatenate([rng.integers(0, cam.height, 2000), np.full(cam.width, cam.height // 3)])
+            res = O.render_pixels(O.project(scene, got, cam), cam, px, py)
+            g = parity.gpu_pixels(*[t.cpu().numpy() for t in outs[v]], px, py)
+            ok, best, skipped = parity.branch_errors(g, res)
+            msg = parity.summary(ok, best, skipped)
+            print(v, got.size, thr.size, msg, flush=True)
+            assert ok.all(), msg
+    finally:
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
