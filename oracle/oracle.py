@@ -16,6 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.c")
+SOURCES = [SRC_PATH, os.path.join(HERE, "slice.c")]
 
 MODE_ALL_LEAVES = 0
 MODE_THRESHOLD = 1
@@ -29,10 +30,11 @@ DEFAULT_EPS = (1e-4, 1e-4, 5e-4)
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (FP64, no FMA contraction, OpenMP)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+    stale = not os.path.exists(LIB_PATH) or any(os.path.getmtime(LIB_PATH) < os.path.getmtime(f) for f in SOURCES)
+    if force or stale:
         tmp = LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-fPIC", "-shared", SRC_PATH, "-o", tmp, "-lm"]
+               "-fopenmp", "-fPIC", "-shared", *SOURCES, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -80,6 +82,12 @@ def lib():
                                        P, P, P, ctypes.c_int32, P, P, P, P]
         L.or_sh_basis.restype = None
         L.or_sh_basis.argtypes = [P, P]
+        L.or_slice_params.restype = None
+        L.or_slice_params.argtypes = [ctypes.c_int64, P, P, P]
+        L.or_slice_occupancy.restype = None
+        L.or_slice_occupancy.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P,
+                                         ctypes.c_double, ctypes.c_double, P]
         L.or_proj_stride.restype = ctypes.c_int32
         L.or_num_threads.restype = ctypes.c_int32
         _lib = L
@@ -194,3 +202,27 @@ def image(res: PixelResult, cam):
     H, W = cam.height, cam.width
     return (p[:, :3].T.reshape(3, H, W).copy(), p[:, 3].reshape(H, W).copy(),
             p[:, 4].reshape(H, W).copy())
+
+
+# ------------------------------------------------------------------ GS-slice
+
+def slice_params(scales, quats) -> np.ndarray:
+    """Per Gaussian (alpha, beta, lambda, c_xx, c_xy, c_yy) of the horizontal
+    slice (see slice.c)."""
+    scales = _c(scales, np.float32); quats = _c(quats, np.float32)
+    n = scales.shape[0]
+    out = np.zeros((n, 6))
+    lib().or_slice_params(n, _p(scales), _p(quats), _p(out))
+    return out
+
+
+def slice_occupancy(means, scales, quats, opacity, x0, y0, cell, nx, ny, heights, rho_min=0.5, amb=1e-9):
+    """(n_planes, ny, nx) int8 map: 0 free, 1 occupied, 2 undecided."""
+    means = _c(means, np.float32); scales = _c(scales, np.float32)
+    quats = _c(quats, np.float32); opacity = _c(opacity, np.float32)
+    heights = _c(heights, np.float32)
+    occ = np.zeros((heights.size, ny, nx), np.int8)
+    lib().or_slice_occupancy(means.shape[0], _p(means), _p(scales), _p(quats), _p(opacity), float(x0), float(y0),
+                             float(cell), int(nx), int(ny), heights.size, _p(heights), float(rho_min), float(amb),
+                             _p(occ))
+    return occ

@@ -417,6 +417,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     ca.dec = P<uint8_t>(c->dec);
     ca.ctr = ctr;
     ca.mlp = (c->lod_mode == HGS_LOD_LEARNED && c->mlp_loaded) ? c->mlp_dev.p : nullptr;
+    ca.p_star = c->mlp_host.p_star;
     ca.s_hi = c->s_hi;
     ca.cand = nullptr;
     ca.cand_cap = 0;

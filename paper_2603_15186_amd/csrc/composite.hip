@@ -146,7 +146,8 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
             s_c[j] = StageC{P.c1, P.c2};
             m = block_mask(u, v, P.p, P.r, P.s);
         }
-        // 2. per-block lists in depth order
+        // 2. per-block lists in depth order: each entry's rank among its
+        // wave's entries marking block b, then each wave's start per block
         uint32_t pre[kBlocks];
 #pragma unroll
         for (int b = 0; b < kBlocks; ++b) {
@@ -155,20 +156,20 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
             if (lane == 0) s_wc[w * kBlocks + b] = (uint32_t)__popcll(bal);
         }
         __syncthreads();
-#pragma unroll
-        for (int b = 0; b < kBlocks; ++b) {
-            if ((m >> b) & 1u) {
-                uint32_t off = pre[b];
-                for (int ww = 0; ww < w; ++ww) off += s_wc[ww * kBlocks + b];
-                s_idx[b * BATCH + off] = (uint16_t)(j * 16);     // byte offset of the record
-            }
-        }
         if (threadIdx.x < kBlocks) {
             uint32_t t = 0;
-            for (int ww = 0; ww < kNT / kWave; ++ww) t += s_wc[ww * kBlocks + threadIdx.x];
+#pragma unroll
+            for (int ww = 0; ww < kNT / kWave; ++ww) {
+                const uint32_t c = s_wc[ww * kBlocks + threadIdx.x];
+                s_wc[ww * kBlocks + threadIdx.x] = t;
+                t += c;
+            }
             s_n[threadIdx.x] = t;
         }
         __syncthreads();
+#pragma unroll
+        for (int b = 0; b < kBlocks; ++b)
+            if ((m >> b) & 1u) s_idx[b * BATCH + s_wc[w * kBlocks + b] + pre[b]] = (uint16_t)(j * 16);
         // 3. compositing: pad this block's list with the empty record up to
         // the wave's step count, so every step reads four offsets as they are
         const uint32_t n_mine = s_n[gid];

@@ -392,7 +392,8 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.cut_cap = a.cut_cap;
         c.tmp = a.scan_tmp;
         c.dec = a.dec;
-        c.defer = a.mode == HGS_LOD_LEARNED && a.mlp != nullptr;
+        // p* = 0 refines every candidate: nothing for the network to decide
+        c.defer = a.mode == HGS_LOD_LEARNED && a.mlp != nullptr && a.p_star > 0.f;
         c.ctr = a.ctr;
         c.mode = a.mode;
         c.mlp = a.mlp;

@@ -128,6 +128,7 @@ struct CutArgs {
     // learned refinement (nullptr = off); candidate band for it and for
     // candidate collection: refined by the threshold and s <= s_hi pixels
     const void* mlp;
+    float p_star;                    // learned cut: 0 refines every candidate (the threshold cut)
     double s_hi;
     uint2* cand;                     // nullptr: do not collect candidates
     uint32_t cand_cap;

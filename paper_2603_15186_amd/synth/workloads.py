@@ -121,3 +121,13 @@ def building30m(scale=1.0, n_views=64, use_cache=True, with_plan=False):
         pos, yaw = trajectory(fs, per, seed=105 + f, height=1.2)
         cams += _cams(pos, yaw, 1920, 1080, 1300.0)
     return (scene, cams, plan) if with_plan else (scene, cams)
+
+
+def building30m_calibration(plan, n_per_floor=8):
+    """Poses for calibrating the learned cut's p* on the building: other
+    trajectories (seeds 205, 206) at the same height and camera."""
+    cams = []
+    for f in range(2):
+        pos, yaw = trajectory(FreeSpace(plan, f), n_per_floor, seed=205 + f, height=1.2)
+        cams += _cams(pos, yaw, 1920, 1080, 1300.0)
+    return cams
