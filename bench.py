@@ -56,10 +56,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels instead of replaying a graph")
-    ap.add_argument("--workload", default="plan2m-lod", choices=["plan2m-lod", "plan8m", "building30m"],
+    ap.add_argument("--workload", default="plan2m-lod", choices=["plan2m-lod", "plan8m", "building30m", "slice"],
                     help="plan2m-lod (the metric's workload), plan8m (256 mixed-resolution views of the "
                          "8M-leaf plan, threshold cuts) or building30m (64 1080p views of the 30M-leaf "
-                         "two-floor building, learned cut); the last two are reported for reference")
+                         "two-floor building, learned cut) or slice (GS-slice collision map of the 30M-leaf "
+                         "building); the last three are reported for reference")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed batched learned path (for profilers): no quality evaluation, no "
                          "threshold or single-view comparison")
@@ -261,12 +262,76 @@ def run_building(args):
     r.close()
 
 
+def run_slice(args):
+    """GS-slice collision maps of the 30M-leaf building's two floors: 15
+    planes 0.1 .. 1.5 m above each floor over its 20 x 15 m extent at 5 cm
+    (404 x 304 cells), every leaf Gaussian sliced; timed with HIP events on
+    the stream; the FP64 oracle timed on the host for the same maps."""
+    import numpy as np
+    import torch
+    from paper_2603_15186_amd import hgs
+    from paper_2603_15186_amd.synth import workloads as W
+    t = time.perf_counter()
+    scene, _, plan = W.building30m(with_plan=True)
+    log(f"building30m: {scene.n} nodes ({time.perf_counter() - t:.1f} s)")
+    r = hgs.Renderer(0)
+    r.load_scene(scene)
+    n_leaves = int(np.count_nonzero(scene.child_count == 0))
+    floors = [np.arange(0.1, 1.55, 0.1) + f * plan.ceiling for f in range(2)]
+    nx, ny, cell = 404, 304, 0.05
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        for h in floors:
+            r.slice_occupancy(-0.1, -0.1, cell, nx, ny, h)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        for h in floors:
+            occ, m = r.slice_occupancy(-0.1, -0.1, cell, nx, ny, h)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    frac = [float(r.slice_occupancy(-0.1, -0.1, cell, nx, ny, h)[1].float().mean()) for h in floors]
+    planes = sum(len(h) for h in floors)
+    cells = planes * nx * ny
+    # algorithmic bytes per step: each leaf's 48-byte record and id per map,
+    # every plane and union byte written once
+    alg = len(floors) * (n_leaves * 52 + (len(floors[0]) + 1) * nx * ny)
+    gbs = alg / (ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        ids = np.nonzero(scene.child_count == 0)[0]
+        t0 = time.perf_counter()
+        for h in floors:
+            O.slice_occupancy(scene.means[ids], scene.scales[ids], scene.quats[ids], scene.opacity[ids], -0.1, -0.1,
+                              cell, nx, ny, h.astype(np.float32))
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": cells / t_cpu / 1e6, "unit": "Mcells/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"both floors' maps once ({t_cpu:.2f} s)"}
+    out = {"metric": "Mcells/s, GS-slice collision maps of the 30M-leaf building (2 floors x 15 planes, 5 cm)",
+           "value": cells / (ms * 1e-3) / 1e6, "unit": "Mcells/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "building30m leaves, 2 floors x 15 planes 0.1-1.5 m, 404x304 cells of 5 cm",
+                      "leaves": n_leaves, "parallelism": "single GPU"},
+           "roofline": {"kernel": "k_slice", "bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                        "frac": gbs / 8000.0, "traffic": None},
+           "cpu_baseline": cpu,
+           "extra": {"occupied_fraction_per_floor": frac, "algorithmic_bytes_per_step": alg}}
+    print(json.dumps(out), flush=True)
+    r.close()
+
+
 def main():
     args = parse()
     if args.workload == "plan8m":
         return run_plan8m(args)
     if args.workload == "building30m":
         return run_building(args)
+    if args.workload == "slice":
+        return run_slice(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: the "

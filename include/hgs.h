@@ -337,6 +337,35 @@ hgs_status hgs_set_surfaces(hgs_ctx* ctx, int32_t n, const hgs_surface* surfaces
  * hit nothing take the camera's background. */
 hgs_status hgs_render_surfaces(hgs_ctx* ctx, void* stream, int32_t view, int32_t ss, float* rgb);
 
+/* ---------------------------------------------------------------------- */
+/* GS-slice collision map (NavGSim Sec. III-C and the Supplementary        */
+/* derivation of Gaussian slicing).                                          */
+
+typedef struct {
+    double x0, y0;                /* world x, y (metres) of the grid's lower corner */
+    double cell;                  /* cell edge (metres), > 0 */
+    int32_t nx, ny;               /* cells per row, rows: 1..16384 each */
+    int32_t n_planes;             /* 1..256 */
+    float rho_min;                /* solid threshold, in (0, 1) */
+    const float* heights;         /* host array of n_planes plane heights (metres) */
+} hgs_slice_grid;
+
+/* Occupancy of the scene's leaf Gaussians (every Gaussian of a flat scene)
+ * on horizontal planes.  A Gaussian cut by the plane z is the 2D Gaussian
+ * o exp(-lambda (z - mu_z)^2 / 2) exp(-q / 2), q = (x - mu(z))^T C_xy
+ * (x - mu(z)), with C = Sigma^-1, C_xy its xy block, (alpha, beta) solving
+ * C_xy (alpha, beta)^T = (c_xz, c_yz)^T, lambda = c_zz - (alpha, beta) .
+ * (c_xz, c_yz) and mu(z) = (mu_x, mu_y) - (z - mu_z)(alpha, beta); it is
+ * solid where that value is >= rho_min.  Cell (i, j), the closed square
+ * [x0 + i cell, x0 + (i+1) cell] x [y0 + j cell, y0 + (j+1) cell], is 1 in
+ * plane k of occ when some solid ellipse on plane k meets it, else 0.  occ
+ * (device, [n_planes][ny][nx] bytes) and map (device, [ny][nx] bytes: the
+ * union over the planes) are caller-owned; either may be NULL, not both.
+ * Asynchronous on `stream`.  HGS_E_INVALID on bad sizes, HGS_E_STATE
+ * without a scene. */
+hgs_status hgs_slice_occupancy(hgs_ctx* ctx, void* stream, const hgs_slice_grid* grid, uint8_t* occ,
+                               uint8_t* map);
+
 #ifdef __cplusplus
 }
 #endif

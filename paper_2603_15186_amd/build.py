@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhgs.so")
-SOURCES = ["api.hip", "cut.hip", "project.hip", "sort.hip", "composite.hip", "mlp.hip", "imgutil.hip", "surfaces.hip"]
+SOURCES = ["api.hip", "cut.hip", "project.hip", "sort.hip", "composite.hip", "mlp.hip", "imgutil.hip", "surfaces.hip",
+           "slice.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

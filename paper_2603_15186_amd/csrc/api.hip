@@ -1468,6 +1468,39 @@ hgs_status hgs_set_surfaces(hgs_ctx* c, int32_t n, const hgs_surface* surfaces) 
     return HGS_OK;
 }
 
+hgs_status hgs_slice_occupancy(hgs_ctx* c, void* stream, const hgs_slice_grid* grid, uint8_t* occ, uint8_t* map) {
+    if (!c) return HGS_E_INVALID;
+    if (!c->loaded) return fail(c, HGS_E_STATE, "no scene");
+    if (!grid || (!occ && !map) || !grid->heights) return fail(c, HGS_E_INVALID, "NULL grid, heights or outputs");
+    const hgs_slice_grid& g = *grid;
+    if (g.nx < 1 || g.ny < 1 || g.nx > 16384 || g.ny > 16384) return fail(c, HGS_E_INVALID, "grid must be 1..16384 cells per side");
+    if (g.n_planes < 1 || g.n_planes > 256) return fail(c, HGS_E_INVALID, "need 1..256 planes");
+    if (!(g.cell > 0.0) || !std::isfinite(g.cell) || !std::isfinite(g.x0) || !std::isfinite(g.y0))
+        return fail(c, HGS_E_INVALID, "cell size must be positive and the corner finite");
+    if (!(g.rho_min > 0.f && g.rho_min < 1.f)) return fail(c, HGS_E_INVALID, "rho_min must be in (0, 1)");
+    for (int k = 0; k < g.n_planes; ++k)
+        if (!finite(g.heights[k])) return fail(c, HGS_E_INVALID, "plane %d height not finite", k);
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    SliceArgs a{};
+    a.geo = P<float4>(c->geo);
+    a.ids = c->hier ? P<int32_t>(c->leaf_ids) : nullptr;
+    a.n = (uint32_t)(c->hier ? c->n_leaves : c->n);
+    a.x0 = g.x0;
+    a.y0 = g.y0;
+    a.cell = g.cell;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.n_planes = g.n_planes;
+    for (int k = 0; k < g.n_planes; ++k) a.heights[k] = g.heights[k];
+    a.rho_min = g.rho_min;
+    a.occ = occ;
+    a.map = map;
+    launch_slice(a, s);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
 hgs_status hgs_render_surfaces(hgs_ctx* c, void* stream, int32_t view, int32_t ss, float* rgb) {
     if (!c || !rgb) return HGS_E_INVALID;
     if (view < 0 || view >= (int32_t)c->cams.size()) return fail(c, HGS_E_INVALID, "view out of range");

@@ -210,6 +210,22 @@ void launch_composite(const CompositeArgs& a, hipStream_t s);
 
 void launch_reset_counters(Counters* c, hipStream_t s);
 
+// GS-slice occupancy (slice.hip): occ[k][j][i] and map[j][i] bytes (either
+// may be null), cell (i, j) = [x0 + i cell, x0 + (i+1) cell] x [y0 + j cell,
+// y0 + (j+1) cell].
+struct SliceArgs {
+    const float4* geo;               // [n_nodes * 3]
+    const int32_t* ids;              // Gaussians to slice (null: 0..n-1)
+    uint32_t n;
+    double x0, y0, cell;
+    int nx, ny, n_planes;
+    double rho_min;
+    float heights[256];              // plane heights (passed by value)
+    uint8_t* occ;
+    uint8_t* map;
+};
+void launch_slice(const SliceArgs& a, hipStream_t s);
+
 // learned-LOD network (mlp.hip)
 void launch_mlp_forward(const float* feats, uint32_t n, const float* mean, const float* stdv, const uint16_t* w,
                         float* logits, hipStream_t s);

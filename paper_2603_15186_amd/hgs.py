@@ -78,6 +78,12 @@ class hgs_stats(ctypes.Structure):
                 ("n_eval", ctypes.c_int64)]
 
 
+class hgs_slice_grid(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("cell", ctypes.c_double), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("n_planes", ctypes.c_int32), ("rho_min", ctypes.c_float),
+                ("heights", ctypes.c_void_p)]
+
+
 class hgs_plan(ctypes.Structure):
     _fields_ = [("batch_depth", ctypes.c_int32), ("persistent", ctypes.c_int32), ("sort_digit_bits", ctypes.c_int32),
                 ("from_cache", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
@@ -115,6 +121,7 @@ EXPORTS = [
     ("hgs_region_mse", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.POINTER(hgs_region), _P]),
     ("hgs_set_surfaces", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
     ("hgs_render_surfaces", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
+    ("hgs_slice_occupancy", ctypes.c_int32, [_P, _P, ctypes.POINTER(hgs_slice_grid), _P, _P]),
 ]
 
 N_MLP_PARAMS = 1377
@@ -394,6 +401,20 @@ class Renderer:
             out = torch.empty((3, c.height, c.width), dtype=torch.float32, device=torch.device("cuda", self.device))
         self._check(self.lib.hgs_render_surfaces(self.ctx, self._stream(stream), int(view), int(ss), out.data_ptr()))
         return out
+
+    def slice_occupancy(self, x0, y0, cell, nx, ny, heights, rho_min=0.5, occ=True, stream=None):
+        """GS-slice occupancy of the scene's leaves on planes at `heights`:
+        (occ uint8 [n_planes, ny, nx] or None, map uint8 [ny, nx])."""
+        import torch
+        h = np.ascontiguousarray(np.asarray(heights, np.float32).ravel())
+        dev = torch.device("cuda", self.device)
+        o = torch.empty((h.size, ny, nx), dtype=torch.uint8, device=dev) if occ else None
+        m = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
+        g = hgs_slice_grid(float(x0), float(y0), float(cell), int(nx), int(ny), h.size, float(rho_min),
+                           h.ctypes.data_as(ctypes.c_void_p))
+        self._check(self.lib.hgs_slice_occupancy(self.ctx, self._stream(stream), ctypes.byref(g),
+                                                 o.data_ptr() if o is not None else None, m.data_ptr()))
+        return o, m
 
     def sort_pairs(self, keys, vals, key_bits, stream=None):
         """Sort device uint32 tensors (as int32 storage) in place."""

@@ -55,6 +55,12 @@ def test_plan_struct_matches_header_fields():
     assert ctypes.sizeof(hgs.hgs_plan) == 4 * 4 + 2 * 8
 
 
+def test_slice_grid_struct_matches_header():
+    assert ctypes.sizeof(hgs.hgs_slice_grid) == 3 * 8 + 4 * 4 + 8
+    assert [n for n, _ in hgs.hgs_slice_grid._fields_] == ["x0", "y0", "cell", "nx", "ny", "n_planes", "rho_min",
+                                                           "heights"]
+
+
 def test_binding_struct_sizes_match_header_layout():
     import ctypes
     assert ctypes.sizeof(hgs.hgs_gaussians) == 8 + 4 + 4 + 5 * 8

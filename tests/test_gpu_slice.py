@@ -1,0 +1,86 @@
+"""GPU GS-slice occupancy through the C ABI against the FP64 oracle: every
+cell the oracle decides (free or occupied) must agree; cells it reports as
+undecided (a test within 1e-9 relative of its threshold) may go either way."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_15186_amd.synth import make_random_box, workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_15186_amd import hgs
+    r = hgs.Renderer(0)
+    yield r
+    r.close()
+
+
+def _compare(gpu, want):
+    decided = want != 2
+    bad = decided & (gpu.astype(np.int8) != want)
+    assert not bad.any(), f"{int(bad.sum())} of {int(decided.sum())} decided cells differ"
+
+
+def _leaves(scene):
+    ids = scene.leaf_ids()
+    return scene.means[ids], scene.scales[ids], scene.quats[ids], scene.opacity[ids]
+
+
+def test_random_gaussians_match_oracle(R):
+    """3,000 Gaussians of a random box (scales 4 mm - 0.3 m, random
+    rotations), a ragged 45 x 37 grid of 5 cm cells, seven planes."""
+    rng = np.random.default_rng(0)
+    scene = make_random_box(3000, seed=4, box=(2.0, 2.0, 2.0))
+    scene.scales[:] = np.exp(rng.uniform(np.log(0.004), np.log(0.3), size=scene.scales.shape)).astype(np.float32)
+    R.load_scene(scene)
+    heights = np.array([0.1, 0.4, 0.7, 1.0, 1.3, 1.6, 1.9], np.float32)
+    occ, m = R.slice_occupancy(-0.1, 0.05, 0.05, 45, 37, heights, rho_min=0.5)
+    torch.cuda.synchronize()
+    g = occ.cpu().numpy()
+    want = O.slice_occupancy(*_leaves(scene), -0.1, 0.05, 0.05, 45, 37, heights, rho_min=0.5)
+    _compare(g, want)
+    assert (want == 1).sum() > 100
+    np.testing.assert_array_equal(m.cpu().numpy(), g.max(axis=0))
+    _, m2 = R.slice_occupancy(-0.1, 0.05, 0.05, 45, 37, heights, rho_min=0.5, occ=False)
+    np.testing.assert_array_equal(m2.cpu().numpy(), m.cpu().numpy())
+    # a higher threshold marks a subset
+    occ9, _ = R.slice_occupancy(-0.1, 0.05, 0.05, 45, 37, heights, rho_min=0.9)
+    assert np.all(occ9.cpu().numpy() <= g)
+
+
+def test_floor_plan_collision_map_matches_oracle(R):
+    """The 2M-leaf plan: 15 planes from 0.1 to 1.5 m over its 20 x 15 m
+    extent at 5 cm (404 x 304 cells).  Walls and clutter occupy, the floor
+    and ceiling sheets (far from every plane) do not."""
+    scene, _, fp = W.plan2m(n_poses=2, with_plan=True)
+    R.load_scene(scene)
+    heights = np.arange(0.1, 1.55, 0.1).astype(np.float32)
+    occ, m = R.slice_occupancy(-0.1, -0.1, 0.05, 404, 304, heights, rho_min=0.5)
+    torch.cuda.synchronize()
+    g = occ.cpu().numpy()
+    want = O.slice_occupancy(*_leaves(scene), -0.1, -0.1, 0.05, 404, 304, heights, rho_min=0.5)
+    _compare(g, want)
+    frac = g.max(axis=0).mean()
+    print("occupied fraction", frac, "undecided", int((want == 2).sum()), flush=True)
+    assert 0.02 < frac < 0.6
+    np.testing.assert_array_equal(m.cpu().numpy(), g.max(axis=0))
+
+
+def test_slice_arguments_are_checked(R):
+    from paper_2603_15186_amd import hgs
+    scene = make_random_box(100, seed=1)
+    R.load_scene(scene)
+    for kw in ({"rho_min": 0.0}, {"rho_min": 1.0}):
+        with pytest.raises(hgs.HgsError) as ei:
+            R.slice_occupancy(0, 0, 0.05, 10, 10, [0.5], **kw)
+        assert ei.value.status == hgs.HGS_E_INVALID
+    with pytest.raises(hgs.HgsError):
+        R.slice_occupancy(0, 0, 0.0, 10, 10, [0.5])
+    with pytest.raises(hgs.HgsError):
+        R.slice_occupancy(0, 0, 0.05, 0, 10, [0.5])
