@@ -198,17 +198,26 @@ def run_building(args):
     r = hgs.Renderer(0)
     r.load_scene(scene)
     r.set_surfaces(plan.surfaces)
-    model = lod.LodModel.load(args.model or lod.default_model_path())
-    # the network was trained on the 2M-leaf plan at 720p: p* is calibrated
-    # again on 16 poses of this building (other trajectories), the threshold
-    # cut being the fallback when no p* keeps the loss within budget
+    own = lod.default_model_path("building30m_lod_mlp.npz")
     calib = W.building30m_calibration(plan)
-    crefs = lod.reference_images(r, calib)
-    cbase, _, _ = lod.evaluate(r, calib, crefs, None, tau=1.0)
-    p_star, closs, table = lod.calibrate(r, model, calib, crefs, cbase)
-    model.p_star = p_star
-    del crefs
-    log(f"calibrated p* = {p_star} (loss {closs:.3f} dB on {len(calib)} poses)")
+    table, closs = [], float("nan")
+    if args.model is None and os.path.exists(own):
+        # the building's own network (trained and calibrated on its poses)
+        model = lod.LodModel.load(own)
+        origin = os.path.relpath(own, ROOT)
+        p_star = model.p_star
+    else:
+        # the 2M-leaf plan's network: p* is calibrated again on 16 poses of
+        # this building (other trajectories); the threshold cut is the
+        # fallback when no p* keeps the loss within budget
+        model = lod.LodModel.load(args.model or lod.default_model_path())
+        origin = os.path.relpath(args.model or lod.default_model_path(), ROOT)
+        crefs = lod.reference_images(r, calib)
+        cbase, _, _ = lod.evaluate(r, calib, crefs, None, tau=1.0)
+        p_star, closs, table = lod.calibrate(r, model, calib, crefs, cbase)
+        model.p_star = p_star
+        del crefs
+    log(f"learned cut: {origin}, p* = {p_star}")
     model.install(r)
     free0, total = torch.cuda.mem_get_info()
     peak = total - free0
@@ -249,13 +258,13 @@ def run_building(args):
            "value": res["learned"]["mpix_s"], "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": res["learned"]["ms_per_batch"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "building30m 64 views 1920x1080 fx=1300, learned cut (2M-leaf plan network, "
-                                  "p* calibrated on the building, threshold tau=1 fallback)", "nodes": scene.n,
+           "config": {"workload": "building30m 64 views 1920x1080 fx=1300, learned cut (threshold tau=1 fallback)",
+                      "nodes": scene.n,
                       "pixels_per_batch": px,
                       "parallelism": "single GPU"},
            "extra": {"render": res, "quality_8_views": q, "peak_device_gb": peak / 1e9,
-                     "p_star": p_star, "calibration": {"poses": len(calib), "loss_db": closs,
-                                                       "table": [list(t) for t in table]},
+                     "p_star": p_star, "model": origin,
+                     "calibration": {"poses": len(calib), "loss_db": closs, "table": [list(t) for t in table]},
                      "frames_s_learned": res["learned"]["frames_s"],
                      "speedup_learned_vs_tau1": res["tau1"]["ms_per_batch"] / res["learned"]["ms_per_batch"]}}
     print(json.dumps(out), flush=True)

@@ -55,7 +55,7 @@ struct hgs_ctx {
     int lod_mode = HGS_LOD_THRESHOLD;
     float tau = 1.0f;
     bool mlp_loaded = false;
-    DevMem mlp_w, mlp_dev;
+    DevMem mlp_w, mlp_w32, mlp_dev;
     LodMlpDev mlp_host{};
     double s_hi = 64.0;               // candidate band of the learned cut (pixels)
     DevMem train_scratch, region_dev, surf;
@@ -418,6 +418,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     ca.ctr = ctr;
     ca.mlp = (c->lod_mode == HGS_LOD_LEARNED && c->mlp_loaded) ? c->mlp_dev.p : nullptr;
     ca.p_star = c->mlp_host.p_star;
+    ca.mlp_w32 = c->mlp_loaded ? P<float>(c->mlp_w32) : nullptr;
     ca.s_hi = c->s_hi;
     ca.cand = nullptr;
     ca.cand_cap = 0;
@@ -648,7 +649,7 @@ void hgs_destroy(hgs_ctx* c) {
     (void)hipDeviceSynchronize();
     DevMem* all[] = {&c->geo, &c->sh, &c->bound, &c->child, &c->leaf_ids, &c->parent, &c->nodefeat, &c->lvl,
                      &c->train_scratch, &c->region_dev, &c->surf, &c->views,
-                     &c->tile_view, &c->mlp_w, &c->mlp_dev, &c->frontier[0], &c->frontier[1], &c->cut, &c->proj,
+                     &c->tile_view, &c->mlp_w, &c->mlp_w32, &c->mlp_dev, &c->frontier[0], &c->frontier[1], &c->cut, &c->proj,
                      &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->bins, &c->offsets, &c->dec,
                      &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
                      &c->counters, &c->sort_k, &c->sort_v, &c->sort_n};
@@ -1349,10 +1350,15 @@ hgs_status hgs_load_lod_mlp(hgs_ctx* c, const uint16_t* bf16, const float* mean,
     }
     HIP_TRY(c, hipSetDevice(c->device));
     hgs_status st;
-    if ((st = ensure(c, c->mlp_w, kMlpParams * sizeof(uint16_t))) || (st = ensure(c, c->mlp_dev, sizeof(LodMlpDev))))
+    if ((st = ensure(c, c->mlp_w, kMlpParams * sizeof(uint16_t))) || (st = ensure(c, c->mlp_dev, sizeof(LodMlpDev))) ||
+        (st = ensure(c, c->mlp_w32, kMlpParams * sizeof(float))))
         return st;
     HIP_TRY(c, hipDeviceSynchronize());
     HIP_TRY(c, hipMemcpy(c->mlp_w.p, bf16, kMlpParams * sizeof(uint16_t), hipMemcpyHostToDevice));
+    // the same weights widened to FP32 (exact), read by the cut's network pass
+    std::vector<float> w32(kMlpParams);
+    for (int i = 0; i < kMlpParams; ++i) w32[i] = bf16_to_f32_host(bf16[i]);
+    HIP_TRY(c, hipMemcpy(c->mlp_w32.p, w32.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice));
     LodMlpDev m = mlp_geometry(c);
     m.w = P<uint16_t>(c->mlp_w);
     for (int i = 0; i < kMlpIn; ++i) {

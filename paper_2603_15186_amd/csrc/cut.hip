@@ -71,6 +71,7 @@ struct LevelCtx {
     uint4* tmp;               // [G] block counts, then offsets; [G] = level bases
     uint8_t* dec;             // per frontier entry: decision of the count pass
     bool defer;               // learned cut: candidates are decided by k_level_mlp
+    const float* w32;         // learned cut: FP32 weights (uniform: read through the scalar cache)
     Counters* ctr;
     int mode;
     const void* mlp;
@@ -95,15 +96,6 @@ __device__ __forceinline__ uint4 counts_of(const LevelCtx& c, uint32_t d, int nc
     const uint32_t kind = d & 3u;
     return make_uint4(kind == kEmit ? 1u : 0u, kind == kExpand ? (uint32_t)nchild : 0u,
                       (c.cand != nullptr && (d & kCandidate)) ? 1u : 0u, 0u);
-}
-
-// The network's weights widened to FP32 in LDS (learned mode only).
-__device__ __forceinline__ const float* stage_weights(const LevelCtx& c, float* s_w) {
-    if (c.mode != HGS_LOD_LEARNED || c.mlp == nullptr) return nullptr;
-    const uint16_t* w = ((const LodMlpDev*)c.mlp)->w;
-    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) s_w[i] = bf16_to_f32(w[i]);
-    __syncthreads();
-    return s_w;
 }
 
 // Count pass: decide every entry of the block's chunk once, remember the
@@ -152,7 +144,6 @@ __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap
 // network keeps a node (emits it) unless its probability reaches p*; the
 // block's counts lose each kept node's children and gain one emitted entry.
 __global__ __launch_bounds__(kNT) void k_level_mlp(LevelCtx c, uint32_t in_cap) {
-    __shared__ float s_w[kMlpParams];
     __shared__ uint32_t s_q[2 * kNT];
     __shared__ uint32_t s_wc[kNW + 1];
     __shared__ uint32_t s_n;
@@ -162,7 +153,10 @@ __global__ __launch_bounds__(kNT) void k_level_mlp(LevelCtx c, uint32_t in_cap) 
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
     if (lo >= hi) return;
-    const float* sw = stage_weights(c, s_w);
+    // constant address space: the weights (same for every lane) come through
+    // the scalar cache into SGPR operands
+    using ConstF = __attribute__((address_space(4))) const float*;
+    const ConstF sw = (ConstF)c.w32;
     const LodMlpDev& m = *(const LodMlpDev*)c.mlp;
     const int w = threadIdx.x / kWave;
     if (threadIdx.x == 0) s_n = 0;
@@ -394,6 +388,7 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.dec = a.dec;
         // p* = 0 refines every candidate: nothing for the network to decide
         c.defer = a.mode == HGS_LOD_LEARNED && a.mlp != nullptr && a.p_star > 0.f;
+        c.w32 = a.mlp_w32;
         c.ctr = a.ctr;
         c.mode = a.mode;
         c.mlp = a.mlp;

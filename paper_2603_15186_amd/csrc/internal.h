@@ -129,6 +129,7 @@ struct CutArgs {
     // candidate collection: refined by the threshold and s <= s_hi pixels
     const void* mlp;
     float p_star;                    // learned cut: 0 refines every candidate (the threshold cut)
+    const float* mlp_w32;            // learned cut: the network's weights widened to FP32
     double s_hi;
     uint2* cand;                     // nullptr: do not collect candidates
     uint32_t cand_cap;

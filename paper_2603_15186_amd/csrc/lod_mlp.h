@@ -106,9 +106,11 @@ __device__ __forceinline__ float lod_mlp_logit(const uint16_t* __restrict__ w, c
     return out;
 }
 
-// Forward pass with the weights already widened to FP32 (e.g. staged in
-// LDS); same arithmetic as lod_mlp_logit.
-__device__ __forceinline__ float lod_mlp_logit_f32(const float* w, const float x[kMlpIn]) {
+// Forward pass with the weights already widened to FP32; same arithmetic as
+// lod_mlp_logit.  W is a pointer type: a constant-address-space pointer lets
+// uniform weight reads go through the scalar cache.
+template <class W>
+__device__ __forceinline__ float lod_mlp_logit_f32(W w, const float x[kMlpIn]) {
     float h1[kMlpH];
 #pragma unroll
     for (int j = 0; j < kMlpH; ++j) {
@@ -118,6 +120,7 @@ __device__ __forceinline__ float lod_mlp_logit_f32(const float* w, const float x
         h1[j] = acc > 0.f ? acc : 0.f;
     }
     float out = w[kOffB3];
+#pragma unroll 4
     for (int j = 0; j < kMlpH; ++j) {
         float acc = w[kOffB2 + j];
 #pragma unroll
@@ -130,9 +133,10 @@ __device__ __forceinline__ float lod_mlp_logit_f32(const float* w, const float x
 
 // For a candidate node (the threshold rule refines it and its projected
 // size is at most s_hi): does the learned cut refine it?  Yes iff the
-// network's probability reaches p_star.  sw: the weights as FP32 (LDS).
-__device__ __forceinline__ bool lod_mlp_expand(const LodMlpDev& m, const float* sw, const ViewDev& V, int k,
-                                               float4 b, const NodeGeom& g, int level) {
+// network's probability reaches p_star.  sw: the weights as FP32.
+template <class W>
+__device__ __forceinline__ bool lod_mlp_expand(const LodMlpDev& m, W sw, const ViewDev& V, int k, float4 b,
+                                               const NodeGeom& g, int level) {
     float f[kMlpIn];
     lod_features(m, V, k, b, g, level, f);
 #pragma unroll

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhgs.so")
+LIB_PATH = os.environ.get("HGS_LIBRARY") or os.path.join(HERE, "libhgs.so")
 
 HGS_OK = 0
 HGS_E_INVALID = -1

@@ -308,13 +308,15 @@ def tau_matched(r: hgs.Renderer, cams, refs, base_psnr, loss_db, lo=1.0, hi=256.
 
 
 def main(argv=None):
-    """Train the learned cut of the 2M-leaf floor plan on its 2,000 training
-    poses and save it: python -m paper_2603_15186_amd.lod --out PATH."""
+    """Train a learned cut and save it: the 2M-leaf floor plan on its 2,000
+    training poses (default), or the 30M-leaf building on random poses of
+    both floors (--scene building30m).  python -m paper_2603_15186_amd.lod"""
     import argparse
     import time
     from .synth import workloads as W
     ap = argparse.ArgumentParser(description=main.__doc__)
-    ap.add_argument("--out", default=default_model_path())
+    ap.add_argument("--scene", default="plan2m", choices=["plan2m", "building30m"])
+    ap.add_argument("--out", default=None)
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--per-view", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
@@ -322,17 +324,25 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args(argv)
     t0 = time.time()
-    scene, train_cams, _, plan = W.plan2m_lod(with_plan=True)
+    log = lambda *a: print(*a, flush=True)  # noqa: E731
+    if args.scene == "plan2m":
+        scene, train_cams, _, plan = W.plan2m_lod(with_plan=True)
+        out = args.out or default_model_path()
+    else:
+        scene, _, plan = W.building30m(with_plan=True)
+        train_cams = W.building30m_training(plan, (args.train + 1) // 2)
+        out = args.out or default_model_path("building30m_lod_mlp.npz")
+    log(f"{args.scene}: {scene.n} nodes, {len(train_cams)} training poses ({time.time() - t0:.1f} s)")
     r = hgs.Renderer(0)
     r.load_scene(scene)
     r.set_surfaces(plan.surfaces)
     model = train_pipeline(r, train_cams[:args.train], calib_n=args.calib, per_view=args.per_view,
-                           epochs=args.epochs, seed=args.seed, log=lambda *a: print(*a, flush=True))
+                           epochs=args.epochs, seed=args.seed, log=log)
     model.info["train_views"] = min(args.train, len(train_cams))
     model.info["seconds"] = time.time() - t0
-    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-    model.save(args.out)
-    print("saved", args.out, model.p_star, model.info, flush=True)
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    model.save(out)
+    print("saved", out, model.p_star, model.info, flush=True)
     r.close()
 
 

@@ -123,6 +123,16 @@ def building30m(scale=1.0, n_views=64, use_cache=True, with_plan=False):
     return (scene, cams, plan) if with_plan else (scene, cams)
 
 
+def building30m_training(plan, n_per_floor=300):
+    """Training poses of the building's learned cut: random free positions on
+    each floor (seeds 301, 302), 1.2 m high, uniform yaw, 1920x1080, f = 1300."""
+    cams = []
+    for f in range(2):
+        pos, yaw = random_poses(FreeSpace(plan, f), n_per_floor, 301 + f, height=(1.2, 1.2))
+        cams += _cams(pos, yaw, 1920, 1080, 1300.0)
+    return cams
+
+
 def building30m_calibration(plan, n_per_floor=8):
     """Poses for calibrating the learned cut's p* on the building: other
     trajectories (seeds 205, 206) at the same height and camera."""
