@@ -366,6 +366,17 @@ typedef struct {
 hgs_status hgs_slice_occupancy(hgs_ctx* ctx, void* stream, const hgs_slice_grid* grid, uint8_t* occ,
                                uint8_t* map);
 
+/* Disc robots against a 2D occupancy map (e.g. the union map of
+ * hgs_slice_occupancy), for collision checks of many robots at once:
+ * out[q] = 1 when the closed disc of `radius` metres around
+ * (xy[2q], xy[2q+1]) meets the closed square [x0 + i cell, x0 + (i+1) cell] x
+ * [y0 + j cell, y0 + (j+1) cell] of some occupied cell (map[j * nx + i] != 0),
+ * else 0; cells outside the grid are free.  map (device, ny * nx bytes), xy
+ * (device, n pairs of doubles) and out (device, n bytes) are caller-owned.
+ * Asynchronous on `stream`.  HGS_E_INVALID on bad sizes or radius. */
+hgs_status hgs_disc_collision(hgs_ctx* ctx, void* stream, const uint8_t* map, double x0, double y0, double cell,
+                              int32_t nx, int32_t ny, int64_t n, const double* xy, double radius, uint8_t* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -88,6 +88,9 @@ def lib():
         L.or_slice_occupancy.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P,
                                          ctypes.c_double, ctypes.c_double, P]
+        L.or_disc_collision.restype = None
+        L.or_disc_collision.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int64, P, ctypes.c_double, ctypes.c_double, P]
         L.or_proj_stride.restype = ctypes.c_int32
         L.or_num_threads.restype = ctypes.c_int32
         _lib = L
@@ -226,3 +229,15 @@ def slice_occupancy(means, scales, quats, opacity, x0, y0, cell, nx, ny, heights
                              float(cell), int(nx), int(ny), heights.size, _p(heights), float(rho_min), float(amb),
                              _p(occ))
     return occ
+
+
+def disc_collision(occ_map, x0, y0, cell, xy, radius, amb=1e-9):
+    """Per query (x, y): 1 if a disc of `radius` meets an occupied cell of
+    occ_map ([ny, nx] bytes), 0 if not, 2 if undecided (see slice.c)."""
+    m = _c(occ_map, np.uint8)
+    ny, nx = m.shape
+    xy = _c(xy, np.float64).reshape(-1, 2)
+    out = np.zeros(xy.shape[0], np.int8)
+    lib().or_disc_collision(_p(m), float(x0), float(y0), float(cell), int(nx), int(ny), xy.shape[0], _p(xy),
+                            float(radius), float(amb), _p(out))
+    return out

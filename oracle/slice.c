@@ -138,3 +138,27 @@ void or_slice_occupancy(int64_t n, const float* means, const float* scales, cons
     }
     free(P);
 }
+
+/* Disc robots against a 2D occupancy map: query q at (x, y) with radius
+ * rad collides (1) when some occupied cell's closed square lies within
+ * distance rad of (x, y), else 0; 2 when the nearest occupied square is
+ * within a relative margin amb of rad.  Cells outside the grid are free.
+ * Every cell is examined (no search structure). */
+void or_disc_collision(const uint8_t* map, double x0, double y0, double cell, int32_t nx, int32_t ny, int64_t n,
+                       const double* xy, double rad, double amb, int8_t* out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; q++) {
+        const double x = xy[2 * q], y = xy[2 * q + 1];
+        double best = INFINITY;
+        for (int32_t j = 0; j < ny; j++)
+            for (int32_t i = 0; i < nx; i++) {
+                if (!map[(size_t)j * nx + i]) continue;
+                const double ax = x0 + (double)i * cell, ay = y0 + (double)j * cell;
+                const double dx = fmax(fmax(ax - x, 0.0), x - (ax + cell));
+                const double dy = fmax(fmax(ay - y, 0.0), y - (ay + cell));
+                const double d = sqrt(dx * dx + dy * dy);
+                if (d < best) best = d;
+            }
+        out[q] = best <= rad * (1.0 - amb) ? 1 : (best <= rad * (1.0 + amb) ? 2 : 0);
+    }
+}

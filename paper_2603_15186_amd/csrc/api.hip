@@ -1507,6 +1507,21 @@ hgs_status hgs_slice_occupancy(hgs_ctx* c, void* stream, const hgs_slice_grid* g
     return HGS_OK;
 }
 
+hgs_status hgs_disc_collision(hgs_ctx* c, void* stream, const uint8_t* map, double x0, double y0, double cell,
+                              int32_t nx, int32_t ny, int64_t n, const double* xy, double radius, uint8_t* out) {
+    if (!c) return HGS_E_INVALID;
+    if (nx < 1 || ny < 1 || nx > 16384 || ny > 16384) return fail(c, HGS_E_INVALID, "grid must be 1..16384 cells per side");
+    if (n < 0 || (n > 0 && (!map || !xy || !out))) return fail(c, HGS_E_INVALID, "bad query arrays");
+    if (!(cell > 0.0) || !std::isfinite(cell) || !std::isfinite(x0) || !std::isfinite(y0))
+        return fail(c, HGS_E_INVALID, "cell size must be positive and the corner finite");
+    if (!(radius >= 0.0) || !std::isfinite(radius)) return fail(c, HGS_E_INVALID, "radius must be finite and >= 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    DiscArgs d{map, x0, y0, cell, nx, ny, n, xy, radius, out};
+    launch_disc_collision(d, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
 hgs_status hgs_render_surfaces(hgs_ctx* c, void* stream, int32_t view, int32_t ss, float* rgb) {
     if (!c || !rgb) return HGS_E_INVALID;
     if (view < 0 || view >= (int32_t)c->cams.size()) return fail(c, HGS_E_INVALID, "view out of range");

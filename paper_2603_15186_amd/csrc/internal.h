@@ -227,6 +227,18 @@ struct SliceArgs {
 };
 void launch_slice(const SliceArgs& a, hipStream_t s);
 
+// Disc robots against a 2D map (slice.hip).
+struct DiscArgs {
+    const uint8_t* map;              // [ny][nx], nonzero = occupied
+    double x0, y0, cell;
+    int nx, ny;
+    int64_t n;
+    const double* xy;                // n (x, y) pairs
+    double radius;
+    uint8_t* out;                    // n flags
+};
+void launch_disc_collision(const DiscArgs& d, hipStream_t s);
+
 // learned-LOD network (mlp.hip)
 void launch_mlp_forward(const float* feats, uint32_t n, const float* mean, const float* stdv, const uint16_t* w,
                         float* logits, hipStream_t s);

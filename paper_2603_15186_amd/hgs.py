@@ -122,6 +122,8 @@ EXPORTS = [
     ("hgs_set_surfaces", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
     ("hgs_render_surfaces", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
     ("hgs_slice_occupancy", ctypes.c_int32, [_P, _P, ctypes.POINTER(hgs_slice_grid), _P, _P]),
+    ("hgs_disc_collision", ctypes.c_int32, [_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_double, _P]),
 ]
 
 N_MLP_PARAMS = 1377
@@ -415,6 +417,18 @@ class Renderer:
         self._check(self.lib.hgs_slice_occupancy(self.ctx, self._stream(stream), ctypes.byref(g),
                                                  o.data_ptr() if o is not None else None, m.data_ptr()))
         return o, m
+
+    def disc_collision(self, occ_map, x0, y0, cell, xy, radius, stream=None):
+        """Flags (uint8 [n]) of discs of `radius` at xy (device float64 [n, 2])
+        that meet an occupied cell of occ_map (device uint8 [ny, nx])."""
+        import torch
+        ny, nx = occ_map.shape
+        n = xy.shape[0]
+        out = torch.empty(n, dtype=torch.uint8, device=xy.device)
+        self._check(self.lib.hgs_disc_collision(self.ctx, self._stream(stream), occ_map.data_ptr(), float(x0), float(y0),
+                                                float(cell), int(nx), int(ny), int(n), xy.data_ptr(), float(radius),
+                                                out.data_ptr()))
+        return out
 
     def sort_pairs(self, keys, vals, key_bits, stream=None):
         """Sort device uint32 tensors (as int32 storage) in place."""

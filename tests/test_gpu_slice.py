@@ -84,3 +84,45 @@ def test_slice_arguments_are_checked(R):
         R.slice_occupancy(0, 0, 0.0, 10, 10, [0.5])
     with pytest.raises(hgs.HgsError):
         R.slice_occupancy(0, 0, 0.05, 0, 10, [0.5])
+
+
+def test_disc_collision_matches_oracle(R):
+    """Disc robots against random maps and against the plan's collision map:
+    every decided query agrees with the oracle's brute force over all cells;
+    queries off the grid see free space."""
+    scene = make_random_box(10, seed=2)
+    R.load_scene(scene)
+    rng = np.random.default_rng(9)
+    for ny, nx, p in ((37, 53, 0.03), (128, 96, 0.002)):
+        m = (rng.uniform(size=(ny, nx)) < p).astype(np.uint8)
+        xy = np.stack([rng.uniform(-0.3, nx * 0.05 + 0.3, 4000), rng.uniform(-0.3, ny * 0.05 + 0.3, 4000)], 1)
+        for radius in (0.0, 0.07, 0.3):
+            got = R.disc_collision(torch.from_numpy(m).cuda(), 0.0, 0.0, 0.05, torch.from_numpy(xy).cuda(),
+                                   radius).cpu().numpy()
+            want = O.disc_collision(m, 0.0, 0.0, 0.05, xy, radius)
+            _compare(got, want)
+    far = R.disc_collision(torch.from_numpy(m).cuda(), 0.0, 0.0, 0.05,
+                           torch.tensor([[-5.0, -5.0], [100.0, 2.0]], dtype=torch.float64).cuda(), 0.5)
+    assert far.cpu().numpy().tolist() == [0, 0]
+
+
+def test_robot_poses_against_the_plan_collision_map(R):
+    """The 2M-leaf plan's union map (15 planes, 5 cm) and 20,000 random
+    positions for a 0.25 m robot: GPU = oracle on every decided query; the
+    trajectory poses of the generator (0.3 m clearance) are free."""
+    scene, cams, fp = W.plan2m(n_poses=200, with_plan=True)
+    R.load_scene(scene)
+    heights = np.arange(0.1, 1.55, 0.1).astype(np.float32)
+    _, m = R.slice_occupancy(-0.1, -0.1, 0.05, 404, 304, heights)
+    rng = np.random.default_rng(10)
+    xy = rng.uniform([-0.1, -0.1], [20.1, 15.1], size=(20000, 2))
+    got = R.disc_collision(m, -0.1, -0.1, 0.05, torch.from_numpy(xy).cuda(), 0.25).cpu().numpy()
+    mh = m.cpu().numpy()
+    want = O.disc_collision(mh, -0.1, -0.1, 0.05, xy, 0.25)
+    _compare(got, want)
+    print("colliding fraction", got.mean(), flush=True)
+    assert 0.05 < got.mean() < 0.95
+    path = np.array([[c.position[0], c.position[1]] for c in cams], np.float64)
+    free = R.disc_collision(m, -0.1, -0.1, 0.05, torch.from_numpy(path).cuda(), 0.2).cpu().numpy()
+    print("trajectory poses colliding at 0.2 m:", int(free.sum()), "of", free.size, flush=True)
+    assert free.mean() < 0.05

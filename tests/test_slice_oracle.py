@@ -163,3 +163,47 @@ def test_vertical_sheet_occupies_a_line_of_cells():
         cols = np.nonzero(occ[k].any(axis=0))[0]
         assert set(cols.tolist()) <= {19, 20}
         assert occ[k][6:34, 19].all() or occ[k][6:34, 20].all()
+
+
+def test_disc_collision_single_cell_closed_form():
+    """One occupied cell [1.0, 1.05] x [2.0, 2.05]: a disc collides iff its
+    centre is within the radius of the square (distance to the clamped
+    point); cells outside the grid count as free."""
+    m = np.zeros((60, 40), np.uint8)
+    m[40, 20] = 1                       # x0 = 0, y0 = 0, cell 0.05
+    rng = np.random.default_rng(6)
+    xy = rng.uniform([0.5, 1.5], [1.6, 2.6], size=(2000, 2))
+    got = O.disc_collision(m, 0.0, 0.0, 0.05, xy, 0.2)
+    cx = np.clip(xy[:, 0], 1.0, 1.05)
+    cy = np.clip(xy[:, 1], 2.0, 2.05)
+    d = np.hypot(xy[:, 0] - cx, xy[:, 1] - cy)
+    np.testing.assert_array_equal(got == 1, d < 0.2 * (1 - 1e-9))
+    assert set(np.unique(got[np.abs(d - 0.2) > 1e-6])) <= {0, 1}
+    far = O.disc_collision(m, 0.0, 0.0, 0.05, np.array([[5.0, 5.0], [-3.0, 1.0]]), 0.5)
+    assert np.all(far == 0)
+
+
+def test_disc_collision_against_sampled_discs():
+    """Random maps: a sample point of the disc inside an occupied cell means
+    collision; a collision means some occupied square is within the radius
+    (checked on its corners' and edges' nearest points)."""
+    rng = np.random.default_rng(7)
+    m = (rng.uniform(size=(30, 30)) < 0.04).astype(np.uint8)
+    xy = rng.uniform(0, 1.5, size=(300, 2))
+    got = O.disc_collision(m, 0.0, 0.0, 0.05, xy, 0.12)
+    t = np.linspace(0, 2 * np.pi, 64, endpoint=False)
+    rr = np.linspace(0, 0.12 * (1 - 1e-6), 12)
+    for q in range(300):
+        px = (xy[q, 0] + rr[:, None] * np.cos(t)[None, :]).ravel()
+        py = (xy[q, 1] + rr[:, None] * np.sin(t)[None, :]).ravel()
+        i = np.floor(px / 0.05).astype(int)
+        j = np.floor(py / 0.05).astype(int)
+        ok = (i >= 0) & (i < 30) & (j >= 0) & (j < 30)
+        hit = bool(m[j[ok], i[ok]].any())
+        if hit:
+            assert got[q] == 1, q
+        if got[q] == 1:
+            jj, ii = np.nonzero(m)
+            dx = np.maximum(np.maximum(ii * 0.05 - xy[q, 0], 0), xy[q, 0] - (ii + 1) * 0.05)
+            dy = np.maximum(np.maximum(jj * 0.05 - xy[q, 1], 0), xy[q, 1] - (jj + 1) * 0.05)
+            assert np.hypot(dx, dy).min() <= 0.12
