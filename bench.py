@@ -302,6 +302,19 @@ def run_slice(args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     frac = [float(r.slice_occupancy(-0.1, -0.1, cell, nx, ny, h)[1].float().mean()) for h in floors]
+    # collision checks of 1M disc robots (radius 0.25 m) against floor 0's map
+    _, m0 = r.slice_occupancy(-0.1, -0.1, cell, nx, ny, floors[0], occ=False)
+    rng = np.random.default_rng(0)
+    q = torch.from_numpy(rng.uniform([-0.1, -0.1], [20.1, 15.1], size=(1 << 20, 2))).cuda()
+    r.disc_collision(m0, -0.1, -0.1, cell, q, 0.25)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        hits = r.disc_collision(m0, -0.1, -0.1, cell, q, 0.25)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_q = e0.elapsed_time(e1) / args.steps
+    log(f"maps {ms:.3f} ms per step; 1M collision queries {ms_q:.3f} ms ({float(hits.float().mean()):.3f} colliding)")
     planes = sum(len(h) for h in floors)
     cells = planes * nx * ny
     # algorithmic bytes per step: each leaf's 48-byte record and id per map,
@@ -328,7 +341,8 @@ def run_slice(args):
            "roofline": {"kernel": "k_slice", "bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
                         "frac": gbs / 8000.0, "traffic": None},
            "cpu_baseline": cpu,
-           "extra": {"occupied_fraction_per_floor": frac, "algorithmic_bytes_per_step": alg}}
+           "extra": {"occupied_fraction_per_floor": frac, "algorithmic_bytes_per_step": alg,
+                     "collision_queries_per_s": (1 << 20) / (ms_q * 1e-3), "collision_radius_m": 0.25}}
     print(json.dumps(out), flush=True)
     r.close()
 
