@@ -284,6 +284,45 @@ def plan_lod():
     return scene, held
 
 
+def _check_learned_view(scene, model, cam, got, img, rng, n_px=2000):
+    """The GPU's learned cut `got` of view `cam` against the threshold cut:
+    every threshold-cut node has exactly one ancestor-or-self in `got`, the
+    node itself or a candidate of the band (refined by the threshold,
+    projected size <= s_hi); every node of `got` outside the threshold cut is
+    such a candidate.  Then n_px sampled pixels and one full row of `img`
+    (rgb, depth, alpha) against the oracle's render of `got`."""
+    from tests import parity
+    thr = O.cut(scene, cam, O.MODE_THRESHOLD, 1.0)
+    lhs, d2 = _sizes(scene, cam)
+    internal = scene.child_count > 0
+    band = internal & (lhs > d2) & (lhs <= (model.s_hi * model.s_hi) * d2)   # tau = 1
+    in_got = np.zeros(scene.n, bool)
+    in_got[got] = True
+    hits = np.zeros(thr.size, np.int64)
+    first = np.full(thr.size, -1, np.int64)
+    cur = thr.astype(np.int64)
+    while True:
+        alive = cur >= 0
+        if not alive.any():
+            break
+        h = alive & in_got[np.where(alive, cur, 0)]
+        hits += h
+        first = np.where(h & (first < 0), cur, first)
+        cur = np.where(alive, scene.parent[np.where(alive, cur, 0)], -1)
+    assert np.all(hits == 1)
+    assert np.all((first == thr) | band[first])
+    assert np.all(band[np.setdiff1d(got, thr)])
+    assert got.size <= thr.size
+    px = np.concatenate([rng.integers(0, cam.width, n_px), np.arange(cam.width)])
+    py = np.concatenate([rng.integers(0, cam.height, n_px), np.full(cam.width, cam.height // 3)])
+    res = O.render_pixels(O.project(scene, got, cam), cam, px, py)
+    g = parity.gpu_pixels(*img, px, py)
+    ok, best, skipped = parity.branch_errors(g, res)
+    msg = parity.summary(ok, best, skipped)
+    print(got.size, thr.size, msg, flush=True)
+    assert ok.all(), msg
+
+
 def test_bench_step_at_full_size(R, plan_lod):
     """The benchmark's step at full size: 50 held-out 1280x720 views of the
     2M-leaf plan in one call with the committed learned-cut network,
@@ -294,7 +333,6 @@ def test_bench_step_at_full_size(R, plan_lod):
     is such a candidate; 2,000 sampled pixels and one full row match the
     oracle's render of the GPU's cut."""
     from paper_2603_15186_amd import hgs, lod
-    from tests import parity
     scene, held = plan_lod
     model = lod.LodModel.load(lod.default_model_path())
     R.load_scene(scene)
@@ -312,37 +350,40 @@ def test_bench_step_at_full_size(R, plan_lod):
         assert st["graph_launches"] >= 2 and st["passes"] == 1
         rng = np.random.default_rng(11)
         for v in (0, 21, 49):
-            cam = views[v]
-            got = R.get_cut(v)
-            thr = O.cut(scene, cam, O.MODE_THRESHOLD, 1.0)
-            lhs, d2 = _sizes(scene, cam)
-            internal = scene.child_count > 0
-            band = internal & (lhs > d2) & (lhs <= (model.s_hi * model.s_hi) * d2)   # tau = 1
-            in_got = np.zeros(scene.n, bool)
-            in_got[got] = True
-            hits = np.zeros(thr.size, np.int64)
-            first = np.full(thr.size, -1, np.int64)
-            cur = thr.astype(np.int64)
-            while True:
-                alive = cur >= 0
-                if not alive.any():
-                    break
-                h = alive & in_got[np.where(alive, cur, 0)]
-                hits += h
-                first = np.where(h & (first < 0), cur, first)
-                cur = np.where(alive, scene.parent[np.where(alive, cur, 0)], -1)
-            assert np.all(hits == 1), v
-            assert np.all((first == thr) | band[first]), v
-            extra = np.setdiff1d(got, thr)
-            assert np.all(band[extra]), v
-            assert got.size <= thr.size
-            px = np.concatenate([rng.integers(0, cam.width, 2000), np.arange(cam.width)])
-            py = np.concatenate([rng.integers(0, cam.height, 2000), np.full(cam.width, cam.height // 3)])
-            res = O.render_pixels(O.project(scene, got, cam), cam, px, py)
-            g = parity.gpu_pixels(*[t.cpu().numpy() for t in outs[v]], px, py)
-            ok, best, skipped = parity.branch_errors(g, res)
-            msg = parity.summary(ok, best, skipped)
-            print(v, got.size, thr.size, msg, flush=True)
-            assert ok.all(), msg
+            _check_learned_view(scene, model, views[v], R.get_cut(v), [t.cpu().numpy() for t in outs[v]], rng)
     finally:
         R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+
+
+@pytest.fixture(scope="module")
+def building():
+    return W.building30m()
+
+
+@pytest.mark.timeout(900)
+def test_building_batch_at_full_size(R, building):
+    """The 30M-leaf building's benchmark batch at full size: 64 views at
+    1920x1080 (f = 1300) in one call with the building's learned cut, from a
+    captured graph; one view per floor checked as in the 720p step above."""
+    from paper_2603_15186_amd import hgs, lod
+    scene, views = building
+    model = lod.LodModel.load(lod.default_model_path("building30m_lod_mlp.npz"))
+    R.load_scene(scene)
+    model.install(R)
+    R.set_cameras(views)
+    R.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
+    outs = R.alloc_outputs()
+    R.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
+    try:
+        for _ in range(2):
+            R.render(outs)
+        torch.cuda.synchronize()
+        assert R.stats()["passes"] == 1
+        rng = np.random.default_rng(12)
+        for v in (5, 40):
+            _check_learned_view(scene, model, views[v], R.get_cut(v), [t.cpu().numpy() for t in outs[v]], rng,
+                                n_px=1500)
+    finally:
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+    del outs
+    torch.cuda.empty_cache()
