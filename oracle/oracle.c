@@ -224,6 +224,90 @@ static void transpose3(const double a[9], double t[9]) {
         for (int j = 0; j < 3; j++) t[3 * j + i] = a[3 * i + j];
 }
 
+/* Camera of the projection (FP64 copies and the Jacobian clamp range). */
+typedef struct {
+    double Rv[9], o[3], fx, fy, cx, cy, xlo, xhi, ylo, yhi, znear;
+} proj_cam;
+
+static void proj_cam_init(proj_cam* k, const or_camera* cam) {
+    for (int i = 0; i < 9; i++) k->Rv[i] = cam->R[i];
+    for (int i = 0; i < 3; i++) k->o[i] = cam->position[i];
+    k->fx = cam->fx; k->fy = cam->fy; k->cx = cam->cx; k->cy = cam->cy;
+    /* Jacobian clamp: x/z within the image's tangent range widened by 15 %
+     * of the image size on each side (1.3 x the half field of view when the
+     * principal point is centred) */
+    const double W = cam->width, H = cam->height;
+    k->xlo = (-k->cx - 0.15 * W) / k->fx; k->xhi = (W - k->cx + 0.15 * W) / k->fx;
+    k->ylo = (-k->cy - 0.15 * H) / k->fy; k->yhi = (H - k->cy + 0.15 * H) / k->fy;
+    k->znear = cam->znear;
+}
+
+/* Sigma = R S S^T R^T of Gaussian g from its normalised quaternion. */
+static void gauss_sigma(const float* scales, const float* quats, int64_t g, double Sig[9]) {
+    double qw = quats[4 * g], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
+    double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    double Rq[9] = {
+        1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+        2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+        2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+    double S[9] = {0};
+    for (int i = 0; i < 3; i++) S[4 * i] = (double)scales[3 * g + i];
+    double RS[9], RSt[9];
+    matmul3(Rq, S, RS);
+    transpose3(RS, RSt);
+    matmul3(RS, RSt, Sig);
+}
+
+/* Projection of one Gaussian (mean mu, covariance Sig, opacity op, SH
+ * coefficients shc[k*3 + c]) into row r. */
+static void project_one(const proj_cam* k, const double mu[3], const double Sig[9], double op, const double* shc,
+                        int K, double* r) {
+    memset(r, 0, sizeof(double) * OP_STRIDE);
+    double d[3] = {mu[0] - k->o[0], mu[1] - k->o[1], mu[2] - k->o[2]};
+    /* camera-space mean, each row summed left to right */
+    double t[3];
+    for (int i = 0; i < 3; i++)
+        t[i] = (k->Rv[3 * i] * d[0] + k->Rv[3 * i + 1] * d[1]) + k->Rv[3 * i + 2] * d[2];
+    r[OP_Z] = t[2];
+    r[OP_ZKEY] = (double)(float)t[2];
+    r[OP_TX] = t[0]; r[OP_TY] = t[1];
+    r[OP_OPAC] = op;
+    if (!(t[2] > k->znear)) return;
+    /* Jacobian of the perspective map at the (clamped) mean */
+    double tz = t[2];
+    double xr = t[0] / tz, yr = t[1] / tz;
+    if (xr < k->xlo) xr = k->xlo;
+    if (xr > k->xhi) xr = k->xhi;
+    if (yr < k->ylo) yr = k->ylo;
+    if (yr > k->yhi) yr = k->yhi;
+    double xh = xr * tz, yh = yr * tz;
+    double J[9] = {k->fx / tz, 0, -k->fx * xh / (tz * tz), 0, k->fy / tz, -k->fy * yh / (tz * tz), 0, 0, 0};
+    double JW[9], JWt[9], tmp[9], C2[9];
+    matmul3(J, k->Rv, JW);
+    transpose3(JW, JWt);
+    matmul3(JW, Sig, tmp);
+    matmul3(tmp, JWt, C2);
+    double s00 = C2[0] + OR_LOWPASS, s01 = C2[1], s11 = C2[4] + OR_LOWPASS;
+    double det = s00 * s11 - s01 * s01;
+    r[OP_S00] = s00; r[OP_S01] = s01; r[OP_S11] = s11;
+    if (!(det > 0.0)) return;
+    r[OP_A] = s11 / det; r[OP_B] = -s01 / det; r[OP_C] = s00 / det;
+    r[OP_U] = k->fx * t[0] / tz + k->cx;
+    r[OP_V] = k->fy * t[1] / tz + k->cy;
+    /* colour from spherical harmonics in the world-space view direction */
+    double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double dir[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
+    double Y[16];
+    or_sh_basis(dir, Y);
+    for (int c = 0; c < 3; c++) {
+        double v = 0.5;
+        for (int q = 0; q < K; q++) v += shc[q * 3 + c] * Y[q];
+        r[OP_R + c] = v < 0 ? 0 : (v > 1 ? 1 : v);
+    }
+    r[OP_VALID] = 1.0;
+}
+
 /* Project the Gaussians ids[0..m) into the camera; out has OP_STRIDE doubles
  * per entry.  Entries behind the near plane (t_z <= znear) or with a
  * non-positive 2D determinant are marked invalid. */
@@ -231,78 +315,64 @@ void or_project(int64_t m, const int32_t* ids, const float* means, const float* 
                 const float* quats, const float* opacity, const float* sh,
                 int32_t sh_degree, const or_camera* cam, double* out) {
     const int K = (sh_degree + 1) * (sh_degree + 1);
-    double Rv[9], o[3];
-    for (int i = 0; i < 9; i++) Rv[i] = cam->R[i];
-    for (int i = 0; i < 3; i++) o[i] = cam->position[i];
-    const double fx = cam->fx, fy = cam->fy, cx = cam->cx, cy = cam->cy;
-    /* Jacobian clamp: x/z within the image's tangent range widened by 15 %
-     * of the image size on each side (1.3 x the half field of view when the
-     * principal point is centred) */
-    const double W = cam->width, H = cam->height;
-    const double xlo = (-cx - 0.15 * W) / fx, xhi = (W - cx + 0.15 * W) / fx;
-    const double ylo = (-cy - 0.15 * H) / fy, yhi = (H - cy + 0.15 * H) / fy;
+    proj_cam k;
+    proj_cam_init(&k, cam);
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < m; e++) {
-        int64_t g = ids[e];
-        double* r = out + OP_STRIDE * e;
-        memset(r, 0, sizeof(double) * OP_STRIDE);
-        double d[3] = {(double)means[3 * g] - o[0], (double)means[3 * g + 1] - o[1],
-                       (double)means[3 * g + 2] - o[2]};
-        /* camera-space mean, each row summed left to right */
-        double t[3];
-        for (int i = 0; i < 3; i++)
-            t[i] = (Rv[3 * i] * d[0] + Rv[3 * i + 1] * d[1]) + Rv[3 * i + 2] * d[2];
-        r[OP_Z] = t[2];
-        r[OP_ZKEY] = (double)(float)t[2];
-        r[OP_TX] = t[0]; r[OP_TY] = t[1];
-        r[OP_OPAC] = (double)opacity[g];
-        if (!(t[2] > (double)cam->znear)) continue;
-        /* Sigma = R S S^T R^T from the normalised quaternion */
-        double qw = quats[4 * g], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
-        double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-        qw /= qn; qx /= qn; qy /= qn; qz /= qn;
-        double Rq[9] = {
-            1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
-            2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
-            2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
-        double S[9] = {0};
-        for (int i = 0; i < 3; i++) S[4 * i] = (double)scales[3 * g + i];
-        double RS[9], RSt[9], Sig[9];
-        matmul3(Rq, S, RS);
-        transpose3(RS, RSt);
-        matmul3(RS, RSt, Sig);
-        /* Jacobian of the perspective map at the (clamped) mean */
-        double tz = t[2];
-        double xr = t[0] / tz, yr = t[1] / tz;
-        if (xr < xlo) xr = xlo;
-        if (xr > xhi) xr = xhi;
-        if (yr < ylo) yr = ylo;
-        if (yr > yhi) yr = yhi;
-        double xh = xr * tz, yh = yr * tz;
-        double J[9] = {fx / tz, 0, -fx * xh / (tz * tz), 0, fy / tz, -fy * yh / (tz * tz), 0, 0, 0};
-        double JW[9], JWt[9], tmp[9], C2[9];
-        matmul3(J, Rv, JW);
-        transpose3(JW, JWt);
-        matmul3(JW, Sig, tmp);
-        matmul3(tmp, JWt, C2);
-        double s00 = C2[0] + OR_LOWPASS, s01 = C2[1], s11 = C2[4] + OR_LOWPASS;
-        double det = s00 * s11 - s01 * s01;
-        r[OP_S00] = s00; r[OP_S01] = s01; r[OP_S11] = s11;
-        if (!(det > 0.0)) continue;
-        r[OP_A] = s11 / det; r[OP_B] = -s01 / det; r[OP_C] = s00 / det;
-        r[OP_U] = fx * t[0] / tz + cx;
-        r[OP_V] = fy * t[1] / tz + cy;
-        /* colour from spherical harmonics in the world-space view direction */
-        double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        double dir[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
-        double Y[16];
-        or_sh_basis(dir, Y);
-        for (int c = 0; c < 3; c++) {
-            double v = 0.5;
-            for (int k = 0; k < K; k++) v += (double)sh[(g * K + k) * 3 + c] * Y[k];
-            r[OP_R + c] = v < 0 ? 0 : (v > 1 ? 1 : v);
+        const int64_t g = ids[e];
+        double mu[3] = {means[3 * g], means[3 * g + 1], means[3 * g + 2]};
+        double Sig[9], shc[48];
+        gauss_sigma(scales, quats, g, Sig);
+        for (int q = 0; q < 3 * K; q++) shc[q] = (double)sh[g * K * 3 + q];
+        project_one(&k, mu, Sig, (double)opacity[g], shc, K, out + OP_STRIDE * e);
+    }
+}
+
+/* Level-of-detail blending (Sec. III-B: transition regions are smoothly
+ * interpolated; the rule is a reading): a cut node g with parent p takes
+ * mean, covariance, opacity and SH coefficients p + t (g - p), where
+ * t = clamp((s_p - tau) / tau, 0, 1) and s_p = 2 f r_p / |c_p - o| is the
+ * parent's projected size (f = max(fx, fy), (c_p, r_p) its bounding sphere):
+ * a node refined just past the threshold looks like its parent, one whose
+ * parent is twice the threshold looks like itself.  Roots are not blended.
+ * s_p and t are evaluated as written, in FP64. */
+void or_project_blend(int64_t m, const int32_t* ids, const float* means, const float* scales,
+                      const float* quats, const float* opacity, const float* sh, int32_t sh_degree,
+                      const int32_t* parent, const float* bound, float tau, const or_camera* cam,
+                      double* out, double* tout) {
+    const int K = (sh_degree + 1) * (sh_degree + 1);
+    proj_cam k;
+    proj_cam_init(&k, cam);
+    const double f2 = 2.0 * (cam->fx > cam->fy ? (double)cam->fx : (double)cam->fy);
+    const double tauv = tau;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < m; e++) {
+        const int64_t g = ids[e];
+        const int64_t p = parent[g];
+        double t = 1.0;
+        if (p >= 0) {
+            const double dx = (double)bound[4 * p] - k.o[0], dy = (double)bound[4 * p + 1] - k.o[1],
+                         dz = (double)bound[4 * p + 2] - k.o[2];
+            const double d2 = (dx * dx + dy * dy) + dz * dz;
+            const double sp = f2 * (double)bound[4 * p + 3] / sqrt(d2);
+            t = (sp - tauv) / tauv;
+            t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
         }
-        r[OP_VALID] = 1.0;
+        if (tout) tout[e] = t;
+        double mu[3], Sig[9], shc[48], op;
+        gauss_sigma(scales, quats, g, Sig);
+        for (int i = 0; i < 3; i++) mu[i] = means[3 * g + i];
+        op = opacity[g];
+        for (int q = 0; q < 3 * K; q++) shc[q] = (double)sh[g * K * 3 + q];
+        if (p >= 0) {
+            double Sp[9];
+            gauss_sigma(scales, quats, p, Sp);
+            for (int i = 0; i < 9; i++) Sig[i] = Sp[i] + t * (Sig[i] - Sp[i]);
+            for (int i = 0; i < 3; i++) mu[i] = (double)means[3 * p + i] + t * (mu[i] - (double)means[3 * p + i]);
+            op = (double)opacity[p] + t * (op - (double)opacity[p]);
+            for (int q = 0; q < 3 * K; q++) shc[q] = (double)sh[p * K * 3 + q] + t * (shc[q] - (double)sh[p * K * 3 + q]);
+        }
+        project_one(&k, mu, Sig, op, shc, K, out + OP_STRIDE * e);
     }
 }
 

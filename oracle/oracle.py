@@ -77,6 +77,9 @@ def lib():
         L.or_project.restype = None
         L.or_project.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32,
                                  ctypes.POINTER(_Camera), P]
+        L.or_project_blend.restype = None
+        L.or_project_blend.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32, P, P, ctypes.c_float,
+                                       ctypes.POINTER(_Camera), P, P]
         L.or_render_pixels.restype = ctypes.c_int32
         L.or_render_pixels.argtypes = [ctypes.c_int64, P, ctypes.POINTER(_Camera), ctypes.c_int64,
                                        P, P, P, ctypes.c_int32, P, P, P, P]
@@ -157,6 +160,24 @@ def project(scene, ids, cam) -> np.ndarray:
     return out
 
 
+def project_blend(scene, ids, cam, tau, with_t=False):
+    """FP64 projection with level-of-detail blending (see oracle.c): each
+    cut node is interpolated toward its parent by t = clamp((s_p - tau) /
+    tau, 0, 1)."""
+    L = lib()
+    ids = _c(ids, np.int32)
+    m = ids.size
+    out = np.zeros((m, int(L.or_proj_stride())))
+    tout = np.zeros(m)
+    means = _c(scene.means, np.float32); scales = _c(scene.scales, np.float32)
+    quats = _c(scene.quats, np.float32); op = _c(scene.opacity, np.float32)
+    sh = _c(scene.sh, np.float32)
+    par = _c(scene.parent, np.int32); bound = _c(scene.bound, np.float32)
+    L.or_project_blend(m, _p(ids), _p(means), _p(scales), _p(quats), _p(op), _p(sh), int(scene.sh_degree), _p(par),
+                       _p(bound), float(tau), ctypes.byref(_cam(cam)), _p(out), _p(tout))
+    return (out, tout) if with_t else out
+
+
 class PixelResult:
     """Oracle output for a set of pixels.
 
@@ -188,12 +209,13 @@ def render_pixels(proj, cam, px, py, eps=DEFAULT_EPS, cap=8) -> PixelResult:
     return PixelResult(px, py, out, nb, nalg, fl)
 
 
-def render(scene, cam, mode=MODE_THRESHOLD, tau=1.0, eps=DEFAULT_EPS, cap=8, ids=None):
-    """Full-image oracle render.  Returns (PixelResult over all pixels in
+def render(scene, cam, mode=MODE_THRESHOLD, tau=1.0, eps=DEFAULT_EPS, cap=8, ids=None, blend=False):
+    """Full-image oracle render (with blend: level-of-detail transition
+    blending, see project_blend).  Returns (PixelResult over all pixels in
     row-major order, cut ids, projection)."""
     if ids is None:
         ids = cut(scene, cam, mode, tau)
-    proj = project(scene, ids, cam)
+    proj = project_blend(scene, ids, cam, tau) if blend else project(scene, ids, cam)
     yy, xx = np.mgrid[0:cam.height, 0:cam.width]
     res = render_pixels(proj, cam, xx.ravel(), yy.ravel(), eps, cap)
     return res, ids, proj
