@@ -72,6 +72,18 @@ typedef int32_t hgs_status;
                                      renderer itself when a pass would outgrow
                                      the 2^28-entry index space.  Images do not
                                      depend on the passes. */
+#define HGS_OPT_LOD_BLEND 12      /* 1: level-of-detail transition blending (NavGSim
+                                     Sec. III-B: transition regions between levels
+                                     are smoothly interpolated).  A cut node g with
+                                     parent p is drawn with mean, covariance,
+                                     opacity and SH coefficients p + t (g - p),
+                                     t = clamp((s_p - tau) / tau, 0, 1), s_p =
+                                     2 max(fx, fy) r_p / |c_p - o| the parent's
+                                     projected bounding-sphere size in pixels:
+                                     a node just refined looks like its parent,
+                                     one whose parent spans 2 tau looks like
+                                     itself.  Threshold and learned cuts of a
+                                     hierarchy only; 0 (default): off. */
 
 typedef struct hgs_ctx hgs_ctx;
 

@@ -440,6 +440,9 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pa.bins = P<BinRec>(c->bins);
     pa.exact_tiles = c->ropts.exact_tiles;
     pa.ctr = ctr;
+    pa.blend = c->ropts.lod_blend && c->hier && c->lod_mode != HGS_LOD_ALL_LEAVES;
+    pa.parent = P<int32_t>(c->parent);
+    pa.bound = P<float4>(c->bound);
     launch_project(pa, s);
     mark(c, 2, s);
 
@@ -840,6 +843,7 @@ hgs_status hgs_set_cameras(hgs_ctx* c, int32_t n, const hgs_camera* cams) {
         d.W = (double)k.width; d.H = (double)k.height; d.znear = k.znear;
         d.f2 = 2.0 * std::max(d.fx, d.fy);
         d.tau2 = (double)c->tau * (double)c->tau;
+        d.tau = (double)c->tau;
         {
             // same arithmetic order as the device node test (no contraction:
             // these are single products and sums)
@@ -889,7 +893,10 @@ hgs_status hgs_set_lod(hgs_ctx* c, int32_t mode, float tau) {
     c->lod_mode = mode;
     c->tau = tau;
     if (c->views_host) HIP_TRY(c, hipEventSynchronize(c->views_copied));
-    for (size_t v = 0; c->views_host && v < c->cams.size(); ++v) c->views_host[v].tau2 = (double)tau * (double)tau;
+    for (size_t v = 0; c->views_host && v < c->cams.size(); ++v) {
+        c->views_host[v].tau2 = (double)tau * (double)tau;
+        c->views_host[v].tau = (double)tau;
+    }
     c->views_dirty = true;
     return HGS_OK;
 }
@@ -908,6 +915,7 @@ hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
         case HGS_OPT_USE_GRAPH: c->use_graph = val != 0; return HGS_OK;
         case HGS_OPT_PERSISTENT: c->ropts.persistent = val != 0; return HGS_OK;
         case HGS_OPT_EXACT_TILES: c->ropts.exact_tiles = val != 0; return HGS_OK;
+        case HGS_OPT_LOD_BLEND: c->ropts.lod_blend = val != 0; return HGS_OK;
         case HGS_OPT_PASS_VIEWS:
             if (val < 0 || val > kMaxViews) return fail(c, HGS_E_INVALID, "views per pass must be 0..%d", kMaxViews);
             c->pass_views = (int)val;

@@ -41,6 +41,7 @@ struct ViewDev {
     double R[9];
     double fx, fy, cx, cy, W, H, znear;
     double f2, tau2;                 // cut: 2 max(fx, fy) and tau^2
+    double tau;                      // LOD threshold, pixels (transition blending)
     double nl, nr, nt, nb;           // squared lengths of the side-plane normals
     double xlo, xhi, ylo, yhi;       // Jacobian clamp range of x/z and y/z
     float bg[3];
@@ -95,6 +96,7 @@ struct RenderOpts {
     bool count_nalg = false;
     bool persistent = false;
     bool exact_tiles = true;
+    bool lod_blend = false;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -157,6 +159,10 @@ struct ProjectArgs {
     BinRec* bins;
     bool exact_tiles;
     Counters* ctr;
+    // transition blending (blend false: off): parent ids and bounding spheres
+    bool blend;
+    const int32_t* parent;
+    const float4* bound;
 };
 void launch_project(const ProjectArgs& a, hipStream_t s);
 

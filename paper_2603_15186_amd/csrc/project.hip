@@ -31,8 +31,11 @@ constexpr double kBinSlack = 1e-3;
 // normalising factor, e.g. 0.5 sqrt(1/pi), sqrt(3/(4 pi)), 0.5 sqrt(15/pi),
 // 0.25 sqrt(5/pi), 0.25 sqrt(15/pi), 0.25 sqrt(35/(2 pi)), 0.5 sqrt(105/pi),
 // 0.25 sqrt(21/(2 pi)), 0.25 sqrt(7/pi), 0.25 sqrt(105/pi).
-__device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t n, int64_t g, int deg, float x,
-                                          float y, float z, float rgb[3]) {
+// With Blend, coefficient f of node g becomes f_p + t (f_g - f_p) with f_p
+// that of node pg (pg < 0: no blending).
+template <bool Blend>
+__device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t n, int64_t g, int64_t pg, float t,
+                                          int deg, float x, float y, float z, float rgb[3]) {
     constexpr float k00 = 0.28209479177387814f;
     constexpr float k1 = 0.48860251190291992f;
     constexpr float k2a = 1.0925484305920792f, k2b = 0.31539156525252005f, k2c = 0.54627421529603959f;
@@ -69,7 +72,14 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t 
     float acc[3] = {0.5f, 0.5f, 0.5f};
     for (int k = 0; k < K; ++k) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] = fmaf(sh[(int64_t)(k * 3 + c) * n + g], Y[k], acc[c]);
+        for (int c = 0; c < 3; ++c) {
+            float f = sh[(int64_t)(k * 3 + c) * n + g];
+            if (Blend && pg >= 0) {
+                const float fp = sh[(int64_t)(k * 3 + c) * n + pg];
+                f = fp + t * (f - fp);
+            }
+            acc[c] = fmaf(f, Y[k], acc[c]);
+        }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) rgb[c] = fminf(fmaxf(acc[c], 0.f), 1.f);
@@ -156,6 +166,38 @@ __device__ __forceinline__ uint32_t count_tiles(const Proj& p, ushort4 rc, int W
     return n;
 }
 
+// Rows of T = M R diag(s) for the Gaussian with quaternion (w, x, y, z) =
+// q and scales sc, and the entries of T T^T.
+__device__ __forceinline__ void proj_cov(const double M0[3], const double M1[3], float4 q, float4 sc, double* a00,
+                                         double* a01, double* a11) {
+    double qw = q.x, qx = q.y, qy = q.z, qz = q.w;
+    const double qi = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= qi; qx *= qi; qy *= qi; qz *= qi;
+    const double Rq[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
+                          2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
+                          2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
+    const double s[3] = {sc.x, sc.y, sc.z};
+    double T0[3], T1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T0[k] = (M0[0] * Rq[k] + M0[1] * Rq[3 + k] + M0[2] * Rq[6 + k]) * s[k];
+        T1[k] = (M1[0] * Rq[k] + M1[1] * Rq[3 + k] + M1[2] * Rq[6 + k]) * s[k];
+    }
+    *a00 = T0[0] * T0[0] + T0[1] * T0[1] + T0[2] * T0[2];
+    *a01 = T0[0] * T1[0] + T0[1] * T1[1] + T0[2] * T1[2];
+    *a11 = T1[0] * T1[0] + T1[1] * T1[1] + T1[2] * T1[2];
+}
+
+// Blend: level-of-detail transition blending.  Node g with parent p takes
+// the weight t = clamp((s_p - tau) / tau, 0, 1) of the parent's projected
+// bounding-sphere size s_p = 2 max(fx, fy) r_p / |c_p - o| (FP64, in the
+// cut's order of operations), and is projected as the Gaussian with mean
+// mu_p + t (mu_g - mu_p), covariance Sigma_p + t (Sigma_g - Sigma_p) (formed
+// after projection as (1 - t) T_p T_p^T + t T_g T_g^T, positive
+// semidefinite by construction), opacity and SH coefficients interpolated
+// alike.  The blended mean and depth key follow the same FP64 steps as the
+// unblended ones.
+template <bool Blend>
 __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
     const uint32_t m = min(a.ctr->cut, a.cut_cap);
     uint32_t vis = 0;
@@ -164,12 +206,41 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
         const ViewDev& V = a.views[e.y];
         const int64_t g = e.x;
         const float4 g0 = a.geo[3 * g], g1 = a.geo[3 * g + 1], g2 = a.geo[3 * g + 2];
+        int64_t pg = -1;
+        double t = 1.0;
+        float4 p0 = g0;
+        if (Blend) {
+            const int32_t par = a.parent[g];
+            if (par >= 0) {
+                const float4 b = a.bound[par];
+                {
+#pragma clang fp contract(off)
+                    const double bx = (double)b.x - V.o[0], by = (double)b.y - V.o[1], bz = (double)b.z - V.o[2];
+                    const double d2 = (bx * bx + by * by) + bz * bz;
+                    const double sp = V.f2 * (double)b.w / sqrt(d2);
+                    t = (sp - V.tau) / V.tau;
+                }
+                t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+                if (t < 1.0) {
+                    pg = par;
+                    p0 = a.geo[3 * pg];
+                }
+            }
+        }
         double dx, dy, dz, tx, ty, tz;
+        double op = g0.w;
         {
 #pragma clang fp contract(off)
-            dx = (double)g0.x - V.o[0];
-            dy = (double)g0.y - V.o[1];
-            dz = (double)g0.z - V.o[2];
+            double mx = g0.x, my = g0.y, mz = g0.z;
+            if (Blend && pg >= 0) {
+                mx = (double)p0.x + t * ((double)g0.x - (double)p0.x);
+                my = (double)p0.y + t * ((double)g0.y - (double)p0.y);
+                mz = (double)p0.z + t * ((double)g0.z - (double)p0.z);
+                op = (double)p0.w + t * ((double)g0.w - (double)p0.w);
+            }
+            dx = mx - V.o[0];
+            dy = my - V.o[1];
+            dz = mz - V.o[2];
             tx = (V.R[0] * dx + V.R[1] * dy) + V.R[2] * dz;
             ty = (V.R[3] * dx + V.R[4] * dy) + V.R[5] * dz;
             tz = (V.R[6] * dx + V.R[7] * dy) + V.R[8] * dz;
@@ -179,13 +250,6 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
         ushort4 rc = make_ushort4(1, 1, 0, 0);
         const float zf = (float)tz;
         if (tz > V.znear) {
-            // rotation of the normalised quaternion (w, x, y, z)
-            double qw = g1.x, qx = g1.y, qy = g1.z, qz = g1.w;
-            const double qi = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-            qw *= qi; qx *= qi; qy *= qi; qz *= qi;
-            const double Rq[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
-                                  2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
-                                  2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
             const double iz = 1.0 / tz;
             double xr = tx * iz, yr = ty * iz;
             xr = fmin(fmax(xr, V.xlo), V.xhi);
@@ -197,17 +261,19 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
                 M0[j] = V.fx * iz * (V.R[j] - xr * V.R[6 + j]);
                 M1[j] = V.fy * iz * (V.R[3 + j] - yr * V.R[6 + j]);
             }
-            // T = M R diag(s)
-            const double sc[3] = {g2.x, g2.y, g2.z};
-            double T0[3], T1[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                T0[k] = (M0[0] * Rq[k] + M0[1] * Rq[3 + k] + M0[2] * Rq[6 + k]) * sc[k];
-                T1[k] = (M1[0] * Rq[k] + M1[1] * Rq[3 + k] + M1[2] * Rq[6 + k]) * sc[k];
+            double c00, c01, c11;
+            proj_cov(M0, M1, g1, g2, &c00, &c01, &c11);
+            if (Blend && pg >= 0) {
+                double b00, b01, b11;
+                proj_cov(M0, M1, a.geo[3 * pg + 1], a.geo[3 * pg + 2], &b00, &b01, &b11);
+                const double u = 1.0 - t;
+                c00 = u * b00 + t * c00;
+                c01 = u * b01 + t * c01;
+                c11 = u * b11 + t * c11;
             }
-            const double s00 = T0[0] * T0[0] + T0[1] * T0[1] + T0[2] * T0[2] + 0.3;
-            const double s01 = T0[0] * T1[0] + T0[1] * T1[1] + T0[2] * T1[2];
-            const double s11 = T1[0] * T1[0] + T1[1] * T1[1] + T1[2] * T1[2] + 0.3;
+            const double s00 = c00 + 0.3;
+            const double s01 = c01;
+            const double s11 = c11 + 0.3;
             const double det = s00 * s11 - s01 * s01;
             if (det > 0.0) {
                 const double u = V.fx * tx * iz + V.cx;
@@ -220,7 +286,7 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
                 p.p = (float)sqrt(s11 / det);
                 p.r = (float)(-s01 / sqrt(det * s11));
                 p.s = (float)sqrt(is11);
-                p.opacity = g0.w;
+                p.opacity = (float)op;
                 p.z = zf;
                 // pixel-centre bounding box of q <= 9 (1 + slack)
                 const double qm = 9.0 * (1.0 + kBinSlack);
@@ -237,7 +303,8 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
                 if (ntiles > 0) {
                     const double id = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
                     float rgb[3];
-                    sh_colour(a.sh, a.n, g, a.sh_degree, (float)(dx * id), (float)(dy * id), (float)(dz * id), rgb);
+                    sh_colour<Blend>(a.sh, a.n, g, pg, (float)t, a.sh_degree, (float)(dx * id), (float)(dy * id),
+                                     (float)(dz * id), rgb);
                     p.c0 = rgb[0];
                     p.c1 = rgb[1];
                     p.c2 = rgb[2];
@@ -418,7 +485,10 @@ __global__ __launch_bounds__(kNT) void k_emit(EmitArgs a) {
 }  // namespace
 
 void launch_project(const ProjectArgs& a, hipStream_t s) {
-    k_project<<<4096, kNT, 0, s>>>(a);
+    if (a.blend)
+        k_project<true><<<4096, kNT, 0, s>>>(a);
+    else
+        k_project<false><<<4096, kNT, 0, s>>>(a);
 }
 
 void launch_emit(const EmitArgs& a, hipStream_t s) {

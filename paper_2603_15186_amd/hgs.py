@@ -38,6 +38,7 @@ HGS_OPT_INITIAL_CAPACITY = 8
 HGS_OPT_STAGE_TIMING = 9
 HGS_OPT_SORT_DIGIT_BITS = 10
 HGS_OPT_PASS_VIEWS = 11
+HGS_OPT_LOD_BLEND = 12
 
 PROJECTED_FIELDS = ("u", "v", "A", "B", "C", "r", "g", "b", "depth", "opacity", "ntiles", "valid")
 
