@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.c")
-SOURCES = [SRC_PATH, os.path.join(HERE, "slice.c")]
+SOURCES = [SRC_PATH, os.path.join(HERE, "slice.c"), os.path.join(HERE, "nav.c")]
 
 MODE_ALL_LEAVES = 0
 MODE_THRESHOLD = 1
@@ -94,6 +94,14 @@ def lib():
         L.or_disc_collision.restype = None
         L.or_disc_collision.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int64, P, ctypes.c_double, ctypes.c_double, P]
+        L.or_navigable.restype = None
+        L.or_navigable.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_double, ctypes.c_double, P]
+        L.or_distance_fields.restype = None
+        L.or_distance_fields.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
+        L.or_trace_paths.restype = None
+        L.or_trace_paths.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64, P, P, ctypes.c_int32,
+                                     P, P]
         L.or_proj_stride.restype = ctypes.c_int32
         L.or_num_threads.restype = ctypes.c_int32
         _lib = L
@@ -263,3 +271,45 @@ def disc_collision(occ_map, x0, y0, cell, xy, radius, amb=1e-9):
     lib().or_disc_collision(_p(m), float(x0), float(y0), float(cell), int(nx), int(ny), xy.shape[0], _p(xy),
                             float(radius), float(amb), _p(out))
     return out
+
+
+# ------------------------------------------------------------------ planning
+
+
+def navigable(occ_map, x0, y0, cell, radius, amb=1e-9):
+    """[ny, nx] int8: 1 where a disc robot of `radius` centred on the cell is
+    collision free, 0 where it collides, 2 undecided (see nav.c)."""
+    m = _c(occ_map, np.uint8)
+    ny, nx = m.shape
+    out = np.zeros((ny, nx), np.int8)
+    lib().or_navigable(_p(m), float(x0), float(y0), float(cell), int(nx), int(ny), float(radius), float(amb),
+                       _p(out))
+    return out
+
+
+def distance_fields(nav, goals):
+    """Shortest-path distances to each goal cell (index j*nx + i) over the
+    8-connected navigable grid: int64 array [n_goals, ny, nx, 2] of (a, b) =
+    (orthogonal, diagonal) moves, cost a + b sqrt 2; (-1, -1) unreachable."""
+    m = _c(nav, np.uint8)
+    ny, nx = m.shape
+    goals = _c(goals, np.int64).ravel()
+    out = np.zeros((goals.size, ny, nx, 2), np.int64)
+    lib().or_distance_fields(_p(m), int(nx), int(ny), goals.size, _p(goals), _p(out))
+    return out
+
+
+def trace_paths(nav, dist, starts, slots, cap):
+    """Trajectories from cells `starts` down fields dist[slots]: (paths
+    [n, cap] int64 cell indices, lengths [n]); see nav.c for the rule."""
+    m = _c(nav, np.uint8)
+    ny, nx = m.shape
+    dist = _c(dist, np.int64)
+    starts = _c(starts, np.int64).ravel()
+    slots = _c(slots, np.int32).ravel()
+    n = starts.size
+    paths = np.full((n, max(int(cap), 1)), -1, np.int64)
+    lens = np.zeros(n, np.int64)
+    lib().or_trace_paths(_p(m), int(nx), int(ny), _p(dist), n, _p(starts), _p(slots), int(cap), _p(paths),
+                         _p(lens))
+    return paths[:, :cap], lens
