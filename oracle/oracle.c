@@ -163,6 +163,186 @@ int64_t or_cut(int64_t n, const float* bound, const int32_t* parent,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Learned level-of-detail cut                                               */
+/* ------------------------------------------------------------------------ */
+
+/* The learned refinement of the cut is this project's (the paper selects
+ * Gaussians from the tree's levels, Sec. III-B, without a learned rule).
+ * Definition: the threshold cut, except that a candidate, an internal node
+ * the threshold refines whose projected size is at most s_hi pixels, is
+ * refined only when the network's logit z of its 8 standardised features
+ * reaches z* = logit(p*).  Features of node k seen from the camera (FP64):
+ *   0 log of its projected size 2 f r / |c - o| (size at least 1e-6,
+ *     distance at least 1e-9), 1 log of its camera-space depth (at least
+ *     znear), 2 its opacity, 3 its child count, 4 the variance of its
+ *     children's DC colour (C0^2 times the summed per-channel variance of
+ *     the DC coefficients; 0 for fewer than two children), 5 |cos| between
+ *     c - o and its thinnest axis (the rotation's column of the least scale,
+ *     the first on ties), 6 its level, 7 log of its parent's projected size
+ *     (its own for a root).
+ * Network: 8 -> 32 -> 32 -> 1, ReLU, parameters W1[32][8], b1, W2[32][32],
+ * b2, w3, b3 (the BF16 values, widened).  A candidate whose logit lies
+ * within `margin` of z* is reported as undecided; the walk takes z >= z*. */
+typedef struct {
+    const double* w;
+    const double* mean;
+    const double* std;
+    double z_star, s_hi, margin;
+    const float* quats;
+    const float* scales;
+    const float* opacity;
+    const float* sh;
+    int K;
+    const int32_t* parent;
+    const int32_t* level;
+} lod_net;
+
+static double lod_logit(const lod_net* net, const cut_cam* k, const float* bound, const int32_t* first_child,
+                        const int32_t* child_count, int32_t node) {
+    const float* b = bound + 4 * (int64_t)node;
+    const double dx = (double)b[0] - k->o[0], dy = (double)b[1] - k->o[1], dz = (double)b[2] - k->o[2];
+    const double r = b[3];
+    const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+    const double dd = dist > 1e-9 ? dist : 1e-9;
+    double f[8];
+    const double size = k->f2 * r / dd;
+    f[0] = log(size > 1e-6 ? size : 1e-6);
+    const double pz = k->R[6] * dx + k->R[7] * dy + k->R[8] * dz;
+    f[1] = log(pz > k->znear ? pz : k->znear);
+    f[2] = net->opacity[node];
+    const int32_t nc = child_count[node];
+    f[3] = nc;
+    double var = 0.0;
+    if (nc > 1) {
+        for (int c = 0; c < 3; c++) {
+            double s1 = 0.0, s2 = 0.0;
+            for (int32_t j = 0; j < nc; j++) {
+                const double v = net->sh[((int64_t)(first_child[node] + j) * net->K) * 3 + c];
+                s1 += v;
+                s2 += v * v;
+            }
+            const double m = s1 / nc;
+            var += s2 / nc - m * m;
+        }
+        var *= 0.28209479177387814 * 0.28209479177387814;
+    }
+    f[4] = var > 0.0 ? var : 0.0;
+    {
+        const float* q = net->quats + 4 * (int64_t)node;
+        const float* sc = net->scales + 3 * (int64_t)node;
+        const double qn = sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3]);
+        const double qw = q[0] / qn, qx = q[1] / qn, qy = q[2] / qn, qz = q[3] / qn;
+        const double Rq[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy),
+                              2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx),
+                              2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)};
+        int a = 0;
+        if (sc[1] < sc[a]) a = 1;
+        if (sc[2] < sc[a]) a = 2;
+        f[5] = fabs(dx * Rq[a] + dy * Rq[3 + a] + dz * Rq[6 + a]) / dd;
+    }
+    f[6] = net->level[node];
+    const int32_t p = net->parent[node];
+    if (p >= 0) {
+        const float* pb = bound + 4 * (int64_t)p;
+        const double qx = (double)pb[0] - k->o[0], qy = (double)pb[1] - k->o[1], qz = (double)pb[2] - k->o[2];
+        const double pd = sqrt(qx * qx + qy * qy + qz * qz);
+        const double ps = k->f2 * (double)pb[3] / (pd > 1e-9 ? pd : 1e-9);
+        f[7] = log(ps > 1e-6 ? ps : 1e-6);
+    } else {
+        f[7] = f[0];
+    }
+    double x[8], h1[32];
+    for (int i = 0; i < 8; i++) x[i] = (f[i] - net->mean[i]) / net->std[i];
+    const double* W1 = net->w;
+    const double* b1 = W1 + 32 * 8;
+    const double* W2 = b1 + 32;
+    const double* b2 = W2 + 32 * 32;
+    const double* w3 = b2 + 32;
+    const double b3 = w3[32];
+    for (int j = 0; j < 32; j++) {
+        double acc = b1[j];
+        for (int i = 0; i < 8; i++) acc += W1[8 * j + i] * x[i];
+        h1[j] = acc > 0.0 ? acc : 0.0;
+    }
+    double z = b3;
+    for (int j = 0; j < 32; j++) {
+        double acc = b2[j];
+        for (int i = 0; i < 32; i++) acc += W2[32 * j + i] * h1[i];
+        z += w3[j] * (acc > 0.0 ? acc : 0.0);
+    }
+    return z;
+}
+
+typedef struct {
+    cut_walk base;
+    const lod_net* net;
+    int32_t* amb;
+    int64_t amb_cap, amb_count;
+    const int32_t* flip;      /* ascending undecided candidates to take the other way */
+    int64_t n_flip, bad_flips;
+} lcut_walk;
+
+static void lcut_visit(lcut_walk* w, int32_t k) {
+    const float* b = w->base.bound + 4 * (int64_t)k;
+    const cut_cam* cam = w->base.cam;
+    double d[3] = {(double)b[0] - cam->o[0], (double)b[1] - cam->o[1], (double)b[2] - cam->o[2]};
+    double r = (double)b[3];
+    if (cut_culled(cam, d, r)) return;
+    int32_t nc = w->base.child_count[k];
+    int expand = nc > 0 && cut_expand(cam, d, r);
+    if (expand) {
+        const double a = cam->f2 * r;
+        const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+        if (a * a <= (w->net->s_hi * w->net->s_hi) * d2) {
+            const double z = lod_logit(w->net, cam, w->base.bound, w->base.first_child, w->base.child_count, k);
+            if (fabs(z - w->net->z_star) <= w->net->margin) {
+                if (w->amb_count < w->amb_cap) w->amb[w->amb_count] = k;
+                w->amb_count++;
+            }
+            const int undecided = fabs(z - w->net->z_star) <= w->net->margin;
+            expand = z >= w->net->z_star;
+            if (w->n_flip && bsearch(&k, w->flip, (size_t)w->n_flip, sizeof(int32_t), cmp_i32)) {
+                if (undecided) expand = !expand;
+                else w->bad_flips++;
+            }
+        }
+    }
+    if (expand) {
+        for (int32_t j = 0; j < nc; j++) lcut_visit(w, w->base.first_child[k] + j);
+        return;
+    }
+    if (w->base.count < w->base.cap) w->base.out[w->base.count] = k;
+    w->base.count++;
+}
+
+/* Learned cut (see above): node ids ascending in out (count returned),
+ * undecided candidates reached ascending in amb (count in *n_amb).  Every
+ * node of flip (ascending) that the walk reaches as an undecided candidate
+ * takes the other decision, which is as valid; *bad_flips counts flip
+ * nodes reached as decided candidates (left as decided). */
+int64_t or_cut_learned(int64_t n, const float* bound, const int32_t* parent, const int32_t* first_child,
+                       const int32_t* child_count, const int32_t* level, const float* quats, const float* scales,
+                       const float* opacity, const float* sh, int32_t sh_degree, const double* w,
+                       const double* mean, const double* std, double z_star, double s_hi, double margin,
+                       const or_camera* cam, float tau, const int32_t* flip, int64_t n_flip, int32_t* out,
+                       int64_t cap, int32_t* amb, int64_t amb_cap, int64_t* n_amb, int64_t* bad_flips) {
+    cut_cam k;
+    cut_cam_init(&k, cam, tau);
+    lod_net net = {w, mean, std, z_star, s_hi, margin, quats, scales, opacity, sh,
+                   (sh_degree + 1) * (sh_degree + 1), parent, level};
+    lcut_walk lw = {{bound, first_child, child_count, &k, out, cap, 0}, &net, amb, amb_cap, 0, flip, n_flip, 0};
+    for (int64_t i = 0; i < n; i++)
+        if (parent[i] < 0) lcut_visit(&lw, (int32_t)i);
+    int64_t m = lw.base.count < cap ? lw.base.count : cap;
+    qsort(out, (size_t)m, sizeof(int32_t), cmp_i32);
+    int64_t ma = lw.amb_count < amb_cap ? lw.amb_count : amb_cap;
+    qsort(amb, (size_t)ma, sizeof(int32_t), cmp_i32);
+    *n_amb = lw.amb_count;
+    *bad_flips = lw.bad_flips;
+    return lw.base.count;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Real spherical harmonics (Condon-Shortley phase), l <= 3                 */
 /* ------------------------------------------------------------------------ */
 

@@ -8,6 +8,7 @@ follows.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -94,6 +95,11 @@ def lib():
         L.or_disc_collision.restype = None
         L.or_disc_collision.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int64, P, ctypes.c_double, ctypes.c_double, P]
+        L.or_cut_learned.restype = ctypes.c_int64
+        L.or_cut_learned.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, P, ctypes.c_int32, P, P, P,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_Camera),
+                                     ctypes.c_float, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.or_navigable.restype = None
         L.or_navigable.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_double, ctypes.c_double, P]
@@ -151,6 +157,45 @@ def cut(scene, cam, mode=MODE_THRESHOLD, tau=1.0) -> np.ndarray:
         if cnt <= cap:
             return out[:cnt].copy()
         cap = int(cnt)
+
+
+def cut_learned(scene, cam, params, mean, std, p_star, s_hi, tau=1.0, margin=1e-3, flip=()):
+    """Learned level-of-detail cut (see oracle.c): (ascending node ids,
+    ascending undecided candidates: logit within `margin` of logit(p*)).
+    params: the network's 1377 parameters as used (BF16 values); mean, std:
+    feature standardisation; 0 < p* < 1.  Undecided candidates listed in
+    `flip` take the other (equally valid) decision; listing a decided one
+    raises ValueError."""
+    L = lib()
+    if not 0.0 < float(p_star) < 1.0:
+        raise ValueError("p* must lie in (0, 1)")
+    n = scene.n
+    lvl = np.zeros(n, np.int32)
+    lo = np.asarray(scene.level_offset, np.int64)
+    for l in range(lo.size - 1):
+        lvl[lo[l]:lo[l + 1]] = l
+    arrs = [_c(scene.bound, np.float32), _c(scene.parent, np.int32), _c(scene.first_child, np.int32),
+            _c(scene.child_count, np.int32), lvl, _c(scene.quats, np.float32), _c(scene.scales, np.float32),
+            _c(scene.opacity, np.float32), _c(scene.sh, np.float32)]
+    w = _c(params, np.float64); mu = _c(mean, np.float64); sd = _c(std, np.float64)
+    ps = float(np.float32(p_star))
+    z_star = math.log(ps) - math.log1p(-ps)
+    k = _cam(cam)
+    cap = 1 << 16
+    while True:
+        out = np.empty(cap, np.int32)
+        amb = np.empty(cap, np.int32)
+        na = ctypes.c_int64()
+        bad = ctypes.c_int64()
+        fl = np.unique(np.asarray(flip, np.int32))
+        cnt = L.or_cut_learned(n, *[_p(a) for a in arrs[:9]], int(scene.sh_degree), _p(w), _p(mu), _p(sd),
+                               z_star, float(s_hi), float(margin), ctypes.byref(k), float(tau), _p(fl), fl.size,
+                               _p(out), cap, _p(amb), cap, ctypes.byref(na), ctypes.byref(bad))
+        if bad.value:
+            raise ValueError(f"{bad.value} flipped candidates are decided")
+        if cnt <= cap and na.value <= cap:
+            return out[:cnt].copy(), amb[:na.value].copy()
+        cap = int(max(cnt, na.value))
 
 
 def project(scene, ids, cam) -> np.ndarray:
