@@ -389,6 +389,47 @@ hgs_status hgs_slice_occupancy(hgs_ctx* ctx, void* stream, const hgs_slice_grid*
 hgs_status hgs_disc_collision(hgs_ctx* ctx, void* stream, const uint8_t* map, double x0, double y0, double cell,
                               int32_t nx, int32_t ny, int64_t n, const double* xy, double radius, uint8_t* out);
 
+/* Shortest-path planning on the navigable areas (NavGSim Sec. III-C: the
+ * slice map serves collision checks and path planning; Sec. IV: expert
+ * trajectories from a shortest-path planner between random starts and
+ * goals).  Grids are row-major [ny][nx]; a cell index is j * nx + i. */
+
+/* Navigable map for a disc robot: nav[j * nx + i] = 1 when the closed disc
+ * of `radius` metres around the cell's centre (x0 + (i + 1/2) cell,
+ * y0 + (j + 1/2) cell) meets no occupied cell of map (the test of
+ * hgs_disc_collision), else 0.  map and nav: device, ny * nx bytes,
+ * caller-owned.  Asynchronous on `stream`.  HGS_E_INVALID on bad sizes. */
+hgs_status hgs_navigable_map(hgs_ctx* ctx, void* stream, const uint8_t* map, double x0, double y0, double cell,
+                             int32_t nx, int32_t ny, double radius, uint8_t* nav);
+
+/* Distance fields to n_goals goal cells over the navigable cells (nav != 0)
+ * of an 8-connected grid: orthogonal moves cost 1, diagonal moves sqrt 2
+ * and need both side cells navigable.  dist[g * ny * nx + c] (device,
+ * caller-owned, n_goals * ny * nx uint64) = a | b << 32 with (a, b) the
+ * orthogonal and diagonal moves of a shortest path from cell c to goal g
+ * (unique: the cost a + b sqrt 2 determines it), or UINT64_MAX when c is
+ * unreachable; a goal outside the grid or on a blocked cell reaches
+ * nothing.  goals: host array of n_goals cell indices.  Blocking: returns
+ * after the fields are complete; *rounds (may be NULL) receives the number
+ * of relaxation rounds.  Grids up to 2^24 cells, 1..16384 per side;
+ * n_goals 1..65535.  HGS_E_INVALID on bad sizes. */
+hgs_status hgs_distance_fields(hgs_ctx* ctx, void* stream, const uint8_t* nav, int32_t nx, int32_t ny,
+                               int32_t n_goals, const int32_t* goals, uint64_t* dist, int64_t* rounds);
+
+/* Trajectories down distance fields: query q starts at cell starts[q] and
+ * follows field slots[q]; at each step it moves to the first neighbour, in
+ * the order E (+x), W, S (+y), N, SE, SW, NE, NW, that is a legal move and
+ * whose pair plus the move's unit equals the current pair, until the goal.
+ * lengths[q] = cells on the path, start and goal included (0: start off the
+ * grid, slot out of range or start unreachable; -1: dist is not a distance
+ * field); the first min(length, cap) cells go to paths[q * cap ...].
+ * nav and dist as for hgs_distance_fields; starts, slots, paths, lengths:
+ * device, caller-owned.  Asynchronous on `stream`.  HGS_E_INVALID on bad
+ * sizes. */
+hgs_status hgs_trace_paths(hgs_ctx* ctx, void* stream, const uint8_t* nav, int32_t nx, int32_t ny,
+                           const uint64_t* dist, int32_t n_goals, int64_t n, const int32_t* starts,
+                           const int32_t* slots, int32_t cap, int32_t* paths, int32_t* lengths);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,9 @@ struct hgs_ctx {
     int64_t acc_n = 0;
     // sort scratch for hgs_sort_pairs
     DevMem sort_k, sort_v, sort_n;
+    // distance-field scratch: goals, tile flags, per-round change counts
+    DevMem nav_goals, nav_flags, nav_active;
+    uint32_t* nav_active_host = nullptr;   // pinned
 };
 
 namespace {
@@ -655,8 +658,10 @@ void hgs_destroy(hgs_ctx* c) {
                      &c->tile_view, &c->mlp_w, &c->mlp_w32, &c->mlp_dev, &c->frontier[0], &c->frontier[1], &c->cut, &c->proj,
                      &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->bins, &c->offsets, &c->dec,
                      &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
-                     &c->counters, &c->sort_k, &c->sort_v, &c->sort_n};
+                     &c->counters, &c->sort_k, &c->sort_v, &c->sort_n, &c->nav_goals, &c->nav_flags,
+                     &c->nav_active};
     for (DevMem* m : all) release(*m);
+    if (c->nav_active_host) (void)hipHostFree(c->nav_active_host);
     if (c->views_host) (void)hipHostFree(c->views_host);
     if (c->ctr_host) (void)hipHostFree(c->ctr_host);
     if (c->views_copied) (void)hipEventDestroy(c->views_copied);
@@ -1526,6 +1531,100 @@ hgs_status hgs_disc_collision(hgs_ctx* c, void* stream, const uint8_t* map, doub
     HIP_TRY(c, hipSetDevice(c->device));
     DiscArgs d{map, x0, y0, cell, nx, ny, n, xy, radius, out};
     launch_disc_collision(d, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
+namespace {
+
+hgs_status check_grid(hgs_ctx* c, int32_t nx, int32_t ny) {
+    if (nx < 1 || ny < 1 || nx > 16384 || ny > 16384) return fail(c, HGS_E_INVALID, "grid must be 1..16384 cells per side");
+    if ((int64_t)nx * ny > (int64_t)1 << 24) return fail(c, HGS_E_INVALID, "grid must hold at most 2^24 cells");
+    return HGS_OK;
+}
+
+constexpr int kNavBatch = 16;          // relaxation rounds between convergence checks
+constexpr int64_t kNavMaxRounds = 1 << 22;
+
+}  // namespace
+
+hgs_status hgs_navigable_map(hgs_ctx* c, void* stream, const uint8_t* map, double x0, double y0, double cell,
+                             int32_t nx, int32_t ny, double radius, uint8_t* nav) {
+    if (!c) return HGS_E_INVALID;
+    if (hgs_status s = check_grid(c, nx, ny)) return s;
+    if (!map || !nav) return fail(c, HGS_E_INVALID, "map and nav must be device buffers");
+    if (!(cell > 0.0) || !std::isfinite(cell) || !std::isfinite(x0) || !std::isfinite(y0))
+        return fail(c, HGS_E_INVALID, "cell size must be positive and the corner finite");
+    if (!(radius >= 0.0) || !std::isfinite(radius)) return fail(c, HGS_E_INVALID, "radius must be finite and >= 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    NavArgs a{map, x0, y0, cell, nx, ny, radius, nav};
+    launch_navigable(a, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_distance_fields(hgs_ctx* c, void* stream, const uint8_t* nav, int32_t nx, int32_t ny,
+                               int32_t n_goals, const int32_t* goals, uint64_t* dist, int64_t* rounds) {
+    if (!c) return HGS_E_INVALID;
+    if (hgs_status s = check_grid(c, nx, ny)) return s;
+    if (n_goals < 1 || n_goals > 65535) return fail(c, HGS_E_INVALID, "n_goals must be 1..65535");
+    if (!nav || !goals || !dist) return fail(c, HGS_E_INVALID, "nav, goals and dist are required");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int T = dist_tile();
+    const int tx = (nx + T - 1) / T, ty = (ny + T - 1) / T;
+    const size_t tiles = (size_t)tx * ty;
+    hgs_status s;
+    if ((s = ensure(c, c->nav_goals, (size_t)n_goals * 4)) || (s = ensure(c, c->nav_flags, 2 * tiles * n_goals)) ||
+        (s = ensure(c, c->nav_active, kNavBatch * 4)))
+        return s;
+    if (!c->nav_active_host)
+        HIP_TRY(c, hipHostMalloc((void**)&c->nav_active_host, kNavBatch * 4, hipHostMallocDefault));
+    HIP_TRY(c, hipMemcpyAsync(c->nav_goals.p, goals, (size_t)n_goals * 4, hipMemcpyHostToDevice, st));
+    DistArgs d{};
+    d.nav = nav;
+    d.nx = nx;
+    d.ny = ny;
+    d.tiles_x = tx;
+    d.tiles_y = ty;
+    d.n_goals = n_goals;
+    d.goals = P<int32_t>(c->nav_goals);
+    d.dist = dist;
+    d.flags[0] = P<uint8_t>(c->nav_flags);
+    d.flags[1] = P<uint8_t>(c->nav_flags) + tiles * n_goals;
+    d.active = P<uint32_t>(c->nav_active);
+    launch_dist_init(d, st);
+    HIP_TRY(c, hipGetLastError());
+    // rounds in batches; a round in which no tile changed is a fixed point
+    int64_t done = -1;
+    for (int64_t r0 = 0; r0 < kNavMaxRounds && done < 0; r0 += kNavBatch) {
+        launch_dist_rounds(d, (int)(r0 & 1), kNavBatch, st);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipMemcpyAsync(c->nav_active_host, c->nav_active.p, kNavBatch * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        for (int k = 0; k < kNavBatch; ++k)
+            if (c->nav_active_host[k] == 0) {
+                done = r0 + k + 1;
+                break;
+            }
+    }
+    if (done < 0) return fail(c, HGS_E_UNSUPPORTED, "distance fields did not settle within %lld rounds", (long long)kNavMaxRounds);
+    if (rounds) *rounds = done;
+    return HGS_OK;
+}
+
+hgs_status hgs_trace_paths(hgs_ctx* c, void* stream, const uint8_t* nav, int32_t nx, int32_t ny,
+                           const uint64_t* dist, int32_t n_goals, int64_t n, const int32_t* starts,
+                           const int32_t* slots, int32_t cap, int32_t* paths, int32_t* lengths) {
+    if (!c) return HGS_E_INVALID;
+    if (hgs_status s = check_grid(c, nx, ny)) return s;
+    if (n_goals < 1 || n_goals > 65535) return fail(c, HGS_E_INVALID, "n_goals must be 1..65535");
+    if (n < 0 || cap < 0) return fail(c, HGS_E_INVALID, "n and cap must be >= 0");
+    if (n > 0 && (!nav || !dist || !starts || !slots || !lengths || (cap > 0 && !paths)))
+        return fail(c, HGS_E_INVALID, "bad query arrays");
+    HIP_TRY(c, hipSetDevice(c->device));
+    TraceArgs a{nav, nx, ny, dist, n_goals, n, starts, slots, cap, paths, lengths};
+    launch_trace(a, (hipStream_t)stream);
     HIP_TRY(c, hipGetLastError());
     return HGS_OK;
 }

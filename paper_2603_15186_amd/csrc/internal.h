@@ -245,6 +245,41 @@ struct DiscArgs {
 };
 void launch_disc_collision(const DiscArgs& d, hipStream_t s);
 
+// shortest-path planning (nav.hip)
+struct NavArgs {
+    const uint8_t* map;              // [ny][nx], nonzero = occupied
+    double x0, y0, cell;
+    int nx, ny;
+    double radius;
+    uint8_t* nav;                    // [ny][nx]: 1 navigable, 0 not
+};
+struct DistArgs {
+    const uint8_t* nav;              // [ny][nx], nonzero = navigable
+    int nx, ny, tiles_x, tiles_y;
+    int n_goals;
+    const int32_t* goals;            // device [n_goals] cell indices
+    uint64_t* dist;                  // [n_goals][ny][nx]: a | b << 32, ~0 unreached
+    uint8_t* flags[2];               // [n_goals][tiles]: tile changed in the last round
+    uint32_t* active;                // per round of a batch: tiles that changed
+};
+struct TraceArgs {
+    const uint8_t* nav;
+    int nx, ny;
+    const uint64_t* dist;
+    int n_goals;
+    int64_t n;
+    const int32_t* starts;           // device [n] cell indices
+    const int32_t* slots;            // device [n] field index
+    int32_t cap;
+    int32_t* paths;                  // device [n][cap]
+    int32_t* lengths;                // device [n]
+};
+int dist_tile();
+void launch_navigable(const NavArgs& a, hipStream_t s);
+void launch_dist_init(const DistArgs& d, hipStream_t s);
+void launch_dist_rounds(const DistArgs& d, int round0, int n_rounds, hipStream_t s);
+void launch_trace(const TraceArgs& a, hipStream_t s);
+
 // learned-LOD network (mlp.hip)
 void launch_mlp_forward(const float* feats, uint32_t n, const float* mean, const float* stdv, const uint16_t* w,
                         float* logits, hipStream_t s);

@@ -1,0 +1,268 @@
+// Shortest-path planning on the collision map (the navigable areas of Sec.
+// III-C serve collision checks and path planning; expert trajectories come
+// from a shortest-path planner, Sec. IV):
+//
+//   * navigable map: a cell is navigable when a disc robot centred on it
+//     meets no occupied cell;
+//   * distance fields: per goal cell, the least cost of an 8-connected path
+//     (orthogonal move 1, diagonal move sqrt 2, a diagonal move only between
+//     two navigable side cells) from every cell, kept as the pair (a, b) of
+//     orthogonal and diagonal moves of such a path, which is unique since
+//     sqrt 2 is irrational.  Pairs are compared exactly in integers:
+//     a1 + b1 sqrt 2 < a2 + b2 sqrt 2 iff da < db sqrt 2 with da = a1 - a2,
+//     db = b2 - b1, decided by signs and then by da^2 against 2 db^2;
+//   * trajectories: from a start cell, repeatedly the first neighbour in the
+//     order E, W, S, N, SE, SW, NE, NW whose pair plus the move's unit equals
+//     the current pair, until the goal.
+//
+// The distance field is computed by tiled relaxation: the grid is split
+// into 32 x 32 tiles; in each round every tile whose 3 x 3 neighbourhood
+// changed in the previous round loads itself and a one-cell halo into LDS
+// and relaxes its cells to a local fixed point (each thread owns four cells
+// and takes the best of its neighbours' pairs until no thread improves),
+// then writes back what improved.  Relaxation only lowers pairs toward the
+// exact distances, so the result does not depend on the order of rounds,
+// tiles or threads; the host repeats rounds until one changes nothing.
+#include "device_util.h"
+#include "grid.h"
+#include "internal.h"
+
+namespace hgs {
+
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kT = 32;                     // tile edge (cells)
+constexpr int kH = kT + 2;                 // tile with its halo
+constexpr int kRowsPerPass = kNT / kT;     // 8 rows of a tile per thread pass
+constexpr uint64_t kUnreached = ~0ull;
+constexpr uint64_t kOrth = 1ull;           // (a, b) packed a | b << 32
+constexpr uint64_t kDiag = 1ull << 32;
+
+// E, W, S, N, SE, SW, NE, NW with x to the right and y down the rows
+__constant__ int kDX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
+__constant__ int kDY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
+
+// p < q in cost for reached pairs p, q.
+__device__ __forceinline__ bool cost_less(uint64_t p, uint64_t q) {
+    const int64_t da = (int64_t)(uint32_t)p - (int64_t)(uint32_t)q;
+    const int64_t db = (int64_t)(q >> 32) - (int64_t)(p >> 32);
+    if (da < 0 && db >= 0) return true;
+    if (da >= 0 && db <= 0) return false;
+    if (da < 0) return da * da > 2 * db * db;
+    return da * da < 2 * db * db;
+}
+
+__device__ __forceinline__ bool improves(uint64_t cand, uint64_t cur) {
+    return cur == kUnreached || cost_less(cand, cur);
+}
+
+__device__ __forceinline__ uint64_t load_relaxed(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_relaxed(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kNT) void k_navigable(NavArgs a) {
+    const int64_t N = (int64_t)a.nx * a.ny;
+    for (int64_t c = blockIdx.x * (int64_t)kNT + threadIdx.x; c < N; c += (int64_t)gridDim.x * kNT) {
+        const int i = (int)(c % a.nx), j = (int)(c / a.nx);
+        double x, y;
+        {
+#pragma clang fp contract(off)
+            x = a.x0 + ((double)i + 0.5) * a.cell;
+            y = a.y0 + ((double)j + 0.5) * a.cell;
+        }
+        a.nav[c] = disc_hits(a.map, a.x0, a.y0, a.cell, a.nx, a.ny, x, y, a.radius) ? 0 : 1;
+    }
+}
+
+// Fields start unreached except valid goals (navigable cells in the grid),
+// whose tiles are the active set of round 0.
+__global__ __launch_bounds__(kNT) void k_dist_init(DistArgs d) {
+    const int64_t N = (int64_t)d.nx * d.ny;
+    const int64_t tiles = (int64_t)d.tiles_x * d.tiles_y;
+    const int64_t total = N * d.n_goals;
+    for (int64_t k = blockIdx.x * (int64_t)kNT + threadIdx.x; k < total; k += (int64_t)gridDim.x * kNT) {
+        const int64_t g = k / N, c = k % N;
+        const int32_t goal = d.goals[g];
+        const bool ok = goal >= 0 && goal < N && d.nav[goal] != 0;
+        d.dist[k] = (ok && c == goal) ? 0ull : kUnreached;
+    }
+    for (int64_t k = blockIdx.x * (int64_t)kNT + threadIdx.x; k < tiles * d.n_goals; k += (int64_t)gridDim.x * kNT) {
+        const int64_t g = k / tiles, t = k % tiles;
+        const int32_t goal = d.goals[g];
+        const bool ok = goal >= 0 && goal < N && d.nav[goal] != 0;
+        const int64_t gt = ok ? (int64_t)((goal / d.nx) / kT) * d.tiles_x + (goal % d.nx) / kT : -1;
+        d.flags[0][k] = t == gt ? 1 : 0;
+        d.flags[1][k] = 0;
+    }
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0;
+}
+
+// One round: block (tile, goal).
+__global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int slot) {
+    __shared__ uint64_t sd[kH * kH];
+    __shared__ uint8_t sn[kH * kH];
+    __shared__ int s_act;
+    const int t = blockIdx.x, g = blockIdx.y;
+    const int tx = t % d.tiles_x, ty = t / d.tiles_x;
+    const int64_t tiles = (int64_t)d.tiles_x * d.tiles_y;
+    const uint8_t* prev = d.flags[round & 1] + g * tiles;
+    uint8_t* next = d.flags[(round + 1) & 1] + g * tiles;
+    if (threadIdx.x == 0) {
+        int act = 0;
+        for (int v = max(ty - 1, 0); v <= min(ty + 1, d.tiles_y - 1); ++v)
+            for (int u = max(tx - 1, 0); u <= min(tx + 1, d.tiles_x - 1); ++u) act |= prev[v * d.tiles_x + u];
+        s_act = act;
+    }
+    __syncthreads();
+    if (!s_act) {
+        if (threadIdx.x == 0) next[t] = 0;
+        return;
+    }
+    const int gx0 = tx * kT - 1, gy0 = ty * kT - 1;
+    uint64_t* D = d.dist + (size_t)g * d.nx * d.ny;
+    for (int k = threadIdx.x; k < kH * kH; k += kNT) {
+        const int gx = gx0 + k % kH, gy = gy0 + k / kH;
+        const bool in = gx >= 0 && gy >= 0 && gx < d.nx && gy < d.ny;
+        const size_t c = (size_t)gy * d.nx + gx;
+        sn[k] = (in && d.nav[c] != 0) ? 1 : 0;
+        sd[k] = in ? load_relaxed(D + c) : kUnreached;
+    }
+    __syncthreads();
+    int li[4];
+    bool own[4];
+    uint64_t init[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        li[k] = (threadIdx.x / kT + kRowsPerPass * k + 1) * kH + threadIdx.x % kT + 1;
+        own[k] = sn[li[k]] != 0;                 // navigable cell inside the grid
+        init[k] = sd[li[k]];
+    }
+    for (;;) {
+        bool ch = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!own[k]) continue;
+            const int q = li[k];
+            const uint64_t cur = sd[q];
+            uint64_t best = cur;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int dx = m < 4 ? (m == 0 ? 1 : m == 1 ? -1 : 0) : (m == 4 || m == 6 ? 1 : -1);
+                const int dy = m < 4 ? (m == 2 ? 1 : m == 3 ? -1 : 0) : (m < 6 ? 1 : -1);
+                const int n = q + dy * kH + dx;
+                if (!sn[n]) continue;
+                if (m >= 4 && !(sn[q + dx] && sn[q + dy * kH])) continue;
+                const uint64_t v = sd[n];
+                if (v == kUnreached) continue;
+                const uint64_t cand = v + (m < 4 ? kOrth : kDiag);
+                if (improves(cand, best)) best = cand;
+            }
+            if (best != cur) {
+                sd[q] = best;
+                ch = true;
+            }
+        }
+        if (!__syncthreads_or(ch)) break;
+    }
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (own[k] && sd[li[k]] != init[k]) {
+            const int q = li[k];
+            store_relaxed(D + (size_t)(gy0 + q / kH) * d.nx + (gx0 + q % kH), sd[q]);
+            any = true;
+        }
+    }
+    const int blk = __syncthreads_or(any);
+    if (threadIdx.x == 0) {
+        next[t] = blk ? 1 : 0;
+        if (blk) atomicAdd(d.active + slot, 1u);
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_trace(TraceArgs a) {
+    const int64_t N = (int64_t)a.nx * a.ny;
+    for (int64_t q = blockIdx.x * (int64_t)kNT + threadIdx.x; q < a.n; q += (int64_t)gridDim.x * kNT) {
+        const int32_t s = a.starts[q], slot = a.slots[q];
+        int32_t len = 0;
+        if (slot >= 0 && slot < a.n_goals && s >= 0 && s < N) {
+            const uint64_t* D = a.dist + (size_t)slot * N;
+            int64_t c = s;
+            uint64_t v = D[c];
+            if (v != kUnreached) {
+                int64_t m = 0;
+                for (;;) {
+                    if (m < a.cap) a.paths[q * a.cap + m] = (int32_t)c;
+                    ++m;
+                    if (v == 0) break;
+                    if (m > N) {                 // no shortest-path field: stop
+                        m = -1;
+                        break;
+                    }
+                    const int i = (int)(c % a.nx), j = (int)(c / a.nx);
+                    int64_t nxt = -1;
+                    uint64_t nv = 0;
+                    for (int k = 0; k < 8; ++k) {
+                        const int u = i + kDX[k], w = j + kDY[k];
+                        if (u < 0 || w < 0 || u >= a.nx || w >= a.ny) continue;
+                        const int64_t n = (int64_t)w * a.nx + u;
+                        if (!a.nav[n]) continue;
+                        if (k >= 4 && !(a.nav[(int64_t)j * a.nx + u] && a.nav[(int64_t)w * a.nx + i])) continue;
+                        const uint64_t dv = D[n];
+                        if (dv == kUnreached) continue;
+                        if (dv + (k < 4 ? kOrth : kDiag) == v) {
+                            nxt = n;
+                            nv = dv;
+                            break;
+                        }
+                    }
+                    if (nxt < 0) {
+                        m = -1;
+                        break;
+                    }
+                    c = nxt;
+                    v = nv;
+                }
+                len = (int32_t)m;
+            }
+        }
+        a.lengths[q] = len;
+    }
+}
+
+unsigned grid_for(int64_t n) {
+    const int64_t b = (n + kNT - 1) / kNT;
+    return (unsigned)(b < 1 ? 1 : (b < 4096 ? b : 4096));
+}
+
+}  // namespace
+
+int dist_tile() { return kT; }
+
+void launch_navigable(const NavArgs& a, hipStream_t s) {
+    k_navigable<<<grid_for((int64_t)a.nx * a.ny), kNT, 0, s>>>(a);
+}
+
+void launch_dist_init(const DistArgs& d, hipStream_t s) {
+    k_dist_init<<<grid_for((int64_t)d.nx * d.ny * d.n_goals), kNT, 0, s>>>(d);
+}
+
+void launch_dist_rounds(const DistArgs& d, int round0, int n_rounds, hipStream_t s) {
+    k_zero_u32<<<1, 64, 0, s>>>(d.active, n_rounds);
+    const dim3 grid((unsigned)(d.tiles_x * d.tiles_y), (unsigned)d.n_goals);
+    for (int r = 0; r < n_rounds; ++r) k_dist_round<<<grid, kNT, 0, s>>>(d, round0 + r, r);
+}
+
+void launch_trace(const TraceArgs& a, hipStream_t s) {
+    if (a.n > 0) k_trace<<<grid_for(a.n), kNT, 0, s>>>(a);
+}
+
+}  // namespace hgs

@@ -19,6 +19,7 @@
 // Gaussians that reach no plane (floor and ceiling sheets, other floors) are
 // dropped after a cheap vertical test, before the FP64 slice algebra.
 #include "device_util.h"
+#include "grid.h"
 #include "internal.h"
 
 namespace hgs {
@@ -126,34 +127,10 @@ __global__ __launch_bounds__(kNT) void k_slice(SliceArgs s) {
     }
 }
 
-// Disc robots against a map: thread per query, the cells of the disc's
-// bounding box, distance from the centre to each occupied square.
+// Disc robots against a map: thread per query.
 __global__ __launch_bounds__(kNT) void k_disc_collision(DiscArgs d) {
-    for (int64_t q = blockIdx.x * (int64_t)kNT + threadIdx.x; q < d.n; q += (int64_t)gridDim.x * kNT) {
-        const double x = d.xy[2 * q], y = d.xy[2 * q + 1];
-        const double r = d.radius, r2 = r * r;
-        const double fi0 = floor((x - r - d.x0) / d.cell), fi1 = floor((x + r - d.x0) / d.cell);
-        const double fj0 = floor((y - r - d.y0) / d.cell), fj1 = floor((y + r - d.y0) / d.cell);
-        uint8_t hit = 0;
-        if (fi1 >= 0.0 && fi0 <= (double)(d.nx - 1) && fj1 >= 0.0 && fj0 <= (double)(d.ny - 1)) {
-            const int i0 = (int)fmax(fi0, 0.0), i1 = (int)fmin(fi1, (double)(d.nx - 1));
-            const int j0 = (int)fmax(fj0, 0.0), j1 = (int)fmin(fj1, (double)(d.ny - 1));
-            for (int j = j0; j <= j1 && !hit; ++j) {
-                const double ay = d.y0 + (double)j * d.cell;
-                const double dy = fmax(fmax(ay - y, 0.0), y - (ay + d.cell));
-                for (int i = i0; i <= i1; ++i) {
-                    if (!d.map[(size_t)j * d.nx + i]) continue;
-                    const double ax = d.x0 + (double)i * d.cell;
-                    const double dx = fmax(fmax(ax - x, 0.0), x - (ax + d.cell));
-                    if (dx * dx + dy * dy <= r2) {
-                        hit = 1;
-                        break;
-                    }
-                }
-            }
-        }
-        d.out[q] = hit;
-    }
+    for (int64_t q = blockIdx.x * (int64_t)kNT + threadIdx.x; q < d.n; q += (int64_t)gridDim.x * kNT)
+        d.out[q] = disc_hits(d.map, d.x0, d.y0, d.cell, d.nx, d.ny, d.xy[2 * q], d.xy[2 * q + 1], d.radius) ? 1 : 0;
 }
 
 void zero_bytes(uint8_t* p, size_t n, hipStream_t st) {

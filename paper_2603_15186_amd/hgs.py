@@ -125,6 +125,12 @@ EXPORTS = [
     ("hgs_slice_occupancy", ctypes.c_int32, [_P, _P, ctypes.POINTER(hgs_slice_grid), _P, _P]),
     ("hgs_disc_collision", ctypes.c_int32, [_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_double, _P]),
+    ("hgs_navigable_map", ctypes.c_int32, [_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P]),
+    ("hgs_distance_fields", ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                             ctypes.POINTER(ctypes.c_int64)]),
+    ("hgs_trace_paths", ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
+                                         ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P]),
 ]
 
 N_MLP_PARAMS = 1377
@@ -430,6 +436,64 @@ class Renderer:
                                                 float(cell), int(nx), int(ny), int(n), xy.data_ptr(), float(radius),
                                                 out.data_ptr()))
         return out
+
+    # ------------------------------------------------------------ planning
+    @staticmethod
+    def _dev(t, dtype, name):
+        import torch
+        if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+        return t
+
+    def navigable_map(self, occ_map, x0, y0, cell, radius, stream=None):
+        """uint8 [ny, nx]: 1 where a disc robot of `radius` centred on the
+        cell meets no occupied cell of occ_map (device uint8 [ny, nx])."""
+        import torch
+        self._dev(occ_map, torch.uint8, "occ_map")
+        ny, nx = occ_map.shape
+        nav = torch.empty_like(occ_map)
+        self._check(self.lib.hgs_navigable_map(self.ctx, self._stream(stream), occ_map.data_ptr(), float(x0),
+                                               float(y0), float(cell), int(nx), int(ny), float(radius),
+                                               nav.data_ptr()))
+        return nav
+
+    def distance_fields(self, nav, goals, dist=None, stream=None):
+        """Distance fields to the goal cells (indices j*nx + i): (int64
+        tensor [n_goals, ny, nx] holding the uint64 pairs a | b << 32, -1
+        unreachable; relaxation rounds).  Blocks until complete."""
+        import torch
+        self._dev(nav, torch.uint8, "nav")
+        ny, nx = nav.shape
+        g = np.ascontiguousarray(np.asarray(goals, np.int32).ravel())
+        if dist is None:
+            dist = torch.empty((g.size, ny, nx), dtype=torch.int64, device=nav.device)
+        self._dev(dist, torch.int64, "dist")
+        if dist.numel() < g.size * ny * nx:
+            raise ValueError("dist is too small")
+        rounds = ctypes.c_int64()
+        self._check(self.lib.hgs_distance_fields(self.ctx, self._stream(stream), nav.data_ptr(), int(nx), int(ny),
+                                                 g.size, g.ctypes.data_as(ctypes.c_void_p), dist.data_ptr(),
+                                                 ctypes.byref(rounds)))
+        return dist, rounds.value
+
+    def trace_paths(self, nav, dist, starts, slots, cap, stream=None):
+        """Trajectories (int32 [n, cap] cell indices, int32 [n] lengths) from
+        device int32 start cells down fields dist[slots]."""
+        import torch
+        self._dev(nav, torch.uint8, "nav")
+        self._dev(dist, torch.int64, "dist")
+        self._dev(starts, torch.int32, "starts")
+        self._dev(slots, torch.int32, "slots")
+        ny, nx = nav.shape
+        n = starts.numel()
+        if slots.numel() != n:
+            raise ValueError("starts and slots differ in length")
+        paths = torch.empty((n, max(int(cap), 1)), dtype=torch.int32, device=nav.device)
+        lens = torch.empty(n, dtype=torch.int32, device=nav.device)
+        self._check(self.lib.hgs_trace_paths(self.ctx, self._stream(stream), nav.data_ptr(), int(nx), int(ny),
+                                             dist.data_ptr(), int(dist.shape[0]), int(n), starts.data_ptr(),
+                                             slots.data_ptr(), int(cap), paths.data_ptr(), lens.data_ptr()))
+        return paths[:, :cap], lens
 
     def sort_pairs(self, keys, vals, key_bits, stream=None):
         """Sort device uint32 tensors (as int32 storage) in place."""

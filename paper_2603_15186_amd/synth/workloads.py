@@ -141,3 +141,25 @@ def building30m_calibration(plan, n_per_floor=8):
         pos, yaw = trajectory(FreeSpace(plan, f), n_per_floor, seed=205 + f, height=1.2)
         cams += _cams(pos, yaw, 1920, 1080, 1300.0)
     return cams
+
+
+def nav_queries(nav, n_goals=9, per_goal=200, seed=0):
+    """Planning queries on a navigable map ([ny, nx], nonzero = navigable):
+    the paper's shape of 9 annotated goals with 200 trajectories each.
+    Goals and starts are distinct-goal uniform draws from the largest
+    4-connected navigable region (every cell of it reaches every other: a
+    diagonal move needs both side cells navigable, so 8-connected regions
+    without corner cutting are the 4-connected ones).  Returns (goals int32
+    [n_goals], starts int32 [n_goals * per_goal], slots int32: the goal
+    index of each start), cell indices j * nx + i."""
+    from scipy import ndimage
+    lab, n = ndimage.label(np.asarray(nav) != 0)
+    if n == 0:
+        raise ValueError("no navigable cell")
+    sizes = np.bincount(lab.ravel())[1:]
+    region = np.flatnonzero(lab.ravel() == 1 + int(np.argmax(sizes)))
+    rng = np.random.default_rng(seed)
+    goals = rng.choice(region, size=n_goals, replace=False).astype(np.int32)
+    starts = rng.choice(region, size=n_goals * per_goal).astype(np.int32)
+    slots = np.repeat(np.arange(n_goals, dtype=np.int32), per_goal)
+    return goals, starts, slots
