@@ -54,17 +54,24 @@ def test_random_gaussians_match_oracle(R):
     assert np.all(occ9.cpu().numpy() <= g)
 
 
-def test_floor_plan_collision_map_matches_oracle(R):
-    """The 2M-leaf plan: 15 planes from 0.1 to 1.5 m over its 20 x 15 m
-    extent at 5 cm (404 x 304 cells).  Walls and clutter occupy, the floor
-    and ceiling sheets (far from every plane) do not."""
-    scene, _, fp = W.plan2m(n_poses=2, with_plan=True)
-    R.load_scene(scene)
+@pytest.fixture(scope="module")
+def plan_oracle():
+    """The 2M-leaf plan and the oracle's planes for it: 15 planes from 0.1
+    to 1.5 m over its 20 x 15 m extent at 5 cm (404 x 304 cells)."""
+    scene, cams, fp = W.plan2m(n_poses=200, with_plan=True)
     heights = np.arange(0.1, 1.55, 0.1).astype(np.float32)
+    want = O.slice_occupancy(*_leaves(scene), -0.1, -0.1, 0.05, 404, 304, heights, rho_min=0.5)
+    return scene, cams, heights, want
+
+
+def test_floor_plan_collision_map_matches_oracle(R, plan_oracle):
+    """Walls and clutter occupy, the floor and ceiling sheets (far from
+    every plane) do not."""
+    scene, _, heights, want = plan_oracle
+    R.load_scene(scene)
     occ, m = R.slice_occupancy(-0.1, -0.1, 0.05, 404, 304, heights, rho_min=0.5)
     torch.cuda.synchronize()
     g = occ.cpu().numpy()
-    want = O.slice_occupancy(*_leaves(scene), -0.1, -0.1, 0.05, 404, 304, heights, rho_min=0.5)
     _compare(g, want)
     frac = g.max(axis=0).mean()
     print("occupied fraction", frac, "undecided", int((want == 2).sum()), flush=True)
@@ -106,19 +113,21 @@ def test_disc_collision_matches_oracle(R):
     assert far.cpu().numpy().tolist() == [0, 0]
 
 
-def test_robot_poses_against_the_plan_collision_map(R):
+def test_robot_poses_against_the_plan_collision_map(R, plan_oracle):
     """The 2M-leaf plan's union map (15 planes, 5 cm) and 20,000 random
-    positions for a 0.25 m robot: GPU = oracle on every decided query; the
+    positions for a 0.25 m robot: GPU (on its own map) = oracle (on the
+    oracle's map, which has no undecided cell) on every decided query; the
     trajectory poses of the generator (0.3 m clearance) are free."""
-    scene, cams, fp = W.plan2m(n_poses=200, with_plan=True)
+    scene, cams, heights, planes = plan_oracle
+    mo = planes.max(axis=0)
+    assert not (mo == 2).any()
     R.load_scene(scene)
-    heights = np.arange(0.1, 1.55, 0.1).astype(np.float32)
     _, m = R.slice_occupancy(-0.1, -0.1, 0.05, 404, 304, heights)
+    assert np.array_equal(m.cpu().numpy(), mo)
     rng = np.random.default_rng(10)
     xy = rng.uniform([-0.1, -0.1], [20.1, 15.1], size=(20000, 2))
     got = R.disc_collision(m, -0.1, -0.1, 0.05, torch.from_numpy(xy).cuda(), 0.25).cpu().numpy()
-    mh = m.cpu().numpy()
-    want = O.disc_collision(mh, -0.1, -0.1, 0.05, xy, 0.25)
+    want = O.disc_collision(mo.astype(np.uint8), -0.1, -0.1, 0.05, xy, 0.25)
     _compare(got, want)
     print("colliding fraction", got.mean(), flush=True)
     assert 0.05 < got.mean() < 0.95
