@@ -56,11 +56,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels instead of replaying a graph")
-    ap.add_argument("--workload", default="plan2m-lod", choices=["plan2m-lod", "plan8m", "building30m", "slice"],
+    ap.add_argument("--workload", default="plan2m-lod",
+                    choices=["plan2m-lod", "plan8m", "building30m", "slice", "nav"],
                     help="plan2m-lod (the metric's workload), plan8m (256 mixed-resolution views of the "
-                         "8M-leaf plan, threshold cuts) or building30m (64 1080p views of the 30M-leaf "
-                         "two-floor building, learned cut) or slice (GS-slice collision map of the 30M-leaf "
-                         "building); the last three are reported for reference")
+                         "8M-leaf plan, threshold cuts), building30m (64 1080p views of the 30M-leaf "
+                         "two-floor building, learned cut), slice (GS-slice collision map of the 30M-leaf "
+                         "building) or nav (expert trajectories on the building's navigable maps); the "
+                         "last four are reported for reference")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed batched learned path (for profilers): no quality evaluation, no "
                          "threshold or single-view comparison")
@@ -347,6 +349,105 @@ def run_slice(args):
     r.close()
 
 
+def run_nav(args):
+    """Expert trajectories on the 30M-leaf building: per floor the GS-slice
+    collision map (15 planes, 404 x 304 cells of 5 cm, built once,
+    untimed), then per step the navigable map of a 0.25 m disc robot,
+    distance fields to 9 goals and 200 shortest-path trajectories per goal
+    (3,600 per step over both floors); the FP64 oracle timed on the host for
+    the same step."""
+    import numpy as np
+    import torch
+    from paper_2603_15186_amd import hgs
+    from paper_2603_15186_amd.synth import workloads as W
+    t = time.perf_counter()
+    scene, _, plan = W.building30m(with_plan=True)
+    log(f"building30m: {scene.n} nodes ({time.perf_counter() - t:.1f} s)")
+    r = hgs.Renderer(0)
+    r.load_scene(scene)
+    nx, ny, cell, radius, cap = 404, 304, 0.05, 0.25, 2048
+    floors = []
+    for f in range(2):
+        _, m = r.slice_occupancy(-0.1, -0.1, cell, nx, ny, np.arange(0.1, 1.55, 0.1) + f * plan.ceiling, occ=False)
+        nav0 = r.navigable_map(m, -0.1, -0.1, cell, radius).cpu().numpy()
+        goals, starts, slots = W.nav_queries(nav0, n_goals=9, per_goal=200, seed=f)
+        floors.append((m, goals, torch.from_numpy(starts).cuda(), torch.from_numpy(slots).cuda()))
+
+    def step():
+        out = []
+        for m, goals, st, sl in floors:
+            nav = r.navigable_map(m, -0.1, -0.1, cell, radius)
+            dist, rounds = r.distance_fields(nav, goals)
+            paths, lens = r.trace_paths(nav, dist, st, sl, cap)
+            out.append((nav, dist, rounds, paths, lens))
+        return out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    n_traj = sum(int(st.numel()) for _, _, st, _ in floors)
+    lens = np.concatenate([x[4].cpu().numpy() for x in res])
+    rounds = [x[2] for x in res]
+    # stage times of one step with HIP events (eager)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    st_ms = np.zeros(3)
+    for m, goals, stt, sl in floors:
+        ev[0].record(stream)
+        nav = r.navigable_map(m, -0.1, -0.1, cell, radius)
+        ev[1].record(stream)
+        dist, _ = r.distance_fields(nav, goals)
+        ev[2].record(stream)
+        r.trace_paths(nav, dist, stt, sl, cap)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        st_ms += [ev[k].elapsed_time(ev[k + 1]) for k in range(3)]
+    log(f"nav step {ms:.3f} ms: navigable / fields / traces {st_ms.round(3).tolist()} ms; rounds {rounds}; "
+        f"path cells mean {lens.mean():.1f} max {lens.max()}")
+    cells = nx * ny
+    # algorithmic bytes of the fields: every cell's 8-byte pair written once
+    # and its navigable byte read once, per goal
+    alg = sum(len(g) for _, g, _, _ in floors) * cells * 9
+    gbs = alg / (st_ms[1] * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        maps = [(x[0].cpu().numpy(), x[1], x[2].cpu().numpy(), x[3].cpu().numpy()) for x in floors]
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            for m, goals, stt, sl in maps:
+                nav = O.navigable(m, -0.1, -0.1, cell, radius)
+                d = O.distance_fields((nav == 1).astype(np.uint8), goals)
+                O.trace_paths((nav == 1).astype(np.uint8), d, stt, sl, cap)
+            reps += 1
+            if time.perf_counter() - t0 > 3.0:
+                break
+        t_cpu = (time.perf_counter() - t0) / reps
+        cpu = {"value": n_traj / t_cpu, "unit": "trajectories/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"the whole step ({reps} repetitions, {t_cpu * 1e3:.1f} ms each)"}
+    out = {"metric": "expert trajectories/s (navigable map, distance fields, shortest paths) on the 30M-leaf "
+                     "building's collision maps",
+           "value": n_traj / (ms * 1e-3), "unit": "trajectories/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "building30m, 2 floors x 404x304 cells of 5 cm, 0.25 m robot, 9 goals x 200 "
+                                  "starts per floor", "parallelism": "single GPU"},
+           "roofline": {"kernel": "k_dist_round", "bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                        "frac": gbs / 8000.0, "traffic": None},
+           "cpu_baseline": cpu,
+           "extra": {"stage_ms_per_step": {"navigable": st_ms[0], "fields": st_ms[1], "traces": st_ms[2]},
+                     "relaxation_rounds": rounds, "path_cells_mean": float(lens.mean()),
+                     "path_cells_max": int(lens.max()), "unreachable": int((lens <= 0).sum())}}
+    print(json.dumps(out), flush=True)
+    r.close()
+
+
 def main():
     args = parse()
     if args.workload == "plan8m":
@@ -355,6 +456,8 @@ def main():
         return run_building(args)
     if args.workload == "slice":
         return run_slice(args)
+    if args.workload == "nav":
+        return run_nav(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: the "
@@ -452,13 +555,18 @@ def main():
 
     single = eval_cams[:args.single]
     px1 = single[0].width * single[0].height
-    ms_t1 = ms_tm = ms_single = float("nan")
+    ms_t1 = ms_tm = ms_single = ms_blend = float("nan")
     if not args.quick:
         # batched threshold cuts
         r.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
         ms_t1, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
         r.set_lod(hgs.HGS_LOD_THRESHOLD, tau_m)
         ms_tm, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
+        # the learned cut with level-of-detail transition blending
+        r.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
+        r.set_option(hgs.HGS_OPT_LOD_BLEND, 1)
+        ms_blend, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
+        r.set_option(hgs.HGS_OPT_LOD_BLEND, 0)
 
         # plain single-view path, tau = 1
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
@@ -488,6 +596,7 @@ def main():
     extra = {
         "batched_threshold_tau1_mpix_s": mpix(ms_t1, px_per_step),
         "batched_threshold_matched_mpix_s": mpix(ms_tm, px_per_step),
+        "batched_learned_blended_mpix_s": mpix(ms_blend, px_per_step),
         "matched_tau": tau_m, "matched_tau_loss_db": loss_m,
         "plain_single_view_tau1_mpix_s": mpix(ms_single, px1),
         "speedup_vs_plain_single_view": value / mpix(ms_single, px1),

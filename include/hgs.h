@@ -424,8 +424,10 @@ hgs_status hgs_distance_fields(hgs_ctx* ctx, void* stream, const uint8_t* nav, i
  * grid, slot out of range or start unreachable; -1: dist is not a distance
  * field); the first min(length, cap) cells go to paths[q * cap ...].
  * nav and dist as for hgs_distance_fields; starts, slots, paths, lengths:
- * device, caller-owned.  Asynchronous on `stream`.  HGS_E_INVALID on bad
- * sizes. */
+ * device, caller-owned.  The library keeps a table of each cell's step per
+ * field (n_goals * ny * nx bytes, grown on demand).  Asynchronous on
+ * `stream`.  HGS_E_INVALID on bad sizes, HGS_E_OOM if the table cannot
+ * grow. */
 hgs_status hgs_trace_paths(hgs_ctx* ctx, void* stream, const uint8_t* nav, int32_t nx, int32_t ny,
                            const uint64_t* dist, int32_t n_goals, int64_t n, const int32_t* starts,
                            const int32_t* slots, int32_t cap, int32_t* paths, int32_t* lengths);

@@ -88,7 +88,7 @@ struct hgs_ctx {
     // sort scratch for hgs_sort_pairs
     DevMem sort_k, sort_v, sort_n;
     // distance-field scratch: goals, tile flags, per-round change counts
-    DevMem nav_goals, nav_flags, nav_active;
+    DevMem nav_goals, nav_flags, nav_active, nav_steps;
     uint32_t* nav_active_host = nullptr;   // pinned
 };
 
@@ -659,7 +659,7 @@ void hgs_destroy(hgs_ctx* c) {
                      &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->bins, &c->offsets, &c->dec,
                      &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
                      &c->counters, &c->sort_k, &c->sort_v, &c->sort_n, &c->nav_goals, &c->nav_flags,
-                     &c->nav_active};
+                     &c->nav_active, &c->nav_steps};
     for (DevMem* m : all) release(*m);
     if (c->nav_active_host) (void)hipHostFree(c->nav_active_host);
     if (c->views_host) (void)hipHostFree(c->views_host);
@@ -1623,7 +1623,10 @@ hgs_status hgs_trace_paths(hgs_ctx* c, void* stream, const uint8_t* nav, int32_t
     if (n > 0 && (!nav || !dist || !starts || !slots || !lengths || (cap > 0 && !paths)))
         return fail(c, HGS_E_INVALID, "bad query arrays");
     HIP_TRY(c, hipSetDevice(c->device));
-    TraceArgs a{nav, nx, ny, dist, n_goals, n, starts, slots, cap, paths, lengths};
+    if (n > 0) {
+        if (hgs_status s = ensure(c, c->nav_steps, (size_t)n_goals * nx * ny)) return s;
+    }
+    TraceArgs a{nav, nx, ny, dist, n_goals, n, starts, slots, cap, paths, lengths, P<uint8_t>(c->nav_steps)};
     launch_trace(a, (hipStream_t)stream);
     HIP_TRY(c, hipGetLastError());
     return HGS_OK;

@@ -273,6 +273,7 @@ struct TraceArgs {
     int32_t cap;
     int32_t* paths;                  // device [n][cap]
     int32_t* lengths;                // device [n]
+    uint8_t* steps;                  // scratch [n_goals][ny][nx]: each cell's move
 };
 int dist_tile();
 void launch_navigable(const NavArgs& a, hipStream_t s);

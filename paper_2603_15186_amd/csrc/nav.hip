@@ -8,12 +8,13 @@
 //     (orthogonal move 1, diagonal move sqrt 2, a diagonal move only between
 //     two navigable side cells) from every cell, kept as the pair (a, b) of
 //     orthogonal and diagonal moves of such a path, which is unique since
-//     sqrt 2 is irrational.  Pairs are compared exactly in integers:
-//     a1 + b1 sqrt 2 < a2 + b2 sqrt 2 iff da < db sqrt 2 with da = a1 - a2,
-//     db = b2 - b1, decided by signs and then by da^2 against 2 db^2;
+//     sqrt 2 is irrational.  Pairs are ordered by their FP64 costs, which
+//     is exact for grids of up to 2^24 cells (see pair_cost);
 //   * trajectories: from a start cell, repeatedly the first neighbour in the
 //     order E, W, S, N, SE, SW, NE, NW whose pair plus the move's unit equals
-//     the current pair, until the goal.
+//     the current pair, until the goal.  That neighbour is found once per
+//     cell and field (a byte per cell), so a trajectory is a chain of byte
+//     loads.
 //
 // The distance field is computed by tiled relaxation: the grid is split
 // into 32 x 32 tiles; in each round every tile whose 3 x 3 neighbourhood
@@ -38,24 +39,11 @@ constexpr int kRowsPerPass = kNT / kT;     // 8 rows of a tile per thread pass
 constexpr uint64_t kUnreached = ~0ull;
 constexpr uint64_t kOrth = 1ull;           // (a, b) packed a | b << 32
 constexpr uint64_t kDiag = 1ull << 32;
+constexpr double kSqrt2 = 1.4142135623730951;
 
 // E, W, S, N, SE, SW, NE, NW with x to the right and y down the rows
 __constant__ int kDX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
 __constant__ int kDY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
-
-// p < q in cost for reached pairs p, q.
-__device__ __forceinline__ bool cost_less(uint64_t p, uint64_t q) {
-    const int64_t da = (int64_t)(uint32_t)p - (int64_t)(uint32_t)q;
-    const int64_t db = (int64_t)(q >> 32) - (int64_t)(p >> 32);
-    if (da < 0 && db >= 0) return true;
-    if (da >= 0 && db <= 0) return false;
-    if (da < 0) return da * da > 2 * db * db;
-    return da * da < 2 * db * db;
-}
-
-__device__ __forceinline__ bool improves(uint64_t cand, uint64_t cur) {
-    return cur == kUnreached || cost_less(cand, cur);
-}
 
 __device__ __forceinline__ uint64_t load_relaxed(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -105,9 +93,18 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
     for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0;
 }
 
+// Cost a + b sqrt 2 of a reached pair, rounded once (within 2^-28 of the
+// exact value for a + b < 2^24).  For grids of at most 2^24 cells two
+// different pairs differ in cost by at least 1 / (2 sqrt 2 |db| + 1) > 2e-8
+// (|da^2 - 2 db^2| >= 1), so comparing these costs orders pairs exactly and
+// equal pairs have equal costs.
+__device__ __forceinline__ double pair_cost(uint64_t p) {
+    return fma((double)(uint32_t)(p >> 32), kSqrt2, (double)(uint32_t)p);
+}
+
 // One round: block (tile, goal).
 __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int slot) {
-    __shared__ uint64_t sd[kH * kH];
+    __shared__ uint64_t sd[kH * kH];       // pairs (one 64-bit LDS access each)
     __shared__ uint8_t sn[kH * kH];
     __shared__ int s_act;
     const int t = blockIdx.x, g = blockIdx.y;
@@ -136,34 +133,49 @@ __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int s
         sd[k] = in ? load_relaxed(D + c) : kUnreached;
     }
     __syncthreads();
+    // own cells and their legal moves (bit m: move m of E, W, S, N, SE, SW,
+    // NE, NW leads to a navigable cell, diagonals between navigable sides)
+    constexpr int kOff[8] = {1, -1, kH, -kH, kH + 1, kH - 1, -kH + 1, -kH - 1};
     int li[4];
-    bool own[4];
+    uint32_t mv[4];
     uint64_t init[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        li[k] = (threadIdx.x / kT + kRowsPerPass * k + 1) * kH + threadIdx.x % kT + 1;
-        own[k] = sn[li[k]] != 0;                 // navigable cell inside the grid
-        init[k] = sd[li[k]];
+        const int q = (threadIdx.x / kT + kRowsPerPass * k + 1) * kH + threadIdx.x % kT + 1;
+        li[k] = q;
+        init[k] = sd[q];
+        uint32_t m = 0;
+        if (sn[q]) {
+            const bool e = sn[q + 1], w = sn[q - 1], so = sn[q + kH], no = sn[q - kH];
+            m = (e ? 1u : 0u) | (w ? 2u : 0u) | (so ? 4u : 0u) | (no ? 8u : 0u);
+            if (e && so && sn[q + kH + 1]) m |= 16u;
+            if (w && so && sn[q + kH - 1]) m |= 32u;
+            if (e && no && sn[q - kH + 1]) m |= 64u;
+            if (w && no && sn[q - kH - 1]) m |= 128u;
+        }
+        mv[k] = m;
     }
     for (;;) {
         bool ch = false;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (!own[k]) continue;
+            const uint32_t m = mv[k];
+            if (!m) continue;
             const int q = li[k];
             const uint64_t cur = sd[q];
             uint64_t best = cur;
+            double bk = cur == kUnreached ? __builtin_huge_val() : pair_cost(cur);
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int dx = m < 4 ? (m == 0 ? 1 : m == 1 ? -1 : 0) : (m == 4 || m == 6 ? 1 : -1);
-                const int dy = m < 4 ? (m == 2 ? 1 : m == 3 ? -1 : 0) : (m < 6 ? 1 : -1);
-                const int n = q + dy * kH + dx;
-                if (!sn[n]) continue;
-                if (m >= 4 && !(sn[q + dx] && sn[q + dy * kH])) continue;
-                const uint64_t v = sd[n];
+            for (int j = 0; j < 8; ++j) {
+                if (!(m & (1u << j))) continue;
+                const uint64_t v = sd[q + kOff[j]];
                 if (v == kUnreached) continue;
-                const uint64_t cand = v + (m < 4 ? kOrth : kDiag);
-                if (improves(cand, best)) best = cand;
+                const uint64_t cand = v + (j < 4 ? kOrth : kDiag);
+                const double ck = pair_cost(cand);
+                if (ck < bk) {
+                    best = cand;
+                    bk = ck;
+                }
             }
             if (best != cur) {
                 sd[q] = best;
@@ -175,8 +187,8 @@ __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int s
     bool any = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (own[k] && sd[li[k]] != init[k]) {
-            const int q = li[k];
+        const int q = li[k];
+        if (sd[q] != init[k]) {
             store_relaxed(D + (size_t)(gy0 + q / kH) * d.nx + (gx0 + q % kH), sd[q]);
             any = true;
         }
@@ -188,51 +200,61 @@ __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int s
     }
 }
 
+// Step of every cell of every field: the first move (0..7 in the order E,
+// W, S, N, SE, SW, NE, NW) to a neighbour whose pair plus the move's unit is
+// the cell's pair; kGoal at a goal, kNone when unreached or when no move
+// fits (dist is then no distance field).
+constexpr uint8_t kGoal = 0xfe, kNone = 0xff;
+
+__global__ __launch_bounds__(kNT) void k_steps(TraceArgs a) {
+    const int64_t N = (int64_t)a.nx * a.ny;
+    const int64_t total = N * a.n_goals;
+    for (int64_t k = blockIdx.x * (int64_t)kNT + threadIdx.x; k < total; k += (int64_t)gridDim.x * kNT) {
+        const int64_t c = k % N;
+        const uint64_t* D = a.dist + (k - c);
+        const uint64_t v = D[c];
+        uint8_t step = kNone;
+        if (v == 0) {
+            step = kGoal;
+        } else if (v != kUnreached && a.nav[c]) {
+            const int i = (int)(c % a.nx), j = (int)(c / a.nx);
+            for (int m = 0; m < 8; ++m) {
+                const int u = i + kDX[m], w = j + kDY[m];
+                if (u < 0 || w < 0 || u >= a.nx || w >= a.ny) continue;
+                const int64_t n = (int64_t)w * a.nx + u;
+                if (!a.nav[n]) continue;
+                if (m >= 4 && !(a.nav[(int64_t)j * a.nx + u] && a.nav[(int64_t)w * a.nx + i])) continue;
+                const uint64_t dv = D[n];
+                if (dv != kUnreached && dv + (m < 4 ? kOrth : kDiag) == v) {
+                    step = (uint8_t)m;
+                    break;
+                }
+            }
+        }
+        a.steps[k] = step;
+    }
+}
+
 __global__ __launch_bounds__(kNT) void k_trace(TraceArgs a) {
     const int64_t N = (int64_t)a.nx * a.ny;
     for (int64_t q = blockIdx.x * (int64_t)kNT + threadIdx.x; q < a.n; q += (int64_t)gridDim.x * kNT) {
         const int32_t s = a.starts[q], slot = a.slots[q];
         int32_t len = 0;
-        if (slot >= 0 && slot < a.n_goals && s >= 0 && s < N) {
-            const uint64_t* D = a.dist + (size_t)slot * N;
-            int64_t c = s;
-            uint64_t v = D[c];
-            if (v != kUnreached) {
-                int64_t m = 0;
-                for (;;) {
-                    if (m < a.cap) a.paths[q * a.cap + m] = (int32_t)c;
-                    ++m;
-                    if (v == 0) break;
-                    if (m > N) {                 // no shortest-path field: stop
-                        m = -1;
-                        break;
-                    }
-                    const int i = (int)(c % a.nx), j = (int)(c / a.nx);
-                    int64_t nxt = -1;
-                    uint64_t nv = 0;
-                    for (int k = 0; k < 8; ++k) {
-                        const int u = i + kDX[k], w = j + kDY[k];
-                        if (u < 0 || w < 0 || u >= a.nx || w >= a.ny) continue;
-                        const int64_t n = (int64_t)w * a.nx + u;
-                        if (!a.nav[n]) continue;
-                        if (k >= 4 && !(a.nav[(int64_t)j * a.nx + u] && a.nav[(int64_t)w * a.nx + i])) continue;
-                        const uint64_t dv = D[n];
-                        if (dv == kUnreached) continue;
-                        if (dv + (k < 4 ? kOrth : kDiag) == v) {
-                            nxt = n;
-                            nv = dv;
-                            break;
-                        }
-                    }
-                    if (nxt < 0) {
-                        m = -1;
-                        break;
-                    }
-                    c = nxt;
-                    v = nv;
+        if (slot >= 0 && slot < a.n_goals && s >= 0 && s < N && a.dist[(size_t)slot * N + s] != kUnreached) {
+            const uint8_t* S = a.steps + (size_t)slot * N;
+            int64_t c = s, m = 0;
+            for (;;) {
+                if (m < a.cap) a.paths[q * a.cap + m] = (int32_t)c;
+                ++m;
+                const uint8_t st = S[c];
+                if (st == kGoal) break;
+                if (st == kNone || m > N) {          // no distance field
+                    m = -1;
+                    break;
                 }
-                len = (int32_t)m;
+                c += (int64_t)kDY[st] * a.nx + kDX[st];
             }
+            len = (int32_t)m;
         }
         a.lengths[q] = len;
     }
@@ -262,7 +284,9 @@ void launch_dist_rounds(const DistArgs& d, int round0, int n_rounds, hipStream_t
 }
 
 void launch_trace(const TraceArgs& a, hipStream_t s) {
-    if (a.n > 0) k_trace<<<grid_for(a.n), kNT, 0, s>>>(a);
+    if (a.n == 0) return;
+    k_steps<<<grid_for((int64_t)a.nx * a.ny * a.n_goals), kNT, 0, s>>>(a);
+    k_trace<<<grid_for(a.n), kNT, 0, s>>>(a);
 }
 
 }  // namespace hgs

@@ -327,7 +327,8 @@ def test_plan2m_sampled_pixel_parity(R, plan_full):
     for i in (10, 150):
         cam = cams[i]
         img = _render(R, scene, [cam])[0]
-        ids = R.get_cut(0)
+        ids = O.cut(scene, cam, O.MODE_THRESHOLD, 1.0)
+        assert np.array_equal(R.get_cut(0), ids)
         px = np.concatenate([rng.integers(0, 1280, 3000), np.arange(1280), np.arange(1280)])
         py = np.concatenate([rng.integers(0, 720, 3000), np.full(1280, 360), np.full(1280, 719)])
         proj = O.project(scene, ids, cam)
