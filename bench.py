@@ -145,6 +145,30 @@ def timed_loop(r, hgs, torch, batches, outs, steps, warmup, stage_timing):
     return (t1 - t0) * 1e3 / steps, st
 
 
+def time_backward(r, hgs, torch, batches, outs, steps):
+    """ms per backward pass of a batch: each step renders a batch (untimed
+    part of the stream) and runs the backward pass with fixed random image
+    gradients; only the backward is inside the HIP events."""
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    grads = [tuple(torch.randn(t.shape, generator=gen, device="cuda") for t in o) for o in outs]
+    stream = torch.cuda.current_stream()
+    total = 0.0
+    acc = None
+    for i in range(steps + 1):
+        r.set_cameras(batches[i % len(batches)])
+        r.render(outs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        acc = r.backward(grads, out=acc)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i:                                   # the first one warms up
+            total += e0.elapsed_time(e1)
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
+    return total / steps
+
+
 def run_plan8m(args):
     """256 views (128 @ 320x240, 96 @ 640x480, 32 @ 1280x720) of the
     8M-leaf 40 x 30 m plan in one call, threshold cuts at tau 1, 2, 4."""
@@ -555,7 +579,7 @@ def main():
 
     single = eval_cams[:args.single]
     px1 = single[0].width * single[0].height
-    ms_t1 = ms_tm = ms_single = ms_blend = float("nan")
+    ms_t1 = ms_tm = ms_single = ms_blend = ms_bwd = float("nan")
     if not args.quick:
         # batched threshold cuts
         r.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
@@ -567,6 +591,9 @@ def main():
         r.set_option(hgs.HGS_OPT_LOD_BLEND, 1)
         ms_blend, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
         r.set_option(hgs.HGS_OPT_LOD_BLEND, 0)
+        # backward pass of the learned batch (random image gradients),
+        # eager launches, timed with HIP events on the stream
+        ms_bwd = time_backward(r, hgs, torch, batches, outs, args.steps)
 
         # plain single-view path, tau = 1
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
@@ -597,6 +624,7 @@ def main():
         "batched_threshold_tau1_mpix_s": mpix(ms_t1, px_per_step),
         "batched_threshold_matched_mpix_s": mpix(ms_tm, px_per_step),
         "batched_learned_blended_mpix_s": mpix(ms_blend, px_per_step),
+        "backward_ms_per_step": ms_bwd, "backward_mpix_s": mpix(ms_bwd, px_per_step),
         "matched_tau": tau_m, "matched_tau_loss_db": loss_m,
         "plain_single_view_tau1_mpix_s": mpix(ms_single, px1),
         "speedup_vs_plain_single_view": value / mpix(ms_single, px1),

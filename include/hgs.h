@@ -389,6 +389,37 @@ hgs_status hgs_slice_occupancy(hgs_ctx* ctx, void* stream, const hgs_slice_grid*
 hgs_status hgs_disc_collision(hgs_ctx* ctx, void* stream, const uint8_t* map, double x0, double y0, double cell,
                               int32_t nx, int32_t ny, int64_t n, const double* xy, double radius, uint8_t* out);
 
+/* Backward pass of the last render (the gradients scene reconstruction
+ * optimises with, NavGSim Sec. III-B).  grads[v] holds, for view v, device
+ * planar dL/dRGB [3][height][width], dL/dD [height][width] (D = the raw
+ * depth output) and dL/dalpha [height][width]; any may be NULL (zero).  The
+ * gradients of L with respect to the rendered Gaussians' parameters are
+ * ADDED to out's device arrays: means [n][3], scales [n][3], quats [n][4]
+ * (w, x, y, z, as given to hgs_load_scene, before normalisation), opacity
+ * [n], sh [n][K][3] (K = (degree + 1)^2); n = every node of the scene (only
+ * rendered ones receive gradients).  Discrete decisions (q <= 9, alpha >=
+ * 1/255, the early stop) carry no gradient, nor does an opacity-weighted
+ * alpha capped at 0.99 or a colour channel clamped to [0, 1].  Run on the
+ * render's stream after it; the render must have been one pass (no
+ * HGS_OPT_PASS_VIEWS split) without HGS_OPT_LOD_BLEND (HGS_E_STATE,
+ * HGS_E_UNSUPPORTED).  Asynchronous on `stream`; the summation order of the
+ * atomic adds is not fixed, so results vary in the last bits. */
+typedef struct {
+    const float* rgb;
+    const float* depth;
+    const float* alpha;
+} hgs_image_grad;
+
+typedef struct {
+    float* means;
+    float* scales;
+    float* quats;
+    float* opacity;
+    float* sh;
+} hgs_scene_grad;
+
+hgs_status hgs_render_backward(hgs_ctx* ctx, void* stream, const hgs_image_grad* grads, const hgs_scene_grad* out);
+
 /* Shortest-path planning on the navigable areas (NavGSim Sec. III-C: the
  * slice map serves collision checks and path planning; Sec. IV: expert
  * trajectories from a shortest-path planner between random starts and

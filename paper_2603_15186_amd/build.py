@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhgs.so")
 SOURCES = ["api.hip", "cut.hip", "project.hip", "sort.hip", "composite.hip", "mlp.hip", "imgutil.hip", "surfaces.hip",
-           "slice.hip", "nav.hip"]
+           "slice.hip", "nav.hip", "backward.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

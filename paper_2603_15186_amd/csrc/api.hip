@@ -89,6 +89,11 @@ struct hgs_ctx {
     DevMem sort_k, sort_v, sort_n;
     // distance-field scratch: goals, tile flags, per-round change counts
     DevMem nav_goals, nav_flags, nav_active, nav_steps;
+    // backward pass: per-entry gradients and per-view image gradients; the
+    // last render's final pair buffer and whether it blended levels
+    DevMem egrad, dimg;
+    int last_pair_buf = 0;
+    bool last_blend = false;
     uint32_t* nav_active_host = nullptr;   // pinned
 };
 
@@ -487,6 +492,8 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pb.max_digit_bits = c->sort_digit_bits;
     pb.hist = sa.hist;
     const int pr = launch_sort(pb, s);
+    c->last_pair_buf = pr;
+    c->last_blend = pa.blend;
 
     CompositeArgs xa{};
     xa.keys = pb.keys[pr];
@@ -659,7 +666,7 @@ void hgs_destroy(hgs_ctx* c) {
                      &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->bins, &c->offsets, &c->dec,
                      &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
                      &c->counters, &c->sort_k, &c->sort_v, &c->sort_n, &c->nav_goals, &c->nav_flags,
-                     &c->nav_active, &c->nav_steps};
+                     &c->nav_active, &c->nav_steps, &c->egrad, &c->dimg};
     for (DevMem* m : all) release(*m);
     if (c->nav_active_host) (void)hipHostFree(c->nav_active_host);
     if (c->views_host) (void)hipHostFree(c->views_host);
@@ -1628,6 +1635,53 @@ hgs_status hgs_trace_paths(hgs_ctx* c, void* stream, const uint8_t* nav, int32_t
     }
     TraceArgs a{nav, nx, ny, dist, n_goals, n, starts, slots, cap, paths, lengths, P<uint8_t>(c->nav_steps)};
     launch_trace(a, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_render_backward(hgs_ctx* c, void* stream, const hgs_image_grad* grads, const hgs_scene_grad* out) {
+    if (!c || !grads || !out) return HGS_E_INVALID;
+    if (!c->last_valid) return fail(c, HGS_E_STATE, "backward needs a completed render");
+    if (n_passes(c) != 1) return fail(c, HGS_E_STATE, "backward needs a render done in one pass");
+    if (c->last_blend) return fail(c, HGS_E_UNSUPPORTED, "backward of a blended render is not supported");
+    if (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh)
+        return fail(c, HGS_E_INVALID, "every gradient array is required");
+    const int nv = (int)c->cams.size();
+    std::vector<ImgGrad> ig((size_t)nv);
+    for (int v = 0; v < nv; ++v) ig[v] = ImgGrad{grads[v].rgb, grads[v].depth, grads[v].alpha};
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    hgs_status s;
+    if ((s = ensure(c, c->egrad, (size_t)c->cut_cap * kEntryGrad * sizeof(float))) ||
+        (s = ensure(c, c->dimg, (size_t)nv * sizeof(ImgGrad))))
+        return s;
+    HIP_TRY(c, hipMemcpyAsync(c->dimg.p, ig.data(), (size_t)nv * sizeof(ImgGrad), hipMemcpyHostToDevice, st));
+    BwdArgs b{};
+    b.vals = P<uint32_t>(c->pval[c->last_pair_buf]);
+    b.ranges = P<uint2>(c->ranges);
+    b.total_tiles = pass_tile0(c, 1) - pass_tile0(c, 0);
+    b.proj = P<Proj>(c->proj);
+    b.cut_cap = c->cut_cap;
+    b.views = P<ViewDev>(c->views);
+    b.tile_view = P<uint32_t>(c->tile_view);
+    b.dimg = P<ImgGrad>(c->dimg);
+    b.egrad = P<float>(c->egrad);
+    ProjBwdArgs p{};
+    p.cut = P<uint2>(c->cut);
+    p.cut_cap = c->cut_cap;
+    p.geo = P<float4>(c->geo);
+    p.sh = P<float>(c->sh);
+    p.n = c->n;
+    p.sh_degree = c->sh_degree;
+    p.views = P<ViewDev>(c->views);
+    p.egrad = b.egrad;
+    p.ctr = P<Counters>(c->counters);
+    p.g_means = out->means;
+    p.g_scales = out->scales;
+    p.g_quats = out->quats;
+    p.g_opacity = out->opacity;
+    p.g_sh = out->sh;
+    launch_backward(b, p, st);
     HIP_TRY(c, hipGetLastError());
     return HGS_OK;
 }

@@ -1,0 +1,411 @@
+// Backward pass of the renderer: gradients of a loss, given its gradients
+// with respect to the output images (RGB, raw depth D = sum w z, alpha =
+// 1 - T), with respect to the Gaussians' means, scales, rotations,
+// opacities and SH coefficients (the optimisation behind the paper's scene
+// reconstruction, Sec. III-B).
+//
+// Compositing (one 256-thread workgroup per 16x16 tile, a pixel per thread):
+// the tile's depth-ordered entries are staged in LDS in batches exactly as
+// the forward compositor stages them, and each pixel replays the forward
+// recurrence with the same single-precision operations to find where it
+// stopped and its final transmittance T_N.  It then walks its entries back
+// to front, recovering T before entry i as T_{i+1} / (1 - alpha_i), with
+//   dL/dalpha_i = sum_c gC_c (c_ic T_i - B_c / (1 - alpha_i))
+//               + gD (z_i T_i - B_D / (1 - alpha_i)) + gA T_N / (1 - alpha_i)
+// where B holds what lies behind entry i (T_N bg for the colour).  Through
+// alpha = o e^{-q/2} (no gradient where capped at 0.99) and q = t1^2 + t2^2,
+// t1 = p dx + r dy, t2 = s dy, each pixel yields ten numbers per entry
+// (2D mean, conic factors p r s, opacity, colour, depth); a wave sums them
+// with shuffles, the four waves of the tile add them in LDS, and one
+// global atomic add per number and tile lands them in a per-entry buffer.
+//
+// Projection (one thread per cut entry, FP64): the chain rule from the 2D
+// mean, the conic factors of Sigma' = T T^T + 0.3 I (T = J W R S), the
+// camera depth and the SH colour back to the Gaussian's parameters, added
+// atomically (a Gaussian seen in several views gathers several entries).
+#include "device_util.h"
+#include "internal.h"
+
+namespace hgs {
+
+namespace {
+
+constexpr int kNT = kTilePx;
+constexpr int kB = 256;                         // entries staged per batch
+constexpr float kNegHalfLog2e = -0.72134752044448170f;
+constexpr int kNG = 10;                         // per-entry gradient numbers
+
+struct BwdShared {
+    float u[kB], v[kB], p[kB], r[kB], s[kB], c1[kB], c2[kB], lo[kB], o[kB], z[kB], col[3][kB];
+    float acc[kNG][kB];
+    uint32_t maxlast;
+    uint32_t entry[kB];
+};
+
+__device__ __forceinline__ float wave_fsum(float x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
+__device__ __forceinline__ void stage(const BwdArgs& a, BwdShared& S, uint32_t base, uint32_t cnt, double dx0,
+                                      double dy0) {
+    const int j = threadIdx.x;
+    if (j < (int)cnt) {
+        const uint32_t e = a.vals[base + j];
+        const Proj P = a.proj[e < a.cut_cap ? e : 0u];
+        const float u = (float)(P.u - dx0), v = (float)(P.v - dy0);
+        S.u[j] = u;
+        S.v[j] = v;
+        S.p[j] = P.p;
+        S.r[j] = P.r;
+        S.s[j] = P.s;
+        S.c1[j] = -fmaf(P.p, u, P.r * v);
+        S.c2[j] = -P.s * v;
+        S.lo[j] = __log2f(P.opacity);
+        S.o[j] = P.opacity;
+        S.z[j] = P.z;
+        S.col[0][j] = P.c0;
+        S.col[1][j] = P.c1;
+        S.col[2][j] = P.c2;
+        S.entry[j] = e;
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_composite_bwd(BwdArgs a) {
+    __shared__ BwdShared S;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t view = a.tile_view[tile];
+    const ViewDev& V = a.views[view];
+    const ImgGrad G = a.dimg[view];
+    const uint32_t local = tile - V.tile_base;
+    const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int lx = threadIdx.x & (kTile - 1), ly = threadIdx.x / kTile;
+    const int px = x0 + lx, py = y0 + ly;
+    const bool inside = px < V.width && py < V.height;
+    const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
+    const double dx0 = (double)x0, dy0 = (double)y0;
+    const uint2 rg = a.ranges[tile];
+    const uint32_t n = rg.y - rg.x;
+    if (threadIdx.x == 0) S.maxlast = 0;
+
+    // 1. forward replay: where the pixel stops and its final transmittance
+    float T = 1.f;
+    bool live = inside;
+    uint32_t last = 0;
+    for (uint32_t b0 = 0; b0 < n; b0 += kB) {
+        const uint32_t cnt = min((uint32_t)kB, n - b0);
+        __syncthreads();
+        stage(a, S, rg.x + b0, cnt, dx0, dy0);
+        __syncthreads();
+        for (uint32_t i = 0; i < cnt && live; ++i) {
+            const float t1 = fmaf(S.p[i], fx, fmaf(S.r[i], fy, S.c1[i]));
+            const float t2 = fmaf(S.s[i], fy, S.c2[i]);
+            const float q = fmaf(t1, t1, t2 * t2);
+            const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, S.lo[i])));
+            const float al = (q <= 9.f && al0 >= 1.f / 255.f) ? al0 : 0.f;
+            const float Tn = T * (1.f - al);
+            if (Tn < 1e-4f) {
+                live = false;
+                last = b0 + i;
+            } else {
+                T = Tn;
+            }
+        }
+        if (__syncthreads_count(live ? 1 : 0) == 0) break;
+    }
+    if (live) last = n;
+    if (!inside) last = 0;
+    atomicMax(&S.maxlast, last);
+
+    // 2. back to front
+    const size_t plane = (size_t)V.width * V.height;
+    const size_t pix = (size_t)py * V.width + px;
+    float gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gA = 0.f;
+    if (inside) {
+        gC0 = G.rgb ? G.rgb[pix] : 0.f;
+        gC1 = G.rgb ? G.rgb[plane + pix] : 0.f;
+        gC2 = G.rgb ? G.rgb[2 * plane + pix] : 0.f;
+        gD = G.depth ? G.depth[pix] : 0.f;
+        gA = G.alpha ? G.alpha[pix] : 0.f;
+    }
+    const float TN = T;
+    float Tc = T;
+    float B0 = T * V.bg[0], B1 = T * V.bg[1], B2 = T * V.bg[2], BD = 0.f;
+    for (int k = threadIdx.x; k < kNG * kB; k += kNT) (&S.acc[0][0])[k] = 0.f;
+    __syncthreads();
+    const uint32_t maxlast = S.maxlast;
+    const int nb = (int)((maxlast + kB - 1) / kB);
+    for (int bi = nb - 1; bi >= 0; --bi) {
+        const uint32_t b0 = (uint32_t)bi * kB;
+        const uint32_t cnt = min((uint32_t)kB, n - b0);
+        stage(a, S, rg.x + b0, cnt, dx0, dy0);
+        __syncthreads();
+        for (int i = (int)cnt - 1; i >= 0; --i) {
+            float g[kNG];
+#pragma unroll
+            for (int k = 0; k < kNG; ++k) g[k] = 0.f;
+            bool has = false;
+            if (b0 + (uint32_t)i < last) {
+                const float t1 = fmaf(S.p[i], fx, fmaf(S.r[i], fy, S.c1[i]));
+                const float t2 = fmaf(S.s[i], fy, S.c2[i]);
+                const float q = fmaf(t1, t1, t2 * t2);
+                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, S.lo[i])));
+                const float al = (q <= 9.f && al0 >= 1.f / 255.f) ? al0 : 0.f;
+                if (al > 0.f) {
+                    has = true;
+                    const float om = 1.f - al, iom = 1.f / om;
+                    const float Ti = Tc * iom;
+                    const float c0 = S.col[0][i], c1 = S.col[1][i], c2 = S.col[2][i], z = S.z[i];
+                    const float w = al * Ti;
+                    const float dLda = gC0 * (c0 * Ti - B0 * iom) + gC1 * (c1 * Ti - B1 * iom) +
+                                       gC2 * (c2 * Ti - B2 * iom) + gD * (z * Ti - BD * iom) + gA * TN * iom;
+                    g[6] = gC0 * w;
+                    g[7] = gC1 * w;
+                    g[8] = gC2 * w;
+                    g[9] = gD * w;
+                    B0 = fmaf(c0, w, B0);
+                    B1 = fmaf(c1, w, B1);
+                    B2 = fmaf(c2, w, B2);
+                    BD = fmaf(z, w, BD);
+                    Tc = Ti;
+                    if (al0 < 0.99f) {
+                        const float o = S.o[i];
+                        const float gq = -0.5f * al * dLda;
+                        const float dx = fx - S.u[i], dy = fy - S.v[i];
+                        const float p = S.p[i], r = S.r[i], s = S.s[i];
+                        g[0] = gq * (-2.f * t1 * p);
+                        g[1] = gq * (-2.f * (t1 * r + t2 * s));
+                        g[2] = gq * (2.f * t1 * dx);
+                        g[3] = gq * (2.f * t1 * dy);
+                        g[4] = gq * (2.f * t2 * dy);
+                        g[5] = dLda * al / o;
+                    }
+                }
+            }
+            if (__ballot(has)) {
+#pragma unroll
+                for (int k = 0; k < kNG; ++k) {
+                    const float sum = wave_fsum(g[k]);
+                    if (lane_id() == 0 && sum != 0.f) atomicAdd(&S.acc[k][i], sum);
+                }
+            }
+        }
+        __syncthreads();
+        const int j = threadIdx.x;
+        if (j < (int)cnt) {
+            const uint32_t e = S.entry[j];
+            if (e < a.cut_cap) {
+                float* dst = a.egrad + (size_t)e * kEntryGrad;
+#pragma unroll
+                for (int k = 0; k < kNG; ++k) {
+                    const float x = S.acc[k][j];
+                    if (x != 0.f) atomicAdd(dst + k, x);
+                    S.acc[k][j] = 0.f;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_egrad(float* g, const Counters* ctr, uint32_t cap) {
+    const uint64_t n = (uint64_t)min(ctr->cut, cap) * kEntryGrad;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        g[i] = 0.f;
+}
+
+// Real SH basis (as in the projection) and its gradient with respect to the
+// direction's components, FP64.
+__device__ void sh_basis_grad(double x, double y, double z, int deg, double Y[16], double dY[16][3]) {
+    constexpr double k00 = 0.28209479177387814, k1 = 0.48860251190291992;
+    constexpr double k2a = 1.0925484305920792, k2b = 0.31539156525252005, k2c = 0.54627421529603959;
+    constexpr double k3a = 0.59004358992664352, k3b = 2.8906114426405538, k3c = 0.45704579946446572,
+                     k3d = 0.3731763325901154, k3e = 1.4453057213202769;
+    for (int k = 0; k < 16; ++k) Y[k] = dY[k][0] = dY[k][1] = dY[k][2] = 0.0;
+    Y[0] = k00;
+    if (deg >= 1) {
+        Y[1] = -k1 * y; dY[1][1] = -k1;
+        Y[2] = k1 * z; dY[2][2] = k1;
+        Y[3] = -k1 * x; dY[3][0] = -k1;
+    }
+    if (deg >= 2) {
+        Y[4] = k2a * x * y; dY[4][0] = k2a * y; dY[4][1] = k2a * x;
+        Y[5] = -k2a * y * z; dY[5][1] = -k2a * z; dY[5][2] = -k2a * y;
+        Y[6] = k2b * (3.0 * z * z - 1.0); dY[6][2] = 6.0 * k2b * z;
+        Y[7] = -k2a * x * z; dY[7][0] = -k2a * z; dY[7][2] = -k2a * x;
+        Y[8] = k2c * (x * x - y * y); dY[8][0] = 2.0 * k2c * x; dY[8][1] = -2.0 * k2c * y;
+    }
+    if (deg >= 3) {
+        Y[9] = -k3a * y * (3.0 * x * x - y * y);
+        dY[9][0] = -6.0 * k3a * x * y; dY[9][1] = -k3a * (3.0 * x * x - 3.0 * y * y);
+        Y[10] = k3b * x * y * z;
+        dY[10][0] = k3b * y * z; dY[10][1] = k3b * x * z; dY[10][2] = k3b * x * y;
+        Y[11] = -k3c * y * (5.0 * z * z - 1.0);
+        dY[11][1] = -k3c * (5.0 * z * z - 1.0); dY[11][2] = -10.0 * k3c * y * z;
+        Y[12] = k3d * z * (5.0 * z * z - 3.0);
+        dY[12][2] = k3d * (15.0 * z * z - 3.0);
+        Y[13] = -k3c * x * (5.0 * z * z - 1.0);
+        dY[13][0] = -k3c * (5.0 * z * z - 1.0); dY[13][2] = -10.0 * k3c * x * z;
+        Y[14] = k3e * z * (x * x - y * y);
+        dY[14][0] = 2.0 * k3e * x * z; dY[14][1] = -2.0 * k3e * y * z; dY[14][2] = k3e * (x * x - y * y);
+        Y[15] = -k3a * x * (x * x - 3.0 * y * y);
+        dY[15][0] = -k3a * (3.0 * x * x - 3.0 * y * y); dY[15][1] = 6.0 * k3a * x * y;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+    const uint32_t m = min(a.ctr->cut, a.cut_cap);
+    const int K = (a.sh_degree + 1) * (a.sh_degree + 1);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        const float* eg = a.egrad + (size_t)i * kEntryGrad;
+        double gin[kNG];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kNG; ++k) {
+            gin[k] = eg[k];
+            any = any || gin[k] != 0.0;
+        }
+        if (!any) continue;
+        const uint2 e = a.cut[i];
+        const ViewDev& V = a.views[e.y];
+        const int64_t g = e.x;
+        const float4 g0 = a.geo[3 * g], g1 = a.geo[3 * g + 1], g2 = a.geo[3 * g + 2];
+        const double dx = (double)g0.x - V.o[0], dy = (double)g0.y - V.o[1], dz = (double)g0.z - V.o[2];
+        const double tx = (V.R[0] * dx + V.R[1] * dy) + V.R[2] * dz;
+        const double ty = (V.R[3] * dx + V.R[4] * dy) + V.R[5] * dz;
+        const double tz = (V.R[6] * dx + V.R[7] * dy) + V.R[8] * dz;
+        if (!(tz > V.znear)) continue;
+        const double iz = 1.0 / tz;
+        const double xr0 = tx * iz, yr0 = ty * iz;
+        const bool xcl = xr0 < V.xlo || xr0 > V.xhi, ycl = yr0 < V.ylo || yr0 > V.yhi;
+        const double xr = fmin(fmax(xr0, V.xlo), V.xhi), yr = fmin(fmax(yr0, V.ylo), V.yhi);
+        double M[2][3];
+        for (int j = 0; j < 3; ++j) {
+            M[0][j] = V.fx * iz * (V.R[j] - xr * V.R[6 + j]);
+            M[1][j] = V.fy * iz * (V.R[3 + j] - yr * V.R[6 + j]);
+        }
+        double qw = g1.x, qx = g1.y, qy = g1.z, qz = g1.w;
+        const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+        qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+        const double R[3][3] = {{1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy)},
+                                {2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx)},
+                                {2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)}};
+        const double sc[3] = {g2.x, g2.y, g2.z};
+        double MR[2][3], Tm[2][3];
+        for (int r = 0; r < 2; ++r)
+            for (int k = 0; k < 3; ++k) {
+                MR[r][k] = M[r][0] * R[0][k] + M[r][1] * R[1][k] + M[r][2] * R[2][k];
+                Tm[r][k] = MR[r][k] * sc[k];
+            }
+        const double s00 = Tm[0][0] * Tm[0][0] + Tm[0][1] * Tm[0][1] + Tm[0][2] * Tm[0][2] + 0.3;
+        const double s01 = Tm[0][0] * Tm[1][0] + Tm[0][1] * Tm[1][1] + Tm[0][2] * Tm[1][2];
+        const double s11 = Tm[1][0] * Tm[1][0] + Tm[1][1] * Tm[1][1] + Tm[1][2] * Tm[1][2] + 0.3;
+        const double det = s00 * s11 - s01 * s01;
+        if (!(det > 0.0)) continue;
+        // conic factors p = sqrt(s11 / det), r = -s01 / sqrt(det s11),
+        // s = 1 / sqrt(s11) and their derivatives
+        const double gp = gin[2], gr = gin[3], gs = gin[4];
+        const double pp = sqrt(s11 / det), idet2 = 1.0 / (det * det);
+        const double mm = det * s11, im12 = 1.0 / sqrt(mm), im32 = im12 / mm;
+        const double h00 = gp * (0.5 / pp) * (-s11 * s11 * idet2) + gr * 0.5 * s01 * im32 * s11 * s11;
+        const double h01 = gp * (0.5 / pp) * (2.0 * s11 * s01 * idet2) + gr * (-im12 - s01 * s01 * s11 * im32);
+        const double h11 = gp * (0.5 / pp) * (-s01 * s01 * idet2) + gr * 0.5 * s01 * im32 * (det + s00 * s11) +
+                           gs * (-0.5 / (s11 * sqrt(s11)));
+        // Sigma' = T T^T: dL/dT
+        double gT[2][3];
+        for (int k = 0; k < 3; ++k) {
+            gT[0][k] = 2.0 * h00 * Tm[0][k] + h01 * Tm[1][k];
+            gT[1][k] = 2.0 * h11 * Tm[1][k] + h01 * Tm[0][k];
+        }
+        double gsc[3], gMR[2][3];
+        for (int k = 0; k < 3; ++k) {
+            gsc[k] = gT[0][k] * MR[0][k] + gT[1][k] * MR[1][k];
+            gMR[0][k] = gT[0][k] * sc[k];
+            gMR[1][k] = gT[1][k] * sc[k];
+        }
+        double gR[3][3], gM[2][3];
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k) gR[j][k] = M[0][j] * gMR[0][k] + M[1][j] * gMR[1][k];
+        for (int r = 0; r < 2; ++r)
+            for (int j = 0; j < 3; ++j) gM[r][j] = gMR[r][0] * R[j][0] + gMR[r][1] * R[j][1] + gMR[r][2] * R[j][2];
+        // quaternion: dL/d(normalised q), then through the normalisation
+        const double gw = 2.0 * (-qz * gR[0][1] + qy * gR[0][2] + qz * gR[1][0] - qx * gR[1][2] - qy * gR[2][0] +
+                                 qx * gR[2][1]);
+        const double gx = 2.0 * (qy * gR[0][1] + qz * gR[0][2] + qy * gR[1][0] - 2.0 * qx * gR[1][1] - qw * gR[1][2] +
+                                 qz * gR[2][0] + qw * gR[2][1] - 2.0 * qx * gR[2][2]);
+        const double gy = 2.0 * (-2.0 * qy * gR[0][0] + qx * gR[0][1] + qw * gR[0][2] + qx * gR[1][0] +
+                                 qz * gR[1][2] - qw * gR[2][0] + qz * gR[2][1] - 2.0 * qy * gR[2][2]);
+        const double gz = 2.0 * (-2.0 * qz * gR[0][0] - qw * gR[0][1] + qx * gR[0][2] + qw * gR[1][0] -
+                                 2.0 * qz * gR[1][1] + qy * gR[1][2] + qx * gR[2][0] + qy * gR[2][1]);
+        const double qd = qw * gw + qx * gx + qy * gy + qz * gz;
+        // camera-space mean: 2D mean, depth, Jacobian
+        const double gu = gin[0], gv = gin[1];
+        double gt0 = gu * V.fx * iz, gt1 = gv * V.fy * iz;
+        double gt2 = -(gu * V.fx * tx + gv * V.fy * ty) * iz * iz + gin[9];
+        const double iz2 = iz * iz;
+        for (int j = 0; j < 3; ++j) {
+            const double w0 = V.R[j], w1 = V.R[3 + j], w2 = V.R[6 + j];
+            if (!xcl) {
+                gt0 += gM[0][j] * (-V.fx * iz2 * w2);
+                gt2 += gM[0][j] * (-V.fx * iz2 * w0 + 2.0 * V.fx * xr * iz2 * w2);
+            } else {
+                gt2 += gM[0][j] * (-V.fx * iz2 * (w0 - xr * w2));
+            }
+            if (!ycl) {
+                gt1 += gM[1][j] * (-V.fy * iz2 * w2);
+                gt2 += gM[1][j] * (-V.fy * iz2 * w1 + 2.0 * V.fy * yr * iz2 * w2);
+            } else {
+                gt2 += gM[1][j] * (-V.fy * iz2 * (w1 - yr * w2));
+            }
+        }
+        double gmu[3];
+        for (int j = 0; j < 3; ++j) gmu[j] = V.R[j] * gt0 + V.R[3 + j] * gt1 + V.R[6 + j] * gt2;
+        // colour: SH coefficients and the view direction
+        const double dn = sqrt(dx * dx + dy * dy + dz * dz), idn = 1.0 / dn;
+        const double ux = dx * idn, uy = dy * idn, uz = dz * idn;
+        double Y[16], dY[16][3];
+        sh_basis_grad(ux, uy, uz, a.sh_degree, Y, dY);
+        double gdir[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; ++c) {
+            const double gc = gin[6 + c];
+            if (gc == 0.0) continue;
+            double val = 0.5;
+            for (int k = 0; k < K; ++k) val += (double)a.sh[(int64_t)(k * 3 + c) * a.n + g] * Y[k];
+            if (val < 0.0 || val > 1.0) continue;                       // clamped colour
+            for (int k = 0; k < K; ++k) {
+                const double f = a.sh[(int64_t)(k * 3 + c) * a.n + g];
+                atomicAdd(a.g_sh + ((size_t)g * K + k) * 3 + c, (float)(gc * Y[k]));
+                gdir[0] += gc * f * dY[k][0];
+                gdir[1] += gc * f * dY[k][1];
+                gdir[2] += gc * f * dY[k][2];
+            }
+        }
+        const double dd = ux * gdir[0] + uy * gdir[1] + uz * gdir[2];
+        gmu[0] += (gdir[0] - ux * dd) * idn;
+        gmu[1] += (gdir[1] - uy * dd) * idn;
+        gmu[2] += (gdir[2] - uz * dd) * idn;
+        atomicAdd(a.g_means + 3 * g, (float)gmu[0]);
+        atomicAdd(a.g_means + 3 * g + 1, (float)gmu[1]);
+        atomicAdd(a.g_means + 3 * g + 2, (float)gmu[2]);
+        atomicAdd(a.g_scales + 3 * g, (float)gsc[0]);
+        atomicAdd(a.g_scales + 3 * g + 1, (float)gsc[1]);
+        atomicAdd(a.g_scales + 3 * g + 2, (float)gsc[2]);
+        atomicAdd(a.g_quats + 4 * g, (float)((gw - qw * qd) / qn));
+        atomicAdd(a.g_quats + 4 * g + 1, (float)((gx - qx * qd) / qn));
+        atomicAdd(a.g_quats + 4 * g + 2, (float)((gy - qy * qd) / qn));
+        atomicAdd(a.g_quats + 4 * g + 3, (float)((gz - qz * qd) / qn));
+        atomicAdd(a.g_opacity + g, (float)gin[5]);
+    }
+}
+
+}  // namespace
+
+void launch_backward(const BwdArgs& b, const ProjBwdArgs& p, hipStream_t s) {
+    k_zero_egrad<<<1024, 256, 0, s>>>(b.egrad, p.ctr, b.cut_cap);
+    if (b.total_tiles) k_composite_bwd<<<b.total_tiles, kNT, 0, s>>>(b);
+    k_project_bwd<<<2048, 256, 0, s>>>(p);
+}
+
+}  // namespace hgs

@@ -245,6 +245,42 @@ struct DiscArgs {
 };
 void launch_disc_collision(const DiscArgs& d, hipStream_t s);
 
+// backward pass (backward.hip)
+constexpr int kEntryGrad = 12;       // floats per cut entry: u, v, p, r, s, opacity, rgb, depth, 2 spare
+struct ImgGrad {
+    const float* rgb;                // [3][h][w] or null
+    const float* depth;              // [h][w] or null
+    const float* alpha;              // [h][w] or null
+};
+struct BwdArgs {
+    const uint32_t* vals;            // tile-sorted entry indices
+    const uint2* ranges;
+    uint32_t total_tiles;
+    const Proj* proj;
+    uint32_t cut_cap;
+    const ViewDev* views;
+    const uint32_t* tile_view;
+    const ImgGrad* dimg;             // per view of the pass
+    float* egrad;                    // [cut_cap][kEntryGrad]
+};
+struct ProjBwdArgs {
+    const uint2* cut;
+    uint32_t cut_cap;
+    const float4* geo;
+    const float* sh;                 // planar
+    int64_t n;
+    int sh_degree;
+    const ViewDev* views;
+    const float* egrad;
+    const Counters* ctr;
+    float* g_means;                  // [n][3]
+    float* g_scales;                 // [n][3]
+    float* g_quats;                  // [n][4]
+    float* g_opacity;                // [n]
+    float* g_sh;                     // [n][K][3]
+};
+void launch_backward(const BwdArgs& b, const ProjBwdArgs& p, hipStream_t s);
+
 // shortest-path planning (nav.hip)
 struct NavArgs {
     const uint8_t* map;              // [ny][nx], nonzero = occupied

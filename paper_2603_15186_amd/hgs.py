@@ -85,6 +85,15 @@ class hgs_slice_grid(ctypes.Structure):
                 ("heights", ctypes.c_void_p)]
 
 
+class hgs_image_grad(ctypes.Structure):
+    _fields_ = [("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("alpha", ctypes.c_void_p)]
+
+
+class hgs_scene_grad(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
 class hgs_plan(ctypes.Structure):
     _fields_ = [("batch_depth", ctypes.c_int32), ("persistent", ctypes.c_int32), ("sort_digit_bits", ctypes.c_int32),
                 ("from_cache", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
@@ -125,6 +134,7 @@ EXPORTS = [
     ("hgs_slice_occupancy", ctypes.c_int32, [_P, _P, ctypes.POINTER(hgs_slice_grid), _P, _P]),
     ("hgs_disc_collision", ctypes.c_int32, [_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_double, _P]),
+    ("hgs_render_backward", ctypes.c_int32, [_P, _P, _P, _P]),
     ("hgs_navigable_map", ctypes.c_int32, [_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P]),
     ("hgs_distance_fields", ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
@@ -244,6 +254,8 @@ class Renderer:
         return st
 
     def load_scene(self, scene):
+        self.scene_n = int(scene.n)
+        self.scene_sh_degree = int(scene.sh_degree)
         keep = []
         g = make_gaussians(scene, keep)
         h = make_hierarchy(scene, keep)
@@ -435,6 +447,42 @@ class Renderer:
         self._check(self.lib.hgs_disc_collision(self.ctx, self._stream(stream), occ_map.data_ptr(), float(x0), float(y0),
                                                 float(cell), int(nx), int(ny), int(n), xy.data_ptr(), float(radius),
                                                 out.data_ptr()))
+        return out
+
+    def backward(self, grads, out=None, stream=None):
+        """Backward pass of the last render.  grads: per view (d_rgb [3,H,W],
+        d_depth [H,W], d_alpha [H,W]) float32 CUDA tensors or None.  Returns
+        the dict of parameter gradients (means, scales, quats, opacity, sh
+        [n, K, 3]), added to `out` when given, else to zeros."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        n, K = self.scene_n, (self.scene_sh_degree + 1) ** 2
+        if out is None:
+            out = {"means": torch.zeros((n, 3), dtype=torch.float32, device=dev),
+                   "scales": torch.zeros((n, 3), dtype=torch.float32, device=dev),
+                   "quats": torch.zeros((n, 4), dtype=torch.float32, device=dev),
+                   "opacity": torch.zeros(n, dtype=torch.float32, device=dev),
+                   "sh": torch.zeros((n, K, 3), dtype=torch.float32, device=dev)}
+        if len(grads) != len(self.cams):
+            raise ValueError("one gradient triple per view")
+        arr = (hgs_image_grad * len(grads))()
+        for i, g in enumerate(grads):
+            c = self.cams[i]
+            shapes = ((3, c.height, c.width), (c.height, c.width), (c.height, c.width))
+            ptrs = []
+            for t, shp in zip(g, shapes):
+                if t is None:
+                    ptrs.append(None)
+                    continue
+                if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == shp):
+                    raise ValueError(f"image gradients of view {i} must be contiguous float32 CUDA tensors {shp}")
+                ptrs.append(t.data_ptr())
+            arr[i] = hgs_image_grad(*ptrs)
+        for k, t in out.items():
+            self._dev(t, torch.float32, k)
+        sg = hgs_scene_grad(out["means"].data_ptr(), out["scales"].data_ptr(), out["quats"].data_ptr(),
+                            out["opacity"].data_ptr(), out["sh"].data_ptr())
+        self._check(self.lib.hgs_render_backward(self.ctx, self._stream(stream), arr, ctypes.byref(sg)))
         return out
 
     # ------------------------------------------------------------ planning
