@@ -91,7 +91,7 @@ struct hgs_ctx {
     DevMem nav_goals, nav_flags, nav_active, nav_steps;
     // backward pass: per-entry gradients and per-view image gradients; the
     // last render's final pair buffer and whether it blended levels
-    DevMem egrad, dimg;
+    DevMem egrad, dimg, brec;
     int last_pair_buf = 0;
     bool last_blend = false;
     uint32_t* nav_active_host = nullptr;   // pinned
@@ -666,7 +666,7 @@ void hgs_destroy(hgs_ctx* c) {
                      &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->bins, &c->offsets, &c->dec,
                      &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
                      &c->counters, &c->sort_k, &c->sort_v, &c->sort_n, &c->nav_goals, &c->nav_flags,
-                     &c->nav_active, &c->nav_steps, &c->egrad, &c->dimg};
+                     &c->nav_active, &c->nav_steps, &c->egrad, &c->dimg, &c->brec};
     for (DevMem* m : all) release(*m);
     if (c->nav_active_host) (void)hipHostFree(c->nav_active_host);
     if (c->views_host) (void)hipHostFree(c->views_host);
@@ -1653,6 +1653,7 @@ hgs_status hgs_render_backward(hgs_ctx* c, void* stream, const hgs_image_grad* g
     hipStream_t st = (hipStream_t)stream;
     hgs_status s;
     if ((s = ensure(c, c->egrad, (size_t)c->cut_cap * kEntryGrad * sizeof(float))) ||
+        (s = ensure(c, c->brec, (size_t)c->cut_cap * kEntryRec * sizeof(float))) ||
         (s = ensure(c, c->dimg, (size_t)nv * sizeof(ImgGrad))))
         return s;
     HIP_TRY(c, hipMemcpyAsync(c->dimg.p, ig.data(), (size_t)nv * sizeof(ImgGrad), hipMemcpyHostToDevice, st));
@@ -1676,12 +1677,28 @@ hgs_status hgs_render_backward(hgs_ctx* c, void* stream, const hgs_image_grad* g
     p.views = P<ViewDev>(c->views);
     p.egrad = b.egrad;
     p.ctr = P<Counters>(c->counters);
-    p.g_means = out->means;
-    p.g_scales = out->scales;
-    p.g_quats = out->quats;
-    p.g_opacity = out->opacity;
-    p.g_sh = out->sh;
-    launch_backward(b, p, st);
+    p.rec = P<float>(c->brec);
+    SortArgs sa{};
+    sa.keys[0] = P<uint32_t>(c->dkey[0]);
+    sa.keys[1] = P<uint32_t>(c->dkey[1]);
+    sa.vals[0] = P<uint32_t>(c->dval[0]);
+    sa.vals[1] = P<uint32_t>(c->dval[1]);
+    sa.count = &p.ctr->cut;
+    sa.cap = c->cut_cap;
+    sa.key_bits = bits_for((uint32_t)c->n);
+    sa.max_digit_bits = c->sort_digit_bits;
+    sa.hist = P<uint32_t>(c->hist);
+    GatherArgs ga{};
+    ga.cap = c->cut_cap;
+    ga.ctr = p.ctr;
+    ga.rec = p.rec;
+    ga.sh_degree = c->sh_degree;
+    ga.g_means = out->means;
+    ga.g_scales = out->scales;
+    ga.g_quats = out->quats;
+    ga.g_opacity = out->opacity;
+    ga.g_sh = out->sh;
+    launch_backward(b, p, sa, ga, st);
     HIP_TRY(c, hipGetLastError());
     return HGS_OK;
 }

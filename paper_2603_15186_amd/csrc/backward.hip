@@ -4,25 +4,33 @@
 // opacities and SH coefficients (the optimisation behind the paper's scene
 // reconstruction, Sec. III-B).
 //
-// Compositing (one 256-thread workgroup per 16x16 tile, a pixel per thread):
-// the tile's depth-ordered entries are staged in LDS in batches exactly as
-// the forward compositor stages them, and each pixel replays the forward
-// recurrence with the same single-precision operations to find where it
-// stopped and its final transmittance T_N.  It then walks its entries back
-// to front, recovering T before entry i as T_{i+1} / (1 - alpha_i), with
+// Compositing (one 256-thread workgroup per 16x16 tile, a pixel per thread,
+// a 16-lane quarter-wave per 4x4 block as in the forward compositor): the
+// tile's depth-ordered entries are staged in LDS in batches and listed per
+// block exactly as the forward stages and lists them, and each pixel replays
+// the forward recurrence over its block's list with the same
+// single-precision operations to find where it stopped and its final
+// transmittance T_N.  It then walks the lists back to front, recovering T
+// before entry i as T_{i+1} / (1 - alpha_i), with
 //   dL/dalpha_i = sum_c gC_c (c_ic T_i - B_c / (1 - alpha_i))
 //               + gD (z_i T_i - B_D / (1 - alpha_i)) + gA T_N / (1 - alpha_i)
 // where B holds what lies behind entry i (T_N bg for the colour).  Through
 // alpha = o e^{-q/2} (no gradient where capped at 0.99) and q = t1^2 + t2^2,
 // t1 = p dx + r dy, t2 = s dy, each pixel yields ten numbers per entry
-// (2D mean, conic factors p r s, opacity, colour, depth); a wave sums them
-// with shuffles, the four waves of the tile add them in LDS, and one
-// global atomic add per number and tile lands them in a per-entry buffer.
+// (2D mean, conic factors p r s, opacity, colour, depth); the 16 lanes of a
+// block, which walk the same entry, sum them with shuffles, blocks add them
+// in LDS, and one global atomic add per number and tile lands them in a
+// per-entry buffer.
 //
 // Projection (one thread per cut entry, FP64): the chain rule from the 2D
 // mean, the conic factors of Sigma' = T T^T + 0.3 I (T = J W R S), the
-// camera depth and the SH colour back to the Gaussian's parameters, added
-// atomically (a Gaussian seen in several views gathers several entries).
+// camera depth and the colour back to the Gaussian's mean, scale, rotation
+// and opacity, written as a per-entry record with the entry's colour
+// gradient and view direction.  The entries are then sorted by Gaussian
+// (the radix sort of the binning) and one thread per Gaussian sums its
+// records, forming the SH coefficients' gradients sum g_c Y_k(d) on the
+// way: no scattered atomics on the parameter arrays.
+#include "blocks.h"
 #include "device_util.h"
 #include "internal.h"
 
@@ -36,40 +44,87 @@ constexpr float kNegHalfLog2e = -0.72134752044448170f;
 constexpr int kNG = 10;                         // per-entry gradient numbers
 
 struct BwdShared {
-    float u[kB], v[kB], p[kB], r[kB], s[kB], c1[kB], c2[kB], lo[kB], o[kB], z[kB], col[3][kB];
-    float acc[kNG][kB];
-    uint32_t maxlast;
+    StageA a[kB + 1];
+    StageB b[kB + 1];
+    StageC c[kB + 1];
+    float2 uv[kB];                              // tile-relative 2D means
+    float io[kB];                               // inverse opacities
     uint32_t entry[kB];
+    float acc[kNG][kB];
+    alignas(16) uint16_t idx[kBlocks * kB];
+    uint32_t wc[(kNT / kWave) * kBlocks];
+    uint32_t n[kBlocks];
+    uint32_t maxlast;
 };
 
-__device__ __forceinline__ float wave_fsum(float x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
-    return x;
-}
-
-__device__ __forceinline__ void stage(const BwdArgs& a, BwdShared& S, uint32_t base, uint32_t cnt, double dx0,
-                                      double dy0) {
+// Stage entries [base, base + cnt) of the tile's list and build each 4x4
+// block's list of staged offsets (16 B units, depth order), padded with the
+// empty record up to a multiple of four of its wave's longest list.
+// Returns this lane's block list length and writes the padded length.
+__device__ __forceinline__ uint32_t stage_lists(const BwdArgs& a, BwdShared& S, uint32_t base, uint32_t cnt,
+                                                double dx0, double dy0, int w, int lane, int gid, int k,
+                                                uint32_t* n_step_out) {
+    uint32_t m = 0;
     const int j = threadIdx.x;
     if (j < (int)cnt) {
         const uint32_t e = a.vals[base + j];
         const Proj P = a.proj[e < a.cut_cap ? e : 0u];
         const float u = (float)(P.u - dx0), v = (float)(P.v - dy0);
-        S.u[j] = u;
-        S.v[j] = v;
-        S.p[j] = P.p;
-        S.r[j] = P.r;
-        S.s[j] = P.s;
-        S.c1[j] = -fmaf(P.p, u, P.r * v);
-        S.c2[j] = -P.s * v;
-        S.lo[j] = __log2f(P.opacity);
-        S.o[j] = P.opacity;
-        S.z[j] = P.z;
-        S.col[0][j] = P.c0;
-        S.col[1][j] = P.c1;
-        S.col[2][j] = P.c2;
+        S.a[j] = StageA{P.p, P.r, -fmaf(P.p, u, P.r * v), P.s};
+        S.b[j] = StageB{-P.s * v, __log2f(P.opacity), P.z, P.c0};
+        S.c[j] = StageC{P.c1, P.c2};
+        S.uv[j] = make_float2(u, v);
+        S.io[j] = 1.f / P.opacity;
         S.entry[j] = e;
+        m = block_mask(u, v, P.p, P.r, P.s);
     }
+    uint32_t pre[kBlocks];
+#pragma unroll
+    for (int b = 0; b < kBlocks; ++b) {
+        const uint64_t bal = __ballot((m >> b) & 1u);
+        pre[b] = (uint32_t)__popcll(bal & lanemask_lt());
+        if (lane == 0) S.wc[w * kBlocks + b] = (uint32_t)__popcll(bal);
+    }
+    __syncthreads();
+    if (threadIdx.x < kBlocks) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int ww = 0; ww < kNT / kWave; ++ww) {
+            const uint32_t c = S.wc[ww * kBlocks + threadIdx.x];
+            S.wc[ww * kBlocks + threadIdx.x] = t;
+            t += c;
+        }
+        S.n[threadIdx.x] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < kBlocks; ++b)
+        if ((m >> b) & 1u) S.idx[b * kB + S.wc[w * kBlocks + b] + pre[b]] = (uint16_t)(j * 16);
+    const uint32_t n_mine = S.n[gid];
+    const uint32_t n_wave = __builtin_amdgcn_readfirstlane(
+        max(max(S.n[w * 4], S.n[w * 4 + 1]), max(S.n[w * 4 + 2], S.n[w * 4 + 3])));
+    const uint32_t n_step = (n_wave + 3u) & ~3u;
+    uint16_t* list = S.idx + gid * kB;
+    for (uint32_t p = n_mine + (uint32_t)k; p < n_step; p += 16) list[p] = (uint16_t)(kB * 16);
+    __syncthreads();
+    *n_step_out = n_step;
+    return n_mine;
+}
+
+// Sum over the 16 lanes of a DPP row, left in every lane of the row: lane
+// pairs (quad_perm 1,0,3,2), quad pairs (2,3,0,1), then the mirrored half
+// row and the mirrored row.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float group_sum(float x) {
+    x += dpp_f<0xb1>(x);      // quad_perm [1, 0, 3, 2]
+    x += dpp_f<0x4e>(x);      // quad_perm [2, 3, 0, 1]
+    x += dpp_f<0x141>(x);     // row_half_mirror
+    x += dpp_f<0x140>(x);     // row_mirror
+    return x;
 }
 
 __global__ __launch_bounds__(kNT) void k_composite_bwd(BwdArgs a) {
@@ -81,45 +136,56 @@ __global__ __launch_bounds__(kNT) void k_composite_bwd(BwdArgs a) {
     const uint32_t local = tile - V.tile_base;
     const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
     const int x0 = tx * kTile, y0 = ty * kTile;
-    const int lx = threadIdx.x & (kTile - 1), ly = threadIdx.x / kTile;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int g = lane >> 4, k = lane & 15;
+    const int gid = w * 4 + g;
+    const int lx = g * 4 + (k & 3), ly = w * 4 + (k >> 2);
     const int px = x0 + lx, py = y0 + ly;
     const bool inside = px < V.width && py < V.height;
     const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
     const double dx0 = (double)x0, dy0 = (double)y0;
     const uint2 rg = a.ranges[tile];
     const uint32_t n = rg.y - rg.x;
-    if (threadIdx.x == 0) S.maxlast = 0;
+    if (threadIdx.x == 0) {
+        S.a[kB] = StageA{0.f, 0.f, 0.f, 0.f};
+        S.b[kB] = StageB{0.f, -__builtin_inff(), 0.f, 0.f};
+        S.c[kB] = StageC{0.f, 0.f};
+        S.maxlast = 0;
+    }
 
-    // 1. forward replay: where the pixel stops and its final transmittance
+    // 1. forward replay over the block lists (the forward's operations):
+    // where the pixel stops and its final transmittance
     float T = 1.f;
     bool live = inside;
-    uint32_t last = 0;
+    uint32_t last = n;
     for (uint32_t b0 = 0; b0 < n; b0 += kB) {
         const uint32_t cnt = min((uint32_t)kB, n - b0);
-        __syncthreads();
-        stage(a, S, rg.x + b0, cnt, dx0, dy0);
-        __syncthreads();
-        for (uint32_t i = 0; i < cnt && live; ++i) {
-            const float t1 = fmaf(S.p[i], fx, fmaf(S.r[i], fy, S.c1[i]));
-            const float t2 = fmaf(S.s[i], fy, S.c2[i]);
+        uint32_t n_step;
+        stage_lists(a, S, rg.x + b0, cnt, dx0, dy0, w, lane, gid, k, &n_step);
+        const uint16_t* list = S.idx + gid * kB;
+        for (uint32_t p = 0; p < n_step; ++p) {
+            const uint32_t off = list[p];
+            const StageA A = *reinterpret_cast<const StageA*>(reinterpret_cast<const char*>(S.a) + off);
+            const StageB B = *reinterpret_cast<const StageB*>(reinterpret_cast<const char*>(S.b) + off);
+            const float t1 = fmaf(A.p, fx, fmaf(A.r, fy, A.c1));
+            const float t2 = fmaf(A.s, fy, B.c2);
             const float q = fmaf(t1, t1, t2 * t2);
-            const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, S.lo[i])));
-            const float al = (q <= 9.f && al0 >= 1.f / 255.f) ? al0 : 0.f;
+            const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, B.lo)));
+            const float al = (q <= kQMax && live && al0 >= 1.f / 255.f) ? al0 : 0.f;
             const float Tn = T * (1.f - al);
-            if (Tn < 1e-4f) {
+            if (live && Tn < 1e-4f) {
                 live = false;
-                last = b0 + i;
-            } else {
-                T = Tn;
+                last = b0 + off / 16;
             }
+            T = live ? Tn : T;
+            if ((p & 3u) == 3u && __ballot(live) == 0) break;
         }
         if (__syncthreads_count(live ? 1 : 0) == 0) break;
     }
-    if (live) last = n;
     if (!inside) last = 0;
     atomicMax(&S.maxlast, last);
 
-    // 2. back to front
+    // 2. back to front over the same lists
     const size_t plane = (size_t)V.width * V.height;
     const size_t pix = (size_t)py * V.width + px;
     float gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gA = 0.f;
@@ -133,76 +199,84 @@ __global__ __launch_bounds__(kNT) void k_composite_bwd(BwdArgs a) {
     const float TN = T;
     float Tc = T;
     float B0 = T * V.bg[0], B1 = T * V.bg[1], B2 = T * V.bg[2], BD = 0.f;
-    for (int k = threadIdx.x; k < kNG * kB; k += kNT) (&S.acc[0][0])[k] = 0.f;
+    for (int i = threadIdx.x; i < kNG * kB; i += kNT) (&S.acc[0][0])[i] = 0.f;
     __syncthreads();
     const uint32_t maxlast = S.maxlast;
     const int nb = (int)((maxlast + kB - 1) / kB);
     for (int bi = nb - 1; bi >= 0; --bi) {
         const uint32_t b0 = (uint32_t)bi * kB;
         const uint32_t cnt = min((uint32_t)kB, n - b0);
-        stage(a, S, rg.x + b0, cnt, dx0, dy0);
-        __syncthreads();
-        for (int i = (int)cnt - 1; i >= 0; --i) {
-            float g[kNG];
+        uint32_t n_step;
+        stage_lists(a, S, rg.x + b0, cnt, dx0, dy0, w, lane, gid, k, &n_step);
+        const uint16_t* list = S.idx + gid * kB;
+        for (int p = (int)n_step - 1; p >= 0; --p) {
+            const uint32_t off = list[p];
+            const uint32_t j = off / 16;
+            float gr[kNG];
 #pragma unroll
-            for (int k = 0; k < kNG; ++k) g[k] = 0.f;
+            for (int t = 0; t < kNG; ++t) gr[t] = 0.f;
             bool has = false;
-            if (b0 + (uint32_t)i < last) {
-                const float t1 = fmaf(S.p[i], fx, fmaf(S.r[i], fy, S.c1[i]));
-                const float t2 = fmaf(S.s[i], fy, S.c2[i]);
+            if (j < kB && b0 + j < last) {
+                const StageA A = S.a[j];
+                const StageB B = S.b[j];
+                const StageC C = S.c[j];
+                const float t1 = fmaf(A.p, fx, fmaf(A.r, fy, A.c1));
+                const float t2 = fmaf(A.s, fy, B.c2);
                 const float q = fmaf(t1, t1, t2 * t2);
-                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, S.lo[i])));
-                const float al = (q <= 9.f && al0 >= 1.f / 255.f) ? al0 : 0.f;
+                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, B.lo)));
+                const float al = (q <= kQMax && al0 >= 1.f / 255.f) ? al0 : 0.f;
                 if (al > 0.f) {
                     has = true;
-                    const float om = 1.f - al, iom = 1.f / om;
+                    const float iom = __builtin_amdgcn_rcpf(1.f - al);
                     const float Ti = Tc * iom;
-                    const float c0 = S.col[0][i], c1 = S.col[1][i], c2 = S.col[2][i], z = S.z[i];
-                    const float w = al * Ti;
+                    const float c0 = B.col0, c1 = C.col1, c2 = C.col2, z = B.z;
+                    const float wgt = al * Ti;
                     const float dLda = gC0 * (c0 * Ti - B0 * iom) + gC1 * (c1 * Ti - B1 * iom) +
                                        gC2 * (c2 * Ti - B2 * iom) + gD * (z * Ti - BD * iom) + gA * TN * iom;
-                    g[6] = gC0 * w;
-                    g[7] = gC1 * w;
-                    g[8] = gC2 * w;
-                    g[9] = gD * w;
-                    B0 = fmaf(c0, w, B0);
-                    B1 = fmaf(c1, w, B1);
-                    B2 = fmaf(c2, w, B2);
-                    BD = fmaf(z, w, BD);
+                    gr[6] = gC0 * wgt;
+                    gr[7] = gC1 * wgt;
+                    gr[8] = gC2 * wgt;
+                    gr[9] = gD * wgt;
+                    B0 = fmaf(c0, wgt, B0);
+                    B1 = fmaf(c1, wgt, B1);
+                    B2 = fmaf(c2, wgt, B2);
+                    BD = fmaf(z, wgt, BD);
                     Tc = Ti;
                     if (al0 < 0.99f) {
-                        const float o = S.o[i];
                         const float gq = -0.5f * al * dLda;
-                        const float dx = fx - S.u[i], dy = fy - S.v[i];
-                        const float p = S.p[i], r = S.r[i], s = S.s[i];
-                        g[0] = gq * (-2.f * t1 * p);
-                        g[1] = gq * (-2.f * (t1 * r + t2 * s));
-                        g[2] = gq * (2.f * t1 * dx);
-                        g[3] = gq * (2.f * t1 * dy);
-                        g[4] = gq * (2.f * t2 * dy);
-                        g[5] = dLda * al / o;
+                        const float2 uv = S.uv[j];
+                        const float dx = fx - uv.x, dy = fy - uv.y;
+                        gr[0] = gq * (-2.f * t1 * A.p);
+                        gr[1] = gq * (-2.f * (t1 * A.r + t2 * A.s));
+                        gr[2] = gq * (2.f * t1 * dx);
+                        gr[3] = gq * (2.f * t1 * dy);
+                        gr[4] = gq * (2.f * t2 * dy);
+                        gr[5] = dLda * al * S.io[j];
                     }
                 }
             }
-            if (__ballot(has)) {
+            // the 16 lanes of a block share the entry: sum them when any
+            // contributes (a block-uniform branch)
+            const uint32_t gbits = (uint32_t)(__ballot(has) >> (16 * g)) & 0xffffu;
+            if (gbits) {
 #pragma unroll
-                for (int k = 0; k < kNG; ++k) {
-                    const float sum = wave_fsum(g[k]);
-                    if (lane_id() == 0 && sum != 0.f) atomicAdd(&S.acc[k][i], sum);
+                for (int t = 0; t < kNG; ++t) {
+                    const float sum = group_sum(gr[t]);
+                    if (k == 0 && sum != 0.f) atomicAdd(&S.acc[t][j], sum);
                 }
             }
         }
         __syncthreads();
-        const int j = threadIdx.x;
-        if (j < (int)cnt) {
-            const uint32_t e = S.entry[j];
+        const int jj = threadIdx.x;
+        if (jj < (int)cnt) {
+            const uint32_t e = S.entry[jj];
             if (e < a.cut_cap) {
                 float* dst = a.egrad + (size_t)e * kEntryGrad;
 #pragma unroll
-                for (int k = 0; k < kNG; ++k) {
-                    const float x = S.acc[k][j];
-                    if (x != 0.f) atomicAdd(dst + k, x);
-                    S.acc[k][j] = 0.f;
+                for (int t = 0; t < kNG; ++t) {
+                    const float x = S.acc[t][jj];
+                    if (x != 0.f) atomicAdd(dst + t, x);
+                    S.acc[t][jj] = 0.f;
                 }
             }
         }
@@ -218,7 +292,9 @@ __global__ void k_zero_egrad(float* g, const Counters* ctr, uint32_t cap) {
 
 // Real SH basis (as in the projection) and its gradient with respect to the
 // direction's components, FP64.
-__device__ void sh_basis_grad(double x, double y, double z, int deg, double Y[16], double dY[16][3]) {
+template <int DEG>
+__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, double Y[16], double dY[16][3]) {
+    constexpr int deg = DEG;
     constexpr double k00 = 0.28209479177387814, k1 = 0.48860251190291992;
     constexpr double k2a = 1.0925484305920792, k2b = 0.31539156525252005, k2c = 0.54627421529603959;
     constexpr double k3a = 0.59004358992664352, k3b = 2.8906114426405538, k3c = 0.45704579946446572,
@@ -255,9 +331,10 @@ __device__ void sh_basis_grad(double x, double y, double z, int deg, double Y[16
     }
 }
 
+template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     const uint32_t m = min(a.ctr->cut, a.cut_cap);
-    const int K = (a.sh_degree + 1) * (a.sh_degree + 1);
+    constexpr int K = (DEG + 1) * (DEG + 1);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         const float* eg = a.egrad + (size_t)i * kEntryGrad;
         double gin[kNG];
@@ -267,6 +344,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
             gin[k] = eg[k];
             any = any || gin[k] != 0.0;
         }
+        float4* rec0 = reinterpret_cast<float4*>(a.rec + (size_t)i * kEntryRec);
+        for (int t = 0; t < kEntryRec / 4; ++t) rec0[t] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (!any) continue;
         const uint2 e = a.cut[i];
         const ViewDev& V = a.views[e.y];
@@ -366,46 +445,122 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
         const double dn = sqrt(dx * dx + dy * dy + dz * dz), idn = 1.0 / dn;
         const double ux = dx * idn, uy = dy * idn, uz = dz * idn;
         double Y[16], dY[16][3];
-        sh_basis_grad(ux, uy, uz, a.sh_degree, Y, dY);
+        sh_basis_grad<DEG>(ux, uy, uz, Y, dY);
         double gdir[3] = {0.0, 0.0, 0.0};
+        double gcm[3] = {0.0, 0.0, 0.0};                              // colour gradient, 0 where clamped
         for (int c = 0; c < 3; ++c) {
             const double gc = gin[6 + c];
             if (gc == 0.0) continue;
-            double val = 0.5;
-            for (int k = 0; k < K; ++k) val += (double)a.sh[(int64_t)(k * 3 + c) * a.n + g] * Y[k];
-            if (val < 0.0 || val > 1.0) continue;                       // clamped colour
+            double val = 0.5, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
             for (int k = 0; k < K; ++k) {
                 const double f = a.sh[(int64_t)(k * 3 + c) * a.n + g];
-                atomicAdd(a.g_sh + ((size_t)g * K + k) * 3 + c, (float)(gc * Y[k]));
-                gdir[0] += gc * f * dY[k][0];
-                gdir[1] += gc * f * dY[k][1];
-                gdir[2] += gc * f * dY[k][2];
+                val += f * Y[k];
+                d0 += f * dY[k][0];
+                d1 += f * dY[k][1];
+                d2 += f * dY[k][2];
             }
+            if (val < 0.0 || val > 1.0) continue;                       // clamped colour
+            gcm[c] = gc;
+            gdir[0] += gc * d0;
+            gdir[1] += gc * d1;
+            gdir[2] += gc * d2;
         }
         const double dd = ux * gdir[0] + uy * gdir[1] + uz * gdir[2];
         gmu[0] += (gdir[0] - ux * dd) * idn;
         gmu[1] += (gdir[1] - uy * dd) * idn;
         gmu[2] += (gdir[2] - uz * dd) * idn;
-        atomicAdd(a.g_means + 3 * g, (float)gmu[0]);
-        atomicAdd(a.g_means + 3 * g + 1, (float)gmu[1]);
-        atomicAdd(a.g_means + 3 * g + 2, (float)gmu[2]);
-        atomicAdd(a.g_scales + 3 * g, (float)gsc[0]);
-        atomicAdd(a.g_scales + 3 * g + 1, (float)gsc[1]);
-        atomicAdd(a.g_scales + 3 * g + 2, (float)gsc[2]);
-        atomicAdd(a.g_quats + 4 * g, (float)((gw - qw * qd) / qn));
-        atomicAdd(a.g_quats + 4 * g + 1, (float)((gx - qx * qd) / qn));
-        atomicAdd(a.g_quats + 4 * g + 2, (float)((gy - qy * qd) / qn));
-        atomicAdd(a.g_quats + 4 * g + 3, (float)((gz - qz * qd) / qn));
-        atomicAdd(a.g_opacity + g, (float)gin[5]);
+        float4* rec = reinterpret_cast<float4*>(a.rec + (size_t)i * kEntryRec);
+        rec[0] = make_float4((float)gmu[0], (float)gmu[1], (float)gmu[2], (float)gsc[0]);
+        rec[1] = make_float4((float)gsc[1], (float)gsc[2], (float)((gw - qw * qd) / qn), (float)((gx - qx * qd) / qn));
+        rec[2] = make_float4((float)((gy - qy * qd) / qn), (float)((gz - qz * qd) / qn), (float)gin[5], (float)gcm[0]);
+        rec[3] = make_float4((float)gcm[1], (float)gcm[2], (float)ux, (float)uy);
+        rec[4] = make_float4((float)uz, 0.f, 0.f, 0.f);
+    }
+}
+
+// Entry records ordered by Gaussian: thread p starts a run when its key
+// differs from the previous one and sums the run's records; the SH
+// coefficients' gradients are sum_entries g_c Y_k(d_entry).  One thread per
+// Gaussian, so the outputs are updated without atomics.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_gather_bwd(GatherArgs a) {
+    const uint32_t m = min(a.ctr->cut, a.cap);
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
+        const uint32_t key = a.keys[p];
+        if (p > 0 && a.keys[p - 1] == key) continue;
+        float acc[11];
+#pragma unroll
+        for (int t = 0; t < 11; ++t) acc[t] = 0.f;
+        float sh[3 * K];
+#pragma unroll
+        for (int t = 0; t < 3 * K; ++t) sh[t] = 0.f;
+        bool any = false;
+        for (uint32_t q = p; q < m && a.keys[q] == key; ++q) {
+            const float4* rec = reinterpret_cast<const float4*>(a.rec + (size_t)a.vals[q] * kEntryRec);
+            const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3], r4 = rec[4];
+            const float v[11] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z};
+#pragma unroll
+            for (int t = 0; t < 11; ++t) {
+                acc[t] += v[t];
+                any = any || v[t] != 0.f;
+            }
+            const float gc[3] = {r2.w, r3.x, r3.y};
+            if (gc[0] != 0.f || gc[1] != 0.f || gc[2] != 0.f) {
+                any = true;
+                double Y[16], dY[16][3];
+                sh_basis_grad<DEG>(r3.z, r3.w, r4.x, Y, dY);
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) sh[k * 3 + c] += (float)(gc[c] * Y[k]);
+            }
+        }
+        if (!any) continue;
+        const size_t g = key;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) a.g_means[3 * g + t] += acc[t];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) a.g_scales[3 * g + t] += acc[3 + t];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a.g_quats[4 * g + t] += acc[6 + t];
+        a.g_opacity[g] += acc[10];
+#pragma unroll
+        for (int t = 0; t < 3 * K; ++t) a.g_sh[g * 3 * K + t] += sh[t];
+    }
+}
+
+__global__ void k_entry_keys(const uint2* cut, const Counters* ctr, uint32_t cap, uint32_t* keys, uint32_t* vals) {
+    const uint32_t m = min(ctr->cut, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        keys[i] = cut[i].x;
+        vals[i] = i;
     }
 }
 
 }  // namespace
 
-void launch_backward(const BwdArgs& b, const ProjBwdArgs& p, hipStream_t s) {
+void launch_backward(const BwdArgs& b, const ProjBwdArgs& p, SortArgs sa, GatherArgs ga, hipStream_t s) {
     k_zero_egrad<<<1024, 256, 0, s>>>(b.egrad, p.ctr, b.cut_cap);
     if (b.total_tiles) k_composite_bwd<<<b.total_tiles, kNT, 0, s>>>(b);
-    k_project_bwd<<<2048, 256, 0, s>>>(p);
+    switch (p.sh_degree) {
+        case 0: k_project_bwd<0><<<2048, 256, 0, s>>>(p); break;
+        case 1: k_project_bwd<1><<<2048, 256, 0, s>>>(p); break;
+        case 2: k_project_bwd<2><<<2048, 256, 0, s>>>(p); break;
+        default: k_project_bwd<3><<<2048, 256, 0, s>>>(p); break;
+    }
+    // order the entries by Gaussian and sum each Gaussian's records
+    k_entry_keys<<<2048, 256, 0, s>>>(p.cut, p.ctr, p.cut_cap, sa.keys[0], sa.vals[0]);
+    const int r = launch_sort(sa, s);
+    ga.keys = sa.keys[r];
+    ga.vals = sa.vals[r];
+    switch (ga.sh_degree) {
+        case 0: k_gather_bwd<0><<<2048, 256, 0, s>>>(ga); break;
+        case 1: k_gather_bwd<1><<<2048, 256, 0, s>>>(ga); break;
+        case 2: k_gather_bwd<2><<<2048, 256, 0, s>>>(ga); break;
+        default: k_gather_bwd<3><<<2048, 256, 0, s>>>(ga); break;
+    }
 }
 
 }  // namespace hgs

@@ -273,13 +273,23 @@ struct ProjBwdArgs {
     const ViewDev* views;
     const float* egrad;
     const Counters* ctr;
+    float* rec;                      // [cut_cap][kEntryRec]: per-entry parameter gradients
+};
+constexpr int kEntryRec = 20;        // mean 3, scale 3, quaternion 4, opacity, colour 3, direction 3, pad
+struct GatherArgs {
+    const uint32_t* keys;            // Gaussian ids of the entries, ascending
+    const uint32_t* vals;            // entry indices
+    uint32_t cap;
+    const Counters* ctr;
+    const float* rec;
+    int sh_degree;
     float* g_means;                  // [n][3]
     float* g_scales;                 // [n][3]
     float* g_quats;                  // [n][4]
     float* g_opacity;                // [n]
     float* g_sh;                     // [n][K][3]
 };
-void launch_backward(const BwdArgs& b, const ProjBwdArgs& p, hipStream_t s);
+void launch_backward(const BwdArgs& b, const ProjBwdArgs& p, SortArgs sa, GatherArgs ga, hipStream_t s);
 
 // shortest-path planning (nav.hip)
 struct NavArgs {
