@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--quick", action="store_true",
                     help="only the timed batched learned path (for profilers): no quality evaluation, no "
                          "threshold or single-view comparison")
+    ap.add_argument("--with-backward", action="store_true",
+                    help="with --quick: also time the backward pass of the learned batch")
     return ap.parse_args()
 
 
@@ -113,8 +115,11 @@ def traffic_entry(kernel):
             e[k.strip()] = v.strip()
     if e.get("kernel") != kernel:
         return None
-    src = os.path.join(ROOT, "paper_2603_15186_amd", "csrc", e["source"])
-    if hashlib.sha1(open(src, "rb").read()).hexdigest() != e.get("source_sha1"):
+    h = hashlib.sha1()
+    for name in e["source"].split():
+        with open(os.path.join(ROOT, "paper_2603_15186_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != e.get("source_sha1"):
         return None
     return int(e["bytes_per_launch"])
 
@@ -577,6 +582,9 @@ def main():
     n = st["timed_renders"]
     stage = {k: st["ms_" + k] / n for k in ("cut", "project", "sort", "composite")}
 
+    if args.quick and args.with_backward:
+        ms_bwd_q = time_backward(r, hgs, torch, batches, outs, args.steps)
+        log(f"backward: {ms_bwd_q:.3f} ms per batch")
     single = eval_cams[:args.single]
     px1 = single[0].width * single[0].height
     ms_t1 = ms_tm = ms_single = ms_blend = ms_bwd = float("nan")
