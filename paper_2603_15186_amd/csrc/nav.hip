@@ -19,9 +19,8 @@
 // The distance field is computed by tiled relaxation: the grid is split
 // into 32 x 32 tiles; in each round every tile whose 3 x 3 neighbourhood
 // changed in the previous round loads itself and a one-cell halo into LDS
-// and relaxes its cells to a local fixed point (each thread owns four cells
-// and takes the best of its neighbours' pairs until no thread improves),
-// then writes back what improved.  Relaxation only lowers pairs toward the
+// and relaxes its cells to a local fixed point by directional sweeps (see
+// k_dist_round), then writes back what improved.  Relaxation only lowers pairs toward the
 // exact distances, so the result does not depend on the order of rounds,
 // tiles or threads; the host repeats rounds until one changes nothing.
 #include "device_util.h"
@@ -35,7 +34,6 @@ namespace {
 constexpr int kNT = 256;
 constexpr int kT = 32;                     // tile edge (cells)
 constexpr int kH = kT + 2;                 // tile with its halo
-constexpr int kRowsPerPass = kNT / kT;     // 8 rows of a tile per thread pass
 constexpr uint64_t kUnreached = ~0ull;
 constexpr uint64_t kOrth = 1ull;           // (a, b) packed a | b << 32
 constexpr uint64_t kDiag = 1ull << 32;
@@ -102,99 +100,151 @@ __device__ __forceinline__ double pair_cost(uint64_t p) {
     return fma((double)(uint32_t)(p >> 32), kSqrt2, (double)(uint32_t)p);
 }
 
-// One round: block (tile, goal).
+// One round: block (tile, group of kGW goals), one wave per goal.  The
+// tile's navigability and each interior cell's legal moves are shared by
+// the goals; each wave loads its goal's tile and halo into LDS and relaxes
+// it to a local fixed point by directional sweeps: in the x phase lanes
+// 0-31 sweep the 32 rows eastward and lanes 32-63 westward, each step
+// relaxing a column's cells from the column behind (orthogonal and both
+// diagonals), so a value crosses the tile in one sweep; the y phase does
+// the same for the columns southward and northward.  Lanes of one wave run
+// in step, so a cell is written by at most one lane per step and every
+// write is a minimum over values read at that step: relaxation stays
+// monotone.  The wave stops when a full x and y phase changes nothing.
+constexpr int kGW = kNT / kWave;           // goals per workgroup
+
+struct DistShared {
+    uint64_t d[kGW][kH * kH];              // pairs, one 64-bit LDS access each
+    uint8_t nav[kH * kH];
+    uint8_t mv[kH * kH];                   // legal moves of interior cells
+};
+
+// Relax cell q from the three cells behind it (offsets o0 orthogonal, o1
+// and o2 diagonal, move bits b0..b2 of q's mask m).
+__device__ __forceinline__ bool relax3(uint64_t* sd, int q, uint32_t m, int o0, int b0, int o1, int b1, int o2,
+                                       int b2) {
+    const uint64_t cur = sd[q];
+    uint64_t best = cur;
+    double bk = cur == kUnreached ? __builtin_huge_val() : pair_cost(cur);
+    if (m & (1u << b0)) {
+        const uint64_t v = sd[q + o0];
+        if (v != kUnreached) {
+            const uint64_t c = v + kOrth;
+            const double ck = pair_cost(c);
+            if (ck < bk) { best = c; bk = ck; }
+        }
+    }
+    if (m & (1u << b1)) {
+        const uint64_t v = sd[q + o1];
+        if (v != kUnreached) {
+            const uint64_t c = v + kDiag;
+            const double ck = pair_cost(c);
+            if (ck < bk) { best = c; bk = ck; }
+        }
+    }
+    if (m & (1u << b2)) {
+        const uint64_t v = sd[q + o2];
+        if (v != kUnreached) {
+            const uint64_t c = v + kDiag;
+            const double ck = pair_cost(c);
+            if (ck < bk) { best = c; bk = ck; }
+        }
+    }
+    if (best != cur) {
+        sd[q] = best;
+        return true;
+    }
+    return false;
+}
+
 __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int slot) {
-    __shared__ uint64_t sd[kH * kH];       // pairs (one 64-bit LDS access each)
-    __shared__ uint8_t sn[kH * kH];
-    __shared__ int s_act;
-    const int t = blockIdx.x, g = blockIdx.y;
+    __shared__ DistShared S;
+    const int t = blockIdx.x;
     const int tx = t % d.tiles_x, ty = t / d.tiles_x;
     const int64_t tiles = (int64_t)d.tiles_x * d.tiles_y;
-    const uint8_t* prev = d.flags[round & 1] + g * tiles;
-    uint8_t* next = d.flags[(round + 1) & 1] + g * tiles;
-    if (threadIdx.x == 0) {
-        int act = 0;
-        for (int v = max(ty - 1, 0); v <= min(ty + 1, d.tiles_y - 1); ++v)
-            for (int u = max(tx - 1, 0); u <= min(tx + 1, d.tiles_x - 1); ++u) act |= prev[v * d.tiles_x + u];
-        s_act = act;
-    }
-    __syncthreads();
-    if (!s_act) {
-        if (threadIdx.x == 0) next[t] = 0;
-        return;
-    }
     const int gx0 = tx * kT - 1, gy0 = ty * kT - 1;
-    uint64_t* D = d.dist + (size_t)g * d.nx * d.ny;
     for (int k = threadIdx.x; k < kH * kH; k += kNT) {
         const int gx = gx0 + k % kH, gy = gy0 + k / kH;
         const bool in = gx >= 0 && gy >= 0 && gx < d.nx && gy < d.ny;
-        const size_t c = (size_t)gy * d.nx + gx;
-        sn[k] = (in && d.nav[c] != 0) ? 1 : 0;
-        sd[k] = in ? load_relaxed(D + c) : kUnreached;
+        S.nav[k] = (in && d.nav[(size_t)gy * d.nx + gx] != 0) ? 1 : 0;
     }
     __syncthreads();
-    // own cells and their legal moves (bit m: move m of E, W, S, N, SE, SW,
-    // NE, NW leads to a navigable cell, diagonals between navigable sides)
-    constexpr int kOff[8] = {1, -1, kH, -kH, kH + 1, kH - 1, -kH + 1, -kH - 1};
-    int li[4];
-    uint32_t mv[4];
-    uint64_t init[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int q = (threadIdx.x / kT + kRowsPerPass * k + 1) * kH + threadIdx.x % kT + 1;
-        li[k] = q;
-        init[k] = sd[q];
+    // bit m: move m of E, W, S, N, SE, SW, NE, NW leads to a navigable
+    // cell (diagonals between navigable side cells)
+    for (int k = threadIdx.x; k < kH * kH; k += kNT) {
+        const int lx = k % kH, ly = k / kH;
         uint32_t m = 0;
-        if (sn[q]) {
-            const bool e = sn[q + 1], w = sn[q - 1], so = sn[q + kH], no = sn[q - kH];
+        if (lx >= 1 && lx <= kT && ly >= 1 && ly <= kT && S.nav[k]) {
+            const bool e = S.nav[k + 1], w = S.nav[k - 1], so = S.nav[k + kH], no = S.nav[k - kH];
             m = (e ? 1u : 0u) | (w ? 2u : 0u) | (so ? 4u : 0u) | (no ? 8u : 0u);
-            if (e && so && sn[q + kH + 1]) m |= 16u;
-            if (w && so && sn[q + kH - 1]) m |= 32u;
-            if (e && no && sn[q - kH + 1]) m |= 64u;
-            if (w && no && sn[q - kH - 1]) m |= 128u;
+            if (e && so && S.nav[k + kH + 1]) m |= 16u;
+            if (w && so && S.nav[k + kH - 1]) m |= 32u;
+            if (e && no && S.nav[k - kH + 1]) m |= 64u;
+            if (w && no && S.nav[k - kH - 1]) m |= 128u;
         }
-        mv[k] = m;
+        S.mv[k] = (uint8_t)m;
     }
+    __syncthreads();
+    // from here each wave works alone on its goal
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int g = blockIdx.y * kGW + w;
+    if (g >= d.n_goals) return;
+    const uint8_t* prev = d.flags[round & 1] + g * tiles;
+    uint8_t* next = d.flags[(round + 1) & 1] + g * tiles;
+    int act = 0;
+    for (int v = max(ty - 1, 0); v <= min(ty + 1, d.tiles_y - 1); ++v)
+        for (int u = max(tx - 1, 0); u <= min(tx + 1, d.tiles_x - 1); ++u) act |= prev[v * d.tiles_x + u];
+    if (!act) {
+        if (lane == 0) next[t] = 0;
+        return;
+    }
+    uint64_t* D = d.dist + (size_t)g * d.nx * d.ny;
+    uint64_t* sd = S.d[w];
+    for (int k = lane; k < kH * kH; k += kWave) {
+        const int gx = gx0 + k % kH, gy = gy0 + k / kH;
+        const bool in = gx >= 0 && gy >= 0 && gx < d.nx && gy < d.ny;
+        sd[k] = in ? load_relaxed(D + (size_t)gy * d.nx + gx) : kUnreached;
+    }
+    // lanes 0-31 sweep east / south, lanes 32-63 west / north; li is the
+    // lane's row (x phase) or column (y phase), 1..32
+    const int fwd = lane < 32 ? 1 : -1, li = (lane & 31) + 1;
+    const int x0 = fwd > 0 ? 1 : kT;
+    const int xo0 = -fwd, xo1 = -kH - fwd, xo2 = kH - fwd;           // W, NW, SW (east) or E, NE, SE
+    const int xb0 = fwd > 0 ? 1 : 0, xb1 = fwd > 0 ? 7 : 6, xb2 = fwd > 0 ? 5 : 4;
+    const int yo0 = -fwd * kH, yo1 = -fwd * kH - 1, yo2 = -fwd * kH + 1;  // N, NW, NE (south) or S, SW, SE
+    const int yb0 = fwd > 0 ? 3 : 2, yb1 = fwd > 0 ? 7 : 5, yb2 = fwd > 0 ? 6 : 4;
+    bool any = false;
     for (;;) {
         bool ch = false;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t m = mv[k];
-            if (!m) continue;
-            const int q = li[k];
-            const uint64_t cur = sd[q];
-            uint64_t best = cur;
-            double bk = cur == kUnreached ? __builtin_huge_val() : pair_cost(cur);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (!(m & (1u << j))) continue;
-                const uint64_t v = sd[q + kOff[j]];
-                if (v == kUnreached) continue;
-                const uint64_t cand = v + (j < 4 ? kOrth : kDiag);
-                const double ck = pair_cost(cand);
-                if (ck < bk) {
-                    best = cand;
-                    bk = ck;
-                }
-            }
-            if (best != cur) {
-                sd[q] = best;
-                ch = true;
+        for (int st = 0; st < kT; ++st) {
+            const int q = li * kH + x0 + fwd * st;
+            const uint32_t m = S.mv[q];
+            if (m) ch |= relax3(sd, q, m, xo0, xb0, xo1, xb1, xo2, xb2);
+        }
+        for (int st = 0; st < kT; ++st) {
+            const int q = (x0 + fwd * st) * kH + li;
+            const uint32_t m = S.mv[q];
+            if (m) ch |= relax3(sd, q, m, yo0, yb0, yo1, yb1, yo2, yb2);
+        }
+        any |= ch;
+        if (__ballot(ch) == 0) break;
+    }
+    bool wrote = false;
+    if (__ballot(any)) {
+        for (int k = lane; k < kT * kT; k += kWave) {
+            const int q = (k / kT + 1) * kH + k % kT + 1;
+            const int gx = gx0 + q % kH, gy = gy0 + q / kH;
+            if (gx >= d.nx || gy >= d.ny) continue;
+            uint64_t* cell = D + (size_t)gy * d.nx + gx;
+            const uint64_t v = sd[q];
+            if (v != load_relaxed(cell)) {
+                store_relaxed(cell, v);
+                wrote = true;
             }
         }
-        if (!__syncthreads_or(ch)) break;
     }
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int q = li[k];
-        if (sd[q] != init[k]) {
-            store_relaxed(D + (size_t)(gy0 + q / kH) * d.nx + (gx0 + q % kH), sd[q]);
-            any = true;
-        }
-    }
-    const int blk = __syncthreads_or(any);
-    if (threadIdx.x == 0) {
+    const bool blk = __ballot(wrote) != 0;
+    if (lane == 0) {
         next[t] = blk ? 1 : 0;
         if (blk) atomicAdd(d.active + slot, 1u);
     }
@@ -279,7 +329,7 @@ void launch_dist_init(const DistArgs& d, hipStream_t s) {
 
 void launch_dist_rounds(const DistArgs& d, int round0, int n_rounds, hipStream_t s) {
     k_zero_u32<<<1, 64, 0, s>>>(d.active, n_rounds);
-    const dim3 grid((unsigned)(d.tiles_x * d.tiles_y), (unsigned)d.n_goals);
+    const dim3 grid((unsigned)(d.tiles_x * d.tiles_y), (unsigned)((d.n_goals + kGW - 1) / kGW));
     for (int r = 0; r < n_rounds; ++r) k_dist_round<<<grid, kNT, 0, s>>>(d, round0 + r, r);
 }
 
