@@ -116,3 +116,15 @@ def test_validation_rejects_broken_hierarchies(hier):
     st, _ = hgs.validate_scene(h)
     h.bound = old
     assert st == hgs.HGS_E_INVALID
+
+
+def test_backward_structs_match_header():
+    src = open(os.path.join(ROOT, "include", "hgs.h")).read()
+    for name, fields in (("hgs_image_grad", ["rgb", "depth", "alpha"]),
+                         ("hgs_scene_grad", ["means", "scales", "quats", "opacity", "sh"])):
+        end = src.index("} " + name + ";")
+        body = src[src.rindex("typedef struct {", 0, end):end]
+        assert re.findall(r"\*\s*([a-z_]+);", body) == fields, name
+        st = getattr(hgs, name)
+        assert [n for n, _ in st._fields_] == fields
+        assert ctypes.sizeof(st) == 8 * len(fields)
