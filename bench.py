@@ -57,12 +57,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels instead of replaying a graph")
     ap.add_argument("--workload", default="plan2m-lod",
-                    choices=["plan2m-lod", "plan8m", "building30m", "slice", "nav"],
+                    choices=["plan2m-lod", "plan8m", "building30m", "slice", "nav", "backward"],
                     help="plan2m-lod (the metric's workload), plan8m (256 mixed-resolution views of the "
                          "8M-leaf plan, threshold cuts), building30m (64 1080p views of the 30M-leaf "
                          "two-floor building, learned cut), slice (GS-slice collision map of the 30M-leaf "
-                         "building) or nav (expert trajectories on the building's navigable maps); the "
-                         "last four are reported for reference")
+                         "building), nav (expert trajectories on the building's navigable maps) or backward "
+                         "(the backward pass of the headline batch); the last five are reported for "
+                         "reference")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed batched learned path (for profilers): no quality evaluation, no "
                          "threshold or single-view comparison")
@@ -172,6 +173,115 @@ def time_backward(r, hgs, torch, batches, outs, steps):
             total += e0.elapsed_time(e1)
     r.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
     return total / steps
+
+
+# FP32 operations per evaluated (pixel, Gaussian) pair of the backward
+# compositing kernel, counted from its formulas (FMA = 2): the forward replay
+# (24, as the forward compositor) and the reverse step (64: q and alpha 13,
+# transmittance recovery 2, dL/dalpha 14, colour and depth gradients 4,
+# what-lies-behind updates 8, the conic and mean gradients 19, opacity 2,
+# rounded up to whole FMAs).
+FLOPS_PER_PAIR_BWD = 88
+
+
+def run_backward(args):
+    """Backward pass of the headline batch: 50 held-out 1280x720 views of
+    plan2m-lod with the learned cut, random image gradients; each step
+    renders the batch and runs the backward pass, only the backward is timed
+    (HIP events on the stream).  The oracle's FP64 autograd gradients are
+    timed on a 128x128 window of one view for the CPU baseline."""
+    import numpy as np
+    import torch
+    from paper_2603_15186_amd import hgs, lod
+    from paper_2603_15186_amd.synth import workloads as W
+    scene, _, eval_cams = W.plan2m_lod()
+    B = args.views
+    batches = [eval_cams[i:i + B] for i in range(0, min(len(eval_cams), args.poses) - B + 1, B)]
+    px_per_step = B * eval_cams[0].width * eval_cams[0].height
+    r = hgs.Renderer(0)
+    r.load_scene(scene)
+    model = lod.LodModel.load(args.model or lod.default_model_path())
+    model.install(r)
+    r.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
+    r.set_cameras(batches[0])
+    outs = r.alloc_outputs()
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    grads = [tuple(torch.randn(t.shape, generator=gen, device="cuda") for t in o) for o in outs]
+    # evaluated pairs per batch (forward count; the backward walks the same pairs)
+    r.set_option(hgs.HGS_OPT_COUNT_NALG, 1)
+    n_alg = []
+    for bt in batches:
+        r.set_cameras(bt)
+        r.render(outs)
+        n_alg.append(r.stats()["n_alg"])
+    r.set_option(hgs.HGS_OPT_COUNT_NALG, 0)
+    acc = None
+    for i in range(args.warmup):
+        r.set_cameras(batches[i % len(batches)])
+        r.render(outs)
+        acc = r.backward(grads, out=acc)
+    torch.cuda.synchronize()
+    r.set_option(hgs.HGS_OPT_STAGE_TIMING, 1)
+    stream = torch.cuda.current_stream()
+    total = 0.0
+    alg = 0
+    for i in range(args.steps):
+        r.set_cameras(batches[i % len(batches)])
+        r.render(outs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        acc = r.backward(grads, out=acc)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total += e0.elapsed_time(e1)
+        alg += n_alg[i % len(batches)]
+    st = r.stats()
+    r.set_option(hgs.HGS_OPT_STAGE_TIMING, 0)
+    ms = total / args.steps
+    ms_comp = st["ms_bwd_composite"] / max(st["timed_backwards"], 1)
+    achieved = FLOPS_PER_PAIR_BWD * (alg / args.steps) / (ms_comp * 1e-3) / 1e12
+    log(f"backward {ms:.3f} ms per batch (compositing {ms_comp:.3f} ms), {px_per_step / ms / 1e3:.1f} Mpix/s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import grad as G
+        from oracle import oracle as O
+        cam = batches[0][0]
+        x0, y0, w = 576, 296, 128
+        ids = O.cut(scene, cam, O.MODE_THRESHOLD, 1.0)
+        pr = O.project(scene, ids, cam)
+        ok = pr[:, O.PF["valid"]] > 0
+        ex = np.sqrt(9.0 * pr[:, O.PF["S00"]]) + 1
+        ey = np.sqrt(9.0 * pr[:, O.PF["S11"]]) + 1
+        near = ok & (pr[:, O.PF["u"]] + ex >= x0) & (pr[:, O.PF["u"]] - ex <= x0 + w) & \
+            (pr[:, O.PF["v"]] + ey >= y0) & (pr[:, O.PF["v"]] - ey <= y0 + w)
+        sub = ids[near]
+        yy, xx = np.mgrid[y0:y0 + w, x0:x0 + w]
+        rng = np.random.default_rng(0)
+        P = w * w
+        up = (rng.normal(size=(P, 3)), rng.normal(size=P), rng.normal(size=P))
+        t0 = time.perf_counter()
+        p = G.leaf_params(scene, sub)
+        G.render(p, scene.sh_degree, cam, xx.ravel(), yy.ravel(), upstream=up)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": P / t_cpu / 1e6, "unit": "Mpixels/s", "cores": torch.get_num_threads(), "kind": "oracle",
+               "sample": f"FP64 autograd gradients of a {w}x{w} window of one view ({sub.size} Gaussians "
+                         f"reaching it, threshold cut tau=1), {t_cpu:.2f} s"}
+    out = {"metric": "Mpixels/s, backward pass (image gradients to Gaussian parameters) of the 720p "
+                     "learned-LOD batch",
+           "value": px_per_step / ms / 1e3, "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "plan2m-lod 50 x 1280x720 held-out views, learned LOD cut, random image "
+                                  "gradients", "parallelism": "single GPU"},
+           "roofline": {"kernel": "k_composite_bwd", "bound": "alu", "achieved": achieved,
+                        "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                        "traffic": None, "ms_per_launch": ms_comp, "n_alg_per_launch": alg / args.steps,
+                        "flops_per_pair": FLOPS_PER_PAIR_BWD},
+           "cpu_baseline": cpu,
+           "extra": {"ms_backward_composite": ms_comp,
+                     "ms_backward_params": st["ms_bwd_total"] / max(st["timed_backwards"], 1) - ms_comp}}
+    print(json.dumps(out), flush=True)
+    r.close()
 
 
 def run_plan8m(args):
@@ -487,6 +597,8 @@ def main():
         return run_slice(args)
     if args.workload == "nav":
         return run_nav(args)
+    if args.workload == "backward":
+        return run_backward(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: the "

@@ -158,6 +158,8 @@ typedef struct {
     int64_t passes;               /* pipeline passes of the last render */
     int64_t n_eval;               /* (pixel, list entry) slots the compositor walked,
                                      including q > 9 and stopped pixels (if counted) */
+    int64_t timed_backwards;      /* backward passes summed in the ms_bwd_* fields */
+    double ms_bwd_composite, ms_bwd_total;   /* compositing part and whole backward pass */
 } hgs_stats;
 
 /* Create a context on HIP device `device`.  *out is set on success. */

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "internal.h"
@@ -92,6 +93,10 @@ struct hgs_ctx {
     // backward pass: per-entry gradients and per-view image gradients; the
     // last render's final pair buffer and whether it blended levels
     DevMem egrad, dimg, brec;
+    // stage timing of backward passes: (start, compositing done, end)
+    std::vector<std::array<hipEvent_t, 3>> bwd_ev;
+    double bwd_ms[2] = {0, 0};
+    int64_t bwd_n = 0;
     int last_pair_buf = 0;
     bool last_blend = false;
     uint32_t* nav_active_host = nullptr;   // pinned
@@ -312,6 +317,17 @@ hgs_status upload_views(hgs_ctx* c, hipStream_t s, const hgs_output* outs) {
 }
 
 hgs_status harvest_events(hgs_ctx* c) {
+    for (auto& e : c->bwd_ev) {
+        HIP_TRY(c, hipEventSynchronize(e[2]));
+        float a = 0.f, b = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&a, e[0], e[1]));
+        HIP_TRY(c, hipEventElapsedTime(&b, e[0], e[2]));
+        c->bwd_ms[0] += a;
+        c->bwd_ms[1] += b;
+        ++c->bwd_n;
+        for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    }
+    c->bwd_ev.clear();
     for (size_t b = 0; b + 6 <= c->ev_used; b += 6) {
         HIP_TRY(c, hipEventSynchronize(c->ev_pool[b + 5]));
         float t[5];
@@ -668,6 +684,8 @@ void hgs_destroy(hgs_ctx* c) {
                      &c->counters, &c->sort_k, &c->sort_v, &c->sort_n, &c->nav_goals, &c->nav_flags,
                      &c->nav_active, &c->nav_steps, &c->egrad, &c->dimg, &c->brec};
     for (DevMem* m : all) release(*m);
+    for (auto& e : c->bwd_ev)
+        for (hipEvent_t x : e) (void)hipEventDestroy(x);
     if (c->nav_active_host) (void)hipHostFree(c->nav_active_host);
     if (c->views_host) (void)hipHostFree(c->views_host);
     if (c->ctr_host) (void)hipHostFree(c->ctr_host);
@@ -943,6 +961,8 @@ hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
             c->stage_timing = val != 0;
             for (double& a : c->acc_ms) a = 0;
             c->acc_n = 0;
+            c->bwd_ms[0] = c->bwd_ms[1] = 0;
+            c->bwd_n = 0;
             return HGS_OK;
         }
         case HGS_OPT_INITIAL_CAPACITY: {
@@ -1136,6 +1156,9 @@ hgs_status hgs_get_stats(hgs_ctx* c, hgs_stats* out) {
     out->ms_sort = c->acc_ms[2];
     out->ms_composite = c->acc_ms[3];
     out->ms_total = c->acc_ms[4];
+    out->timed_backwards = c->bwd_n;
+    out->ms_bwd_composite = c->bwd_ms[0];
+    out->ms_bwd_total = c->bwd_ms[1];
     return HGS_OK;
 }
 
@@ -1698,7 +1721,22 @@ hgs_status hgs_render_backward(hgs_ctx* c, void* stream, const hgs_image_grad* g
     ga.g_quats = out->quats;
     ga.g_opacity = out->opacity;
     ga.g_sh = out->sh;
-    launch_backward(b, p, sa, ga, st);
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (c->stage_timing) {
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+        if (ev[0]) HIP_TRY(c, hipEventRecord(ev[0], st));
+    }
+    launch_backward_composite(b, p.ctr, st);
+    if (ev[1]) HIP_TRY(c, hipEventRecord(ev[1], st));
+    launch_backward_params(p, sa, ga, st);
+    if (ev[2]) HIP_TRY(c, hipEventRecord(ev[2], st));
+    if (ev[0] && ev[1] && ev[2]) {
+        c->bwd_ev.push_back({ev[0], ev[1], ev[2]});
+    } else {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
     HIP_TRY(c, hipGetLastError());
     return HGS_OK;
 }

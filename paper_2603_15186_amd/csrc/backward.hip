@@ -541,9 +541,12 @@ __global__ void k_entry_keys(const uint2* cut, const Counters* ctr, uint32_t cap
 
 }  // namespace
 
-void launch_backward(const BwdArgs& b, const ProjBwdArgs& p, SortArgs sa, GatherArgs ga, hipStream_t s) {
-    k_zero_egrad<<<1024, 256, 0, s>>>(b.egrad, p.ctr, b.cut_cap);
+void launch_backward_composite(const BwdArgs& b, const Counters* ctr, hipStream_t s) {
+    k_zero_egrad<<<1024, 256, 0, s>>>(b.egrad, ctr, b.cut_cap);
     if (b.total_tiles) k_composite_bwd<<<b.total_tiles, kNT, 0, s>>>(b);
+}
+
+void launch_backward_params(const ProjBwdArgs& p, SortArgs sa, GatherArgs ga, hipStream_t s) {
     switch (p.sh_degree) {
         case 0: k_project_bwd<0><<<2048, 256, 0, s>>>(p); break;
         case 1: k_project_bwd<1><<<2048, 256, 0, s>>>(p); break;

@@ -289,7 +289,8 @@ struct GatherArgs {
     float* g_opacity;                // [n]
     float* g_sh;                     // [n][K][3]
 };
-void launch_backward(const BwdArgs& b, const ProjBwdArgs& p, SortArgs sa, GatherArgs ga, hipStream_t s);
+void launch_backward_composite(const BwdArgs& b, const Counters* ctr, hipStream_t s);
+void launch_backward_params(const ProjBwdArgs& p, SortArgs sa, GatherArgs ga, hipStream_t s);
 
 // shortest-path planning (nav.hip)
 struct NavArgs {

@@ -76,7 +76,8 @@ class hgs_stats(ctypes.Structure):
                 ("n_alg", ctypes.c_int64), ("tiles", ctypes.c_int64), ("regrows", ctypes.c_int64),
                 ("timed_renders", ctypes.c_int64), ("graph_launches", ctypes.c_int64), ("ms_cut", ctypes.c_double), ("ms_project", ctypes.c_double), ("ms_sort", ctypes.c_double),
                 ("ms_composite", ctypes.c_double), ("ms_total", ctypes.c_double), ("passes", ctypes.c_int64),
-                ("n_eval", ctypes.c_int64)]
+                ("n_eval", ctypes.c_int64), ("timed_backwards", ctypes.c_int64), ("ms_bwd_composite", ctypes.c_double),
+                ("ms_bwd_total", ctypes.c_double)]
 
 
 class hgs_slice_grid(ctypes.Structure):
