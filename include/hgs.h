@@ -42,7 +42,7 @@ typedef int32_t hgs_status;
 #define HGS_E_HIP (-4)            /* a HIP runtime call failed */
 #define HGS_E_CAPACITY (-5)       /* a work buffer overflowed and regrowth is off */
 #define HGS_E_BAD_HIERARCHY (-6)  /* hierarchy arrays are inconsistent */
-#define HGS_E_UNSUPPORTED (-7)    /* valid request this build does not support */
+#define HGS_E_UNSUPPORTED (-7)    /* valid request the library does not support */
 
 /* LOD modes (hgs_set_lod). */
 #define HGS_LOD_ALL_LEAVES 0      /* every leaf, no culling */

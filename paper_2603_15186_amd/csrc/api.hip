@@ -93,6 +93,8 @@ struct hgs_ctx {
     // backward pass: per-entry gradients and per-view image gradients; the
     // last render's final pair buffer and whether it blended levels
     DevMem egrad, dimg, brec;
+    ImgGrad* dimg_host = nullptr;        // pinned, kMaxViews entries
+    hipEvent_t dimg_copied = nullptr;
     // stage timing of backward passes: (start, compositing done, end)
     std::vector<std::array<hipEvent_t, 3>> bwd_ev;
     double bwd_ms[2] = {0, 0};
@@ -663,7 +665,9 @@ hgs_status hgs_create(int32_t device, hgs_ctx** out) {
     c->device = device;
     if (ensure(c, c->counters, sizeof(Counters) * kMaxViews) != HGS_OK ||
         hipHostMalloc((void**)&c->ctr_host, sizeof(Counters) * kMaxViews, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&c->views_copied, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->views_copied, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&c->dimg_host, sizeof(ImgGrad) * kMaxViews, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->dimg_copied, hipEventDisableTiming) != hipSuccess) {
         hgs_destroy(c);
         return HGS_E_HIP;
     }
@@ -690,6 +694,8 @@ void hgs_destroy(hgs_ctx* c) {
     if (c->views_host) (void)hipHostFree(c->views_host);
     if (c->ctr_host) (void)hipHostFree(c->ctr_host);
     if (c->views_copied) (void)hipEventDestroy(c->views_copied);
+    if (c->dimg_copied) (void)hipEventDestroy(c->dimg_copied);
+    if (c->dimg_host) (void)hipHostFree(c->dimg_host);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     invalidate_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -1670,16 +1676,17 @@ hgs_status hgs_render_backward(hgs_ctx* c, void* stream, const hgs_image_grad* g
     if (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh)
         return fail(c, HGS_E_INVALID, "every gradient array is required");
     const int nv = (int)c->cams.size();
-    std::vector<ImgGrad> ig((size_t)nv);
-    for (int v = 0; v < nv; ++v) ig[v] = ImgGrad{grads[v].rgb, grads[v].depth, grads[v].alpha};
     HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipEventSynchronize(c->dimg_copied));    // the previous copy is done with the mirror
+    for (int v = 0; v < nv; ++v) c->dimg_host[v] = ImgGrad{grads[v].rgb, grads[v].depth, grads[v].alpha};
     hipStream_t st = (hipStream_t)stream;
     hgs_status s;
     if ((s = ensure(c, c->egrad, (size_t)c->cut_cap * kEntryGrad * sizeof(float))) ||
         (s = ensure(c, c->brec, (size_t)c->cut_cap * kEntryRec * sizeof(float))) ||
         (s = ensure(c, c->dimg, (size_t)nv * sizeof(ImgGrad))))
         return s;
-    HIP_TRY(c, hipMemcpyAsync(c->dimg.p, ig.data(), (size_t)nv * sizeof(ImgGrad), hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(c->dimg.p, c->dimg_host, (size_t)nv * sizeof(ImgGrad), hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipEventRecord(c->dimg_copied, st));
     BwdArgs b{};
     b.vals = P<uint32_t>(c->pval[c->last_pair_buf]);
     b.ranges = P<uint2>(c->ranges);
