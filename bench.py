@@ -151,11 +151,12 @@ def timed_loop(r, hgs, torch, batches, outs, steps, warmup, stage_timing):
     return (t1 - t0) * 1e3 / steps, st
 
 
-def time_backward(r, hgs, torch, batches, outs, steps):
+def time_backward(r, hgs, torch, batches, outs, steps, lanes=1):
     """ms per backward pass of a batch: each step renders a batch (untimed
     part of the stream) and runs the backward pass with fixed random image
     gradients; only the backward is inside the HIP events."""
     r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+    r.set_option(hgs.HGS_OPT_LANES, 1)          # the backward pass needs a one-pass render
     gen = torch.Generator(device="cuda").manual_seed(0)
     grads = [tuple(torch.randn(t.shape, generator=gen, device="cuda") for t in o) for o in outs]
     stream = torch.cuda.current_stream()
@@ -171,6 +172,7 @@ def time_backward(r, hgs, torch, batches, outs, steps):
         torch.cuda.synchronize()
         if i:                                   # the first one warms up
             total += e0.elapsed_time(e1)
+    r.set_option(hgs.HGS_OPT_LANES, lanes)
     r.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
     return total / steps
 
@@ -309,7 +311,7 @@ def run_plan8m(args):
         n = st["timed_renders"]
         res[f"tau{tau:g}"] = {"ms_per_batch": ms, "mpix_s": px / (ms * 1e-3) / 1e6, "cut": st["cut_size"],
                                "pairs": st["pairs"], "passes": st["passes"],
-                               "plan": {k: plan[k] for k in ("batch_depth", "persistent", "sort_digit_bits")},
+                               "plan": {k: plan[k] for k in ("lanes", "batch_depth", "persistent", "sort_digit_bits")},
                                "stage_ms": {k: st["ms_" + k] / n for k in ("cut", "project", "sort", "composite")}}
         log(f"tau={tau}: {ms:.2f} ms per batch, {res[f'tau{tau:g}']['mpix_s']:.0f} Mpix/s")
     out = {"metric": "Mpixels/s, 256 mixed-resolution views of the 8M-leaf plan in one call",
@@ -695,11 +697,12 @@ def main():
     stage = {k: st["ms_" + k] / n for k in ("cut", "project", "sort", "composite")}
 
     if args.quick and args.with_backward:
-        ms_bwd_q = time_backward(r, hgs, torch, batches, outs, args.steps)
+        ms_bwd_q = time_backward(r, hgs, torch, batches, outs, args.steps, plan["lanes"])
         log(f"backward: {ms_bwd_q:.3f} ms per batch")
     single = eval_cams[:args.single]
     px1 = single[0].width * single[0].height
-    ms_t1 = ms_tm = ms_single = ms_blend = ms_bwd = float("nan")
+    ms_t1 = ms_tm = ms_single = ms_blend = ms_bwd = ms_lanes2 = float("nan")
+    plan2 = None
     if not args.quick:
         # batched threshold cuts
         r.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
@@ -713,7 +716,17 @@ def main():
         r.set_option(hgs.HGS_OPT_LOD_BLEND, 0)
         # backward pass of the learned batch (random image gradients),
         # eager launches, timed with HIP events on the stream
-        ms_bwd = time_backward(r, hgs, torch, batches, outs, args.steps)
+        ms_bwd = time_backward(r, hgs, torch, batches, outs, args.steps, plan["lanes"])
+        # the learned batch on two pipeline lanes (passes overlapping on two
+        # streams; same images), with its own launch plan
+        r.set_option(hgs.HGS_OPT_LANES, 2)
+        plan2 = r.autotune(reps=3)
+        r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
+        ms_lanes2, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
+        r.set_option(hgs.HGS_OPT_LANES, 1)
+        r.set_option(hgs.HGS_OPT_BATCH_DEPTH, plan["batch_depth"])
+        r.set_option(hgs.HGS_OPT_PERSISTENT, plan["persistent"])
+        r.set_option(hgs.HGS_OPT_SORT_DIGIT_BITS, plan["sort_digit_bits"])
 
         # plain single-view path, tau = 1
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
@@ -745,6 +758,9 @@ def main():
         "batched_threshold_matched_mpix_s": mpix(ms_tm, px_per_step),
         "batched_learned_blended_mpix_s": mpix(ms_blend, px_per_step),
         "backward_ms_per_step": ms_bwd, "backward_mpix_s": mpix(ms_bwd, px_per_step),
+        "batched_learned_two_lanes_mpix_s": mpix(ms_lanes2, px_per_step),
+        "two_lanes_plan": None if plan2 is None else {k: plan2[k] for k in ("batch_depth", "persistent",
+                                                                               "sort_digit_bits")},
         "matched_tau": tau_m, "matched_tau_loss_db": loss_m,
         "plain_single_view_tau1_mpix_s": mpix(ms_single, px1),
         "speedup_vs_plain_single_view": value / mpix(ms_single, px1),
@@ -773,7 +789,7 @@ def main():
                    "leaves": int(np.count_nonzero(scene.child_count == 0)), "nodes": scene.n,
                    "views_per_step": B, "resolution": "1280x720", "fx": 900,
                    "lod": f"learned (p*={model.p_star}, s_hi={model.s_hi}px, threshold tau=1 fallback)",
-                   "plan": {k: plan[k] for k in ("batch_depth", "persistent", "sort_digit_bits")},
+                   "plan": {k: plan[k] for k in ("lanes", "batch_depth", "persistent", "sort_digit_bits")},
                    "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -72,6 +72,12 @@ typedef int32_t hgs_status;
                                      renderer itself when a pass would outgrow
                                      the 2^28-entry index space.  Images do not
                                      depend on the passes. */
+#define HGS_OPT_LANES 13          /* 2: split a batch into at least two pipeline passes
+                                     that alternate between two work-buffer sets and
+                                     two streams, so one pass's compositing overlaps
+                                     the next pass's cut, projection and binning
+                                     (twice the work-buffer memory); 1 (default): one
+                                     set, one stream.  Images do not depend on it. */
 #define HGS_OPT_LOD_BLEND 12      /* 1: level-of-detail transition blending (NavGSim
                                      Sec. III-B: transition regions between levels
                                      are smoothly interpolated).  A cut node g with
@@ -229,17 +235,20 @@ typedef struct {
     int32_t from_cache;           /* 1: read from the plan cache, not timed */
     double ms;                    /* render time of the plan (mean over reps) */
     double ms_default;            /* render time of the default plan */
+    int32_t lanes;                /* HGS_OPT_LANES in force (not searched) */
+    int32_t reserved;             /* 0 */
 } hgs_plan;
 
 /* Time the launch choices that do not change the image (compositor batch
  * depth 64/128/256, persistent or one-workgroup-per-tile compositing, radix
- * digit width 6..11) on the current scene, views and LOD, rendering every
- * view reps >= 1 times per candidate into internal buffers on `stream`, and
- * keep the fastest as the context's options (*out describes it; may be
- * NULL).  Coordinate search: compositor choices first, then the digit
- * width.  cache_path (NULL: none) names a text file of earlier plans keyed
+ * digit width 6..11) on the current scene, views, LOD and lanes (kept as
+ * set), rendering every view reps >= 1 times per candidate into internal
+ * buffers on `stream`, and keep the fastest as the context's options (*out
+ * describes it; may be NULL).  Coordinate search: compositor choices first,
+ * then the digit width.  cache_path (NULL: none) names a text file of earlier plans keyed
  * by scene size, view sizes and LOD; a matching line is applied without
- * timing, a new plan is appended.  Synchronous; leaves stage timing off. */
+ * timing, a new plan is appended (the key includes the lanes setting).
+ * Synchronous; leaves stage timing off. */
 hgs_status hgs_autotune(hgs_ctx* ctx, void* stream, const char* cache_path, int32_t reps, hgs_plan* out);
 
 /* Sort n (key, value) pairs on the device by the low `key_bits` bits of the

@@ -23,6 +23,14 @@ struct DevMem {
     size_t bytes = 0;
 };
 
+// Work buffers of one pipeline pass.  With two lanes, consecutive passes
+// alternate between two sets on two streams, so one pass's compositing
+// overlaps the next pass's cut, projection and binning.
+struct Work {
+    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, bins, offsets, dec;
+    DevMem pkey[2], pval[2], scan_tmp, hist;
+};
+
 }  // namespace
 
 struct hgs_ctx {
@@ -66,8 +74,11 @@ struct hgs_ctx {
     RenderOpts ropts;
     // work buffers
     uint32_t frontier_cap = 0, cut_cap = 0, pair_cap = 0;
-    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, bins, offsets, dec;
-    DevMem pkey[2], pval[2], ranges, scan_tmp, hist, counters;
+    Work w[2];                        // per lane
+    DevMem ranges, counters;          // shared: indexed by absolute tile / by pass
+    int lanes = 1;                    // HGS_OPT_LANES
+    hipStream_t lane_stream = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     Counters* ctr_host = nullptr;     // pinned
     bool last_valid = false;
     int64_t regrows = 0;
@@ -100,6 +111,7 @@ struct hgs_ctx {
     double bwd_ms[2] = {0, 0};
     int64_t bwd_n = 0;
     int last_pair_buf = 0;
+    int last_lane = 0;
     bool last_blend = false;
     uint32_t* nav_active_host = nullptr;   // pinned
 };
@@ -253,23 +265,36 @@ __global__ void k_reset(Counters* c) {
 hgs_status alloc_work(hgs_ctx* c) {
     hgs_status s;
     const size_t F = c->frontier_cap, M = c->cut_cap, Pc = c->pair_cap;
-    for (int i = 0; i < 2; ++i)
-        if ((s = ensure(c, c->frontier[i], F * sizeof(uint2)))) return s;
-    if ((s = ensure(c, c->dec, F))) return s;
-    if ((s = ensure(c, c->cut, M * sizeof(uint2)))) return s;
-    if ((s = ensure(c, c->proj, M * sizeof(Proj)))) return s;
-    for (int i = 0; i < 2; ++i) {
-        if ((s = ensure(c, c->dkey[i], M * 4))) return s;
-        if ((s = ensure(c, c->dval[i], M * 4))) return s;
-        if ((s = ensure(c, c->pkey[i], Pc * 4))) return s;
-        if ((s = ensure(c, c->pval[i], Pc * 4))) return s;
+    for (int l = 0; l < c->lanes; ++l) {
+        Work& w = c->w[l];
+        for (int i = 0; i < 2; ++i)
+            if ((s = ensure(c, w.frontier[i], F * sizeof(uint2)))) return s;
+        if ((s = ensure(c, w.dec, F))) return s;
+        if ((s = ensure(c, w.cut, M * sizeof(uint2)))) return s;
+        if ((s = ensure(c, w.proj, M * sizeof(Proj)))) return s;
+        for (int i = 0; i < 2; ++i) {
+            if ((s = ensure(c, w.dkey[i], M * 4))) return s;
+            if ((s = ensure(c, w.dval[i], M * 4))) return s;
+            if ((s = ensure(c, w.pkey[i], Pc * 4))) return s;
+            if ((s = ensure(c, w.pval[i], Pc * 4))) return s;
+        }
+        if ((s = ensure(c, w.ntiles, M * 4))) return s;
+        if ((s = ensure(c, w.bins, M * sizeof(BinRec)))) return s;
+        if ((s = ensure(c, w.offsets, M * 4))) return s;
+        if ((s = ensure(c, w.scan_tmp, (kScanBlocks + 1) * sizeof(uint4)))) return s;
+        if ((s = ensure(c, w.hist, (size_t)kSortBins * (kSortBlocks + 1) * 4))) return s;
     }
-    if ((s = ensure(c, c->ntiles, M * 4))) return s;
-    if ((s = ensure(c, c->bins, M * sizeof(BinRec)))) return s;
-    if ((s = ensure(c, c->offsets, M * 4))) return s;
-    if ((s = ensure(c, c->scan_tmp, (kScanBlocks + 1) * sizeof(uint4)))) return s;
-    if ((s = ensure(c, c->hist, (size_t)kSortBins * (kSortBlocks + 1) * 4))) return s;
     return HGS_OK;
+}
+
+// Lane of pass g and the work set it uses.
+int lane_of(const hgs_ctx* c, int g) { return c->lanes > 1 ? g % c->lanes : 0; }
+
+void release_work(Work& w) {
+    DevMem* all[] = {&w.frontier[0], &w.frontier[1], &w.cut, &w.proj, &w.dkey[0], &w.dkey[1], &w.dval[0],
+                     &w.dval[1], &w.ntiles, &w.bins, &w.offsets, &w.dec, &w.pkey[0], &w.pkey[1], &w.pval[0],
+                     &w.pval[1], &w.scan_tmp, &w.hist};
+    for (DevMem* m : all) release(*m);
 }
 
 // Cut entries are addressed by 28-bit indices inside pair values; pairs by
@@ -374,6 +399,7 @@ uint32_t pass_tile0(const hgs_ctx* c, int g) {
 // device table (the layout changed); otherwise only the host mirror moves.
 hgs_status plan_passes(hgs_ctx* c, int want, bool upload_table) {
     const int V = (int)c->cams.size();
+    want = std::max(c->lanes, want);
     want = std::max(1, std::min(want, V));
     uint64_t total = 0;
     for (const hgs_camera& k : c->cams) total += (uint64_t)k.width * k.height;
@@ -416,6 +442,7 @@ hgs_status plan_passes(hgs_ctx* c, int want, bool upload_table) {
 
 // One pipeline pass over the views of pass g (counters slot g).
 void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
+    Work& W = c->w[lane_of(c, g)];
     Counters* ctr = P<Counters>(c->counters) + g;
     const int v0 = c->pass_v0[g], v1 = c->pass_v0[g + 1];
     const uint32_t t0 = pass_tile0(c, g), t1 = pass_tile0(c, g + 1);
@@ -434,13 +461,13 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     ca.flat = !c->hier;
     ca.views = P<ViewDev>(c->views) + v0;
     ca.n_views = v1 - v0;
-    ca.frontier[0] = P<uint2>(c->frontier[0]);
-    ca.frontier[1] = P<uint2>(c->frontier[1]);
+    ca.frontier[0] = P<uint2>(W.frontier[0]);
+    ca.frontier[1] = P<uint2>(W.frontier[1]);
     ca.frontier_cap = c->frontier_cap;
-    ca.cut = P<uint2>(c->cut);
+    ca.cut = P<uint2>(W.cut);
     ca.cut_cap = c->cut_cap;
-    ca.scan_tmp = P<uint4>(c->scan_tmp);
-    ca.dec = P<uint8_t>(c->dec);
+    ca.scan_tmp = P<uint4>(W.scan_tmp);
+    ca.dec = P<uint8_t>(W.dec);
     ca.ctr = ctr;
     ca.mlp = (c->lod_mode == HGS_LOD_LEARNED && c->mlp_loaded) ? c->mlp_dev.p : nullptr;
     ca.p_star = c->mlp_host.p_star;
@@ -459,11 +486,11 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pa.n = c->n;
     pa.sh_degree = c->sh_degree;
     pa.views = ca.views;
-    pa.proj = P<Proj>(c->proj);
-    pa.depth_key = P<uint32_t>(c->dkey[0]);
-    pa.depth_val = P<uint32_t>(c->dval[0]);
-    pa.ntiles = P<uint32_t>(c->ntiles);
-    pa.bins = P<BinRec>(c->bins);
+    pa.proj = P<Proj>(W.proj);
+    pa.depth_key = P<uint32_t>(W.dkey[0]);
+    pa.depth_val = P<uint32_t>(W.dval[0]);
+    pa.ntiles = P<uint32_t>(W.ntiles);
+    pa.bins = P<BinRec>(W.bins);
     pa.exact_tiles = c->ropts.exact_tiles;
     pa.ctr = ctr;
     pa.blend = c->ropts.lod_blend && c->hier && c->lod_mode != HGS_LOD_ALL_LEAVES;
@@ -473,15 +500,15 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     mark(c, 2, s);
 
     SortArgs sa{};
-    sa.keys[0] = P<uint32_t>(c->dkey[0]);
-    sa.keys[1] = P<uint32_t>(c->dkey[1]);
-    sa.vals[0] = P<uint32_t>(c->dval[0]);
-    sa.vals[1] = P<uint32_t>(c->dval[1]);
+    sa.keys[0] = P<uint32_t>(W.dkey[0]);
+    sa.keys[1] = P<uint32_t>(W.dkey[1]);
+    sa.vals[0] = P<uint32_t>(W.dval[0]);
+    sa.vals[1] = P<uint32_t>(W.dval[1]);
     sa.count = &ctr->cut;
     sa.cap = c->cut_cap;
     sa.key_bits = 32;
     sa.max_digit_bits = c->sort_digit_bits;
-    sa.hist = P<uint32_t>(c->hist);
+    sa.hist = P<uint32_t>(W.hist);
     const int dr = launch_sort(sa, s);
 
     EmitArgs ea{};
@@ -490,9 +517,9 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     ea.bins = pa.bins;
     ea.proj = pa.proj;
     ea.cut_cap = c->cut_cap;
-    ea.offsets = P<uint32_t>(c->offsets);
-    ea.keys = P<uint32_t>(c->pkey[0]);
-    ea.vals = P<uint32_t>(c->pval[0]);
+    ea.offsets = P<uint32_t>(W.offsets);
+    ea.keys = P<uint32_t>(W.pkey[0]);
+    ea.vals = P<uint32_t>(W.pval[0]);
     ea.pair_cap = c->pair_cap;
     ea.exact_tiles = c->ropts.exact_tiles;
     ea.scan_tmp = ca.scan_tmp;
@@ -500,10 +527,10 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     launch_emit(ea, s);
 
     SortArgs pb{};
-    pb.keys[0] = P<uint32_t>(c->pkey[0]);
-    pb.keys[1] = P<uint32_t>(c->pkey[1]);
-    pb.vals[0] = P<uint32_t>(c->pval[0]);
-    pb.vals[1] = P<uint32_t>(c->pval[1]);
+    pb.keys[0] = P<uint32_t>(W.pkey[0]);
+    pb.keys[1] = P<uint32_t>(W.pkey[1]);
+    pb.vals[0] = P<uint32_t>(W.pval[0]);
+    pb.vals[1] = P<uint32_t>(W.pval[1]);
     pb.count = &ctr->pairs;
     pb.cap = c->pair_cap;
     pb.key_bits = bits_for(t1 - t0);
@@ -511,6 +538,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pb.hist = sa.hist;
     const int pr = launch_sort(pb, s);
     c->last_pair_buf = pr;
+    c->last_lane = lane_of(c, g);
     c->last_blend = pa.blend;
 
     CompositeArgs xa{};
@@ -518,7 +546,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     xa.vals = pb.vals[pr];
     xa.pair_cap = c->pair_cap;
     xa.cut_cap = c->cut_cap;
-    xa.ranges = P<uint2>(c->ranges);
+    xa.ranges = P<uint2>(c->ranges) + t0;
     xa.total_tiles = t1 - t0;
     xa.proj = pa.proj;
     xa.views = ca.views;
@@ -533,8 +561,21 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     if (c->stage_timing) c->ev_used += 6;
 }
 
+// Passes in order; with two lanes the odd passes run on the second stream
+// (forked from and joined back into s by events), each lane in order on its
+// own work set.
 void enqueue_render(hgs_ctx* c, hipStream_t s) {
-    for (int g = 0; g < n_passes(c); ++g) enqueue_pass(c, s, g);
+    const int np = n_passes(c);
+    const bool two = c->lanes > 1 && np > 1 && c->lane_stream;
+    if (two) {
+        (void)hipEventRecord(c->fork_ev, s);
+        (void)hipStreamWaitEvent(c->lane_stream, c->fork_ev, 0);
+    }
+    for (int g = 0; g < np; ++g) enqueue_pass(c, two && (g & 1) ? c->lane_stream : s, g);
+    if (two) {
+        (void)hipEventRecord(c->join_ev, c->lane_stream);
+        (void)hipStreamWaitEvent(s, c->join_ev, 0);
+    }
     if (c->stage_timing) ++c->acc_n;
 }
 
@@ -604,8 +645,8 @@ std::string plan_key(const hgs_ctx* c) {
     };
     for (const hgs_camera& k : c->cams) mix(((uint64_t)k.width << 32) | (uint32_t)k.height);
     char buf[160];
-    std::snprintf(buf, sizeof buf, "n%lld_v%zu_%016llx_lod%d_tau%.6g", (long long)c->n, c->cams.size(),
-                  (unsigned long long)h, c->lod_mode, (double)c->tau);
+    std::snprintf(buf, sizeof buf, "n%lld_v%zu_%016llx_lod%d_tau%.6g_l%d", (long long)c->n, c->cams.size(),
+                  (unsigned long long)h, c->lod_mode, (double)c->tau, c->lanes);
     return buf;
 }
 
@@ -618,8 +659,11 @@ bool read_plan(const char* path, const std::string& key, hgs_plan* p) {
     while (std::fgets(line, sizeof line, f)) {
         char k[256];
         hgs_plan q{};
-        if (std::sscanf(line, "%255s %d %d %d %lf %lf", k, &q.batch_depth, &q.persistent, &q.sort_digit_bits, &q.ms,
-                        &q.ms_default) == 6 && key == k) {
+        q.lanes = 1;
+        const int got = std::sscanf(line, "%255s %d %d %d %lf %lf %d", k, &q.batch_depth, &q.persistent,
+                                    &q.sort_digit_bits, &q.ms, &q.ms_default, &q.lanes);
+        if (got >= 6 && key == k) {
+            if (got == 6) q.lanes = 1;
             *p = q;          // the last matching line wins
             found = true;
         }
@@ -682,12 +726,14 @@ void hgs_destroy(hgs_ctx* c) {
     (void)hipDeviceSynchronize();
     DevMem* all[] = {&c->geo, &c->sh, &c->bound, &c->child, &c->leaf_ids, &c->parent, &c->nodefeat, &c->lvl,
                      &c->train_scratch, &c->region_dev, &c->surf, &c->views,
-                     &c->tile_view, &c->mlp_w, &c->mlp_w32, &c->mlp_dev, &c->frontier[0], &c->frontier[1], &c->cut, &c->proj,
-                     &c->dkey[0], &c->dkey[1], &c->dval[0], &c->dval[1], &c->ntiles, &c->bins, &c->offsets, &c->dec,
-                     &c->pkey[0], &c->pkey[1], &c->pval[0], &c->pval[1], &c->ranges, &c->scan_tmp, &c->hist,
+                     &c->tile_view, &c->mlp_w, &c->mlp_w32, &c->mlp_dev, &c->ranges,
                      &c->counters, &c->sort_k, &c->sort_v, &c->sort_n, &c->nav_goals, &c->nav_flags,
                      &c->nav_active, &c->nav_steps, &c->egrad, &c->dimg, &c->brec};
     for (DevMem* m : all) release(*m);
+    for (Work& w : c->w) release_work(w);
+    if (c->lane_stream) (void)hipStreamDestroy(c->lane_stream);
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     for (auto& e : c->bwd_ev)
         for (hipEvent_t x : e) (void)hipEventDestroy(x);
     if (c->nav_active_host) (void)hipHostFree(c->nav_active_host);
@@ -952,6 +998,27 @@ hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
         case HGS_OPT_PERSISTENT: c->ropts.persistent = val != 0; return HGS_OK;
         case HGS_OPT_EXACT_TILES: c->ropts.exact_tiles = val != 0; return HGS_OK;
         case HGS_OPT_LOD_BLEND: c->ropts.lod_blend = val != 0; return HGS_OK;
+        case HGS_OPT_LANES: {
+            if (val != 1 && val != 2) return fail(c, HGS_E_INVALID, "lanes must be 1 or 2");
+            if (val == 2 && !c->lane_stream) {
+                HIP_TRY(c, hipSetDevice(c->device));
+                HIP_TRY(c, hipStreamCreateWithFlags(&c->lane_stream, hipStreamNonBlocking));
+                HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+                HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+            }
+            c->lanes = (int)val;
+            invalidate_graph(c);
+            if (c->lanes == 1) {
+                HIP_TRY(c, hipDeviceSynchronize());
+                release_work(c->w[1]);
+            }
+            if (c->loaded && !c->cams.empty()) {
+                hgs_status st = alloc_work(c);
+                if (st) return st;
+            }
+            if (!c->cams.empty()) return plan_passes(c, c->lanes, false);
+            return HGS_OK;
+        }
         case HGS_OPT_PASS_VIEWS:
             if (val < 0 || val > kMaxViews) return fail(c, HGS_E_INVALID, "views per pass must be 0..%d", kMaxViews);
             c->pass_views = (int)val;
@@ -976,11 +1043,8 @@ hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
             c->forced_cap = (uint32_t)val;
             if (c->forced_cap) {
                 // shrink: drop the work buffers so they are re-made at this size
-                DevMem* w[] = {&c->frontier[0], &c->frontier[1], &c->dec, &c->cut, &c->proj, &c->dkey[0], &c->dkey[1],
-                               &c->dval[0], &c->dval[1], &c->ntiles, &c->bins, &c->offsets, &c->pkey[0],
-                               &c->pkey[1], &c->pval[0], &c->pval[1]};
                 HIP_TRY(c, hipDeviceSynchronize());
-                for (DevMem* m : w) release(*m);
+                for (Work& w : c->w) release_work(w);
                 c->frontier_cap = c->cut_cap = c->pair_cap = 0;
                 if (c->loaded && !c->cams.empty()) {
                     initial_caps(c);
@@ -1085,7 +1149,7 @@ hgs_status hgs_get_cut(hgs_ctx* c, int32_t view, int32_t* ids, int64_t cap, int6
     const uint32_t m = std::min(c->ctr_host[last].cut, c->cut_cap);
     const uint32_t vrel = (uint32_t)(view - vb);
     std::vector<uint2> e(m);
-    if (m) HIP_TRY(c, hipMemcpy(e.data(), c->cut.p, (size_t)m * sizeof(uint2), hipMemcpyDeviceToHost));
+    if (m) HIP_TRY(c, hipMemcpy(e.data(), c->w[c->last_lane].cut.p, (size_t)m * sizeof(uint2), hipMemcpyDeviceToHost));
     int64_t k = 0;
     for (uint32_t i = 0; i < m; ++i)
         if (e[i].y == vrel) {
@@ -1113,9 +1177,10 @@ hgs_status hgs_get_projected(hgs_ctx* c, int32_t view, float* out, int64_t cap, 
     std::vector<Proj> p(m);
     std::vector<uint32_t> nt(m);
     if (m) {
-        HIP_TRY(c, hipMemcpy(e.data(), c->cut.p, (size_t)m * sizeof(uint2), hipMemcpyDeviceToHost));
-        HIP_TRY(c, hipMemcpy(p.data(), c->proj.p, (size_t)m * sizeof(Proj), hipMemcpyDeviceToHost));
-        HIP_TRY(c, hipMemcpy(nt.data(), c->ntiles.p, (size_t)m * 4, hipMemcpyDeviceToHost));
+        const Work& W = c->w[c->last_lane];
+        HIP_TRY(c, hipMemcpy(e.data(), W.cut.p, (size_t)m * sizeof(uint2), hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(p.data(), W.proj.p, (size_t)m * sizeof(Proj), hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(nt.data(), W.ntiles.p, (size_t)m * 4, hipMemcpyDeviceToHost));
     }
     int64_t k = 0;
     for (uint32_t i = 0; i < m; ++i) {
@@ -1182,6 +1247,7 @@ hgs_status hgs_autotune(hgs_ctx* c, void* stream, const char* cache_path, int32_
             (st = hgs_set_option(c, HGS_OPT_PERSISTENT, best.persistent)) ||
             (st = hgs_set_option(c, HGS_OPT_SORT_DIGIT_BITS, best.sort_digit_bits)))
             return st;
+        best.lanes = c->lanes;
         best.from_cache = 1;
         if (out) *out = best;
         return HGS_OK;
@@ -1236,7 +1302,7 @@ hgs_status hgs_autotune(hgs_ctx* c, void* stream, const char* cache_path, int32_
         restore();
         return st;
     }
-    best = hgs_plan{256, 0, 8, 0, ms_default, ms_default};
+    best = hgs_plan{256, 0, 8, 0, ms_default, ms_default, c->lanes, 0};
     const int batches[3] = {64, 128, 256};
     for (int b : batches)
         for (int pers = 0; pers < 2; ++pers) {
@@ -1266,8 +1332,8 @@ hgs_status hgs_autotune(hgs_ctx* c, void* stream, const char* cache_path, int32_
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(c, HGS_E_INVALID, "cannot append to plan cache %s", cache_path);
-        std::fprintf(f, "%s %d %d %d %.6f %.6f\n", key.c_str(), best.batch_depth, best.persistent,
-                     best.sort_digit_bits, best.ms, best.ms_default);
+        std::fprintf(f, "%s %d %d %d %.6f %.6f %d\n", key.c_str(), best.batch_depth, best.persistent,
+                     best.sort_digit_bits, best.ms, best.ms_default, best.lanes);
         std::fclose(f);
     }
     if (out) *out = best;
@@ -1283,7 +1349,7 @@ hgs_status hgs_sort_pairs(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* va
     hipStream_t s = (hipStream_t)stream;
     hgs_status st;
     if ((st = ensure(c, c->sort_k, (size_t)n * 4)) || (st = ensure(c, c->sort_v, (size_t)n * 4)) ||
-        (st = ensure(c, c->sort_n, 4)) || (st = ensure(c, c->hist, (size_t)kSortBins * (kSortBlocks + 1) * 4)))
+        (st = ensure(c, c->sort_n, 4)) || (st = ensure(c, c->w[0].hist, (size_t)kSortBins * (kSortBlocks + 1) * 4)))
         return st;
     const uint32_t nn = (uint32_t)n;
     HIP_TRY(c, hipMemcpyAsync(c->sort_n.p, &nn, 4, hipMemcpyHostToDevice, s));
@@ -1296,7 +1362,7 @@ hgs_status hgs_sort_pairs(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* va
     a.cap = nn;
     a.key_bits = key_bits;
     a.max_digit_bits = c->sort_digit_bits;
-    a.hist = P<uint32_t>(c->hist);
+    a.hist = P<uint32_t>(c->w[0].hist);
     const int r = launch_sort(a, s);
     if (r == 1) {
         HIP_TRY(c, hipMemcpyAsync(keys, a.keys[1], (size_t)n * 4, hipMemcpyDeviceToDevice, s));
@@ -1353,13 +1419,13 @@ hgs_status hgs_lod_candidates(hgs_ctx* c, void* stream, float s_hi, uint32_t* en
         ca.flat = false;
         ca.views = P<ViewDev>(c->views);
         ca.n_views = (int)c->cams.size();
-        ca.frontier[0] = P<uint2>(c->frontier[0]);
-        ca.frontier[1] = P<uint2>(c->frontier[1]);
+        ca.frontier[0] = P<uint2>(c->w[0].frontier[0]);
+        ca.frontier[1] = P<uint2>(c->w[0].frontier[1]);
         ca.frontier_cap = c->frontier_cap;
-        ca.cut = P<uint2>(c->cut);
+        ca.cut = P<uint2>(c->w[0].cut);
         ca.cut_cap = c->cut_cap;
-        ca.scan_tmp = P<uint4>(c->scan_tmp);
-        ca.dec = P<uint8_t>(c->dec);
+        ca.scan_tmp = P<uint4>(c->w[0].scan_tmp);
+        ca.dec = P<uint8_t>(c->w[0].dec);
         ca.ctr = ctr;
         ca.mlp = nullptr;
         ca.s_hi = s_hi;
@@ -1688,17 +1754,18 @@ hgs_status hgs_render_backward(hgs_ctx* c, void* stream, const hgs_image_grad* g
     HIP_TRY(c, hipMemcpyAsync(c->dimg.p, c->dimg_host, (size_t)nv * sizeof(ImgGrad), hipMemcpyHostToDevice, st));
     HIP_TRY(c, hipEventRecord(c->dimg_copied, st));
     BwdArgs b{};
-    b.vals = P<uint32_t>(c->pval[c->last_pair_buf]);
+    Work& W = c->w[c->last_lane];
+    b.vals = P<uint32_t>(W.pval[c->last_pair_buf]);
     b.ranges = P<uint2>(c->ranges);
     b.total_tiles = pass_tile0(c, 1) - pass_tile0(c, 0);
-    b.proj = P<Proj>(c->proj);
+    b.proj = P<Proj>(W.proj);
     b.cut_cap = c->cut_cap;
     b.views = P<ViewDev>(c->views);
     b.tile_view = P<uint32_t>(c->tile_view);
     b.dimg = P<ImgGrad>(c->dimg);
     b.egrad = P<float>(c->egrad);
     ProjBwdArgs p{};
-    p.cut = P<uint2>(c->cut);
+    p.cut = P<uint2>(W.cut);
     p.cut_cap = c->cut_cap;
     p.geo = P<float4>(c->geo);
     p.sh = P<float>(c->sh);
@@ -1709,15 +1776,15 @@ hgs_status hgs_render_backward(hgs_ctx* c, void* stream, const hgs_image_grad* g
     p.ctr = P<Counters>(c->counters);
     p.rec = P<float>(c->brec);
     SortArgs sa{};
-    sa.keys[0] = P<uint32_t>(c->dkey[0]);
-    sa.keys[1] = P<uint32_t>(c->dkey[1]);
-    sa.vals[0] = P<uint32_t>(c->dval[0]);
-    sa.vals[1] = P<uint32_t>(c->dval[1]);
+    sa.keys[0] = P<uint32_t>(W.dkey[0]);
+    sa.keys[1] = P<uint32_t>(W.dkey[1]);
+    sa.vals[0] = P<uint32_t>(W.dval[0]);
+    sa.vals[1] = P<uint32_t>(W.dval[1]);
     sa.count = &p.ctr->cut;
     sa.cap = c->cut_cap;
     sa.key_bits = bits_for((uint32_t)c->n);
     sa.max_digit_bits = c->sort_digit_bits;
-    sa.hist = P<uint32_t>(c->hist);
+    sa.hist = P<uint32_t>(W.hist);
     GatherArgs ga{};
     ga.cap = c->cut_cap;
     ga.ctr = p.ctr;

@@ -39,6 +39,7 @@ HGS_OPT_STAGE_TIMING = 9
 HGS_OPT_SORT_DIGIT_BITS = 10
 HGS_OPT_PASS_VIEWS = 11
 HGS_OPT_LOD_BLEND = 12
+HGS_OPT_LANES = 13
 
 PROJECTED_FIELDS = ("u", "v", "A", "B", "C", "r", "g", "b", "depth", "opacity", "ntiles", "valid")
 
@@ -97,7 +98,8 @@ class hgs_scene_grad(ctypes.Structure):
 
 class hgs_plan(ctypes.Structure):
     _fields_ = [("batch_depth", ctypes.c_int32), ("persistent", ctypes.c_int32), ("sort_digit_bits", ctypes.c_int32),
-                ("from_cache", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
+                ("from_cache", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double),
+                ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 # (name, restype, argtypes) of every exported entry point

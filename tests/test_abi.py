@@ -52,7 +52,7 @@ def test_plan_struct_matches_header_fields():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = [n.strip() for n in re.findall(r"(?:int32_t|double) ([^;]+);", body)]
     assert [n for n, _ in hgs.hgs_plan._fields_] == names
-    assert ctypes.sizeof(hgs.hgs_plan) == 4 * 4 + 2 * 8
+    assert ctypes.sizeof(hgs.hgs_plan) == 4 * 4 + 2 * 8 + 2 * 4
 
 
 def test_slice_grid_struct_matches_header():

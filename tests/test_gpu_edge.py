@@ -1,0 +1,98 @@
+"""Edge cases of the GPU path against the oracle: a single Gaussian, images
+of one pixel, one row, one column and exactly one tile, a Gaussian behind
+the camera, views batched with very different sizes, and the backward
+pass of a one-Gaussian scene."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import grad as G
+from oracle import oracle as O
+from paper_2603_15186_amd.synth import Scene, make_random_box, yaw_camera
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_15186_amd import hgs
+    r = hgs.Renderer(0)
+    yield r
+    r.close()
+
+
+def _one(o=0.7, at=(0.0, 0.0, 0.0), scale=0.05):
+    sh = np.array([[0.4, -0.2, 0.1]], np.float32)
+    return Scene(np.array([at], np.float32), np.full((1, 3), scale, np.float32),
+                 np.array([[0.9, 0.1, -0.2, 0.3]], np.float32), np.array([o], np.float32), sh, 0)
+
+
+def _check(R, scene, cams):
+    R.load_scene(scene)
+    R.set_cameras(cams)
+    outs = R.render()
+    torch.cuda.synchronize()
+    for cam, (rgb, dep, alp) in zip(cams, outs):
+        res, _, _ = O.render(scene, cam)
+        g = parity.gpu_pixels(rgb.cpu().numpy(), dep.cpu().numpy(), alp.cpu().numpy(), res.px, res.py)
+        ok, best, skipped = parity.branch_errors(g, res)
+        assert ok.all(), (cam.width, cam.height, parity.summary(ok, best, skipped))
+
+
+@pytest.mark.parametrize("W_,H_", [(1, 1), (1, 40), (40, 1), (16, 16), (17, 33)])
+def test_single_gaussian_tiny_images(R, W_, H_):
+    """One Gaussian seen from 2 m, the principal point at the image centre:
+    it covers the centre of every image size."""
+    cam = yaw_camera(W_, H_, 30.0, (0.0, -2.0, 0.0), math.pi / 2, bg=(0.2, 0.3, 0.4))
+    _check(R, _one(), [cam])
+
+
+def test_gaussian_behind_the_camera_leaves_background(R):
+    cam = yaw_camera(24, 16, 20.0, (0.0, -2.0, 0.0), -math.pi / 2, bg=(0.5, 0.25, 0.125))
+    scene = _one()
+    R.load_scene(scene)
+    R.set_cameras([cam])
+    rgb, dep, alp = (t.cpu().numpy() for t in R.render()[0])
+    assert np.all(alp == 0) and np.all(dep == 0)
+    np.testing.assert_array_equal(rgb[:, 0, 0], np.array([0.5, 0.25, 0.125], np.float32))
+    _check(R, scene, [cam])
+
+
+def test_batch_of_very_different_views(R):
+    scene = make_random_box(3000, seed=11, box=(2.0, 2.0, 2.0))
+    cams = [yaw_camera(1, 1, 1.0, (1.0, -1.0, 1.0), math.pi / 2),
+            yaw_camera(300, 200, 250.0, (1.0, -1.5, 1.0), math.pi / 2),
+            yaw_camera(16, 48, 20.0, (3.0, 1.0, 1.0), math.pi),
+            yaw_camera(47, 3, 40.0, (1.0, 1.0, 1.0), 0.3)]
+    _check(R, scene, cams)
+
+
+def test_backward_of_one_gaussian(R):
+    scene = _one(o=0.6)
+    cam = yaw_camera(20, 14, 24.0, (0.0, -2.0, 0.0), math.pi / 2)
+    rng = np.random.default_rng(1)
+    P = cam.width * cam.height
+    g = [rng.normal(size=(P, 3)), rng.normal(size=P), rng.normal(size=P)]
+    g = [a.astype(np.float32).astype(np.float64) for a in g]
+    res, _, _ = O.render(scene, cam)
+    assert (res.flags == 0).all()
+    want, _ = G.gradients(scene, cam, *g)
+    R.load_scene(scene)
+    R.set_cameras([cam])
+    R.render()
+    got = R.backward([(torch.from_numpy(np.ascontiguousarray(g[0].T.reshape(3, cam.height, cam.width),
+                                                             dtype=np.float32)).cuda(),
+                       torch.from_numpy(g[1].reshape(cam.height, cam.width).astype(np.float32)).cuda(),
+                       torch.from_numpy(g[2].reshape(cam.height, cam.width).astype(np.float32)).cuda())])
+    torch.cuda.synchronize()
+    # the Gaussian is isotropic: its rotation gradient is rounding noise on
+    # both sides, so the absolute floor comes from the largest gradient
+    top = max(np.abs(w).max() for w in want.values())
+    for k, w in want.items():
+        gk = got[k].cpu().numpy().astype(np.float64).reshape(w.shape)
+        np.testing.assert_allclose(gk, w, rtol=1e-4, atol=5e-5 * top, err_msg=k)

@@ -268,6 +268,39 @@ def test_multi_pass_batches_equal_one_pass(R, plan_small):
         R.set_option(hgs.HGS_OPT_PASS_VIEWS, 0)
 
 
+def test_two_lanes_give_identical_images(R, plan_small):
+    """Passes alternating between two work sets and two streams give the
+    one-lane images bitwise, eagerly and replayed from a captured graph; the
+    last pass's intermediates stay readable."""
+    scene, cams = plan_small
+    hgs = _hgs()
+    views = [_small_cam(cams[1], 320, 240), _small_cam(cams[4], 128, 72), cams[7], _small_cam(cams[9], 33, 17),
+             _small_cam(cams[2], 200, 117)]
+    one = _render(R, scene, views)
+    try:
+        R.set_option(hgs.HGS_OPT_LANES, 2)
+        for pv in (0, 1):
+            got = _render(R, scene, views, pass_views=pv)
+            assert R.stats()["passes"] >= 2
+            for v in range(len(views)):
+                for a, b in zip(one[v], got[v]):
+                    assert np.array_equal(a, b), (pv, v)
+        last = len(views) - 1
+        assert np.array_equal(R.get_cut(last), O.cut(scene, views[last], O.MODE_THRESHOLD, 1.0))
+        outs = R.alloc_outputs()
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
+        for rep in range(3):
+            R.render(outs)
+            torch.cuda.synchronize()
+            for v in range(len(views)):
+                for a, b in zip(one[v], outs[v]):
+                    assert np.array_equal(a, b.cpu().numpy()), (rep, v)
+    finally:
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+        R.set_option(hgs.HGS_OPT_PASS_VIEWS, 0)
+        R.set_option(hgs.HGS_OPT_LANES, 1)
+
+
 def test_autotune_keeps_images_and_caches_the_plan(R, plan_small, tmp_path):
     """The autotuner's plan renders the same images bitwise; a second call
     with the same cache file applies the stored plan without timing."""
@@ -289,13 +322,15 @@ def test_autotune_keeps_images_and_caches_the_plan(R, plan_small, tmp_path):
                 assert np.array_equal(a, b.cpu().numpy()), v
         again = R.autotune(cache, reps=2)
         assert again["from_cache"] == 1
-        assert (again["batch_depth"], again["persistent"], again["sort_digit_bits"]) == \
-            (plan["batch_depth"], plan["persistent"], plan["sort_digit_bits"])
+        assert (again["batch_depth"], again["persistent"], again["sort_digit_bits"], again["lanes"]) == \
+            (plan["batch_depth"], plan["persistent"], plan["sort_digit_bits"], plan["lanes"])
+        assert plan["lanes"] in (1, 2)
         assert len(cache.read_text().splitlines()) == 1
     finally:
         R.set_option(hgs.HGS_OPT_BATCH_DEPTH, 256)
         R.set_option(hgs.HGS_OPT_PERSISTENT, 0)
         R.set_option(hgs.HGS_OPT_SORT_DIGIT_BITS, 8)
+        R.set_option(hgs.HGS_OPT_LANES, 1)
 
 
 # ---------------------------------------------------------- full-size scene
