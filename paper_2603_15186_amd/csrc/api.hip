@@ -98,7 +98,7 @@ struct hgs_ctx {
     double acc_ms[5] = {0, 0, 0, 0, 0};
     int64_t acc_n = 0;
     // sort scratch for hgs_sort_pairs
-    DevMem sort_k, sort_v, sort_n;
+    DevMem sort_k, sort_v, sort_n, sort_hist;
     // distance-field scratch: goals, tile flags, per-round change counts
     DevMem nav_goals, nav_flags, nav_active, nav_steps;
     // backward pass: per-entry gradients and per-view image gradients; the
@@ -282,7 +282,7 @@ hgs_status alloc_work(hgs_ctx* c) {
         if ((s = ensure(c, w.bins, M * sizeof(BinRec)))) return s;
         if ((s = ensure(c, w.offsets, M * 4))) return s;
         if ((s = ensure(c, w.scan_tmp, (kScanBlocks + 1) * sizeof(uint4)))) return s;
-        if ((s = ensure(c, w.hist, (size_t)kSortBins * (kSortBlocks + 1) * 4))) return s;
+        if ((s = ensure(c, w.hist, sort_hist_bytes((uint32_t)std::max(M, Pc))))) return s;
     }
     return HGS_OK;
 }
@@ -727,7 +727,7 @@ void hgs_destroy(hgs_ctx* c) {
     DevMem* all[] = {&c->geo, &c->sh, &c->bound, &c->child, &c->leaf_ids, &c->parent, &c->nodefeat, &c->lvl,
                      &c->train_scratch, &c->region_dev, &c->surf, &c->views,
                      &c->tile_view, &c->mlp_w, &c->mlp_w32, &c->mlp_dev, &c->ranges,
-                     &c->counters, &c->sort_k, &c->sort_v, &c->sort_n, &c->nav_goals, &c->nav_flags,
+                     &c->counters, &c->sort_k, &c->sort_v, &c->sort_n, &c->sort_hist, &c->nav_goals, &c->nav_flags,
                      &c->nav_active, &c->nav_steps, &c->egrad, &c->dimg, &c->brec};
     for (DevMem* m : all) release(*m);
     for (Work& w : c->w) release_work(w);
@@ -1349,7 +1349,7 @@ hgs_status hgs_sort_pairs(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* va
     hipStream_t s = (hipStream_t)stream;
     hgs_status st;
     if ((st = ensure(c, c->sort_k, (size_t)n * 4)) || (st = ensure(c, c->sort_v, (size_t)n * 4)) ||
-        (st = ensure(c, c->sort_n, 4)) || (st = ensure(c, c->w[0].hist, (size_t)kSortBins * (kSortBlocks + 1) * 4)))
+        (st = ensure(c, c->sort_n, 4)) || (st = ensure(c, c->sort_hist, sort_hist_bytes((uint32_t)n))))
         return st;
     const uint32_t nn = (uint32_t)n;
     HIP_TRY(c, hipMemcpyAsync(c->sort_n.p, &nn, 4, hipMemcpyHostToDevice, s));
@@ -1362,7 +1362,7 @@ hgs_status hgs_sort_pairs(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* va
     a.cap = nn;
     a.key_bits = key_bits;
     a.max_digit_bits = c->sort_digit_bits;
-    a.hist = P<uint32_t>(c->w[0].hist);
+    a.hist = P<uint32_t>(c->sort_hist);
     const int r = launch_sort(a, s);
     if (r == 1) {
         HIP_TRY(c, hipMemcpyAsync(keys, a.keys[1], (size_t)n * 4, hipMemcpyDeviceToDevice, s));

@@ -170,14 +170,15 @@ __global__ __launch_bounds__(kNT) void k_composite_bwd(BwdArgs a) {
             const float t1 = fmaf(A.p, fx, fmaf(A.r, fy, A.c1));
             const float t2 = fmaf(A.s, fy, B.c2);
             const float q = fmaf(t1, t1, t2 * t2);
-            const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, B.lo)));
-            const float al = (q <= kQMax && live && al0 >= 1.f / 255.f) ? al0 : 0.f;
-            const float Tn = T * (1.f - al);
-            if (live && Tn < 1e-4f) {
+            const float x = fmaf(q, kNegHalfLog2e, B.lo);
+            const float al = fminf(0.99f, __builtin_amdgcn_exp2f(x));
+            const float Tn = T - al * T;
+            const bool add = live && q <= kQMax && x >= kLog2AlphaMin;
+            if (add && Tn < 1e-4f) {
                 live = false;
                 last = b0 + off / 16;
             }
-            T = live ? Tn : T;
+            T = add && live ? Tn : T;
             if ((p & 3u) == 3u && __ballot(live) == 0) break;
         }
         if (__syncthreads_count(live ? 1 : 0) == 0) break;
@@ -223,8 +224,9 @@ __global__ __launch_bounds__(kNT) void k_composite_bwd(BwdArgs a) {
                 const float t1 = fmaf(A.p, fx, fmaf(A.r, fy, A.c1));
                 const float t2 = fmaf(A.s, fy, B.c2);
                 const float q = fmaf(t1, t1, t2 * t2);
-                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, B.lo)));
-                const float al = (q <= kQMax && al0 >= 1.f / 255.f) ? al0 : 0.f;
+                const float x = fmaf(q, kNegHalfLog2e, B.lo);
+                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(x));
+                const float al = (q <= kQMax && x >= kLog2AlphaMin) ? al0 : 0.f;
                 if (al > 0.f) {
                     has = true;
                     const float iom = __builtin_amdgcn_rcpf(1.f - al);

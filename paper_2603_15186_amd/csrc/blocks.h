@@ -15,6 +15,8 @@ constexpr int kBlocks = 16;                 // 4x4-pixel blocks per tile
 constexpr float kQMax = 9.f;
 constexpr float kQMask = 9.f * 1.001f;      // bound used to mark blocks
 
+constexpr float kLog2AlphaMin = -7.99435343685885793f;   // log2(1/255)
+
 // One staged Gaussian: t1 = p x + r y + c1, t2 = s y + c2 over tile-relative
 // pixel centres (x, y); lo = log2(opacity).
 struct alignas(16) StageA { float p, r, c1, s; };

@@ -15,9 +15,10 @@
 //     with a record that contributes nothing.  The body has no branches:
 //       q = t1^2 + t2^2 with t1 = p dx + r dy = p x + r y + c1 and
 //           t2 = s dy = s y + c2 around the tile origin;
-//       alpha = min(0.99, 2^(log2(o) - q log2(e)/2)) = min(0.99, o e^(-q/2)),
-//           replaced by 0 unless q <= 9, alpha >= 1/255 and the pixel is live;
-//       T' = T (1 - alpha); if T' < 1e-4 the pixel stops without adding,
+//       x = log2(o) - q log2(e)/2, alpha = min(0.99, 2^x) = min(0.99, o e^(-q/2));
+//       the entry adds only to a live pixel with q <= 9 and x >= log2(1/255)
+//       (alpha >= 1/255, the cap 0.99 lying above it);
+//       T' = T - alpha T; if T' < 1e-4 the pixel stops without adding,
 //       else C += c alpha T, D += z alpha T, T = T'.
 // A wave leaves its lists once a ballot shows all its pixels stopped, the
 // workgroup once a barrier count does.  This is plain FP32 vector arithmetic,
@@ -156,19 +157,21 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
                 const float t1 = fmaf(A.p, fx, fmaf(A.r, fy, A.c1));
                 const float t2 = fmaf(A.s, fy, B.c2);
                 const float q = fmaf(t1, t1, t2 * t2);
-                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, B.lo)));
-                const bool in = q <= kQMax;
-                if (COUNT) nalg += (live && in && i + u < n_mine) ? 1u : 0u;
-                const float al = (in && live && al0 >= 1.f / 255.f) ? al0 : 0.f;
-                const float Tn = T * (1.f - al);
-                const bool stop = Tn < 1e-4f;
-                const float wgt = stop ? 0.f : al * T;
+                const float x = fmaf(q, kNegHalfLog2e, B.lo);
+                const float al = fminf(0.99f, __builtin_amdgcn_exp2f(x));
+                if (COUNT) nalg += (live && q <= kQMax && i + u < n_mine) ? 1u : 0u;
+                const float w0 = al * T;
+                const float Tn = T - w0;
+                const bool add = live && q <= kQMax && x >= kLog2AlphaMin;
+                const bool keep = Tn >= 1e-4f;
+                const bool take = add && keep;
+                const float wgt = take ? w0 : 0.f;
                 C0 = fmaf(wgt, B.col0, C0);
                 C1 = fmaf(wgt, Cc.col1, C1);
                 C2 = fmaf(wgt, Cc.col2, C2);
                 D = fmaf(wgt, B.z, D);
-                T = stop ? T : Tn;
-                live = live && !stop;
+                T = take ? Tn : T;
+                live = live && (keep || !add);
             }
             if (__ballot(live) == 0) break;
         }
@@ -216,8 +219,10 @@ struct Shared {
     uint32_t tile;
 };
 
+// Register budget for seven waves per SIMD (the LDS of seven 256-entry
+// workgroups fits a CU): the staging gathers need that many to hide.
 template <int BATCH, bool COUNT>
-__global__ __launch_bounds__(kNT) void k_composite(CompositeArgs a) {
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(7))) void k_composite(CompositeArgs a) {
     __shared__ Shared<BATCH> sh;
     composite_tile<BATCH, COUNT>(a, blockIdx.x, sh.a, sh.b, sh.c, sh.idx, sh.wc, sh.n, sh.red);
 }
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(kNT) void k_composite(CompositeArgs a) {
 // Persistent variant: a fixed grid takes tiles from a global counter until
 // the counter passes the last tile (every workgroup reaches that exit).
 template <int BATCH, bool COUNT>
-__global__ __launch_bounds__(kNT) void k_composite_persistent(CompositeArgs a) {
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(7))) void k_composite_persistent(CompositeArgs a) {
     __shared__ Shared<BATCH> sh;
     for (;;) {
         if (threadIdx.x == 0) sh.tile = atomicAdd(&a.ctr->tile_queue, 1u);
