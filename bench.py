@@ -702,6 +702,8 @@ def main():
     single = eval_cams[:args.single]
     px1 = single[0].width * single[0].height
     ms_t1 = ms_tm = ms_single = ms_blend = ms_bwd = ms_lanes2 = float("nan")
+    if args.quick and args.with_backward:
+        ms_bwd = ms_bwd_q
     plan2 = None
     if not args.quick:
         # batched threshold cuts

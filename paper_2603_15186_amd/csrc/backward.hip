@@ -39,7 +39,7 @@ namespace hgs {
 namespace {
 
 constexpr int kNT = kTilePx;
-constexpr int kB = 256;                         // entries staged per batch
+constexpr int kB = 128;                         // entries staged per batch
 constexpr float kNegHalfLog2e = -0.72134752044448170f;
 constexpr int kNG = 10;                         // per-entry gradient numbers
 
@@ -127,7 +127,10 @@ __device__ __forceinline__ float group_sum(float x) {
     return x;
 }
 
-__global__ __launch_bounds__(kNT) void k_composite_bwd(BwdArgs a) {
+// Batches of 128 entries and a register budget of eight waves per SIMD: the
+// reverse walk is a chain of row reductions and LDS adds whose latency only
+// more resident waves hide.
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(8))) void k_composite_bwd(BwdArgs a) {
     __shared__ BwdShared S;
     const uint32_t tile = blockIdx.x;
     const uint32_t view = a.tile_view[tile];

@@ -219,10 +219,11 @@ struct Shared {
     uint32_t tile;
 };
 
-// Register budget for seven waves per SIMD (the LDS of seven 256-entry
-// workgroups fits a CU): the staging gathers need that many to hide.
+// Register budget for as many waves per SIMD as the LDS allows (seven
+// 256-entry workgroups or eight smaller ones per CU): the staging gathers
+// need that many to hide.
 template <int BATCH, bool COUNT>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(7))) void k_composite(CompositeArgs a) {
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(BATCH > 128 ? 7 : 8))) void k_composite(CompositeArgs a) {
     __shared__ Shared<BATCH> sh;
     composite_tile<BATCH, COUNT>(a, blockIdx.x, sh.a, sh.b, sh.c, sh.idx, sh.wc, sh.n, sh.red);
 }
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(7))) void k
 // Persistent variant: a fixed grid takes tiles from a global counter until
 // the counter passes the last tile (every workgroup reaches that exit).
 template <int BATCH, bool COUNT>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(7))) void k_composite_persistent(CompositeArgs a) {
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(BATCH > 128 ? 7 : 8))) void k_composite_persistent(CompositeArgs a) {
     __shared__ Shared<BATCH> sh;
     for (;;) {
         if (threadIdx.x == 0) sh.tile = atomicAdd(&a.ctr->tile_queue, 1u);
