@@ -282,7 +282,7 @@ hgs_status alloc_work(hgs_ctx* c) {
         if ((s = ensure(c, w.bins, M * sizeof(BinRec)))) return s;
         if ((s = ensure(c, w.offsets, M * 4))) return s;
         if ((s = ensure(c, w.scan_tmp, (kScanBlocks + 1) * sizeof(uint4)))) return s;
-        if ((s = ensure(c, w.hist, sort_hist_bytes((uint32_t)std::max(M, Pc))))) return s;
+        if ((s = ensure(c, w.hist, kSortHistBytes))) return s;
     }
     return HGS_OK;
 }
@@ -1349,7 +1349,7 @@ hgs_status hgs_sort_pairs(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* va
     hipStream_t s = (hipStream_t)stream;
     hgs_status st;
     if ((st = ensure(c, c->sort_k, (size_t)n * 4)) || (st = ensure(c, c->sort_v, (size_t)n * 4)) ||
-        (st = ensure(c, c->sort_n, 4)) || (st = ensure(c, c->sort_hist, sort_hist_bytes((uint32_t)n))))
+        (st = ensure(c, c->sort_n, 4)) || (st = ensure(c, c->sort_hist, kSortHistBytes)))
         return st;
     const uint32_t nn = (uint32_t)n;
     HIP_TRY(c, hipMemcpyAsync(c->sort_n.p, &nn, 4, hipMemcpyHostToDevice, s));

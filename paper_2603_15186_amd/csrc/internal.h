@@ -105,12 +105,10 @@ struct RenderOpts {
 constexpr int kScanBlocks = 1024;
 constexpr int kSortBlocks = 1024;
 constexpr int kSortBins = 2048;          // widest radix digit: 11 bits
-constexpr int kSortGroup = 8192;         // elements per histogram group of the radix sort
-
-// Histogram groups of a sort over at most cap elements, and the bytes of its
-// histogram buffer (per-group counts of every digit, then digit totals).
-inline uint32_t sort_groups(uint32_t cap) { return (cap + (uint32_t)kSortGroup - 1) / (uint32_t)kSortGroup; }
-inline size_t sort_hist_bytes(uint32_t cap) { return (size_t)kSortBins * ((size_t)sort_groups(cap) + 1) * 4; }
+constexpr int kSortGroup = 8192;         // histogram groups of the radix sort: multiples of this size,
+constexpr int kSortMaxGroups = 8192;     // at most this many groups per sort
+// histogram buffer: per-group counts of every digit, then the digit totals
+constexpr size_t kSortHistBytes = (size_t)kSortBins * (kSortMaxGroups + 1) * 4;
 
 // Threshold / all-leaves / flat cut for all views.  Writes (node, view)
 // entries to `cut` and the count to ctr->cut.
@@ -200,7 +198,7 @@ struct SortArgs {
     uint32_t cap;
     int key_bits;
     int max_digit_bits = 11;         // 6..11
-    uint32_t* hist;                  // sort_hist_bytes(cap)
+    uint32_t* hist;                  // kSortHistBytes
 };
 int launch_sort(const SortArgs& a, hipStream_t s);
 

@@ -3,8 +3,9 @@
 // A sort over `bits` key bits runs ceil(bits / D) passes with digits of
 // ceil(bits / passes) bits, D the widest digit allowed (6..11: up to 2048
 // buckets), so a 17-bit tile key takes two or three passes and a 32-bit depth
-// key three to six.  The input is cut into groups of kSortGroup elements; a
-// workgroup takes groups b, b + G, b + 2G, ... so that the groups in flight
+// key three to six.  The input is cut into at most kSortMaxGroups groups, each
+// the smallest multiple of kSortGroup elements that keeps their number in that
+// bound; a workgroup takes groups b, b + G, b + 2G, ... so that the groups in flight
 // at any moment form one contiguous window of the input and each digit's
 // output advances as one front (writes of neighbouring groups land next to
 // each other and fill whole cache lines).  Each pass is three launches with
@@ -34,6 +35,13 @@ __device__ __forceinline__ uint32_t n_of(const uint32_t* count, uint32_t cap) {
     return n < cap ? n : cap;
 }
 
+// Elements per histogram group of an n-element sort (a multiple of
+// kSortGroup; at most kSortMaxGroups groups).
+__device__ __forceinline__ uint32_t group_size(uint32_t n) {
+    const uint32_t per = ceil_div(n, (uint32_t)kSortGroup * (uint32_t)kSortMaxGroups);
+    return (per > 1u ? per : 1u) * (uint32_t)kSortGroup;
+}
+
 // Lanes of the wave (among `active`) whose DB-bit digit equals this lane's.
 template <int DB>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
@@ -60,15 +68,15 @@ __global__ __launch_bounds__(kNT) void k_upsweep(const uint32_t* __restrict__ ke
     const int t = threadIdx.x;
     uint32_t* hw = h[t / kWave];
     const uint32_t n = n_of(count, cap);
-    const uint32_t ng = ceil_div(n, (uint32_t)kSortGroup);
+    const uint32_t gs = group_size(n), ng = ceil_div(n, gs);
     for (uint32_t g = blockIdx.x; g < ng; g += gridDim.x) {
         for (int i = t; i < NB; i += kNT) {
 #pragma unroll
             for (int w = 0; w < kNW; ++w) h[w][i] = 0;
         }
         __syncthreads();
-        const uint32_t lo = g * (uint32_t)kSortGroup;
-        const uint32_t hi = min(lo + (uint32_t)kSortGroup, n);
+        const uint32_t lo = g * gs;
+        const uint32_t hi = min(lo + gs, n);
         uint32_t base = lo;
         for (; base + 4 * kNT <= hi; base += 4 * kNT) {
             const uint4 k4 = *reinterpret_cast<const uint4*>(keys + base + 4 * t);
@@ -95,7 +103,8 @@ __global__ __launch_bounds__(1024) void k_rowscan(uint32_t* __restrict__ hist, c
                                                   uint32_t stride, uint32_t* __restrict__ totals) {
     __shared__ uint32_t sh[1024 / kWave + 1];
     const int d = blockIdx.x, t = threadIdx.x;
-    const uint32_t ng = ceil_div(n_of(count, cap), (uint32_t)kSortGroup);
+    const uint32_t n = n_of(count, cap);
+    const uint32_t ng = ceil_div(n, group_size(n));
     uint32_t* row = hist + (size_t)d * stride;
     uint32_t run = 0;
     for (uint32_t base = 0; base < ng; base += 1024) {
@@ -133,7 +142,7 @@ __global__ __launch_bounds__(kNT) void k_downsweep(const uint32_t* __restrict__ 
     const int t = threadIdx.x;
     const int w = t / kWave, l = lane_id();
     const uint32_t n = n_of(count, cap);
-    const uint32_t ng = ceil_div(n, (uint32_t)kSortGroup);
+    const uint32_t gs = group_size(n), ng = ceil_div(n, gs);
     if (blockIdx.x >= ng) return;
     {
         uint32_t mine[PER];
@@ -156,8 +165,8 @@ __global__ __launch_bounds__(kNT) void k_downsweep(const uint32_t* __restrict__ 
     for (uint32_t g = blockIdx.x; g < ng; g += gridDim.x) {
         __syncthreads();
         for (int d = t; d < NB; d += kNT) s_off[d] = s_start[d] + hist[(size_t)d * stride + g];
-        const uint32_t lo = g * (uint32_t)kSortGroup;
-        const uint32_t hi = min(lo + (uint32_t)kSortGroup, n);
+        const uint32_t lo = g * gs;
+        const uint32_t hi = min(lo + gs, n);
         for (uint32_t base = lo; base < hi; base += SUB) {
             for (int i = t; i < NB; i += kNT) {
 #pragma unroll
@@ -255,7 +264,7 @@ __global__ __launch_bounds__(kNT) void k_downsweep(const uint32_t* __restrict__ 
 template <int DB>
 void pass(const SortArgs& a, int cur, int shift, int nbits, hipStream_t s) {
     const int G = kSortBlocks;
-    const uint32_t stride = sort_groups(a.cap);
+    const uint32_t stride = kSortMaxGroups;
     uint32_t* hist = a.hist;
     uint32_t* totals = a.hist + (size_t)kSortBins * stride;
     const uint32_t mask = nbits >= 32 ? 0xffffffffu : ((1u << nbits) - 1u);

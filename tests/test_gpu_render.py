@@ -60,13 +60,15 @@ def _check_full(img, scene, cam, mode=O.MODE_THRESHOLD, tau=1.0, ids=None, max_s
 
 # ------------------------------------------------------------------ sort
 
-# sizes around the 8192-element histogram groups, and past 1024 groups (a
-# workgroup then owns several groups)
+# sizes around the 8192-element histogram groups, past 1024 groups (a
+# workgroup then owns several groups) and past 8192 * 8192 elements (groups
+# then grow to keep at most 8192)
 @pytest.mark.parametrize("n,bits,digit", [(1, 8, 11), (1000, 8, 8), (300001, 12, 11), (300001, 12, 6),
                                           (300001, 19, 11), (300001, 19, 8), (2_000_003, 32, 11),
                                           (2_000_003, 32, 8), (5_000_000, 17, 11), (5_000_000, 17, 9),
                                           (8191, 10, 9), (8192, 10, 9), (8193, 13, 6),
-                                          (8_388_608, 18, 6), (9_000_005, 18, 8), (9_000_005, 32, 10)])
+                                          (8_388_608, 18, 6), (9_000_005, 18, 8), (9_000_005, 32, 10),
+                                          (70_000_001, 18, 6)])
 def test_radix_sort_bit_exact(R, n, bits, digit):
     hgs = _hgs()
     rng = np.random.default_rng(n + bits)
