@@ -151,12 +151,14 @@ def timed_loop(r, hgs, torch, batches, outs, steps, warmup, stage_timing):
     return (t1 - t0) * 1e3 / steps, st
 
 
-def time_backward(r, hgs, torch, batches, outs, steps, lanes=1):
+def time_backward(r, hgs, torch, batches, outs, steps, lanes=1, keep=True):
     """ms per backward pass of a batch: each step renders a batch (untimed
-    part of the stream) and runs the backward pass with fixed random image
-    gradients; only the backward is inside the HIP events."""
+    part of the stream; with keep, keeping its pixel states for the backward
+    pass) and runs the backward pass with fixed random image gradients; only
+    the backward is inside the HIP events."""
     r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
     r.set_option(hgs.HGS_OPT_LANES, 1)          # the backward pass needs a one-pass render
+    r.set_option(hgs.HGS_OPT_KEEP_STATE, 1 if keep else 0)
     gen = torch.Generator(device="cuda").manual_seed(0)
     grads = [tuple(torch.randn(t.shape, generator=gen, device="cuda") for t in o) for o in outs]
     stream = torch.cuda.current_stream()
@@ -172,18 +174,20 @@ def time_backward(r, hgs, torch, batches, outs, steps, lanes=1):
         torch.cuda.synchronize()
         if i:                                   # the first one warms up
             total += e0.elapsed_time(e1)
+    r.set_option(hgs.HGS_OPT_KEEP_STATE, 0)
     r.set_option(hgs.HGS_OPT_LANES, lanes)
     r.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
     return total / steps
 
 
 # FP32 operations per evaluated (pixel, Gaussian) pair of the backward
-# compositing kernel, counted from its formulas (FMA = 2): the forward replay
-# (24, as the forward compositor) and the reverse step (64: q and alpha 13,
-# transmittance recovery 2, dL/dalpha 14, colour and depth gradients 4,
-# what-lies-behind updates 8, the conic and mean gradients 19, opacity 2,
-# rounded up to whole FMAs).
-FLOPS_PER_PAIR_BWD = 88
+# compositing kernel, counted from its formulas (FMA = 2): the reverse step
+# (64: q and alpha 13, transmittance recovery 2, dL/dalpha 14, colour and
+# depth gradients 4, what-lies-behind updates 8, the conic and mean gradients
+# 19, opacity 2, rounded up to whole FMAs).  The timed renders keep their
+# pixel states, so the kernel does not replay the forward walk (24 more
+# per pair when it does).
+FLOPS_PER_PAIR_BWD = 64
 
 
 def run_backward(args):
@@ -217,6 +221,8 @@ def run_backward(args):
         r.render(outs)
         n_alg.append(r.stats()["n_alg"])
     r.set_option(hgs.HGS_OPT_COUNT_NALG, 0)
+    # the renders keep their pixel states for the backward pass
+    r.set_option(hgs.HGS_OPT_KEEP_STATE, 1)
     acc = None
     for i in range(args.warmup):
         r.set_cameras(batches[i % len(batches)])
@@ -240,6 +246,9 @@ def run_backward(args):
     st = r.stats()
     r.set_option(hgs.HGS_OPT_STAGE_TIMING, 0)
     ms = total / args.steps
+    # for reference: the backward pass replaying the forward walk itself
+    r.set_option(hgs.HGS_OPT_KEEP_STATE, 0)
+    ms_replay = time_backward(r, hgs, torch, batches, outs, args.steps, keep=False)
     ms_comp = st["ms_bwd_composite"] / max(st["timed_backwards"], 1)
     achieved = FLOPS_PER_PAIR_BWD * (alg / args.steps) / (ms_comp * 1e-3) / 1e12
     log(f"backward {ms:.3f} ms per batch (compositing {ms_comp:.3f} ms), {px_per_step / ms / 1e3:.1f} Mpix/s")
@@ -274,14 +283,15 @@ def run_backward(args):
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "plan2m-lod 50 x 1280x720 held-out views, learned LOD cut, random image "
-                                  "gradients", "parallelism": "single GPU"},
+                                  "gradients", "kept_pixel_states": True, "parallelism": "single GPU"},
            "roofline": {"kernel": "k_composite_bwd", "bound": "alu", "achieved": achieved,
                         "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                         "traffic": None, "ms_per_launch": ms_comp, "n_alg_per_launch": alg / args.steps,
                         "flops_per_pair": FLOPS_PER_PAIR_BWD},
            "cpu_baseline": cpu,
            "extra": {"ms_backward_composite": ms_comp,
-                     "ms_backward_params": st["ms_bwd_total"] / max(st["timed_backwards"], 1) - ms_comp}}
+                     "ms_backward_params": st["ms_bwd_total"] / max(st["timed_backwards"], 1) - ms_comp,
+                     "ms_per_step_replaying_forward": ms_replay}}
     print(json.dumps(out), flush=True)
     r.close()
 

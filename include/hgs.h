@@ -90,6 +90,13 @@ typedef int32_t hgs_status;
                                      one whose parent spans 2 tau looks like
                                      itself.  Threshold and learned cuts of a
                                      hierarchy only; 0 (default): off. */
+#define HGS_OPT_KEEP_STATE 14     /* 1: every render also keeps, per pixel, where its
+                                     front-to-back walk stopped and its final
+                                     transmittance (8 bytes per pixel of the batch,
+                                     context-owned), so that hgs_render_backward
+                                     need not replay the forward walk; 0 (default):
+                                     not kept, the backward pass replays it.  Images
+                                     and gradients do not depend on it. */
 
 typedef struct hgs_ctx hgs_ctx;
 
@@ -413,8 +420,11 @@ hgs_status hgs_disc_collision(hgs_ctx* ctx, void* stream, const uint8_t* map, do
  * alpha capped at 0.99 or a colour channel clamped to [0, 1].  Run on the
  * render's stream after it; the render must have been one pass (no
  * HGS_OPT_PASS_VIEWS split) without HGS_OPT_LOD_BLEND (HGS_E_STATE,
- * HGS_E_UNSUPPORTED).  Asynchronous on `stream`; the summation order of the
- * atomic adds is not fixed, so results vary in the last bits. */
+ * HGS_E_UNSUPPORTED).  A render made with HGS_OPT_KEEP_STATE hands over each
+ * pixel's stop position and final transmittance; otherwise the backward pass
+ * replays the forward walk to find them.  Asynchronous on `stream`; the
+ * summation order of the atomic adds is not fixed, so results vary in the
+ * last bits. */
 typedef struct {
     const float* rgb;
     const float* depth;

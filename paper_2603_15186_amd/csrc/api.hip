@@ -99,6 +99,7 @@ struct hgs_ctx {
     int64_t acc_n = 0;
     // sort scratch for hgs_sort_pairs
     DevMem sort_k, sort_v, sort_n, sort_hist;
+    DevMem px_state;                  // per pixel of the last render: stop position, final T
     // distance-field scratch: goals, tile flags, per-round change counts
     DevMem nav_goals, nav_flags, nav_active, nav_steps;
     // backward pass: per-entry gradients and per-view image gradients; the
@@ -113,6 +114,7 @@ struct hgs_ctx {
     int last_pair_buf = 0;
     int last_lane = 0;
     bool last_blend = false;
+    bool last_keep = false;           // the last render kept its pixel states (px_state)
     uint32_t* nav_active_host = nullptr;   // pinned
 };
 
@@ -540,6 +542,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     c->last_pair_buf = pr;
     c->last_lane = lane_of(c, g);
     c->last_blend = pa.blend;
+    c->last_keep = c->ropts.keep_state;
 
     CompositeArgs xa{};
     xa.keys = pb.keys[pr];
@@ -554,6 +557,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     xa.n_views = ca.n_views;
     xa.opts = c->ropts;
     xa.ctr = ctr;
+    xa.state = c->ropts.keep_state ? P<uint2>(c->px_state) + (size_t)t0 * kTilePx : nullptr;
     launch_ranges(xa, s);
     mark(c, 4, s);
     launch_composite(xa, s);
@@ -727,7 +731,7 @@ void hgs_destroy(hgs_ctx* c) {
     DevMem* all[] = {&c->geo, &c->sh, &c->bound, &c->child, &c->leaf_ids, &c->parent, &c->nodefeat, &c->lvl,
                      &c->train_scratch, &c->region_dev, &c->surf, &c->views,
                      &c->tile_view, &c->mlp_w, &c->mlp_w32, &c->mlp_dev, &c->ranges,
-                     &c->counters, &c->sort_k, &c->sort_v, &c->sort_n, &c->sort_hist, &c->nav_goals, &c->nav_flags,
+                     &c->counters, &c->sort_k, &c->sort_v, &c->sort_n, &c->sort_hist, &c->px_state, &c->nav_goals, &c->nav_flags,
                      &c->nav_active, &c->nav_steps, &c->egrad, &c->dimg, &c->brec};
     for (DevMem* m : all) release(*m);
     for (Work& w : c->w) release_work(w);
@@ -998,6 +1002,7 @@ hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
         case HGS_OPT_PERSISTENT: c->ropts.persistent = val != 0; return HGS_OK;
         case HGS_OPT_EXACT_TILES: c->ropts.exact_tiles = val != 0; return HGS_OK;
         case HGS_OPT_LOD_BLEND: c->ropts.lod_blend = val != 0; return HGS_OK;
+        case HGS_OPT_KEEP_STATE: c->ropts.keep_state = val != 0; return HGS_OK;
         case HGS_OPT_LANES: {
             if (val != 1 && val != 2) return fail(c, HGS_E_INVALID, "lanes must be 1 or 2");
             if (val == 2 && !c->lane_stream) {
@@ -1070,6 +1075,11 @@ hgs_status hgs_render(hgs_ctx* c, void* stream, const hgs_output* outs) {
     hipStream_t s = (hipStream_t)stream;
     hgs_status st;
     if ((st = upload_views(c, s, outs))) return st;
+    if (c->ropts.keep_state) {
+        void* before = c->px_state.p;
+        if ((st = ensure(c, c->px_state, (size_t)c->total_tiles * kTilePx * sizeof(uint2)))) return st;
+        if (c->px_state.p != before) invalidate_graph(c);
+    }
     c->regrows = 0;
     for (int attempt = 0; attempt < 16; ++attempt) {
         if (c->use_graph && !c->stage_timing) {
@@ -1764,6 +1774,7 @@ hgs_status hgs_render_backward(hgs_ctx* c, void* stream, const hgs_image_grad* g
     b.tile_view = P<uint32_t>(c->tile_view);
     b.dimg = P<ImgGrad>(c->dimg);
     b.egrad = P<float>(c->egrad);
+    b.state = c->last_keep ? P<uint2>(c->px_state) : nullptr;
     ProjBwdArgs p{};
     p.cut = P<uint2>(W.cut);
     p.cut_cap = c->cut_cap;

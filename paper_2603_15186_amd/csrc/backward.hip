@@ -156,12 +156,19 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(8))) void k
         S.maxlast = 0;
     }
 
-    // 1. forward replay over the block lists (the forward's operations):
-    // where the pixel stops and its final transmittance
+    // 1. where the pixel stopped and its final transmittance: kept by the
+    // forward compositor, else a forward replay over the block lists (the
+    // forward's operations)
     float T = 1.f;
     bool live = inside;
     uint32_t last = n;
-    for (uint32_t b0 = 0; b0 < n; b0 += kB) {
+    if (a.state) {
+        const uint2 st = a.state[(size_t)tile * kNT + threadIdx.x];
+        last = st.x;
+        T = __uint_as_float(st.y);
+        __syncthreads();                            // S.maxlast is set
+    }
+    for (uint32_t b0 = 0; !a.state && b0 < n; b0 += kB) {
         const uint32_t cnt = min((uint32_t)kB, n - b0);
         uint32_t n_step;
         stage_lists(a, S, rg.x + b0, cnt, dx0, dy0, w, lane, gid, k, &n_step);

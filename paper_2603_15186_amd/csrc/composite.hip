@@ -68,7 +68,7 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const Counters* ctr,
     }
 }
 
-template <int BATCH, bool COUNT>
+template <int BATCH, bool COUNT, bool KEEP>
 __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t tile, StageA* s_a, StageB* s_b,
                                                StageC* s_c, uint16_t* s_idx, uint32_t* s_wc, uint32_t* s_n,
                                                uint32_t* s_red) {
@@ -90,6 +90,7 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
     bool live = inside;
     uint32_t nalg = 0, neval = 0;
+    uint32_t stop_at = 0xffffffffu;                     // list position where the pixel stopped
     if (threadIdx.x == 0) {                             // record that adds nothing
         s_a[BATCH] = StageA{0.f, 0.f, 0.f, 0.f};
         s_b[BATCH] = StageB{0.f, -__builtin_inff(), 0.f, 0.f};
@@ -171,6 +172,7 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
                 C2 = fmaf(wgt, Cc.col2, C2);
                 D = fmaf(wgt, B.z, D);
                 T = take ? Tn : T;
+                if (KEEP) stop_at = (add && !keep) ? (base - rg.x) + (id4[u] >> 4) : stop_at;
                 live = live && (keep || !add);
             }
             if (__ballot(live) == 0) break;
@@ -185,6 +187,10 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
         V.rgb[2 * plane + o] = C2 + T * V.bg[2];
         if (V.depth) V.depth[o] = D;
         if (V.alpha) V.alpha[o] = 1.f - T;
+    }
+    if (KEEP) {
+        const uint32_t L = !inside ? 0u : (stop_at != 0xffffffffu ? stop_at : rg.y - rg.x);
+        a.state[(size_t)tile * kNT + threadIdx.x] = make_uint2(L, __float_as_uint(T));
     }
     if (COUNT) {
         const uint32_t sum = wave_sum(nalg);
@@ -222,15 +228,15 @@ struct Shared {
 // Register budget for as many waves per SIMD as the LDS allows (seven
 // 256-entry workgroups or eight smaller ones per CU): the staging gathers
 // need that many to hide.
-template <int BATCH, bool COUNT>
+template <int BATCH, bool COUNT, bool KEEP>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(BATCH > 128 ? 7 : 8))) void k_composite(CompositeArgs a) {
     __shared__ Shared<BATCH> sh;
-    composite_tile<BATCH, COUNT>(a, blockIdx.x, sh.a, sh.b, sh.c, sh.idx, sh.wc, sh.n, sh.red);
+    composite_tile<BATCH, COUNT, KEEP>(a, blockIdx.x, sh.a, sh.b, sh.c, sh.idx, sh.wc, sh.n, sh.red);
 }
 
 // Persistent variant: a fixed grid takes tiles from a global counter until
 // the counter passes the last tile (every workgroup reaches that exit).
-template <int BATCH, bool COUNT>
+template <int BATCH, bool COUNT, bool KEEP>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(BATCH > 128 ? 7 : 8))) void k_composite_persistent(CompositeArgs a) {
     __shared__ Shared<BATCH> sh;
     for (;;) {
@@ -239,20 +245,25 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(BATCH > 128
         const uint32_t tile = sh.tile;
         __syncthreads();
         if (tile >= a.total_tiles) break;
-        composite_tile<BATCH, COUNT>(a, tile, sh.a, sh.b, sh.c, sh.idx, sh.wc, sh.n, sh.red);
+        composite_tile<BATCH, COUNT, KEEP>(a, tile, sh.a, sh.b, sh.c, sh.idx, sh.wc, sh.n, sh.red);
         __syncthreads();
     }
 }
 
+// Counting and keeping pixel states are not combined (the counters are a
+// profiling aid): a kept state takes precedence.
 template <int BATCH>
 void launch_b(const CompositeArgs& a, hipStream_t s) {
+    const bool keep = a.state != nullptr;
     if (a.opts.persistent) {
         const uint32_t grid = min(a.total_tiles, 256u * 8u);
-        if (a.opts.count_nalg) k_composite_persistent<BATCH, true><<<grid, kNT, 0, s>>>(a);
-        else k_composite_persistent<BATCH, false><<<grid, kNT, 0, s>>>(a);
+        if (keep) k_composite_persistent<BATCH, false, true><<<grid, kNT, 0, s>>>(a);
+        else if (a.opts.count_nalg) k_composite_persistent<BATCH, true, false><<<grid, kNT, 0, s>>>(a);
+        else k_composite_persistent<BATCH, false, false><<<grid, kNT, 0, s>>>(a);
     } else {
-        if (a.opts.count_nalg) k_composite<BATCH, true><<<a.total_tiles, kNT, 0, s>>>(a);
-        else k_composite<BATCH, false><<<a.total_tiles, kNT, 0, s>>>(a);
+        if (keep) k_composite<BATCH, false, true><<<a.total_tiles, kNT, 0, s>>>(a);
+        else if (a.opts.count_nalg) k_composite<BATCH, true, false><<<a.total_tiles, kNT, 0, s>>>(a);
+        else k_composite<BATCH, false, false><<<a.total_tiles, kNT, 0, s>>>(a);
     }
 }
 

@@ -97,6 +97,7 @@ struct RenderOpts {
     bool persistent = false;
     bool exact_tiles = true;
     bool lod_blend = false;
+    bool keep_state = false;         // compositor keeps each pixel's stop position and final T
 };
 
 // ---------------------------------------------------------------- launchers
@@ -215,6 +216,9 @@ struct CompositeArgs {
     int n_views;
     RenderOpts opts;
     Counters* ctr;
+    // per pixel of the pass, [tile][256 pixels]: (list position where the
+    // pixel stopped, or the list length; final transmittance bits); null: not kept
+    uint2* state;
 };
 void launch_ranges(const CompositeArgs& a, hipStream_t s);
 void launch_composite(const CompositeArgs& a, hipStream_t s);
@@ -266,6 +270,7 @@ struct BwdArgs {
     const uint32_t* tile_view;
     const ImgGrad* dimg;             // per view of the pass
     float* egrad;                    // [cut_cap][kEntryGrad]
+    const uint2* state;              // the forward's kept pixel states (CompositeArgs::state); null: replay
 };
 struct ProjBwdArgs {
     const uint2* cut;

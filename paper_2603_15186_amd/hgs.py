@@ -40,6 +40,7 @@ HGS_OPT_SORT_DIGIT_BITS = 10
 HGS_OPT_PASS_VIEWS = 11
 HGS_OPT_LOD_BLEND = 12
 HGS_OPT_LANES = 13
+HGS_OPT_KEEP_STATE = 14
 
 PROJECTED_FIELDS = ("u", "v", "A", "B", "C", "r", "g", "b", "depth", "opacity", "ntiles", "valid")
 

@@ -85,8 +85,12 @@ def _colours_away_from_clamp(scene, cam, ids=None):
     return np.all((np.abs(raw) > 1e-4) & (np.abs(raw - 1) > 1e-4))
 
 
+@pytest.mark.parametrize("keep", [0, 1])
 @pytest.mark.parametrize("seed,W_,H_", [(5, 72, 56), (6, 100, 45)])
-def test_flat_scene_gradients_match_oracle(R, seed, W_, H_):
+def test_flat_scene_gradients_match_oracle(R, seed, W_, H_, keep):
+    """keep = 1: the render keeps its pixel states and the backward pass
+    reads them; keep = 0: the backward pass replays the forward walk."""
+    from paper_2603_15186_amd import hgs
     scene = _scene(400, seed)
     cam = yaw_camera(W_, H_, 0.9 * W_, (0.6, -1.3, 0.6), math.pi / 2)
     assert _colours_away_from_clamp(scene, cam)
@@ -96,10 +100,48 @@ def test_flat_scene_gradients_match_oracle(R, seed, W_, H_):
     want, _ = G.gradients(scene, cam, *g)
     R.load_scene(scene)
     R.set_cameras([cam])
-    R.render()
-    got = R.backward([_to_gpu(cam, g)])
-    torch.cuda.synchronize()
-    _compare(got, want, f"seed {seed}")
+    R.set_option(hgs.HGS_OPT_KEEP_STATE, keep)
+    try:
+        R.render()
+        got = R.backward([_to_gpu(cam, g)])
+        torch.cuda.synchronize()
+    finally:
+        R.set_option(hgs.HGS_OPT_KEEP_STATE, 0)
+    _compare(got, want, f"seed {seed} keep {keep}")
+
+
+def test_kept_states_leave_images_and_gradients_unchanged(R):
+    """Images are bit-identical with and without kept pixel states, and the
+    backward pass from kept states equals the replaying one up to the
+    order of its atomic sums."""
+    from paper_2603_15186_amd import hgs
+    scene, cams = W.plan2m(scale=0.02, n_poses=6)
+    views = [yaw_camera(160, 90, 900.0 * 160 / 1280, c.position, math.atan2(c.R[2][1], c.R[2][0]))
+             for c in cams[:3]]
+    R.load_scene(scene)
+    R.set_cameras(views)
+    R.set_lod(1, 1.0)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    res = {}
+    try:
+        for keep in (0, 1):
+            R.set_option(hgs.HGS_OPT_KEEP_STATE, keep)
+            outs = R.render()
+            grads = [tuple(torch.randn(t.shape, generator=gen.manual_seed(7 + v), device="cuda") for t in o)
+                     for v, o in enumerate(outs)]
+            got = R.backward(grads)
+            torch.cuda.synchronize()
+            res[keep] = ([tuple(t.cpu().numpy() for t in o) for o in outs], {k: v.cpu().numpy() for k, v in got.items()})
+    finally:
+        R.set_option(hgs.HGS_OPT_KEEP_STATE, 0)
+    for a, b in zip(res[0][0], res[1][0]):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+    for f in FIELDS:
+        a, b = res[0][1][f], res[1][1][f]
+        scale = np.abs(a).max()
+        assert scale > 0, f
+        np.testing.assert_allclose(b, a, rtol=1e-4, atol=1e-5 * scale, err_msg=f)
 
 
 def test_two_views_sum_their_gradients(R):
@@ -138,13 +180,18 @@ def test_hierarchy_cut_gradients_match_oracle(R):
     rng = np.random.default_rng(8)
     g, bad = _upstream(scene, cam, rng, ids=ids)
     want, _ = G.gradients(scene, cam, *g, ids=ids)
+    from paper_2603_15186_amd import hgs
     R.load_scene(scene)
     R.set_cameras([cam])
     R.set_lod(1, 1.0)
-    R.render()
-    assert np.array_equal(R.get_cut(0), ids)
-    got = R.backward([_to_gpu(cam, g)])
-    torch.cuda.synchronize()
+    R.set_option(hgs.HGS_OPT_KEEP_STATE, 1)
+    try:
+        R.render()
+        assert np.array_equal(R.get_cut(0), ids)
+        got = R.backward([_to_gpu(cam, g)])
+        torch.cuda.synchronize()
+    finally:
+        R.set_option(hgs.HGS_OPT_KEEP_STATE, 0)
     sub = {k: v.cpu()[torch.from_numpy(ids.astype(np.int64))] for k, v in got.items()}
     _compare(sub, want, "plan cut")
     mask = np.ones(scene.n, bool)
