@@ -22,14 +22,15 @@
 // in LDS, and one global atomic add per number and tile lands them in a
 // per-entry buffer.
 //
-// Projection (one thread per cut entry, FP64): the chain rule from the 2D
-// mean, the conic factors of Sigma' = T T^T + 0.3 I (T = J W R S), the
-// camera depth and the colour back to the Gaussian's mean, scale, rotation
-// and opacity, written as a per-entry record with the entry's colour
-// gradient and view direction.  The entries are then sorted by Gaussian
-// (the radix sort of the binning) and one thread per Gaussian sums its
-// records, forming the SH coefficients' gradients sum g_c Y_k(d) on the
-// way: no scattered atomics on the parameter arrays.
+// Projection (FP64): the cut entries are sorted by Gaussian (the radix sort
+// of the binning); one thread per entry in that order takes the chain rule
+// from the 2D mean, the conic factors of Sigma' = T T^T + 0.3 I
+// (T = J W R S), the camera depth and the colour back to the Gaussian's
+// mean, scale, rotation and opacity, written as a per-entry record (in the
+// sorted order) with the entry's colour gradient and view direction.  One
+// thread per Gaussian then sums its run of records, forming the SH
+// coefficients' gradients sum g_c Y_k(d) on the way: no scattered atomics on
+// the parameter arrays.
 #include "blocks.h"
 #include "device_util.h"
 #include "internal.h"
@@ -347,7 +348,8 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     const uint32_t m = min(a.ctr->cut, a.cut_cap);
     constexpr int K = (DEG + 1) * (DEG + 1);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
+        const uint32_t i = a.order[p];
         const float* eg = a.egrad + (size_t)i * kEntryGrad;
         double gin[kNG];
         bool any = false;
@@ -356,7 +358,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
             gin[k] = eg[k];
             any = any || gin[k] != 0.0;
         }
-        float4* rec0 = reinterpret_cast<float4*>(a.rec + (size_t)i * kEntryRec);
+        float4* rec0 = reinterpret_cast<float4*>(a.rec + (size_t)p * kEntryRec);
         for (int t = 0; t < kEntryRec / 4; ++t) rec0[t] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (!any) continue;
         const uint2 e = a.cut[i];
@@ -482,7 +484,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
         gmu[0] += (gdir[0] - ux * dd) * idn;
         gmu[1] += (gdir[1] - uy * dd) * idn;
         gmu[2] += (gdir[2] - uz * dd) * idn;
-        float4* rec = reinterpret_cast<float4*>(a.rec + (size_t)i * kEntryRec);
+        float4* rec = reinterpret_cast<float4*>(a.rec + (size_t)p * kEntryRec);
         rec[0] = make_float4((float)gmu[0], (float)gmu[1], (float)gmu[2], (float)gsc[0]);
         rec[1] = make_float4((float)gsc[1], (float)gsc[2], (float)((gw - qw * qd) / qn), (float)((gx - qx * qd) / qn));
         rec[2] = make_float4((float)((gy - qy * qd) / qn), (float)((gz - qz * qd) / qn), (float)gin[5], (float)gcm[0]);
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     }
 }
 
-// Entry records ordered by Gaussian: thread p starts a run when its key
+// Entry records in Gaussian order: thread p starts a run when its key
 // differs from the previous one and sums the run's records; the SH
 // coefficients' gradients are sum_entries g_c Y_k(d_entry).  One thread per
 // Gaussian, so the outputs are updated without atomics.
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(256) void k_gather_bwd(GatherArgs a) {
         for (int t = 0; t < 3 * K; ++t) sh[t] = 0.f;
         bool any = false;
         for (uint32_t q = p; q < m && a.keys[q] == key; ++q) {
-            const float4* rec = reinterpret_cast<const float4*>(a.rec + (size_t)a.vals[q] * kEntryRec);
+            const float4* rec = reinterpret_cast<const float4*>(a.rec + (size_t)q * kEntryRec);
             const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3], r4 = rec[4];
             const float v[11] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z};
 #pragma unroll
@@ -558,18 +560,20 @@ void launch_backward_composite(const BwdArgs& b, const Counters* ctr, hipStream_
     if (b.total_tiles) k_composite_bwd<<<b.total_tiles, kNT, 0, s>>>(b);
 }
 
-void launch_backward_params(const ProjBwdArgs& p, SortArgs sa, GatherArgs ga, hipStream_t s) {
+void launch_backward_params(ProjBwdArgs p, SortArgs sa, GatherArgs ga, hipStream_t s) {
+    // the entries in Gaussian order: the chain rule reads each Gaussian's
+    // parameters for its views in a row and writes the records in that
+    // order, which the sum then reads sequentially
+    k_entry_keys<<<2048, 256, 0, s>>>(p.cut, p.ctr, p.cut_cap, sa.keys[0], sa.vals[0]);
+    const int r = launch_sort(sa, s);
+    p.order = sa.vals[r];
+    ga.keys = sa.keys[r];
     switch (p.sh_degree) {
         case 0: k_project_bwd<0><<<2048, 256, 0, s>>>(p); break;
         case 1: k_project_bwd<1><<<2048, 256, 0, s>>>(p); break;
         case 2: k_project_bwd<2><<<2048, 256, 0, s>>>(p); break;
         default: k_project_bwd<3><<<2048, 256, 0, s>>>(p); break;
     }
-    // order the entries by Gaussian and sum each Gaussian's records
-    k_entry_keys<<<2048, 256, 0, s>>>(p.cut, p.ctr, p.cut_cap, sa.keys[0], sa.vals[0]);
-    const int r = launch_sort(sa, s);
-    ga.keys = sa.keys[r];
-    ga.vals = sa.vals[r];
     switch (ga.sh_degree) {
         case 0: k_gather_bwd<0><<<2048, 256, 0, s>>>(ga); break;
         case 1: k_gather_bwd<1><<<2048, 256, 0, s>>>(ga); break;

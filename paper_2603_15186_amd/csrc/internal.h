@@ -282,12 +282,12 @@ struct ProjBwdArgs {
     const ViewDev* views;
     const float* egrad;
     const Counters* ctr;
-    float* rec;                      // [cut_cap][kEntryRec]: per-entry parameter gradients
+    const uint32_t* order;           // entry at each position of the Gaussian-sorted order
+    float* rec;                      // [cut_cap][kEntryRec]: per-entry parameter gradients, in that order
 };
 constexpr int kEntryRec = 20;        // mean 3, scale 3, quaternion 4, opacity, colour 3, direction 3, pad
 struct GatherArgs {
     const uint32_t* keys;            // Gaussian ids of the entries, ascending
-    const uint32_t* vals;            // entry indices
     uint32_t cap;
     const Counters* ctr;
     const float* rec;
@@ -299,7 +299,7 @@ struct GatherArgs {
     float* g_sh;                     // [n][K][3]
 };
 void launch_backward_composite(const BwdArgs& b, const Counters* ctr, hipStream_t s);
-void launch_backward_params(const ProjBwdArgs& p, SortArgs sa, GatherArgs ga, hipStream_t s);
+void launch_backward_params(ProjBwdArgs p, SortArgs sa, GatherArgs ga, hipStream_t s);
 
 // shortest-path planning (nav.hip)
 struct NavArgs {
