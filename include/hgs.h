@@ -54,7 +54,8 @@ typedef int32_t hgs_status;
                                      checks capacities; 0: fully asynchronous,
                                      call hgs_check() after synchronising */
 #define HGS_OPT_AUTO_REGROW 2     /* 1 (default): regrow and re-render on overflow */
-#define HGS_OPT_COUNT_NALG 3      /* 1: count evaluated (pixel, Gaussian) pairs */
+#define HGS_OPT_COUNT_NALG 3      /* 1: count evaluated (pixel, Gaussian) pairs (not
+                                     while HGS_OPT_KEEP_STATE is on) */
 #define HGS_OPT_BATCH_DEPTH 4     /* Gaussians staged in LDS per batch: 64, 128 or 256 */
 #define HGS_OPT_USE_GRAPH 5       /* 1: capture the render in a hipGraph on first use and
                                      replay it while cameras, LOD, options, scene and

@@ -7,10 +7,11 @@
 // Compositing (one 256-thread workgroup per 16x16 tile, a pixel per thread,
 // a 16-lane quarter-wave per 4x4 block as in the forward compositor): the
 // tile's depth-ordered entries are staged in LDS in batches and listed per
-// block exactly as the forward stages and lists them, and each pixel replays
-// the forward recurrence over its block's list with the same
-// single-precision operations to find where it stopped and its final
-// transmittance T_N.  It then walks the lists back to front, recovering T
+// block exactly as the forward stages and lists them.  Where each pixel
+// stopped and its final transmittance T_N come from the forward compositor
+// when the render kept them; else the pixel replays the forward recurrence
+// over its block's list with the same single-precision operations.  It then
+// walks the lists back to front, recovering T
 // before entry i as T_{i+1} / (1 - alpha_i), with
 //   dL/dalpha_i = sum_c gC_c (c_ic T_i - B_c / (1 - alpha_i))
 //               + gD (z_i T_i - B_D / (1 - alpha_i)) + gA T_N / (1 - alpha_i)
