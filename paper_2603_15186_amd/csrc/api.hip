@@ -773,16 +773,15 @@ hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarch
     HIP_TRY(c, hipSetDevice(c->device));
     const int64_t n = g->n;
     const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
-    // host-side re-layout: geo = 3 float4 per Gaussian, SH planar by (k, c)
+    // host-side re-layout: geo = 3 float4 per Gaussian; SH as given, the
+    // 3 K coefficients of a Gaussian contiguous ([g][k][c])
     std::vector<float4> geo((size_t)n * 3);
     for (int64_t i = 0; i < n; ++i) {
         geo[3 * i] = make_float4(g->means[3 * i], g->means[3 * i + 1], g->means[3 * i + 2], g->opacity[i]);
         geo[3 * i + 1] = make_float4(g->quats[4 * i], g->quats[4 * i + 1], g->quats[4 * i + 2], g->quats[4 * i + 3]);
         geo[3 * i + 2] = make_float4(g->scales[3 * i], g->scales[3 * i + 1], g->scales[3 * i + 2], 0.f);
     }
-    std::vector<float> sh((size_t)n * K * 3);
-    for (int64_t i = 0; i < n; ++i)
-        for (int k = 0; k < K * 3; ++k) sh[(size_t)k * n + i] = g->sh[(size_t)i * K * 3 + k];
+    std::vector<float> sh(g->sh, g->sh + (size_t)n * K * 3);
     // new buffers first, so a failure leaves the old scene intact
     DevMem ngeo, nsh, nbound, nchild, nleaf, nparent, nfeat, nlvl;
     auto cleanup = [&]() {

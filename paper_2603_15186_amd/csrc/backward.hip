@@ -469,7 +469,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
             double val = 0.5, d0 = 0.0, d1 = 0.0, d2 = 0.0;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const double f = a.sh[(int64_t)(k * 3 + c) * a.n + g];
+                const double f = a.sh[((int64_t)g * K + k) * 3 + c];
                 val += f * Y[k];
                 d0 += f * dY[k][0];
                 d1 += f * dY[k][1];

@@ -153,7 +153,7 @@ struct ProjectArgs {
     const uint2* cut;
     uint32_t cut_cap;
     const float4* geo;               // [n*3]
-    const float* sh;                 // planar [(k*3+c)*n + g]
+    const float* sh;                 // [g][k][c]: the 3 K coefficients of a Gaussian contiguous
     int64_t n;
     int sh_degree;
     const ViewDev* views;
@@ -276,7 +276,7 @@ struct ProjBwdArgs {
     const uint2* cut;
     uint32_t cut_cap;
     const float4* geo;
-    const float* sh;                 // planar
+    const float* sh;                 // [g][k][c]
     int64_t n;
     int sh_degree;
     const ViewDev* views;

@@ -32,10 +32,32 @@ constexpr double kBinSlack = 1e-3;
 // 0.25 sqrt(5/pi), 0.25 sqrt(15/pi), 0.25 sqrt(35/(2 pi)), 0.5 sqrt(105/pi),
 // 0.25 sqrt(21/(2 pi)), 0.25 sqrt(7/pi), 0.25 sqrt(105/pi).
 // With Blend, coefficient f of node g becomes f_p + t (f_g - f_p) with f_p
-// that of node pg (pg < 0: no blending).
-template <bool Blend>
-__device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t n, int64_t g, int64_t pg, float t,
-                                          int deg, float x, float y, float z, float rgb[3]) {
+// that of node pg (pg < 0: no blending).  The coefficients of a Gaussian are
+// one contiguous run of 3 K floats ([k][c]), read with 16-byte loads when
+// 3 K is a multiple of four.
+template <int DEG>
+__device__ __forceinline__ void load_sh(const float* __restrict__ sh, int64_t g, float f[3 * (DEG + 1) * (DEG + 1)]) {
+    constexpr int NF = 3 * (DEG + 1) * (DEG + 1);
+    const float* src = sh + g * NF;
+    if constexpr (NF % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < NF / 4; ++q) {
+            const float4 v = reinterpret_cast<const float4*>(src)[q];
+            f[4 * q] = v.x;
+            f[4 * q + 1] = v.y;
+            f[4 * q + 2] = v.z;
+            f[4 * q + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NF; ++q) f[q] = src[q];
+    }
+}
+
+template <bool Blend, int DEG>
+__device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t g, int64_t pg, float t, float x,
+                                          float y, float z, float rgb[3]) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr float k00 = 0.28209479177387814f;
     constexpr float k1 = 0.48860251190291992f;
     constexpr float k2a = 1.0925484305920792f, k2b = 0.31539156525252005f, k2c = 0.54627421529603959f;
@@ -43,22 +65,19 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t 
                     k3d = 0.3731763325901154f, k3e = 1.4453057213202769f;
     float Y[16];
     Y[0] = k00;
-    int K = 1;
-    if (deg >= 1) {
+    if constexpr (DEG >= 1) {
         Y[1] = -k1 * y;
         Y[2] = k1 * z;
         Y[3] = -k1 * x;
-        K = 4;
     }
-    if (deg >= 2) {
+    if constexpr (DEG >= 2) {
         const float xx = x * x, yy = y * y, zz = z * z;
         Y[4] = k2a * x * y;
         Y[5] = -k2a * y * z;
         Y[6] = k2b * (3.f * zz - 1.f);
         Y[7] = -k2a * x * z;
         Y[8] = k2c * (xx - yy);
-        K = 9;
-        if (deg >= 3) {
+        if constexpr (DEG >= 3) {
             Y[9] = -k3a * y * (3.f * xx - yy);
             Y[10] = k3b * x * y * z;
             Y[11] = -k3c * y * (5.f * zz - 1.f);
@@ -66,20 +85,21 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ sh, int64_t 
             Y[13] = -k3c * x * (5.f * zz - 1.f);
             Y[14] = k3e * z * (xx - yy);
             Y[15] = -k3a * x * (xx - 3.f * yy);
-            K = 16;
         }
     }
+    float f[3 * K];
+    load_sh<DEG>(sh, g, f);
+    if (Blend && pg >= 0) {
+        float fp[3 * K];
+        load_sh<DEG>(sh, pg, fp);
+#pragma unroll
+        for (int q = 0; q < 3 * K; ++q) f[q] = fp[q] + t * (f[q] - fp[q]);
+    }
     float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float f = sh[(int64_t)(k * 3 + c) * n + g];
-            if (Blend && pg >= 0) {
-                const float fp = sh[(int64_t)(k * 3 + c) * n + pg];
-                f = fp + t * (f - fp);
-            }
-            acc[c] = fmaf(f, Y[k], acc[c]);
-        }
+        for (int c = 0; c < 3; ++c) acc[c] = fmaf(f[3 * k + c], Y[k], acc[c]);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) rgb[c] = fminf(fmaxf(acc[c], 0.f), 1.f);
@@ -197,7 +217,7 @@ __device__ __forceinline__ void proj_cov(const double M0[3], const double M1[3],
 // semidefinite by construction), opacity and SH coefficients interpolated
 // alike.  The blended mean and depth key follow the same FP64 steps as the
 // unblended ones.
-template <bool Blend>
+template <bool Blend, int DEG>
 __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
     const uint32_t m = min(a.ctr->cut, a.cut_cap);
     uint32_t vis = 0;
@@ -303,8 +323,8 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
                 if (ntiles > 0) {
                     const double id = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
                     float rgb[3];
-                    sh_colour<Blend>(a.sh, a.n, g, pg, (float)t, a.sh_degree, (float)(dx * id), (float)(dy * id),
-                                     (float)(dz * id), rgb);
+                    sh_colour<Blend, DEG>(a.sh, g, pg, (float)t, (float)(dx * id), (float)(dy * id),
+                                          (float)(dz * id), rgb);
                     p.c0 = rgb[0];
                     p.c1 = rgb[1];
                     p.c2 = rgb[2];
@@ -484,11 +504,21 @@ __global__ __launch_bounds__(kNT) void k_emit(EmitArgs a) {
 
 }  // namespace
 
+template <bool Blend>
+void launch_project_b(const ProjectArgs& a, hipStream_t s) {
+    switch (a.sh_degree) {
+        case 0: k_project<Blend, 0><<<4096, kNT, 0, s>>>(a); break;
+        case 1: k_project<Blend, 1><<<4096, kNT, 0, s>>>(a); break;
+        case 2: k_project<Blend, 2><<<4096, kNT, 0, s>>>(a); break;
+        default: k_project<Blend, 3><<<4096, kNT, 0, s>>>(a); break;
+    }
+}
+
 void launch_project(const ProjectArgs& a, hipStream_t s) {
     if (a.blend)
-        k_project<true><<<4096, kNT, 0, s>>>(a);
+        launch_project_b<true>(a, s);
     else
-        k_project<false><<<4096, kNT, 0, s>>>(a);
+        launch_project_b<false>(a, s);
 }
 
 void launch_emit(const EmitArgs& a, hipStream_t s) {
