@@ -610,10 +610,7 @@ hgs_status read_counters(hgs_ctx* c, hipStream_t s) {
 LodMlpDev mlp_geometry(hgs_ctx* c) {
     LodMlpDev m{};
     m.nodefeat = P<float4>(c->nodefeat);
-    m.parent = P<int32_t>(c->parent);
     m.bound = P<float4>(c->bound);
-    m.geo = P<float4>(c->geo);
-    m.child = P<int2>(c->child);
     m.level_offset = P<int64_t>(c->lvl);
     m.n_levels = c->n_levels;
     return m;
@@ -800,13 +797,15 @@ hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarch
         std::vector<float4> bound((size_t)n);
         std::vector<int2> child((size_t)n);
         std::vector<int32_t> leaves;
-        std::vector<float4> feat((size_t)n);
+        std::vector<float4> feat((size_t)n * 3);
         for (int64_t i = 0; i < n; ++i) {
             bound[i] = make_float4(h->bound[4 * i], h->bound[4 * i + 1], h->bound[4 * i + 2], h->bound[4 * i + 3]);
             child[i] = make_int2(h->child_count[i] > 0 ? h->first_child[i] : 0, h->child_count[i]);
             if (h->child_count[i] == 0) leaves.push_back((int32_t)i);
         }
-        // learned-LOD node features: thinnest axis and children's colour variance
+        // learned-LOD node record (three float4): thinnest axis and children's
+        // colour variance; the parent's bounding sphere (radius -1: a root);
+        // opacity and child count
         for (int64_t i = 0; i < n; ++i) {
             const float* q = g->quats + 4 * i;
             const double qn = std::sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3]);
@@ -832,7 +831,10 @@ hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarch
                 var = m2 / cc - (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / ((double)cc * cc);
                 var *= 0.28209479177387814 * 0.28209479177387814;
             }
-            feat[i] = make_float4((float)col[0], (float)col[1], (float)col[2], (float)std::max(var, 0.0));
+            feat[3 * i] = make_float4((float)col[0], (float)col[1], (float)col[2], (float)std::max(var, 0.0));
+            const int32_t par = h->parent[i];
+            feat[3 * i + 1] = par >= 0 ? bound[par] : make_float4(0.f, 0.f, 0.f, -1.f);
+            feat[3 * i + 2] = make_float4(g->opacity[i], (float)cc, 0.f, 0.f);
         }
         if ((s = ensure(c, nbound, bound.size() * sizeof(float4))) || (s = ensure(c, nchild, child.size() * sizeof(int2))) ||
             (s = ensure(c, nleaf, leaves.size() * sizeof(int32_t))) || (s = ensure(c, nparent, (size_t)n * 4)) ||

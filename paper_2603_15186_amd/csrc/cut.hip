@@ -140,40 +140,55 @@ __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap
 
 // Learned-cut candidates of one level.  Block b takes the count pass's
 // chunk b, gathers its candidates (decision bit kCandidate) into an LDS
-// queue in order and evaluates them 256 at a time, one per lane.  The
-// network keeps a node (emits it) unless its probability reaches p*; the
-// block's counts lose each kept node's children and gain one emitted entry.
-__global__ __launch_bounds__(kNT) void k_level_mlp(LevelCtx c, uint32_t in_cap) {
+// queue in order and evaluates them 256 at a time: one lane per candidate
+// for the features, the matrix cores for the network (64 candidates per
+// wave).  The network keeps a node (emits it) unless its probability
+// reaches p*; the block's counts lose each kept node's children and gain
+// one emitted entry.
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k_level_mlp(LevelCtx c, uint32_t in_cap) {
     __shared__ uint32_t s_q[2 * kNT];
     __shared__ uint32_t s_wc[kNW + 1];
     __shared__ uint32_t s_n;
     __shared__ uint2 s_fix[kNW];
+    __shared__ float s_x[kNT * kMlpXStride];
+    __shared__ float s_w[kMlpParams];              // the network's FP32 weights
     uint32_t n = *c.in_count;
     n = n < in_cap ? n : in_cap;
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
     if (lo >= hi) return;
-    // constant address space: the weights (same for every lane) come through
-    // the scalar cache into SGPR operands
-    using ConstF = __attribute__((address_space(4))) const float*;
-    const ConstF sw = (ConstF)c.w32;
+    for (int k = threadIdx.x; k < kMlpParams; k += kNT) s_w[k] = c.w32[k];
     const LodMlpDev& m = *(const LodMlpDev*)c.mlp;
     const int w = threadIdx.x / kWave;
     if (threadIdx.x == 0) s_n = 0;
     uint32_t kept_n = 0, lost = 0;
     auto evaluate = [&](uint32_t cnt) {
-        if (threadIdx.x < cnt) {
-            const uint32_t i = s_q[threadIdx.x];
-            const uint2 e = c.in[i];
+        const bool valid = threadIdx.x < cnt;
+        uint32_t i = 0;
+        uint2 e = make_uint2(0, 0);
+        float f[kMlpIn];
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k) f[k] = 0.f;
+        if (valid) {
+            i = s_q[threadIdx.x];
+            e = c.in[i];
             const ViewDev& V = c.views[e.y];
             const float4 b = c.bound[e.x];
             NodeGeom g;
             node_geometry(V, b, &g);
-            if (!lod_mlp_expand(m, sw, V, (int)e.x, b, g, c.level)) {
-                c.dec[i] = (uint8_t)kEmit;
-                ++kept_n;
-                lost += (uint32_t)c.child[e.x].y;
-            }
+            lod_features(m, V, (int)e.x, b, g, c.level, f);
+#pragma unroll
+            for (int k = 0; k < kMlpIn; ++k) f[k] = (f[k] - m.mean[k]) * m.inv_std[k];
+        }
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k) s_x[threadIdx.x * kMlpXStride + k] = f[k];
+        __syncthreads();
+        const float z = lod_mlp_logit_mfma(s_w, s_x + w * kWave * kMlpXStride);
+        __syncthreads();                            // s_x is refilled by the next call
+        if (valid && !(1.f / (1.f + __expf(-z)) >= m.p_star)) {
+            c.dec[i] = (uint8_t)kEmit;
+            ++kept_n;
+            lost += (uint32_t)c.child[e.x].y;
         }
     };
     for (uint32_t s = lo; s < hi; s += kNT) {

@@ -24,11 +24,11 @@ struct LodMlpDev {
     float inv_std[kMlpIn];
     float p_star;                 // refine iff sigmoid(out) >= p_star
     float s_hi;                   // candidates: projected size <= s_hi pixels
-    const float4* nodefeat;       // (normal x, y, z, child colour variance)
-    const int32_t* parent;
+    // per node, three float4: (thinnest axis x, y, z, children's colour
+    // variance), the parent's bounding sphere (radius < 0: none), (opacity,
+    // child count, 0, 0); one gather per candidate
+    const float4* nodefeat;
     const float4* bound;
-    const float4* geo;            // geo[3k].w = opacity
-    const int2* child;
     const int64_t* level_offset;  // device copy, n_levels + 1 entries
     int n_levels;
 };
@@ -67,15 +67,14 @@ __device__ __forceinline__ void lod_features(const LodMlpDev& m, const ViewDev& 
     const double size = V.f2 * g.r * inv;
     f[0] = (float)log(size > 1e-6 ? size : 1e-6);
     f[1] = (float)log(g.pz > V.znear ? g.pz : V.znear);
-    f[2] = m.geo[3 * (int64_t)k].w;
-    f[3] = (float)m.child[k].y;
-    const float4 nf = m.nodefeat[k];
+    const float4 nf = m.nodefeat[3 * (int64_t)k], pb = m.nodefeat[3 * (int64_t)k + 1],
+                 oc = m.nodefeat[3 * (int64_t)k + 2];
+    f[2] = oc.x;
+    f[3] = oc.y;
     f[4] = nf.w;
     f[5] = (float)fabs((g.dx * nf.x + g.dy * nf.y + g.dz * nf.z) * inv);
     f[6] = (float)level;
-    const int p = m.parent[k];
-    if (p >= 0) {
-        const float4 pb = m.bound[p];
+    if (pb.w >= 0.f) {
         const double qx = (double)pb.x - V.o[0], qy = (double)pb.y - V.o[1], qz = (double)pb.z - V.o[2];
         const double pd = sqrt(qx * qx + qy * qy + qz * qz);
         const double ps = V.f2 * (double)pb.w / (pd > 1e-9 ? pd : 1e-9);
@@ -106,44 +105,80 @@ __device__ __forceinline__ float lod_mlp_logit(const uint16_t* __restrict__ w, c
     return out;
 }
 
-// Forward pass with the weights already widened to FP32; same arithmetic as
-// lod_mlp_logit.  W is a pointer type: a constant-address-space pointer lets
-// uniform weight reads go through the scalar cache.
-template <class W>
-__device__ __forceinline__ float lod_mlp_logit_f32(W w, const float x[kMlpIn]) {
-    float h1[kMlpH];
-#pragma unroll
-    for (int j = 0; j < kMlpH; ++j) {
-        float acc = w[kOffB1 + j];
-#pragma unroll
-        for (int i = 0; i < kMlpIn; ++i) acc = fmaf(w[kOffW1 + j * kMlpIn + i], x[i], acc);
-        h1[j] = acc > 0.f ? acc : 0.f;
-    }
-    float out = w[kOffB3];
-#pragma unroll 4
-    for (int j = 0; j < kMlpH; ++j) {
-        float acc = w[kOffB2 + j];
-#pragma unroll
-        for (int i = 0; i < kMlpH; ++i) acc = fmaf(w[kOffW2 + j * kMlpH + i], h1[i], acc);
-        acc = acc > 0.f ? acc : 0.f;
-        out = fmaf(w[kOffW3 + j], acc, out);
-    }
-    return out;
-}
+// The same network for the 64 candidates of a wave on the matrix cores
+// (FP32 MFMA 16x16x4, FP32 products and sums): candidates are the N
+// dimension, hidden units the M dimension, so a layer's accumulators
+// (lane l, register r: hidden unit 4 (l / 16) + r of a 16-unit tile,
+// candidate l % 16 of a 16-candidate tile) are the next layer's B operand
+// as they stand, with the weights loaded in the matching K order.  x: the
+// wave's standardised features, candidate c's at x[c * kMlpXStride + i].
+// Every lane of the wave takes part; returns the logit of the lane's own
+// candidate (lane c: candidate c).
+constexpr int kMlpXStride = kMlpIn + 1;
+typedef float mlp_f4 __attribute__((ext_vector_type(4)));
 
-// For a candidate node (the threshold rule refines it and its projected
-// size is at most s_hi): does the learned cut refine it?  Yes iff the
-// network's probability reaches p_star.  sw: the weights as FP32.
-template <class W>
-__device__ __forceinline__ bool lod_mlp_expand(const LodMlpDev& m, W sw, const ViewDev& V, int k, float4 b,
-                                               const NodeGeom& g, int level) {
-    float f[kMlpIn];
-    lod_features(m, V, k, b, g, level, f);
+__device__ __forceinline__ float lod_mlp_logit_mfma(const float* __restrict__ w, const float* x) {
+    const int l = __lane_id();
+    const int lr = l & 15, lg = l >> 4;
+    mlp_f4 h1[2][4];
 #pragma unroll
-    for (int i = 0; i < kMlpIn; ++i) f[i] = (f[i] - m.mean[i]) * m.inv_std[i];
-    const float z = lod_mlp_logit_f32(sw, f);
-    const float p = 1.f / (1.f + __expf(-z));
-    return p >= m.p_star;
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) h1[m][t] = mlp_f4{0.f, 0.f, 0.f, 0.f};
+    // layer 1: H1^T (32 x 64) = W1 (32 x 8) X^T (8 x 64)
+#pragma unroll
+    for (int s = 0; s < kMlpIn / 4; ++s) {
+        float a[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) a[m] = w[kOffW1 + (16 * m + lr) * kMlpIn + 4 * s + lg];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float b = x[(16 * t + lr) * kMlpXStride + 4 * s + lg];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) h1[m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b, h1[m][t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float bias = w[kOffB1 + 16 * m + 4 * lg + r];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) h1[m][t][r] = fmaxf(h1[m][t][r] + bias, 0.f);
+        }
+    // layer 2: H2^T (32 x 64) = W2 (32 x 32) H1^T, one 16-unit output tile m
+    // at a time, the K steps over (tile mp, register r); layer 3 takes each
+    // tile's units as they come: every lane sums its four units per
+    // candidate tile, then the four lane groups are added
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        mlp_f4 h2[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) h2[t] = mlp_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float a = w[kOffW2 + (16 * m + lr) * kMlpH + 16 * mp + 4 * lg + r];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    h2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, h1[mp][t][r], h2[t], 0, 0, 0);
+            }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float bias = w[kOffB2 + 16 * m + 4 * lg + r], w3 = w[kOffW3 + 16 * m + 4 * lg + r];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) part[t] = fmaf(w3, fmaxf(h2[t][r] + bias, 0.f), part[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        part[t] += __shfl_xor(part[t], 16, 64);
+        part[t] += __shfl_xor(part[t], 32, 64);
+    }
+    const float z = lg == 0 ? part[0] : (lg == 1 ? part[1] : (lg == 2 ? part[2] : part[3]));
+    return w[kOffB3] + z;
 }
 
 }  // namespace hgs
