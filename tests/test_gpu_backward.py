@@ -219,3 +219,39 @@ def test_backward_preconditions(R):
         assert all(not out[k].any() for k in FIELDS)
     finally:
         r.close()
+
+
+def test_kept_states_through_graph_replays(R):
+    """Renders replayed from a captured hipGraph keep their pixel states:
+    the backward pass after each replay equals the one after an eager
+    render (up to the order of its atomic sums), replay after replay."""
+    from paper_2603_15186_amd import hgs
+    scene, cams = W.plan2m(scale=0.02, n_poses=6)
+    views = [yaw_camera(128, 72, 900.0 * 128 / 1280, c.position, math.atan2(c.R[2][1], c.R[2][0]))
+             for c in cams[2:4]]
+    R.load_scene(scene)
+    R.set_cameras(views)
+    R.set_lod(1, 1.0)
+    gen = torch.Generator(device="cuda")
+    try:
+        R.set_option(hgs.HGS_OPT_KEEP_STATE, 1)
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+        outs = R.render()
+        grads = [tuple(torch.randn(t.shape, generator=gen.manual_seed(11 + v), device="cuda") for t in o)
+                 for v, o in enumerate(outs)]
+        want = {k: v.cpu().numpy() for k, v in R.backward(grads).items()}
+        torch.cuda.synchronize()
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
+        for rep in range(3):
+            R.render(outs)
+            got = R.backward(grads)
+            torch.cuda.synchronize()
+            for f in FIELDS:
+                scale = np.abs(want[f]).max()
+                assert scale > 0, f
+                np.testing.assert_allclose(got[f].cpu().numpy(), want[f], rtol=1e-4, atol=1e-5 * scale,
+                                           err_msg=f"{f} replay {rep}")
+        assert R.stats()["graph_launches"] >= 3
+    finally:
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+        R.set_option(hgs.HGS_OPT_KEEP_STATE, 0)
