@@ -1,7 +1,7 @@
 """Edge cases of the GPU path against the oracle: a single Gaussian, images
 of one pixel, one row, one column and exactly one tile, a Gaussian behind
-the camera, views batched with very different sizes, and the backward
-pass of a one-Gaussian scene."""
+the camera, views batched with very different sizes, the backward
+pass of a one-Gaussian scene, and SH degrees 0 to 2 forward and backward."""
 import math
 
 import numpy as np
@@ -96,3 +96,60 @@ def test_backward_of_one_gaussian(R):
     for k, w in want.items():
         gk = got[k].cpu().numpy().astype(np.float64).reshape(w.shape)
         np.testing.assert_allclose(gk, w, rtol=1e-4, atol=5e-5 * top, err_msg=k)
+
+
+@pytest.mark.parametrize("deg", [1, 2])
+def test_sh_degrees_one_and_two(R, deg):
+    """Scenes of SH degree 1 and 2 (the projection kernel is instantiated per
+    degree, and the coefficient loads differ: 16-byte loads for degree 1,
+    scalar loads for degree 2) against the oracle, full frame."""
+    base = make_random_box(2500, seed=20 + deg, box=(2.0, 2.0, 2.0))
+    rng = np.random.default_rng(30 + deg)
+    K = (deg + 1) ** 2
+    sh = np.zeros((base.n, K, 3), np.float32)
+    sh[:, 0, :] = np.asarray(base.sh, np.float32).reshape(base.n, -1, 3)[:, 0, :]
+    sh[:, 1:, :] = rng.normal(0, 0.15, size=(base.n, K - 1, 3))
+    scene = Scene(base.means, base.scales, base.quats, base.opacity, sh.reshape(base.n, K * 3), deg)
+    cams = [yaw_camera(96, 64, 80.0, (1.0, -1.2, 1.0), math.pi / 2),
+            yaw_camera(80, 80, 70.0, (3.2, 1.0, 1.0), math.pi)]
+    _check(R, scene, cams)
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2])
+def test_backward_sh_degrees_zero_to_two(R, deg):
+    """The backward pass of scenes of SH degree 0, 1 and 2 (its kernels are
+    instantiated per degree) against the FP64 gradient oracle."""
+    base = make_random_box(300, seed=40 + deg, box=(1.2, 1.2, 1.2))
+    rng = np.random.default_rng(50 + deg)
+    K = (deg + 1) ** 2
+    sh = np.zeros((base.n, K, 3), np.float32)
+    sh[:, 0, :] = np.asarray(base.sh, np.float32).reshape(base.n, -1, 3)[:, 0, :] * 0.6
+    if K > 1:
+        sh[:, 1:, :] = rng.normal(0, 0.06, size=(base.n, K - 1, 3))
+    scales = np.exp(rng.uniform(np.log(0.02), np.log(0.12), size=(base.n, 3))).astype(np.float32)
+    scene = Scene(base.means, scales, base.quats, base.opacity, sh.reshape(base.n, K * 3), deg)
+    cam = yaw_camera(64, 48, 58.0, (0.6, -1.3, 0.6), math.pi / 2)
+    res, _, _ = O.render(scene, cam, O.MODE_THRESHOLD, 1.0)
+    P = cam.width * cam.height
+    g = [rng.normal(size=(P, 3)), rng.normal(size=P) * 0.2, rng.normal(size=P)]
+    p = G.leaf_params(scene)
+    yy, xx = np.mgrid[0:cam.height, 0:cam.width]
+    _, _, _, cap = G.render(p, scene.sh_degree, cam, xx.ravel(), yy.ravel())
+    bad = (res.flags != 0) | cap
+    for a in g:
+        a[bad] = 0.0
+    g = [a.astype(np.float32).astype(np.float64) for a in g]
+    want, _ = G.gradients(scene, cam, *g)
+    R.load_scene(scene)
+    R.set_cameras([cam])
+    R.render()
+    got = R.backward([(torch.from_numpy(np.ascontiguousarray(g[0].T.reshape(3, cam.height, cam.width),
+                                                             dtype=np.float32)).cuda(),
+                       torch.from_numpy(g[1].reshape(cam.height, cam.width).astype(np.float32)).cuda(),
+                       torch.from_numpy(g[2].reshape(cam.height, cam.width).astype(np.float32)).cuda())])
+    torch.cuda.synchronize()
+    for k, w in want.items():
+        gk = got[k].cpu().numpy().astype(np.float64).reshape(w.shape)
+        top = np.abs(w).max()
+        assert top > 0, k
+        np.testing.assert_allclose(gk, w, rtol=1e-4, atol=5e-5 * top, err_msg=f"{k} degree {deg}")
