@@ -110,10 +110,11 @@ def test_flat_scene_gradients_match_oracle(R, seed, W_, H_, keep):
     _compare(got, want, f"seed {seed} keep {keep}")
 
 
-def test_kept_states_leave_images_and_gradients_unchanged(R):
+@pytest.mark.parametrize("batch,persistent", [(128, 0), (256, 0), (64, 1)])
+def test_kept_states_leave_images_and_gradients_unchanged(R, batch, persistent):
     """Images are bit-identical with and without kept pixel states, and the
     backward pass from kept states equals the replaying one up to the
-    order of its atomic sums."""
+    order of its atomic sums (each compositor variant keeps the states)."""
     from paper_2603_15186_amd import hgs
     scene, cams = W.plan2m(scale=0.02, n_poses=6)
     views = [yaw_camera(160, 90, 900.0 * 160 / 1280, c.position, math.atan2(c.R[2][1], c.R[2][0]))
@@ -123,6 +124,8 @@ def test_kept_states_leave_images_and_gradients_unchanged(R):
     R.set_lod(1, 1.0)
     gen = torch.Generator(device="cuda").manual_seed(3)
     res = {}
+    R.set_option(hgs.HGS_OPT_BATCH_DEPTH, batch)
+    R.set_option(hgs.HGS_OPT_PERSISTENT, persistent)
     try:
         for keep in (0, 1):
             R.set_option(hgs.HGS_OPT_KEEP_STATE, keep)
@@ -134,6 +137,8 @@ def test_kept_states_leave_images_and_gradients_unchanged(R):
             res[keep] = ([tuple(t.cpu().numpy() for t in o) for o in outs], {k: v.cpu().numpy() for k, v in got.items()})
     finally:
         R.set_option(hgs.HGS_OPT_KEEP_STATE, 0)
+        R.set_option(hgs.HGS_OPT_BATCH_DEPTH, 256)
+        R.set_option(hgs.HGS_OPT_PERSISTENT, 0)
     for a, b in zip(res[0][0], res[1][0]):
         for x, y in zip(a, b):
             np.testing.assert_array_equal(x, y)
