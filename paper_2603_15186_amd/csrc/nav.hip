@@ -120,36 +120,27 @@ struct DistShared {
 };
 
 // Relax cell q from the three cells behind it (offsets o0 orthogonal, o1
-// and o2 diagonal, move bits b0..b2 of q's mask m).
+// and o2 diagonal, move bits b0..b2 of q's mask m).  The four reads are
+// issued together (every offset stays inside the haloed tile) and illegal
+// or unreached candidates become kUnreached, so a step waits for one LDS
+// round trip; the candidates are compared in a fixed order with a strict
+// test, which picks the same pair as testing them one after another.
 __device__ __forceinline__ bool relax3(uint64_t* sd, int q, uint32_t m, int o0, int b0, int o1, int b1, int o2,
                                        int b2) {
     const uint64_t cur = sd[q];
+    const uint64_t v0 = sd[q + o0], v1 = sd[q + o1], v2 = sd[q + o2];
+    const uint64_t c0 = ((m >> b0) & 1u) && v0 != kUnreached ? v0 + kOrth : kUnreached;
+    const uint64_t c1 = ((m >> b1) & 1u) && v1 != kUnreached ? v1 + kDiag : kUnreached;
+    const uint64_t c2 = ((m >> b2) & 1u) && v2 != kUnreached ? v2 + kDiag : kUnreached;
+    const double inf = __builtin_huge_val();
     uint64_t best = cur;
-    double bk = cur == kUnreached ? __builtin_huge_val() : pair_cost(cur);
-    if (m & (1u << b0)) {
-        const uint64_t v = sd[q + o0];
-        if (v != kUnreached) {
-            const uint64_t c = v + kOrth;
-            const double ck = pair_cost(c);
-            if (ck < bk) { best = c; bk = ck; }
-        }
-    }
-    if (m & (1u << b1)) {
-        const uint64_t v = sd[q + o1];
-        if (v != kUnreached) {
-            const uint64_t c = v + kDiag;
-            const double ck = pair_cost(c);
-            if (ck < bk) { best = c; bk = ck; }
-        }
-    }
-    if (m & (1u << b2)) {
-        const uint64_t v = sd[q + o2];
-        if (v != kUnreached) {
-            const uint64_t c = v + kDiag;
-            const double ck = pair_cost(c);
-            if (ck < bk) { best = c; bk = ck; }
-        }
-    }
+    double bk = cur == kUnreached ? inf : pair_cost(cur);
+    const double k0 = c0 == kUnreached ? inf : pair_cost(c0);
+    const double k1 = c1 == kUnreached ? inf : pair_cost(c1);
+    const double k2 = c2 == kUnreached ? inf : pair_cost(c2);
+    if (k0 < bk) { best = c0; bk = k0; }
+    if (k1 < bk) { best = c1; bk = k1; }
+    if (k2 < bk) { best = c2; bk = k2; }
     if (best != cur) {
         sd[q] = best;
         return true;
@@ -200,11 +191,19 @@ __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int s
     }
     uint64_t* D = d.dist + (size_t)g * d.nx * d.ny;
     uint64_t* sd = S.d[w];
-    for (int k = lane; k < kH * kH; k += kWave) {
+    // all of a lane's loads in flight together, then the LDS stores
+    constexpr int kLoads = (kH * kH + kWave - 1) / kWave;
+    uint64_t ld[kLoads];
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+        const int k = lane + j * kWave;
         const int gx = gx0 + k % kH, gy = gy0 + k / kH;
-        const bool in = gx >= 0 && gy >= 0 && gx < d.nx && gy < d.ny;
-        sd[k] = in ? load_relaxed(D + (size_t)gy * d.nx + gx) : kUnreached;
+        const bool in = k < kH * kH && gx >= 0 && gy >= 0 && gx < d.nx && gy < d.ny;
+        ld[j] = in ? load_relaxed(D + (size_t)gy * d.nx + gx) : kUnreached;
     }
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j)
+        if (lane + j * kWave < kH * kH) sd[lane + j * kWave] = ld[j];
     // lanes 0-31 sweep east / south, lanes 32-63 west / north; li is the
     // lane's row (x phase) or column (y phase), 1..32
     const int fwd = lane < 32 ? 1 : -1, li = (lane & 31) + 1;
@@ -216,29 +215,37 @@ __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int s
     bool any = false;
     for (;;) {
         bool ch = false;
+#pragma unroll 4
         for (int st = 0; st < kT; ++st) {
             const int q = li * kH + x0 + fwd * st;
-            const uint32_t m = S.mv[q];
-            if (m) ch |= relax3(sd, q, m, xo0, xb0, xo1, xb1, xo2, xb2);
+            ch |= relax3(sd, q, S.mv[q], xo0, xb0, xo1, xb1, xo2, xb2);
         }
+#pragma unroll 4
         for (int st = 0; st < kT; ++st) {
             const int q = (x0 + fwd * st) * kH + li;
-            const uint32_t m = S.mv[q];
-            if (m) ch |= relax3(sd, q, m, yo0, yb0, yo1, yb1, yo2, yb2);
+            ch |= relax3(sd, q, S.mv[q], yo0, yb0, yo1, yb1, yo2, yb2);
         }
         any |= ch;
         if (__ballot(ch) == 0) break;
     }
     bool wrote = false;
     if (__ballot(any)) {
-        for (int k = lane; k < kT * kT; k += kWave) {
+        constexpr int kCells = kT * kT / kWave;
+        uint64_t old[kCells];
+#pragma unroll
+        for (int j = 0; j < kCells; ++j) {
+            const int k = lane + j * kWave;
+            const int gx = gx0 + k % kT + 1, gy = gy0 + k / kT + 1;
+            old[j] = gx < d.nx && gy < d.ny ? load_relaxed(D + (size_t)gy * d.nx + gx) : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kCells; ++j) {
+            const int k = lane + j * kWave;
             const int q = (k / kT + 1) * kH + k % kT + 1;
-            const int gx = gx0 + q % kH, gy = gy0 + q / kH;
-            if (gx >= d.nx || gy >= d.ny) continue;
-            uint64_t* cell = D + (size_t)gy * d.nx + gx;
+            const int gx = gx0 + k % kT + 1, gy = gy0 + k / kT + 1;
             const uint64_t v = sd[q];
-            if (v != load_relaxed(cell)) {
-                store_relaxed(cell, v);
+            if (gx < d.nx && gy < d.ny && v != old[j]) {
+                store_relaxed(D + (size_t)gy * d.nx + gx, v);
                 wrote = true;
             }
         }
