@@ -292,6 +292,11 @@ __global__ __launch_bounds__(kNT) void k_steps(TraceArgs a) {
     }
 }
 
+// Offsets of move st (per lane) from 2-bit fields of an immediate, offset
+// by one: no table in memory on the walk's dependent chain.
+__device__ __forceinline__ int step_dx(uint32_t st) { return (int)((0x2252u >> (2 * st)) & 3u) - 1; }
+__device__ __forceinline__ int step_dy(uint32_t st) { return (int)((0x0A25u >> (2 * st)) & 3u) - 1; }
+
 __global__ __launch_bounds__(kNT) void k_trace(TraceArgs a) {
     const int64_t N = (int64_t)a.nx * a.ny;
     for (int64_t q = blockIdx.x * (int64_t)kNT + threadIdx.x; q < a.n; q += (int64_t)gridDim.x * kNT) {
@@ -309,7 +314,7 @@ __global__ __launch_bounds__(kNT) void k_trace(TraceArgs a) {
                     m = -1;
                     break;
                 }
-                c += (int64_t)kDY[st] * a.nx + kDX[st];
+                c += (int64_t)step_dy(st) * a.nx + step_dx(st);
             }
             len = (int32_t)m;
         }
