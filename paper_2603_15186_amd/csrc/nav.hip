@@ -39,9 +39,11 @@ constexpr uint64_t kOrth = 1ull;           // (a, b) packed a | b << 32
 constexpr uint64_t kDiag = 1ull << 32;
 constexpr double kSqrt2 = 1.4142135623730951;
 
-// E, W, S, N, SE, SW, NE, NW with x to the right and y down the rows
-__constant__ int kDX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
-__constant__ int kDY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
+// Offsets of move m in the order E, W, S, N, SE, SW, NE, NW (x to the
+// right, y down the rows), from 2-bit fields of an immediate offset by one:
+// a per-lane move index then costs no memory access.
+__device__ __forceinline__ int step_dx(uint32_t m) { return (int)((0x2252u >> (2 * m)) & 3u) - 1; }
+__device__ __forceinline__ int step_dy(uint32_t m) { return (int)((0x0A25u >> (2 * m)) & 3u) - 1; }
 
 __device__ __forceinline__ uint64_t load_relaxed(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -110,7 +112,7 @@ __device__ __forceinline__ double pair_cost(uint64_t p) {
 // the same for the columns southward and northward.  Lanes of one wave run
 // in step, so a cell is written by at most one lane per step and every
 // write is a minimum over values read at that step: relaxation stays
-// monotone.  The wave stops when a full x and y phase changes nothing.
+// monotone.  The wave stops after two phases in a row that change nothing.
 constexpr int kGW = kNT / kWave;           // goals per workgroup
 
 struct DistShared {
@@ -212,21 +214,28 @@ __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int s
     const int xb0 = fwd > 0 ? 1 : 0, xb1 = fwd > 0 ? 7 : 6, xb2 = fwd > 0 ? 5 : 4;
     const int yo0 = -fwd * kH, yo1 = -fwd * kH - 1, yo2 = -fwd * kH + 1;  // N, NW, NE (south) or S, SW, SE
     const int yb0 = fwd > 0 ? 3 : 2, yb1 = fwd > 0 ? 7 : 5, yb2 = fwd > 0 ? 6 : 4;
+    // An x phase that changes nothing leaves every cell relaxed over E, W
+    // and the four diagonals, a y phase over N, S and the diagonals: two
+    // phases in a row that change nothing, in either order, mark a fixed
+    // point over all eight moves.
     bool any = false;
-    for (;;) {
+    for (int quiet = 0, ph = 0; quiet < 2; ph ^= 1) {
         bool ch = false;
+        if (ph == 0) {
 #pragma unroll 4
-        for (int st = 0; st < kT; ++st) {
-            const int q = li * kH + x0 + fwd * st;
-            ch |= relax3(sd, q, S.mv[q], xo0, xb0, xo1, xb1, xo2, xb2);
-        }
+            for (int st = 0; st < kT; ++st) {
+                const int q = li * kH + x0 + fwd * st;
+                ch |= relax3(sd, q, S.mv[q], xo0, xb0, xo1, xb1, xo2, xb2);
+            }
+        } else {
 #pragma unroll 4
-        for (int st = 0; st < kT; ++st) {
-            const int q = (x0 + fwd * st) * kH + li;
-            ch |= relax3(sd, q, S.mv[q], yo0, yb0, yo1, yb1, yo2, yb2);
+            for (int st = 0; st < kT; ++st) {
+                const int q = (x0 + fwd * st) * kH + li;
+                ch |= relax3(sd, q, S.mv[q], yo0, yb0, yo1, yb1, yo2, yb2);
+            }
         }
         any |= ch;
-        if (__ballot(ch) == 0) break;
+        quiet = __ballot(ch) ? 0 : quiet + 1;
     }
     bool wrote = false;
     if (__ballot(any)) {
@@ -276,7 +285,7 @@ __global__ __launch_bounds__(kNT) void k_steps(TraceArgs a) {
         } else if (v != kUnreached && a.nav[c]) {
             const int i = (int)(c % a.nx), j = (int)(c / a.nx);
             for (int m = 0; m < 8; ++m) {
-                const int u = i + kDX[m], w = j + kDY[m];
+                const int u = i + step_dx(m), w = j + step_dy(m);
                 if (u < 0 || w < 0 || u >= a.nx || w >= a.ny) continue;
                 const int64_t n = (int64_t)w * a.nx + u;
                 if (!a.nav[n]) continue;
@@ -291,11 +300,6 @@ __global__ __launch_bounds__(kNT) void k_steps(TraceArgs a) {
         a.steps[k] = step;
     }
 }
-
-// Offsets of move st (per lane) from 2-bit fields of an immediate, offset
-// by one: no table in memory on the walk's dependent chain.
-__device__ __forceinline__ int step_dx(uint32_t st) { return (int)((0x2252u >> (2 * st)) & 3u) - 1; }
-__device__ __forceinline__ int step_dy(uint32_t st) { return (int)((0x0A25u >> (2 * st)) & 3u) - 1; }
 
 __global__ __launch_bounds__(kNT) void k_trace(TraceArgs a) {
     const int64_t N = (int64_t)a.nx * a.ny;
