@@ -151,6 +151,11 @@ __device__ __forceinline__ bool relax3(uint64_t* sd, int q, uint32_t m, int o0, 
 }
 
 __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int slot) {
+    // After a round of the batch that changed no tile the fields are
+    // settled: the rest of the batch returns at once (its counts stay zero,
+    // and the host stops at the first zero count, so the tile flags these
+    // rounds leave as they were are never read).
+    if (slot > 0 && d.active[slot - 1] == 0) return;
     __shared__ DistShared S;
     const int t = blockIdx.x;
     const int tx = t % d.tiles_x, ty = t / d.tiles_x;
