@@ -121,16 +121,13 @@ struct DistShared {
     uint8_t mv[kH * kH];                   // legal moves of interior cells
 };
 
-// Relax cell q from the three cells behind it (offsets o0 orthogonal, o1
-// and o2 diagonal, move bits b0..b2 of q's mask m).  The four reads are
-// issued together (every offset stays inside the haloed tile) and illegal
-// or unreached candidates become kUnreached, so a step waits for one LDS
-// round trip; the candidates are compared in a fixed order with a strict
-// test, which picks the same pair as testing them one after another.
-__device__ __forceinline__ bool relax3(uint64_t* sd, int q, uint32_t m, int o0, int b0, int o1, int b1, int o2,
-                                       int b2) {
-    const uint64_t cur = sd[q];
-    const uint64_t v0 = sd[q + o0], v1 = sd[q + o1], v2 = sd[q + o2];
+// Best of a cell's pair cur and the candidates from the three cells behind
+// it (pairs v0 orthogonal, v1 and v2 diagonal, legal when move bits b0..b2
+// of its mask m are set); unreached or illegal candidates drop out.  The
+// candidates are compared in a fixed order with a strict test, which picks
+// the same pair as testing them one after another.
+__device__ __forceinline__ uint64_t relax_pair(uint64_t cur, uint32_t m, uint64_t v0, int b0, uint64_t v1, int b1,
+                                               uint64_t v2, int b2) {
     const uint64_t c0 = ((m >> b0) & 1u) && v0 != kUnreached ? v0 + kOrth : kUnreached;
     const uint64_t c1 = ((m >> b1) & 1u) && v1 != kUnreached ? v1 + kDiag : kUnreached;
     const uint64_t c2 = ((m >> b2) & 1u) && v2 != kUnreached ? v2 + kDiag : kUnreached;
@@ -142,12 +139,97 @@ __device__ __forceinline__ bool relax3(uint64_t* sd, int q, uint32_t m, int o0, 
     const double k2 = c2 == kUnreached ? inf : pair_cost(c2);
     if (k0 < bk) { best = c0; bk = k0; }
     if (k1 < bk) { best = c1; bk = k1; }
-    if (k2 < bk) { best = c2; bk = k2; }
-    if (best != cur) {
-        sd[q] = best;
-        return true;
+    if (k2 < bk) best = c2;
+    return best;
+}
+
+// The value of lane l - 1 (from_below) or l + 1 (from_above) in the wave;
+// lanes 0 and 63 receive zero.
+__device__ __forceinline__ uint64_t from_below(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)v, 0x138, 0xf, 0xf, false);   // wave_shr:1
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(v >> 32), 0x138, 0xf, 0xf, false);
+    return (uint64_t)hi << 32 | lo;
+}
+__device__ __forceinline__ uint64_t from_above(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)v, 0x130, 0xf, 0xf, false);   // wave_shl:1
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(v >> 32), 0x130, 0xf, 0xf, false);
+    return (uint64_t)hi << 32 | lo;
+}
+
+// One phase of a wave's sweeps over its tile: lane li (1..kT) walks line li
+// (cells li*A + x*L, x = 1..kT), lanes 0-31 forward and 32-63 backward, and
+// relaxes each cell from the three cells one step behind (o0 on its line,
+// o1 and o2 on lines li - 1 and li + 1).  This lane and its neighbours in
+// the wave wrote those three at the step before, so their pairs come from
+// registers (lane shifts) rather than from LDS; lines 1 and kT take their
+// outer one from the halo, as does every lane at the first step.  A cell's
+// own pair is read ahead of its step: the lanes sweeping the other way
+// reach the cells of a lane's first half only after it has passed them
+// (from their step kT/2 on) and write those of its second half only before
+// it gets there (in their first kT/2 steps), so once the second half's
+// reads follow the first half's writes, every pair used equals what a read
+// at the step itself would return, and storing a cell's pair unchanged
+// overwrites nothing newer.  Returns whether the lane changed a cell.
+template <int L, int A>
+__device__ __forceinline__ bool sweep(uint64_t* sd, const uint8_t* mv, int li, int fwd, int x0, int b0, int b1,
+                                      int b2) {
+    constexpr int kHalf = kT / 2, kChunk = 4, kChunks = kHalf / kChunk;
+    int q0 = li * A + x0 * L, dq = fwd * L;
+    // formed anew at every call: nothing derived from them is hoisted out
+    // of the caller's loop over phases to stay live in registers
+    __asm__ volatile("" : "+v"(q0), "+v"(dq));
+    const int o0 = -dq, o1 = -A - dq, o2 = A - dq;
+    const int ob = li == 1 ? o1 : o2;
+    // The reads of a half go out one chunk of steps ahead of their use; the
+    // (compiler-only) fences keep later chunks from being hoisted into the
+    // registers, and the second half's reads after the first half's writes.
+    __asm__ volatile("" ::: "memory");
+    uint64_t best = sd[q0 + o0];
+    const uint64_t up0 = sd[q0 + o1], dn0 = sd[q0 + o2];
+    bool ch = false;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        uint64_t cur[2][kChunk], hal[2][kChunk];
+        uint32_t m[2][kChunk];
+        int qb[2];
+        auto load = [&](int c) {
+            // the chunk's first cell, opaque to the compiler so that it
+            // forms the chunk's addresses then instead of keeping every
+            // step's address in a register from the start
+            qb[c & 1] = q0 + dq * (h * kHalf + c * kChunk);
+            __asm__ volatile("" : "+v"(qb[c & 1]));
+#pragma unroll
+            for (int s = 0; s < kChunk; ++s) {
+                const int q = qb[c & 1] + dq * s;
+                cur[c & 1][s] = sd[q];
+                hal[c & 1][s] = sd[q + ob];
+                m[c & 1][s] = mv[q];
+            }
+        };
+        __asm__ volatile("" ::: "memory");
+        load(0);
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            __asm__ volatile("" ::: "memory");
+            if (c + 1 < kChunks) load(c + 1);
+#pragma unroll
+            for (int s = 0; s < kChunk; ++s) {
+                const int st = h * kHalf + c * kChunk + s;
+                uint64_t v1 = up0, v2 = dn0;
+                if (st > 0) {
+                    const uint64_t lb = from_below(best), la = from_above(best);
+                    v1 = li == 1 ? hal[c & 1][s] : lb;
+                    v2 = li == kT ? hal[c & 1][s] : la;
+                }
+                const uint64_t nb = relax_pair(cur[c & 1][s], m[c & 1][s], best, b0, v1, b1, v2, b2);
+                sd[qb[c & 1] + dq * s] = nb;
+                ch |= nb != cur[c & 1][s];
+                best = nb;
+            }
+        }
+        __asm__ volatile("" ::: "memory");
     }
-    return false;
+    return ch;
 }
 
 __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int slot) {
@@ -215,9 +297,9 @@ __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int s
     // lane's row (x phase) or column (y phase), 1..32
     const int fwd = lane < 32 ? 1 : -1, li = (lane & 31) + 1;
     const int x0 = fwd > 0 ? 1 : kT;
-    const int xo0 = -fwd, xo1 = -kH - fwd, xo2 = kH - fwd;           // W, NW, SW (east) or E, NE, SE
+    // move bits of the cells behind: W, NW, SW (east) or E, NE, SE (west);
+    // N, NW, NE (south) or S, SW, SE (north)
     const int xb0 = fwd > 0 ? 1 : 0, xb1 = fwd > 0 ? 7 : 6, xb2 = fwd > 0 ? 5 : 4;
-    const int yo0 = -fwd * kH, yo1 = -fwd * kH - 1, yo2 = -fwd * kH + 1;  // N, NW, NE (south) or S, SW, SE
     const int yb0 = fwd > 0 ? 3 : 2, yb1 = fwd > 0 ? 7 : 5, yb2 = fwd > 0 ? 6 : 4;
     // An x phase that changes nothing leaves every cell relaxed over E, W
     // and the four diagonals, a y phase over N, S and the diagonals: two
@@ -225,20 +307,8 @@ __global__ __launch_bounds__(kNT) void k_dist_round(DistArgs d, int round, int s
     // point over all eight moves.
     bool any = false;
     for (int quiet = 0, ph = 0; quiet < 2; ph ^= 1) {
-        bool ch = false;
-        if (ph == 0) {
-#pragma unroll 4
-            for (int st = 0; st < kT; ++st) {
-                const int q = li * kH + x0 + fwd * st;
-                ch |= relax3(sd, q, S.mv[q], xo0, xb0, xo1, xb1, xo2, xb2);
-            }
-        } else {
-#pragma unroll 4
-            for (int st = 0; st < kT; ++st) {
-                const int q = (x0 + fwd * st) * kH + li;
-                ch |= relax3(sd, q, S.mv[q], yo0, yb0, yo1, yb1, yo2, yb2);
-            }
-        }
+        const bool ch = ph == 0 ? sweep<1, kH>(sd, S.mv, li, fwd, x0, xb0, xb1, xb2)
+                                : sweep<kH, 1>(sd, S.mv, li, fwd, x0, yb0, yb1, yb2);
         any |= ch;
         quiet = __ballot(ch) ? 0 : quiet + 1;
     }
