@@ -505,8 +505,8 @@ def run_nav(args):
     collision map (15 planes, 404 x 304 cells of 5 cm, built once,
     untimed), then per step the navigable map of a 0.25 m disc robot,
     distance fields to 9 goals and 200 shortest-path trajectories per goal
-    (3,600 per step over both floors); the FP64 oracle timed on the host for
-    the same step."""
+    (3,600 per step over both floors, the two floors in flight together);
+    the FP64 oracle timed on the host for the same step."""
     import numpy as np
     import torch
     from paper_2603_15186_amd import hgs
@@ -524,14 +524,31 @@ def run_nav(args):
         goals, starts, slots = W.nav_queries(nav0, n_goals=9, per_goal=200, seed=f)
         floors.append((m, goals, torch.from_numpy(starts).cuda(), torch.from_numpy(slots).cuda()))
 
+    # The floors are independent problems: each runs on a context and a HIP
+    # stream of its own (the second context holds no scene; planning reads
+    # only its maps), floor 1 from a worker thread, since a distance-field
+    # call waits on the host between batches of rounds (the library's calls
+    # release the GIL).  Together the two floors give the GPU twice the
+    # waves of one, which the latency-bound relaxation rounds need.
+    from concurrent.futures import ThreadPoolExecutor
+    ctxs = [r, hgs.Renderer(0)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    pool = ThreadPoolExecutor(max_workers=1)
+    torch.cuda.synchronize()
+
+    def floor_step(i):
+        m, goals, st, sl = floors[i]
+        R, s = ctxs[i], streams[i]
+        with torch.cuda.stream(s):
+            nav = R.navigable_map(m, -0.1, -0.1, cell, radius, stream=s)
+            dist, rounds = R.distance_fields(nav, goals, stream=s)
+            paths, lens = R.trace_paths(nav, dist, st, sl, cap, stream=s)
+        return nav, dist, rounds, paths, lens
+
     def step():
-        out = []
-        for m, goals, st, sl in floors:
-            nav = r.navigable_map(m, -0.1, -0.1, cell, radius)
-            dist, rounds = r.distance_fields(nav, goals)
-            paths, lens = r.trace_paths(nav, dist, st, sl, cap)
-            out.append((nav, dist, rounds, paths, lens))
-        return out
+        fut = pool.submit(floor_step, 1)
+        out0 = floor_step(0)
+        return [out0, fut.result()]
 
     for _ in range(args.warmup):
         step()
@@ -544,7 +561,7 @@ def run_nav(args):
     n_traj = sum(int(st.numel()) for _, _, st, _ in floors)
     lens = np.concatenate([x[4].cpu().numpy() for x in res])
     rounds = [x[2] for x in res]
-    # stage times of one step with HIP events (eager)
+    # stage times with HIP events, one floor at a time on one stream
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     st_ms = np.zeros(3)
@@ -558,7 +575,8 @@ def run_nav(args):
         ev[3].record(stream)
         torch.cuda.synchronize()
         st_ms += [ev[k].elapsed_time(ev[k + 1]) for k in range(3)]
-    log(f"nav step {ms:.3f} ms: navigable / fields / traces {st_ms.round(3).tolist()} ms; rounds {rounds}; "
+    log(f"nav step {ms:.3f} ms (floors concurrent); one floor after the other: navigable / fields / traces "
+        f"{st_ms.round(3).tolist()} ms; rounds {rounds}; "
         f"path cells mean {lens.mean():.1f} max {lens.max()}")
     cells = nx * ny
     # algorithmic bytes of the fields: every cell's 8-byte pair written once
@@ -588,14 +606,17 @@ def run_nav(args):
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int64", "data": "synthetic",
            "config": {"workload": "building30m, 2 floors x 404x304 cells of 5 cm, 0.25 m robot, 9 goals x 200 "
-                                  "starts per floor", "parallelism": "single GPU"},
+                                  "starts per floor", "parallelism": "single GPU, the two floors on two streams"},
            "roofline": {"kernel": "k_dist_round", "bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
                         "frac": gbs / 8000.0, "traffic": None},
            "cpu_baseline": cpu,
-           "extra": {"stage_ms_per_step": {"navigable": st_ms[0], "fields": st_ms[1], "traces": st_ms[2]},
+           "extra": {"stage_ms_one_floor_after_the_other": {"navigable": st_ms[0], "fields": st_ms[1],
+                                                            "traces": st_ms[2]},
                      "relaxation_rounds": rounds, "path_cells_mean": float(lens.mean()),
                      "path_cells_max": int(lens.max()), "unreachable": int((lens <= 0).sum())}}
     print(json.dumps(out), flush=True)
+    pool.shutdown()
+    ctxs[1].close()
     r.close()
 
 
