@@ -123,24 +123,23 @@ struct DistShared {
 
 // Best of a cell's pair cur and the candidates from the three cells behind
 // it (pairs v0 orthogonal, v1 and v2 diagonal, legal when move bits b0..b2
-// of its mask m are set); unreached or illegal candidates drop out.  The
-// candidates are compared in a fixed order with a strict test, which picks
-// the same pair as testing them one after another.
+// of its mask m are set and the cell is reached).  An illegal candidate
+// costs infinity, so its pair (which may have wrapped) is never chosen.
+// The cheaper of (cur, c0) and of (c1, c2) are found side by side, then the
+// cheaper of the two: equal costs mean equal pairs, so the grouping of the
+// tests does not change the pair returned.
 __device__ __forceinline__ uint64_t relax_pair(uint64_t cur, uint32_t m, uint64_t v0, int b0, uint64_t v1, int b1,
                                                uint64_t v2, int b2) {
-    const uint64_t c0 = ((m >> b0) & 1u) && v0 != kUnreached ? v0 + kOrth : kUnreached;
-    const uint64_t c1 = ((m >> b1) & 1u) && v1 != kUnreached ? v1 + kDiag : kUnreached;
-    const uint64_t c2 = ((m >> b2) & 1u) && v2 != kUnreached ? v2 + kDiag : kUnreached;
     const double inf = __builtin_huge_val();
-    uint64_t best = cur;
-    double bk = cur == kUnreached ? inf : pair_cost(cur);
-    const double k0 = c0 == kUnreached ? inf : pair_cost(c0);
-    const double k1 = c1 == kUnreached ? inf : pair_cost(c1);
-    const double k2 = c2 == kUnreached ? inf : pair_cost(c2);
-    if (k0 < bk) { best = c0; bk = k0; }
-    if (k1 < bk) { best = c1; bk = k1; }
-    if (k2 < bk) best = c2;
-    return best;
+    const uint64_t c0 = v0 + kOrth, c1 = v1 + kDiag, c2 = v2 + kDiag;
+    const double kc = cur == kUnreached ? inf : pair_cost(cur);
+    const double k0 = ((m >> b0) & 1u) && v0 != kUnreached ? pair_cost(c0) : inf;
+    const double k1 = ((m >> b1) & 1u) && v1 != kUnreached ? pair_cost(c1) : inf;
+    const double k2 = ((m >> b2) & 1u) && v2 != kUnreached ? pair_cost(c2) : inf;
+    const bool t0 = k0 < kc, t1 = k2 < k1;
+    const uint64_t p01 = t0 ? c0 : cur, p12 = t1 ? c2 : c1;
+    const double q01 = t0 ? k0 : kc, q12 = t1 ? k2 : k1;
+    return q12 < q01 ? p12 : p01;
 }
 
 // The value of lane l - 1 (from_below) or l + 1 (from_above) in the wave;
