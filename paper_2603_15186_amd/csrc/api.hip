@@ -1736,10 +1736,11 @@ hgs_status hgs_trace_paths(hgs_ctx* c, void* stream, const uint8_t* nav, int32_t
     if (n > 0 && (!nav || !dist || !starts || !slots || !lengths || (cap > 0 && !paths)))
         return fail(c, HGS_E_INVALID, "bad query arrays");
     HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t stride = ((int64_t)nx * ny + 15) / 16 * 16;
     if (n > 0) {
-        if (hgs_status s = ensure(c, c->nav_steps, (size_t)n_goals * nx * ny)) return s;
+        if (hgs_status s = ensure(c, c->nav_steps, (size_t)n_goals * stride)) return s;
     }
-    TraceArgs a{nav, nx, ny, dist, n_goals, n, starts, slots, cap, paths, lengths, P<uint8_t>(c->nav_steps)};
+    TraceArgs a{nav, nx, ny, dist, n_goals, n, starts, slots, cap, paths, lengths, P<uint8_t>(c->nav_steps), stride};
     launch_trace(a, (hipStream_t)stream);
     HIP_TRY(c, hipGetLastError());
     return HGS_OK;

@@ -329,7 +329,8 @@ struct TraceArgs {
     int32_t cap;
     int32_t* paths;                  // device [n][cap]
     int32_t* lengths;                // device [n]
-    uint8_t* steps;                  // scratch [n_goals][ny][nx]: each cell's move
+    uint8_t* steps;                  // scratch [n_goals][stride]: each cell's move
+    int64_t stride;                  // bytes per goal: nx * ny rounded up to 16
 };
 int dist_tile();
 void launch_navigable(const NavArgs& a, hipStream_t s);

@@ -371,32 +371,103 @@ __global__ __launch_bounds__(kNT) void k_steps(TraceArgs a) {
                 }
             }
         }
-        a.steps[k] = step;
+        a.steps[(k / N) * a.stride + c] = step;
     }
 }
 
-__global__ __launch_bounds__(kNT) void k_trace(TraceArgs a) {
+// Walk of query q from cell s down its field's moves (rd(c): the move of
+// cell c), storing up to cap cells; returns the path's cell count, or -1
+// when a cell has no move (dist is then no distance field).  When rows of
+// paths are 16-byte aligned the cells go out four at a time (the last four
+// kept in registers), a quarter of the scattered stores.
+template <class Rd>
+__device__ __forceinline__ int32_t walk(const TraceArgs& a, int64_t q, int32_t s, Rd rd) {
     const int64_t N = (int64_t)a.nx * a.ny;
+    int32_t* out = a.paths + q * a.cap;
+    const bool vec = (a.cap & 3) == 0 && (reinterpret_cast<uintptr_t>(a.paths) & 15) == 0;
+    int64_t c = s, m = 0;
+    int32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;   // the last four cells, c3 the latest
+    bool ok = true;
+    for (;;) {
+        c0 = c1;
+        c1 = c2;
+        c2 = c3;
+        c3 = (int32_t)c;
+        if (!vec) {
+            if (m < a.cap) out[m] = c3;
+        } else if ((m & 3) == 3 && m < a.cap) {
+            *reinterpret_cast<int4*>(out + m - 3) = make_int4(c0, c1, c2, c3);
+        }
+        ++m;
+        const uint8_t st = rd(c);
+        if (st == kGoal) break;
+        if (st == kNone || m > N) {
+            ok = false;
+            break;
+        }
+        c += (int64_t)step_dy(st) * a.nx + step_dx(st);
+    }
+    if (vec) {                             // the cells after the last full four
+        const int r = (int)(m & 3);
+        if (r >= 3 && m - 3 < a.cap) out[m - 3] = c1;
+        if (r >= 2 && m - 2 < a.cap) out[m - 2] = c2;
+        if (r >= 1 && m - 1 < a.cap) out[m - 1] = c3;
+    }
+    return ok ? (int32_t)m : -1;
+}
+
+__device__ __forceinline__ bool query_ok(const TraceArgs& a, int32_t s, int32_t slot) {
+    const int64_t N = (int64_t)a.nx * a.ny;
+    return slot >= 0 && slot < a.n_goals && s >= 0 && s < N && a.dist[(size_t)slot * N + s] != kUnreached;
+}
+
+// One query per thread, the moves read from global memory (L2).
+__global__ __launch_bounds__(kNT) void k_trace(TraceArgs a) {
     for (int64_t q = blockIdx.x * (int64_t)kNT + threadIdx.x; q < a.n; q += (int64_t)gridDim.x * kNT) {
         const int32_t s = a.starts[q], slot = a.slots[q];
         int32_t len = 0;
-        if (slot >= 0 && slot < a.n_goals && s >= 0 && s < N && a.dist[(size_t)slot * N + s] != kUnreached) {
-            const uint8_t* S = a.steps + (size_t)slot * N;
-            int64_t c = s, m = 0;
-            for (;;) {
-                if (m < a.cap) a.paths[q * a.cap + m] = (int32_t)c;
-                ++m;
-                const uint8_t st = S[c];
-                if (st == kGoal) break;
-                if (st == kNone || m > N) {          // no distance field
-                    m = -1;
-                    break;
-                }
-                c += (int64_t)step_dy(st) * a.nx + step_dx(st);
-            }
-            len = (int32_t)m;
+        if (query_ok(a, s, slot)) {
+            const uint8_t* S = a.steps + (size_t)slot * a.stride;
+            len = walk(a, q, s, [&](int64_t c) { return S[c]; });
         }
         a.lengths[q] = len;
+    }
+}
+
+// kTraceSplit workgroups per goal, each with the goal's moves staged in LDS
+// (a walk step then waits for an LDS read rather than an L2 round trip).
+// Workgroup part gathers the goal's queries q with q % kTraceSplit == part,
+// in passes of kTraceList queries, and walks them one per thread, so a
+// goal's walks spread over kTraceSplit compute units; the workgroups of
+// goal 0 also end the queries of no goal.
+constexpr int kTraceTable = 128 * 1024;    // bytes: the grids whose moves fit
+constexpr int kTraceList = 4096;
+constexpr int kTraceSplit = 8;
+
+__global__ __launch_bounds__(kNT) void k_trace_lds(TraceArgs a) {
+    __shared__ __align__(16) uint8_t L[kTraceTable];
+    __shared__ int32_t list[kTraceList];
+    __shared__ uint32_t cnt;
+    const int g = blockIdx.x / kTraceSplit, part = blockIdx.x % kTraceSplit;
+    const uint4* src = reinterpret_cast<const uint4*>(a.steps + (size_t)g * a.stride);
+    for (int k = threadIdx.x; k < (int)(a.stride / 16); k += kNT) reinterpret_cast<uint4*>(L)[k] = src[k];
+    for (int64_t base = 0; base < a.n; base += kTraceList) {
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();                   // (first pass: also the staged moves)
+        const int64_t end = min(a.n, base + (int64_t)kTraceList);
+        for (int64_t q = base + part + (int64_t)threadIdx.x * kTraceSplit; q < end; q += kNT * kTraceSplit) {
+            const int32_t slot = a.slots[q];
+            if (slot == g || (g == 0 && (slot < 0 || slot >= a.n_goals)))
+                list[atomicAdd(&cnt, 1u)] = (int32_t)(q - base);
+        }
+        __syncthreads();
+        const uint32_t k = cnt;
+        for (uint32_t i = threadIdx.x; i < k; i += kNT) {
+            const int64_t q = base + list[i];
+            const int32_t s = a.starts[q], slot = a.slots[q];
+            a.lengths[q] = query_ok(a, s, slot) ? walk(a, q, s, [&](int64_t c) { return L[c]; }) : 0;
+        }
+        __syncthreads();                   // list and count are reused
     }
 }
 
@@ -426,7 +497,12 @@ void launch_dist_rounds(const DistArgs& d, int round0, int n_rounds, hipStream_t
 void launch_trace(const TraceArgs& a, hipStream_t s) {
     if (a.n == 0) return;
     k_steps<<<grid_for((int64_t)a.nx * a.ny * a.n_goals), kNT, 0, s>>>(a);
-    k_trace<<<grid_for(a.n), kNT, 0, s>>>(a);
+    // moves in LDS when a goal's fit and every workgroup's scan of the
+    // queries stays small
+    if (a.stride <= kTraceTable && (int64_t)a.n_goals * kTraceSplit * a.n <= ((int64_t)1 << 26))
+        k_trace_lds<<<a.n_goals * kTraceSplit, kNT, 0, s>>>(a);
+    else
+        k_trace<<<grid_for(a.n), kNT, 0, s>>>(a);
 }
 
 }  // namespace hgs

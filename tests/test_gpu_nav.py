@@ -87,6 +87,35 @@ def test_trajectories_bit_exact(R):
     assert (wl > 0).sum() > 1000
 
 
+@pytest.mark.parametrize("ny,nx,n", [(96, 130, 9000), (340, 400, 2500)])
+def test_trajectories_many_queries_and_large_grids(R, ny, nx, n):
+    """More queries than one gathering pass of the per-goal walk holds
+    (9,000 over 4 goals), and a grid whose moves do not fit in LDS
+    (136,000 cells), which the one-query-per-thread walk serves."""
+    rng = np.random.default_rng(ny + nx + n)
+    nav = _random_nav(rng, ny, nx, 0.25)
+    free = np.flatnonzero(nav)
+    goals = rng.choice(free, size=4, replace=False)
+    navd = torch.from_numpy(nav).cuda()
+    dist, _ = R.distance_fields(navd, goals)
+    want_d = O.distance_fields(nav, goals)
+    np.testing.assert_array_equal(_pairs(dist), want_d)
+    starts = rng.choice(free, size=n).astype(np.int32)
+    slots = rng.integers(-1, 5, size=n).astype(np.int32)
+    cap = 900
+    paths, lens = R.trace_paths(navd, dist, torch.from_numpy(starts).cuda(), torch.from_numpy(slots).cuda(), cap)
+    torch.cuda.synchronize()
+    ok = (slots >= 0) & (slots < 4)
+    wp, wl = O.trace_paths(nav, want_d, starts, np.clip(slots, 0, 3), cap)
+    wl = np.where(ok, wl, 0)
+    np.testing.assert_array_equal(lens.cpu().numpy(), wl)
+    gp = paths.cpu().numpy()
+    for q in np.flatnonzero(wl > 0):
+        k = min(int(wl[q]), cap)
+        np.testing.assert_array_equal(gp[q, :k], wp[q, :k], err_msg=f"query {q}")
+    assert (wl > 0).sum() > n // 2
+
+
 def test_navigable_map_matches_oracle(R):
     rng = np.random.default_rng(21)
     m = (rng.uniform(size=(83, 61)) < 0.02).astype(np.uint8)
