@@ -1656,7 +1656,7 @@ hgs_status check_grid(hgs_ctx* c, int32_t nx, int32_t ny) {
     return HGS_OK;
 }
 
-constexpr int kNavBatch = 16;          // relaxation rounds between convergence checks
+constexpr int kNavBatch = 32;          // relaxation rounds between convergence checks (settled rounds return at once)
 constexpr int64_t kNavMaxRounds = 1 << 22;
 
 }  // namespace
