@@ -387,7 +387,7 @@ __device__ __forceinline__ int32_t walk(const TraceArgs& a, int64_t q, int32_t s
     const bool vec = (a.cap & 3) == 0 && (reinterpret_cast<uintptr_t>(a.paths) & 15) == 0;
     int64_t c = s, m = 0;
     int32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;   // the last four cells, c3 the latest
-    bool ok = true;
+    uint32_t st;
     for (;;) {
         c0 = c1;
         c1 = c2;
@@ -399,12 +399,8 @@ __device__ __forceinline__ int32_t walk(const TraceArgs& a, int64_t q, int32_t s
             *reinterpret_cast<int4*>(out + m - 3) = make_int4(c0, c1, c2, c3);
         }
         ++m;
-        const uint8_t st = rd(c);
-        if (st == kGoal) break;
-        if (st == kNone || m > N) {
-            ok = false;
-            break;
-        }
+        st = rd(c);
+        if (st >= kGoal || m > N) break;      // kGoal and kNone are the codes above the moves
         c += (int64_t)step_dy(st) * a.nx + step_dx(st);
     }
     if (vec) {                             // the cells after the last full four
@@ -413,7 +409,7 @@ __device__ __forceinline__ int32_t walk(const TraceArgs& a, int64_t q, int32_t s
         if (r >= 2 && m - 2 < a.cap) out[m - 2] = c2;
         if (r >= 1 && m - 1 < a.cap) out[m - 1] = c3;
     }
-    return ok ? (int32_t)m : -1;
+    return st == kGoal ? (int32_t)m : -1;
 }
 
 __device__ __forceinline__ bool query_ok(const TraceArgs& a, int32_t s, int32_t slot) {
