@@ -29,16 +29,26 @@ MODE_THRESHOLD = 1
 DEFAULT_EPS = (1e-4, 1e-4, 5e-4)
 
 
-def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (FP64, no FMA contraction, OpenMP)."""
-    stale = not os.path.exists(LIB_PATH) or any(os.path.getmtime(LIB_PATH) < os.path.getmtime(f) for f in SOURCES)
+# The compiler flags that define the oracle's arithmetic.
+CFLAGS = ["-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
+
+# HGS_ORACLE_LIB names another build of the same sources to load instead (the
+# sanitizer test points it at an address/undefined-behaviour sanitized build).
+SAN_ENV = "HGS_ORACLE_LIB"
+
+
+def build(force: bool = False, out: str = LIB_PATH, extra=()) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP) into
+    `out`; `extra` adds flags (e.g. sanitizers) to the optimised build."""
+    if os.environ.get(SAN_ENV) and out == LIB_PATH and not force:
+        return os.environ[SAN_ENV]
+    stale = not os.path.exists(out) or any(os.path.getmtime(out) < os.path.getmtime(f) for f in SOURCES)
     if force or stale:
-        tmp = LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-fPIC", "-shared", *SOURCES, "-o", tmp, "-lm"]
+        tmp = out + ".tmp"
+        cmd = ["gcc", "-O2", *CFLAGS, *extra, *SOURCES, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+        os.replace(tmp, out)
+    return out
 
 
 class _Camera(ctypes.Structure):
@@ -69,8 +79,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(LIB_PATH)
+        L = ctypes.CDLL(build())
         P = ctypes.c_void_p
         L.or_cut.restype = ctypes.c_int64
         L.or_cut.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.POINTER(_Camera),

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhgs.so")
 SOURCES = ["api.hip", "cut.hip", "project.hip", "sort.hip", "composite.hip", "mlp.hip", "imgutil.hip", "surfaces.hip",
-           "slice.hip", "nav.hip", "backward.hip"]
+           "slice.hip", "nav.hip", "backward.hip", "validate.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -29,7 +29,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     procs = []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(bdir, src.replace(".hip", ".o"))
+        obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         cmd = [HIPCC, *FLAGS, "-c", "-I", INCLUDE, "-I", CSRC, os.path.join(CSRC, src), "-o", obj]
         cmd.remove("-shared")

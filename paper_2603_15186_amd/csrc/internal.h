@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "hgs.h"
+#include "validate.h"
 
 namespace hgs {
 
@@ -23,9 +24,6 @@ constexpr int kMaxViews = 4096;
 constexpr int kNtShift = 28;
 constexpr uint32_t kEntryMask = (1u << kNtShift) - 1u;
 constexpr uint32_t kNtSat = 15u;
-
-// Hierarchy levels the scene validation allows.
-constexpr int kMaxLevels = 64;
 
 // Overflow bits in Counters::overflow.
 constexpr uint32_t kOvFrontier = 1u;

@@ -19,7 +19,9 @@ TOL_DEPTH_REL = 2e-4
 def branch_errors(gpu, res):
     """gpu: (n, 5) float array (R, G, B, depth, alpha) for the oracle's
     pixels.  Returns (ok mask, best normalised error per pixel, skipped mask)
-    where the normalised error is max over outputs of |diff| / tolerance."""
+    where the normalised error is max over outputs of |diff| / tolerance.
+    A pixel whose branch list overflowed the oracle's fork cap (skipped) is
+    not complete, so it counts as a failure."""
     br = res.branches                                    # (n, cap, 5)
     nb = res.nbranch
     cap = br.shape[1]
@@ -31,7 +33,7 @@ def branch_errors(gpu, res):
     e = np.where(valid, e, np.inf)
     best = e.min(axis=1)
     skipped = res.flags != 0
-    ok = (best <= 1.0) | skipped
+    ok = (best <= 1.0) & ~skipped
     return ok, best, skipped
 
 

@@ -46,7 +46,7 @@ def _render(r, scene, cams, mode=1, tau=1.0, **opts):
     return [(a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()) for a, b, c in outs]
 
 
-def _check_full(img, scene, cam, mode=O.MODE_THRESHOLD, tau=1.0, ids=None, max_skip=0.002):
+def _check_full(img, scene, cam, mode=O.MODE_THRESHOLD, tau=1.0, ids=None):
     res, _, _ = O.render(scene, cam, mode, tau, ids=ids)
     px, py = res.px, res.py
     g = parity.gpu_pixels(*img, px, py)
@@ -54,7 +54,7 @@ def _check_full(img, scene, cam, mode=O.MODE_THRESHOLD, tau=1.0, ids=None, max_s
     msg = parity.summary(ok, best, skipped)
     print(msg, flush=True)
     assert ok.all(), msg
-    assert skipped.mean() <= max_skip, msg
+    assert not skipped.any(), msg
     return res
 
 
@@ -379,7 +379,7 @@ def test_plan2m_sampled_pixel_parity(R, plan_full):
         msg = parity.summary(ok, best, skipped)
         print(i, msg, flush=True)
         assert ok.all(), msg
-        assert skipped.mean() <= 0.002, msg
+        assert not skipped.any(), msg
 
 
 def test_graph_replays_match_eager_render(R, plan_small):
