@@ -269,6 +269,7 @@ def train_pipeline(r: hgs.Renderer, train_cams, calib_n=64, per_view=256, epochs
     master, bf16, mean, std, hist = train(r, feats, labels, epochs=epochs, seed=seed, log=log)
     model = LodModel(master, bf16, mean, std, 0.5, s_hi,
                      {"samples": st["sampled"], "refine_frac": st["refine"] / max(1, st["sampled"]),
+                      "first_loss": hist[0] if hist else float("nan"),
                       "final_loss": hist[-1] if hist else float("nan"), "epochs": epochs})
     step = max(1, len(train_cams) // calib_n)
     ccams = train_cams[::step][:calib_n]

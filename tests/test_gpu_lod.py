@@ -226,8 +226,12 @@ def test_training_pipeline_end_to_end(R, plan):
     R.load_scene(scene)
     R.set_surfaces(fp.surfaces)
     model = lod.train_pipeline(R, cams[:10], calib_n=4, per_view=128, epochs=15, seed=0, s_hi=256.0)
+    print(model.info, model.p_star, flush=True)
     assert model.info["samples"] > 100
-    assert 0.0 <= model.p_star <= 0.9
+    assert model.info["final_loss"] < model.info["first_loss"]
+    # calibration found a threshold p* at which the network keeps some
+    # candidates (p* = 0 would be the threshold cut, the fallback)
+    assert 0.0 < model.p_star <= 0.95
     assert model.info["calib_loss_db"] <= lod.TARGET_TRAIN_DB + 1e-9
 
 
@@ -387,3 +391,137 @@ def test_building_batch_at_full_size(R, building):
         R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
     del outs
     torch.cuda.empty_cache()
+
+
+# ------------------------- the timed path: graph replays across pose batches
+
+def _render_batches(R, hgs, batches, outs, stream=None, sync=True):
+    for b in batches:
+        R.set_cameras(b)
+        R.render(outs, stream)
+    if sync:
+        torch.cuda.synchronize()
+
+
+def test_graph_replay_follows_pose_changes(R, plan_lod):
+    """The benchmark's timed loop: one graph captured on a 50-view batch is
+    replayed for other 50-view batches of the same layout, the cameras set
+    between replays (poses live in device memory uploaded before each
+    launch).  After replays over several batches, asynchronously and
+    synchronously, the images equal eager renders of the last batch bit for
+    bit and its cut equals the oracle's, for the threshold and the learned
+    cut."""
+    from paper_2603_15186_amd import hgs, lod
+    scene, held = plan_lod
+    model = lod.LodModel.load(lod.default_model_path())
+    R.load_scene(scene)
+    model.install(R)
+    A, B, C = held[:50], held[50:100], held[100:150]
+    rng = np.random.default_rng(21)
+    stream = torch.cuda.current_stream()
+    for mode in (hgs.HGS_LOD_THRESHOLD, hgs.HGS_LOD_LEARNED):
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+        R.set_lod(mode, 1.0)
+        R.set_cameras(C)
+        eager = R.alloc_outputs()
+        R.render(eager)
+        torch.cuda.synchronize()
+        want = [[t.cpu().numpy() for t in o] for o in eager]
+        cuts = {v: R.get_cut(v) for v in (3, 44)}
+        outs = R.alloc_outputs()
+        R.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
+        try:
+            _render_batches(R, hgs, [A, A], outs)                  # capture, then replay
+            g0 = R.stats()["graph_launches"]
+            R.set_option(hgs.HGS_OPT_SYNC_CHECK, 0)
+            _render_batches(R, hgs, [B, C, A, B, C], outs, stream)  # as the timed loop does
+            assert R.check() == hgs.HGS_OK
+            R.set_option(hgs.HGS_OPT_SYNC_CHECK, 1)
+            assert R.stats()["graph_launches"] == g0 + 5
+            for v in range(50):
+                for got, w in zip(outs[v], want[v]):
+                    np.testing.assert_array_equal(got.cpu().numpy(), w, err_msg=f"mode {mode} view {v}")
+            _render_batches(R, hgs, [B, C], outs)
+            assert R.stats()["graph_launches"] == g0 + 7
+            for v in (0, 17, 49):
+                for got, w in zip(outs[v], want[v]):
+                    np.testing.assert_array_equal(got.cpu().numpy(), w)
+            for v, want_cut in cuts.items():
+                got = R.get_cut(v)
+                np.testing.assert_array_equal(got, want_cut)
+                if mode == hgs.HGS_LOD_THRESHOLD:
+                    np.testing.assert_array_equal(got, O.cut(scene, C[v], O.MODE_THRESHOLD, 1.0))
+                else:
+                    _check_learned_view(scene, model, C[v], got, [t.cpu().numpy() for t in outs[v]], rng, n_px=500)
+        finally:
+            R.set_option(hgs.HGS_OPT_SYNC_CHECK, 1)
+            R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+
+
+@pytest.fixture(scope="module")
+def plan_lod_surfaces():
+    scene, _, held, fp = W.plan2m_lod(with_plan=True)
+    return scene, held, fp
+
+
+def _ms_per_batch(R, hgs, batches, outs, steps=20):
+    """Graph-replayed batches as the benchmark times them (HIP events on the
+    stream, cameras set between replays)."""
+    stream = torch.cuda.current_stream()
+    R.set_option(hgs.HGS_OPT_USE_GRAPH, 1)
+    _render_batches(R, hgs, batches * 2, outs)
+    R.set_option(hgs.HGS_OPT_SYNC_CHECK, 0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(3):
+        e0.record(stream)
+        for i in range(steps):
+            R.set_cameras(batches[i % len(batches)])
+            R.render(outs, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / steps)
+    assert R.check() == hgs.HGS_OK
+    R.set_option(hgs.HGS_OPT_SYNC_CHECK, 1)
+    R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+    return float(np.median(times))
+
+
+def test_learned_cut_gains_over_the_threshold_cut(R, plan_lod_surfaces):
+    """What the trained network gains (the committed checkpoint, 100 held-out
+    720p poses, PSNR against the ray-cast ground truth of the synthetic
+    surfaces): its cut is at most 0.6 of the tau = 1 cut at a PSNR loss of
+    at most 0.1 dB, and it is smaller and renders faster than the threshold
+    cut at the coarsest tau whose loss is no larger (the method without the
+    network, tuned to the same quality)."""
+    from paper_2603_15186_amd import hgs, lod
+    scene, held, fp = plan_lod_surfaces
+    cams = held[:100]
+    R.load_scene(scene)
+    R.set_surfaces(fp.surfaces)
+    model = lod.LodModel.load(lod.default_model_path())
+    assert model.p_star > 0.0
+    refs = lod.reference_images(R, cams)
+    base_psnr, base_cut, _ = lod.evaluate(R, cams, refs, None, tau=1.0)
+    learn_psnr, learn_cut, _ = lod.evaluate(R, cams, refs, model)
+    loss = base_psnr - learn_psnr
+    tau_m, loss_m, cut_m = lod.tau_matched(R, cams, refs, base_psnr, max(loss, 0.0))
+    del refs
+    print(f"PSNR tau=1 {base_psnr:.3f} learned {learn_psnr:.3f} (loss {loss:.3f} dB), cut {learn_cut / base_cut:.3f}"
+          f" of tau=1; matched tau {tau_m:.2f} loss {loss_m:.3f} cut {cut_m / base_cut:.3f}", flush=True)
+    assert loss <= 0.1
+    assert learn_cut <= 0.6 * base_cut
+    assert cut_m is not None and learn_cut < cut_m
+    batches = [cams[:50], cams[50:]]
+    R.set_cameras(batches[0])
+    outs = R.alloc_outputs()
+    model.install(R)
+    R.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
+    ms_learned = _ms_per_batch(R, hgs, batches, outs)
+    R.set_lod(hgs.HGS_LOD_THRESHOLD, tau_m)
+    ms_matched = _ms_per_batch(R, hgs, batches, outs)
+    R.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
+    ms_tau1 = _ms_per_batch(R, hgs, batches, outs)
+    print(f"ms per 50-view batch: learned {ms_learned:.3f}, tau-matched {ms_matched:.3f}, tau=1 {ms_tau1:.3f}",
+          flush=True)
+    assert ms_learned < ms_matched < ms_tau1

@@ -183,3 +183,44 @@ def test_floor_plan_planning_matches_oracle(R, plan_maps):
     for q in range(starts.size):
         np.testing.assert_array_equal(gp[q, :wl[q]], wp[q, :wl[q]])
     print(f"navigable {nav.mean():.3f}, {rounds} rounds, path cells mean {wl.mean():.1f} max {wl.max()}", flush=True)
+
+
+def test_serpentine_corridor_needs_several_round_batches(R):
+    """A corridor that winds back and forth across the grid (walls every
+    fourth row, the gap alternating between the two ends), so a field
+    crosses tile boundaries hundreds of times: more than two batches of the
+    relaxation rounds between the host's convergence checks, with fields
+    and trajectories still bit-exact against the oracle."""
+    ny, nx = 131, 150
+    nav = np.ones((ny, nx), np.uint8)
+    for k, j in enumerate(range(3, ny - 1, 4)):
+        nav[j, :] = 0
+        if k % 2:
+            nav[j, :2] = 1
+        else:
+            nav[j, -2:] = 1
+    goals = [0, (ny // 2) * nx + nx // 2, ny * nx - 1]
+    assert all(nav.flat[g] for g in goals)
+    navd = torch.from_numpy(nav).cuda()
+    dist, rounds = R.distance_fields(navd, goals)
+    torch.cuda.synchronize()
+    want = O.distance_fields(nav, goals)
+    np.testing.assert_array_equal(_pairs(dist), want)
+    print(f"serpentine {ny}x{nx}: {rounds} rounds", flush=True)
+    assert rounds > 64
+    assert (want[..., 0] >= 0).all(axis=0)[nav > 0].all()     # one connected corridor
+    rng = np.random.default_rng(5)
+    free = np.flatnonzero(nav)
+    n = 600
+    starts = rng.choice(free, size=n).astype(np.int32)
+    slots = rng.integers(0, len(goals), size=n).astype(np.int32)
+    cap = 8192
+    paths, lens = R.trace_paths(navd, dist, torch.from_numpy(starts).cuda(), torch.from_numpy(slots).cuda(), cap)
+    torch.cuda.synchronize()
+    wp, wl = O.trace_paths(nav, want, starts, slots, cap)
+    np.testing.assert_array_equal(lens.cpu().numpy(), wl)
+    gp = paths.cpu().numpy()
+    for q in range(n):
+        k = min(int(wl[q]), cap)
+        np.testing.assert_array_equal(gp[q, :k], wp[q, :k], err_msg=f"query {q}")
+    assert wl.max() > 2000
