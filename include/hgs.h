@@ -266,6 +266,22 @@ hgs_status hgs_autotune(hgs_ctx* ctx, void* stream, const char* cache_path, int3
 hgs_status hgs_sort_pairs(hgs_ctx* ctx, void* stream, uint32_t* keys, uint32_t* vals,
                           int64_t n, int32_t key_bits);
 
+/* Most pairs hgs_sort_pairs_noalloc sorts. */
+#define HGS_SORT_NOALLOC_MAX 4194304
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the sort
+ * of hgs_sort_pairs -- the same order, stable, by the low key_bits bits,
+ * digits of up to HGS_OPT_SORT_DIGIT_BITS bits -- without allocating
+ * anything.  keys/vals are n caller-owned device uint32 arrays, sorted in
+ * place; 0 <= n <= HGS_SORT_NOALLOC_MAX, else HGS_E_INVALID (nothing is
+ * launched).  Its scratch memory (about 36 MB) is one static device array
+ * per GPU, shared by every context and call on that GPU and held until the
+ * process ends: calls that overlap in time on one GPU race.  Asynchronous
+ * on `stream` (no synchronisation, so it may be captured). */
+hgs_status hgs_sort_pairs_noalloc(hgs_ctx* ctx, void* stream, uint32_t* keys, uint32_t* vals,
+                                  int64_t n, int32_t key_bits);
+
 /* ---------------------------------------------------------------------- */
 /* Learned level-of-detail refinement.  The paper's LOD rendering picks     */
 /* Gaussians from different tree levels (NavGSim Sec. III-B); the learned  */

@@ -10,6 +10,7 @@
 #include <string>
 #include <array>
 #include <vector>
+#include <mutex>
 
 #include "internal.h"
 #include "lod_mlp.h"
@@ -116,6 +117,7 @@ struct hgs_ctx {
     bool last_blend = false;
     bool last_keep = false;           // the last render kept its pixel states (px_state)
     uint32_t* nav_active_host = nullptr;   // pinned
+    void* scratch = nullptr;          // this device's static scratch area (hgs_sort_pairs_noalloc)
 };
 
 namespace {
@@ -621,6 +623,60 @@ hgs_status time_plan(hgs_ctx* c, hipStream_t s, const hgs_output* outs, int reps
 
 extern "C" {
 
+// ------------------------------------------------ static scratch memory
+
+namespace {
+
+// hgs_sort_pairs_noalloc sorts in a fixed area that every context on a GPU
+// shares: the second key and value arrays of the ping-pong, the element
+// count and the digit histograms of at most kStaticSortGroups groups.
+constexpr uint32_t kStaticSortMax = HGS_SORT_NOALLOC_MAX;
+constexpr uint32_t kStaticSortGroups = kStaticSortMax / kSortGroup;
+static_assert(kStaticSortMax % kSortGroup == 0, "whole histogram groups");
+constexpr size_t kScratchPing = (size_t)kStaticSortMax * 4;
+constexpr size_t kScratchHistOff = 2 * kScratchPing + 256;
+constexpr size_t kScratchBytes = kScratchHistOff + (size_t)kSortBins * (kStaticSortGroups + 1) * 4;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+// One copy per GPU, held until the process ends.  Host code never uses this
+// name as an address: each device's address comes from hipGetSymbolAddress.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, which must be current;
+// looked up once per device.
+hipError_t scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+
+__global__ void k_set_count(uint32_t* count, uint32_t n) {
+    if (threadIdx.x == 0) *count = n;
+}
+
+__global__ void k_copy_pairs(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ vs, uint32_t* kd,
+                             uint32_t* vd, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        kd[i] = ks[i];
+        vd[i] = vs[i];
+    }
+}
+
+}  // namespace
+
 hgs_status hgs_create(int32_t device, hgs_ctx** out) {
     if (!out) return HGS_E_INVALID;
     *out = nullptr;
@@ -629,11 +685,17 @@ hgs_status hgs_create(int32_t device, hgs_ctx** out) {
         (void)hipGetLastError();
         return HGS_E_HIP;
     }
-    if (device < 0 || device >= nd) return HGS_E_INVALID;
+    if (device < 0 || device >= nd || device >= kMaxDevices) return HGS_E_INVALID;
     if (hipSetDevice(device) != hipSuccess) return HGS_E_HIP;
+    void* scr = nullptr;
+    if (scratch_address(device, &scr) != hipSuccess) {
+        (void)hipGetLastError();
+        return HGS_E_HIP;
+    }
     hgs_ctx* c = new (std::nothrow) hgs_ctx();
     if (!c) return HGS_E_OOM;
     c->device = device;
+    c->scratch = scr;
     if (ensure(c, c->counters, sizeof(Counters) * kMaxViews) != HGS_OK ||
         hipHostMalloc((void**)&c->ctr_host, sizeof(Counters) * kMaxViews, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->views_copied, hipEventDisableTiming) != hipSuccess ||
@@ -1296,6 +1358,40 @@ hgs_status hgs_sort_pairs(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* va
     }
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(s));
+    return HGS_OK;
+}
+
+hgs_status hgs_sort_pairs_noalloc(hgs_ctx* c, void* stream, uint32_t* keys, uint32_t* vals, int64_t n,
+                                  int32_t key_bits) {
+    if (!c || (!keys && n > 0) || (!vals && n > 0)) return HGS_E_INVALID;
+    if (n < 0 || n > (int64_t)kStaticSortMax)
+        return fail(c, HGS_E_INVALID, "n = %lld is outside 0..%u, the pairs the static scratch area holds",
+                    (long long)n, kStaticSortMax);
+    if (key_bits < 1 || key_bits > 32) return fail(c, HGS_E_INVALID, "key_bits must be 1..32");
+    if (n == 0) return HGS_OK;
+    if (!c->scratch) return fail(c, HGS_E_STATE, "no scratch address for device %d", c->device);
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* base = static_cast<uint8_t*>(c->scratch);
+    SortArgs a{};
+    a.keys[0] = keys;
+    a.keys[1] = reinterpret_cast<uint32_t*>(base);
+    a.vals[0] = vals;
+    a.vals[1] = reinterpret_cast<uint32_t*>(base + kScratchPing);
+    uint32_t* count = reinterpret_cast<uint32_t*>(base + 2 * kScratchPing);
+    a.count = count;
+    a.cap = (uint32_t)n;
+    a.key_bits = key_bits;
+    a.max_digit_bits = c->sort_digit_bits;
+    a.hist = reinterpret_cast<uint32_t*>(base + kScratchHistOff);
+    a.hist_stride = kStaticSortGroups;
+    // the count of the previous call is still there: every call writes its own
+    k_set_count<<<1, 64, 0, s>>>(count, (uint32_t)n);
+    if (launch_sort(a, s) == 1) {
+        const uint32_t grid = std::min<uint32_t>((uint32_t)((n + 255) / 256), 2048u);
+        k_copy_pairs<<<grid, 256, 0, s>>>(a.keys[1], a.vals[1], keys, vals, (uint32_t)n);
+    }
+    HIP_TRY(c, hipGetLastError());
     return HGS_OK;
 }
 

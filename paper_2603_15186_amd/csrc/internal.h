@@ -197,7 +197,8 @@ struct SortArgs {
     uint32_t cap;
     int key_bits;
     int max_digit_bits = 11;         // 6..11
-    uint32_t* hist;                  // kSortHistBytes
+    uint32_t* hist;                  // kSortBins * (hist_stride + 1) counts
+    uint32_t hist_stride = kSortMaxGroups;   // per-digit row of hist: at least the sort's group count
 };
 int launch_sort(const SortArgs& a, hipStream_t s);
 

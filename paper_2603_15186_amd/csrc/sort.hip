@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kNT) void k_downsweep(const uint32_t* __restrict__ 
 template <int DB>
 void pass(const SortArgs& a, int cur, int shift, int nbits, hipStream_t s) {
     const int G = kSortBlocks;
-    const uint32_t stride = kSortMaxGroups;
+    const uint32_t stride = a.hist_stride;
     uint32_t* hist = a.hist;
     uint32_t* totals = a.hist + (size_t)kSortBins * stride;
     const uint32_t mask = nbits >= 32 ? 0xffffffffu : ((1u << nbits) - 1u);

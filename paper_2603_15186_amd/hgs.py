@@ -22,6 +22,7 @@ HGS_E_HIP = -4
 HGS_E_CAPACITY = -5
 HGS_E_BAD_HIERARCHY = -6
 HGS_E_UNSUPPORTED = -7
+HGS_SORT_NOALLOC_MAX = 4194304
 
 HGS_LOD_ALL_LEAVES = 0
 HGS_LOD_THRESHOLD = 1
@@ -122,6 +123,7 @@ EXPORTS = [
     ("hgs_get_stats", ctypes.c_int32, [_P, ctypes.POINTER(hgs_stats)]),
     ("hgs_autotune", ctypes.c_int32, [_P, _P, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(hgs_plan)]),
     ("hgs_sort_pairs", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32]),
+    ("hgs_sort_pairs_noalloc", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32]),
     ("hgs_set_keep_nodes", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
     ("hgs_lod_candidates", ctypes.c_int32, [_P, _P, ctypes.c_float, _P, _P, _P, ctypes.c_int64,
                                             ctypes.POINTER(ctypes.c_int64)]),
@@ -546,6 +548,15 @@ class Renderer:
                                              dist.data_ptr(), int(dist.shape[0]), int(n), starts.data_ptr(),
                                              slots.data_ptr(), int(cap), paths.data_ptr(), lens.data_ptr()))
         return paths[:, :cap], lens
+
+    def sort_pairs_noalloc(self, keys, vals, key_bits, stream=None):
+        """Sort device uint32 tensors (as int32 storage) in place in the
+        library's static scratch area (no allocation; asynchronous)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._check(self.lib.hgs_sort_pairs_noalloc(self.ctx, ctypes.c_void_p(stream.cuda_stream), keys.data_ptr(),
+                                                    vals.data_ptr(), keys.numel(), int(key_bits)))
 
     def sort_pairs(self, keys, vals, key_bits, stream=None):
         """Sort device uint32 tensors (as int32 storage) in place."""
