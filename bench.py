@@ -33,10 +33,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpixels/s at 720p: batched learned-LOD vs plain cut at ≤0.1 dB PSNR loss"
 FP32_PEAK_TFLOPS = 157.3
-# FP32 flops of one evaluated (pixel, Gaussian) pair in the compositor:
-# dx, dy (2), t1 (3), t2 (1), q (3), exponent scale (1), exp (1), alpha (1),
-# cap (1), T' (2), weight (1), three colour and one depth FMA (8).
-FLOPS_PER_PAIR = 24
+HBM_PEAK_GBS = 8000.0
+# Algorithmic FP32 vector operations of one evaluated (pixel, Gaussian) pair
+# in the compositor: dx, dy, q, the exponent scale -q/2 log2(e), exp2, alpha,
+# the 0.99 cap, two compares, T', the weight, three colour FMAs and one depth
+# FMA -- 21 lane operations.  Counting flops instead (an FMA as two, the
+# tile-relative offsets and conic factors written out) gives 24.
+OPS_PER_PAIR = 21
+FLOPS_PER_PAIR_ALT = 24
 TRAFFIC_FILE = "composite_traffic_plan2m_lod_50x720p.txt"
 
 
@@ -53,12 +57,16 @@ def parse():
     ap.add_argument("--poses", type=int, default=500, help="held-out poses cycled through")
     ap.add_argument("--single", type=int, default=100, help="poses timed on the single-view path")
     ap.add_argument("--model", default=None, help="learned-cut checkpoint (.npz)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--cpu-frames", type=int, default=8, help="held-out frames the CPU oracle renders")
+    ap.add_argument("--oracle-pixels", type=int, default=4000,
+                    help="building30m: pixels per quality view the oracle's full-leaf render computes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels instead of replaying a graph")
     ap.add_argument("--workload", default="plan2m-lod",
-                    choices=["plan2m-lod", "plan8m", "building30m", "slice", "nav", "backward"],
-                    help="plan2m-lod (the metric's workload), plan8m (256 mixed-resolution views of the "
+                    choices=["plan2m-lod", "box20k", "plan2m", "plan8m", "building30m", "slice", "nav", "backward"],
+                    help="plan2m-lod (the metric's workload), box20k (the flat 20k-Gaussian box, one 256x256 "
+                         "view), plan2m (the 2M-leaf plan's 200-pose trajectory, tau=1), plan8m (256 "
+                         "mixed-resolution views of the "
                          "8M-leaf plan, threshold cuts), building30m (64 1080p views of the 30M-leaf "
                          "two-floor building, learned cut), slice (GS-slice collision map of the 30M-leaf "
                          "building), nav (expert trajectories on the building's navigable maps) or backward "
@@ -72,32 +80,37 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(scene, cam, tau, budget_s):
-    """The FP64 oracle on one frame: full cut and projection, then
-    compositing of random pixels for about budget_s; the frame time is
-    extrapolated from the per-pixel time."""
-    import numpy as np
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_frames(scene, cams, model=None, tau=1.0):
+    """The FP64 oracle renders whole frames of `cams`: the threshold cut at
+    tau, or the learned cut of `model` (FP64 features and network), then
+    projection and per-pixel compositing of every pixel.  Returns (seconds,
+    pixels, Gaussians per frame)."""
+    from oracle import mlp as M
     from oracle import oracle as O
     t0 = time.perf_counter()
-    ids = O.cut(scene, cam, O.MODE_THRESHOLD, tau)
-    proj = O.project(scene, ids, cam)
-    t_fixed = time.perf_counter() - t0
-    rng = np.random.default_rng(0)
-    npx = cam.width * cam.height
-    done, t_pix, n = 0, 0.0, 256
-    while t_pix < budget_s and done < npx:
-        px = rng.integers(0, cam.width, n)
-        py = rng.integers(0, cam.height, n)
-        t1 = time.perf_counter()
-        O.render_pixels(proj, cam, px, py)
-        t_pix += time.perf_counter() - t1
-        done += n
-        n = min(n * 2, 1 << 16)
-    t_frame = t_fixed + t_pix * npx / done
-    return {"value": npx / t_frame / 1e6, "unit": "Mpixels/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"1 frame 1280x720 (threshold cut tau={tau}): full cut ({ids.size} Gaussians) + projection "
-                      f"({t_fixed:.2f} s), {done} random pixels composited ({t_pix:.2f} s), frame time "
-                      f"extrapolated to {t_frame:.1f} s"}
+    px, sizes = 0, []
+    for cam in cams:
+        if model is None:
+            ids = O.cut(scene, cam, O.MODE_THRESHOLD, tau)
+        else:
+            ids, _ = O.cut_learned(scene, cam, M.bf16_value(model.bf16), model.mean, model.std, model.p_star,
+                                   model.s_hi, tau=tau)
+        O.render(scene, cam, ids=ids)
+        px += cam.width * cam.height
+        sizes.append(int(ids.size))
+    return time.perf_counter() - t0, px, sizes
 
 
 def traffic_entry(kernel):
@@ -296,6 +309,117 @@ def run_backward(args):
     r.close()
 
 
+def composite_roofline(r, hgs, torch, batches, outs, steps):
+    """Compositor roofline of the batches as rendered now: evaluated pairs
+    per step (counted in an untimed pass) and the compositing kernel's mean
+    time (HIP events on the render stream, eager launches)."""
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+    r.set_option(hgs.HGS_OPT_COUNT_NALG, 1)
+    n_alg = n_eval = 0
+    for bt in batches:
+        r.set_cameras(bt)
+        r.render(outs)
+        st = r.stats()
+        n_alg += st["n_alg"]
+        n_eval += st["n_eval"]
+    r.set_option(hgs.HGS_OPT_COUNT_NALG, 0)
+    _, st = timed_loop(r, hgs, torch, batches, outs, steps, 1, True)
+    n = st["timed_renders"]
+    stage = {k: st["ms_" + k] / n for k in ("cut", "project", "sort", "composite")}
+    per_step = n_alg / len(batches)
+    achieved = OPS_PER_PAIR * per_step / (stage["composite"] * 1e-3) / 1e12
+    roof = {"kernel": "k_composite", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+            "ms_per_launch": stage["composite"], "n_alg_per_launch": per_step, "ops_per_pair": OPS_PER_PAIR}
+    return roof, stage, {"lane_efficiency": n_alg / max(n_eval, 1), "cut_entries": st["cut_size"],
+                         "pairs": st["pairs"]}
+
+
+def run_box20k(args):
+    """The flat scene: 20,000 Gaussians in a 4 x 4 x 3 m box, one 256 x 256
+    camera (f = 256) 1 m outside the box looking in; every render is the
+    whole path for that one view (no hierarchy), replayed from a graph."""
+    import torch
+    from paper_2603_15186_amd import hgs
+    from paper_2603_15186_amd.synth import workloads as W
+    scene, cams = W.box20k()
+    r = hgs.Renderer(0)
+    r.load_scene(scene)
+    r.set_cameras(cams)
+    outs = r.alloc_outputs()
+    px = cams[0].width * cams[0].height
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
+    ms, _ = timed_loop(r, hgs, torch, [cams], outs, args.steps, args.warmup, False)
+    roof, stage, info = composite_roofline(r, hgs, torch, [cams], outs, args.steps)
+    log(f"box20k: {ms * 1e3:.1f} us per frame, {px / (ms * 1e-3) / 1e6:.0f} Mpix/s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        t_cpu, npx, _ = oracle_frames(scene, cams)
+        cpu = {"value": npx / t_cpu / 1e6, "unit": "Mpixels/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"the whole 256x256 frame ({t_cpu:.2f} s); host CPU {cpu_model()}"}
+    out = {"metric": "Mpixels/s, flat 20k-Gaussian scene, one 256x256 view per render",
+           "value": px / (ms * 1e-3) / 1e6, "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "box20k: 20,000 Gaussians, 4x4x3 m box, one 256x256 view, f=256",
+                      "parallelism": "single GPU"},
+           "roofline": roof, "cpu_baseline": cpu,
+           "extra": {"stage_ms_eager": stage, **info}}
+    print(json.dumps(out), flush=True)
+    r.close()
+
+
+def run_plan2m(args):
+    """The 2M-leaf plan along its 200-pose robot trajectory at 1280x720 with
+    the tau = 1 threshold cut: batches of 50 consecutive poses in one call,
+    and the plain path of one view per call."""
+    import numpy as np
+    import torch
+    from paper_2603_15186_amd import hgs
+    from paper_2603_15186_amd.synth import workloads as W
+    scene, cams = W.plan2m()
+    r = hgs.Renderer(0)
+    r.load_scene(scene)
+    r.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
+    B = args.views
+    batches = [cams[i:i + B] for i in range(0, len(cams) - B + 1, B)]
+    px = B * cams[0].width * cams[0].height
+    r.set_cameras(batches[0])
+    outs = r.alloc_outputs()
+    r.autotune(reps=2)
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
+    ms, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
+    roof, stage, info = composite_roofline(r, hgs, torch, batches, outs, args.steps)
+    # plain single-view path over the whole trajectory
+    r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
+    r.set_cameras([cams[0]])
+    o1 = r.alloc_outputs()
+    ms1, _ = timed_loop(r, hgs, torch, [[c] for c in cams], o1, len(cams), 3, False)
+    px1 = cams[0].width * cams[0].height
+    log(f"plan2m: batched {ms:.3f} ms per {B} views ({px / (ms * 1e-3) / 1e6:.0f} Mpix/s), single view "
+        f"{ms1:.3f} ms ({px1 / (ms1 * 1e-3) / 1e6:.0f} Mpix/s)")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        sample = cams[::len(cams) // args.cpu_frames][:args.cpu_frames]
+        t_cpu, npx, sizes = oracle_frames(scene, sample)
+        cpu = {"value": npx / t_cpu / 1e6, "unit": "Mpixels/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"{len(sample)} of the 200 trajectory poses, whole frames (threshold cut tau=1, "
+                         f"{int(np.mean(sizes))} Gaussians per frame), {t_cpu:.1f} s; host CPU {cpu_model()}"}
+    out = {"metric": "Mpixels/s, 2M-leaf plan, 200-pose trajectory at 1280x720, threshold cut tau=1",
+           "value": px / (ms * 1e-3) / 1e6, "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"plan2m trajectory, {B} views per call, 1280x720 fx=900, tau=1",
+                      "nodes": scene.n, "parallelism": "single GPU"},
+           "roofline": roof, "cpu_baseline": cpu,
+           "extra": {"stage_ms_eager": stage, "single_view_ms": ms1, "single_view_mpix_s": px1 / (ms1 * 1e-3) / 1e6,
+                     "speedup_batched_vs_single": (px / ms) / (px1 / ms1), **info}}
+    print(json.dumps(out), flush=True)
+    r.close()
+
+
 def run_plan8m(args):
     """256 views (128 @ 320x240, 96 @ 640x480, 32 @ 1280x720) of the
     8M-leaf 40 x 30 m plan in one call, threshold cuts at tau 1, 2, 4."""
@@ -399,13 +523,46 @@ def run_building(args):
     sample = views[::8]
     full = lod.render_rgb(r, sample, hgs.HGS_LOD_ALL_LEAVES, 1.0)
     gt = lod.reference_images(r, sample)
-    q = {}
+    q, imgs = {}, {}
     for name, mode in (("learned", hgs.HGS_LOD_LEARNED), ("tau1", hgs.HGS_LOD_THRESHOLD)):
         img = lod.render_rgb(r, sample, mode, 1.0)
-        q[name] = {"psnr_vs_full_leaf_db": float(np.mean(lod.psnr(r, img, full))),
+        imgs[name] = [t.cpu().numpy() for t in img]
+        q[name] = {"psnr_vs_gpu_full_leaf_render_db": float(np.mean(lod.psnr(r, img, full))),
                    "psnr_vs_surfaces_db": float(np.mean(lod.psnr(r, img, gt)))}
         free, _ = torch.cuda.mem_get_info()
         peak = max(peak, total - free)
+    imgs["gpu_full_leaf"] = [t.cpu().numpy() for t in full]
+    del full, gt
+    torch.cuda.empty_cache()
+    # the FP64 oracle's full-leaf render (every leaf projected, no cut) of
+    # sampled pixels of the same 8 views: the PSNR reference, and the
+    # oracle's time per 1080p frame extrapolated from the sample
+    from oracle import oracle as O
+    rng = np.random.default_rng(8)
+    n_px = args.oracle_pixels
+    se = {k: 0.0 for k in imgs}
+    t_proj = t_pix = 0.0
+    leaves = O.cut(scene, sample[0], O.MODE_ALL_LEAVES)
+    for v, cam in enumerate(sample):
+        t0 = time.perf_counter()
+        pr = O.project(scene, leaves, cam)
+        t1 = time.perf_counter()
+        px = rng.integers(0, cam.width, n_px)
+        py = rng.integers(0, cam.height, n_px)
+        pres = O.render_pixels(pr, cam, px, py)
+        t_pix += time.perf_counter() - t1
+        t_proj += t1 - t0
+        ref = pres.primary[:, :3]
+        for k, im in imgs.items():
+            se[k] += float(((im[v][:, py, px].T.astype(np.float64) - ref) ** 2).sum())
+        del pr
+    npx_frame = sample[0].width * sample[0].height
+    for k in imgs:
+        mse = max(se[k] / (3 * n_px * len(sample)), 1e-10)
+        q.setdefault(k, {})["psnr_vs_oracle_full_leaf_db"] = 10.0 * np.log10(1.0 / mse)
+    oracle_s_frame = (t_proj + t_pix * npx_frame / n_px) / len(sample)
+    q["oracle_reference"] = (f"FP64 oracle full-leaf render ({leaves.size} leaves projected per view) of {n_px} "
+                             f"random pixels in each of the 8 views; PSNR over those pixels")
     log(f"quality: {q}")
     out = {"metric": "Mpixels/s, 64 views at 1920x1080 of the 30M-leaf building in one call (learned cut)",
            "value": res["learned"]["mpix_s"], "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
@@ -415,6 +572,12 @@ def run_building(args):
                       "nodes": scene.n,
                       "pixels_per_batch": px,
                       "parallelism": "single GPU"},
+           "cpu_baseline": {"value": npx_frame / oracle_s_frame / 1e6, "unit": "Mpixels/s", "cores": O.num_threads(),
+                            "kind": "oracle",
+                            "sample": f"full-leaf 1920x1080 frames of the 8 quality views: every leaf projected "
+                                      f"({t_proj / len(sample):.2f} s per view), {n_px} random pixels composited "
+                                      f"per view ({t_pix / len(sample):.2f} s), frame time extrapolated to "
+                                      f"{oracle_s_frame:.1f} s; host CPU {cpu_model()}"},
            "extra": {"render": res, "quality_8_views": q, "peak_device_gb": peak / 1e9,
                      "p_star": p_star, "model": origin,
                      "calibration": {"poses": len(calib), "loss_db": closs, "table": [list(t) for t in table]},
@@ -622,6 +785,10 @@ def run_nav(args):
 
 def main():
     args = parse()
+    if args.workload == "box20k":
+        return run_box20k(args)
+    if args.workload == "plan2m":
+        return run_plan2m(args)
     if args.workload == "plan8m":
         return run_plan8m(args)
     if args.workload == "building30m":
@@ -668,6 +835,7 @@ def main():
     log(f"learned cut: p*={model.p_star}, s_hi={model.s_hi} ({origin})")
 
     base_psnr = learn_psnr = loss = loss_m = float("nan")
+    full_q = None
     base_cut = learn_cut = 1
     tau_m = 1.0
     if not args.quick:
@@ -681,6 +849,18 @@ def main():
             f"cut {learn_cut / base_cut:.3f} of tau=1; matched tau {tau_m:.2f} (loss {loss_m:.3f}, cut "
             f"{(cut_m or base_cut) / base_cut:.3f})")
         del refs
+        # the same views against the full-leaf render (every leaf, no cut)
+        fulls = []
+        for i in range(0, len(eval_cams), B):
+            fulls += [t.clone() for t in lod.render_rgb(r, eval_cams[i:i + B], hgs.HGS_LOD_ALL_LEAVES, 1.0)]
+        fb, _, fb_all = lod.evaluate(r, eval_cams, fulls, None, tau=1.0)
+        fl, _, fl_all = lod.evaluate(r, eval_cams, fulls, model)
+        fm, _, _ = lod.evaluate(r, eval_cams, fulls, None, tau=tau_m)
+        full_q = {"tau1_db": fb, "learned_db": fl, "matched_tau_db": fm, "learned_loss_db": fb - fl,
+                  "note": "mean over views of per-view PSNR (MSE floored at 1e-10, i.e. at most 100 dB) against "
+                          "the GPU's all-leaves render of the same view"}
+        log(f"PSNR vs full-leaf render: tau=1 {fb:.2f} dB, learned {fl:.2f} dB, matched tau {fm:.2f} dB")
+        del fulls
         torch.cuda.empty_cache()
 
     r.set_cameras(batches[0])
@@ -782,11 +962,13 @@ def main():
     mpix = lambda ms, px: px / (ms * 1e-3) / 1e6  # noqa: E731
 
     comp_ms = stage["composite"]
-    achieved = FLOPS_PER_PAIR * n_alg_step / (comp_ms * 1e-3) / 1e12
+    achieved = OPS_PER_PAIR * n_alg_step / (comp_ms * 1e-3) / 1e12
+    alt = FLOPS_PER_PAIR_ALT * n_alg_step / (comp_ms * 1e-3) / 1e12
     roof = {"kernel": "k_composite", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic_entry("composite"),
-            "ms_per_launch": comp_ms, "n_alg_per_launch": n_alg_step, "flops_per_pair": FLOPS_PER_PAIR}
+            "ms_per_launch": comp_ms, "n_alg_per_launch": n_alg_step, "ops_per_pair": OPS_PER_PAIR}
     extra = {
+        "composite_tflops_at_24_flops_per_pair": alt, "composite_frac_at_24_flops_per_pair": alt / FP32_PEAK_TFLOPS,
         # the build disables packed FP32 (v_pk_*): the attainable FP32 vector
         # peak is half the published one
         "composite_frac_of_unpacked_fp32_peak": achieved / (FP32_PEAK_TFLOPS / 2),
@@ -803,6 +985,7 @@ def main():
         "speedup_vs_batched_threshold_tau1": value / mpix(ms_t1, px_per_step),
         "psnr_tau1_db": base_psnr, "psnr_learned_db": learn_psnr, "psnr_loss_db": loss,
         "psnr_reference": "ray-cast ground truth of the synthetic surfaces, 3x3 supersampled",
+        "psnr_vs_full_leaf_render": full_q,
         "cut_learned_over_tau1": learn_cut / base_cut,
         "learned_p_star": model.p_star, "learned_s_hi": model.s_hi, "learned_model": origin,
         "stage_ms_per_step_eager": stage, "ms_per_step_eager": ms_learn_eager, "graph": not args.no_graph,
@@ -814,9 +997,19 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         from oracle import oracle as O
-        sizes = [O.cut(scene, c, O.MODE_THRESHOLD, 1.0).size for c in batches[0]]
-        med = batches[0][int(np.argsort(sizes)[len(sizes) // 2])]
-        cpu = cpu_baseline(scene, med, 1.0, args.cpu_seconds)
+        sample = batches[0][:args.cpu_frames]
+        t_l, px_l, sz_l = oracle_frames(scene, sample, model)
+        t_t, px_t, sz_t = oracle_frames(scene, sample, None, 1.0)
+        cpu = {"value": px_l / t_l / 1e6, "unit": "Mpixels/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"{len(sample)} held-out 1280x720 poses (the first of the timed batch) with the learned "
+                         f"cut ({int(np.mean(sz_l))} Gaussians per frame), whole frames: the oracle's cut, "
+                         f"projection and every pixel composited, {t_l:.1f} s; host CPU {cpu_model()}"}
+        extra["cpu_oracle"] = {"cpu_model": cpu_model(), "threads": O.num_threads(), "frames": len(sample),
+                               "learned_s_per_frame": t_l / len(sample), "learned_mpix_s": px_l / t_l / 1e6,
+                               "tau1_s_per_frame": t_t / len(sample), "tau1_mpix_s": px_t / t_t / 1e6,
+                               "tau1_gaussians_per_frame": float(np.mean(sz_t)),
+                               "learned_gaussians_per_frame": float(np.mean(sz_l))}
+        log(f"oracle: learned {t_l / len(sample):.2f} s/frame, tau=1 {t_t / len(sample):.2f} s/frame")
     out = {
         "metric": METRIC, "value": value, "unit": "Mpixels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_learn, "higher_is_better": True, "scaling": "weak",
