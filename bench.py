@@ -113,6 +113,41 @@ def oracle_frames(scene, cams, model=None, tau=1.0):
     return time.perf_counter() - t0, px, sizes
 
 
+def hbm_probe(r, torch, gib=1, reps=10):
+    """Attainable HBM bandwidth (GB/s, read + write) of the library's
+    streaming copy over a `gib` GiB buffer, HIP events on the stream."""
+    n = (gib << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        r.stream_copy(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        r.stream_copy(a, b)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(a, b))
+    gbs = 2.0 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs, ok
+
+
+# Algorithmic bytes of the HBM-bound stages (the minimum each must move):
+# cut: a visited (node, view) reads its 16-byte bounding sphere and 8-byte
+# child range, an emitted id is 4 bytes; projection: a cut Gaussian reads
+# its 236 bytes (mean, scale, quaternion, opacity, degree-3 SH) and 4-byte
+# id and writes a 48-byte record; binning: the tile-count scan reads 8 bytes
+# per Gaussian, pair emission writes 12 bytes per pair, the sort reads and
+# writes each pair once (24 bytes), the tile ranges read 8.
+def stage_bytes(visited, cut, pairs, sh_bytes=192):
+    return {"cut": 24 * visited + 4 * cut,
+            "project": (44 + sh_bytes + 4 + 48) * cut,
+            "sort": 8 * cut + (12 + 24 + 8) * pairs}
+
+
 def traffic_entry(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
@@ -164,6 +199,14 @@ def timed_loop(r, hgs, torch, batches, outs, steps, warmup, stage_timing):
     return (t1 - t0) * 1e3 / steps, st
 
 
+def apply_plan(r, hgs, plan):
+    """Set the launch options of an autotuned plan."""
+    r.set_tile_shape(plan["tile_w"], plan["tile_h"], plan["pixels_per_thread"])
+    r.set_option(hgs.HGS_OPT_BATCH_DEPTH, plan["batch_depth"])
+    r.set_option(hgs.HGS_OPT_PERSISTENT, plan["persistent"])
+    r.set_option(hgs.HGS_OPT_SORT_DIGIT_BITS, plan["sort_digit_bits"])
+
+
 def time_backward(r, hgs, torch, batches, outs, steps, lanes=1, keep=True):
     """ms per backward pass of a batch: each step renders a batch (untimed
     part of the stream; with keep, keeping its pixel states for the backward
@@ -171,6 +214,7 @@ def time_backward(r, hgs, torch, batches, outs, steps, lanes=1, keep=True):
     the backward is inside the HIP events."""
     r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
     r.set_option(hgs.HGS_OPT_LANES, 1)          # the backward pass needs a one-pass render
+    r.set_tile_shape(16, 16, 1)                 # and 16x16 tiles
     r.set_option(hgs.HGS_OPT_KEEP_STATE, 1 if keep else 0)
     gen = torch.Generator(device="cuda").manual_seed(0)
     grads = [tuple(torch.randn(t.shape, generator=gen, device="cuda") for t in o) for o in outs]
@@ -871,14 +915,18 @@ def main():
     r.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
     r.set_option(hgs.HGS_OPT_COUNT_NALG, 1)
     n_alg = n_eval = 0
+    per = {"visited": 0, "cut_size": 0, "pairs": 0}
     for bt in batches:
         r.set_cameras(bt)
         r.render(outs)
         st0 = r.stats()
         n_alg += st0["n_alg"]
         n_eval += st0["n_eval"]
+        for k in per:
+            per[k] += st0[k]
     n_alg_step = n_alg / len(batches)
     n_eval_step = n_eval / len(batches)
+    per = {k: v / len(batches) for k, v in per.items()}
     r.set_option(hgs.HGS_OPT_COUNT_NALG, 0)
     # launch plan (batch depth, persistent compositing, radix digit width)
     # picked by the library's autotuner on the first batch; images do not
@@ -909,6 +957,7 @@ def main():
 
     if args.quick and args.with_backward:
         ms_bwd_q = time_backward(r, hgs, torch, batches, outs, args.steps, plan["lanes"])
+        apply_plan(r, hgs, plan)
         log(f"backward: {ms_bwd_q:.3f} ms per batch")
     single = eval_cams[:args.single]
     px1 = single[0].width * single[0].height
@@ -930,6 +979,7 @@ def main():
         # backward pass of the learned batch (random image gradients),
         # eager launches, timed with HIP events on the stream
         ms_bwd = time_backward(r, hgs, torch, batches, outs, args.steps, plan["lanes"])
+        apply_plan(r, hgs, plan)
         # the learned batch on two pipeline lanes (passes overlapping on two
         # streams; same images), with its own launch plan
         r.set_option(hgs.HGS_OPT_LANES, 2)
@@ -937,9 +987,7 @@ def main():
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
         ms_lanes2, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
         r.set_option(hgs.HGS_OPT_LANES, 1)
-        r.set_option(hgs.HGS_OPT_BATCH_DEPTH, plan["batch_depth"])
-        r.set_option(hgs.HGS_OPT_PERSISTENT, plan["persistent"])
-        r.set_option(hgs.HGS_OPT_SORT_DIGIT_BITS, plan["sort_digit_bits"])
+        apply_plan(r, hgs, plan)
 
         # plain single-view path, tau = 1
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
@@ -962,7 +1010,20 @@ def main():
     mpix = lambda ms, px: px / (ms * 1e-3) / 1e6  # noqa: E731
 
     comp_ms = stage["composite"]
+    probe_gbs, probe_ok = hbm_probe(r, torch)
+    log(f"HBM probe: {probe_gbs:.0f} GB/s (copy {'correct' if probe_ok else 'WRONG'})")
+    sb = stage_bytes(per["visited"], per["cut_size"], per["pairs"])
+    stage_roof = {}
+    t_min = 0.0
+    for k, b in sb.items():
+        gbs = b / (stage[k] * 1e-3) / 1e9
+        stage_roof[k] = {"bound": "hbm", "alg_bytes": b, "ms": stage[k], "achieved_gbs": gbs,
+                         "frac": gbs / HBM_PEAK_GBS, "frac_of_probe": gbs / probe_gbs}
+        t_min += b / (HBM_PEAK_GBS * 1e9)
+    t_min += OPS_PER_PAIR * n_alg_step / (FP32_PEAK_TFLOPS * 1e12)
     achieved = OPS_PER_PAIR * n_alg_step / (comp_ms * 1e-3) / 1e12
+    stage_roof["composite"] = {"bound": "alu", "alg_ops": OPS_PER_PAIR * n_alg_step, "ms": comp_ms,
+                               "achieved_tflops": achieved, "frac": achieved / FP32_PEAK_TFLOPS}
     alt = FLOPS_PER_PAIR_ALT * n_alg_step / (comp_ms * 1e-3) / 1e12
     roof = {"kernel": "k_composite", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic_entry("composite"),
@@ -977,7 +1038,8 @@ def main():
         "batched_learned_blended_mpix_s": mpix(ms_blend, px_per_step),
         "backward_ms_per_step": ms_bwd, "backward_mpix_s": mpix(ms_bwd, px_per_step),
         "batched_learned_two_lanes_mpix_s": mpix(ms_lanes2, px_per_step),
-        "two_lanes_plan": None if plan2 is None else {k: plan2[k] for k in ("batch_depth", "persistent",
+        "two_lanes_plan": None if plan2 is None else {k: plan2[k] for k in ("tile_w", "tile_h", "pixels_per_thread",
+                                                                               "batch_depth", "persistent",
                                                                                "sort_digit_bits")},
         "matched_tau": tau_m, "matched_tau_loss_db": loss_m,
         "plain_single_view_tau1_mpix_s": mpix(ms_single, px1),
@@ -989,6 +1051,10 @@ def main():
         "cut_learned_over_tau1": learn_cut / base_cut,
         "learned_p_star": model.p_star, "learned_s_hi": model.s_hi, "learned_model": origin,
         "stage_ms_per_step_eager": stage, "ms_per_step_eager": ms_learn_eager, "graph": not args.no_graph,
+        "stage_roofline": stage_roof, "hbm_probe_gbs": probe_gbs, "hbm_probe_correct": probe_ok,
+        "frame_roofline_frac": t_min * 1e3 / ms_learn,
+        "frame_roofline_frac_eager": t_min * 1e3 / sum(stage.values()),
+        "cut_visited_per_step": per["visited"],
         "n_alg_per_step": n_alg_step, "held_out_poses": len(eval_cams),
         "composite_slots_per_step": n_eval_step, "composite_lane_efficiency": n_alg_step / max(n_eval_step, 1),
         "cut_entries_per_step": st["cut_size"], "visible_per_step": st["visible"], "pairs_per_step": st["pairs"],
@@ -1018,7 +1084,8 @@ def main():
                    "leaves": int(np.count_nonzero(scene.child_count == 0)), "nodes": scene.n,
                    "views_per_step": B, "resolution": "1280x720", "fx": 900,
                    "lod": f"learned (p*={model.p_star}, s_hi={model.s_hi}px, threshold tau=1 fallback)",
-                   "plan": {k: plan[k] for k in ("lanes", "batch_depth", "persistent", "sort_digit_bits")},
+                   "plan": {k: plan[k] for k in ("lanes", "tile_w", "tile_h", "pixels_per_thread", "batch_depth",
+                                                 "persistent", "sort_digit_bits")},
                    "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

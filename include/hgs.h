@@ -99,6 +99,17 @@ typedef int32_t hgs_status;
                                      not kept, the backward pass replays it.  Images
                                      and gradients do not depend on it. */
 
+#define HGS_OPT_TILE_SHAPE 15       /* binning and compositing tile, (width << 16) | height:
+                                       8x8, 16x8, 16x16 (default), 32x8 or 32x16 pixels.
+                                       Each pixel's value does not depend on it (the
+                                       3-sigma support is per pixel, the order is depth
+                                       then cut order).  Kept pixel states and the
+                                       backward pass need 16x16. */
+#define HGS_OPT_PIXELS_PER_THREAD 16 /* pixels each compositing thread evaluates: 1
+                                       (default), 2 or 4 horizontally adjacent pixels,
+                                       at least 64 threads per tile.  Images do not
+                                       depend on it. */
+
 typedef struct hgs_ctx hgs_ctx;
 
 /* Gaussians, host arrays borrowed for the duration of the call (copied).
@@ -174,6 +185,7 @@ typedef struct {
                                      including q > 9 and stopped pixels (if counted) */
     int64_t timed_backwards;      /* backward passes summed in the ms_bwd_* fields */
     double ms_bwd_composite, ms_bwd_total;   /* compositing part and whole backward pass */
+    int64_t visited;              /* (node, view) pairs the cut tested (threshold and learned cuts) */
 } hgs_stats;
 
 /* Create a context on HIP device `device`.  *out is set on success. */
@@ -245,15 +257,20 @@ typedef struct {
     double ms_default;            /* render time of the default plan */
     int32_t lanes;                /* HGS_OPT_LANES in force (not searched) */
     int32_t reserved;             /* 0 */
+    int32_t tile_w, tile_h;       /* HGS_OPT_TILE_SHAPE */
+    int32_t pixels_per_thread;    /* HGS_OPT_PIXELS_PER_THREAD */
+    int32_t reserved2;            /* 0 */
 } hgs_plan;
 
-/* Time the launch choices that do not change the image (compositor batch
- * depth 64/128/256, persistent or one-workgroup-per-tile compositing, radix
+/* Time the launch choices that do not change the image (tile shape 8x8,
+ * 16x8, 16x16, 32x8 or 32x16 with 1, 2 or 4 pixels per compositing thread;
+ * compositor batch depth 64/128/256, at most the tile's thread count;
+ * persistent or one-workgroup-per-tile compositing for 16x16 tiles; radix
  * digit width 6..11) on the current scene, views, LOD and lanes (kept as
- * set), rendering every view reps >= 1 times per candidate into internal
- * buffers on `stream`, and keep the fastest as the context's options (*out
- * describes it; may be NULL).  Coordinate search: compositor choices first,
- * then the digit width.  cache_path (NULL: none) names a text file of earlier plans keyed
+ * set; with kept pixel states, 16x16 tiles only), rendering every view reps
+ * >= 1 times per candidate into internal buffers on `stream`, and keep the
+ * fastest as the context's options (*out describes it; may be NULL).
+ * Coordinate search: compositor choices first, then the digit width.  cache_path (NULL: none) names a text file of earlier plans keyed
  * by scene size, view sizes and LOD; a matching line is applied without
  * timing, a new plan is appended (the key includes the lanes setting).
  * Synchronous; leaves stage timing off. */
@@ -338,6 +355,12 @@ hgs_status hgs_mlp_bf16_from_master(hgs_ctx* ctx, void* stream, const float* mas
 /* Column mean and standard deviation of device features[n*8] into device
  * mean_std[16] (8 means then 8 deviations, at least 1e-6). */
 hgs_status hgs_feature_stats(hgs_ctx* ctx, void* stream, const float* features, int64_t n, float* mean_std);
+
+/* Device-to-device streaming copy of `bytes` (a multiple of 16; both
+ * pointers 16-byte aligned, else HGS_E_INVALID), asynchronous on `stream`:
+ * the probe of attainable HBM bandwidth (read + write) that the roofline
+ * fractions are quoted against beside the 8 TB/s peak. */
+hgs_status hgs_stream_copy(hgs_ctx* ctx, void* stream, const void* src, void* dst, int64_t bytes);
 
 /* dst[3][H][W] = 2x2 box average of src[3][2H][2W] (device, planar). */
 hgs_status hgs_downsample2x(hgs_ctx* ctx, void* stream, const float* src, int32_t width, int32_t height,

@@ -116,6 +116,7 @@ struct hgs_ctx {
     int last_lane = 0;
     bool last_blend = false;
     bool last_keep = false;           // the last render kept its pixel states (px_state)
+    bool last_default_tiles = true;   // the last render binned to kTile x kTile tiles
     uint32_t* nav_active_host = nullptr;   // pinned
     void* scratch = nullptr;          // this device's static scratch area (hgs_sort_pairs_noalloc)
 };
@@ -426,6 +427,8 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pa.blend = c->ropts.lod_blend && c->hier && c->lod_mode != HGS_LOD_ALL_LEAVES;
     pa.parent = P<int32_t>(c->parent);
     pa.bound = P<float4>(c->bound);
+    pa.tile_w = c->ropts.tile_w;
+    pa.tile_h = c->ropts.tile_h;
     launch_project(pa, s);
     mark(c, 2, s);
 
@@ -454,6 +457,8 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     ea.exact_tiles = c->ropts.exact_tiles;
     ea.scan_tmp = ca.scan_tmp;
     ea.ctr = ctr;
+    ea.tile_w = c->ropts.tile_w;
+    ea.tile_h = c->ropts.tile_h;
     launch_emit(ea, s);
 
     SortArgs pb{};
@@ -471,6 +476,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     c->last_lane = lane_of(c, g);
     c->last_blend = pa.blend;
     c->last_keep = c->ropts.keep_state;
+    c->last_default_tiles = c->ropts.tile_w == kTile && c->ropts.tile_h == kTile;
 
     CompositeArgs xa{};
     xa.keys = pb.keys[pr];
@@ -589,9 +595,12 @@ bool read_plan(const char* path, const std::string& key, hgs_plan* p) {
         char k[256];
         hgs_plan q{};
         q.lanes = 1;
-        const int got = std::sscanf(line, "%255s %d %d %d %lf %lf %d", k, &q.batch_depth, &q.persistent,
-                                    &q.sort_digit_bits, &q.ms, &q.ms_default, &q.lanes);
-        if (got >= 6 && key == k) {
+        q.tile_w = q.tile_h = kTile;
+        q.pixels_per_thread = 1;
+        const int got = std::sscanf(line, "%255s %d %d %d %lf %lf %d %d %d %d", k, &q.batch_depth, &q.persistent,
+                                    &q.sort_digit_bits, &q.ms, &q.ms_default, &q.lanes, &q.tile_w, &q.tile_h,
+                                    &q.pixels_per_thread);
+        if (got >= 6 && key == k && tile_shape_ok(q.tile_w, q.tile_h, q.pixels_per_thread)) {
             if (got == 6) q.lanes = 1;
             *p = q;          // the last matching line wins
             found = true;
@@ -871,11 +880,12 @@ hgs_status hgs_set_cameras(hgs_ctx* c, int32_t n, const hgs_camera* cams) {
     }
     HIP_TRY(c, hipSetDevice(c->device));
     // tile layout: views in order, row-major tiles within a view
+    const int tw = c->ropts.tile_w, th = c->ropts.tile_h;
     uint64_t tiles = 0;
     std::vector<uint32_t> tile_base(n);
     for (int v = 0; v < n; ++v) {
         tile_base[v] = (uint32_t)tiles;
-        tiles += (uint64_t)((cams[v].width + kTile - 1) / kTile) * ((cams[v].height + kTile - 1) / kTile);
+        tiles += (uint64_t)((cams[v].width + tw - 1) / tw) * ((cams[v].height + th - 1) / th);
     }
     if (tiles >= (1ull << 31)) return fail(c, HGS_E_UNSUPPORTED, "too many tiles");
     // same view count and image sizes as before: the tile layout, its device
@@ -928,8 +938,8 @@ hgs_status hgs_set_cameras(hgs_ctx* c, int32_t n, const hgs_camera* cams) {
         d.yhi = (d.H - d.cy + 0.15 * d.H) / d.fy;
         for (int i = 0; i < 3; ++i) d.bg[i] = k.bg[i];
         d.width = k.width; d.height = k.height;
-        d.tiles_x = (k.width + kTile - 1) / kTile;
-        d.tiles_y = (k.height + kTile - 1) / kTile;
+        d.tiles_x = (k.width + tw - 1) / tw;
+        d.tiles_y = (k.height + th - 1) / th;
         d.tile_base = tile_base[v];
         d.keep_node = -1;
         d.rgb = d.depth = d.alpha = nullptr;
@@ -965,6 +975,37 @@ hgs_status hgs_set_lod(hgs_ctx* c, int32_t mode, float tau) {
     return HGS_OK;
 }
 
+namespace {
+
+// Tile layout of the views already set, for a new tile shape: per-view tile
+// counts, the views' tile bases and the tile -> view table (the device
+// mirror of the views is uploaded again before the next render).
+hgs_status relayout_tiles(hgs_ctx* c) {
+    const int V = (int)c->cams.size();
+    if (V == 0) return HGS_OK;
+    const int tw = c->ropts.tile_w, th = c->ropts.tile_h;
+    uint64_t tiles = 0;
+    std::vector<uint32_t> base(V);
+    for (int v = 0; v < V; ++v) {
+        base[v] = (uint32_t)tiles;
+        tiles += (uint64_t)((c->cams[v].width + tw - 1) / tw) * ((c->cams[v].height + th - 1) / th);
+    }
+    if (tiles >= (1ull << 31)) return fail(c, HGS_E_UNSUPPORTED, "too many tiles");
+    hgs_status s;
+    if ((s = ensure(c, c->tile_view, tiles * 4)) || (s = ensure(c, c->ranges, tiles * sizeof(uint2)))) return s;
+    HIP_TRY(c, hipEventSynchronize(c->views_copied));
+    for (int v = 0; v < V; ++v) {
+        c->views_host[v].tiles_x = (c->cams[v].width + tw - 1) / tw;
+        c->views_host[v].tiles_y = (c->cams[v].height + th - 1) / th;
+    }
+    c->total_tiles = (uint32_t)tiles;
+    c->tile_abs = base;
+    c->last_valid = false;
+    return plan_passes(c, c->want_passes, true);
+}
+
+}  // namespace
+
 hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
     if (!c) return HGS_E_INVALID;
     invalidate_graph(c);
@@ -980,7 +1021,29 @@ hgs_status hgs_set_option(hgs_ctx* c, int32_t opt, int64_t val) {
         case HGS_OPT_PERSISTENT: c->ropts.persistent = val != 0; return HGS_OK;
         case HGS_OPT_EXACT_TILES: c->ropts.exact_tiles = val != 0; return HGS_OK;
         case HGS_OPT_LOD_BLEND: c->ropts.lod_blend = val != 0; return HGS_OK;
-        case HGS_OPT_KEEP_STATE: c->ropts.keep_state = val != 0; return HGS_OK;
+        case HGS_OPT_KEEP_STATE:
+            if (val != 0 && (c->ropts.tile_w != kTile || c->ropts.tile_h != kTile))
+                return fail(c, HGS_E_UNSUPPORTED, "kept pixel states need %dx%d tiles", kTile, kTile);
+            c->ropts.keep_state = val != 0;
+            return HGS_OK;
+        case HGS_OPT_TILE_SHAPE: {
+            const int tw = (int)(val >> 16), th = (int)(val & 0xffff);
+            if (val < 0 || !tile_shape_ok(tw, th, 1) || !tile_shape_ok(tw, th, c->ropts.px))
+                return fail(c, HGS_E_INVALID, "tile shape %dx%d is not one of 8x8, 16x8, 16x16, 32x8, 32x16 "
+                            "(or does not allow %d pixels per thread)", tw, th, c->ropts.px);
+            if (c->ropts.keep_state && (tw != kTile || th != kTile))
+                return fail(c, HGS_E_UNSUPPORTED, "kept pixel states need %dx%d tiles", kTile, kTile);
+            if (tw == c->ropts.tile_w && th == c->ropts.tile_h) return HGS_OK;
+            c->ropts.tile_w = tw;
+            c->ropts.tile_h = th;
+            return relayout_tiles(c);
+        }
+        case HGS_OPT_PIXELS_PER_THREAD:
+            if (!tile_shape_ok(c->ropts.tile_w, c->ropts.tile_h, (int)val))
+                return fail(c, HGS_E_INVALID, "%lld pixels per thread: 1, 2 or 4, at least 64 threads per %dx%d tile",
+                            (long long)val, c->ropts.tile_w, c->ropts.tile_h);
+            c->ropts.px = (int)val;
+            return HGS_OK;
         case HGS_OPT_LANES: {
             if (val != 1 && val != 2) return fail(c, HGS_E_INVALID, "lanes must be 1 or 2");
             if (val == 2 && !c->lane_stream) {
@@ -1202,6 +1265,7 @@ hgs_status hgs_get_stats(hgs_ctx* c, hgs_stats* out) {
         out->pairs += std::min(k.pairs, c->pair_cap);
         out->n_alg += (int64_t)k.nalg;
         out->n_eval += (int64_t)k.neval;
+        out->visited += (int64_t)k.visited;
     }
     out->passes = np;
     out->tiles = c->total_tiles;
@@ -1229,9 +1293,13 @@ hgs_status hgs_autotune(hgs_ctx* c, void* stream, const char* cache_path, int32_
     HIP_TRY(c, hipSetDevice(c->device));
     const std::string key = plan_key(c);
     hgs_plan best{};
-    if (read_plan(cache_path, key, &best)) {
+    if (read_plan(cache_path, key, &best) &&
+        (!c->ropts.keep_state || (best.tile_w == kTile && best.tile_h == kTile))) {
         hgs_status st;
-        if ((st = hgs_set_option(c, HGS_OPT_BATCH_DEPTH, best.batch_depth)) ||
+        if ((st = hgs_set_option(c, HGS_OPT_PIXELS_PER_THREAD, 1)) ||
+            (st = hgs_set_option(c, HGS_OPT_TILE_SHAPE, ((int64_t)best.tile_w << 16) | best.tile_h)) ||
+            (st = hgs_set_option(c, HGS_OPT_PIXELS_PER_THREAD, best.pixels_per_thread)) ||
+            (st = hgs_set_option(c, HGS_OPT_BATCH_DEPTH, best.batch_depth)) ||
             (st = hgs_set_option(c, HGS_OPT_PERSISTENT, best.persistent)) ||
             (st = hgs_set_option(c, HGS_OPT_SORT_DIGIT_BITS, best.sort_digit_bits)))
             return st;
@@ -1279,49 +1347,85 @@ hgs_status hgs_autotune(hgs_ctx* c, void* stream, const char* cache_path, int32_
     c->use_graph = false;
     c->sync_check = true;
     invalidate_graph(c);
-    auto run = [&](int batch, int pers, int digits, double* ms) -> hgs_status {
+    // a plan: tile shape, pixels per thread, batch depth, persistent, digit width
+    auto apply = [&](int tw, int th, int px, int batch, int pers, int digits) -> hgs_status {
+        c->ropts.px = 1;
+        if (tw != c->ropts.tile_w || th != c->ropts.tile_h) {
+            c->ropts.tile_w = tw;
+            c->ropts.tile_h = th;
+            hgs_status r = relayout_tiles(c);
+            if (r) return r;
+        }
+        c->ropts.px = px;
         c->ropts.batch = batch;
         c->ropts.persistent = pers != 0;
         c->sort_digit_bits = digits;
-        return time_plan(c, s, outs.data(), reps, e0, e1, ms);
+        return HGS_OK;
+    };
+    auto run = [&](int tw, int th, int px, int batch, int pers, int digits, double* ms) -> hgs_status {
+        hgs_status r = apply(tw, th, px, batch, pers, digits);
+        return r ? r : time_plan(c, s, outs.data(), reps, e0, e1, ms);
     };
     double ms_default = 0.0;
-    if ((st = run(256, 0, 8, &ms_default))) {
+    if ((st = run(kTile, kTile, 1, 256, 0, 8, &ms_default))) {
         restore();
         return st;
     }
-    best = hgs_plan{256, 0, 8, 0, ms_default, ms_default, c->lanes, 0};
+    best = hgs_plan{256, 0, 8, 0, ms_default, ms_default, c->lanes, 0, kTile, kTile, 1, 0};
+    // compositor choices: every supported tile shape and pixels per thread
+    // (kept pixel states: the default shape only), the batch depths a tile's
+    // threads can stage (one entry each), persistent tiles for the default
+    // shape
+    const int shapes[5][2] = {{8, 8}, {16, 8}, {16, 16}, {32, 8}, {32, 16}};
     const int batches[3] = {64, 128, 256};
-    for (int b : batches)
-        for (int pers = 0; pers < 2; ++pers) {
-            if (b == 256 && pers == 0) continue;
-            double ms;
-            if ((st = run(b, pers, best.sort_digit_bits, &ms))) {
-                restore();
-                return st;
+    for (const auto& sh : shapes)
+        for (int px = 1; px <= 4; px *= 2) {
+            if (!tile_shape_ok(sh[0], sh[1], px)) continue;
+            const bool deflt = sh[0] == kTile && sh[1] == kTile && px == 1;
+            if (c->ropts.keep_state && !deflt) continue;
+            for (int b : batches) {
+                if (b > sh[0] * sh[1] / px) continue;
+                for (int pers = 0; pers < (deflt ? 2 : 1); ++pers) {
+                    if (deflt && b == 256 && pers == 0) continue;
+                    double ms;
+                    if ((st = run(sh[0], sh[1], px, b, pers, best.sort_digit_bits, &ms))) {
+                        restore();
+                        return st;
+                    }
+                    if (ms < best.ms) {
+                        best.tile_w = sh[0];
+                        best.tile_h = sh[1];
+                        best.pixels_per_thread = px;
+                        best.batch_depth = b;
+                        best.persistent = pers;
+                        best.ms = ms;
+                    }
+                }
             }
-            if (ms < best.ms) { best.batch_depth = b; best.persistent = pers; best.ms = ms; }
         }
     for (int d = 6; d <= 11; ++d) {
         if (d == best.sort_digit_bits) continue;
         double ms;
-        if ((st = run(best.batch_depth, best.persistent, d, &ms))) {
+        if ((st = run(best.tile_w, best.tile_h, best.pixels_per_thread, best.batch_depth, best.persistent, d, &ms))) {
             restore();
             return st;
         }
         if (ms < best.ms) { best.sort_digit_bits = d; best.ms = ms; }
     }
-    c->ropts.batch = best.batch_depth;
-    c->ropts.persistent = best.persistent != 0;
-    c->sort_digit_bits = best.sort_digit_bits;
+    if ((st = apply(best.tile_w, best.tile_h, best.pixels_per_thread, best.batch_depth, best.persistent,
+                    best.sort_digit_bits))) {
+        restore();
+        return st;
+    }
     c->last_valid = false;           // the last render went to internal buffers
     restore();
     invalidate_graph(c);
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(c, HGS_E_INVALID, "cannot append to plan cache %s", cache_path);
-        std::fprintf(f, "%s %d %d %d %.6f %.6f %d\n", key.c_str(), best.batch_depth, best.persistent,
-                     best.sort_digit_bits, best.ms, best.ms_default, best.lanes);
+        std::fprintf(f, "%s %d %d %d %.6f %.6f %d %d %d %d\n", key.c_str(), best.batch_depth, best.persistent,
+                     best.sort_digit_bits, best.ms, best.ms_default, best.lanes, best.tile_w, best.tile_h,
+                     best.pixels_per_thread);
         std::fclose(f);
     }
     if (out) *out = best;
@@ -1561,6 +1665,17 @@ hgs_status hgs_feature_stats(hgs_ctx* c, void* stream, const float* feats, int64
     return HGS_OK;
 }
 
+hgs_status hgs_stream_copy(hgs_ctx* c, void* stream, const void* src, void* dst, int64_t bytes) {
+    if (!c) return HGS_E_INVALID;
+    if (bytes < 0 || bytes % 16 || (bytes && (!src || !dst)) || ((uintptr_t)src | (uintptr_t)dst) % 16)
+        return fail(c, HGS_E_INVALID, "bytes must be a multiple of 16 and both pointers 16-byte aligned");
+    if (bytes == 0) return HGS_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    launch_stream_copy(src, dst, (size_t)bytes, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
 hgs_status hgs_downsample2x(hgs_ctx* c, void* stream, const float* src, int32_t width, int32_t height, float* dst) {
     if (!c || !src || !dst || width < 1 || height < 1 || width > 8192 || height > 8192)
         return fail(c, HGS_E_INVALID, "bad downsample arguments");
@@ -1762,6 +1877,8 @@ hgs_status hgs_render_backward(hgs_ctx* c, void* stream, const hgs_image_grad* g
     if (!c->last_valid) return fail(c, HGS_E_STATE, "backward needs a completed render");
     if (n_passes(c) != 1) return fail(c, HGS_E_STATE, "backward needs a render done in one pass");
     if (c->last_blend) return fail(c, HGS_E_UNSUPPORTED, "backward of a blended render is not supported");
+    if (!c->last_default_tiles)
+        return fail(c, HGS_E_UNSUPPORTED, "backward needs a render binned to %dx%d tiles", kTile, kTile);
     if (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh)
         return fail(c, HGS_E_INVALID, "every gradient array is required");
     const int nv = (int)c->cams.size();

@@ -42,7 +42,6 @@ namespace {
 
 constexpr int kNT = kTilePx;
 constexpr int kB = 128;                         // entries staged per batch
-constexpr float kNegHalfLog2e = -0.72134752044448170f;
 constexpr int kNG = 10;                         // per-entry gradient numbers
 
 struct BwdShared {
@@ -185,7 +184,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(8))) void k
             const float x = fmaf(q, kNegHalfLog2e, B.lo);
             const float al = fminf(0.99f, __builtin_amdgcn_exp2f(x));
             const float Tn = T - al * T;
-            const bool add = live && q <= kQMax && x >= kLog2AlphaMin;
+            const bool add = live && x >= entry_xmin(B.lo);
             if (add && Tn < 1e-4f) {
                 live = false;
                 last = b0 + off / 16;
@@ -238,7 +237,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(8))) void k
                 const float q = fmaf(t1, t1, t2 * t2);
                 const float x = fmaf(q, kNegHalfLog2e, B.lo);
                 const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(x));
-                const float al = (q <= kQMax && x >= kLog2AlphaMin) ? al0 : 0.f;
+                const float al = x >= entry_xmin(B.lo) ? al0 : 0.f;
                 if (al > 0.f) {
                     has = true;
                     const float iom = __builtin_amdgcn_rcpf(1.f - al);

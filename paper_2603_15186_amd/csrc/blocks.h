@@ -16,6 +16,15 @@ constexpr float kQMax = 9.f;
 constexpr float kQMask = 9.f * 1.001f;      // bound used to mark blocks
 
 constexpr float kLog2AlphaMin = -7.99435343685885793f;   // log2(1/255)
+constexpr float kNegHalfLog2e = -0.72134752044448170f;   // exp(-q/2) = 2^(q * kNegHalfLog2e)
+
+// The exponent x = log2(o) - q log2(e) / 2 of alpha = o e^(-q/2) at which
+// an entry stops counting: it adds to a pixel only where x >= xmin, i.e. q
+// <= 9 and alpha >= 1/255 (x is non-increasing in q, so q <= 9 is x at
+// least its value at q = 9, up to the rounding of one FMA).
+__device__ __forceinline__ float entry_xmin(float lo) {
+    return fmaxf(kLog2AlphaMin, fmaf(kQMax, kNegHalfLog2e, lo));
+}
 
 // One staged Gaussian: t1 = p x + r y + c1, t2 = s y + c2 over tile-relative
 // pixel centres (x, y); lo = log2(opacity).
@@ -47,6 +56,40 @@ __device__ __forceinline__ uint32_t block_mask(float u, float v, float p, float 
         const int c0 = max(0, (int)ceilf(xl - 0.501f)), c1 = min(kTile - 1, (int)floorf(xr - 0.499f));
         if (y0 <= y1 && c0 <= c1)
             m |= ((2u << ((uint32_t)c1 >> 2)) - (1u << ((uint32_t)c0 >> 2))) << (4 * band);
+    }
+    return m;
+}
+
+// Blocks of a TW x TH tile (TW, TH in {8, 16, 32} x {8, 16}) that may hold
+// a pixel centre with q <= kQMask, as block_mask above, numbered cell-major:
+// a cell is the tile's part within one 16-pixel column of the pixel grid
+// (min(TW, 16) wide), blocks row-major inside it.  u, v: the mean relative
+// to the tile origin.
+template <int TW, int TH>
+__device__ __forceinline__ uint32_t block_mask_tile(float u, float v, float p, float r, float s) {
+    constexpr int CW = TW < 16 ? TW : 16;           // cell width
+    constexpr int CBX = CW / 4;                     // block columns per cell
+    constexpr int BPC = CBX * (TH / 4);             // blocks per cell
+    const float R = sqrtf(kQMask) / s;
+    const float ystar = -r * sqrtf(kQMask) / (s * sqrtf(fmaf(r, r, s * s)));
+    const float ip = 1.f / p;
+    uint32_t m = 0;
+#pragma unroll
+    for (int band = 0; band < TH / 4; ++band) {
+        const float y0 = fmaxf((float)(4 * band) + 0.5f - v, -R);
+        const float y1 = fminf((float)(4 * band) + 3.5f - v, R);
+        const float yr = fminf(fmaxf(ystar, y0), y1), yl = fminf(fmaxf(-ystar, y0), y1);
+        const float sr = s * yr, sl = s * yl;
+        const float xr = u + (sqrtf(fmaxf(fmaf(-sr, sr, kQMask), 0.f)) - r * yr) * ip;
+        const float xl = u - (sqrtf(fmaxf(fmaf(-sl, sl, kQMask), 0.f)) + r * yl) * ip;
+        const int c0 = max(0, (int)ceilf(xl - 0.501f)), c1 = min(TW - 1, (int)floorf(xr - 0.499f));
+        if (y0 <= y1 && c0 <= c1) {
+            // block columns c0/4 .. c1/4 of the tile, then split by cell
+            const uint32_t cols = (2u << ((uint32_t)c1 >> 2)) - (1u << ((uint32_t)c0 >> 2));
+#pragma unroll
+            for (int cell = 0; cell < TW / CW; ++cell)
+                m |= ((cols >> (cell * CBX)) & ((1u << CBX) - 1u)) << (cell * BPC + band * CBX);
+        }
     }
     return m;
 }

@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
 }
 
-__global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G) {
+__global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G, uint32_t in_cap) {
     __shared__ uint4 sh[1024 / kWave + 1];
     const int t = threadIdx.x;
     const uint4 x = t < G ? c.tmp[t] : make_uint4(0, 0, 0, 0);
@@ -241,6 +241,8 @@ __global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G) {
     if (t < G) c.tmp[t] = ex;
     if (t == 0) {
         Counters* k = c.ctr;
+        const uint32_t n_in = *c.in_count;
+        k->visited += n_in < in_cap ? n_in : in_cap;
         const uint32_t base = k->cut;
         const uint32_t cbase = k->cand;
         c.tmp[G] = make_uint4(base, 0, cbase, 0);
@@ -414,7 +416,7 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.out_slot = cur ^ 1;
         k_level_count<<<G, kNT, 0, s>>>(c, a.frontier_cap);
         if (c.defer) k_level_mlp<<<G, kNT, 0, s>>>(c, a.frontier_cap);
-        k_level_scan<<<1, 1024, 0, s>>>(c, G);
+        k_level_scan<<<1, 1024, 0, s>>>(c, G, a.frontier_cap);
         k_level_emit<<<G, kNT, 0, s>>>(c, a.frontier_cap);
         cur ^= 1;
     }

@@ -8,6 +8,23 @@ namespace hgs {
 
 namespace {
 
+// Streaming copy (the bandwidth probe): four independent 16-byte loads in
+// flight per thread and step, then four stores; grid-stride, so every
+// workgroup stays resident and the copy front advances contiguously.
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                     size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
+}
+
 __global__ void k_downsample2x(const float* __restrict__ src, int W, int H, float* __restrict__ dst) {
     const size_t plane = (size_t)W * H, splane = 4 * plane;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < 3 * plane; i += (size_t)gridDim.x * blockDim.x) {
@@ -42,6 +59,10 @@ __global__ __launch_bounds__(256) void k_region_mse(const RegionDev* __restrict_
 }
 
 }  // namespace
+
+void launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    k_stream_copy<<<256 * 8, 256, 0, s>>>(static_cast<const uint4*>(src), static_cast<uint4*>(dst), bytes / 16);
+}
 
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s) {
     const size_t n = 3 * (size_t)W * H;

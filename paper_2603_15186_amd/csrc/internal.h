@@ -14,8 +14,8 @@
 
 namespace hgs {
 
-constexpr int kTile = 16;                 // tile edge in pixels
-constexpr int kTilePx = kTile * kTile;    // pixels per tile
+constexpr int kTile = 16;                 // default tile edge in pixels (the backward pass's tile)
+constexpr int kTilePx = kTile * kTile;    // pixels per default tile
 constexpr int kMaxViews = 4096;
 // Cut entries are addressed by 28-bit indices: the depth-sorted values
 // carry the entry index in the low 28 bits and min(tile count, 15) in the
@@ -86,6 +86,7 @@ struct Counters {
     uint32_t need_cand;
     unsigned long long nalg;         // evaluated (pixel, Gaussian) pairs with q <= 9
     unsigned long long neval;        // (pixel, list entry) slots the compositor walked
+    unsigned long long visited;      // (node, view) pairs the cut tested, over all levels
 };
 
 // Options of the compositor and binning.
@@ -96,7 +97,14 @@ struct RenderOpts {
     bool exact_tiles = true;
     bool lod_blend = false;
     bool keep_state = false;         // compositor keeps each pixel's stop position and final T
+    int tile_w = kTile, tile_h = kTile;   // binning and compositing tile (8x8 .. 32x16)
+    int px = 1;                      // pixels per compositor thread (1, 2 or 4)
 };
+
+// Tile shapes the binning and the compositor support, and the pixels per
+// compositor thread each allows (a workgroup of tile_w * tile_h / px
+// threads, at least one wave64).
+bool tile_shape_ok(int tile_w, int tile_h, int px);
 
 // ---------------------------------------------------------------- launchers
 
@@ -166,6 +174,7 @@ struct ProjectArgs {
     bool blend;
     const int32_t* parent;
     const float4* bound;
+    int tile_w, tile_h;              // tile shape in pixels
 };
 void launch_project(const ProjectArgs& a, hipStream_t s);
 
@@ -184,6 +193,7 @@ struct EmitArgs {
     bool exact_tiles;
     uint4* scan_tmp;
     Counters* ctr;
+    int tile_w, tile_h;              // tile shape in pixels
 };
 void launch_emit(const EmitArgs& a, hipStream_t s);
 
@@ -354,6 +364,8 @@ struct RegionDev {
     int32_t w, h, ref_w, ref_h, x0, y0;
 };
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
+// dst = src, `bytes` (a multiple of 16) of 16-byte aligned device memory
+void launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 // ground-truth surfaces of synthetic scenes (surfaces.hip); layout of
 // hgs_surface

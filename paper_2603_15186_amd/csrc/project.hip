@@ -154,33 +154,34 @@ __device__ __forceinline__ bool band_span(const RowSpan& r, double u, double v, 
     return true;
 }
 
-__device__ __forceinline__ void row_tiles(const RowSpan& r, double u, double v, int ty, int W, int H, int tx_lo,
-                                          int tx_hi, int* lo, int* hi) {
+// Tiles [lo, hi] of tile row ty (tiles of tw x th pixels) that the ellipse
+// reaches, within [tx_lo, tx_hi]; lo > hi when none.
+__device__ __forceinline__ void row_tiles(const RowSpan& r, double u, double v, int ty, int tw, int th, int H,
+                                          int tx_lo, int tx_hi, int* lo, int* hi) {
     double xa, xb;
-    const double ya = ty * kTile + 0.5, yb = fmin((double)(ty * kTile + kTile - 1), (double)(H - 1)) + 0.5;
+    const double ya = ty * th + 0.5, yb = fmin((double)(ty * th + th - 1), (double)(H - 1)) + 0.5;
     if (!band_span(r, u, v, ya, yb, &xa, &xb)) {
         *lo = 1;
         *hi = 0;
         return;
     }
-    // tile tx covers pixel centres [16 tx + 0.5, 16 tx + 15.5]
-    const int a = (int)ceil((xa - (kTile - 0.5)) / kTile);
-    const int b = (int)floor((xb - 0.5) / kTile);
+    // tile tx covers pixel centres [tw tx + 0.5, tw tx + tw - 0.5]
+    const int a = (int)ceil((xa - (tw - 0.5)) / tw);
+    const int b = (int)floor((xb - 0.5) / tw);
     *lo = a > tx_lo ? a : tx_lo;
     *hi = b < tx_hi ? b : tx_hi;
-    (void)W;
 }
 
 // Number of tiles of rect `rc` that the ellipse reaches (all of them when
 // exact is false).
-__device__ __forceinline__ uint32_t count_tiles(const Proj& p, ushort4 rc, int W, int H, bool exact) {
+__device__ __forceinline__ uint32_t count_tiles(const Proj& p, ushort4 rc, int tw, int th, int H, bool exact) {
     const uint32_t all = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
     if (!exact || all <= 1) return all;
     const RowSpan r = row_span_init(p);
     uint32_t n = 0;
     for (int ty = rc.y; ty <= rc.w; ++ty) {
         int lo, hi;
-        row_tiles(r, p.u, p.v, ty, W, H, rc.x, rc.z, &lo, &hi);
+        row_tiles(r, p.u, p.v, ty, tw, th, H, rc.x, rc.z, &lo, &hi);
         n += hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
     }
     return n;
@@ -316,9 +317,9 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
                 const double cx0 = fmax(px0, 0.0), cx1 = fmin(px1, (double)(V.width - 1));
                 const double cy0 = fmax(py0, 0.0), cy1 = fmin(py1, (double)(V.height - 1));
                 if (cx0 <= cx1 && cy0 <= cy1) {
-                    rc = make_ushort4((unsigned short)((int)cx0 / kTile), (unsigned short)((int)cy0 / kTile),
-                                      (unsigned short)((int)cx1 / kTile), (unsigned short)((int)cy1 / kTile));
-                    ntiles = count_tiles(p, rc, V.width, V.height, a.exact_tiles);
+                    rc = make_ushort4((unsigned short)((int)cx0 / a.tile_w), (unsigned short)((int)cy0 / a.tile_h),
+                                      (unsigned short)((int)cx1 / a.tile_w), (unsigned short)((int)cy1 / a.tile_h));
+                    ntiles = count_tiles(p, rc, a.tile_w, a.tile_h, V.height, a.exact_tiles);
                 }
                 if (ntiles > 0) {
                     const double id = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
@@ -442,7 +443,7 @@ __device__ __forceinline__ void entry_tiles(const EmitArgs& a, uint32_t e, uint3
     const RowSpan r = row_span_init(p);
     for (int ty = rc.y; ty <= rc.w; ++ty) {
         int lo, hi;
-        row_tiles(r, p.u, p.v, ty, 0, br.height, rc.x, rc.z, &lo, &hi);
+        row_tiles(r, p.u, p.v, ty, a.tile_w, a.tile_h, br.height, rc.x, rc.z, &lo, &hi);
         for (int tx = lo; tx <= hi; ++tx) put(k++, br.tile_base + (uint32_t)ty * tw + (uint32_t)tx);
     }
 }

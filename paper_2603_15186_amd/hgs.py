@@ -42,6 +42,8 @@ HGS_OPT_PASS_VIEWS = 11
 HGS_OPT_LOD_BLEND = 12
 HGS_OPT_LANES = 13
 HGS_OPT_KEEP_STATE = 14
+HGS_OPT_TILE_SHAPE = 15
+HGS_OPT_PIXELS_PER_THREAD = 16
 
 PROJECTED_FIELDS = ("u", "v", "A", "B", "C", "r", "g", "b", "depth", "opacity", "ntiles", "valid")
 
@@ -80,7 +82,7 @@ class hgs_stats(ctypes.Structure):
                 ("timed_renders", ctypes.c_int64), ("graph_launches", ctypes.c_int64), ("ms_cut", ctypes.c_double), ("ms_project", ctypes.c_double), ("ms_sort", ctypes.c_double),
                 ("ms_composite", ctypes.c_double), ("ms_total", ctypes.c_double), ("passes", ctypes.c_int64),
                 ("n_eval", ctypes.c_int64), ("timed_backwards", ctypes.c_int64), ("ms_bwd_composite", ctypes.c_double),
-                ("ms_bwd_total", ctypes.c_double)]
+                ("ms_bwd_total", ctypes.c_double), ("visited", ctypes.c_int64)]
 
 
 class hgs_slice_grid(ctypes.Structure):
@@ -101,7 +103,8 @@ class hgs_scene_grad(ctypes.Structure):
 class hgs_plan(ctypes.Structure):
     _fields_ = [("batch_depth", ctypes.c_int32), ("persistent", ctypes.c_int32), ("sort_digit_bits", ctypes.c_int32),
                 ("from_cache", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double),
-                ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32), ("pixels_per_thread", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 # (name, restype, argtypes) of every exported entry point
@@ -134,6 +137,7 @@ EXPORTS = [
     ("hgs_mlp_bf16_from_master", ctypes.c_int32, [_P, _P, _P, _P]),
     ("hgs_feature_stats", ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, _P]),
     ("hgs_downsample2x", ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
+    ("hgs_stream_copy", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64]),
     ("hgs_region_mse", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.POINTER(hgs_region), _P]),
     ("hgs_set_surfaces", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
     ("hgs_render_surfaces", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
@@ -331,6 +335,13 @@ class Renderer:
         self._check(self.lib.hgs_get_stats(self.ctx, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in hgs_stats._fields_}
 
+    def set_tile_shape(self, width, height, pixels_per_thread=1):
+        """Tile shape (HGS_OPT_TILE_SHAPE) and pixels per compositing thread
+        (HGS_OPT_PIXELS_PER_THREAD); images do not depend on them."""
+        self.set_option(HGS_OPT_PIXELS_PER_THREAD, 1)
+        self.set_option(HGS_OPT_TILE_SHAPE, (int(width) << 16) | int(height))
+        self.set_option(HGS_OPT_PIXELS_PER_THREAD, int(pixels_per_thread))
+
     def autotune(self, cache_path=None, reps=3, stream=None) -> dict:
         """Pick the fastest image-preserving launch plan for the current
         scene, views and LOD (see hgs_autotune) and keep it."""
@@ -396,6 +407,14 @@ class Renderer:
         self._check(self.lib.hgs_feature_stats(self.ctx, self._stream(stream), feats.data_ptr(), feats.shape[0],
                                                out.data_ptr()))
         return out
+
+    def stream_copy(self, src, dst, stream=None):
+        """dst <- src (device tensors of the same byte size, a multiple of
+        16), asynchronous: the HBM bandwidth probe."""
+        n = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() != n:
+            raise ValueError("src and dst differ in size")
+        self._check(self.lib.hgs_stream_copy(self.ctx, self._stream(stream), src.data_ptr(), dst.data_ptr(), n))
 
     def downsample2x(self, src, stream=None):
         import torch

@@ -50,9 +50,9 @@ def test_plan_struct_matches_header_fields():
     src = open(os.path.join(ROOT, "include", "hgs.h")).read()
     body = src[src.index("typedef struct {\n    int32_t batch_depth;"):src.index("} hgs_plan;")]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    names = [n.strip() for n in re.findall(r"(?:int32_t|double) ([^;]+);", body)]
+    names = [n.strip() for d in re.findall(r"(?:int32_t|double) ([^;]+);", body) for n in d.split(",")]
     assert [n for n, _ in hgs.hgs_plan._fields_] == names
-    assert ctypes.sizeof(hgs.hgs_plan) == 4 * 4 + 2 * 8 + 2 * 4
+    assert ctypes.sizeof(hgs.hgs_plan) == 4 * 4 + 2 * 8 + 6 * 4
 
 
 def test_slice_grid_struct_matches_header():

@@ -307,6 +307,52 @@ def test_two_lanes_give_identical_images(R, plan_small):
         R.set_option(hgs.HGS_OPT_LANES, 1)
 
 
+LAUNCH_SHAPES = [(8, 8, 1), (16, 8, 1), (16, 8, 2), (16, 16, 1), (16, 16, 2), (16, 16, 4), (32, 8, 1), (32, 8, 2),
+                 (32, 16, 1), (32, 16, 2), (32, 16, 4)]
+
+
+def test_tile_shapes_and_pixels_per_thread_give_identical_images(R, plan_small, box):
+    """Every tile shape (8x8 .. 32x16), pixels per compositing thread (1, 2,
+    4) and batch depth renders the default launch's images bit for bit: a
+    floor-plan batch of views whose sizes are not multiples of the tiles,
+    and the 20k box.  One 32-wide shape is also checked against the oracle
+    on a full frame; unsupported shapes and kept pixel states with a
+    non-default shape are refused."""
+    hgs = _hgs()
+    scene, cams = plan_small
+    views = [_small_cam(cams[1], 200, 117), cams[7], _small_cam(cams[9], 33, 17), _small_cam(cams[4], 97, 211)]
+    bs, bc = box
+    try:
+        ref = _render(R, scene, views, batch_depth=256, persistent=0)
+        ref_box = _render(R, bs, bc)[0]
+        for tw, th, px in LAUNCH_SHAPES:
+            R.set_tile_shape(tw, th, px)
+            for b in (64, 128, 256):
+                img = _render(R, scene, views, batch_depth=b)
+                for v in range(len(views)):
+                    for a, c in zip(ref[v], img[v]):
+                        assert np.array_equal(a, c), (tw, th, px, b, v)
+            img = _render(R, bs, bc, batch_depth=256)[0]
+            for a, c in zip(ref_box, img):
+                assert np.array_equal(a, c), (tw, th, px, "box")
+        R.set_tile_shape(32, 16, 4)
+        _check_full(_render(R, bs, bc)[0], bs, bc[0])
+        with pytest.raises(hgs.HgsError) as ei:
+            R.set_option(hgs.HGS_OPT_KEEP_STATE, 1)
+        assert ei.value.status == hgs.HGS_E_UNSUPPORTED
+        for bad in ((24 << 16) | 8, (16 << 16) | 32, (4 << 16) | 4):
+            with pytest.raises(hgs.HgsError) as ei:
+                R.set_option(hgs.HGS_OPT_TILE_SHAPE, bad)
+            assert ei.value.status == hgs.HGS_E_INVALID
+        R.set_tile_shape(32, 8, 2)
+        with pytest.raises(hgs.HgsError) as ei:
+            R.set_option(hgs.HGS_OPT_PIXELS_PER_THREAD, 4)
+        assert ei.value.status == hgs.HGS_E_INVALID
+    finally:
+        R.set_tile_shape(16, 16, 1)
+        R.set_option(hgs.HGS_OPT_BATCH_DEPTH, 256)
+
+
 def test_autotune_keeps_images_and_caches_the_plan(R, plan_small, tmp_path):
     """The autotuner's plan renders the same images bitwise; a second call
     with the same cache file applies the stored plan without timing."""
@@ -328,11 +374,17 @@ def test_autotune_keeps_images_and_caches_the_plan(R, plan_small, tmp_path):
                 assert np.array_equal(a, b.cpu().numpy()), v
         again = R.autotune(cache, reps=2)
         assert again["from_cache"] == 1
-        assert (again["batch_depth"], again["persistent"], again["sort_digit_bits"], again["lanes"]) == \
-            (plan["batch_depth"], plan["persistent"], plan["sort_digit_bits"], plan["lanes"])
+        fields = ("batch_depth", "persistent", "sort_digit_bits", "lanes", "tile_w", "tile_h", "pixels_per_thread")
+        assert [again[k] for k in fields] == [plan[k] for k in fields]
+        outs = R.render()
+        torch.cuda.synchronize()
+        for v in range(len(views)):
+            for a, b in zip(ref[v], outs[v]):
+                assert np.array_equal(a, b.cpu().numpy()), v
         assert plan["lanes"] in (1, 2)
         assert len(cache.read_text().splitlines()) == 1
     finally:
+        R.set_tile_shape(16, 16, 1)
         R.set_option(hgs.HGS_OPT_BATCH_DEPTH, 256)
         R.set_option(hgs.HGS_OPT_PERSISTENT, 0)
         R.set_option(hgs.HGS_OPT_SORT_DIGIT_BITS, 8)
