@@ -42,6 +42,11 @@ HBM_PEAK_GBS = 8000.0
 OPS_PER_PAIR = 21
 FLOPS_PER_PAIR_ALT = 24
 TRAFFIC_FILE = "composite_traffic_plan2m_lod_50x720p.txt"
+# Launch plans the autotuner chose on MI355X for the workloads below (scene,
+# views, LOD and lanes key each line); its top plans lie within a fraction
+# of a percent of each other, so a stored plan keeps the timed kernels, and
+# the profiles taken of them, the same from run to run.
+PLAN_CACHE = os.path.join(ROOT, "paper_2603_15186_amd", "plans", "mi355x.txt")
 
 
 def log(*a):
@@ -72,6 +77,10 @@ def parse():
                          "building), nav (expert trajectories on the building's navigable maps) or backward "
                          "(the backward pass of the headline batch); the last five are reported for "
                          "reference")
+    ap.add_argument("--plan-cache", default=PLAN_CACHE,
+                    help="launch-plan cache of the library's autotuner: a plan stored for the same scene, views "
+                         "and LOD is applied without timing; a missing one is tuned and appended")
+    ap.add_argument("--retune", action="store_true", help="tune every launch plan afresh (cache not used)")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed batched learned path (for profilers): no quality evaluation, no "
                          "threshold or single-view comparison")
@@ -146,6 +155,17 @@ def stage_bytes(visited, cut, pairs, sh_bytes=192):
     return {"cut": 24 * visited + 4 * cut,
             "project": (44 + sh_bytes + 4 + 48) * cut,
             "sort": 8 * cut + (12 + 24 + 8) * pairs}
+
+
+def composite_kernel(plan):
+    """Name of the compositing kernel a launch plan runs (as rocprofv3 shows
+    it): the batch depth is capped at the tile's thread count."""
+    tw, th, px = plan["tile_w"], plan["tile_h"], plan["pixels_per_thread"]
+    if plan["persistent"] and (tw, th) == (16, 16):
+        return f"k_composite_persistent<{plan['batch_depth']}, false, false>"
+    if (tw, th) == (16, 16):
+        px = 1 if plan["persistent"] else px
+    return f"k_composite<{tw}, {th}, {px}, {min(plan['batch_depth'], tw * th // px)}, false, false>"
 
 
 def traffic_entry(kernel):
@@ -431,7 +451,7 @@ def run_plan2m(args):
     px = B * cams[0].width * cams[0].height
     r.set_cameras(batches[0])
     outs = r.alloc_outputs()
-    r.autotune(reps=2)
+    r.autotune(None if args.retune else args.plan_cache, reps=2)
     r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
     ms, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
     roof, stage, info = composite_roofline(r, hgs, torch, batches, outs, args.steps)
@@ -481,7 +501,7 @@ def run_plan8m(args):
     res = {}
     for tau in (1.0, 2.0, 4.0):
         r.set_lod(hgs.HGS_LOD_THRESHOLD, tau)
-        plan = r.autotune(reps=2)
+        plan = r.autotune(None if args.retune else args.plan_cache, reps=2)
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
         ms, _ = timed_loop(r, hgs, torch, [views], outs, args.steps, args.warmup, False)
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
@@ -548,7 +568,7 @@ def run_building(args):
     res = {}
     for name, mode in (("learned", hgs.HGS_LOD_LEARNED), ("tau1", hgs.HGS_LOD_THRESHOLD)):
         r.set_lod(mode, 1.0)
-        plan_ = r.autotune(reps=2)
+        plan_ = r.autotune(None if args.retune else args.plan_cache, reps=2)
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
         ms, _ = timed_loop(r, hgs, torch, [views], outs, args.steps, args.warmup, False)
         free, _ = torch.cuda.mem_get_info()
@@ -932,18 +952,9 @@ def main():
     # picked by the library's autotuner on the first batch; images do not
     # depend on it
     r.set_cameras(batches[0])
-    plan = r.autotune(reps=3)
+    plan = r.autotune(None if args.retune else args.plan_cache, reps=3)
     log(f"autotuned plan: {plan}")
     r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
-
-    if args.quick:
-        # reference copy of known size (256 MiB read + 256 MiB written) for
-        # scaling the profiler's HBM byte counters
-        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     # batched learned cut: the headline value (stage timing needs eager launches)
     ms_learn, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
@@ -983,7 +994,7 @@ def main():
         # the learned batch on two pipeline lanes (passes overlapping on two
         # streams; same images), with its own launch plan
         r.set_option(hgs.HGS_OPT_LANES, 2)
-        plan2 = r.autotune(reps=3)
+        plan2 = r.autotune(None if args.retune else args.plan_cache, reps=3)
         r.set_option(hgs.HGS_OPT_USE_GRAPH, 0 if args.no_graph else 1)
         ms_lanes2, _ = timed_loop(r, hgs, torch, batches, outs, args.steps, args.warmup, False)
         r.set_option(hgs.HGS_OPT_LANES, 1)
@@ -1010,6 +1021,8 @@ def main():
     mpix = lambda ms, px: px / (ms * 1e-3) / 1e6  # noqa: E731
 
     comp_ms = stage["composite"]
+    # the probe's copies (1 GiB read + 1 GiB written each) also scale the
+    # profiler's HBM byte counters
     probe_gbs, probe_ok = hbm_probe(r, torch)
     log(f"HBM probe: {probe_gbs:.0f} GB/s (copy {'correct' if probe_ok else 'WRONG'})")
     sb = stage_bytes(per["visited"], per["cut_size"], per["pairs"])
@@ -1025,8 +1038,9 @@ def main():
     stage_roof["composite"] = {"bound": "alu", "alg_ops": OPS_PER_PAIR * n_alg_step, "ms": comp_ms,
                                "achieved_tflops": achieved, "frac": achieved / FP32_PEAK_TFLOPS}
     alt = FLOPS_PER_PAIR_ALT * n_alg_step / (comp_ms * 1e-3) / 1e12
-    roof = {"kernel": "k_composite", "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic_entry("composite"),
+    kname = composite_kernel(plan)
+    roof = {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic_entry(kname),
             "ms_per_launch": comp_ms, "n_alg_per_launch": n_alg_step, "ops_per_pair": OPS_PER_PAIR}
     extra = {
         "composite_tflops_at_24_flops_per_pair": alt, "composite_frac_at_24_flops_per_pair": alt / FP32_PEAK_TFLOPS,

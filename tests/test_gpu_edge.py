@@ -153,3 +153,20 @@ def test_backward_sh_degrees_zero_to_two(R, deg):
         top = np.abs(w).max()
         assert top > 0, k
         np.testing.assert_allclose(gk, w, rtol=1e-4, atol=5e-5 * top, err_msg=f"{k} degree {deg}")
+
+
+@pytest.mark.parametrize("n16", [1, 255, 1024, 1025, (1 << 20) + 3])
+def test_stream_copy_probe(R, n16):
+    """The bandwidth probe copies exactly (sizes in 16-byte words, including
+    ragged tails of its 4 KiB chunks) and rejects unaligned sizes."""
+    from paper_2603_15186_amd import hgs
+    src = torch.randint(-2 ** 31, 2 ** 31 - 1, (4 * n16,), dtype=torch.int32, device="cuda")
+    dst = torch.zeros(4 * n16 + 4, dtype=torch.int32, device="cuda")
+    R.stream_copy(src, dst[:4 * n16])
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst[:4 * n16])
+    assert int(dst[4 * n16:].abs().sum()) == 0
+    odd = torch.zeros(3, dtype=torch.int32, device="cuda")
+    with pytest.raises(hgs.HgsError) as ei:
+        R.stream_copy(odd, odd.clone())
+    assert ei.value.status == hgs.HGS_E_INVALID
