@@ -82,15 +82,19 @@ typedef int32_t hgs_status;
 #define HGS_OPT_LOD_BLEND 12      /* 1: level-of-detail transition blending (NavGSim
                                      Sec. III-B: transition regions between levels
                                      are smoothly interpolated).  A cut node g with
-                                     parent p is drawn with mean, covariance,
-                                     opacity and SH coefficients p + t (g - p),
-                                     t = clamp((s_p - tau) / tau, 0, 1), s_p =
-                                     2 max(fx, fy) r_p / |c_p - o| the parent's
-                                     projected bounding-sphere size in pixels:
-                                     a node just refined looks like its parent,
-                                     one whose parent spans 2 tau looks like
-                                     itself.  Threshold and learned cuts of a
-                                     hierarchy only; 0 (default): off. */
+                                     parent p is drawn with mean, covariance and
+                                     SH coefficients p + t (g - p), t = clamp((s_p
+                                     - tau) / (s_p - s_g), 0, 1) (1 if s_g >= s_p),
+                                     s = 2 max(fx, fy) r / |c - o| a node's
+                                     projected bounding-sphere size in pixels; the
+                                     first of p's children in the view's cut takes
+                                     opacity o_p + t (o_g - o_p), the others t o_g.
+                                     Just after p is refined (s_p = tau) exactly
+                                     one copy of p is drawn, just before g is
+                                     refined (s_g = tau) g itself: the image is
+                                     continuous across every refine decision.
+                                     Threshold and learned cuts of a hierarchy
+                                     only; 0 (default): off. */
 #define HGS_OPT_KEEP_STATE 14     /* 1: every render also keeps, per pixel, where its
                                      front-to-back walk stopped and its final
                                      transmittance (8 bytes per pixel of the batch,
@@ -349,6 +353,21 @@ hgs_status hgs_mlp_train_step(hgs_ctx* ctx, void* stream, const float* features,
                               float* adam_m, float* adam_v, int32_t step, float lr, float* grad_out,
                               float* loss_out);
 
+/* The training step's two halves as separate calls (the same kernels, so
+ * hgs_mlp_backward followed by hgs_mlp_adam equals hgs_mlp_train_step bit
+ * for bit).  hgs_mlp_backward: forward with the BF16 weights w, mean binary
+ * cross-entropy and its gradient into grad_out[1377] (device, required),
+ * the loss into loss_out[1] (device, optional); weights untouched.
+ * hgs_mlp_adam: one Adam step (beta 0.9/0.999, eps 1e-8, step >= 1, lr > 0)
+ * of the FP32 master[1377] and moments adam_m, adam_v[1377] with the
+ * gradient grad[1377] (all device), then w = BF16 of the masters.  Both
+ * deterministic and asynchronous on `stream`. */
+hgs_status hgs_mlp_backward(hgs_ctx* ctx, void* stream, const float* features, const float* labels, int64_t n,
+                            const float* feat_mean, const float* feat_std, const uint16_t* w, float* grad_out,
+                            float* loss_out);
+hgs_status hgs_mlp_adam(hgs_ctx* ctx, void* stream, const float* grad, float* master, uint16_t* w, float* adam_m,
+                        float* adam_v, int32_t step, float lr);
+
 /* w[1377] = BF16 (nearest, ties to even) of the FP32 master[1377] (device). */
 hgs_status hgs_mlp_bf16_from_master(hgs_ctx* ctx, void* stream, const float* master, uint16_t* w);
 
@@ -377,6 +396,21 @@ typedef struct {
 /* out[i] (device) = mean squared error over the 3 channels of region i.
  * The descriptors are host memory (copied). */
 hgs_status hgs_region_mse(hgs_ctx* ctx, void* stream, int32_t n, const hgs_region* regions, float* out);
+
+/* Expand-vs-keep labels of learned-cut candidates (training data of the
+ * learned rule; the tree and its level selection are NavGSim Sec. III-B, the
+ * rule is the project's).  For candidate i, regions[2i] is its footprint
+ * window rendered with the threshold cut (the node refined) and
+ * regions[2i + 1] the same window rendered with the node's subtree
+ * collapsed to it, both compared with the same crop of a reference image;
+ * with MSE_r and MSE_k their mean squared errors (FP32, floored at 1e-10),
+ * drop_db[i] = 10 log10(MSE_k / MSE_r), the PSNR the window loses when the
+ * node is kept, and labels[i] = 1 when drop_db[i] > label_db, else 0.
+ * labels and drop_db (may be NULL) are device float arrays of n entries;
+ * the 2n descriptors are host memory (copied).  Asynchronous on `stream`
+ * after waiting for its earlier work (the descriptor buffer is reused). */
+hgs_status hgs_lod_labels(hgs_ctx* ctx, void* stream, int32_t n, const hgs_region* regions, float label_db,
+                          float* labels, float* drop_db);
 
 /* ---------------------------------------------------------------------- */
 /* Ground truth of synthetic scenes (evaluation, not the render path): the */

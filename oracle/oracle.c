@@ -509,17 +509,32 @@ void or_project(int64_t m, const int32_t* ids, const float* means, const float* 
 }
 
 /* Level-of-detail blending (Sec. III-B: transition regions are smoothly
- * interpolated; the rule is a reading): a cut node g with parent p takes
- * mean, covariance, opacity and SH coefficients p + t (g - p), where
- * t = clamp((s_p - tau) / tau, 0, 1) and s_p = 2 f r_p / |c_p - o| is the
- * parent's projected size (f = max(fx, fy), (c_p, r_p) its bounding sphere):
- * a node refined just past the threshold looks like its parent, one whose
- * parent is twice the threshold looks like itself.  Roots are not blended.
- * s_p and t are evaluated as written, in FP64. */
+ * interpolated; the rule is a reading).  A cut node g with parent p is drawn
+ * with mean, covariance and SH coefficients p + t (g - p) and opacity
+ *   o_p + t (o_g - o_p)  if g is the first of p's children in the cut,
+ *   t o_g                otherwise,
+ * where, with s_n = 2 f r_n / |c_n - o| the projected size of node n's
+ * bounding sphere (f = max(fx, fy)),
+ *   t = clamp((s_p - tau) / (s_p - s_g), 0, 1)   (t = 1 when s_g >= s_p).
+ * A node's parent is refined only past the threshold (s_p > tau), and a
+ * node that is itself refined at s_g > tau gives way to its children, so
+ * t runs from 0 when p has just been refined -- the children together are
+ * then p itself: the first one carries p, the others are transparent -- to
+ * 1 when g is about to be refined in turn, where g is drawn as itself.  The
+ * image therefore does not jump when a node is refined.  Roots are not
+ * blended.  s_p, s_g and t are evaluated as written, in FP64; cut holds the
+ * ascending ids of the whole cut (ids may be a subset of it). */
+static double blend_size(const float* bound, int64_t n, const proj_cam* k, double f2) {
+    const double dx = (double)bound[4 * n] - k->o[0], dy = (double)bound[4 * n + 1] - k->o[1],
+                 dz = (double)bound[4 * n + 2] - k->o[2];
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    return f2 * (double)bound[4 * n + 3] / sqrt(d2);
+}
+
 void or_project_blend(int64_t m, const int32_t* ids, const float* means, const float* scales,
                       const float* quats, const float* opacity, const float* sh, int32_t sh_degree,
-                      const int32_t* parent, const float* bound, float tau, const or_camera* cam,
-                      double* out, double* tout) {
+                      const int32_t* parent, const int32_t* first_child, const float* bound, int64_t n_cut,
+                      const int32_t* cut, float tau, const or_camera* cam, double* out, double* tout) {
     const int K = (sh_degree + 1) * (sh_degree + 1);
     proj_cam k;
     proj_cam_init(&k, cam);
@@ -530,13 +545,20 @@ void or_project_blend(int64_t m, const int32_t* ids, const float* means, const f
         const int64_t g = ids[e];
         const int64_t p = parent[g];
         double t = 1.0;
+        int first = 1;
         if (p >= 0) {
-            const double dx = (double)bound[4 * p] - k.o[0], dy = (double)bound[4 * p + 1] - k.o[1],
-                         dz = (double)bound[4 * p + 2] - k.o[2];
-            const double d2 = (dx * dx + dy * dy) + dz * dz;
-            const double sp = f2 * (double)bound[4 * p + 3] / sqrt(d2);
-            t = (sp - tauv) / tauv;
-            t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+            const double sp = blend_size(bound, p, &k, f2);
+            const double sg = blend_size(bound, g, &k, f2);
+            if (sg < sp) {
+                t = (sp - tauv) / (sp - sg);
+                t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+            }
+            for (int32_t q = first_child[p]; q < g; q++) {
+                if (bsearch(&q, cut, (size_t)n_cut, sizeof(int32_t), cmp_i32)) {
+                    first = 0;
+                    break;
+                }
+            }
         }
         if (tout) tout[e] = t;
         double mu[3], Sig[9], shc[48], op;
@@ -549,7 +571,7 @@ void or_project_blend(int64_t m, const int32_t* ids, const float* means, const f
             gauss_sigma(scales, quats, p, Sp);
             for (int i = 0; i < 9; i++) Sig[i] = Sp[i] + t * (Sig[i] - Sp[i]);
             for (int i = 0; i < 3; i++) mu[i] = (double)means[3 * p + i] + t * (mu[i] - (double)means[3 * p + i]);
-            op = (double)opacity[p] + t * (op - (double)opacity[p]);
+            op = first ? (double)opacity[p] + t * (op - (double)opacity[p]) : t * op;
             for (int q = 0; q < 3 * K; q++) shc[q] = (double)sh[p * K * 3 + q] + t * (shc[q] - (double)sh[p * K * 3 + q]);
         }
         project_one(&k, mu, Sig, op, shc, K, out + OP_STRIDE * e);

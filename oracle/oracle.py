@@ -88,8 +88,8 @@ def lib():
         L.or_project.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32,
                                  ctypes.POINTER(_Camera), P]
         L.or_project_blend.restype = None
-        L.or_project_blend.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32, P, P, ctypes.c_float,
-                                       ctypes.POINTER(_Camera), P, P]
+        L.or_project_blend.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32, P, P, P, ctypes.c_int64, P,
+                                       ctypes.c_float, ctypes.POINTER(_Camera), P, P]
         L.or_render_pixels.restype = ctypes.c_int32
         L.or_render_pixels.argtypes = [ctypes.c_int64, P, ctypes.POINTER(_Camera), ctypes.c_int64,
                                        P, P, P, ctypes.c_int32, P, P, P, P]
@@ -222,21 +222,27 @@ def project(scene, ids, cam) -> np.ndarray:
     return out
 
 
-def project_blend(scene, ids, cam, tau, with_t=False):
+def project_blend(scene, ids, cam, tau, with_t=False, cut_ids=None):
     """FP64 projection with level-of-detail blending (see oracle.c): each
     cut node is interpolated toward its parent by t = clamp((s_p - tau) /
-    tau, 0, 1)."""
+    (s_p - s_g), 0, 1); the first of a parent's children in the cut carries
+    the parent's opacity, the others fade in from 0.  cut_ids: the whole cut
+    (ascending; default: ids)."""
     L = lib()
     ids = _c(ids, np.int32)
+    cut_ids = ids if cut_ids is None else _c(cut_ids, np.int32)
+    if np.any(np.diff(cut_ids) <= 0):
+        raise ValueError("the cut's ids must be ascending")
     m = ids.size
     out = np.zeros((m, int(L.or_proj_stride())))
     tout = np.zeros(m)
     means = _c(scene.means, np.float32); scales = _c(scene.scales, np.float32)
     quats = _c(scene.quats, np.float32); op = _c(scene.opacity, np.float32)
     sh = _c(scene.sh, np.float32)
-    par = _c(scene.parent, np.int32); bound = _c(scene.bound, np.float32)
+    par = _c(scene.parent, np.int32); fc = _c(scene.first_child, np.int32); bound = _c(scene.bound, np.float32)
     L.or_project_blend(m, _p(ids), _p(means), _p(scales), _p(quats), _p(op), _p(sh), int(scene.sh_degree), _p(par),
-                       _p(bound), float(tau), ctypes.byref(_cam(cam)), _p(out), _p(tout))
+                       _p(fc), _p(bound), cut_ids.size, _p(cut_ids), float(tau), ctypes.byref(_cam(cam)), _p(out),
+                       _p(tout))
     return (out, tout) if with_t else out
 
 

@@ -427,6 +427,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pa.blend = c->ropts.lod_blend && c->hier && c->lod_mode != HGS_LOD_ALL_LEAVES;
     pa.parent = P<int32_t>(c->parent);
     pa.bound = P<float4>(c->bound);
+    pa.child = P<int2>(c->child);
     pa.tile_w = c->ropts.tile_w;
     pa.tile_h = c->ropts.tile_h;
     launch_project(pa, s);
@@ -1649,6 +1650,27 @@ hgs_status hgs_mlp_train_step(hgs_ctx* c, void* stream, const float* feats, cons
     return HGS_OK;
 }
 
+hgs_status hgs_mlp_backward(hgs_ctx* c, void* stream, const float* feats, const float* labels, int64_t n,
+                            const float* mean, const float* stdv, const uint16_t* w, float* grad_out,
+                            float* loss_out) {
+    if (!c) return HGS_E_INVALID;
+    if (!grad_out) return fail(c, HGS_E_INVALID, "grad_out is required");
+    return hgs_mlp_train_step(c, stream, feats, labels, n, mean, stdv, nullptr, const_cast<uint16_t*>(w), nullptr,
+                              nullptr, 0, 0.f, grad_out, loss_out);
+}
+
+hgs_status hgs_mlp_adam(hgs_ctx* c, void* stream, const float* grad, float* master, uint16_t* w, float* adam_m,
+                        float* adam_v, int32_t step, float lr) {
+    if (!c) return HGS_E_INVALID;
+    if (!grad || !master || !w || !adam_m || !adam_v) return fail(c, HGS_E_INVALID, "null argument");
+    if (step < 1) return fail(c, HGS_E_INVALID, "step counts from 1");
+    if (!(lr > 0.f) || !finite(lr)) return fail(c, HGS_E_INVALID, "lr must be > 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    launch_mlp_adam(grad, master, w, adam_m, adam_v, step, lr, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
 hgs_status hgs_mlp_bf16_from_master(hgs_ctx* c, void* stream, const float* master, uint16_t* w) {
     if (!c || !master || !w) return HGS_E_INVALID;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1685,24 +1707,50 @@ hgs_status hgs_downsample2x(hgs_ctx* c, void* stream, const float* src, int32_t 
     return HGS_OK;
 }
 
-hgs_status hgs_region_mse(hgs_ctx* c, void* stream, int32_t n, const hgs_region* regions, float* out) {
-    if (!c || n < 0 || (n > 0 && (!regions || !out))) return HGS_E_INVALID;
-    if (n == 0) return HGS_OK;
-    std::vector<RegionDev> r(n);
-    for (int i = 0; i < n; ++i) {
+namespace {
+
+// Check n region descriptors and copy them to the context's device buffer
+// (after the stream's previous work, which may still read it).
+hgs_status upload_regions(hgs_ctx* c, hipStream_t s, int64_t n, const hgs_region* regions) {
+    std::vector<RegionDev> r((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
         const hgs_region& q = regions[i];
         if (!q.img || !q.ref || q.w < 1 || q.h < 1 || q.x0 < 0 || q.y0 < 0 || q.x0 + q.w > q.ref_w ||
             q.y0 + q.h > q.ref_h)
-            return fail(c, HGS_E_INVALID, "region %d is outside its reference", i);
+            return fail(c, HGS_E_INVALID, "region %lld is outside its reference", (long long)i);
         r[i] = RegionDev{q.img, q.ref, q.w, q.h, q.ref_w, q.ref_h, q.x0, q.y0};
     }
     HIP_TRY(c, hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
     hgs_status st;
     HIP_TRY(c, hipStreamSynchronize(s));   // the descriptor buffer is reused
     if ((st = ensure(c, c->region_dev, sizeof(RegionDev) * (size_t)n))) return st;
     HIP_TRY(c, hipMemcpy(c->region_dev.p, r.data(), sizeof(RegionDev) * (size_t)n, hipMemcpyHostToDevice));
+    return HGS_OK;
+}
+
+}  // namespace
+
+hgs_status hgs_region_mse(hgs_ctx* c, void* stream, int32_t n, const hgs_region* regions, float* out) {
+    if (!c || n < 0 || (n > 0 && (!regions || !out))) return HGS_E_INVALID;
+    if (n == 0) return HGS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hgs_status st = upload_regions(c, s, n, regions);
+    if (st) return st;
     launch_region_mse(P<RegionDev>(c->region_dev), n, out, s);
+    HIP_TRY(c, hipGetLastError());
+    return HGS_OK;
+}
+
+hgs_status hgs_lod_labels(hgs_ctx* c, void* stream, int32_t n, const hgs_region* regions, float label_db,
+                          float* labels, float* drop_db) {
+    if (!c || n < 0 || (n > 0 && (!regions || !labels))) return HGS_E_INVALID;
+    if (!std::isfinite(label_db)) return fail(c, HGS_E_INVALID, "label_db must be finite");
+    if (n > 0x3fffffff) return fail(c, HGS_E_INVALID, "too many candidates");
+    if (n == 0) return HGS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hgs_status st = upload_regions(c, s, 2 * (int64_t)n, regions);
+    if (st) return st;
+    launch_lod_labels(P<RegionDev>(c->region_dev), n, (double)label_db, labels, drop_db, s);
     HIP_TRY(c, hipGetLastError());
     return HGS_OK;
 }

@@ -42,6 +42,49 @@ __global__ void k_downsample2x(const float* __restrict__ src, int W, int H, floa
     }
 }
 
+// Mean squared error over the 3 channels of region r (block of 256 threads,
+// FP64 sums in a fixed order), rounded to FP32; every thread returns it.
+__device__ float region_mse_block(const RegionDev& r, double* sh) {
+    const size_t np = (size_t)r.w * r.h;
+    const size_t rplane = (size_t)r.ref_w * r.ref_h;
+    double acc = 0.0;
+    for (size_t i = threadIdx.x; i < 3 * np; i += 256) {
+        const size_t c = i / np, k = i % np;
+        const int y = (int)(k / r.w), x = (int)(k % r.w);
+        const float a = r.img[i];
+        const float b = r.ref[c * rplane + (size_t)(r.y0 + y) * r.ref_w + (r.x0 + x)];
+        const double d = (double)a - (double)b;
+        acc += d * d;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const float mse = np ? (float)(sh[0] / (3.0 * np)) : 0.f;
+    __syncthreads();
+    return mse;
+}
+
+// Expand-vs-keep label of candidate i: regions 2i (window with the node
+// refined, the threshold cut) and 2i + 1 (the node's subtree collapsed to
+// it) against the same reference crop; the window's PSNR drop from keeping
+// the node, 10 log10(MSE_kept / MSE_refined) with both MSEs floored at
+// 1e-10, labels "refine" when it exceeds label_db.
+__global__ __launch_bounds__(256) void k_lod_labels(const RegionDev* __restrict__ reg, double label_db,
+                                                    float* __restrict__ labels, float* __restrict__ drop_db) {
+    __shared__ double sh[256];
+    const float refined = region_mse_block(reg[2 * blockIdx.x], sh);
+    const float kept = region_mse_block(reg[2 * blockIdx.x + 1], sh);
+    if (threadIdx.x == 0) {
+        const double a = fmax((double)refined, 1e-10), b = fmax((double)kept, 1e-10);
+        const double drop = 10.0 * log10(b / a);
+        if (drop_db) drop_db[blockIdx.x] = (float)drop;
+        labels[blockIdx.x] = drop > label_db ? 1.f : 0.f;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_region_mse(const RegionDev* __restrict__ reg, float* __restrict__ out) {
     __shared__ double sh[256];
     const RegionDev r = reg[blockIdx.x];
@@ -69,6 +112,10 @@ __global__ __launch_bounds__(256) void k_region_mse(const RegionDev* __restrict_
 
 void launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
     k_stream_copy<<<256 * 32, 256, 0, s>>>(static_cast<const v4u*>(src), static_cast<v4u*>(dst), bytes / 16);
+}
+
+void launch_lod_labels(const RegionDev* reg, int n, double label_db, float* labels, float* drop_db, hipStream_t s) {
+    if (n > 0) k_lod_labels<<<n, 256, 0, s>>>(reg, label_db, labels, drop_db);
 }
 
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s) {

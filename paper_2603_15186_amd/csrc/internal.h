@@ -170,10 +170,12 @@ struct ProjectArgs {
     BinRec* bins;
     bool exact_tiles;
     Counters* ctr;
-    // transition blending (blend false: off): parent ids and bounding spheres
+    // transition blending (blend false: off): parent ids, bounding spheres
+    // and (first child, child count) of every node
     bool blend;
     const int32_t* parent;
     const float4* bound;
+    const int2* child;
     int tile_w, tile_h;              // tile shape in pixels
 };
 void launch_project(const ProjectArgs& a, hipStream_t s);
@@ -354,6 +356,8 @@ size_t mlp_train_scratch_floats(uint32_t n);
 void launch_mlp_train_step(const float* feats, const float* labels, uint32_t n, const float* mean, const float* stdv,
                            float* master, uint16_t* w, float* m, float* v, int step, float lr, float* grad_out,
                            float* loss_out, float* scratch, hipStream_t s);
+void launch_mlp_adam(const float* grad, float* master, uint16_t* w, float* m, float* v, int step, float lr,
+                     hipStream_t s);
 void launch_bf16_from_master(const float* master, uint16_t* w, hipStream_t s);
 void launch_feat_stats(const float* f, uint32_t n, float* out, hipStream_t s);
 
@@ -378,5 +382,7 @@ struct SurfaceDev {
 };
 void launch_surfaces(const SurfaceDev* surf, int ns, const ViewDev& V, int ss, float* out, hipStream_t s);
 void launch_region_mse(const RegionDev* reg, int n, float* out, hipStream_t s);
+// labels[i], drop_db[i] (may be null) from regions 2i (refined) and 2i + 1 (kept)
+void launch_lod_labels(const RegionDev* reg, int n, double label_db, float* labels, float* drop_db, hipStream_t s);
 
 }  // namespace hgs

@@ -260,6 +260,27 @@ void launch_mlp_train_step(const float* feats, const float* labels, uint32_t n, 
     k_mlp_reduce_adam<<<(kMlpParams + kNT - 1) / kNT, kNT, 0, s>>>(partial, chunks, a);
 }
 
+void launch_mlp_adam(const float* grad, float* master, uint16_t* w, float* m, float* v, int step, float lr,
+                     hipStream_t s) {
+    AdamArgs a;
+    a.master = master;
+    a.w = w;
+    a.m = m;
+    a.v = v;
+    a.lr = lr;
+    a.beta1 = 0.9f;
+    a.beta2 = 0.999f;
+    a.eps = 1e-8f;
+    a.step = step;
+    a.grad_out = nullptr;
+    a.loss_out = nullptr;
+    a.loss_part = nullptr;
+    a.n_loss_part = 0;
+    a.n = 1;
+    // one "chunk": the gradient itself, summed as g = 0 + grad, exactly grad
+    k_mlp_reduce_adam<<<(kMlpParams + kNT - 1) / kNT, kNT, 0, s>>>(grad, 1, a);
+}
+
 void launch_bf16_from_master(const float* master, uint16_t* w, hipStream_t s) {
     k_bf16_from_master<<<(kMlpParams + 255) / 256, 256, 0, s>>>(master, w);
 }

@@ -209,15 +209,30 @@ __device__ __forceinline__ void proj_cov(const double M0[3], const double M1[3],
     *a11 = T1[0] * T1[0] + T1[1] * T1[1] + T1[2] * T1[2];
 }
 
+// Projected bounding-sphere size 2 max(fx, fy) r / |c - o| in pixels, FP64
+// in the cut's order of operations.
+__device__ __forceinline__ double sphere_size(const ViewDev& V, float4 b) {
+#pragma clang fp contract(off)
+    const double bx = (double)b.x - V.o[0], by = (double)b.y - V.o[1], bz = (double)b.z - V.o[2];
+    const double d2 = (bx * bx + by * by) + bz * bz;
+    return V.f2 * (double)b.w / sqrt(d2);
+}
+
 // Blend: level-of-detail transition blending.  Node g with parent p takes
-// the weight t = clamp((s_p - tau) / tau, 0, 1) of the parent's projected
-// bounding-sphere size s_p = 2 max(fx, fy) r_p / |c_p - o| (FP64, in the
-// cut's order of operations), and is projected as the Gaussian with mean
-// mu_p + t (mu_g - mu_p), covariance Sigma_p + t (Sigma_g - Sigma_p) (formed
-// after projection as (1 - t) T_p T_p^T + t T_g T_g^T, positive
-// semidefinite by construction), opacity and SH coefficients interpolated
-// alike.  The blended mean and depth key follow the same FP64 steps as the
-// unblended ones.
+// the weight t = clamp((s_p - tau) / (s_p - s_g), 0, 1) of the projected
+// bounding-sphere sizes of p and g (t = 1 when s_g >= s_p), and is projected
+// as the Gaussian with mean mu_p + t (mu_g - mu_p), covariance Sigma_p +
+// t (Sigma_g - Sigma_p) (formed after projection as (1 - t) T_p T_p^T +
+// t T_g T_g^T, positive semidefinite by construction) and SH coefficients
+// interpolated alike.  Opacity: the first of p's children in the view's cut
+// carries o_p + t (o_g - o_p), the others t o_g, so that at the refine
+// decision (s_p = tau, t = 0 for every child) exactly one copy of p is drawn
+// and, at the node's own decision (s_g = tau, t = 1), the node itself: the
+// image is continuous across both.  The cut lists a parent's children that
+// it holds next to each other in ascending order (they are decided in one
+// level pass, in frontier order), so g is that first child unless the entry
+// before it is a sibling of the same view.  The blended mean and depth key
+// follow the same FP64 steps as the unblended ones.
 template <bool Blend, int DEG>
 __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
     const uint32_t m = min(a.ctr->cut, a.cut_cap);
@@ -229,19 +244,21 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
         const float4 g0 = a.geo[3 * g], g1 = a.geo[3 * g + 1], g2 = a.geo[3 * g + 2];
         int64_t pg = -1;
         double t = 1.0;
+        bool first = true;
         float4 p0 = g0;
         if (Blend) {
             const int32_t par = a.parent[g];
             if (par >= 0) {
-                const float4 b = a.bound[par];
-                {
+                const double sp = sphere_size(V, a.bound[par]), sg = sphere_size(V, a.bound[g]);
+                if (sg < sp) {
 #pragma clang fp contract(off)
-                    const double bx = (double)b.x - V.o[0], by = (double)b.y - V.o[1], bz = (double)b.z - V.o[2];
-                    const double d2 = (bx * bx + by * by) + bz * bz;
-                    const double sp = V.f2 * (double)b.w / sqrt(d2);
-                    t = (sp - V.tau) / V.tau;
+                    t = (sp - V.tau) / (sp - sg);
+                    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
                 }
-                t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+                if (i > 0) {
+                    const uint2 q = a.cut[i - 1];
+                    first = !(q.y == e.y && (int64_t)q.x >= (int64_t)a.child[par].x && (int64_t)q.x < g);
+                }
                 if (t < 1.0) {
                     pg = par;
                     p0 = a.geo[3 * pg];
@@ -257,7 +274,7 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
                 mx = (double)p0.x + t * ((double)g0.x - (double)p0.x);
                 my = (double)p0.y + t * ((double)g0.y - (double)p0.y);
                 mz = (double)p0.z + t * ((double)g0.z - (double)p0.z);
-                op = (double)p0.w + t * ((double)g0.w - (double)p0.w);
+                op = first ? (double)p0.w + t * ((double)g0.w - (double)p0.w) : t * (double)g0.w;
             }
             dx = mx - V.o[0];
             dy = my - V.o[1];

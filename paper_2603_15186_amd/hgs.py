@@ -134,11 +134,14 @@ EXPORTS = [
     ("hgs_mlp_forward", ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, _P, _P, _P, _P]),
     ("hgs_mlp_train_step", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
                                             ctypes.c_int32, ctypes.c_float, _P, _P]),
+    ("hgs_mlp_backward", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64, _P, _P, _P, _P, _P]),
+    ("hgs_mlp_adam", ctypes.c_int32, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_float]),
     ("hgs_mlp_bf16_from_master", ctypes.c_int32, [_P, _P, _P, _P]),
     ("hgs_feature_stats", ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, _P]),
     ("hgs_downsample2x", ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
     ("hgs_stream_copy", ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int64]),
     ("hgs_region_mse", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.POINTER(hgs_region), _P]),
+    ("hgs_lod_labels", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.POINTER(hgs_region), ctypes.c_float, _P, _P]),
     ("hgs_set_surfaces", ctypes.c_int32, [_P, ctypes.c_int32, _P]),
     ("hgs_render_surfaces", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
     ("hgs_slice_occupancy", ctypes.c_int32, [_P, _P, ctypes.POINTER(hgs_slice_grid), _P, _P]),
@@ -398,6 +401,16 @@ class Renderer:
                                                 feats.shape[0], _ptr(mm), _ptr(sd), ptr(master), w.data_ptr(),
                                                 ptr(m), ptr(v), int(step), float(lr), ptr(grad_out), ptr(loss_out)))
 
+    def mlp_backward(self, feats, labels, mean, std, w, grad_out, loss_out=None, stream=None):
+        mm = _np(mean, np.float32); sd = _np(std, np.float32)
+        self._check(self.lib.hgs_mlp_backward(self.ctx, self._stream(stream), feats.data_ptr(), labels.data_ptr(),
+                                              feats.shape[0], _ptr(mm), _ptr(sd), w.data_ptr(), grad_out.data_ptr(),
+                                              loss_out.data_ptr() if loss_out is not None else None))
+
+    def mlp_adam(self, grad, master, w, m, v, step, lr, stream=None):
+        self._check(self.lib.hgs_mlp_adam(self.ctx, self._stream(stream), grad.data_ptr(), master.data_ptr(),
+                                          w.data_ptr(), m.data_ptr(), v.data_ptr(), int(step), float(lr)))
+
     def mlp_bf16_from_master(self, master, w, stream=None):
         self._check(self.lib.hgs_mlp_bf16_from_master(self.ctx, self._stream(stream), master.data_ptr(), w.data_ptr()))
 
@@ -432,6 +445,23 @@ class Renderer:
                                 ref.shape[1], int(x0), int(y0))
         self._check(self.lib.hgs_region_mse(self.ctx, self._stream(stream), len(regions), arr, out.data_ptr()))
         return out
+
+    def lod_labels(self, pairs, label_db, stream=None):
+        """pairs: list of (refined img, kept img, ref, x0, y0) windows of
+        candidates; returns device float tensors (labels, drop_db)."""
+        import torch
+        n = len(pairs)
+        arr = (hgs_region * (2 * n))()
+        for i, (a, b, ref, x0, y0) in enumerate(pairs):
+            for k, img in enumerate((a, b)):
+                arr[2 * i + k] = hgs_region(img.data_ptr(), ref.data_ptr(), img.shape[2], img.shape[1], ref.shape[2],
+                                            ref.shape[1], int(x0), int(y0))
+        dev = pairs[0][2].device if n else torch.device("cuda", self.device)
+        labels = torch.empty(n, dtype=torch.float32, device=dev)
+        drop = torch.empty(n, dtype=torch.float32, device=dev)
+        self._check(self.lib.hgs_lod_labels(self.ctx, self._stream(stream), n, arr, float(label_db), labels.data_ptr(),
+                                            drop.data_ptr()))
+        return labels, drop
 
     # ------------------------------------------------------------ ground truth
     def set_surfaces(self, surfaces):

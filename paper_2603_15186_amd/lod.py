@@ -19,7 +19,8 @@ PSNR of the tau = 1 threshold cut minus that of the cut.
 Labels: for a candidate n seen from a training pose, the footprint window is
 the clipped screen box of n's bounding sphere; the window is rendered with
 the tau = 1 cut and with n's subtree collapsed to n; the label is "refine"
-when collapsing loses more than 0.05 dB of window PSNR.
+when collapsing loses more than 0.05 dB of window PSNR (hgs_lod_labels
+computes both window errors, the drop and the label on the device).
 
 Every render, feature extraction, PSNR reduction and network pass runs in
 libhgs kernels; this module selects samples, moves tensors and loops.
@@ -158,23 +159,20 @@ def make_labels(r: hgs.Renderer, cams, per_view=256, seed=0, chunk=8, s_hi=S_HI,
             win += [wc, wc]
             keep += [-1, node]
             regs.append((v, x0, y0))
-        mse = np.empty(len(win))
-        for j in range(0, len(win), MAX_VIEWS):
+        labs = []
+        for j in range(0, len(win), MAX_VIEWS):              # MAX_VIEWS is even: pairs stay together
             imgs = render_rgb(r, win[j:j + MAX_VIEWS], hgs.HGS_LOD_THRESHOLD, 1.0, keep[j:j + MAX_VIEWS])
-            out = torch.empty(len(imgs), dtype=torch.float32, device=imgs[0].device)
-            items = []
-            for q, img in enumerate(imgs):
+            pairs = []
+            for q in range(0, len(imgs), 2):
                 v, x0, y0 = regs[(j + q) // 2]
-                items.append((img, refs[v], x0, y0))
-            r.region_mse(items, out)
-            mse[j:j + len(imgs)] = out.cpu().numpy()
-        mse = np.maximum(mse, 1e-10)
-        drop = 10.0 * np.log10(mse[1::2] / mse[0::2])
-        lab = (drop > LABEL_DB).astype(np.float32)
+                pairs.append((imgs[q], imgs[q + 1], refs[v], x0, y0))
+            lab, _ = r.lod_labels(pairs, LABEL_DB)
+            labs.append(lab)
+        lab = torch.cat(labs)
         feats.append(feat[torch.from_numpy(sel).to(feat.device)])
-        labels.append(torch.from_numpy(lab).to(feat.device))
+        labels.append(lab.to(feat.device))
         stats["sampled"] += int(sel.size)
-        stats["refine"] += int(lab.sum())
+        stats["refine"] += int(lab.sum().item())
         if log:
             log(f"labels: poses {i + len(poses)}/{len(cams)}, samples {stats['sampled']}, refine {stats['refine']}")
     return torch.cat(feats), torch.cat(labels), stats

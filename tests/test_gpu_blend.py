@@ -3,10 +3,12 @@ regions between levels are smoothly interpolated) against the FP64 oracle,
 through the C ABI.
 
 The reading: a cut node g with parent p is drawn as p + t (g - p) (mean,
-covariance, opacity, SH), t = clamp((s_p - tau) / tau, 0, 1) with s_p the
-parent's projected bounding-sphere size.  Scene: the floor plan at a tenth
-of its leaves (457k nodes); thresholds of 64 and 128 px put most cut nodes
-inside the transition band, 0.01 px puts none there.
+covariance, SH), t = clamp((s_p - tau) / (s_p - s_g), 0, 1) with s_p, s_g
+the parent's and the node's projected bounding-sphere sizes; the first of
+p's children in the view's cut takes opacity o_p + t (o_g - o_p), the
+others t o_g.  Scene: the floor plan at a tenth of its leaves (457k nodes);
+thresholds of 64 and 128 px put most cut nodes inside the transition band,
+0.01 px puts none there.
 """
 import math
 
@@ -85,6 +87,11 @@ def test_blended_projection_matches_oracle(R, plan, tau):
             assert err.max() <= 1e-5, (v, f, err.max())
         np.testing.assert_array_equal(gv[:, 8], pv[:, O.PF["zkey"]].astype(np.float32))
         np.testing.assert_allclose(gv[:, 9], pv[:, O.PF["opacity"]], rtol=1e-6, atol=1e-7)
+        # later siblings (opacity t o_g) are present, in every view
+        par = scene.parent[ids]
+        prev = np.r_[-1, ids[:-1]]
+        later = (par >= 0) & (prev >= scene.first_child[np.maximum(par, 0)]) & (prev < ids)
+        assert ((t < 1) & later).sum() > 100, v
         vis = gv[:, 10] > 0
         for k, f in ((5, "r"), (6, "g"), (7, "b")):
             np.testing.assert_allclose(gv[vis, k], pv[vis, O.PF[f]], atol=2e-6)
@@ -132,3 +139,26 @@ def test_blending_is_independent_of_batching(R, plan):
         single = _render(R, scene, [cam], 96.0, blend=True)[0]
         for a, b in zip(batch[v], single):
             assert np.array_equal(a, b), v
+
+
+def test_blended_image_is_continuous_where_a_node_is_refined(R, plan):
+    """The GPU renders the two sides of a refine event (adjacent
+    single-precision camera positions, only one node refined between them):
+    the blended images differ by little more than the camera's one-ulp move
+    makes, the plain ones jump."""
+    from tests.test_blend_oracle import refine_events
+    scene, cams = plan
+    tau = 40.0
+    seen = 0
+    for node, a, b, ca, cb in refine_events(scene, cams, tau):
+        on = _render(R, scene, [a, b], tau, blend=True)
+        assert np.array_equal(R.get_cut(0), ca) and np.array_equal(R.get_cut(1), cb)
+        off = _render(R, scene, [a, b], tau, blend=False)
+        jump = np.abs(off[0][0] - off[1][0])
+        step = np.abs(on[0][0] - on[1][0])
+        print(f"node {node}: plain max {jump.max():.4f} mean {jump.mean():.2e}; "
+              f"blended max {step.max():.4f} mean {step.mean():.2e}", flush=True)
+        if jump.max() > 0.02:
+            assert step.max() < 0.2 * jump.max() and step.mean() < 0.05 * jump.mean()
+            seen += 1
+    assert seen >= 2

@@ -87,6 +87,32 @@ def test_adam_steps_match_oracle_and_are_deterministic(R):
     np.testing.assert_array_equal(runs[0], runs[1])
 
 
+def test_backward_then_adam_equals_the_training_step(R):
+    """hgs_mlp_backward followed by hgs_mlp_adam gives the fused step's
+    gradient, loss, masters, moments and BF16 weights bit for bit, over
+    three steps."""
+    F, y = _feats(11, 3000)
+    mean, std = F.mean(0), F.std(0)
+    Fd, yd = torch.from_numpy(F).cuda(), torch.from_numpy(y).cuda()
+    state = []
+    for _ in range(2):
+        master = torch.from_numpy(mlp_init(5)).cuda()
+        w = torch.empty(1377, dtype=torch.int16, device="cuda")
+        R.mlp_bf16_from_master(master, w)
+        state.append([master, w, torch.zeros_like(master), torch.zeros_like(master)])
+    g0, g1 = torch.empty(1377, device="cuda"), torch.empty(1377, device="cuda")
+    l0, l1 = torch.empty(1, device="cuda"), torch.empty(1, device="cuda")
+    for t in range(1, 4):
+        R.mlp_train_step(Fd, yd, mean, std, *state[0], t, 3e-3, grad_out=g0, loss_out=l0)
+        R.mlp_backward(Fd, yd, mean, std, state[1][1], g1, loss_out=l1)
+        R.mlp_adam(g1, *state[1], t, 3e-3)
+        torch.cuda.synchronize()
+        assert torch.equal(g0, g1) and torch.equal(l0, l1), t
+        for a, b in zip(state[0], state[1]):
+            assert torch.equal(a, b), t
+    assert l1.item() > 0
+
+
 def test_feature_stats_and_image_helpers(R):
     F, _ = _feats(9, 5000)
     ms = R.feature_stats(torch.from_numpy(F).cuda()).cpu().numpy()
@@ -103,6 +129,39 @@ def test_feature_stats_and_image_helpers(R):
     want = ((img.cpu().numpy().astype(np.float64) - big[:, 11:18, 5:14]) ** 2).mean()
     assert out[0].item() == pytest.approx(want, rel=1e-6)
     assert out[1].item() == 0.0
+
+
+def test_lod_labels_match_host_rule(R):
+    """Labels of candidate windows on the device: both window errors against
+    the reference crop (FP64 sums, FP32 results, floored at 1e-10), the
+    PSNR drop of keeping the node and the 0.05 dB rule, against the same
+    rule evaluated here from numpy errors."""
+    rng = np.random.default_rng(3)
+    ref = rng.uniform(size=(3, 40, 57)).astype(np.float32)
+    refd = torch.from_numpy(ref).cuda()
+    pairs, want_drop = [], []
+    for i in range(60):
+        w, h = int(rng.integers(1, 20)), int(rng.integers(1, 15))
+        x0, y0 = int(rng.integers(0, 57 - w + 1)), int(rng.integers(0, 40 - h + 1))
+        crop = ref[:, y0:y0 + h, x0:x0 + w]
+        a = (crop + rng.normal(size=crop.shape) * rng.choice([0.0, 0.01, 0.05])).astype(np.float32)
+        b = (a + rng.normal(size=crop.shape) * rng.choice([0.0, 0.001, 0.003, 0.02])).astype(np.float32)
+        if i == 0:
+            a, b = crop.copy(), crop.copy()                  # both exact: floored, no drop
+        pairs.append((torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), refd, x0, y0))
+        ea = max(float(np.float32(((a.astype(np.float64) - crop) ** 2).mean())), 1e-10)
+        eb = max(float(np.float32(((b.astype(np.float64) - crop) ** 2).mean())), 1e-10)
+        want_drop.append(10.0 * math.log10(eb / ea))
+    labels, drop = R.lod_labels(pairs, 0.05)
+    torch.cuda.synchronize()
+    want_drop = np.array(want_drop)
+    got = drop.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, want_drop, rtol=1e-5, atol=1e-5)
+    lab = labels.cpu().numpy()
+    clear = np.abs(want_drop - 0.05) > 1e-4
+    np.testing.assert_array_equal(lab[clear], (want_drop[clear] > 0.05).astype(np.float32))
+    assert lab[0] == 0.0 and got[0] == 0.0
+    assert 0 < lab.sum() < lab.size
 
 
 # ------------------------------------------------------------ candidates
