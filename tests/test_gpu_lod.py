@@ -2,6 +2,7 @@
 network kernels against the FP64 oracle, candidate extraction and features,
 collapsed-subtree renders, the learned cut's fallback, image helpers, and an
 end-to-end training run on a reduced floor plan."""
+import itertools
 import math
 
 import numpy as np
@@ -294,49 +295,123 @@ def test_training_pipeline_end_to_end(R, plan):
     assert model.info["calib_loss_db"] <= lod.TARGET_TRAIN_DB + 1e-9
 
 
+def _surface_options(surf, bg, o, d, tmin, eps=1e-4):
+    """FP64 ray cast of one sample against the surfaces, with every outcome
+    a single-precision cast may reach: a sample within eps of an edge, of a
+    pattern's switch or of a depth tie yields each side.  Returns the set of
+    possible colours (3-tuples)."""
+    def pattern(kind, q):
+        if kind == 1:
+            x = math.sin(2 * math.pi * q[0] / 0.4)
+            return [0.85 + 0.15 * math.copysign(1, x)] + ([0.85, 0.7, 1.0] if abs(x) < eps else [])
+        if kind == 2:
+            m = (math.floor(q[0] / 0.6) + math.floor(q[1] / 0.6)) % 2
+            near = min(abs(q[0] / 0.6 - round(q[0] / 0.6)), abs(q[1] / 0.6 - round(q[1] / 0.6))) < eps
+            return [0.9 + 0.1 * m] + ([0.9, 1.0] if near else [])
+        if kind == 3:
+            z = q[2] % 3.0
+            f = [0.55 if z < 0.12 else 0.92 + 0.08 * math.sin(2 * math.pi * (q[0] + q[1]) / 1.3)]
+            if abs(z - 0.12) < eps or z < eps or 3.0 - z < eps:
+                f += [0.55, 0.92 + 0.08 * math.sin(2 * math.pi * (q[0] + q[1]) / 1.3)]
+            return f
+        return [1.0]
+
+    def hits(s):
+        """(t, hit: True / False / None = either)."""
+        so, a, b = (np.asarray(s[k], np.float64) for k in ("o", "a", "b"))
+        if s["kind"] == 0:
+            n = np.cross(a, b)
+            t = (so - o) @ n / (d @ n)
+            p = o + t * d - so
+            u, v = p @ a / (a @ a), p @ b / (b @ b)
+            if t <= tmin:
+                return []
+            if min(u, v) > eps and max(u, v) < 1 - eps:
+                return [(t, True)]
+            if min(u, v) < -eps or max(u, v) > 1 + eps:
+                return []
+            return [(t, None)]
+        if s["kind"] == 1:
+            px, py = o[0] - so[0], o[1] - so[1]
+            A = d[0] ** 2 + d[1] ** 2
+            B = px * d[0] + py * d[1]
+            C = px * px + py * py - s["r"] ** 2
+            disc = B * B - A * C
+            if disc < 0:
+                return []
+            out = []
+            for t in ((-B - math.sqrt(disc)) / A, (-B + math.sqrt(disc)) / A):
+                z = o[2] + t * d[2]
+                if t > tmin and so[2] - eps <= z <= so[2] + s["h"] + eps:
+                    out.append((t, True if so[2] + eps < z < so[2] + s["h"] - eps else None))
+            return out
+        t = (so[2] - o[2]) / d[2]
+        if t <= tmin:
+            return []
+        r2 = (o[0] + t * d[0] - so[0]) ** 2 + (o[1] + t * d[1] - so[1]) ** 2
+        rr = float(s["r"]) ** 2
+        return [(t, True)] if r2 < rr - eps else ([] if r2 > rr + eps else [(t, None)])
+
+    cands = [(t, i, sure) for i, s in enumerate(surf) for t, sure in hits(s)]
+    cols = set()
+    # every subset of the uncertain hits may be real
+    unsure = [c for c in cands if c[2] is None]
+    for keep in itertools.product([False, True], repeat=len(unsure)):
+        real = [c for c in cands if c[2]] + [c for c, k in zip(unsure, keep) if k]
+        if not real:
+            cols.add(tuple(float(x) for x in bg))
+            continue
+        tmin_ = min(c[0] for c in real)
+        for t, i, _ in real:
+            if t <= tmin_ * (1 + eps):
+                q = o + t * d
+                for f in pattern(int(surf[i]["pattern"]), q):
+                    cols.add(tuple(float(x) for x in np.clip(surf[i]["col"] * f, 0, 1)))
+    return cols
+
+
 def test_surface_ground_truth_matches_a_plain_ray_caster(R):
-    """One rectangle facing the camera and a disk, 2x2 supersampling: the
-    kernel against a numpy ray caster of the same definition."""
+    """A rectangle facing the camera, a disk and a cylinder, 2x2
+    supersampling: the kernel against an FP64 ray caster of the same
+    definition.  Samples that fall on an edge, a pattern's switch or a depth
+    tie (within 1e-4) may land on either side in single precision: such a
+    pixel must equal one of the combinations of its samples' outcomes; all
+    others match to 1e-4.  The rectangle's top edge passes through a row of
+    samples, so the edge case is exercised."""
     from paper_2603_15186_amd.synth import SURFACE_DTYPE, yaw_camera
-    surf = np.zeros(2, SURFACE_DTYPE)
-    surf[0] = (0, 3, (-0.7, 2.0, -0.4), (1.1, 0.0, 0.0), (0.0, 0.0, 0.93), (0.8, 0.5, 0.3), 0.0, 0.0)
-    surf[1] = (2, 0, (0.3, 3.0, 0.1), (0, 0, 0), (0, 0, 0), (0.1, 0.9, 0.2), 0.6, 0.0)
+    surf = np.zeros(3, SURFACE_DTYPE)
+    surf[0] = (0, 3, (-0.7, 2.0, -0.4), (1.1, 0.0, 0.0), (0.0, 0.0, 0.9), (0.8, 0.5, 0.3), 0.0, 0.0)
+    surf[1] = (2, 0, (0.3, 3.0, -0.3), (0, 0, 0), (0, 0, 0), (0.1, 0.9, 0.2), 0.6, 0.0)
+    surf[2] = (1, 1, (0.9, 2.6, -0.5), (0, 0, 0), (0, 0, 0), (0.3, 0.4, 0.9), 0.25, 0.8)
     cam = yaw_camera(40, 30, 30.0, (0.0, 0.0, 0.05), math.pi / 2, bg=(0.2, 0.2, 0.6))
+    bg = np.asarray(cam.bg, np.float64)
     R.set_cameras([cam])
     R.set_surfaces(surf)
     got = R.render_surfaces(0, 2).cpu().numpy()
     Rm = cam.R.astype(np.float64); o = cam.position.astype(np.float64)
-    want = np.zeros((3, 30, 40))
+    n_amb = 0
+    kinds_seen = set()
     for j in range(30):
         for i in range(40):
-            acc = np.zeros(3)
+            opts = []
             for k in range(4):
                 sx, sy = i + (k % 2 + 0.5) / 2, j + (k // 2 + 0.5) / 2
                 d = Rm.T @ np.array([(sx - cam.cx) / cam.fx, (sy - cam.cy) / cam.fy, 1.0])
-                best, col = np.inf, np.array(cam.bg, np.float64)
-                so, a, b = (surf[0]["o"].astype(np.float64), surf[0]["a"].astype(np.float64),
-                            surf[0]["b"].astype(np.float64))
-                n = np.cross(a, b)
-                t = (so - o) @ n / (d @ n)
-                p = o + t * d - so
-                u, v = p @ a / (a @ a), p @ b / (b @ b)
-                if t > 0.2 and 0 <= u <= 1 and 0 <= v <= 1:
-                    best = t
-                    z = (o + t * d)[2] % 3.0
-                    f = 0.55 if z < 0.12 else 0.92 + 0.08 * math.sin(2 * math.pi * ((o + t * d)[0] + (o + t * d)[1]) / 1.3)
-                    col = np.clip(surf[0]["col"] * f, 0, 1)
-                t = (surf[1]["o"][2] - o[2]) / d[2] if abs(d[2]) > 1e-12 else -1
-                q = o + t * d
-                if 0.2 < t < best and (q[0] - 0.3) ** 2 + (q[1] - 3.0) ** 2 <= 0.36:
-                    col = np.clip(surf[1]["col"], 0, 1)
-                acc += col
-            want[:, j, i] = acc / 4
-    # single-precision ray casting: a sample on an edge may flip
-    diff = np.abs(got - want)
-    bad = diff.max(axis=0) > 1e-4
-    assert bad.mean() < 0.01, (bad.sum(), np.argwhere(bad)[:5].tolist(), got[:, bad][:, :5].T.tolist(),
-                               want[:, bad][:, :5].T.tolist())
-    assert np.median(diff) < 1e-6
+                opts.append(sorted(_surface_options(surf, bg, o, d, cam.znear)))
+            g = got[:, j, i]
+            if all(len(x) == 1 for x in opts):
+                want = np.mean([x[0] for x in opts], axis=0)
+                assert np.abs(g - want).max() <= 1e-4, (i, j, g, want)
+                kinds_seen.update(x[0] for x in opts)
+            else:
+                n_amb += 1
+                sums = [np.mean(c, axis=0) for c in itertools.product(*opts)]
+                assert min(np.abs(g - s).max() for s in sums) <= 1e-4, (i, j, g, sums)
+    assert n_amb > 0                     # some samples sit on an edge
+    # background, disk and both cylinder stripes appear unambiguously
+    for c in (bg, surf[1]["col"], surf[2]["col"], surf[2]["col"] * 0.7):
+        assert any(np.abs(np.asarray(k) - c).max() < 1e-6 for k in kinds_seen), c
+    assert len(kinds_seen) > 20          # and the rectangle's wall pattern
 
 
 # --------------------------------- the benchmark's step at full size
