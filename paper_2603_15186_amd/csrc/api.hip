@@ -28,7 +28,7 @@ struct DevMem {
 // alternate between two sets on two streams, so one pass's compositing
 // overlaps the next pass's cut, projection and binning.
 struct Work {
-    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, bins, offsets, dec;
+    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, bins, offsets, dec, runs;
     DevMem pkey[2], pval[2], scan_tmp, hist;
 };
 
@@ -186,6 +186,12 @@ int bits_for(uint32_t n) {
     return b;
 }
 
+// Pair sort keys are view << bits_for(tiles of the largest view) | tile
+// within the view, below 2^31.
+bool pair_keys_fit(int n_views, uint64_t max_view_tiles) {
+    return max_view_tiles < (1ull << 31) && bits_for((uint32_t)n_views) + bits_for((uint32_t)max_view_tiles) <= 31;
+}
+
 __global__ void k_reset(Counters* c) {
     if (threadIdx.x == 0) {
         Counters z = {};
@@ -214,6 +220,7 @@ hgs_status alloc_work(hgs_ctx* c) {
         if ((s = ensure(c, w.offsets, M * 4))) return s;
         if ((s = ensure(c, w.scan_tmp, (kScanBlocks + 1) * sizeof(uint4)))) return s;
         if ((s = ensure(c, w.hist, kSortHistBytes))) return s;
+        if ((s = ensure(c, w.runs, kMaxRunSlots * sizeof(uint32_t)))) return s;
     }
     return HGS_OK;
 }
@@ -224,7 +231,7 @@ int lane_of(const hgs_ctx* c, int g) { return c->lanes > 1 ? g % c->lanes : 0; }
 void release_work(Work& w) {
     DevMem* all[] = {&w.frontier[0], &w.frontier[1], &w.cut, &w.proj, &w.dkey[0], &w.dkey[1], &w.dval[0],
                      &w.dval[1], &w.ntiles, &w.bins, &w.offsets, &w.dec, &w.pkey[0], &w.pkey[1], &w.pval[0],
-                     &w.pval[1], &w.scan_tmp, &w.hist};
+                     &w.pval[1], &w.scan_tmp, &w.hist, &w.runs};
     for (DevMem* m : all) release(*m);
 }
 
@@ -409,6 +416,13 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     launch_cut(ca, s);
     mark(c, 1, s);
 
+    // pair keys: view << key_shift | tile within the view, so that once the
+    // entries are grouped by view only the tile bits need sorting
+    uint32_t max_tiles = 1;
+    for (int v = v0; v < v1; ++v)
+        max_tiles = std::max(max_tiles, (uint32_t)(c->views_host[v].tiles_x * c->views_host[v].tiles_y));
+    const int key_shift = bits_for(max_tiles);
+
     ProjectArgs pa{};
     pa.cut = ca.cut;
     pa.cut_cap = c->cut_cap;
@@ -430,6 +444,15 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pa.child = P<int2>(c->child);
     pa.tile_w = c->ropts.tile_w;
     pa.tile_h = c->ropts.tile_h;
+    pa.key_shift = key_shift;
+    // views of the depth-sorted entries come from the table of the cut's runs
+    const int cut_levels = (ca.flat || ca.mode == HGS_LOD_ALL_LEAVES) ? 1 : ca.n_levels;
+    const int n_slots = cut_levels * ca.n_views;
+    const bool use_runs = ca.n_views > 1 && n_slots <= kMaxRunSlots;
+    pa.runs = use_runs ? P<uint32_t>(W.runs) : nullptr;
+    pa.n_cut_levels = cut_levels;
+    pa.n_views = ca.n_views;
+    if (use_runs) launch_runs_reset(pa.runs, n_slots, s);
     launch_project(pa, s);
     mark(c, 2, s);
 
@@ -443,7 +466,18 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     sa.key_bits = 32;
     sa.max_digit_bits = c->sort_digit_bits;
     sa.hist = P<uint32_t>(W.hist);
-    const int dr = launch_sort(sa, s);
+    int dr = launch_sort(sa, s);
+    if (ca.n_views > 1) {
+        // stable pass on the entries' views: depth order within each view
+        launch_view_keys(sa.vals[dr], ca.cut, pa.runs, n_slots, ca.n_views, &ctr->cut, c->cut_cap, sa.keys[dr], s);
+        SortArgs sv = sa;
+        sv.keys[0] = sa.keys[dr];
+        sv.keys[1] = sa.keys[dr ^ 1];
+        sv.vals[0] = sa.vals[dr];
+        sv.vals[1] = sa.vals[dr ^ 1];
+        sv.key_bits = bits_for((uint32_t)ca.n_views);
+        dr ^= launch_sort(sv, s);
+    }
 
     EmitArgs ea{};
     ea.order = sa.vals[dr];
@@ -469,7 +503,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pb.vals[1] = P<uint32_t>(W.pval[1]);
     pb.count = &ctr->pairs;
     pb.cap = c->pair_cap;
-    pb.key_bits = bits_for(t1 - t0);
+    pb.key_bits = key_shift;
     pb.max_digit_bits = c->sort_digit_bits;
     pb.hist = sa.hist;
     const int pr = launch_sort(pb, s);
@@ -490,6 +524,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     xa.views = ca.views;
     xa.tile_view = P<uint32_t>(c->tile_view) + t0;
     xa.n_views = ca.n_views;
+    xa.key_shift = key_shift;
     xa.opts = c->ropts;
     xa.ctr = ctr;
     xa.state = c->ropts.keep_state ? P<uint2>(c->px_state) + (size_t)t0 * kTilePx : nullptr;
@@ -882,13 +917,15 @@ hgs_status hgs_set_cameras(hgs_ctx* c, int32_t n, const hgs_camera* cams) {
     HIP_TRY(c, hipSetDevice(c->device));
     // tile layout: views in order, row-major tiles within a view
     const int tw = c->ropts.tile_w, th = c->ropts.tile_h;
-    uint64_t tiles = 0;
+    uint64_t tiles = 0, max_tiles = 1;
     std::vector<uint32_t> tile_base(n);
     for (int v = 0; v < n; ++v) {
         tile_base[v] = (uint32_t)tiles;
-        tiles += (uint64_t)((cams[v].width + tw - 1) / tw) * ((cams[v].height + th - 1) / th);
+        const uint64_t t = (uint64_t)((cams[v].width + tw - 1) / tw) * ((cams[v].height + th - 1) / th);
+        tiles += t;
+        max_tiles = std::max(max_tiles, t);
     }
-    if (tiles >= (1ull << 31)) return fail(c, HGS_E_UNSUPPORTED, "too many tiles");
+    if (tiles >= (1ull << 31) || !pair_keys_fit(n, max_tiles)) return fail(c, HGS_E_UNSUPPORTED, "too many tiles");
     // same view count and image sizes as before: the tile layout, its device
     // table and a captured render stay valid (camera poses live in device
     // memory uploaded before each render)
@@ -985,13 +1022,15 @@ hgs_status relayout_tiles(hgs_ctx* c) {
     const int V = (int)c->cams.size();
     if (V == 0) return HGS_OK;
     const int tw = c->ropts.tile_w, th = c->ropts.tile_h;
-    uint64_t tiles = 0;
+    uint64_t tiles = 0, max_tiles = 1;
     std::vector<uint32_t> base(V);
     for (int v = 0; v < V; ++v) {
         base[v] = (uint32_t)tiles;
-        tiles += (uint64_t)((c->cams[v].width + tw - 1) / tw) * ((c->cams[v].height + th - 1) / th);
+        const uint64_t t = (uint64_t)((c->cams[v].width + tw - 1) / tw) * ((c->cams[v].height + th - 1) / th);
+        tiles += t;
+        max_tiles = std::max(max_tiles, t);
     }
-    if (tiles >= (1ull << 31)) return fail(c, HGS_E_UNSUPPORTED, "too many tiles");
+    if (tiles >= (1ull << 31) || !pair_keys_fit(V, max_tiles)) return fail(c, HGS_E_UNSUPPORTED, "too many tiles");
     hgs_status s;
     if ((s = ensure(c, c->tile_view, tiles * 4)) || (s = ensure(c, c->ranges, tiles * sizeof(uint2)))) return s;
     HIP_TRY(c, hipEventSynchronize(c->views_copied));

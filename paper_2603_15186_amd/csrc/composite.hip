@@ -102,11 +102,17 @@ __global__ void k_ranges_zero(uint2* ranges, uint32_t n) {
         ranges[i] = make_uint2(0, 0);
 }
 
-// [first, last + 1) of every tile's run in the tile-sorted keys, four keys
+// [first, last + 1) of every tile's run in the grouped pair keys, four keys
 // per thread and step (16-byte loads; key arrays start 256-byte aligned).
+// A key view << shift | local names the tile tile_base(view) + local of the
+// pass; equal keys form one run.
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const Counters* ctr, uint32_t cap, uint2* ranges,
-                         uint32_t n_tiles) {
+                         uint32_t n_tiles, const ViewDev* views, int n_views, int shift) {
+    __shared__ uint32_t s_base[kMaxViews];
+    for (int v = threadIdx.x; v < n_views; v += blockDim.x) s_base[v] = views[v].tile_base;
+    __syncthreads();
     const uint32_t P = min(ctr->pairs, cap);
+    const uint32_t lmask = (1u << shift) - 1u;
     for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; 4ull * q < P; q += gridDim.x * blockDim.x) {
         const uint32_t i0 = 4 * q;
         uint32_t k[6];
@@ -122,9 +128,14 @@ __global__ void k_ranges(const uint32_t* __restrict__ keys, const Counters* ctr,
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t kk = k[1 + j];
-            if (kk >= n_tiles) continue;
-            if (k[j] != kk) ranges[kk].x = i0 + j;
-            if (k[j + 2] != kk) ranges[kk].y = i0 + j + 1;
+            const bool first = k[j] != kk, last = k[j + 2] != kk;
+            if (!first && !last) continue;
+            const uint32_t v = kk >> shift;
+            if (v >= (uint32_t)n_views) continue;
+            const uint32_t t = s_base[v] + (kk & lmask);
+            if (t >= n_tiles) continue;
+            if (first) ranges[t].x = i0 + j;
+            if (last) ranges[t].y = i0 + j + 1;
         }
     }
 }
@@ -414,7 +425,8 @@ bool tile_shape_ok(int tw, int th, int px) {
 
 void launch_ranges(const CompositeArgs& a, hipStream_t s) {
     k_ranges_zero<<<1024, 256, 0, s>>>(a.ranges, a.total_tiles);
-    k_ranges<<<4096, 256, 0, s>>>(a.keys, a.ctr, a.pair_cap, a.ranges, a.total_tiles);
+    k_ranges<<<4096, 256, 0, s>>>(a.keys, a.ctr, a.pair_cap, a.ranges, a.total_tiles, a.views, a.n_views,
+                                  a.key_shift);
 }
 
 void launch_composite(const CompositeArgs& a, hipStream_t s) {

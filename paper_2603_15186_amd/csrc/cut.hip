@@ -245,6 +245,7 @@ __global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G, uint32_t
         k->visited += n_in < in_cap ? n_in : in_cap;
         const uint32_t base = k->cut;
         const uint32_t cbase = k->cand;
+        k->level_cut[c.level] = base;
         c.tmp[G] = make_uint4(base, 0, cbase, 0);
         if (c.cand != nullptr) {
             const uint64_t want = (uint64_t)cbase + tot.z;

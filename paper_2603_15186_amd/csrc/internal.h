@@ -66,12 +66,15 @@ struct alignas(16) Proj {
 // (16 bytes, so the depth-ordered emission gathers one record).
 struct alignas(16) BinRec {
     ushort4 rc;                      // tile rectangle x0, y0, x1, y1 (inclusive)
-    uint32_t tile_base;              // first tile id of the view within its pass
+    uint32_t tile_base;              // sort key of the view's first tile: view << key_shift
     uint16_t tiles_x;
     uint16_t height;                 // image height in pixels
 };
 
 // Device counters of one render.
+constexpr int kCutLevels = 64;       // hierarchy levels at most (scene validation enforces it)
+constexpr int kMaxRunSlots = 8192;   // (level, view) slots of the table that maps cut entries to views
+
 struct Counters {
     uint32_t frontier[2];            // frontier sizes (ping, pong)
     uint32_t cut;                    // cut entries written so far
@@ -87,6 +90,7 @@ struct Counters {
     unsigned long long nalg;         // evaluated (pixel, Gaussian) pairs with q <= 9
     unsigned long long neval;        // (pixel, list entry) slots the compositor walked
     unsigned long long visited;      // (node, view) pairs the cut tested, over all levels
+    uint32_t level_cut[kCutLevels];  // cut size when each level's entries began
 };
 
 // Options of the compositor and binning.
@@ -177,8 +181,25 @@ struct ProjectArgs {
     const float4* bound;
     const int2* child;
     int tile_w, tile_h;              // tile shape in pixels
+    int key_shift;                   // pair sort keys: view << key_shift | tile within the view
+    // The cut holds, level after level, each view's entries as one run: the
+    // first index of the run of (level L, view v) goes to runs[L * n_views +
+    // v] (null: not recorded; slots without a run keep ~0u).
+    uint32_t* runs;
+    int n_cut_levels;
+    int n_views;
 };
 void launch_project(const ProjectArgs& a, hipStream_t s);
+
+// keys[i] = view of the depth-sorted entry order[i] (order: index | tiles
+// << 28), so that a stable pass on them groups the entries by view.  With a
+// run table (n_slots = levels x views <= kMaxRunSlots; reset by
+// launch_runs_reset before the projection fills it) the view is found by a
+// search over the runs' first indices; without one (runs null) it is read
+// from the cut.
+void launch_runs_reset(uint32_t* runs, int n_slots, hipStream_t s);
+void launch_view_keys(const uint32_t* order, const uint2* cut, uint32_t* runs, int n_slots, int n_views,
+                      const uint32_t* count, uint32_t cap, uint32_t* keys, hipStream_t s);
 
 // Pair emission in depth order: offsets = exclusive scan of ntiles over the
 // depth-sorted entries.
@@ -215,12 +236,13 @@ struct SortArgs {
 int launch_sort(const SortArgs& a, hipStream_t s);
 
 struct CompositeArgs {
-    const uint32_t* keys;            // sorted tile ids
+    const uint32_t* keys;            // pair sort keys (view << key_shift | tile within the view), grouped
     const uint32_t* vals;            // entry indices
     uint32_t pair_cap;
     uint32_t cut_cap;
     uint2* ranges;                   // [total_tiles]
     uint32_t total_tiles;
+    int key_shift;
     const Proj* proj;
     const ViewDev* views;
     const uint32_t* tile_view;       // [total_tiles] view of each global tile
