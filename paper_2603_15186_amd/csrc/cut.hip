@@ -79,6 +79,7 @@ struct LevelCtx {
     uint2* cand;
     uint32_t cand_cap;
     int level;
+    bool leaves;              // the last level: every node is a leaf (no child ranges to read)
     int out_slot;             // index of the next frontier's counter
 };
 
@@ -129,7 +130,8 @@ __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap
         const uint2 e0 = v0 ? c.in[i0] : make_uint2(0, 0);
         const uint2 e1 = v1 ? c.in[i1] : make_uint2(0, 0);
         const float4 b0 = c.bound[e0.x], b1 = c.bound[e1.x];
-        const int2 ch0 = c.child[e0.x], ch1 = c.child[e1.x];
+        const int2 ch0 = c.leaves ? make_int2(0, 0) : c.child[e0.x];
+        const int2 ch1 = c.leaves ? make_int2(0, 0) : c.child[e1.x];
         decide(i0, v0, e0, b0, ch0);
         decide(i1, v1, e1, b1, ch1);
     }
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap)
         uint2 e = make_uint2(0, 0);
         if (i < hi) {
             e = c.in[i];
-            r = counts_of(c, c.dec[i], c.child[e.x].y);
+            r = counts_of(c, c.dec[i], c.leaves ? 0 : c.child[e.x].y);
         }
         uint4 tot;
         const uint4 ex = block_excl_scan4<kNT>(r, sh, &tot);
@@ -414,9 +416,11 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.cand = a.cand;
         c.cand_cap = a.cand_cap;
         c.level = L;
+        c.leaves = L == a.n_levels - 1;
         c.out_slot = cur ^ 1;
         k_level_count<<<G, kNT, 0, s>>>(c, a.frontier_cap);
-        if (c.defer) k_level_mlp<<<G, kNT, 0, s>>>(c, a.frontier_cap);
+        // a leaf is never refined, so the last level has no candidates
+        if (c.defer && !c.leaves) k_level_mlp<<<G, kNT, 0, s>>>(c, a.frontier_cap);
         k_level_scan<<<1, 1024, 0, s>>>(c, G, a.frontier_cap);
         k_level_emit<<<G, kNT, 0, s>>>(c, a.frontier_cap);
         cur ^= 1;
