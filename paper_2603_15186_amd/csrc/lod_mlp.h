@@ -62,23 +62,27 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 // log projected size of the parent.
 __device__ __forceinline__ void lod_features(const LodMlpDev& m, const ViewDev& V, int k, float4 b,
                                              const NodeGeom& g, int level, float f[kMlpIn]) {
-    const double dist = sqrt(g.d2);
-    const double inv = 1.0 / (dist > 1e-9 ? dist : 1e-9);
-    const double size = V.f2 * g.r * inv;
-    f[0] = (float)log(size > 1e-6 ? size : 1e-6);
-    f[1] = (float)log(g.pz > V.znear ? g.pz : V.znear);
+    // The features only feed the network, whose decisions are compared with
+    // a 1e-3 margin on the logit: single precision (the hardware log2 and
+    // reciprocal square root, a few ulp) is far inside it.  The differences
+    // to the camera come from the FP64 geometry.
+    constexpr float kLn2 = 0.69314718055994531f;
+    const float inv = __builtin_amdgcn_rsqf(fmaxf((float)g.d2, 1e-18f));      // 1 / max(|c - o|, 1e-9)
+    const float f2 = (float)V.f2;
+    f[0] = kLn2 * __log2f(fmaxf(f2 * (float)g.r * inv, 1e-6f));
+    f[1] = kLn2 * __log2f((float)(g.pz > V.znear ? g.pz : V.znear));
     const float4 nf = m.nodefeat[3 * (int64_t)k], pb = m.nodefeat[3 * (int64_t)k + 1],
                  oc = m.nodefeat[3 * (int64_t)k + 2];
     f[2] = oc.x;
     f[3] = oc.y;
     f[4] = nf.w;
-    f[5] = (float)fabs((g.dx * nf.x + g.dy * nf.y + g.dz * nf.z) * inv);
+    f[5] = fabsf(((float)g.dx * nf.x + (float)g.dy * nf.y + (float)g.dz * nf.z) * inv);
     f[6] = (float)level;
     if (pb.w >= 0.f) {
-        const double qx = (double)pb.x - V.o[0], qy = (double)pb.y - V.o[1], qz = (double)pb.z - V.o[2];
-        const double pd = sqrt(qx * qx + qy * qy + qz * qz);
-        const double ps = V.f2 * (double)pb.w / (pd > 1e-9 ? pd : 1e-9);
-        f[7] = (float)log(ps > 1e-6 ? ps : 1e-6);
+        const float qx = (float)((double)pb.x - V.o[0]), qy = (float)((double)pb.y - V.o[1]),
+                    qz = (float)((double)pb.z - V.o[2]);
+        const float pinv = __builtin_amdgcn_rsqf(fmaxf(qx * qx + qy * qy + qz * qz, 1e-18f));
+        f[7] = kLn2 * __log2f(fmaxf(f2 * pb.w * pinv, 1e-6f));
     } else {
         f[7] = f[0];
     }
