@@ -611,19 +611,19 @@ def run_building(args):
         t0 = time.perf_counter()
         pr = O.project(scene, leaves, cam)
         t1 = time.perf_counter()
-        px = rng.integers(0, cam.width, n_px)
-        py = rng.integers(0, cam.height, n_px)
-        pres = O.render_pixels(pr, cam, px, py)
+        sx = rng.integers(0, cam.width, n_px)
+        sy = rng.integers(0, cam.height, n_px)
+        pres = O.render_pixels(pr, cam, sx, sy)
         t_pix += time.perf_counter() - t1
         t_proj += t1 - t0
         ref = pres.primary[:, :3]
         for k, im in imgs.items():
-            se[k] += float(((im[v][:, py, px].T.astype(np.float64) - ref) ** 2).sum())
+            se[k] += float(((im[v][:, sy, sx].T.astype(np.float64) - ref) ** 2).sum())
         del pr
     npx_frame = sample[0].width * sample[0].height
     for k in imgs:
         mse = max(se[k] / (3 * n_px * len(sample)), 1e-10)
-        q.setdefault(k, {})["psnr_vs_oracle_full_leaf_db"] = 10.0 * np.log10(1.0 / mse)
+        q.setdefault(k, {})["psnr_vs_oracle_full_leaf_db"] = float(10.0 * np.log10(1.0 / mse))
     oracle_s_frame = (t_proj + t_pix * npx_frame / n_px) / len(sample)
     q["oracle_reference"] = (f"FP64 oracle full-leaf render ({leaves.size} leaves projected per view) of {n_px} "
                              f"random pixels in each of the 8 views; PSNR over those pixels")
