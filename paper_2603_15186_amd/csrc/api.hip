@@ -218,7 +218,7 @@ hgs_status alloc_work(hgs_ctx* c) {
         if ((s = ensure(c, w.ntiles, M * 4))) return s;
         if ((s = ensure(c, w.bins, M * sizeof(BinRec)))) return s;
         if ((s = ensure(c, w.offsets, M * 4))) return s;
-        if ((s = ensure(c, w.scan_tmp, (kScanBlocks + 1) * sizeof(uint4)))) return s;
+        if ((s = ensure(c, w.scan_tmp, (std::max(kScanBlocks, kCutBlocks) + 1) * sizeof(uint4)))) return s;
         if ((s = ensure(c, w.hist, kSortHistBytes))) return s;
         if ((s = ensure(c, w.runs, kMaxRunSlots * sizeof(uint32_t)))) return s;
     }

@@ -234,13 +234,31 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
 }
 
+// Exclusive scan of the G <= 4 * 1024 block counts (four consecutive ones
+// per thread).
 __global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G, uint32_t in_cap) {
     __shared__ uint4 sh[1024 / kWave + 1];
     const int t = threadIdx.x;
-    const uint4 x = t < G ? c.tmp[t] : make_uint4(0, 0, 0, 0);
+    uint4 x[4];
+    uint4 sum = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int b = 4 * t + j;
+        x[j] = b < G ? c.tmp[b] : make_uint4(0, 0, 0, 0);
+        sum.x += x[j].x;
+        sum.y += x[j].y;
+        sum.z += x[j].z;
+    }
     uint4 tot;
-    const uint4 ex = block_excl_scan4<1024>(x, sh, &tot);
-    if (t < G) c.tmp[t] = ex;
+    uint4 ex = block_excl_scan4<1024>(sum, sh, &tot);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int b = 4 * t + j;
+        if (b < G) c.tmp[b] = ex;
+        ex.x += x[j].x;
+        ex.y += x[j].y;
+        ex.z += x[j].z;
+    }
     if (t == 0) {
         Counters* k = c.ctr;
         const uint32_t n_in = *c.in_count;
@@ -383,7 +401,8 @@ void launch_lod_features(const uint2* cand, const uint32_t* count, const ViewDev
 }
 
 void launch_cut(const CutArgs& a, hipStream_t s) {
-    const int G = kScanBlocks;
+    const int G = kCutBlocks;
+    static_assert(kCutBlocks <= 4 * 1024, "the level scan takes four counts per thread");
     if (a.flat || a.mode == HGS_LOD_ALL_LEAVES) {
         const uint32_t n = a.flat ? (uint32_t)a.n_nodes : (uint32_t)a.n_leaves;
         const int32_t* ids = a.flat ? nullptr : a.leaf_ids;

@@ -114,6 +114,7 @@ bool tile_shape_ok(int tile_w, int tile_h, int px);
 
 // Scan scratch needs (uint2 / uint32 elements).
 constexpr int kScanBlocks = 1024;
+constexpr int kCutBlocks = 4096;     // workgroups of a cut level's count and emit passes
 constexpr int kSortBlocks = 1024;
 constexpr int kSortBins = 2048;          // widest radix digit: 11 bits
 constexpr int kSortGroup = 8192;         // histogram groups of the radix sort: multiples of this size,
