@@ -413,21 +413,43 @@ __global__ __launch_bounds__(kNT) void k_scan_reduce(ScanCtx c) {
     if (threadIdx.x == 0) c.tmp[blockIdx.x] = make_uint4(tot, 0, 0, 0);
 }
 
+// Exclusive scan of the G <= 4 * 1024 block counts (four consecutive ones
+// per thread); the total is also summed in 64 bits so that pair counts
+// beyond 2^32 are caught as overflow.
 __global__ __launch_bounds__(1024) void k_scan_blocks(ScanCtx c, int G) {
     __shared__ uint32_t sh[1024 / kWave + 1];
+    __shared__ unsigned long long sh64[1024 / kWave];
     const int t = threadIdx.x;
-    // 64-bit running total: detect pair counts beyond 2^32 as overflow
-    const uint32_t x = t < G ? c.tmp[t].x : 0u;
+    uint32_t x[4], sum = 0;
+    unsigned long long sum64 = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int b = 4 * t + j;
+        x[j] = b < G ? c.tmp[b].x : 0u;
+        sum += x[j];
+        sum64 += x[j];
+    }
     uint32_t tot;
-    const uint32_t ex = block_excl_scan<1024>(x, sh, &tot);
-    if (t < G) c.tmp[t].x = ex;
+    uint32_t ex = block_excl_scan<1024>(sum, sh, &tot);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int b = 4 * t + j;
+        if (b < G) c.tmp[b].x = ex;
+        ex += x[j];
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) sum64 += __shfl_xor(sum64, o, kWave);
+    if (lane_id() == 0) sh64[t / kWave] = sum64;
+    __syncthreads();
     if (t == 0) {
+        unsigned long long total = 0;
+        for (int w = 0; w < 1024 / kWave; ++w) total += sh64[w];
         Counters* k = c.ctr;
-        if (tot > c.pair_cap) {
+        if (total > c.pair_cap) {
             k->overflow |= kOvPairs;
-            if (tot > k->need_pairs) k->need_pairs = tot;
+            const uint32_t need = (uint32_t)(total < 0xffffffffull ? total : 0xffffffffull);
+            if (need > k->need_pairs) k->need_pairs = need;
         }
-        k->pairs = tot < c.pair_cap ? tot : c.pair_cap;
+        k->pairs = total < c.pair_cap ? (uint32_t)total : c.pair_cap;
     }
 }
 
@@ -638,7 +660,8 @@ void launch_view_keys(const uint32_t* order, const uint2* cut, uint32_t* runs, i
 }
 
 void launch_emit(const EmitArgs& a, hipStream_t s) {
-    const int G = kScanBlocks;
+    const int G = kCutBlocks;
+    static_assert(kCutBlocks <= 4 * 1024, "the block scan takes four counts per thread");
     ScanCtx c;
     c.order = a.order;
     c.ntiles = a.ntiles;
@@ -651,7 +674,7 @@ void launch_emit(const EmitArgs& a, hipStream_t s) {
     k_scan_reduce<<<G, kNT, 0, s>>>(c);
     k_scan_blocks<<<1, 1024, 0, s>>>(c, G);
     k_scan_write<<<G, kNT, 0, s>>>(c);
-    k_emit<<<2048, kNT, 0, s>>>(a);
+    k_emit<<<8192, kNT, 0, s>>>(a);
 }
 
 }  // namespace hgs
