@@ -239,6 +239,24 @@ def test_batched_views_equal_single_views(R, plan_small):
             assert np.array_equal(a, b), v
 
 
+def test_very_large_batch_equals_single_views(R, plan_small):
+    """More views than the table of the cut's (level, view) runs holds
+    (levels x views > 8,192): the views of the depth-sorted entries are then
+    read from the cut.  Tiny views; sampled views equal their single-view
+    renders bitwise and the last view's cut equals the oracle's."""
+    scene, cams = plan_small
+    n_levels = len(scene.level_offset) - 1
+    n_views = 8192 // n_levels + 64
+    assert n_levels * n_views > 8192
+    views = [_small_cam(cams[v % len(cams)], 24 + (v % 3) * 8, 16 + (v % 5) * 4) for v in range(n_views)]
+    batch = _render(R, scene, views)
+    assert np.array_equal(R.get_cut(n_views - 1), O.cut(scene, views[-1], O.MODE_THRESHOLD, 1.0))
+    for v in list(range(0, n_views, 97)) + [n_views - 1]:
+        single = _render(R, scene, [views[v]])[0]
+        for a, b in zip(batch[v], single):
+            assert np.array_equal(a, b), v
+
+
 def test_multi_pass_batches_equal_one_pass(R, plan_small):
     """A batch split into passes (at most 2 views, then 1 view per pass)
     gives the one-pass images bitwise, also replayed from a captured graph;
