@@ -246,17 +246,56 @@ def evaluate(r: hgs.Renderer, cams, refs, model: LodModel | None = None, p_star=
 P_GRID = (0.95, 0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3, 0.2, 0.1, 0.05, 0.02, 0.01)
 
 
-def calibrate(r: hgs.Renderer, model: LodModel, cams, refs, base_psnr, target=TARGET_TRAIN_DB, grid=P_GRID):
+def calibrate(r: hgs.Renderer, model: LodModel, cams, refs, base_psnr, target=TARGET_TRAIN_DB, grid=P_GRID,
+              refine=5):
     """Largest p_star (refine iff P(refine) >= p_star) whose PSNR loss on
     cams is within target; 0 (always refine: the threshold cut) when none
-    is.  Returns (p_star, loss, table of (p, loss, cut size))."""
+    is.  The descending grid finds the first value within target; `refine`
+    bisection steps between it and the grid value above it (which was not)
+    then look for a larger one.  Returns (p_star, loss, table of (p, loss,
+    cut size)) with every value tried."""
     table = []
-    for p in grid:
+
+    def loss_of(p):
         mp, cut, _ = evaluate(r, cams, refs, model, p_star=p)
         table.append((p, base_psnr - mp, cut))
-        if base_psnr - mp <= target:
-            return p, base_psnr - mp, table
+        return base_psnr - mp
+
+    above = None
+    for p in grid:
+        loss = loss_of(p)
+        if loss <= target:
+            best = (p, loss)
+            if above is not None:
+                lo, hi = p, above
+                for _ in range(refine):
+                    mid = 0.5 * (lo + hi)
+                    m = loss_of(mid)
+                    if m <= target:
+                        lo = mid
+                        best = (mid, m)
+                    else:
+                        hi = mid
+            return best[0], best[1], table
+        above = p
     return 0.0, 0.0, table
+
+
+def recalibrate(r: hgs.Renderer, model: LodModel, train_cams, calib_n=64, log=None) -> LodModel:
+    """Calibrate p_star of a trained model afresh, on the calibration poses
+    train_pipeline takes (every k-th training pose)."""
+    step = max(1, len(train_cams) // calib_n)
+    ccams = train_cams[::step][:calib_n]
+    crefs = reference_images(r, ccams)
+    base, _, _ = evaluate(r, ccams, crefs, None, tau=1.0)
+    p, loss, table = calibrate(r, model, ccams, crefs, base)
+    model.p_star = p
+    model.info.update({"calib_loss_db": loss, "calib_views": len(ccams)})
+    if log:
+        for row in table:
+            log("  p* %.4f: loss %.4f dB, cut %d" % row)
+        log(f"calibrated p* = {p:.4f} (training-pose loss {loss:.4f} dB)")
+    return model
 
 
 def train_pipeline(r: hgs.Renderer, train_cams, calib_n=64, per_view=256, epochs=40, seed=0, log=None,
@@ -321,6 +360,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--calib", type=int, default=64)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--recalibrate", action="store_true",
+                    help="keep the saved network's weights and calibrate its p* afresh")
     args = ap.parse_args(argv)
     t0 = time.time()
     log = lambda *a: print(*a, flush=True)  # noqa: E731
@@ -335,10 +376,15 @@ def main(argv=None):
     r = hgs.Renderer(0)
     r.load_scene(scene)
     r.set_surfaces(plan.surfaces)
-    model = train_pipeline(r, train_cams[:args.train], calib_n=args.calib, per_view=args.per_view,
-                           epochs=args.epochs, seed=args.seed, log=log)
+    if args.recalibrate:
+        src = default_model_path() if args.scene == "plan2m" else default_model_path("building30m_lod_mlp.npz")
+        model = recalibrate(r, LodModel.load(src), train_cams[:args.train], calib_n=args.calib, log=log)
+    else:
+        model = train_pipeline(r, train_cams[:args.train], calib_n=args.calib, per_view=args.per_view,
+                               epochs=args.epochs, seed=args.seed, log=log)
     model.info["train_views"] = min(args.train, len(train_cams))
-    model.info["seconds"] = time.time() - t0
+    if not args.recalibrate:
+        model.info["seconds"] = time.time() - t0
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     model.save(out)
     print("saved", out, model.p_star, model.info, flush=True)
