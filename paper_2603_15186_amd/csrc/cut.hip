@@ -437,11 +437,16 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.level = L;
         c.leaves = L == a.n_levels - 1;
         c.out_slot = cur ^ 1;
-        k_level_count<<<G, kNT, 0, s>>>(c, a.frontier_cap);
+        // the frontier holds at most (nodes of level L) x views entries;
+        // small levels get a grid of that size (the chunking keeps the
+        // entries' order, so the cut does not depend on the grid)
+        const uint64_t bound = (uint64_t)(a.level_offset_host[L + 1] - a.level_offset_host[L]) * (uint64_t)a.n_views;
+        const int GL = (int)std::min<uint64_t>((uint64_t)G, std::max<uint64_t>(1, (bound + kNT - 1) / kNT));
+        k_level_count<<<GL, kNT, 0, s>>>(c, a.frontier_cap);
         // a leaf is never refined, so the last level has no candidates
-        if (c.defer && !c.leaves) k_level_mlp<<<G, kNT, 0, s>>>(c, a.frontier_cap);
-        k_level_scan<<<1, 1024, 0, s>>>(c, G, a.frontier_cap);
-        k_level_emit<<<G, kNT, 0, s>>>(c, a.frontier_cap);
+        if (c.defer && !c.leaves) k_level_mlp<<<GL, kNT, 0, s>>>(c, a.frontier_cap);
+        k_level_scan<<<1, 1024, 0, s>>>(c, GL, a.frontier_cap);
+        k_level_emit<<<GL, kNT, 0, s>>>(c, a.frontier_cap);
         cur ^= 1;
     }
 }
