@@ -493,6 +493,46 @@ def test_bench_step_at_full_size(R, plan_lod):
         R.set_option(hgs.HGS_OPT_USE_GRAPH, 0)
 
 
+def test_learned_cut_with_candidates_in_the_top_levels(R, plan_lod):
+    """Views so small (48x27 px) that the hierarchy's top levels fall in the
+    learned cut's band, so the network decides nodes of levels 0..2 (the
+    levels whose grids are sized to their few entries); starting from a
+    1,024-entry capacity, so that the frontier overflows and the render
+    regrows.  Every view's cut equals the oracle's learned cut, and sampled
+    pixels match the oracle's render of it."""
+    from paper_2603_15186_amd import hgs, lod
+    scene, held = plan_lod
+    model = lod.LodModel.load(lod.default_model_path())
+    views = []
+    for c in held[:8]:
+        yaw = math.atan2(c.R[2][1], c.R[2][0])
+        views.append(W.yaw_camera(48, 27, 900.0 * 48 / 1280, c.position, yaw))
+    R.load_scene(scene)
+    R.set_cameras(views)
+    R.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
+    ent, _, _ = R.lod_candidates(model.s_hi)
+    top = int(scene.level_offset[3])
+    assert (ent.cpu().numpy()[:, 0] < top).any()       # candidates among levels 0..2
+    model.install(R)
+    R.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
+    try:
+        R.set_option(hgs.HGS_OPT_INITIAL_CAPACITY, 1024)
+        outs = R.render()
+        torch.cuda.synchronize()
+        assert R.stats()["regrows"] >= 1
+    finally:
+        R.set_option(hgs.HGS_OPT_INITIAL_CAPACITY, 0)
+    kept_top = 0
+    rng = np.random.default_rng(3)
+    for v, cam in enumerate(views):
+        got = R.get_cut(v)
+        ids, _ = _oracle_learned_cut(scene, model, cam, got)
+        assert np.array_equal(got, ids), v
+        kept_top += int((got < top).sum())
+        _check_learned_view(scene, model, cam, got, [t.cpu().numpy() for t in outs[v]], rng, n_px=200)
+    print("cut nodes of levels 0..2 kept by the network:", kept_top, flush=True)
+
+
 @pytest.fixture(scope="module")
 def building():
     return W.building30m()
