@@ -116,7 +116,8 @@ __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap
     uint4 acc = make_uint4(0, 0, 0, 0);
     auto decide = [&](uint32_t i, bool valid, uint2 e, float4 b, int2 ch) {
         if (!valid) return;
-        const uint32_t d = node_decision(c.views[e.y], (int)e.x, b, ch.y, c.s_hi);
+        const uint32_t d =
+            on_view(c.views, e.y, [&](const ViewDev& V) { return node_decision(V, (int)e.x, b, ch.y, c.s_hi); });
         c.dec[i] = (uint8_t)d;
         const uint4 r = counts_of(c, d, ch.y);
         acc.x += r.x;
@@ -174,11 +175,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (valid) {
             i = s_q[threadIdx.x];
             e = c.in[i];
-            const ViewDev& V = c.views[e.y];
             const float4 b = c.bound[e.x];
-            NodeGeom g;
-            node_geometry(V, b, &g);
-            lod_features(m, V, (int)e.x, b, g, c.level, f);
+            on_view(c.views, e.y, [&](const ViewDev& V) {
+                NodeGeom g;
+                node_geometry(V, b, &g);
+                lod_features(m, V, (int)e.x, b, g, c.level, f);
+            });
 #pragma unroll
             for (int k = 0; k < kMlpIn; ++k) f[k] = (f[k] - m.mean[k]) * m.inv_std[k];
         }

@@ -51,6 +51,45 @@ struct ViewDev {
     float* alpha;
 };
 
+// Views do not change while a kernel runs.  When every active lane of a
+// wave works on the same view (the usual case: cut and frontier entries come
+// grouped by view), f gets a copy of that view read through the constant
+// address space at a wave-uniform index, so its fields arrive by scalar
+// loads instead of one vector gather per field; otherwise f gets the lane's
+// own view.  Either way f sees the same values.
+typedef const uint64_t __attribute__((address_space(4))) ConstWord;
+static_assert(sizeof(ViewDev) % 8 == 0, "views are copied in 8-byte words");
+
+// View v read through the constant address space (v wave-uniform: scalar
+// loads), word by word into a local copy.
+__device__ __forceinline__ ViewDev view_uniform(const ViewDev* views, uint32_t v) {
+    ConstWord* src = (ConstWord*)(views + v);
+    uint64_t w[sizeof(ViewDev) / 8];
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(ViewDev) / 8); ++k) w[k] = src[k];
+    ViewDev V;
+    __builtin_memcpy(&V, w, sizeof V);
+    return V;
+}
+
+template <class F>
+__device__ __forceinline__ auto on_view(const ViewDev* views, uint32_t v, F&& f) {
+    const uint32_t v0 = __builtin_amdgcn_readfirstlane(v);
+    if (__ballot(v != v0) == 0) {
+        const ViewDev V = view_uniform(views, v0);
+        return f(V);
+    }
+    return f(views[v]);
+}
+
+// A copy of view v (the lane's own), read by scalar loads when every active
+// lane of the wave asks for the same view.
+__device__ __forceinline__ ViewDev load_view(const ViewDev* views, uint32_t v) {
+    const uint32_t v0 = __builtin_amdgcn_readfirstlane(v);
+    if (__ballot(v != v0) == 0) return view_uniform(views, v0);
+    return views[v];
+}
+
 // Projected Gaussian, one per cut entry (48 bytes).  The conic is kept as
 // the factors of q = (p dx + r dy)^2 + (s dy)^2, which evaluates a sum of
 // squares instead of a cancelling quadratic form.

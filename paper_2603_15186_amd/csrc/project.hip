@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
     uint32_t vis = 0;
     for (uint32_t i = blockIdx.x * kNT + threadIdx.x; i < m; i += gridDim.x * kNT) {
         const uint2 e = a.cut[i];
-        const ViewDev& V = a.views[e.y];
+        const ViewDev V = load_view(a.views, e.y);
         const int64_t g = e.x;
         if (a.runs != nullptr && (i == 0 || a.cut[i - 1].y != e.y)) {
             // first entry of a run: its level is the last one begun at or before i
