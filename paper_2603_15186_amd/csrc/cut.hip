@@ -291,8 +291,16 @@ __global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G, uint32_t
     }
 }
 
+// Each thread takes kEmitPer consecutive entries of the chunk, so that one
+// workgroup scan places 1,024 entries.  The children an iteration appends
+// to the next frontier form one run; it is assembled in LDS (up to
+// kEmitStage entries, the rest stored directly) and written out coalesced.
+constexpr int kEmitPer = 4;
+constexpr uint32_t kEmitStage = 4096;
+
 __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap) {
     __shared__ uint4 sh[kNT / kWave + 1];
+    __shared__ uint2 s_out[kEmitStage];
     uint32_t n = *c.in_count;
     n = n < in_cap ? n : in_cap;
     uint32_t lo, hi;
@@ -301,30 +309,76 @@ __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap)
     uint4 off = c.tmp[blockIdx.x];
     const uint32_t base = c.tmp[gridDim.x].x;
     const uint32_t cbase = c.tmp[gridDim.x].z;
-    for (uint32_t s = lo; s < hi; s += kNT) {
-        const uint32_t i = s + threadIdx.x;
-        uint4 r = make_uint4(0, 0, 0, 0);
-        uint2 e = make_uint2(0, 0);
-        if (i < hi) {
-            e = c.in[i];
-            r = counts_of(c, c.dec[i], c.leaves ? 0 : c.child[e.x].y);
+    for (uint32_t s = lo; s < hi; s += kEmitPer * kNT) {
+        // chunks start at multiples of kNT, so i0 is a multiple of kEmitPer
+        const uint32_t i0 = s + kEmitPer * threadIdx.x;
+        uint2 e[kEmitPer];
+        uint32_t d[kEmitPer];
+        if (i0 + kEmitPer <= hi) {
+            const uint4 q0 = *reinterpret_cast<const uint4*>(c.in + i0);
+            const uint4 q1 = *reinterpret_cast<const uint4*>(c.in + i0 + 2);
+            e[0] = make_uint2(q0.x, q0.y);
+            e[1] = make_uint2(q0.z, q0.w);
+            e[2] = make_uint2(q1.x, q1.y);
+            e[3] = make_uint2(q1.z, q1.w);
+            const uint32_t dd = *reinterpret_cast<const uint32_t*>(c.dec + i0);
+#pragma unroll
+            for (int j = 0; j < kEmitPer; ++j) d[j] = (dd >> (8 * j)) & 0xffu;
+        } else {
+#pragma unroll
+            for (int j = 0; j < kEmitPer; ++j) {
+                const bool v = i0 + j < hi;
+                e[j] = v ? c.in[i0 + j] : make_uint2(0, 0);
+                d[j] = v ? c.dec[i0 + j] : (uint32_t)kDrop;
+            }
+        }
+        uint4 r[kEmitPer];
+        int first[kEmitPer];
+        uint4 mine = make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < kEmitPer; ++j) {
+            const bool expand = (d[j] & 3u) == kExpand;
+            const int2 ch = (expand && !c.leaves) ? c.child[e[j].x] : make_int2(0, 0);
+            first[j] = ch.x;
+            r[j] = counts_of(c, d[j], ch.y);
+            mine.x += r[j].x;
+            mine.y += r[j].y;
+            mine.z += r[j].z;
         }
         uint4 tot;
-        const uint4 ex = block_excl_scan4<kNT>(r, sh, &tot);
-        if (r.x) {
-            const uint64_t pos = (uint64_t)base + off.x + ex.x;
-            if (pos < c.cut_cap) c.cut[pos] = e;
-        }
-        if (r.z) {
-            const uint64_t pos = (uint64_t)cbase + off.z + ex.z;
-            if (pos < c.cand_cap) c.cand[pos] = e;
-        }
-        if (r.y) {
-            const int first = c.child[e.x].x;
-            for (uint32_t j = 0; j < r.y; ++j) {
-                const uint64_t pos = (uint64_t)off.y + ex.y + j;
-                if (pos < c.out_cap) c.out[pos] = make_uint2((uint32_t)(first + (int)j), e.y);
+        uint4 ex = block_excl_scan4<kNT>(mine, sh, &tot);
+#pragma unroll
+        for (int j = 0; j < kEmitPer; ++j) {
+            if (r[j].x) {
+                const uint64_t pos = (uint64_t)base + off.x + ex.x;
+                if (pos < c.cut_cap) c.cut[pos] = e[j];
             }
+            if (r[j].z) {
+                const uint64_t pos = (uint64_t)cbase + off.z + ex.z;
+                if (pos < c.cand_cap) c.cand[pos] = e[j];
+            }
+            for (uint32_t q = 0; q < r[j].y; ++q) {
+                const uint32_t L = ex.y + q;
+                const uint2 child = make_uint2((uint32_t)(first[j] + (int)q), e[j].y);
+                if (L < kEmitStage) {
+                    s_out[L] = child;
+                } else {
+                    const uint64_t pos = (uint64_t)off.y + L;
+                    if (pos < c.out_cap) c.out[pos] = child;
+                }
+            }
+            ex.x += r[j].x;
+            ex.y += r[j].y;
+            ex.z += r[j].z;
+        }
+        if (!c.leaves) {
+            __syncthreads();
+            const uint32_t staged = tot.y < kEmitStage ? tot.y : kEmitStage;
+            for (uint32_t q = threadIdx.x; q < staged; q += kNT) {
+                const uint64_t pos = (uint64_t)off.y + q;
+                if (pos < c.out_cap) c.out[pos] = s_out[q];
+            }
+            __syncthreads();
         }
         off.x += tot.x;
         off.y += tot.y;
