@@ -32,8 +32,8 @@ enum : uint32_t { kDrop = 0, kEmit = 1, kExpand = 2, kCandidate = 4 };
 // Decide a node for a view: dropped (sphere outside the frustum), emitted,
 // or expanded into its children.  kCandidate is or-ed into kExpand when the
 // threshold rule refines the node and its projected size is at most s_hi
-// pixels: the band in which the learned rule may keep the node instead (that
-// choice is made by k_level_mlp).
+// pixels: the band in which the learned rule may keep the node instead (the
+// count pass lets the network make that choice).
 __device__ __forceinline__ uint32_t node_decision(const ViewDev& V, int k, float4 b, int nchild, double s_hi) {
 #pragma clang fp contract(off)
     NodeGeom g;
@@ -70,7 +70,7 @@ struct LevelCtx {
     uint32_t cut_cap;
     uint4* tmp;               // [G] block counts, then offsets; [G] = level bases
     uint8_t* dec;             // per frontier entry: decision of the count pass
-    bool defer;               // learned cut: candidates are decided by k_level_mlp
+    bool defer;               // learned cut: the count pass lets the network settle candidates
     const float* w32;         // learned cut: FP32 weights (uniform: read through the scalar cache)
     Counters* ctr;
     int mode;
@@ -100,11 +100,17 @@ __device__ __forceinline__ uint4 counts_of(const LevelCtx& c, uint32_t d, int nc
 }
 
 // Count pass: decide every entry of the block's chunk once, remember the
-// decision for the emit pass, reduce the counts.  In the learned cut a
-// candidate is counted as refined; k_level_mlp may then turn it into an
-// emitted node and correct the block's counts.
+// decision for the emit pass, reduce the counts.  In the learned cut
+// (DEFER) the candidates of each 256 entries are settled right here: their
+// features are computed one lane per candidate and the matrix cores
+// evaluate the network over the group (64 entries per wave; the network's
+// work is negligible, so the group is not compacted).  The network keeps a
+// candidate (emits it) unless its probability reaches p*.
+template <bool DEFER>
 __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap) {
     __shared__ uint4 sh[kNT / kWave + 1];
+    __shared__ float s_x[DEFER ? kNT * kMlpXStride : 1];
+    __shared__ float s_w[DEFER ? kMlpParams : 1];  // the network's FP32 weights
     uint32_t n = *c.in_count;
     n = n < in_cap ? n : in_cap;
     uint32_t lo, hi;
@@ -113,11 +119,39 @@ __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap
         if (threadIdx.x == 0) c.tmp[blockIdx.x] = make_uint4(0, 0, 0, 0);
         return;
     }
+    if (DEFER)
+        for (int k = threadIdx.x; k < kMlpParams; k += kNT) s_w[k] = c.w32[k];
+    const int w = threadIdx.x / kWave;
     uint4 acc = make_uint4(0, 0, 0, 0);
-    auto decide = [&](uint32_t i, bool valid, uint2 e, float4 b, int2 ch) {
+    auto decide = [&](bool valid, uint2 e, float4 b, int2 ch) -> uint32_t {
+        if (!valid) return kDrop;
+        return on_view(c.views, e.y, [&](const ViewDev& V) { return node_decision(V, (int)e.x, b, ch.y, c.s_hi); });
+    };
+    // the network's say on the group's candidates (every thread takes part)
+    auto settle = [&](uint32_t d, uint2 e, float4 b) -> uint32_t {
+        const bool cand = (d & kCandidate) != 0;
+        if (!__syncthreads_or(cand)) return d;     // also orders s_x's reuse and publishes s_w
+        const LodMlpDev& m = *(const LodMlpDev*)c.mlp;
+        float f[kMlpIn];
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k) f[k] = 0.f;
+        if (cand) {
+            on_view(c.views, e.y, [&](const ViewDev& V) {
+                NodeGeom g;
+                node_geometry(V, b, &g);
+                lod_features(m, V, (int)e.x, b, g, c.level, f);
+            });
+#pragma unroll
+            for (int k = 0; k < kMlpIn; ++k) f[k] = (f[k] - m.mean[k]) * m.inv_std[k];
+        }
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k) s_x[threadIdx.x * kMlpXStride + k] = f[k];
+        __syncthreads();
+        const float z = lod_mlp_logit_mfma(s_w, s_x + w * kWave * kMlpXStride);
+        return (cand && !(1.f / (1.f + __expf(-z)) >= m.p_star)) ? (uint32_t)kEmit : d;
+    };
+    auto count = [&](uint32_t i, bool valid, uint32_t d, int2 ch) {
         if (!valid) return;
-        const uint32_t d =
-            on_view(c.views, e.y, [&](const ViewDev& V) { return node_decision(V, (int)e.x, b, ch.y, c.s_hi); });
         c.dec[i] = (uint8_t)d;
         const uint4 r = counts_of(c, d, ch.y);
         acc.x += r.x;
@@ -133,107 +167,18 @@ __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap
         const float4 b0 = c.bound[e0.x], b1 = c.bound[e1.x];
         const int2 ch0 = c.leaves ? make_int2(0, 0) : c.child[e0.x];
         const int2 ch1 = c.leaves ? make_int2(0, 0) : c.child[e1.x];
-        decide(i0, v0, e0, b0, ch0);
-        decide(i1, v1, e1, b1, ch1);
+        uint32_t d0 = decide(v0, e0, b0, ch0);
+        uint32_t d1 = decide(v1, e1, b1, ch1);
+        if (DEFER) {
+            d0 = settle(d0, e0, b0);
+            d1 = settle(d1, e1, b1);
+        }
+        count(i0, v0, d0, ch0);
+        count(i1, v1, d1, ch1);
     }
     uint4 tot;
     block_excl_scan4<kNT>(acc, sh, &tot);
     if (threadIdx.x == 0) c.tmp[blockIdx.x] = tot;
-}
-
-// Learned-cut candidates of one level.  Block b takes the count pass's
-// chunk b, gathers its candidates (decision bit kCandidate) into an LDS
-// queue in order and evaluates them 256 at a time: one lane per candidate
-// for the features, the matrix cores for the network (64 candidates per
-// wave).  The network keeps a node (emits it) unless its probability
-// reaches p*; the block's counts lose each kept node's children and gain
-// one emitted entry.
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) void k_level_mlp(LevelCtx c, uint32_t in_cap) {
-    __shared__ uint32_t s_q[2 * kNT];
-    __shared__ uint32_t s_wc[kNW + 1];
-    __shared__ uint32_t s_n;
-    __shared__ uint2 s_fix[kNW];
-    __shared__ float s_x[kNT * kMlpXStride];
-    __shared__ float s_w[kMlpParams];              // the network's FP32 weights
-    uint32_t n = *c.in_count;
-    n = n < in_cap ? n : in_cap;
-    uint32_t lo, hi;
-    chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
-    if (lo >= hi) return;
-    for (int k = threadIdx.x; k < kMlpParams; k += kNT) s_w[k] = c.w32[k];
-    const LodMlpDev& m = *(const LodMlpDev*)c.mlp;
-    const int w = threadIdx.x / kWave;
-    if (threadIdx.x == 0) s_n = 0;
-    uint32_t kept_n = 0, lost = 0;
-    auto evaluate = [&](uint32_t cnt) {
-        const bool valid = threadIdx.x < cnt;
-        uint32_t i = 0;
-        uint2 e = make_uint2(0, 0);
-        float f[kMlpIn];
-#pragma unroll
-        for (int k = 0; k < kMlpIn; ++k) f[k] = 0.f;
-        if (valid) {
-            i = s_q[threadIdx.x];
-            e = c.in[i];
-            const float4 b = c.bound[e.x];
-            on_view(c.views, e.y, [&](const ViewDev& V) {
-                NodeGeom g;
-                node_geometry(V, b, &g);
-                lod_features(m, V, (int)e.x, b, g, c.level, f);
-            });
-#pragma unroll
-            for (int k = 0; k < kMlpIn; ++k) f[k] = (f[k] - m.mean[k]) * m.inv_std[k];
-        }
-#pragma unroll
-        for (int k = 0; k < kMlpIn; ++k) s_x[threadIdx.x * kMlpXStride + k] = f[k];
-        __syncthreads();
-        const float z = lod_mlp_logit_mfma(s_w, s_x + w * kWave * kMlpXStride);
-        __syncthreads();                            // s_x is refilled by the next call
-        if (valid && !(1.f / (1.f + __expf(-z)) >= m.p_star)) {
-            c.dec[i] = (uint8_t)kEmit;
-            ++kept_n;
-            lost += (uint32_t)c.child[e.x].y;
-        }
-    };
-    for (uint32_t s = lo; s < hi; s += kNT) {
-        const uint32_t i = s + threadIdx.x;
-        const bool cand = i < hi && (c.dec[i] & kCandidate);
-        const uint64_t bal = __ballot(cand);
-        if (lane_id() == 0) s_wc[w] = (uint32_t)__popcll(bal);
-        __syncthreads();
-        uint32_t base = s_n;
-        for (int q = 0; q < w; ++q) base += s_wc[q];
-        if (cand) s_q[base + (uint32_t)__popcll(bal & lanemask_lt())] = i;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = s_n;
-            for (int q = 0; q < kNW; ++q) t += s_wc[q];
-            s_n = t;
-        }
-        __syncthreads();
-        const uint32_t qn = s_n;
-        if (qn >= (uint32_t)kNT) {
-            evaluate(kNT);
-            __syncthreads();
-            if (threadIdx.x < qn - kNT) s_q[threadIdx.x] = s_q[kNT + threadIdx.x];
-            if (threadIdx.x == 0) s_n = qn - kNT;
-            __syncthreads();
-        }
-    }
-    evaluate(s_n);
-    // this block's corrections (the count pass wrote tmp[b])
-    const uint32_t kx = wave_sum(kept_n), ky = wave_sum(lost);
-    if (lane_id() == 0) s_fix[w] = make_uint2(kx, ky);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint2 t = make_uint2(0, 0);
-        for (int q = 0; q < kNW; ++q) {
-            t.x += s_fix[q].x;
-            t.y += s_fix[q].y;
-        }
-        c.tmp[blockIdx.x].x += t.x;
-        c.tmp[blockIdx.x].y -= t.y;
-    }
 }
 
 // Exclusive scan of the G <= 4 * 1024 block counts (four consecutive ones
@@ -498,9 +443,11 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         // entries' order, so the cut does not depend on the grid)
         const uint64_t bound = (uint64_t)(a.level_offset_host[L + 1] - a.level_offset_host[L]) * (uint64_t)a.n_views;
         const int GL = (int)std::min<uint64_t>((uint64_t)G, std::max<uint64_t>(1, (bound + kNT - 1) / kNT));
-        k_level_count<<<GL, kNT, 0, s>>>(c, a.frontier_cap);
         // a leaf is never refined, so the last level has no candidates
-        if (c.defer && !c.leaves) k_level_mlp<<<GL, kNT, 0, s>>>(c, a.frontier_cap);
+        if (c.defer && !c.leaves)
+            k_level_count<true><<<GL, kNT, 0, s>>>(c, a.frontier_cap);
+        else
+            k_level_count<false><<<GL, kNT, 0, s>>>(c, a.frontier_cap);
         k_level_scan<<<1, 1024, 0, s>>>(c, GL, a.frontier_cap);
         k_level_emit<<<GL, kNT, 0, s>>>(c, a.frontier_cap);
         cur ^= 1;
