@@ -85,6 +85,8 @@ struct hgs_ctx {
     int64_t regrows = 0;
     uint32_t forced_cap = 0;          // test hook: start from this capacity
     int sort_digit_bits = 8;          // widest radix digit
+    double mean_lo[3] = {0, 0, 0}, mean_hi[3] = {0, 0, 0};   // bounding box of every node's mean
+    bool depth_full = false;          // a depth fell outside its bound: sort all 32 key bits from then on
     // captured render (HGS_OPT_USE_GRAPH): recorded on cap_stream, replayed
     // on the caller's stream while nothing it depends on has changed
     hipStream_t cap_stream = nullptr;
@@ -433,6 +435,36 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pa.views = ca.views;
     pa.proj = P<Proj>(W.proj);
     pa.depth_key = P<uint32_t>(W.dkey[0]);
+    // Binned depths lie in (znear, distance to the farthest corner of the
+    // means' bounding box] of their view, so the sort needs only the bits
+    // that span that range of FP32 bit patterns (a depth outside raises
+    // kOvDepth and the batch is redone with all 32 bits).
+    int depth_bits = 32;
+    pa.depth_base = 0;
+    pa.depth_top = 0xffffffffu;
+    if (!c->depth_full) {
+        float zn = 0.f;
+        double dmax = 0.0;
+        for (int v = v0; v < v1; ++v) {
+            const ViewDev& d = c->views_host[v];
+            zn = v == v0 ? (float)d.znear : std::min(zn, (float)d.znear);
+            double far2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double e = std::max(std::fabs(c->mean_lo[k] - d.o[k]), std::fabs(c->mean_hi[k] - d.o[k]));
+                far2 += e * e;
+            }
+            dmax = std::max(dmax, std::sqrt(far2));
+        }
+        const float top = (float)(dmax * (1.0 + 1e-6) + 1e-6);
+        uint32_t bb, tb;
+        std::memcpy(&bb, &zn, 4);
+        std::memcpy(&tb, &top, 4);
+        if (zn > 0.f && tb > bb) {
+            pa.depth_base = bb;
+            pa.depth_top = tb;
+            depth_bits = bits_for(tb - bb + 1u);
+        }
+    }
     pa.depth_val = P<uint32_t>(W.dval[0]);
     pa.ntiles = P<uint32_t>(W.ntiles);
     pa.bins = P<BinRec>(W.bins);
@@ -463,7 +495,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     sa.vals[1] = P<uint32_t>(W.dval[1]);
     sa.count = &ctr->cut;
     sa.cap = c->cut_cap;
-    sa.key_bits = 32;
+    sa.key_bits = depth_bits;
     sa.max_digit_bits = c->sort_digit_bits;
     sa.hist = P<uint32_t>(W.hist);
     int dr = launch_sort(sa, s);
@@ -594,6 +626,10 @@ hgs_status grow_from(hgs_ctx* c, const Counters& k) {
     if (k.overflow & kOvFrontier) c->frontier_cap = grow(c->frontier_cap, k.need_frontier, kPairLimit);
     if (k.overflow & kOvCut) c->cut_cap = grow(c->cut_cap, k.need_cut, kEntryLimit);
     if (k.overflow & kOvPairs) c->pair_cap = grow(c->pair_cap, k.need_pairs, kPairLimit);
+    if (k.overflow & kOvDepth) {
+        c->depth_full = true;
+        invalidate_graph(c);
+    }
     // a cut overflow leaves the pair count unknown; keep pairs proportional
     if (k.overflow & kOvCut)
         c->pair_cap = std::max(c->pair_cap, clamp_cap(std::min<uint64_t>(8ull * c->cut_cap, kPairLimit), kPairLimit));
@@ -801,6 +837,13 @@ hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarch
         geo[3 * i + 2] = make_float4(g->scales[3 * i], g->scales[3 * i + 1], g->scales[3 * i + 2], 0.f);
     }
     std::vector<float> sh(g->sh, g->sh + (size_t)n * K * 3);
+    double mlo[3] = {0, 0, 0}, mhi[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            const double x = g->means[3 * i + k];
+            mlo[k] = i == 0 ? x : std::min(mlo[k], x);
+            mhi[k] = i == 0 ? x : std::max(mhi[k], x);
+        }
     // new buffers first, so a failure leaves the old scene intact
     DevMem ngeo, nsh, nbound, nchild, nleaf, nparent, nfeat, nlvl;
     auto cleanup = [&]() {
@@ -890,6 +933,11 @@ hgs_status hgs_load_scene(hgs_ctx* c, const hgs_gaussians* g, const hgs_hierarch
     c->level_offset = lo;
     c->n_levels = h ? h->n_levels : 0;
     c->n_leaves = n_leaves;
+    for (int k = 0; k < 3; ++k) {
+        c->mean_lo[k] = mlo[k];
+        c->mean_hi[k] = mhi[k];
+    }
+    c->depth_full = false;
     c->loaded = true;
     c->mlp_loaded = false;
     c->last_valid = false;

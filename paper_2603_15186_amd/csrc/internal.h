@@ -30,6 +30,7 @@ constexpr uint32_t kOvFrontier = 1u;
 constexpr uint32_t kOvCut = 2u;
 constexpr uint32_t kOvPairs = 4u;
 constexpr uint32_t kOvCand = 8u;
+constexpr uint32_t kOvDepth = 16u;        // a depth key outside the range the pass's key width assumed
 
 // Per-view parameters, resident in device memory.  FP64 copies of the
 // extrinsics and intrinsics feed the cut and the projection; the compositor
@@ -208,7 +209,10 @@ struct ProjectArgs {
     int sh_degree;
     const ViewDev* views;
     Proj* proj;
+    // depth keys: the FP32 depth's bits minus depth_base; binned depths lie
+    // in [depth_base, depth_top] (bit patterns), else kOvDepth is raised
     uint32_t* depth_key;
+    uint32_t depth_base, depth_top;
     uint32_t* depth_val;
     uint32_t* ntiles;
     BinRec* bins;

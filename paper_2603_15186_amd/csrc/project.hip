@@ -363,8 +363,15 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
         br.height = (uint16_t)V.height;
         a.bins[i] = br;
         a.ntiles[i] = ntiles;
-        // positive depths order as their bit patterns; unbinned entries last
-        a.depth_key[i] = ntiles > 0 ? __float_as_uint(zf) : 0xffffffffu;
+        // positive depths order as their bit patterns, and so do their
+        // offsets from depth_base; unbinned entries last
+        uint32_t dk = 0xffffffffu;
+        if (ntiles > 0) {
+            const uint32_t bits = __float_as_uint(zf);
+            if (bits < a.depth_base || bits > a.depth_top) atomicOr(&a.ctr->overflow, kOvDepth);
+            dk = bits - a.depth_base;
+        }
+        a.depth_key[i] = dk;
         a.depth_val[i] = i | (min(ntiles, kNtSat) << kNtShift);
         vis += ntiles > 0 ? 1u : 0u;
     }
