@@ -173,6 +173,21 @@ def test_capacity_regrow_gives_identical_image(R, box):
         assert np.array_equal(a, b)
 
 
+def test_depths_outside_the_key_range_fall_back_to_full_keys(R, box):
+    """The depth sort's key width comes from each batch's depth range (the
+    views' znear to the far corner of the means' bounding box), which holds
+    for rotation matrices.  A camera matrix scaled by 3 (accepted: only its
+    finiteness is checked) triples every depth and leaves that range: the
+    render reports it, is redone with full 32-bit depth keys, and matches
+    the oracle on the full frame."""
+    import dataclasses
+    scene, cams = box
+    cam = dataclasses.replace(cams[0], R=(np.asarray(cams[0].R, np.float32) * 3).astype(np.float32))
+    img = _render(R, scene, [cam])[0]
+    assert R.stats()["regrows"] >= 1
+    _check_full(img, scene, cam)
+
+
 def test_capacity_error_without_regrow(R, box):
     scene, cams = box
     hgs = _hgs()
