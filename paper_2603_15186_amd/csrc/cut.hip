@@ -4,12 +4,15 @@
 // once (NavGSim Sec. III-B: LOD rendering selects Gaussians from different
 // levels of the tree).  The frontier holds (node, view) entries of one level
 // in (view, node) order.  Per level:
-//   count : each block evaluates its contiguous chunk and reduces
-//           (emitted, children) counts;
+//   count : each block decides its contiguous chunk (in the learned cut the
+//           network settles the candidates right there), stores the
+//           decisions and reduces (emitted, children) counts;
 //   scan  : one block scans the per-block counts, advances the cut size and
 //           sets the next frontier size (capacity checks here);
-//   emit  : each block re-evaluates its chunk (deterministic), scans within
-//           the block and writes emitted ids and child ids in order.
+//   emit  : each block reads its chunk's decisions back, scans within the
+//           block and writes emitted ids and child ids in order.
+// A level's grid is sized to its frontier's bound (nodes of the level times
+// views), at most kCutBlocks workgroups.
 // Ids come out ascending per view because ids are level-major and children
 // of a node are contiguous and ordered like their parents.
 //
