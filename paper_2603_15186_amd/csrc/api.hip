@@ -477,10 +477,16 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pa.tile_w = c->ropts.tile_w;
     pa.tile_h = c->ropts.tile_h;
     pa.key_shift = key_shift;
-    // views of the depth-sorted entries come from the table of the cut's runs
+    // When the view fits above the depth bits, one sort on (view, depth)
+    // gives the view-grouped depth order; otherwise a stable pass on the
+    // entries' views follows the depth sort, the views of the depth-sorted
+    // entries coming from the table of the cut's runs.
+    const int view_bits = ca.n_views > 1 ? bits_for((uint32_t)ca.n_views) : 0;
+    const bool view_in_key = ca.n_views > 1 && depth_bits + view_bits <= 32;
+    pa.view_shift = view_in_key ? depth_bits : 0;
     const int cut_levels = (ca.flat || ca.mode == HGS_LOD_ALL_LEAVES) ? 1 : ca.n_levels;
     const int n_slots = cut_levels * ca.n_views;
-    const bool use_runs = ca.n_views > 1 && n_slots <= kMaxRunSlots;
+    const bool use_runs = ca.n_views > 1 && !view_in_key && n_slots <= kMaxRunSlots;
     pa.runs = use_runs ? P<uint32_t>(W.runs) : nullptr;
     pa.n_cut_levels = cut_levels;
     pa.n_views = ca.n_views;
@@ -495,11 +501,11 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     sa.vals[1] = P<uint32_t>(W.dval[1]);
     sa.count = &ctr->cut;
     sa.cap = c->cut_cap;
-    sa.key_bits = depth_bits;
+    sa.key_bits = view_in_key ? depth_bits + view_bits : depth_bits;
     sa.max_digit_bits = c->sort_digit_bits;
     sa.hist = P<uint32_t>(W.hist);
     int dr = launch_sort(sa, s);
-    if (ca.n_views > 1) {
+    if (ca.n_views > 1 && !view_in_key) {
         // stable pass on the entries' views: depth order within each view
         launch_view_keys(sa.vals[dr], ca.cut, pa.runs, n_slots, ca.n_views, &ctr->cut, c->cut_cap, sa.keys[dr], s);
         SortArgs sv = sa;

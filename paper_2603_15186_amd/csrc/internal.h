@@ -213,6 +213,7 @@ struct ProjectArgs {
     // in [depth_base, depth_top] (bit patterns), else kOvDepth is raised
     uint32_t* depth_key;
     uint32_t depth_base, depth_top;
+    int view_shift;                  // > 0: the key also holds the entry's view << view_shift
     uint32_t* depth_val;
     uint32_t* ntiles;
     BinRec* bins;

@@ -370,6 +370,7 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
             const uint32_t bits = __float_as_uint(zf);
             if (bits < a.depth_base || bits > a.depth_top) atomicOr(&a.ctr->overflow, kOvDepth);
             dk = bits - a.depth_base;
+            if (a.view_shift > 0) dk |= e.y << a.view_shift;
         }
         a.depth_key[i] = dk;
         a.depth_val[i] = i | (min(ntiles, kNtSat) << kNtShift);
