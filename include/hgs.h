@@ -231,8 +231,12 @@ hgs_status hgs_set_option(hgs_ctx* ctx, int32_t option, int64_t value);
 hgs_status hgs_render(hgs_ctx* ctx, void* stream, const hgs_output* outs);
 
 /* After an asynchronous render and a stream synchronisation: HGS_OK, or
- * HGS_E_CAPACITY if a work buffer overflowed (outputs are then invalid;
- * capacities have been grown for the next render). */
+ * HGS_E_CAPACITY if a work buffer overflowed, or a depth fell outside the
+ * range the batch's depth keys were sized for (a camera matrix that is not
+ * a rotation can do that): outputs are then invalid, and capacities have
+ * been grown, or full-width depth keys chosen, for the next render.  With
+ * HGS_OPT_SYNC_CHECK and HGS_OPT_AUTO_REGROW on, hgs_render does this
+ * itself and renders again. */
 hgs_status hgs_check(hgs_ctx* ctx);
 
 /* Ascending node ids of view `view`'s cut from the last render.  Writes
