@@ -58,6 +58,16 @@ struct BwdShared {
     uint32_t maxlast;
 };
 
+// Q of a staged entry at pixel centre (fx, fy) by the compositor's own
+// operations (its factors scaled by kS as the compositor stages them,
+// -log2(o) folded into the row term), so that alpha and the stop decisions
+// here are the forward pass's bit for bit.
+__device__ __forceinline__ float compositor_q(const StageA& A, const StageB& B, float fx, float fy) {
+    const float t1 = fmaf(kS * A.p, fx, fmaf(kS * A.r, fy, kS * A.c1));
+    const float t2 = fmaf(kS * A.s, fy, kS * B.c2);
+    return fmaf(t1, t1, fmaf(t2, t2, -B.lo));
+}
+
 // Stage entries [base, base + cnt) of the tile's list and build each 4x4
 // block's list of staged offsets (16 B units, depth order), padded with the
 // empty record up to a multiple of four of its wave's longest list.
@@ -178,13 +188,10 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(8))) void k
             const uint32_t off = list[p];
             const StageA A = *reinterpret_cast<const StageA*>(reinterpret_cast<const char*>(S.a) + off);
             const StageB B = *reinterpret_cast<const StageB*>(reinterpret_cast<const char*>(S.b) + off);
-            const float t1 = fmaf(A.p, fx, fmaf(A.r, fy, A.c1));
-            const float t2 = fmaf(A.s, fy, B.c2);
-            const float q = fmaf(t1, t1, t2 * t2);
-            const float x = fmaf(q, kNegHalfLog2e, B.lo);
-            const float al = fminf(0.99f, __builtin_amdgcn_exp2f(x));
+            const float Q = compositor_q(A, B, fx, fy);
+            const float al = fminf(0.99f, __builtin_amdgcn_exp2f(-Q));
             const float Tn = T - al * T;
-            const bool add = live && x >= entry_xmin(B.lo);
+            const bool add = live && Q <= entry_qmax(-B.lo);
             if (add && Tn < 1e-4f) {
                 live = false;
                 last = b0 + off / 16;
@@ -234,10 +241,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(8))) void k
                 const StageC C = S.c[j];
                 const float t1 = fmaf(A.p, fx, fmaf(A.r, fy, A.c1));
                 const float t2 = fmaf(A.s, fy, B.c2);
-                const float q = fmaf(t1, t1, t2 * t2);
-                const float x = fmaf(q, kNegHalfLog2e, B.lo);
-                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(x));
-                const float al = x >= entry_xmin(B.lo) ? al0 : 0.f;
+                const float Q = compositor_q(A, B, fx, fy);
+                const float al0 = fminf(0.99f, __builtin_amdgcn_exp2f(-Q));
+                const float al = Q <= entry_qmax(-B.lo) ? al0 : 0.f;
                 if (al > 0.f) {
                     has = true;
                     const float iom = __builtin_amdgcn_rcpf(1.f - al);

@@ -15,16 +15,17 @@ constexpr int kBlocks = 16;                 // 4x4-pixel blocks per tile
 constexpr float kQMax = 9.f;
 constexpr float kQMask = 9.f * 1.001f;      // bound used to mark blocks
 
-constexpr float kLog2AlphaMin = -7.99435343685885793f;   // log2(1/255)
-constexpr float kNegHalfLog2e = -0.72134752044448170f;   // exp(-q/2) = 2^(q * kNegHalfLog2e)
+// alpha = min(0.99, o e^(-q/2)) = min(0.99, 2^-Q) with
+// Q = (kS t1)^2 + (kS t2)^2 - log2(o), kS = sqrt(log2(e) / 2): the conic
+// factors are scaled by kS when an entry is staged and -log2(o) is folded
+// into a thread's row term, so a pixel needs two FMAs for Q.  An entry adds
+// to a pixel only where Q <= entry_qmax: q <= 9 and alpha >= 1/255.
+constexpr float kS = 0.84932180028801904f;              // sqrt(log2(e) / 2)
+constexpr float kS2 = kS * kS;
+constexpr float kQCap = 7.99435343685885793f;           // -log2(1/255)
 
-// The exponent x = log2(o) - q log2(e) / 2 of alpha = o e^(-q/2) at which
-// an entry stops counting: it adds to a pixel only where x >= xmin, i.e. q
-// <= 9 and alpha >= 1/255 (x is non-increasing in q, so q <= 9 is x at
-// least its value at q = 9, up to the rounding of one FMA).
-__device__ __forceinline__ float entry_xmin(float lo) {
-    return fmaxf(kLog2AlphaMin, fmaf(kQMax, kNegHalfLog2e, lo));
-}
+// The bound on Q of an entry with nlo = -log2(opacity).
+__device__ __forceinline__ float entry_qmax(float nlo) { return fminf(kQCap, fmaf(kQMax, kS2, nlo)); }
 
 // One staged Gaussian: t1 = p x + r y + c1, t2 = s y + c2 over tile-relative
 // pixel centres (x, y); lo = log2(opacity).

@@ -17,8 +17,10 @@
 //       q = t1^2 + t2^2 with t1 = p dx + r dy = p x + (r y + c1) and
 //           t2 = s dy = s y + c2 (the bracket and t2 are shared by the
 //           pixels of a thread, which lie on one row);
-//       x = log2(o) - q log2(e)/2, alpha = min(0.99, 2^x) = min(0.99, o e^(-q/2));
-//       the entry adds only to a live pixel with x >= xmin (q <= 9 and
+//       Q = q log2(e)/2 - log2(o), alpha = min(0.99, 2^-Q) = min(0.99,
+//       o e^(-q/2)), the factors scaled by sqrt(log2(e)/2) when staged and
+//       -log2(o) folded into the shared row term (two FMAs per pixel);
+//       the entry adds only to a live pixel with Q <= Qmax (q <= 9 and
 //       alpha >= 1/255, the cap 0.99 lying above 1/255);
 //       T' = T - alpha T; if T' < 1e-4 the pixel stops without adding,
 //       else C += c alpha T, D += z alpha T, T = T'.
@@ -63,10 +65,10 @@ struct Shape {
 };
 
 // Staged entry, per cell: t1 = p x + r y + c1, t2 = s y + c2 over pixel
-// centres relative to the cell's grid corner; lo = log2(opacity); xmin as in
-// entry_xmin.  Shared: the colour.
+// centres relative to the cell's grid corner, all five factors scaled by kS;
+// nlo = -log2(opacity); qmax = entry_qmax(nlo).  Shared: the colour.
 struct alignas(16) RecA { float p, r, c1, s; };
-struct alignas(16) RecB { float c2, lo, xmin, z; };
+struct alignas(16) RecB { float c2, nlo, qmax, z; };
 struct alignas(16) RecC { float col0, col1, col2; };
 
 template <int TW, int TH, int PX, int BATCH>
@@ -166,17 +168,16 @@ __device__ __forceinline__ void walk(Shared<TW, TH, PX, BATCH>& sh, const uint16
             // shared by the thread's pixels (one row)
             const float ry = fmaf(A.r, fy, A.c1);
             const float t2 = fmaf(A.s, fy, B.c2);
-            const float t22 = t2 * t2;
+            const float t22 = fmaf(t2, t2, B.nlo);
 #pragma unroll
             for (int j = 0; j < PX; ++j) {
                 const float t1 = fmaf(A.p, fx[j], ry);
-                const float q = fmaf(t1, t1, t22);
-                const float x = fmaf(q, kNegHalfLog2e, B.lo);
-                const float al = fminf(0.99f, __builtin_amdgcn_exp2f(x));
-                if (COUNT) nalg += (live[j] && q <= kQMax && i + u < n_mine) ? 1u : 0u;
+                const float Q = fmaf(t1, t1, t22);
+                const float al = fminf(0.99f, __builtin_amdgcn_exp2f(-Q));
+                if (COUNT) nalg += (live[j] && Q <= fmaf(kQMax, kS2, B.nlo) && i + u < n_mine) ? 1u : 0u;
                 const float w0 = al * T[j];
                 const float Tn = T[j] - w0;
-                const bool add = live[j] && x >= B.xmin;
+                const bool add = live[j] && Q <= B.qmax;
                 const bool keep = Tn >= 1e-4f;
                 const bool take = add && keep;
                 const float wgt = take ? w0 : 0.f;
@@ -238,7 +239,7 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
 #pragma unroll
         for (int c = 0; c < S::NC; ++c) {
             sh.a[c][BATCH] = RecA{0.f, 0.f, 0.f, 0.f};
-            sh.b[c][BATCH] = RecB{0.f, -__builtin_inff(), __builtin_inff(), 0.f};
+            sh.b[c][BATCH] = RecB{0.f, __builtin_inff(), -__builtin_inff(), 0.f};
         }
         sh.c[BATCH] = RecC{0.f, 0.f, 0.f};
     }
@@ -250,13 +251,14 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
         if (j < (int)cnt) {
             const uint32_t e = a.vals[base + j];
             const Proj P = a.proj[e < a.cut_cap ? e : 0u];
-            const float lo = __log2f(P.opacity);
-            const float xmin = entry_xmin(lo);
+            const float nlo = -__log2f(P.opacity);
+            const float qmax = entry_qmax(nlo);
 #pragma unroll
             for (int c = 0; c < S::NC; ++c) {
                 const float u = (float)(P.u - (double)(gx0 + 16 * c)), v = (float)(P.v - (double)gy0);
-                sh.a[c][j] = RecA{P.p, P.r, -fmaf(P.p, u, P.r * v), P.s};
-                sh.b[c][j] = RecB{-P.s * v, lo, xmin, P.z};
+                const float c1 = -fmaf(P.p, u, P.r * v), c2 = -P.s * v;
+                sh.a[c][j] = RecA{kS * P.p, kS * P.r, kS * c1, kS * P.s};
+                sh.b[c][j] = RecB{kS * c2, nlo, qmax, P.z};
             }
             sh.c[j] = RecC{P.c0, P.c1, P.c2};
             m = block_mask_tile<TW, TH>((float)(P.u - (double)x0), (float)(P.v - (double)y0), P.p, P.r, P.s);
