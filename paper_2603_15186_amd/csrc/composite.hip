@@ -349,13 +349,26 @@ __device__ __forceinline__ void composite_tile(const CompositeArgs& a, uint32_t 
     }
 }
 
+// Workgroups go to the eight XCDs in turn, each XCD with its own L2, while
+// neighbouring tiles of a view stage many of the same records.  Within each
+// full window of kXcdWindow consecutive workgroups, XCD x takes a contiguous
+// eighth of the window's tiles; a partial last window keeps the identity.
+// A bijection on [0, n).
+constexpr uint32_t kXcdWindow = 2048;
+static_assert(kXcdWindow % 8 == 0, "eight equal shares per window");
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+    const uint32_t r = b % kXcdWindow, w0 = b - r;
+    if (n - w0 < kXcdWindow) return b;
+    return w0 + (r % 8) * (kXcdWindow / 8) + r / 8;
+}
+
 // Register budget for as many waves per SIMD as the LDS allows: the staging
 // gathers need that many to hide.
 template <int TW, int TH, int PX, int BATCH, bool COUNT, bool KEEP>
 __global__ __launch_bounds__(TW * TH / PX) __attribute__((
     amdgpu_waves_per_eu(waves_per_simd<TW, TH, PX, BATCH>()))) void k_composite(CompositeArgs a) {
     __shared__ Shared<TW, TH, PX, BATCH> sh;
-    composite_tile<TW, TH, PX, BATCH, COUNT, KEEP>(a, blockIdx.x, sh);
+    composite_tile<TW, TH, PX, BATCH, COUNT, KEEP>(a, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
 
 // Persistent variant (default shape): a fixed grid takes tiles from a global
