@@ -28,7 +28,7 @@ struct DevMem {
 // alternate between two sets on two streams, so one pass's compositing
 // overlaps the next pass's cut, projection and binning.
 struct Work {
-    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, bins, offsets, dec, runs;
+    DevMem frontier[2], cut, proj, dkey[2], dval[2], ntiles, bins, offsets, dec;
     DevMem pkey[2], pval[2], scan_tmp, hist;
 };
 
@@ -222,7 +222,6 @@ hgs_status alloc_work(hgs_ctx* c) {
         if ((s = ensure(c, w.offsets, M * 4))) return s;
         if ((s = ensure(c, w.scan_tmp, (std::max(kScanBlocks, kCutBlocks) + 1) * sizeof(uint4)))) return s;
         if ((s = ensure(c, w.hist, kSortHistBytes))) return s;
-        if ((s = ensure(c, w.runs, kMaxRunSlots * sizeof(uint32_t)))) return s;
     }
     return HGS_OK;
 }
@@ -233,7 +232,7 @@ int lane_of(const hgs_ctx* c, int g) { return c->lanes > 1 ? g % c->lanes : 0; }
 void release_work(Work& w) {
     DevMem* all[] = {&w.frontier[0], &w.frontier[1], &w.cut, &w.proj, &w.dkey[0], &w.dkey[1], &w.dval[0],
                      &w.dval[1], &w.ntiles, &w.bins, &w.offsets, &w.dec, &w.pkey[0], &w.pkey[1], &w.pval[0],
-                     &w.pval[1], &w.scan_tmp, &w.hist, &w.runs};
+                     &w.pval[1], &w.scan_tmp, &w.hist};
     for (DevMem* m : all) release(*m);
 }
 
@@ -415,6 +414,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     ca.s_hi = c->s_hi;
     ca.cand = nullptr;
     ca.cand_cap = 0;
+    ca.group_children = !c->ropts.lod_blend;
     launch_cut(ca, s);
     mark(c, 1, s);
 
@@ -479,18 +479,10 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pa.key_shift = key_shift;
     // When the view fits above the depth bits, one sort on (view, depth)
     // gives the view-grouped depth order; otherwise a stable pass on the
-    // entries' views follows the depth sort, the views of the depth-sorted
-    // entries coming from the table of the cut's runs.
+    // entries' views (read from the cut) follows the depth sort.
     const int view_bits = ca.n_views > 1 ? bits_for((uint32_t)ca.n_views) : 0;
     const bool view_in_key = ca.n_views > 1 && depth_bits + view_bits <= 32;
     pa.view_shift = view_in_key ? depth_bits : 0;
-    const int cut_levels = (ca.flat || ca.mode == HGS_LOD_ALL_LEAVES) ? 1 : ca.n_levels;
-    const int n_slots = cut_levels * ca.n_views;
-    const bool use_runs = ca.n_views > 1 && !view_in_key && n_slots <= kMaxRunSlots;
-    pa.runs = use_runs ? P<uint32_t>(W.runs) : nullptr;
-    pa.n_cut_levels = cut_levels;
-    pa.n_views = ca.n_views;
-    if (use_runs) launch_runs_reset(pa.runs, n_slots, s);
     launch_project(pa, s);
     mark(c, 2, s);
 
@@ -507,7 +499,7 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     int dr = launch_sort(sa, s);
     if (ca.n_views > 1 && !view_in_key) {
         // stable pass on the entries' views: depth order within each view
-        launch_view_keys(sa.vals[dr], ca.cut, pa.runs, n_slots, ca.n_views, &ctr->cut, c->cut_cap, sa.keys[dr], s);
+        launch_view_keys(sa.vals[dr], ca.cut, &ctr->cut, c->cut_cap, sa.keys[dr], s);
         SortArgs sv = sa;
         sv.keys[0] = sa.keys[dr];
         sv.keys[1] = sa.keys[dr ^ 1];

@@ -2,8 +2,8 @@
 //
 // Top-down, level-synchronous traversal of the hierarchy for all views at
 // once (NavGSim Sec. III-B: LOD rendering selects Gaussians from different
-// levels of the tree).  The frontier holds (node, view) entries of one level
-// in (view, node) order.  Per level:
+// levels of the tree).  The frontier holds (node, view) entries of one level,
+// a node's views mostly next to each other (see k_level_emit).  Per level:
 //   count : each block decides its contiguous chunk (in the learned cut the
 //           network settles the candidates right there), stores the
 //           decisions and reduces (emitted, children) counts;
@@ -13,8 +13,9 @@
 //           block and writes emitted ids and child ids in order.
 // A level's grid is sized to its frontier's bound (nodes of the level times
 // views), at most kCutBlocks workgroups.
-// Ids come out ascending per view because ids are level-major and children
-// of a node are contiguous and ordered like their parents.
+// Ids come out ascending per view because ids are level-major, children
+// of a node are contiguous and ordered like their parents, and each view's
+// entries keep their order through the emission.
 //
 // The node test is exact: FP64 with +, -, * only, in a fixed order, with FMA
 // contraction disabled, so every IEEE FP64 implementation selects the same
@@ -65,6 +66,7 @@ struct LevelCtx {
     const float4* bound;
     const int2* child;
     const ViewDev* views;
+    int n_views;
     const uint2* in;
     uint32_t* in_count;
     uint2* out;
@@ -83,6 +85,7 @@ struct LevelCtx {
     uint32_t cand_cap;
     int level;
     bool leaves;              // the last level: every node is a leaf (no child ranges to read)
+    bool group;               // children laid out child-major per group of a node's views
     int out_slot;             // index of the next frontier's counter
 };
 
@@ -109,11 +112,23 @@ __device__ __forceinline__ uint4 counts_of(const LevelCtx& c, uint32_t d, int nc
 // evaluate the network over the group (64 entries per wave; the network's
 // work is negligible, so the group is not compacted).  The network keeps a
 // candidate (emits it) unless its probability reaches p*.
+//
+// The pass's views are staged in LDS when there are at most kLdsViews: a
+// wave's entries span several views (a node's views are next to each
+// other), and LDS serves a lane's own view without a gather.  Staged are
+// the leading words through the side-plane normals and keep_node, all that
+// the node test and the features read.
+constexpr int kLdsViews = 64;
+constexpr int kCutViewWords = (int)((offsetof(ViewDev, nb) + sizeof(double)) / 8);
+static_assert(offsetof(ViewDev, o) == 0 && offsetof(ViewDev, nb) % 8 == 0, "views start with their FP64 words");
+
 template <bool DEFER>
 __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap) {
     __shared__ uint4 sh[kNT / kWave + 1];
     __shared__ float s_x[DEFER ? kNT * kMlpXStride : 1];
     __shared__ float s_w[DEFER ? kMlpParams : 1];  // the network's FP32 weights
+    __shared__ uint64_t s_view[kLdsViews * kCutViewWords];
+    __shared__ int32_t s_keep[kLdsViews];
     uint32_t n = *c.in_count;
     n = n < in_cap ? n : in_cap;
     uint32_t lo, hi;
@@ -124,11 +139,36 @@ __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap
     }
     if (DEFER)
         for (int k = threadIdx.x; k < kMlpParams; k += kNT) s_w[k] = c.w32[k];
+    const bool lds_views = c.n_views <= kLdsViews;
+    if (lds_views) {
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(c.views);
+        for (int k = threadIdx.x; k < c.n_views * kCutViewWords; k += kNT) {
+            const int v = k / kCutViewWords, q = k - v * kCutViewWords;
+            s_view[k] = src[(size_t)v * (sizeof(ViewDev) / 8) + q];
+        }
+        for (int v = threadIdx.x; v < c.n_views; v += kNT) s_keep[v] = c.views[v].keep_node;
+        __syncthreads();
+    }
+    // f applied to view v (the staged words; the others, which neither the
+    // node test nor the features read, stay zero)
+    auto with_view = [&](uint32_t v, auto&& f) {
+        if (lds_views) {
+            uint64_t wd[sizeof(ViewDev) / 8];
+#pragma unroll
+            for (int q = 0; q < (int)(sizeof(ViewDev) / 8); ++q)
+                wd[q] = q < kCutViewWords ? s_view[v * kCutViewWords + q] : 0ull;
+            ViewDev V;
+            __builtin_memcpy(&V, wd, sizeof V);
+            V.keep_node = s_keep[v];
+            return f(V);
+        }
+        return on_view(c.views, v, f);
+    };
     const int w = threadIdx.x / kWave;
     uint4 acc = make_uint4(0, 0, 0, 0);
     auto decide = [&](bool valid, uint2 e, float4 b, int2 ch) -> uint32_t {
         if (!valid) return kDrop;
-        return on_view(c.views, e.y, [&](const ViewDev& V) { return node_decision(V, (int)e.x, b, ch.y, c.s_hi); });
+        return with_view(e.y, [&](const ViewDev& V) { return node_decision(V, (int)e.x, b, ch.y, c.s_hi); });
     };
     // the network's say on the group's candidates (every thread takes part)
     auto settle = [&](uint32_t d, uint2 e, float4 b) -> uint32_t {
@@ -139,7 +179,7 @@ __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap
 #pragma unroll
         for (int k = 0; k < kMlpIn; ++k) f[k] = 0.f;
         if (cand) {
-            on_view(c.views, e.y, [&](const ViewDev& V) {
+            with_view(e.y, [&](const ViewDev& V) {
                 NodeGeom g;
                 node_geometry(V, b, &g);
                 lod_features(m, V, (int)e.x, b, g, c.level, f);
@@ -215,7 +255,6 @@ __global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G, uint32_t
         k->visited += n_in < in_cap ? n_in : in_cap;
         const uint32_t base = k->cut;
         const uint32_t cbase = k->cand;
-        k->level_cut[c.level] = base;
         c.tmp[G] = make_uint4(base, 0, cbase, 0);
         if (c.cand != nullptr) {
             const uint64_t want = (uint64_t)cbase + tot.z;
@@ -243,12 +282,25 @@ __global__ __launch_bounds__(1024) void k_level_scan(LevelCtx c, int G, uint32_t
 // workgroup scan places 1,024 entries.  The children an iteration appends
 // to the next frontier form one run; it is assembled in LDS (up to
 // kEmitStage entries, the rest stored directly) and written out coalesced.
+// Within the run, the children of one group (consecutive entries of the
+// same node, one per view) are laid out child-major: (c0, v1), (c0, v2),
+// ..., (c1, v1), ...  A node's views thus stay next to each other at every
+// level, so that the passes reading a node's data per entry (this cut's
+// node tests, the projection's Gaussian and SH reads) find it in cache for
+// the second and later views.  Each view's entries keep their order.
 constexpr int kEmitPer = 4;
 constexpr uint32_t kEmitStage = 4096;
+// Views are grouped kCutViewGroup at a time; within a group the frontier
+// is node-major (a node's views next to each other).  Larger groups share
+// more of a node's reads between views; smaller ones keep fewer views in a
+// wave (32 measured best on 50-view batches, between 16 and 64).
+constexpr uint32_t kCutViewGroup = 32;
 
 __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap) {
     __shared__ uint4 sh[kNT / kWave + 1];
     __shared__ uint2 s_out[kEmitStage];
+    __shared__ uint2 s_last[kNT];                       // (node, view group) of each thread's last entry
+    __shared__ uint32_t s_gbase[kEmitPer * kNT + 1];    // children before each group, then the total
     uint32_t n = *c.in_count;
     n = n < in_cap ? n : in_cap;
     uint32_t lo, hi;
@@ -282,19 +334,48 @@ __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap)
         }
         uint4 r[kEmitPer];
         int first[kEmitPer];
+        bool head[kEmitPer];
         uint4 mine = make_uint4(0, 0, 0, 0);
+        const bool grouped = c.group && !c.leaves;
+        if (grouped) {
+            s_last[threadIdx.x] = make_uint2(e[kEmitPer - 1].x, e[kEmitPer - 1].y / kCutViewGroup);
+            __syncthreads();
+        }
+        uint2 prev = (grouped && threadIdx.x > 0) ? s_last[threadIdx.x - 1] : make_uint2(~0u, ~0u);
 #pragma unroll
         for (int j = 0; j < kEmitPer; ++j) {
             const bool expand = (d[j] & 3u) == kExpand;
             const int2 ch = (expand && !c.leaves) ? c.child[e[j].x] : make_int2(0, 0);
             first[j] = ch.x;
             r[j] = counts_of(c, d[j], ch.y);
+            // a group starts where the node or the view group changes (node
+            // ids are below 2^31)
+            const uint32_t vg = e[j].y / kCutViewGroup;
+            head[j] = e[j].x != prev.x || vg != prev.y;
+            prev = make_uint2(e[j].x, vg);
             mine.x += r[j].x;
             mine.y += r[j].y;
             mine.z += r[j].z;
+            mine.w += head[j] ? 1u : 0u;
         }
         uint4 tot;
         uint4 ex = block_excl_scan4<kNT>(mine, sh, &tot);
+        uint32_t grp[kEmitPer], ey[kEmitPer];
+        {
+            uint4 run = ex;
+#pragma unroll
+            for (int j = 0; j < kEmitPer; ++j) {
+                run.w += head[j] ? 1u : 0u;
+                grp[j] = run.w - 1u;                    // this entry's group within the iteration
+                ey[j] = run.y;
+                if (grouped && head[j]) s_gbase[grp[j]] = run.y;
+                run.y += r[j].y;
+            }
+        }
+        if (grouped) {
+            if (threadIdx.x == 0) s_gbase[tot.w] = tot.y;
+            __syncthreads();
+        }
 #pragma unroll
         for (int j = 0; j < kEmitPer; ++j) {
             if (r[j].x) {
@@ -305,18 +386,30 @@ __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap)
                 const uint64_t pos = (uint64_t)cbase + off.z + ex.z;
                 if (pos < c.cand_cap) c.cand[pos] = e[j];
             }
-            for (uint32_t q = 0; q < r[j].y; ++q) {
-                const uint32_t L = ex.y + q;
-                const uint2 child = make_uint2((uint32_t)(first[j] + (int)q), e[j].y);
-                if (L < kEmitStage) {
-                    s_out[L] = child;
-                } else {
-                    const uint64_t pos = (uint64_t)off.y + L;
-                    if (pos < c.out_cap) c.out[pos] = child;
+            const uint32_t m = r[j].y;
+            if (m) {
+                // every expanding entry of the group has this node's m
+                // children: the group's children are m * n_exp, this entry
+                // is the rank-th expanding one (ungrouped: its children in
+                // order at ey)
+                uint32_t gb = ey[j], n_exp = 1, rank = 0;
+                if (grouped) {
+                    gb = s_gbase[grp[j]];
+                    n_exp = (s_gbase[grp[j] + 1] - gb) / m;
+                    rank = (ey[j] - gb) / m;
+                }
+                for (uint32_t q = 0; q < m; ++q) {
+                    const uint32_t L = gb + q * n_exp + rank;
+                    const uint2 child = make_uint2((uint32_t)(first[j] + (int)q), e[j].y);
+                    if (L < kEmitStage) {
+                        s_out[L] = child;
+                    } else {
+                        const uint64_t pos = (uint64_t)off.y + L;
+                        if (pos < c.out_cap) c.out[pos] = child;
+                    }
                 }
             }
             ex.x += r[j].x;
-            ex.y += r[j].y;
             ex.z += r[j].z;
         }
         if (!c.leaves) {
@@ -334,11 +427,16 @@ __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap)
     }
 }
 
-// Frontier of every view's roots (nodes [0, n_roots)), view-major.
+// Frontier of every view's roots (nodes [0, n_roots)): view groups in
+// order, node-major within a group.
 __global__ void k_init_roots(uint2* out, uint32_t n_roots, uint32_t n_views, uint32_t cap, Counters* ctr, int slot) {
     const uint32_t total = n_roots * n_views;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x)
-        if (i < cap) out[i] = make_uint2(i % n_roots, i / n_roots);
+    const uint32_t per = n_roots * kCutViewGroup;          // entries of a full group
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const uint32_t vb = i / per, loc = i - vb * per;
+        const uint32_t nb = min(kCutViewGroup, n_views - vb * kCutViewGroup);
+        if (i < cap) out[i] = make_uint2(loc / nb, vb * kCutViewGroup + loc % nb);
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (total > cap) {
             ctr->overflow |= kOvFrontier;
@@ -421,6 +519,7 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.bound = a.bound;
         c.child = a.child;
         c.views = a.views;
+        c.n_views = a.n_views;
         c.in = a.frontier[cur];
         c.in_count = &a.ctr->frontier[cur];
         c.out = a.frontier[cur ^ 1];
@@ -440,6 +539,7 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         c.cand_cap = a.cand_cap;
         c.level = L;
         c.leaves = L == a.n_levels - 1;
+        c.group = a.group_children;
         c.out_slot = cur ^ 1;
         // the frontier holds at most (nodes of level L) x views entries;
         // small levels get a grid of that size (the chunking keeps the

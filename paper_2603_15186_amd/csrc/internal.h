@@ -113,7 +113,6 @@ struct alignas(16) BinRec {
 
 // Device counters of one render.
 constexpr int kCutLevels = 64;       // hierarchy levels at most (scene validation enforces it)
-constexpr int kMaxRunSlots = 8192;   // (level, view) slots of the table that maps cut entries to views
 
 struct Counters {
     uint32_t frontier[2];            // frontier sizes (ping, pong)
@@ -130,7 +129,6 @@ struct Counters {
     unsigned long long nalg;         // evaluated (pixel, Gaussian) pairs with q <= 9
     unsigned long long neval;        // (pixel, list entry) slots the compositor walked
     unsigned long long visited;      // (node, view) pairs the cut tested, over all levels
-    uint32_t level_cut[kCutLevels];  // cut size when each level's entries began
 };
 
 // Options of the compositor and binning.
@@ -191,6 +189,10 @@ struct CutArgs {
     double s_hi;
     uint2* cand;                     // nullptr: do not collect candidates
     uint32_t cand_cap;
+    // children of a node's views laid out child-major in the frontier (off
+    // with LOD blending, whose projection takes a view's sibling as the cut
+    // entry before it)
+    bool group_children;
 };
 void launch_cut(const CutArgs& a, hipStream_t s);
 
@@ -227,24 +229,14 @@ struct ProjectArgs {
     const int2* child;
     int tile_w, tile_h;              // tile shape in pixels
     int key_shift;                   // pair sort keys: view << key_shift | tile within the view
-    // The cut holds, level after level, each view's entries as one run: the
-    // first index of the run of (level L, view v) goes to runs[L * n_views +
-    // v] (null: not recorded; slots without a run keep ~0u).
-    uint32_t* runs;
-    int n_cut_levels;
-    int n_views;
 };
 void launch_project(const ProjectArgs& a, hipStream_t s);
 
 // keys[i] = view of the depth-sorted entry order[i] (order: index | tiles
-// << 28), so that a stable pass on them groups the entries by view.  With a
-// run table (n_slots = levels x views <= kMaxRunSlots; reset by
-// launch_runs_reset before the projection fills it) the view is found by a
-// search over the runs' first indices; without one (runs null) it is read
-// from the cut.
-void launch_runs_reset(uint32_t* runs, int n_slots, hipStream_t s);
-void launch_view_keys(const uint32_t* order, const uint2* cut, uint32_t* runs, int n_slots, int n_views,
-                      const uint32_t* count, uint32_t cap, uint32_t* keys, hipStream_t s);
+// << 28), read from the cut, so that a stable pass on them groups the
+// entries by view.
+void launch_view_keys(const uint32_t* order, const uint2* cut, const uint32_t* count, uint32_t cap, uint32_t* keys,
+                      hipStream_t s);
 
 // Pair emission in depth order: offsets = exclusive scan of ntiles over the
 // depth-sorted entries.

@@ -241,12 +241,6 @@ __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
         const uint2 e = a.cut[i];
         const ViewDev V = load_view(a.views, e.y);
         const int64_t g = e.x;
-        if (a.runs != nullptr && (i == 0 || a.cut[i - 1].y != e.y)) {
-            // first entry of a run: its level is the last one begun at or before i
-            uint32_t L = 0;
-            for (int l = 1; l < a.n_cut_levels; ++l) L = a.ctr->level_cut[l] <= i ? (uint32_t)l : L;
-            a.runs[L * (uint32_t)a.n_views + e.y] = i;
-        }
         const float4 g0 = a.geo[3 * g], g1 = a.geo[3 * g + 1], g2 = a.geo[3 * g + 2];
         int64_t pg = -1;
         double t = 1.0;
@@ -567,75 +561,6 @@ __global__ void k_view_keys(const uint32_t* __restrict__ order, const uint2* __r
     }
 }
 
-__global__ void k_runs_reset(uint32_t* runs, int n) {
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) runs[k] = ~0u;
-}
-
-// Slots without a run take the first index of the next run (a suffix
-// minimum), so that the table is non-decreasing and the last slot starting
-// at or before an index is the run holding it.
-__global__ __launch_bounds__(1024) void k_runs_fill(uint32_t* runs, int n) {
-    __shared__ uint32_t s[kMaxRunSlots];
-    constexpr int PER = kMaxRunSlots / 1024;
-    const int t = threadIdx.x;
-    for (int k = t; k < n; k += 1024) s[k] = runs[k];
-    __syncthreads();
-    for (int d = 1; d < n; d <<= 1) {
-        uint32_t v[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int k = t + j * 1024;
-            v[j] = k < n ? (k + d < n ? min(s[k], s[k + d]) : s[k]) : 0u;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int k = t + j * 1024;
-            if (k < n) s[k] = v[j];
-        }
-        __syncthreads();
-    }
-    for (int k = t; k < n; k += 1024) runs[k] = s[k];
-}
-
-__global__ __launch_bounds__(256) void k_view_keys_runs(const uint32_t* __restrict__ order,
-                                                        const uint32_t* __restrict__ runs, int n_slots, int n_views,
-                                                        const uint32_t* count, uint32_t cap,
-                                                        uint32_t* __restrict__ keys) {
-    __shared__ uint32_t s[kMaxRunSlots];
-    for (int k = threadIdx.x; k < n_slots; k += 256) s[k] = runs[k];
-    __syncthreads();
-    const uint32_t n = min(*count, cap);
-    const int steps = 32 - __clz(n_slots);            // halvings until one slot remains
-    // four independent searches per thread and step
-    for (uint32_t i0 = blockIdx.x * 1024 + threadIdx.x; i0 < n; i0 += gridDim.x * 1024) {
-        uint32_t e[4], lo[4], hi[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t i = i0 + 256 * u;
-            e[u] = i < n ? order[i] & kEntryMask : 0u;
-            lo[u] = 0;
-            hi[u] = (uint32_t)n_slots;
-        }
-        // last slot whose run begins at or before e (slot 0 begins at 0)
-        for (int step = 0; step < steps; ++step) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (hi[u] - lo[u] > 1) {
-                    const uint32_t mid = (lo[u] + hi[u]) >> 1;
-                    if (s[mid] <= e[u]) lo[u] = mid;
-                    else hi[u] = mid;
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t i = i0 + 256 * u;
-            if (i < n) keys[i] = lo[u] % (uint32_t)n_views;
-        }
-    }
-}
-
 template <bool Blend>
 void launch_project_b(const ProjectArgs& a, hipStream_t s) {
     switch (a.sh_degree) {
@@ -653,18 +578,9 @@ void launch_project(const ProjectArgs& a, hipStream_t s) {
         launch_project_b<false>(a, s);
 }
 
-void launch_runs_reset(uint32_t* runs, int n_slots, hipStream_t s) {
-    k_runs_reset<<<(n_slots + 255) / 256, 256, 0, s>>>(runs, n_slots);
-}
-
-void launch_view_keys(const uint32_t* order, const uint2* cut, uint32_t* runs, int n_slots, int n_views,
-                      const uint32_t* count, uint32_t cap, uint32_t* keys, hipStream_t s) {
-    if (runs == nullptr) {
-        k_view_keys<<<2048, 256, 0, s>>>(order, cut, count, cap, keys);
-        return;
-    }
-    k_runs_fill<<<1, 1024, 0, s>>>(runs, n_slots);
-    k_view_keys_runs<<<2048, 256, 0, s>>>(order, runs, n_slots, n_views, count, cap, keys);
+void launch_view_keys(const uint32_t* order, const uint2* cut, const uint32_t* count, uint32_t cap, uint32_t* keys,
+                      hipStream_t s) {
+    k_view_keys<<<2048, 256, 0, s>>>(order, cut, count, cap, keys);
 }
 
 void launch_emit(const EmitArgs& a, hipStream_t s) {
