@@ -113,9 +113,10 @@ __device__ __forceinline__ uint4 counts_of(const LevelCtx& c, uint32_t d, int nc
 // work is negligible, so the group is not compacted).  The network keeps a
 // candidate (emits it) unless its probability reaches p*.
 //
-// The pass's views are staged in LDS when there are at most kLdsViews: a
-// wave's entries span several views (a node's views are next to each
-// other), and LDS serves a lane's own view without a gather.  Staged are
+// With node-grouped frontiers, the pass's views are staged in LDS when
+// there are at most kLdsViews: a wave's entries span several views (a
+// node's views are next to each other), and LDS serves a lane's own view
+// without a gather.  Staged are
 // the leading words through the side-plane normals and keep_node, all that
 // the node test and the features read.
 constexpr int kLdsViews = 64;
@@ -139,7 +140,8 @@ __global__ __launch_bounds__(kNT) void k_level_count(LevelCtx c, uint32_t in_cap
     }
     if (DEFER)
         for (int k = threadIdx.x; k < kMlpParams; k += kNT) s_w[k] = c.w32[k];
-    const bool lds_views = c.n_views <= kLdsViews;
+    // (view-major frontiers keep a wave on one view: scalar loads serve it)
+    const bool lds_views = c.group && c.n_views <= kLdsViews;
     if (lds_views) {
         const uint64_t* src = reinterpret_cast<const uint64_t*>(c.views);
         for (int k = threadIdx.x; k < c.n_views * kCutViewWords; k += kNT) {
@@ -427,15 +429,17 @@ __global__ __launch_bounds__(kNT) void k_level_emit(LevelCtx c, uint32_t in_cap)
     }
 }
 
-// Frontier of every view's roots (nodes [0, n_roots)): view groups in
-// order, node-major within a group.
-__global__ void k_init_roots(uint2* out, uint32_t n_roots, uint32_t n_views, uint32_t cap, Counters* ctr, int slot) {
+// Frontier of every view's roots (nodes [0, n_roots)): grouped, view
+// groups in order and node-major within a group; otherwise view-major.
+__global__ void k_init_roots(uint2* out, uint32_t n_roots, uint32_t n_views, uint32_t cap, Counters* ctr, int slot,
+                             bool grouped) {
     const uint32_t total = n_roots * n_views;
     const uint32_t per = n_roots * kCutViewGroup;          // entries of a full group
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         const uint32_t vb = i / per, loc = i - vb * per;
         const uint32_t nb = min(kCutViewGroup, n_views - vb * kCutViewGroup);
-        if (i < cap) out[i] = make_uint2(loc / nb, vb * kCutViewGroup + loc % nb);
+        const uint2 e = grouped ? make_uint2(loc / nb, vb * kCutViewGroup + loc % nb) : make_uint2(i % n_roots, i / n_roots);
+        if (i < cap) out[i] = e;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (total > cap) {
@@ -512,7 +516,8 @@ void launch_cut(const CutArgs& a, hipStream_t s) {
         return;
     }
     const uint32_t n_roots = (uint32_t)a.level_offset_host[1];
-    k_init_roots<<<64, 256, 0, s>>>(a.frontier[0], n_roots, (uint32_t)a.n_views, a.frontier_cap, a.ctr, 0);
+    k_init_roots<<<64, 256, 0, s>>>(a.frontier[0], n_roots, (uint32_t)a.n_views, a.frontier_cap, a.ctr, 0,
+                                    a.group_children);
     int cur = 0;
     for (int L = 0; L < a.n_levels; ++L) {
         LevelCtx c;
