@@ -327,7 +327,7 @@ hgs_status hgs_sort_pairs_noalloc(hgs_ctx* ctx, void* stream, uint32_t* keys, ui
 hgs_status hgs_set_keep_nodes(hgs_ctx* ctx, int32_t n, const int32_t* nodes);
 
 /* Run the threshold cut of the current views and collect the candidates
- * (refined, projected size <= s_hi) in (view, level, id) order.  Device
+ * (refined, projected size <= s_hi) in (level, view, id) order.  Device
  * outputs, cap entries each: entries[2i] = node, entries[2i+1] = view;
  * features[8i..8i+8) raw features; rects[4i..4i+4) = x0, y0, x1, y1 pixel
  * bounds of the node's bounding-sphere projection, clipped to the image.
