@@ -189,9 +189,8 @@ struct CutArgs {
     double s_hi;
     uint2* cand;                     // nullptr: do not collect candidates
     uint32_t cand_cap;
-    // children of a node's views laid out child-major in the frontier (off
-    // with LOD blending, whose projection takes a view's sibling as the cut
-    // entry before it)
+    // children of a node's views laid out child-major in the frontier
+    // (node-grouped), else in plain parent order with view-major roots
     bool group_children;
 };
 void launch_cut(const CutArgs& a, hipStream_t s);
