@@ -255,18 +255,35 @@ def test_batched_views_equal_single_views(R, plan_small):
 
 
 def test_very_large_batch_equals_single_views(R, plan_small):
-    """More views than the table of the cut's (level, view) runs holds
-    (levels x views > 8,192): the views of the depth-sorted entries are then
-    read from the cut.  Tiny views; sampled views equal their single-view
+    """Far more views than fit above the depth bits of the sort keys (a
+    stable view pass then follows the depth sort, reading each entry's view
+    from the cut) and than the cut's count pass stages in LDS (64), in many
+    groups of 32 views.  Tiny views; sampled views equal their single-view
     renders bitwise and the last view's cut equals the oracle's."""
     scene, cams = plan_small
     n_levels = len(scene.level_offset) - 1
     n_views = 8192 // n_levels + 64
-    assert n_levels * n_views > 8192
+    assert n_views > 64
     views = [_small_cam(cams[v % len(cams)], 24 + (v % 3) * 8, 16 + (v % 5) * 4) for v in range(n_views)]
     batch = _render(R, scene, views)
     assert np.array_equal(R.get_cut(n_views - 1), O.cut(scene, views[-1], O.MODE_THRESHOLD, 1.0))
     for v in list(range(0, n_views, 97)) + [n_views - 1]:
+        single = _render(R, scene, [views[v]])[0]
+        for a, b in zip(batch[v], single):
+            assert np.array_equal(a, b), v
+
+
+def test_view_groups_keep_each_views_cut(R, plan_small):
+    """A batch of 40 views: two groups of 32 and 8 views whose frontiers are
+    node-major (a node's views next to each other), views staged in LDS by
+    the count pass.  Every view's cut equals the oracle's, in ascending id
+    order, and sampled views equal their single-view renders bitwise."""
+    scene, cams = plan_small
+    views = [_small_cam(cams[v % len(cams)], 120 + (v % 4) * 20, 68 + (v % 3) * 12) for v in range(40)]
+    batch = _render(R, scene, views)
+    for v, cam in enumerate(views):
+        assert np.array_equal(R.get_cut(v), O.cut(scene, cam, O.MODE_THRESHOLD, 1.0)), v
+    for v in (0, 31, 32, 39):
         single = _render(R, scene, [views[v]])[0]
         for a, b in zip(batch[v], single):
             assert np.array_equal(a, b), v
