@@ -116,9 +116,8 @@ __device__ __forceinline__ uint4 counts_of(const LevelCtx& c, uint32_t d, int nc
 // With node-grouped frontiers, the pass's views are staged in LDS when
 // there are at most kLdsViews: a wave's entries span several views (a
 // node's views are next to each other), and LDS serves a lane's own view
-// without a gather.  Staged are
-// the leading words through the side-plane normals and keep_node, all that
-// the node test and the features read.
+// without a gather.  Staged are the leading words through the side-plane
+// normals and keep_node, all that the node test and the features read.
 constexpr int kLdsViews = 64;
 constexpr int kCutViewWords = (int)((offsetof(ViewDev, nb) + sizeof(double)) / 8);
 static_assert(offsetof(ViewDev, o) == 0 && offsetof(ViewDev, nb) % 8 == 0, "views start with their FP64 words");
