@@ -277,6 +277,35 @@ def test_learned_cut_fallback_and_band(R, plan):
                 assert len(got) <= len(thr)
 
 
+def test_learned_cut_of_a_large_batch_equals_single_views(R, plan):
+    """70 views: node-grouped frontiers in three groups of views, more views
+    than the count pass stages in LDS, so the network's features read each
+    lane's view by gathers.  Every sampled view's learned cut (a random
+    network at p* = 0.5, which keeps some candidates and refines others)
+    equals its cut rendered alone, where a wave works on one view."""
+    from paper_2603_15186_amd import hgs
+    from paper_2603_15186_amd.synth import yaw_camera
+    scene, cams, _ = plan
+    R.load_scene(scene)
+    views = [yaw_camera(160 + (v % 3) * 40, 90 + (v % 2) * 30, 900.0 * (160 + (v % 3) * 40) / 1280.0,
+                        cams[v % len(cams)].position,
+                        math.atan2(cams[v % len(cams)].R[2][1], cams[v % len(cams)].R[2][0]) + 0.05 * v)
+             for v in range(70)]
+    w = M.bf16_bits(mlp_init(5))
+    R.load_lod_mlp(w, np.zeros(8), np.ones(8), 0.5, 256.0)
+    R.set_cameras(views)
+    R.set_lod(hgs.HGS_LOD_LEARNED, 1.0)
+    R.render()
+    torch.cuda.synchronize()
+    cuts = {v: R.get_cut(v) for v in (0, 31, 32, 64, 69)}
+    for v, got in cuts.items():
+        R.set_cameras([views[v]])
+        R.render()
+        torch.cuda.synchronize()
+        assert np.array_equal(R.get_cut(0), got), v
+    R.set_lod(hgs.HGS_LOD_THRESHOLD, 1.0)
+
+
 def test_training_pipeline_end_to_end(R, plan):
     """Labels from collapsed-window renders, training with the library's
     kernels, calibration: the training loss falls and the calibrated cut
