@@ -438,6 +438,8 @@ void enqueue_pass(hgs_ctx* c, hipStream_t s, int g) {
     pa.n = c->n;
     pa.sh_degree = c->sh_degree;
     pa.views = ca.views;
+    pa.n_views = ca.n_views;
+    pa.lds_views = ca.group_children && ca.n_views <= kProjectLdsViews;
     pa.proj = P<Proj>(W.proj);
     pa.depth_key = P<uint32_t>(W.dkey[0]);
     // Binned depths lie in (znear, distance to the farthest corner of the

@@ -228,7 +228,12 @@ struct ProjectArgs {
     const int2* child;
     int tile_w, tile_h;              // tile shape in pixels
     int key_shift;                   // pair sort keys: view << key_shift | tile within the view
+    // the pass's views staged in LDS (at most kProjectLdsViews; for
+    // node-grouped cuts, whose waves span several views)
+    bool lds_views;
+    int n_views;
 };
+constexpr int kProjectLdsViews = 64;
 void launch_project(const ProjectArgs& a, hipStream_t s);
 
 // keys[i] = view of the depth-sorted entry order[i] (order: index | tiles

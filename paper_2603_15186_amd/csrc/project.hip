@@ -235,11 +235,26 @@ __device__ __forceinline__ double sphere_size(const ViewDev& V, float4 b) {
 // follow the same FP64 steps as the unblended ones.
 template <bool Blend, int DEG>
 __global__ __launch_bounds__(kNT) void k_project(ProjectArgs a) {
+    constexpr int kWords = (int)(sizeof(ViewDev) / 8);
+    __shared__ uint64_t s_view[kProjectLdsViews * kWords];
     const uint32_t m = min(a.ctr->cut, a.cut_cap);
+    if (a.lds_views) {
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(a.views);
+        for (int k = threadIdx.x; k < a.n_views * kWords; k += kNT) s_view[k] = src[k];
+        __syncthreads();
+    }
     uint32_t vis = 0;
     for (uint32_t i = blockIdx.x * kNT + threadIdx.x; i < m; i += gridDim.x * kNT) {
         const uint2 e = a.cut[i];
-        const ViewDev V = load_view(a.views, e.y);
+        ViewDev V;
+        if (a.lds_views) {
+            uint64_t wd[kWords];
+#pragma unroll
+            for (int q = 0; q < kWords; ++q) wd[q] = s_view[e.y * kWords + q];
+            __builtin_memcpy(&V, wd, sizeof V);
+        } else {
+            V = load_view(a.views, e.y);
+        }
         const int64_t g = e.x;
         const float4 g0 = a.geo[3 * g], g1 = a.geo[3 * g + 1], g2 = a.geo[3 * g + 2];
         int64_t pg = -1;
