@@ -53,8 +53,9 @@ struct ViewDev {
 };
 
 // Views do not change while a kernel runs.  When every active lane of a
-// wave works on the same view (the usual case: cut and frontier entries come
-// grouped by view), f gets a copy of that view read through the constant
+// wave works on the same view (the usual case for view-major frontiers and
+// cuts; node-grouped ones are served from views staged in LDS), f gets a
+// copy of that view read through the constant
 // address space at a wave-uniform index, so its fields arrive by scalar
 // loads instead of one vector gather per field; otherwise f gets the lane's
 // own view.  Either way f sees the same values.
